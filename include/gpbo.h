@@ -1,0 +1,239 @@
+/*
+ * gpbo.h -- C ABI of the MI355X Gaussian-process surrogate / expected-
+ * improvement engine.
+ *
+ * What it computes.  The paper's search method (Sec. III-A) trains a surrogate
+ * model on the configurations evaluated so far, lets an acquisition function
+ * choose the next configuration, evaluates it and retrains; Sec. IV-D names
+ * the surrogate -- a Gaussian process whose training cost is cubic in the
+ * number N of evaluations -- and runs the independent (or merged) sub-searches
+ * of a tuning problem in parallel.  This library is the data-parallel inner
+ * step of that loop for one sub-search or a batch of them:
+ *
+ *   observations (X, y) --gpbo_fit--> model --gpbo_score(X*)--> mu, sigma, EI,
+ *                                                               argmax EI
+ *
+ * The paper does not give the Gaussian-process formulas; the library uses the
+ * textbook ones (Rasmussen & Williams 2006, Alg. 2.1 and eqs. 2.25-2.26, 4.9,
+ * 4.17) and the closed-form expected improvement for minimisation (Jones,
+ * Schonlau & Welch 1998, eq. 15).  A learned prescreen (an MLP ensemble trained
+ * on the search's own evaluations) narrows million-point candidate pools
+ * before the exact Gaussian process re-scores the survivors.
+ *
+ * Conventions for every entry point.
+ *   - Every call returns a gpbo_status.  Nothing is thrown across the ABI.
+ *   - "device" pointers are HIP device memory on the context's device;
+ *     "host" pointers are ordinary host memory.  All matrices are row-major.
+ *   - The caller owns every buffer it passes.  The library copies what it
+ *     keeps (a model holds its own copy of X and its factors), so the caller
+ *     may free its inputs as soon as a call returns.
+ *   - Work is queued on the context's HIP stream and runs asynchronously,
+ *     except where an entry point says it synchronises.
+ *   - On a non-OK status the outputs are undefined; gpbo_last_error() gives a
+ *     one-line description.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef GPBO_H
+#define GPBO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GPBO_OK = 0,
+  GPBO_E_INVALID_ARG = 1,  /* a size, pointer or enum is out of range          */
+  GPBO_E_NOT_PD = 2,       /* K(X,X) + noise I is not numerically positive-    */
+                           /* definite; the failing pivot is reported          */
+  GPBO_E_NONFINITE = 3,    /* X or y holds a NaN or an infinity                */
+  GPBO_E_OOM = 4,          /* a device allocation failed                       */
+  GPBO_E_HIP = 5,          /* the HIP runtime reported an error (or no device) */
+  GPBO_E_UNSUPPORTED = 6   /* a valid request this build does not implement    */
+} gpbo_status;
+
+/* Covariance functions, both with one lengthscale per input dimension.
+ *   SE:        k(a,b) = sf2 * exp(-r^2 / 2)                       (R&W eq. 4.9)
+ *   MATERN52:  k(a,b) = sf2 * (1 + sqrt5 r + 5 r^2 / 3) exp(-sqrt5 r) (eq. 4.17)
+ * with r^2 = sum_k ((a_k - b_k) / l_k)^2.                                    */
+typedef enum { GPBO_KERNEL_SE = 0, GPBO_KERNEL_MATERN52 = 1 } gpbo_kernel;
+
+/* Arithmetic of the scoring contractions (cross-covariance and the posterior
+ * products).  The fit is always float64.
+ *   FP64: everything in float64; outputs are double.
+ *   FP32: cross-covariance in float32, posterior products on float32 matrix
+ *         cores with float32 accumulation; outputs are float.
+ *   BF16: cross-covariance computed in float32 and rounded to bfloat16, the
+ *         inverse Cholesky factor rounded to bfloat16, products on bfloat16
+ *         matrix cores with float32 accumulation; outputs are float.        */
+typedef enum { GPBO_FP64 = 0, GPBO_FP32 = 1, GPBO_BF16 = 2 } gpbo_precision;
+
+/* Optional device allocator.  alloc returns device memory of at least `bytes`
+ * bytes usable on `stream` (NULL on failure); free releases it.  With no
+ * allocator the library calls hipMalloc / hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, void* stream, void* user);
+  void* user;
+} gpbo_allocator;
+
+typedef struct gpbo_ctx_s* gpbo_ctx;
+typedef struct gpbo_model_s* gpbo_model;
+typedef struct gpbo_mlp_s* gpbo_mlp;
+
+/* One sub-search: the evaluated configurations and the fixed hyperparameters.
+ * X: device, n x d float64.  y: device, n float64 (objective to minimise).
+ * lengthscale: host, d float64, all > 0.  signal_var > 0, noise_var >= 0 are
+ * variances in units of the normalised y.
+ * normalize_y: 1 = y is z-scored with its population standard deviation
+ *   (a zero spread falls back to 1); 0 = y is only centred.
+ * refine_alpha: 0 = alpha = K^-1 ytilde from float64 inverse-factor products
+ *   plus one float64 refinement step; 1 = float32 products plus one float64
+ *   residual-and-correction step (iterative refinement). */
+typedef struct {
+  int32_t n;
+  int32_t d;
+  const double* X;
+  const double* y;
+  int32_t kernel;
+  const double* lengthscale;
+  double signal_var;
+  double noise_var;
+  int32_t normalize_y;
+  int32_t refine_alpha;
+} gpbo_problem;
+
+/* Scalars of a fitted model, in the order of gpbo_model_stats:
+ * [0] mean of y, [1] scale s_y, [2] f_best = min y, [3] log marginal
+ * likelihood of the normalised y, [4] log det K, [5] residual norm
+ * |ytilde - K alpha| before refinement, [6] the same after refinement. */
+#define GPBO_NSTATS 7
+
+const char* gpbo_status_string(gpbo_status s);
+/* Description of the last failure on ctx (or of the last failed context
+ * creation when ctx is NULL).  Valid until the next call on ctx. */
+const char* gpbo_last_error(gpbo_ctx ctx);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t gpbo_version(void);
+
+/* Create a context on HIP device `device`, queuing work on `stream` (a
+ * hipStream_t; NULL = the default stream).  Returns GPBO_E_HIP when there is
+ * no usable device. */
+gpbo_status gpbo_ctx_create(int32_t device, void* stream, const gpbo_allocator* alloc,
+                            gpbo_ctx* out);
+gpbo_status gpbo_ctx_destroy(gpbo_ctx ctx);
+/* Replace the stream work is queued on. */
+gpbo_status gpbo_ctx_set_stream(gpbo_ctx ctx, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Fit (training the surrogate, Sec. IV-D: cubic in n).                    */
+/* ---------------------------------------------------------------------- */
+/* Normalise y, build K = k(X,X) + noise_var I, factor K = L L^T (float64,
+ * blocked, on the GPU), form L^-1, solve alpha and the log marginal
+ * likelihood.  SYNCHRONISES the stream once, to read the factorisation's
+ * status.  On GPBO_E_NOT_PD *bad_pivot (host, may be NULL) receives the
+ * 0-based index of the first pivot that is not positive.  *lml (host, may be
+ * NULL) receives the log marginal likelihood.  *out receives a model that
+ * owns copies of everything it needs; free it with gpbo_model_free. */
+gpbo_status gpbo_fit(gpbo_ctx ctx, const gpbo_problem* prob, gpbo_model* out, double* lml,
+                     int32_t* bad_pivot);
+
+/* Fit B independent sub-searches (Sec. IV-D runs them in parallel).  Problems
+ * of different n and d are factored together, largest first.  SYNCHRONISES
+ * once.  status (host, B) receives each problem's status; lml (host, B) may be
+ * NULL.  Returns GPBO_OK when every problem fitted, else the first failing
+ * problem's status (the models of failed problems are NULL). */
+gpbo_status gpbo_fit_batched(gpbo_ctx ctx, int32_t B, const gpbo_problem* probs,
+                             gpbo_model* out, double* lml, int32_t* status);
+
+gpbo_status gpbo_model_free(gpbo_model model);
+/* Host copy of the GPBO_NSTATS scalars (synchronises). */
+gpbo_status gpbo_model_stats(gpbo_model model, double* stats);
+gpbo_status gpbo_model_shape(gpbo_model model, int32_t* n, int32_t* d);
+/* Device copies of the factors (for checks): L (n x n, lower, float64),
+ * L^-1 (n x n, lower, float64) and alpha (n, float64).  Any may be NULL. */
+gpbo_status gpbo_model_factors(gpbo_ctx ctx, gpbo_model model, double* L, double* Linv,
+                               double* alpha);
+
+/* ---------------------------------------------------------------------- */
+/* Scoring (the acquisition step, Sec. III-A).                             */
+/* ---------------------------------------------------------------------- */
+/* Posterior mean mu, standard deviation sigma (of the latent function, no
+ * noise) and expected improvement for minimisation against f_best = min y:
+ *   mu = ymean + s_y k*^T alpha
+ *   sigma = s_y sqrt(max(signal_var - |L^-1 k*|^2, 0))
+ *   EI = (f_best - mu) Phi(z) + sigma phi(z), z = (f_best - mu) / sigma
+ *        (EI = max(f_best - mu, 0) when sigma = 0)
+ * Xc: device, m x d, double for GPBO_FP64, float otherwise.
+ * mu, sigma, ei: device, m each, double for GPBO_FP64, float otherwise; each
+ * may be NULL.  argmax (device int64) and ei_max (device double): the index
+ * of the largest EI (lowest index among ties) and its value; both may be
+ * NULL, in which case no reduction runs.  m = 0 is allowed (argmax = -1).
+ * Asynchronous. */
+gpbo_status gpbo_score(gpbo_ctx ctx, gpbo_model model, int64_t m, const void* Xc,
+                       gpbo_precision prec, void* mu, void* sigma, void* ei, int64_t* argmax,
+                       double* ei_max);
+
+/* Score B models, each on its own candidate pool, in one persistent launch.
+ * m, Xc, ei: host arrays of B entries (Xc[b], ei[b] are device pointers as
+ * in gpbo_score; ei[b] or the whole ei array may be NULL).  argmax and ei_max
+ * are device arrays of B entries.  prec is GPBO_FP32 or GPBO_BF16.  The
+ * launch sequence is captured in a HIP graph on first use and replayed while
+ * the same models, pools and outputs are passed again.  Asynchronous. */
+gpbo_status gpbo_score_batched(gpbo_ctx ctx, int32_t B, const gpbo_model* models,
+                               const int64_t* m, const void* const* Xc, gpbo_precision prec,
+                               void* const* ei, int64_t* argmax, double* ei_max);
+
+/* Top k of v (device, m floats) by (value descending, index ascending); idx
+ * is a device array of k int64.  NaN entries never rank.  Asynchronous. */
+gpbo_status gpbo_topk(gpbo_ctx ctx, int64_t m, const float* v, int64_t k, int64_t* idx);
+
+/* out[i, :] = Xc[idx[i], :] for i < k (device float arrays, row-major, d
+ * columns).  Asynchronous. */
+gpbo_status gpbo_gather_rows(gpbo_ctx ctx, int64_t k, const int64_t* idx, int32_t d,
+                             const float* Xc, float* out);
+
+/* ---------------------------------------------------------------------- */
+/* Learned prescreen: an ensemble of MLPs d_in -> H -> H -> 1 (GELU),        */
+/* bfloat16 weights and activations on the matrix cores with float32         */
+/* accumulation, float32 master weights and Adam state.                      */
+/* ---------------------------------------------------------------------- */
+/* Parameter layout of one member (P = H*d_in + H + H*H + H + H + 1 floats):
+ *   W1 (H x d_in), b1 (H), W2 (H x H), b2 (H), w3 (H), b3 (1).
+ * init: device, members x P float32 initial master weights. */
+gpbo_status gpbo_mlp_create(gpbo_ctx ctx, int32_t members, int32_t d_in, int32_t hidden,
+                            const float* init, gpbo_mlp* out);
+gpbo_status gpbo_mlp_free(gpbo_mlp mlp);
+/* Number of parameters of one member. */
+int64_t gpbo_mlp_nparams(int32_t d_in, int32_t hidden);
+/* Device copy of the float32 master weights (members x P). */
+gpbo_status gpbo_mlp_params(gpbo_ctx ctx, gpbo_mlp mlp, float* out);
+/* Mean-squared-error loss (1/n) sum (out_i - y_i)^2 of every member on
+ * (X: device n x d_in float, y: device n float) and its gradient with
+ * respect to the master weights.  grad: device members x P float; loss:
+ * device members float. */
+gpbo_status gpbo_mlp_grads(gpbo_ctx ctx, gpbo_mlp mlp, int32_t n, const float* X,
+                           const float* y, float* grad, float* loss);
+/* `steps` full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning
+ * rate lr) on every member.  loss_hist: device steps x members float (the
+ * loss before each step), may be NULL.  The step sequence is captured in a
+ * HIP graph and replayed.  Asynchronous. */
+gpbo_status gpbo_mlp_train(gpbo_ctx ctx, gpbo_mlp mlp, int32_t n, const float* X,
+                           const float* y, int32_t steps, double lr, float* loss_hist);
+/* Member outputs on m candidates: out is device members x m float. */
+gpbo_status gpbo_mlp_forward(gpbo_ctx ctx, gpbo_mlp mlp, int64_t m, const float* Xc,
+                             float* out);
+/* Prescreen: ensemble mean and population standard deviation over members,
+ * EI against f_best (in the network's output units), then the indices of the
+ * k largest EI (device int64, descending EI, ascending index among ties).
+ * ei_out (device m float) may be NULL.  Asynchronous. */
+gpbo_status gpbo_mlp_prescreen(gpbo_ctx ctx, gpbo_mlp mlp, int64_t m, const float* Xc,
+                               double f_best, int64_t k, int64_t* topk_idx, float* ei_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPBO_H */

@@ -1,0 +1,269 @@
+"""Python binding of the gpbo C ABI (``include/gpbo.h``), argument marshalling only.
+
+Every step of fit and scoring runs in the HIP library ``libgpbo.so``; this
+module passes torch tensors' device pointers and torch's current stream to it,
+and gives the library torch's caching allocator for its own device buffers.
+If the library is missing, importing :func:`lib` raises: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgpbo.so")
+
+OK, E_INVALID_ARG, E_NOT_PD, E_NONFINITE, E_OOM, E_HIP, E_UNSUPPORTED = range(7)
+KERNEL_SE, KERNEL_MATERN52 = 0, 1
+FP64, FP32, BF16 = 0, 1, 2
+NSTATS = 7
+PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+
+
+class GpboError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"gpbo status {status}: {msg}")
+        self.status = status
+
+
+class Problem(C.Structure):
+    _fields_ = [("n", C.c_int32), ("d", C.c_int32), ("X", C.c_void_p), ("y", C.c_void_p),
+                ("kernel", C.c_int32), ("lengthscale", C.POINTER(C.c_double)),
+                ("signal_var", C.c_double), ("noise_var", C.c_double),
+                ("normalize_y", C.c_int32), ("refine_alpha", C.c_int32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+_lib = None
+
+# Every symbol the header declares, with its ctypes signature.
+_SIGS = {
+    "gpbo_status_string": (C.c_char_p, [C.c_int]),
+    "gpbo_last_error": (C.c_char_p, [C.c_void_p]),
+    "gpbo_version": (C.c_int32, []),
+    "gpbo_ctx_create": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(Allocator), C.POINTER(C.c_void_p)]),
+    "gpbo_ctx_destroy": (C.c_int, [C.c_void_p]),
+    "gpbo_ctx_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gpbo_fit": (C.c_int, [C.c_void_p, C.POINTER(Problem), C.POINTER(C.c_void_p),
+                           C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "gpbo_fit_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Problem), C.POINTER(C.c_void_p),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "gpbo_model_free": (C.c_int, [C.c_void_p]),
+    "gpbo_model_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "gpbo_model_shape": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "gpbo_model_factors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gpbo_score": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gpbo_score_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p),
+                                     C.POINTER(C.c_int64), C.POINTER(C.c_void_p), C.c_int,
+                                     C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]),
+    "gpbo_topk": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
+    "gpbo_gather_rows": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
+                                   C.c_void_p]),
+    "gpbo_mlp_create": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                  C.POINTER(C.c_void_p)]),
+    "gpbo_mlp_free": (C.c_int, [C.c_void_p]),
+    "gpbo_mlp_nparams": (C.c_int64, [C.c_int32, C.c_int32]),
+    "gpbo_mlp_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gpbo_mlp_grads": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p]),
+    "gpbo_mlp_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                 C.c_int32, C.c_double, C.c_void_p]),
+    "gpbo_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "gpbo_mlp_prescreen": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_double,
+                                     C.c_int64, C.c_void_p, C.c_void_p]),
+}
+
+
+def lib():
+    """Load ``libgpbo.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"gpbo HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """A gpbo context on one device and torch's current stream.
+
+    The library's own buffers come from torch's caching allocator through the
+    allocator callbacks below."""
+
+    def __init__(self, device=0, use_torch_allocator=True):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self._held = {}
+        self._alloc = None
+        if use_torch_allocator:
+            def _a(nbytes, stream, user):
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+                p = t.data_ptr()
+                self._held[p] = t
+                return p
+
+            def _f(ptr, stream, user):
+                self._held.pop(ptr, None)
+
+            self._afn = ALLOC_FN(_a)
+            self._ffn = FREE_FN(_f)
+            self._alloc = Allocator(self._afn, self._ffn, None)
+        h = C.c_void_p()
+        st = lib().gpbo_ctx_create(self.device.index or 0, _stream_handle(self.device),
+                                   C.byref(self._alloc) if self._alloc else None, C.byref(h))
+        if st != OK:
+            raise GpboError(st, lib().gpbo_last_error(None).decode())
+        self.h = h
+
+    def check(self, st):
+        if st != OK:
+            raise GpboError(st, lib().gpbo_last_error(self.h).decode())
+
+    def sync_stream(self):
+        self.check(lib().gpbo_ctx_set_stream(self.h, _stream_handle(self.device)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().gpbo_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Model:
+    """A fitted Gaussian process (owns device copies of X, L, L^-1, alpha)."""
+
+    def __init__(self, ctx: Context, handle, n, d):
+        self.ctx = ctx
+        self.h = handle
+        self.n = n
+        self.d = d
+
+    def stats(self):
+        s = (C.c_double * NSTATS)()
+        self.ctx.check(lib().gpbo_model_stats(self.h, s))
+        keys = ("ymean", "ystd", "fbest", "lml", "logdet", "res0", "res1")
+        return dict(zip(keys, list(s)))
+
+    def factors(self):
+        dev = self.ctx.device
+        L = torch.empty((self.n, self.n), dtype=torch.float64, device=dev)
+        Li = torch.empty_like(L)
+        a = torch.empty(self.n, dtype=torch.float64, device=dev)
+        self.ctx.check(lib().gpbo_model_factors(self.ctx.h, self.h, _ptr(L), _ptr(Li), _ptr(a)))
+        return L, Li, a
+
+    def free(self):
+        if self.h:
+            lib().gpbo_model_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _problem(X, y, lengthscale, kernel, signal_var, noise_var, normalize_y, refine_alpha):
+    assert X.dtype == torch.float64 and y.dtype == torch.float64 and X.is_cuda and y.is_cuda
+    assert X.is_contiguous() and y.is_contiguous()
+    n, d = X.shape
+    ls = (C.c_double * d)(*[float(v) for v in lengthscale])
+    p = Problem(n, d, X.data_ptr(), y.data_ptr(), int(kernel), ls, float(signal_var),
+                float(noise_var), 1 if normalize_y else 0, 1 if refine_alpha else 0)
+    return p, ls
+
+
+def fit(ctx: Context, X, y, lengthscale, kernel=KERNEL_SE, signal_var=1.0, noise_var=1e-4,
+        normalize_y=True, refine_alpha=False):
+    """gpbo_fit: returns a :class:`Model`; raises GpboError (with .bad_pivot on NOT_PD)."""
+    p, _keep = _problem(X, y, lengthscale, kernel, signal_var, noise_var, normalize_y, refine_alpha)
+    h = C.c_void_p()
+    lml = C.c_double()
+    bad = C.c_int32(-1)
+    st = lib().gpbo_fit(ctx.h, C.byref(p), C.byref(h), C.byref(lml), C.byref(bad))
+    if st != OK:
+        err = GpboError(st, lib().gpbo_last_error(ctx.h).decode())
+        err.bad_pivot = bad.value
+        raise err
+    return Model(ctx, h, X.shape[0], X.shape[1])
+
+
+def fit_batched(ctx: Context, problems):
+    """gpbo_fit_batched on a list of dicts with the :func:`fit` arguments."""
+    B = len(problems)
+    arr = (Problem * B)()
+    keep = []
+    for b, pr in enumerate(problems):
+        p, ls = _problem(pr["X"], pr["y"], pr["lengthscale"], pr.get("kernel", KERNEL_SE),
+                         pr.get("signal_var", 1.0), pr.get("noise_var", 1e-4),
+                         pr.get("normalize_y", True), pr.get("refine_alpha", False))
+        arr[b] = p
+        keep.append(ls)
+    hs = (C.c_void_p * B)()
+    lml = (C.c_double * B)()
+    status = (C.c_int32 * B)()
+    st = lib().gpbo_fit_batched(ctx.h, B, arr, hs, lml, status)
+    models = [Model(ctx, C.c_void_p(hs[b]), pr["X"].shape[0], pr["X"].shape[1]) if status[b] == OK
+              else None for b, pr in enumerate(problems)]
+    return st, models, list(status), list(lml)
+
+
+def score(ctx: Context, model: Model, Xc, prec="fp32", want=("mu", "sigma", "ei"), reduce=True):
+    """gpbo_score: posterior mean, sd, EI (device tensors) and the argmax."""
+    pr = PREC[prec] if isinstance(prec, str) else int(prec)
+    odt = torch.float64 if pr == FP64 else torch.float32
+    assert Xc.dtype == odt and Xc.is_contiguous() and Xc.shape[1] == model.d
+    m = Xc.shape[0]
+    out = {k: torch.empty(m, dtype=odt, device=ctx.device) for k in want}
+    am = torch.empty(1, dtype=torch.int64, device=ctx.device) if reduce else None
+    emax = torch.empty(1, dtype=torch.float64, device=ctx.device) if reduce else None
+    ctx.check(lib().gpbo_score(ctx.h, model.h, m, _ptr(Xc), pr, _ptr(out.get("mu")),
+                               _ptr(out.get("sigma")), _ptr(out.get("ei")), _ptr(am), _ptr(emax)))
+    if reduce:
+        out["argmax"] = am
+        out["ei_max"] = emax
+    return out
+
+
+def score_batched(ctx: Context, models, Xcs, prec="bf16", want_ei=True):
+    pr = PREC[prec] if isinstance(prec, str) else int(prec)
+    B = len(models)
+    hs = (C.c_void_p * B)(*[mo.h.value if isinstance(mo.h, C.c_void_p) else mo.h for mo in models])
+    ms = (C.c_int64 * B)(*[x.shape[0] for x in Xcs])
+    xs = (C.c_void_p * B)(*[x.data_ptr() for x in Xcs])
+    eis = [torch.empty(x.shape[0], dtype=torch.float32, device=ctx.device) for x in Xcs] if want_ei else None
+    ep = (C.c_void_p * B)(*[e.data_ptr() for e in eis]) if want_ei else None
+    am = torch.empty(B, dtype=torch.int64, device=ctx.device)
+    emax = torch.empty(B, dtype=torch.float64, device=ctx.device)
+    ctx.check(lib().gpbo_score_batched(ctx.h, B, hs, ms, xs, pr, ep, _ptr(am), _ptr(emax)))
+    return eis, am, emax
