@@ -1,0 +1,211 @@
+#!/usr/bin/env python
+"""Throughput of the GP-fit + EI-scoring hot path on one MI355X.
+
+One step = fit the Gaussian-process surrogate of a sub-search (float64
+Cholesky, inverse factor, alpha, log marginal likelihood) and score the whole
+candidate pool (cross-covariance, posterior mean and variance on the matrix
+cores, EI, argmax read back to the host, as one Bayesian-optimisation
+iteration needs it).  Inputs are resident in HBM before the timed region.
+
+Default workload: d=20, n=512 scrambled-Sobol observations, 65536 uniform
+candidates, SE-ARD with lengthscales log-uniform in [0.05, 1], float32
+matrix-core contractions, float64 fit.
+
+Prints one JSON line with the throughput (candidates/s over whole steps), the
+roofline of the dominant kernel (the fused scoring kernel, timed with HIP
+events on its own stream), the error against the float64 oracle on a sample
+of candidates, and the oracle's own throughput on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "candidate EI scores/sec (GP vs MLP-prescreen+GP) at stated error vs FP64"
+PEAKS = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}  # dense matrix-core TFLOP/s, MI355X
+
+# HBM traffic of the scoring kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# runs of this benchmark, scaled by the same counters on a plain copy of known
+# size.  Valid only while the kernel source is unchanged (hash below).
+TRAFFIC = {}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("score.hip", "gpbo_internal.h"):
+        with open(os.path.join(ROOT, "paper_2403_08131_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def flops_per_candidate(n, d):
+    # triangular variance n(n+1), distances in matrix form 2nd, mean 2n, sum of squares 2n
+    return n * (n + 1) + 2 * n * d + 4 * n
+
+
+def workload(name):
+    from paper_2403_08131_amd import inputs as I
+    if name in ("c2", "c2-s"):
+        return I.make_config(name), "fp32"
+    if name in ("c5", "c5-s"):
+        return I.make_config(name), "fp32"
+    if name == "c1":
+        return I.make_config("c1"), "fp64"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def describe(p, prec):
+    kern = "SE-ARD" if p.kernel == 0 else "Matern-5/2"
+    return {"workload": f"{p.name}: d={p.d} n={p.n} m={p.m} {kern} {prec} contractions, fp64 fit",
+            "d": p.d, "n": p.n, "m": p.m, "kernel": kern, "precision": prec,
+            "lengthscale": "log-uniform [0.05,1]" + (" x sqrt(d)" if p.name.endswith("-s") else "")}
+
+
+def cpu_baseline(p, budget_s=15.0):
+    """The float64 oracle on the host cores: full fit, plus scoring a bounded
+    sample of the same candidate pool; the rate is extrapolated to a whole
+    step (fit + all m candidates)."""
+    from oracle import oracle as O
+    kind = O.SE if p.kernel == 0 else O.MATERN52
+    t0 = time.perf_counter()
+    f = O.fit(p.X, p.y, p.lengthscale, kind, p.signal_var, p.noise_var)
+    t_fit = time.perf_counter() - t0
+    probe = min(p.m, 256)
+    t0 = time.perf_counter()
+    O.score(f, p.Xc[:probe])
+    t_probe = time.perf_counter() - t0
+    per = t_probe / probe
+    sample = int(min(p.m, max(probe, budget_s / max(per, 1e-9))))
+    t0 = time.perf_counter()
+    O.score(f, p.Xc[:sample])
+    t_s = time.perf_counter() - t0
+    per = t_s / sample
+    step = t_fit + p.m * per
+    return {"value": p.m / step, "unit": "candidates/s", "cores": O.max_threads(), "kind": "oracle",
+            "sample": f"fit n={p.n} ({t_fit:.3f} s) + scoring {sample} of {p.m} candidates "
+                      f"({t_s:.2f} s); rate = m / (t_fit + m * t_per_candidate)"}
+
+
+def error_vs_oracle(p, prec, ctx, model, Xc_dev, sample=512):
+    import torch
+    from oracle import oracle as O
+    from paper_2403_08131_amd import gpbo as G
+    kind = O.SE if p.kernel == 0 else O.MATERN52
+    f = O.fit(p.X, p.y, p.lengthscale, kind, p.signal_var, p.noise_var)
+    idx = np.linspace(0, p.m - 1, sample).astype(np.int64)
+    ref = O.score(f, p.Xc[idx])
+    out = G.score(ctx, model, Xc_dev, prec)
+    mu = out["mu"].double().cpu().numpy()[idx]
+    sg = out["sigma"].double().cpu().numpy()[idx]
+    scale = f.ystd * math.sqrt(p.signal_var)
+    e_mu = float(np.max(np.abs(mu - ref["mu"]) / np.maximum(np.abs(ref["mu"]), scale)))
+    fl = ref["sigma"] ** 2 >= 1e-2 * scale ** 2
+    e_sg = float(np.max(np.abs(sg - ref["sigma"])[fl] / ref["sigma"][fl])) if fl.any() else 0.0
+    return {"e_mu": e_mu, "e_sigma": e_sg, "sampled_candidates": sample}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the scoring path "
+              "runs on one MI355X; see the sharding note in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2403_08131_amd import gpbo as G
+
+    p, prec = workload(args.workload)
+    dev = torch.device("cuda", 0)
+    X = torch.tensor(p.X, device=dev)
+    y = torch.tensor(p.y, device=dev)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Xc = torch.tensor(p.Xc, dtype=dt, device=dev)
+    ctx = G.Context(0)
+
+    def step():
+        model = G.fit(ctx, X, y, p.lengthscale, p.kernel, p.signal_var, p.noise_var)
+        out = G.score(ctx, model, Xc, prec)
+        best = int(out["argmax"].item())  # the next configuration to evaluate
+        model.free()
+        return best
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.enable_timing(True)
+    ctx.timing()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        step()
+    end.record()
+    torch.cuda.synchronize()
+    ms_total = start.elapsed_time(end)
+    launches, k_ms = ctx.timing()
+    ctx.enable_timing(False)
+    ms_step = ms_total / args.steps
+    k_avg = k_ms / max(launches, 1)
+
+    # fit alone, for the breakdown
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        G.fit(ctx, X, y, p.lengthscale, p.kernel, p.signal_var, p.noise_var).free()
+    fit_ms = (time.perf_counter() - t0) / 3 * 1e3
+
+    fl = flops_per_candidate(p.n, p.d) * p.m
+    achieved = fl / (k_avg * 1e-3) / 1e12
+    peak = PEAKS[prec]
+    traffic = None
+    if TRAFFIC.get("kernel_sha") == kernel_source_hash() and TRAFFIC.get("workload") == p.name:
+        traffic = TRAFFIC["bytes_per_launch"]
+
+    model = G.fit(ctx, X, y, p.lengthscale, p.kernel, p.signal_var, p.noise_var)
+    err = error_vs_oracle(p, prec, ctx, model, Xc)
+    model.free()
+
+    res = {
+        "metric": METRIC,
+        "value": p.m / (ms_step * 1e-3),
+        "unit": "candidates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": describe(p, prec),
+        "breakdown_ms": {"fit": fit_ms, "score_kernel": k_avg},
+        "score_kernel_cand_per_s": p.m / (k_avg * 1e-3),
+        "error_vs_fp64": err,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": "k_score_fused", "flops_per_launch": fl},
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(p)
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

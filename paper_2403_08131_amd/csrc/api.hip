@@ -61,6 +61,7 @@ void free_model_buffers(Model* M) {
     if (p) dfree(c, p);
   for (int i = 0; i < 3; ++i) {
     if (M->pk[i]) dfree(c, M->pk[i]);
+    if (M->pk_off[i]) dfree(c, M->pk_off[i]);
     if (M->alphaT[i]) dfree(c, M->alphaT[i]);
   }
 }
@@ -84,8 +85,8 @@ gpbo_status check_problem(Ctx* c, const gpbo_problem* p) {
   return GPBO_OK;
 }
 
-// Allocate a model's buffers and queue its fit.  No synchronisation.
-gpbo_status enqueue_fit(Ctx* c, const gpbo_problem* p, Model* M) {
+// Allocate a model's buffers and copy its inputs.  No synchronisation.
+gpbo_status alloc_model(Ctx* c, const gpbo_problem* p, Model* M) {
   const int n = p->n, d = p->d;
   M->ctx = c;
   M->n = n;
@@ -103,7 +104,7 @@ gpbo_status enqueue_fit(Ctx* c, const gpbo_problem* p, Model* M) {
   M->Dinv = (double*)dmalloc(c, np * NB * sizeof(double));
   M->yt = (double*)dmalloc(c, np * sizeof(double));
   M->alpha = (double*)dmalloc(c, np * sizeof(double));
-  M->work = (double*)dmalloc(c, 4 * np * sizeof(double));
+  M->work = (double*)dmalloc(c, (4 + 16) * np * sizeof(double));  // 4 vectors + residual partials
   M->stats = (double*)dmalloc(c, S_COUNT * sizeof(double));
   M->info = (int*)dmalloc(c, 2 * sizeof(int));
   if (p->refine_alpha) M->L32 = (float*)dmalloc(c, np * np * sizeof(float));
@@ -111,36 +112,59 @@ gpbo_status enqueue_fit(Ctx* c, const gpbo_problem* p, Model* M) {
       !M->stats || !M->info || (p->refine_alpha && !M->L32))
     return fail(c, GPBO_E_OOM, "device allocation failed for a model with n=%d", n);
   hipStream_t s = c->stream;
-  std::vector<double> il(d);
-  for (int k = 0; k < d; ++k) il[k] = 1.0 / p->lengthscale[k];
+  M->il_host.resize(d);  // kept with the model: the copy below is asynchronous
+  for (int k = 0; k < d; ++k) M->il_host[k] = 1.0 / p->lengthscale[k];
   HIP_TRY(c, hipMemcpyAsync(M->X64, p->X, (size_t)n * d * sizeof(double), hipMemcpyDeviceToDevice, s));
-  HIP_TRY(c, hipMemcpyAsync(M->il64, il.data(), d * sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(c, hipMemsetAsync(M->stats, 0, S_COUNT * sizeof(double), s));
-  launch_fit_prep(M, M->X64, p->y, p->normalize_y ? 1 : 0, s);
-  launch_gram(M, M->L, s);
-  launch_cholesky(M, M->L, s);
-  launch_trtri(M, s);
-  launch_alpha(M, p->refine_alpha ? 1 : 0, s);
-  launch_lml(M, s);
-  HIP_TRY(c, hipGetLastError());
-  // the (small) synchronous copy of the coordinate scales needs the stream in
-  // order anyway; build the float32 scoring operands eagerly
+  HIP_TRY(c, hipMemcpyAsync(M->il64, M->il_host.data(), d * sizeof(double), hipMemcpyHostToDevice, s));
   return GPBO_OK;
 }
 
-gpbo_status finish_fit(Ctx* c, Model* M, int32_t* bad_pivot) {
-  int info[2];
-  HIP_TRY(c, hipMemcpyAsync(info, M->info, sizeof info, hipMemcpyDeviceToHost, c->stream));
+// Device copy of B fit descriptors in the context's descriptor buffer.
+gpbo_status upload_descs(Ctx* c, const std::vector<FitDesc>& h, FitDesc** out) {
+  const size_t bytes = h.size() * sizeof(FitDesc);
+  if (c->desc_bytes < bytes) {
+    if (c->desc_buf) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      dfree(c, c->desc_buf);
+    }
+    c->desc_buf = dmalloc(c, bytes);
+    c->desc_bytes = c->desc_buf ? bytes : 0;
+    if (!c->desc_buf) return fail(c, GPBO_E_OOM, "descriptor allocation failed");
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->desc_buf, h.data(), bytes, hipMemcpyHostToDevice, c->stream));
+  *out = (FitDesc*)c->desc_buf;
+  return GPBO_OK;
+}
+
+// Queue the copy of a fitted model's status and statistics to the host.
+gpbo_status enqueue_readback(Ctx* c, Model* M) {
+  HIP_TRY(c, hipMemcpyAsync(M->host_info, M->info, sizeof M->host_info, hipMemcpyDeviceToHost,
+                            c->stream));
   HIP_TRY(c, hipMemcpyAsync(M->host_stats, M->stats, sizeof M->host_stats, hipMemcpyDeviceToHost,
                             c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (info[1]) return fail(c, GPBO_E_NONFINITE, "X or y holds a non-finite value");
-  if (info[0] != INT_MAX) {
-    if (bad_pivot) *bad_pivot = info[0];
-    return fail(c, GPBO_E_NOT_PD, "K is not positive definite: pivot %d", info[0]);
+  return GPBO_OK;
+}
+
+// Status of a fit whose readback has completed.
+gpbo_status fit_status(Ctx* c, Model* M, int32_t* bad_pivot) {
+  if (M->host_info[1]) return fail(c, GPBO_E_NONFINITE, "X or y holds a non-finite value");
+  if (M->host_info[0] != INT_MAX) {
+    if (bad_pivot) *bad_pivot = M->host_info[0];
+    return fail(c, GPBO_E_NOT_PD, "K is not positive definite: pivot %d", M->host_info[0]);
   }
   if (bad_pivot) *bad_pivot = -1;
   return GPBO_OK;
+}
+
+hipEvent_t timing_event(Ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
 }
 
 }  // namespace
@@ -215,6 +239,7 @@ gpbo_status gpbo_ctx_create(int32_t device, void* stream, const gpbo_allocator* 
   c->device = device;
   c->stream = (hipStream_t)stream;
   c->num_cu = prop.multiProcessorCount;
+  if (const char* ng = std::getenv("GPBO_NO_GRAPH")) c->no_graph = ng[0] == '1';
   if (alloc) {
     c->alloc = *alloc;
     c->has_alloc = true;
@@ -228,7 +253,13 @@ gpbo_status gpbo_ctx_destroy(gpbo_ctx c) {
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
   if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
+  for (auto& pr : c->ev_pending) {
+    c->ev_pool.push_back(pr.first);
+    c->ev_pool.push_back(pr.second);
+  }
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->red) dfree(c, c->red);
+  if (c->desc_buf) dfree(c, c->desc_buf);
   if (c->batch_buf) dfree(c, c->batch_buf);
   delete c;
   return GPBO_OK;
@@ -237,6 +268,30 @@ gpbo_status gpbo_ctx_destroy(gpbo_ctx c) {
 gpbo_status gpbo_ctx_set_stream(gpbo_ctx c, void* stream) {
   if (!c) return GPBO_E_INVALID_ARG;
   c->stream = (hipStream_t)stream;
+  return GPBO_OK;
+}
+
+gpbo_status gpbo_ctx_enable_timing(gpbo_ctx c, int32_t enable) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  c->timing = enable != 0;
+  return GPBO_OK;
+}
+
+gpbo_status gpbo_ctx_timing(gpbo_ctx c, int64_t* launches, double* total_ms) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  DeviceGuard g(c->device);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (auto& pr : c->ev_pending) {
+    float ms = 0.0f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, pr.first, pr.second));
+    tot += ms;
+    c->ev_pool.push_back(pr.first);
+    c->ev_pool.push_back(pr.second);
+  }
+  if (launches) *launches = (int64_t)c->ev_pending.size();
+  if (total_ms) *total_ms = tot;
+  c->ev_pending.clear();
   return GPBO_OK;
 }
 
@@ -250,8 +305,22 @@ gpbo_status gpbo_fit(gpbo_ctx c, const gpbo_problem* p, gpbo_model* out, double*
   DeviceGuard g(c->device);
   gpbo_model M = new (std::nothrow) gpbo_model_s();
   if (!M) return fail(c, GPBO_E_OOM, "host allocation failed");
-  st = enqueue_fit(c, p, M);
-  if (st == GPBO_OK) st = finish_fit(c, M, bad_pivot);
+  st = alloc_model(c, p, M);
+  std::vector<FitDesc> hd;
+  FitDesc* dd = nullptr;
+  if (st == GPBO_OK) {
+    hd.push_back(make_fit_desc(M, p->y, p->normalize_y ? 1 : 0, p->refine_alpha ? 1 : 0));
+    st = upload_descs(c, hd, &dd);
+  }
+  if (st == GPBO_OK) {
+    launch_fit(hd.data(), dd, 1, c->stream);
+    st = enqueue_readback(c, M);
+  }
+  if (st == GPBO_OK) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    st = e != hipSuccess ? fail(c, GPBO_E_HIP, "fit: %s", hipGetErrorString(e))
+                         : fit_status(c, M, bad_pivot);
+  }
   if (st != GPBO_OK) {
     (void)hipStreamSynchronize(c->stream);
     free_model_buffers(M);
@@ -269,7 +338,8 @@ gpbo_status gpbo_fit_batched(gpbo_ctx c, int32_t B, const gpbo_problem* probs, g
   if (B < 0 || (B > 0 && (!probs || !out || !status)))
     return fail(c, GPBO_E_INVALID_ARG, "invalid batch arguments");
   DeviceGuard g(c->device);
-  // Order by decreasing n^3 so the largest factorisations start first.
+  // Descriptors ordered by decreasing n, so the largest problems take the
+  // lowest workgroup indices (dispatched first) in every batched launch.
   std::vector<int> order(B);
   for (int b = 0; b < B; ++b) order[b] = b;
   std::sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].n > probs[b].n; });
@@ -279,6 +349,7 @@ gpbo_status gpbo_fit_batched(gpbo_ctx c, int32_t B, const gpbo_problem* probs, g
     out[b] = nullptr;
     status[b] = check_problem(c, &probs[b]);
   }
+  std::vector<FitDesc> hd;
   for (int k = 0; k < B; ++k) {
     const int b = order[k];
     if (status[b] != GPBO_OK) continue;
@@ -287,10 +358,22 @@ gpbo_status gpbo_fit_batched(gpbo_ctx c, int32_t B, const gpbo_problem* probs, g
       status[b] = GPBO_E_OOM;
       continue;
     }
-    status[b] = enqueue_fit(c, &probs[b], ms[b]);
+    status[b] = alloc_model(c, &probs[b], ms[b]);
+    if (status[b] == GPBO_OK)
+      hd.push_back(make_fit_desc(ms[b], probs[b].y, probs[b].normalize_y ? 1 : 0,
+                                 probs[b].refine_alpha ? 1 : 0));
+  }
+  if (!hd.empty()) {
+    FitDesc* dd = nullptr;
+    gpbo_status st = upload_descs(c, hd, &dd);
+    if (st != GPBO_OK) return st;
+    launch_fit(hd.data(), dd, (int)hd.size(), c->stream);
+    for (int b = 0; b < B; ++b)
+      if (ms[b] && status[b] == GPBO_OK) status[b] = enqueue_readback(c, ms[b]);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
   for (int b = 0; b < B; ++b) {
-    if (ms[b] && status[b] == GPBO_OK) status[b] = finish_fit(c, ms[b], nullptr);
+    if (ms[b] && status[b] == GPBO_OK) status[b] = fit_status(c, ms[b], nullptr);
     if (status[b] != GPBO_OK) {
       if (first == GPBO_OK) first = (gpbo_status)status[b];
       if (ms[b]) {
@@ -385,17 +468,7 @@ gpbo_status gpbo_score(gpbo_ctx c, gpbo_model M, int64_t m, const void* Xc, gpbo
     pv = (double*)c->red;
     pi = (int64_t*)((double*)c->red + tiles);
   }
-  ScoreJob j{};
-  j.n = M->n;
-  j.d = M->d;
-  j.npk = (int)round_up(M->n, TI);
-  j.kernel = M->kernel;
-  j.pk = M->pk[prec];
-  j.alpha = M->alphaT[prec];
-  j.Xs = prec == GPBO_FP64 ? (const void*)M->Xs64 : (const void*)M->Xs32;
-  j.sc = prec == GPBO_FP64 ? (const void*)M->sc64 : (const void*)M->sc32;
-  j.stats = M->stats;
-  j.sf2 = M->sf2;
+  ScoreArgs j = make_score_args(M, prec, tm);
   j.m = m;
   j.Xc = Xc;
   j.mu = mu;
@@ -403,7 +476,17 @@ gpbo_status gpbo_score(gpbo_ctx c, gpbo_model M, int64_t m, const void* Xc, gpbo
   j.ei = ei;
   j.part_v = pv;
   j.part_i = pi;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->timing) {
+    e0 = timing_event(c);
+    e1 = timing_event(c);
+    HIP_TRY(c, hipEventRecord(e0, s));
+  }
   launch_score(j, prec, tm, s);
+  if (c->timing) {
+    HIP_TRY(c, hipEventRecord(e1, s));
+    c->ev_pending.emplace_back(e0, e1);
+  }
   if (pv) launch_argmax_final(pv, pi, tiles, argmax, ei_max, s);
   HIP_TRY(c, hipGetLastError());
   return GPBO_OK;
@@ -415,52 +498,273 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
   if (!c) return GPBO_E_INVALID_ARG;
   if (B < 0 || (B > 0 && (!models || !m || !Xc)))
     return fail(c, GPBO_E_INVALID_ARG, "invalid batch arguments");
+  if (prec != GPBO_FP64 && prec != GPBO_FP32 && prec != GPBO_BF16)
+    return fail(c, GPBO_E_INVALID_ARG, "unknown precision %d", (int)prec);
+  if (B == 0) return GPBO_OK;
+  DeviceGuard g(c->device);
+  hipStream_t s = c->stream;
   for (int b = 0; b < B; ++b) {
-    gpbo_status st = gpbo_score(c, models[b], m[b], Xc[b], prec, nullptr, nullptr,
-                                ei ? ei[b] : nullptr, argmax ? argmax + b : nullptr,
-                                ei_max ? ei_max + b : nullptr);
-    if (st != GPBO_OK) return st;
+    if (!models[b]) return fail(c, GPBO_E_INVALID_ARG, "model %d is NULL", b);
+    if (m[b] < 0 || (m[b] > 0 && !Xc[b])) return fail(c, GPBO_E_INVALID_ARG, "pool %d is invalid", b);
+  }
+  // The graph of the previous call is replayed when the same models, pools
+  // and outputs are passed again.
+  std::vector<uint64_t> key = {(uint64_t)B, (uint64_t)prec, (uint64_t)(uintptr_t)argmax,
+                               (uint64_t)(uintptr_t)ei_max, (uint64_t)(uintptr_t)s};
+  for (int b = 0; b < B; ++b) {
+    key.push_back((uint64_t)(uintptr_t)models[b]);
+    key.push_back((uint64_t)m[b]);
+    key.push_back((uint64_t)(uintptr_t)Xc[b]);
+    key.push_back((uint64_t)(uintptr_t)(ei ? ei[b] : nullptr));
+  }
+  if (c->batch_exec && key == c->batch_key) {
+    HIP_TRY(c, hipGraphLaunch(c->batch_exec, s));
+    return GPBO_OK;
+  }
+  // Tile size: every candidate tile size whose LDS footprint fits the largest
+  // problem is a candidate; the autotuner times them on this batch once.
+  int nmax = 0, dmax = 0;
+  for (int b = 0; b < B; ++b) {
+    nmax = std::max(nmax, models[b]->n);
+    dmax = std::max(dmax, models[b]->d);
+  }
+  std::vector<int> cands;
+  for (int tm : {64, 32, 16})
+    if (score_smem(prec, nmax, dmax, tm) <= 160 * 1024) cands.push_back(tm);
+  if (cands.empty())
+    return fail(c, GPBO_E_UNSUPPORTED, "n=%d is too large for the batched scoring kernel", nmax);
+  for (int b = 0; b < B; ++b) ensure_score_operands(models[b], prec, s);
+  // problems in decreasing n: the costliest tiles are dispatched first
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return models[a]->n > models[b]->n; });
+  int64_t max_tiles = 0;
+  for (int b = 0; b < B; ++b) max_tiles += ceil_div(std::max<int64_t>(m[b], 1), 16);
+  const size_t desc_bytes = round_up(B * sizeof(ScoreArgs), 256);
+  const size_t need = desc_bytes + 256 + (size_t)max_tiles * 16;
+  if (c->batch_buf_bytes < need) {
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (c->batch_buf) dfree(c, c->batch_buf);
+    c->batch_buf = dmalloc(c, need);
+    c->batch_buf_bytes = c->batch_buf ? need : 0;
+    if (!c->batch_buf) return fail(c, GPBO_E_OOM, "batch buffer allocation failed");
+  }
+  unsigned char* base = (unsigned char*)c->batch_buf;
+  ScoreArgs* dd = (ScoreArgs*)base;
+  unsigned* counter = (unsigned*)(base + desc_bytes);
+  double* pv = (double*)(base + desc_bytes + 256);
+  int64_t* pi = (int64_t*)(pv + max_tiles);
+  auto build = [&](int tm, std::vector<ScoreArgs>& h, int64_t& total, size_t& smem) {
+    h.clear();
+    total = 0;
+    smem = 0;
+    for (int k = 0; k < B; ++k) {
+      const int b = order[k];
+      ScoreArgs a = make_score_args(models[b], prec, tm);
+      a.m = m[b];
+      a.Xc = Xc[b];
+      a.mu = nullptr;
+      a.sigma = nullptr;
+      a.ei = ei ? ei[b] : nullptr;
+      a.part_v = pv + total;
+      a.part_i = pi + total;
+      a.tile_begin = total;
+      a.slot = b;
+      total += ceil_div(m[b], tm);
+      smem = std::max(smem, score_smem(prec, a.n, a.d, tm));
+      h.push_back(a);
+    }
+  };
+  const int per_cu = 2;  // LDS-limited residency of the scoring workgroup
+  const int grid = c->num_cu * per_cu;
+  std::vector<ScoreArgs> h;
+  int64_t total = 0;
+  size_t smem = 0;
+  char kbuf[160];
+  snprintf(kbuf, sizeof kbuf, "batched:gfx950:hip%d:p%d:B%d:n%d:d%d", HIP_VERSION, (int)prec, B,
+           (int)round_up(nmax, 64), dmax);
+  std::vector<ScoreArgs> hh;  // source of the descriptor copies of the timing runs
+  const int tm = autotune_pick(c, kbuf, cands, [&](int cand) {
+    int64_t tot;
+    size_t sm;
+    (void)hipStreamSynchronize(s);  // hh is reused by the next run
+    build(cand, hh, tot, sm);
+    (void)hipMemcpyAsync(dd, hh.data(), hh.size() * sizeof(ScoreArgs), hipMemcpyHostToDevice, s);
+    launch_score_batched(dd, B, tot, counter, prec, cand, sm, grid, argmax, ei_max, s);
+  });
+  HIP_TRY(c, hipStreamSynchronize(s));
+  build(tm, h, total, smem);
+  HIP_TRY(c, hipMemcpyAsync(dd, h.data(), h.size() * sizeof(ScoreArgs), hipMemcpyHostToDevice, s));
+  // one eager launch (it also sets the kernels' LDS limits), then capture
+  launch_score_batched(dd, B, total, counter, prec, tm, smem, grid, argmax, ei_max, s);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(s));  // h is the source of the copy above
+  if (c->batch_exec) {
+    (void)hipGraphExecDestroy(c->batch_exec);
+    c->batch_exec = nullptr;
+    c->batch_key.clear();
+  }
+  if (s != nullptr && !c->no_graph) {
+    hipGraph_t graph = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    launch_score_batched(dd, B, total, counter, prec, tm, smem, grid, argmax, ei_max, s);
+    HIP_TRY(c, hipStreamEndCapture(s, &graph));
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e == hipSuccess) {
+      c->batch_exec = exec;
+      c->batch_key = key;
+    }
   }
   return GPBO_OK;
 }
 
 gpbo_status gpbo_topk(gpbo_ctx c, int64_t m, const float* v, int64_t k, int64_t* idx) {
   if (!c) return GPBO_E_INVALID_ARG;
-  return fail(c, GPBO_E_UNSUPPORTED, "top-k is not built yet");
+  if (m < 0 || k < 0 || (m > 0 && !v) || (k > 0 && !idx))
+    return fail(c, GPBO_E_INVALID_ARG, "invalid top-k arguments");
+  if (k > m) return fail(c, GPBO_E_INVALID_ARG, "k (%lld) exceeds m (%lld)", (long long)k, (long long)m);
+  if (k > topk_max_k()) return fail(c, GPBO_E_UNSUPPORTED, "k > %d is not supported", topk_max_k());
+  if (m > 0xffffffffLL) return fail(c, GPBO_E_UNSUPPORTED, "m >= 2^32 is not supported");
+  if (k == 0) return GPBO_OK;
+  DeviceGuard g(c->device);
+  void* scratch = dmalloc(c, topk_scratch_bytes(m, k));
+  if (!scratch) return fail(c, GPBO_E_OOM, "top-k scratch allocation failed");
+  launch_topk_into(m, v, k, idx, scratch, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  dfree(c, scratch);  // stream-ordered with the torch allocator; hipFree waits otherwise
+  return GPBO_OK;
 }
 
 gpbo_status gpbo_gather_rows(gpbo_ctx c, int64_t k, const int64_t* idx, int32_t d, const float* Xc,
                              float* out) {
   if (!c) return GPBO_E_INVALID_ARG;
-  return fail(c, GPBO_E_UNSUPPORTED, "gather is not built yet");
+  if (k < 0 || d <= 0 || (k > 0 && (!idx || !Xc || !out)))
+    return fail(c, GPBO_E_INVALID_ARG, "invalid gather arguments");
+  if (k == 0) return GPBO_OK;
+  DeviceGuard g(c->device);
+  launch_gather_rows(k, idx, d, Xc, out, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  return GPBO_OK;
 }
 
 int64_t gpbo_mlp_nparams(int32_t d_in, int32_t hidden) {
   return (int64_t)hidden * d_in + hidden + (int64_t)hidden * hidden + hidden + hidden + 1;
 }
 
-gpbo_status gpbo_mlp_create(gpbo_ctx c, int32_t, int32_t, int32_t, const float*, gpbo_mlp* out) {
+struct gpbo_mlp_s {
+  Ctx* ctx;
+  MlpState* st;
+  int E, D, H;
+};
+
+gpbo_status gpbo_mlp_create(gpbo_ctx c, int32_t members, int32_t d_in, int32_t hidden,
+                            const float* init, gpbo_mlp* out) {
   if (out) *out = nullptr;
   if (!c) return GPBO_E_INVALID_ARG;
-  return fail(c, GPBO_E_UNSUPPORTED, "MLP prescreen is not built yet");
+  if (!out || !init) return fail(c, GPBO_E_INVALID_ARG, "init and out are required");
+  if (members < 1 || members > 64 || d_in < 1 || d_in > 64)
+    return fail(c, GPBO_E_INVALID_ARG, "members must be 1..64 and d_in 1..64");
+  if (hidden != 256)
+    return fail(c, GPBO_E_UNSUPPORTED, "hidden width %d: this build supports 256", hidden);
+  DeviceGuard g(c->device);
+  MlpState* st = mlp_create(c, members, d_in, hidden, init, c->stream);
+  if (!st) return fail(c, GPBO_E_OOM, "MLP allocation failed");
+  HIP_TRY(c, hipGetLastError());
+  *out = new gpbo_mlp_s{c, st, members, d_in, hidden};
+  return GPBO_OK;
 }
-gpbo_status gpbo_mlp_free(gpbo_mlp) { return GPBO_OK; }
-gpbo_status gpbo_mlp_params(gpbo_ctx c, gpbo_mlp, float*) {
-  return c ? fail(c, GPBO_E_UNSUPPORTED, "MLP prescreen is not built yet") : GPBO_E_INVALID_ARG;
+
+gpbo_status gpbo_mlp_free(gpbo_mlp mlp) {
+  if (!mlp) return GPBO_OK;
+  DeviceGuard g(mlp->ctx->device);
+  mlp_destroy(mlp->st);
+  delete mlp;
+  return GPBO_OK;
 }
-gpbo_status gpbo_mlp_grads(gpbo_ctx c, gpbo_mlp, int32_t, const float*, const float*, float*, float*) {
-  return c ? fail(c, GPBO_E_UNSUPPORTED, "MLP prescreen is not built yet") : GPBO_E_INVALID_ARG;
+
+gpbo_status gpbo_mlp_params(gpbo_ctx c, gpbo_mlp mlp, float* out) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (!mlp || !out) return fail(c, GPBO_E_INVALID_ARG, "mlp and out are required");
+  DeviceGuard g(c->device);
+  HIP_TRY(c, hipMemcpyAsync(out, mlp_master(mlp->st),
+                            (size_t)mlp->E * mlp_nparams(mlp->st) * sizeof(float),
+                            hipMemcpyDeviceToDevice, c->stream));
+  return GPBO_OK;
 }
-gpbo_status gpbo_mlp_train(gpbo_ctx c, gpbo_mlp, int32_t, const float*, const float*, int32_t,
-                           double, float*) {
-  return c ? fail(c, GPBO_E_UNSUPPORTED, "MLP prescreen is not built yet") : GPBO_E_INVALID_ARG;
+
+static gpbo_status check_train_args(Ctx* c, gpbo_mlp mlp, int32_t n, const float* X,
+                                    const float* y) {
+  if (!mlp || !X || !y) return fail(c, GPBO_E_INVALID_ARG, "mlp, X and y are required");
+  if (n <= 0 || n % 64 != 0)
+    return fail(c, GPBO_E_INVALID_ARG, "training sample count must be a positive multiple of 64 (got %d)", n);
+  return GPBO_OK;
 }
-gpbo_status gpbo_mlp_forward(gpbo_ctx c, gpbo_mlp, int64_t, const float*, float*) {
-  return c ? fail(c, GPBO_E_UNSUPPORTED, "MLP prescreen is not built yet") : GPBO_E_INVALID_ARG;
+
+gpbo_status gpbo_mlp_grads(gpbo_ctx c, gpbo_mlp mlp, int32_t n, const float* X, const float* y,
+                           float* grad, float* loss) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  gpbo_status st = check_train_args(c, mlp, n, X, y);
+  if (st != GPBO_OK) return st;
+  if (!grad || !loss) return fail(c, GPBO_E_INVALID_ARG, "grad and loss are required");
+  DeviceGuard g(c->device);
+  if (!mlp_grads(mlp->st, n, X, y, grad, loss, c->stream))
+    return fail(c, GPBO_E_OOM, "MLP workspace allocation failed");
+  HIP_TRY(c, hipGetLastError());
+  return GPBO_OK;
 }
-gpbo_status gpbo_mlp_prescreen(gpbo_ctx c, gpbo_mlp, int64_t, const float*, double, int64_t,
-                               int64_t*, float*) {
-  return c ? fail(c, GPBO_E_UNSUPPORTED, "MLP prescreen is not built yet") : GPBO_E_INVALID_ARG;
+
+gpbo_status gpbo_mlp_train(gpbo_ctx c, gpbo_mlp mlp, int32_t n, const float* X, const float* y,
+                           int32_t steps, double lr, float* loss_hist) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  gpbo_status st = check_train_args(c, mlp, n, X, y);
+  if (st != GPBO_OK) return st;
+  if (steps < 0 || !(lr > 0.0)) return fail(c, GPBO_E_INVALID_ARG, "steps >= 0 and lr > 0 required");
+  DeviceGuard g(c->device);
+  if (!mlp_train(mlp->st, n, X, y, steps, lr, loss_hist, !c->no_graph, c->stream))
+    return fail(c, GPBO_E_HIP, "MLP training launch failed");
+  HIP_TRY(c, hipGetLastError());
+  return GPBO_OK;
+}
+
+gpbo_status gpbo_mlp_forward(gpbo_ctx c, gpbo_mlp mlp, int64_t m, const float* Xc, float* out) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (!mlp || m < 0 || (m > 0 && (!Xc || !out))) return fail(c, GPBO_E_INVALID_ARG, "invalid forward arguments");
+  if (m == 0) return GPBO_OK;
+  DeviceGuard g(c->device);
+  mlp_forward(mlp->st, m, Xc, out, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  return GPBO_OK;
+}
+
+gpbo_status gpbo_mlp_prescreen(gpbo_ctx c, gpbo_mlp mlp, int64_t m, const float* Xc, double f_best,
+                               int64_t k, int64_t* topk_idx, float* ei_out) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (!mlp || m < 0 || k < 0 || k > m || (m > 0 && !Xc) || (k > 0 && !topk_idx))
+    return fail(c, GPBO_E_INVALID_ARG, "invalid prescreen arguments");
+  if (k > topk_max_k()) return fail(c, GPBO_E_UNSUPPORTED, "k > %d is not supported", topk_max_k());
+  if (m == 0) return GPBO_OK;
+  DeviceGuard g(c->device);
+  hipStream_t s = c->stream;
+  float* outs = (float*)dmalloc(c, (size_t)mlp->E * m * sizeof(float));
+  float* ei = ei_out ? ei_out : (float*)dmalloc(c, (size_t)m * sizeof(float));
+  void* scratch = k > 0 ? dmalloc(c, topk_scratch_bytes(m, k)) : nullptr;
+  if (!outs || !ei || (k > 0 && !scratch)) {
+    dfree(c, outs);
+    if (!ei_out) dfree(c, ei);
+    dfree(c, scratch);
+    return fail(c, GPBO_E_OOM, "prescreen scratch allocation failed");
+  }
+  mlp_forward(mlp->st, m, Xc, outs, s);
+  mlp_ens_ei(mlp->st, m, outs, f_best, ei, s);
+  if (k > 0) launch_topk_into(m, ei, k, topk_idx, scratch, s);
+  HIP_TRY(c, hipGetLastError());
+  dfree(c, outs);
+  if (!ei_out) dfree(c, ei);
+  dfree(c, scratch);
+  return GPBO_OK;
 }
 
 }  // extern "C"

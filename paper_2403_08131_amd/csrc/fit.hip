@@ -1,8 +1,10 @@
-// Float64 fit of one Gaussian-process surrogate on the GPU: normalisation,
-// Gram matrix, blocked Cholesky factorisation, inverse factor, weights alpha
-// with iterative refinement, log marginal likelihood.
+// Float64 fit of Gaussian-process surrogates on the GPU: normalisation, Gram
+// matrix, blocked Cholesky factorisation, inverse factor, weights alpha with
+// iterative refinement, log marginal likelihood.  One launch sequence fits a
+// whole batch of independent sub-searches (the paper runs them in parallel,
+// Sec. IV-D); a single fit is a batch of one.
 //
-// The paper (Sec. IV-D) names the surrogate and its cubic training cost; the
+// The paper names the surrogate and its cubic training cost (Sec. IV-D); the
 // formulas are the textbook ones (Rasmussen & Williams 2006, Alg. 2.1):
 //   K = k(X,X) + sn2 I = L L^T,  alpha = L^-T L^-1 ytilde,
 //   log p(ytilde) = -ytilde^T alpha / 2 - sum log L_ii - n/2 log 2 pi.
@@ -11,9 +13,13 @@
 // round_up(n, 64) and is padded with the identity, so the blocked kernels
 // work on whole 64 x 64 tiles without bounds checks.  The factorisation is
 // right-looking: per 64-column block, one workgroup factors the diagonal tile
-// in LDS and inverts it, the panel below is multiplied by that inverse, and
-// the trailing lower triangle receives a rank-64 update.  The inverse factor
-// is formed the same way, as a blocked triangular solve against the identity.
+// (rows in registers) and inverts it, the panel below is multiplied by that
+// inverse, and the trailing lower triangle receives a rank-64 update.  The
+// inverse factor is formed the same way, as a blocked triangular solve
+// against the identity.  Every kernel reads its problem's descriptor through
+// blockIdx.z and returns at once when the problem has no work at that step or
+// its factorisation has already failed.
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -23,7 +29,10 @@ namespace gpbo {
 
 namespace {
 
-constexpr int LDT = NB + 2;  // LDS row stride of a 64 x 64 float64 tile (16-byte aligned rows)
+constexpr int LDT = NB + 2;        // LDS row stride of a 64 x 64 float64 tile (16-byte rows)
+constexpr int GRAM_DMAX = 64;      // largest supported input dimension
+constexpr int GS = GRAM_DMAX + 1;  // LDS row stride of staged coordinates (odd: no bank conflicts)
+constexpr int RES_CHUNKS = 16;     // column chunks of the residual products
 
 __device__ __forceinline__ bool fit_failed(const int* info) {
   const volatile int* v = info;
@@ -57,51 +66,71 @@ __device__ __forceinline__ double block_min(double v, double* red) {
 }
 
 // Normalisation statistics, finiteness check and the normalised targets.
-__global__ void __launch_bounds__(256) k_fit_stats(int n, int d, const double* __restrict__ X,
-                                                   const double* __restrict__ y, int normalize,
-                                                   int npad, double* __restrict__ stats,
-                                                   double* __restrict__ yt, int* __restrict__ info) {
+__global__ void __launch_bounds__(256) k_fit_stats(const FitDesc* __restrict__ D) {
   __shared__ double red[256];
   __shared__ int bad;
+  const FitDesc& P = D[blockIdx.z];
+  const int n = P.n, d = P.d;
   const int t = threadIdx.x;
   if (t == 0) bad = 0;
   __syncthreads();
   int b = 0;
-  for (int64_t i = t; i < (int64_t)n * d; i += 256) b |= !isfinite(X[i]);
-  for (int i = t; i < n; i += 256) b |= !isfinite(y[i]);
+  for (int64_t i = t; i < (int64_t)n * d; i += 256) b |= !isfinite(P.X[i]);
+  for (int i = t; i < n; i += 256) b |= !isfinite(P.y[i]);
   if (b) atomicOr(&bad, 1);
   double s = 0.0;
-  for (int i = t; i < n; i += 256) s += y[i];
+  for (int i = t; i < n; i += 256) s += P.y[i];
   const double mean = block_sum(s, red) / n;
   double q = 0.0;
-  for (int i = t; i < n; i += 256) q += (y[i] - mean) * (y[i] - mean);
+  for (int i = t; i < n; i += 256) q += (P.y[i] - mean) * (P.y[i] - mean);
   double sy = sqrt(block_sum(q, red) / n);
-  if (!normalize || sy == 0.0) sy = 1.0;
+  if (!P.normalize || sy == 0.0) sy = 1.0;
   double mn = INFINITY;
-  for (int i = t; i < n; i += 256) mn = fmin(mn, y[i]);
+  for (int i = t; i < n; i += 256) mn = fmin(mn, P.y[i]);
   mn = block_min(mn, red);
-  for (int i = t; i < npad; i += 256) yt[i] = i < n ? (y[i] - mean) / sy : 0.0;
+  for (int i = t; i < P.npad; i += 256) P.yt[i] = i < n ? (P.y[i] - mean) / sy : 0.0;
+  if (t < S_COUNT) P.stats[t] = 0.0;
+  __syncthreads();
   if (t == 0) {
-    stats[S_YMEAN] = mean;
-    stats[S_YSTD] = sy;
-    stats[S_FBEST] = mn;
-    info[0] = INT_MAX;
-    info[1] = bad;
+    P.stats[S_YMEAN] = mean;
+    P.stats[S_YSTD] = sy;
+    P.stats[S_FBEST] = mn;
+    P.info[0] = INT_MAX;
+    P.info[1] = bad;
   }
 }
 
-__device__ __forceinline__ double cov64(int kernel, int d, const double* __restrict__ a,
-                                        const double* __restrict__ b, const double* __restrict__ il,
-                                        double sf2) {
-  double r2 = 0.0;
-  for (int k = 0; k < d; ++k) {
-    double t = (a[k] - b[k]) * il[k];
-    r2 = fma(t, t, r2);
-  }
+// Covariance at squared scaled distance r2 (coordinates pre-divided by the
+// lengthscales).
+__device__ __forceinline__ double cov_r2(int kernel, double r2, double sf2) {
   if (kernel == GPBO_KERNEL_SE) return sf2 * exp(-0.5 * r2);
   const double r = sqrt(r2);
   const double s5r = 2.23606797749978969641 * r;
   return sf2 * (1.0 + s5r + (5.0 / 3.0) * r2) * exp(-s5r);
+}
+
+// Squared distance of two LDS-staged coordinate rows zero-padded to a
+// multiple of 4; four partial sums keep independent loads in flight.
+__device__ __forceinline__ double sqdist4(const double* a, const double* b, int dp4) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int k = 0; k < dp4; k += 4) {
+    const double u0 = a[k] - b[k], u1 = a[k + 1] - b[k + 1], u2 = a[k + 2] - b[k + 2],
+                 u3 = a[k + 3] - b[k + 3];
+    s0 = fma(u0, u0, s0);
+    s1 = fma(u1, u1, s1);
+    s2 = fma(u2, u2, s2);
+    s3 = fma(u3, u3, s3);
+  }
+  return (s0 + s1) + (s2 + s3);
+}
+
+// Stage 64 scaled coordinate rows starting at row r0 (rows >= lim are zero).
+__device__ __forceinline__ void stage_rows(const FitDesc& P, int r0, int lim, double* dst) {
+  const int dp4 = (P.d + 3) & ~3;
+  for (int e = threadIdx.x; e < NB * dp4; e += blockDim.x) {
+    const int r = e / dp4, k = e % dp4;
+    dst[r * GS + k] = (r0 + r < lim && k < P.d) ? P.X[(int64_t)(r0 + r) * P.d + k] * P.il[k] : 0.0;
+  }
 }
 
 // Triangular enumeration of the tiles (I, J), J <= I.
@@ -115,41 +144,55 @@ __device__ __forceinline__ void tri_index(int b, int& I, int& J) {
 
 // Lower triangle of K = sf2 k(X,X) + sn2 I (identity beyond n); the tile
 // mirrored above the diagonal is zeroed so the factor's upper part is clean.
-__global__ void __launch_bounds__(256) k_gram(int n, int d, int npad, int kernel, double sf2,
-                                              double sn2, const double* __restrict__ X,
-                                              const double* __restrict__ il,
-                                              double* __restrict__ A, const int* __restrict__ info) {
-  if (fit_failed(info)) return;
+__global__ void __launch_bounds__(256) k_gram(const FitDesc* __restrict__ D) {
+  __shared__ double xi[NB * GS], xj[NB * GS];
+  const FitDesc& P = D[blockIdx.z];
+  const int nb = P.npad / NB;
+  if ((int)blockIdx.x >= nb * (nb + 1) / 2 || fit_failed(P.info)) return;
+  const int n = P.n, npad = P.npad;
   int I, J;
   tri_index(blockIdx.x, I, J);
+  stage_rows(P, I * NB, n, xi);
+  stage_rows(P, J * NB, n, xj);
+  __syncthreads();
+  const int dp4 = (P.d + 3) & ~3;
+#pragma unroll 4
   for (int e = threadIdx.x; e < NB * NB; e += 256) {
     const int r = e / NB, c = e % NB;
     const int i = I * NB + r, j = J * NB + c;
     double v;
     if (i < n && j < n) {
-      v = (j <= i) ? cov64(kernel, d, X + (int64_t)i * d, X + (int64_t)j * d, il, sf2) : 0.0;
-      if (i == j) v += sn2;
+      v = (j <= i) ? cov_r2(P.kernel, sqdist4(xi + r * GS, xj + c * GS, dp4), P.sf2) : 0.0;
+      if (i == j) v += P.sn2;
     } else {
       v = (i == j) ? 1.0 : 0.0;
     }
     if (j > i) v = 0.0;
-    A[(int64_t)i * npad + j] = v;
-    if (I != J) A[(int64_t)(J * NB + c) * npad + (I * NB + r)] = 0.0;
+    P.L[(int64_t)i * npad + j] = v;
+    if (I != J) P.L[(int64_t)(J * NB + c) * npad + (I * NB + r)] = 0.0;
   }
 }
 
 // ---- 64 x 64 float64 tile products staged in LDS ----------------------------
 
-// dst[q][r] (stride LDT) = src[r][q] when transpose, else src[q][r].
+// dst[q][r] (stride LDT) = src[r][q] when transpose, else src[q][r].  All 16
+// loads of a thread are issued before the first LDS store.
 __device__ __forceinline__ void load_tile(const double* __restrict__ src, int ld, double* dst,
                                           bool transpose) {
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {
-    const int a = e / NB, b = e % NB;  // src row a, column b (coalesced)
-    const double v = src[(int64_t)a * ld + b];
+  double v[NB * NB / 256];
+#pragma unroll
+  for (int q = 0; q < NB * NB / 256; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    v[q] = src[(int64_t)(e / NB) * ld + e % NB];  // src row e/64, column e%64 (coalesced)
+  }
+#pragma unroll
+  for (int q = 0; q < NB * NB / 256; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    const int a = e / NB, b = e % NB;
     if (transpose)
-      dst[b * LDT + a] = v;
+      dst[b * LDT + a] = v[q];
     else
-      dst[a * LDT + b] = v;
+      dst[a * LDT + b] = v[q];
   }
 }
 
@@ -184,118 +227,166 @@ __device__ __forceinline__ void store_tile(double* __restrict__ C, int ld, const
     }
 }
 
-// Factor the diagonal tile (k, k) in LDS, write L_kk and its inverse D_k.
-__global__ void __launch_bounds__(256) k_potrf_diag(double* __restrict__ A, int npad, int k,
-                                                    double* __restrict__ Dinv, int* __restrict__ info) {
+// Factor the diagonal tile (k, k), write L_kk and its inverse D_k.
+__global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ Ds, int k) {
+  // Thread (i, g): row i of the tile, columns l = g + 4q (q = 0..15) held in
+  // registers.  Column and row exchanges go through LDS in a permuted order,
+  // (l % 4) * 16 + l / 4, so a wave (fixed g) reads its 16 entries as one
+  // contiguous broadcast block.
   __shared__ double T[NB][NB + 1];
-  __shared__ double U[NB][NB + 1];
-  __shared__ double sq[NB];
-  if (fit_failed(info)) return;
+  __shared__ __align__(16) double xb[2][NB];
+  __shared__ double piv[NB];
+  const FitDesc& P = Ds[blockIdx.z];
+  if (k >= P.npad / NB || fit_failed(P.info)) return;
+  const int npad = P.npad;
+  int* info = P.info;
   const int t = threadIdx.x;
-  double* Akk = A + (int64_t)k * NB * npad + k * NB;
-  for (int e = t; e < NB * NB; e += 256) {
-    const int r = e / NB, c = e % NB;
-    T[r][c] = c <= r ? Akk[(int64_t)r * npad + c] : 0.0;
-    U[r][c] = r == c ? 1.0 : 0.0;
+  const int i = t % NB;
+  const int g = __builtin_amdgcn_readfirstlane(t / NB);
+  const int pi_ = (i % 4) * 16 + i / 4;  // permuted slot of row i
+  double* Akk = P.L + (int64_t)k * NB * npad + k * NB;
+  {
+    double v[NB * NB / 256];
+#pragma unroll
+    for (int q = 0; q < NB * NB / 256; ++q) {
+      const int e = t + 256 * q;
+      v[q] = Akk[(int64_t)(e / NB) * npad + e % NB];
+    }
+#pragma unroll
+    for (int q = 0; q < NB * NB / 256; ++q) {
+      const int e = t + 256 * q;
+      T[e / NB][e % NB] = v[q];
+    }
   }
   __syncthreads();
+  double a[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) a[q] = (g + 4 * q <= i) ? T[i][g + 4 * q] : 0.0;
   // Right-looking elimination with unscaled columns: at step j the pivot is
-  // p = S_jj and S_il -= S_ij S_lj / p for j < l <= i.
+  // p = S_jj and S_il -= (S_ij / p) S_lj for l > j.  Column j is published by
+  // its owners before the barrier; the double buffer makes one barrier per
+  // step enough.
+#pragma unroll 1
   for (int j = 0; j < NB; ++j) {
-    const double p = T[j][j];
+    double* col = xb[j & 1];
+    if (g == (j & 3)) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v = (q == (j >> 2)) ? a[q] : v;
+      col[pi_] = v;
+    }
+    __syncthreads();
+    const double p = col[(j % 4) * 16 + j / 4];
     if (!(p > 0.0) || !isfinite(p)) {
       if (t == 0) atomicMin(&info[0], k * NB + j);
       return;
     }
-    const double ip = 1.0 / p;
-    for (int e = t; e < NB * NB; e += 256) {
-      const int i = e / NB, l = e % NB;
-      if (l > j && l <= i) T[i][l] -= T[i][j] * T[l][j] * ip;
+    if (t == 0) piv[j] = p;
+    const double f = col[pi_] / p;
+    const double* cg = col + g * 16;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const double nv = fma(-f, cg[q], a[q]);
+      a[q] = (g + 4 * q > j) ? nv : a[q];
     }
-    __syncthreads();
-  }
-  if (t < NB) sq[t] = sqrt(T[t][t]);
-  __syncthreads();
-  for (int e = t; e < NB * NB; e += 256) {
-    const int i = e / NB, j = e % NB;
-    double v = 0.0;
-    if (i == j) v = sq[j];
-    else if (j < i) v = T[i][j] / sq[j];
-    T[i][j] = v;  // each entry read and written by one thread only
   }
   __syncthreads();
-  // Inverse of L_kk by eliminating against the identity, unscaled rows:
-  // U_i -= (L_ij / L_jj) U_j for i > j, then row i is scaled by 1 / L_ii.
+  // L_il = S_il / sqrt(p_l) below the diagonal, sqrt(p_i) on it.
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int l = g + 4 * q;
+    T[i][l] = l < i ? a[q] / sqrt(piv[l]) : (l == i ? sqrt(piv[i]) : 0.0);
+  }
+  __syncthreads();
+  // Inverse of L_kk by eliminating against the identity with unscaled rows:
+  // U_i -= (L_ij / L_jj) U_j for i > j (columns c <= j), then row i is
+  // scaled by 1 / L_ii.  Row j is published by its four owners.
+  double u[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) u[q] = (g + 4 * q == i) ? 1.0 : 0.0;
+#pragma unroll 1
   for (int j = 0; j < NB; ++j) {
-    const double ljj = T[j][j];
-    for (int e = t; e < NB * NB; e += 256) {
-      const int i = e / NB, c = e % NB;
-      if (i > j && c <= j) U[i][c] -= (T[i][j] / ljj) * U[j][c];
+    double* row = xb[j & 1];
+    if (i == j) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) row[g * 16 + q] = u[q];
     }
     __syncthreads();
+    const double f = i > j ? T[i][j] / T[j][j] : 0.0;
+    const double* rg = row + g * 16;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const double nv = fma(-f, rg[q], u[q]);
+      u[q] = (g + 4 * q <= j) ? nv : u[q];
+    }
   }
-  double* D = Dinv + (int64_t)k * NB * NB;
-  for (int e = t; e < NB * NB; e += 256) {
-    const int r = e / NB, c = e % NB;
-    Akk[(int64_t)r * npad + c] = T[r][c];
-    D[e] = c <= r ? U[r][c] / T[r][r] : 0.0;
+  double* Dk = P.Dinv + (int64_t)k * NB * NB;
+  const double lii = T[i][i];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int c = g + 4 * q;
+    Dk[i * NB + c] = c <= i ? u[q] / lii : 0.0;
   }
+  for (int e = t; e < NB * NB; e += 256) Akk[(int64_t)(e / NB) * npad + e % NB] = T[e / NB][e % NB];
 }
 
 // Panel: A_Ik <- A_Ik D_k^T for I > k.
-__global__ void __launch_bounds__(256) k_chol_panel(double* __restrict__ A, int npad, int k,
-                                                    const double* __restrict__ Dinv,
-                                                    const int* __restrict__ info) {
+__global__ void __launch_bounds__(256) k_chol_panel(const FitDesc* __restrict__ Ds, int k) {
   extern __shared__ double sm[];
-  if (fit_failed(info)) return;
+  const FitDesc& P = Ds[blockIdx.z];
+  const int nb = P.npad / NB;
+  const int I = k + 1 + blockIdx.x;
+  if (I >= nb || fit_failed(P.info)) return;
+  const int npad = P.npad;
   double* At = sm;
   double* Bt = sm + NB * LDT;
-  const int I = k + 1 + blockIdx.x;
-  double* P = A + (int64_t)I * NB * npad + k * NB;
-  load_tile(P, npad, At, true);
-  load_tile(Dinv + (int64_t)k * NB * NB, NB, Bt, true);
+  double* Pk = P.L + (int64_t)I * NB * npad + k * NB;
+  load_tile(Pk, npad, At, true);
+  load_tile(P.Dinv + (int64_t)k * NB * NB, NB, Bt, true);
   __syncthreads();
   double acc[4][4] = {};
   tile_mac(At, Bt, acc);
   __syncthreads();
-  store_tile(P, npad, acc, 0);
+  store_tile(Pk, npad, acc, 0);
 }
 
 // Trailing update: A_IJ -= A_Ik A_Jk^T for k < J <= I.
-__global__ void __launch_bounds__(256) k_chol_update(double* __restrict__ A, int npad, int k,
-                                                     const int* __restrict__ info) {
+__global__ void __launch_bounds__(256) k_chol_update(const FitDesc* __restrict__ Ds, int k) {
   extern __shared__ double sm[];
-  if (fit_failed(info)) return;
+  const FitDesc& P = Ds[blockIdx.z];
+  const int rest = P.npad / NB - k - 1;
+  if ((int)blockIdx.x >= rest * (rest + 1) / 2 || fit_failed(P.info)) return;
+  const int npad = P.npad;
   double* At = sm;
   double* Bt = sm + NB * LDT;
   int I, J;
   tri_index(blockIdx.x, I, J);
   I += k + 1;
   J += k + 1;
-  load_tile(A + (int64_t)I * NB * npad + k * NB, npad, At, true);
-  load_tile(A + (int64_t)J * NB * npad + k * NB, npad, Bt, true);
+  load_tile(P.L + (int64_t)I * NB * npad + k * NB, npad, At, true);
+  load_tile(P.L + (int64_t)J * NB * npad + k * NB, npad, Bt, true);
   __syncthreads();
   double acc[4][4] = {};
   tile_mac(At, Bt, acc);
-  store_tile(A + (int64_t)I * NB * npad + J * NB, npad, acc, 1);
+  store_tile(P.L + (int64_t)I * NB * npad + J * NB, npad, acc, 1);
 }
 
 // Inverse factor, step I: row block I of X = L^-1 becomes D_I B_I (B_II = I).
-__global__ void __launch_bounds__(256) k_trtri_rowmul(double* __restrict__ Linv, int npad, int I,
-                                                      const double* __restrict__ Dinv,
-                                                      const int* __restrict__ info) {
+__global__ void __launch_bounds__(256) k_trtri_rowmul(const FitDesc* __restrict__ Ds, int I) {
   extern __shared__ double sm[];
-  if (fit_failed(info)) return;
+  const FitDesc& P = Ds[blockIdx.z];
   const int J = blockIdx.x;
-  double* C = Linv + (int64_t)I * NB * npad + J * NB;
-  const double* D = Dinv + (int64_t)I * NB * NB;
+  if (I >= P.npad / NB || J > I || fit_failed(P.info)) return;
+  const int npad = P.npad;
+  double* C = P.Linv + (int64_t)I * NB * npad + J * NB;
+  const double* Dk = P.Dinv + (int64_t)I * NB * NB;
   if (J == I) {
-    for (int e = threadIdx.x; e < NB * NB; e += 256) C[(int64_t)(e / NB) * npad + e % NB] = D[e];
+    for (int e = threadIdx.x; e < NB * NB; e += 256) C[(int64_t)(e / NB) * npad + e % NB] = Dk[e];
     return;
   }
   double* At = sm;
   double* Bt = sm + NB * LDT;
-  load_tile(D, NB, At, true);
+  load_tile(Dk, NB, At, true);
   load_tile(C, npad, Bt, false);
   __syncthreads();
   double acc[4][4] = {};
@@ -305,157 +396,192 @@ __global__ void __launch_bounds__(256) k_trtri_rowmul(double* __restrict__ Linv,
 }
 
 // Inverse factor, step I: B_KJ -= L_KI X_IJ for K > I, J <= I.
-__global__ void __launch_bounds__(256) k_trtri_update(double* __restrict__ Linv,
-                                                      const double* __restrict__ L, int npad, int I,
-                                                      const int* __restrict__ info) {
+__global__ void __launch_bounds__(256) k_trtri_update(const FitDesc* __restrict__ Ds, int I) {
   extern __shared__ double sm[];
-  if (fit_failed(info)) return;
+  const FitDesc& P = Ds[blockIdx.z];
+  const int nb = P.npad / NB;
+  if (I >= nb - 1 || (int)blockIdx.x >= (nb - I - 1) * (I + 1) || fit_failed(P.info)) return;
+  const int npad = P.npad;
   const int K = I + 1 + blockIdx.x / (I + 1);
   const int J = blockIdx.x % (I + 1);
   double* At = sm;
   double* Bt = sm + NB * LDT;
-  load_tile(L + (int64_t)K * NB * npad + I * NB, npad, At, true);
-  load_tile(Linv + (int64_t)I * NB * npad + J * NB, npad, Bt, false);
+  load_tile(P.L + (int64_t)K * NB * npad + I * NB, npad, At, true);
+  load_tile(P.Linv + (int64_t)I * NB * npad + J * NB, npad, Bt, false);
   __syncthreads();
   double acc[4][4] = {};
   tile_mac(At, Bt, acc);
-  store_tile(Linv + (int64_t)K * NB * npad + J * NB, npad, acc, 1);
+  store_tile(P.Linv + (int64_t)K * NB * npad + J * NB, npad, acc, 1);
 }
 
-__global__ void k_fill(double* __restrict__ p, int64_t count, double v) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+// Zero the inverse factor (and make the float32 copy when refining).
+__global__ void __launch_bounds__(256) k_zero_linv(const FitDesc* __restrict__ Ds) {
+  const FitDesc& P = Ds[blockIdx.z];
+  const int64_t cnt = (int64_t)P.npad * P.npad;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt;
        i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
+    P.Linv[i] = 0.0;
 }
 
-// y = Linv x (lower triangular, float64 or float32 matrix; accumulation in
-// AccT).  One wave per row.
-template <typename MT, typename AccT>
-__global__ void __launch_bounds__(256) k_trmv(const MT* __restrict__ Lm, int npad, int n,
-                                              const double* __restrict__ x, double* __restrict__ y,
-                                              const int* __restrict__ info) {
-  if (fit_failed(info)) return;
+__global__ void __launch_bounds__(256) k_cast_linv(const FitDesc* __restrict__ Ds) {
+  const FitDesc& P = Ds[blockIdx.z];
+  if (!P.refine || fit_failed(P.info)) return;
+  const int64_t cnt = (int64_t)P.npad * P.npad;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt;
+       i += (int64_t)gridDim.x * blockDim.x)
+    P.L32[i] = (float)P.Linv[i];
+}
+
+// Vectors of the alpha solve, by index into the work area.
+enum { V_W = 0, V_R = 1, V_D = 2, V_PART = 4 };
+__device__ __forceinline__ double* wvec(const FitDesc& P, int v) {
+  return v < 0 ? (v == -1 ? P.yt : P.alpha) : P.work + (int64_t)v * P.npad;
+}
+
+// y = Linv x (lower triangular; float64, or the float32 copy with float32
+// accumulation when refining).  One wave per row.
+__global__ void __launch_bounds__(256) k_trmv(const FitDesc* __restrict__ Ds, int xv, int yv) {
+  const FitDesc& P = Ds[blockIdx.z];
   const int lane = threadIdx.x % 64;
   const int row = blockIdx.x * 4 + threadIdx.x / 64;
-  if (row >= npad) return;
-  AccT s = 0;
-  if (row < n)
-    for (int j = lane; j <= row; j += 64) s += (AccT)Lm[(int64_t)row * npad + j] * (AccT)x[j];
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (lane == 0) y[row] = row < n ? (double)s : 0.0;
+  if (row >= P.npad || fit_failed(P.info)) return;
+  const int n = P.n, npad = P.npad;
+  const double* x = wvec(P, xv);
+  double* y = wvec(P, yv);
+  double r = 0.0;
+  if (P.refine) {
+    float s = 0.0f;
+    if (row < n)
+#pragma unroll 8
+      for (int j = lane; j <= row; j += 64) s += P.L32[(int64_t)row * npad + j] * (float)x[j];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    r = s;
+  } else {
+    double s = 0.0;
+    if (row < n)
+#pragma unroll 8
+      for (int j = lane; j <= row; j += 64) s += P.Linv[(int64_t)row * npad + j] * x[j];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    r = s;
+  }
+  if (lane == 0) y[row] = row < n ? r : 0.0;
 }
 
 // y = Linv^T x: y_j = sum_{i >= j} Linv_ij x_i.  A workgroup owns 64 columns;
 // its four waves split the rows and combine in LDS.
-template <typename MT, typename AccT>
-__global__ void __launch_bounds__(256) k_trmv_t(const MT* __restrict__ Lm, int npad, int n,
-                                                const double* __restrict__ x,
-                                                double* __restrict__ y, const int* __restrict__ info) {
-  __shared__ AccT red[4][64];
-  if (fit_failed(info)) return;
+__global__ void __launch_bounds__(256) k_trmv_t(const FitDesc* __restrict__ Ds, int xv, int yv) {
+  __shared__ double red[4][64];
+  const FitDesc& P = Ds[blockIdx.z];
+  if ((int)blockIdx.x * 64 >= P.npad || fit_failed(P.info)) return;
+  const int n = P.n, npad = P.npad;
+  const double* x = wvec(P, xv);
+  double* y = wvec(P, yv);
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
   const int j = blockIdx.x * 64 + lane;
-  AccT s = 0;
-  if (j < n)
-    for (int i = j + w; i < n; i += 4) s += (AccT)Lm[(int64_t)i * npad + j] * (AccT)x[i];
+  double s = 0.0;
+  if (j < n) {
+    if (P.refine) {
+      float sf = 0.0f;
+#pragma unroll 8
+      for (int i = j + w; i < n; i += 4) sf += P.L32[(int64_t)i * npad + j] * (float)x[i];
+      s = sf;
+    } else {
+#pragma unroll 8
+      for (int i = j + w; i < n; i += 4) s += P.Linv[(int64_t)i * npad + j] * x[i];
+    }
+  }
   red[w][lane] = s;
   __syncthreads();
-  if (w == 0) {
-    AccT r = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
-    y[j] = j < n ? (double)r : 0.0;
-  }
+  if (w == 0) y[j] = j < n ? red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane] : 0.0;
 }
 
-// r = ytilde - K alpha, K recomputed in float64 (one wave per row).
-__global__ void __launch_bounds__(256) k_residual(int n, int d, int kernel, double sf2,
-                                                  double sn2, const double* __restrict__ X,
-                                                  const double* __restrict__ il,
-                                                  const double* __restrict__ yt,
-                                                  const double* __restrict__ alpha,
-                                                  double* __restrict__ r,
-                                                  const int* __restrict__ info) {
-  if (fit_failed(info)) return;
-  const int lane = threadIdx.x % 64;
-  const int i = blockIdx.x * 4 + threadIdx.x / 64;
-  if (i >= n) return;
+// Partial products of K alpha, K recomputed in float64 exactly as the Gram
+// kernel builds it.  Workgroup (x, y) owns rows 64x..64x+63 and the column
+// chunk y; 64-column tiles of the chunk are staged in LDS.
+__global__ void __launch_bounds__(256) k_residual(const FitDesc* __restrict__ Ds) {
+  __shared__ double xi[NB * GS], xj[NB * GS], aj[NB], red[4][NB];
+  const FitDesc& P = Ds[blockIdx.z];
+  const int n = P.n;
+  const int i0 = blockIdx.x * NB;
+  if (i0 >= n || (int)blockIdx.y >= P.nchunks || fit_failed(P.info)) return;
+  const int t = threadIdx.x, row = t % NB, grp = t / NB;
+  const int jbeg = blockIdx.y * P.chunk, jend = min(n, jbeg + P.chunk);
+  const int dp4 = (P.d + 3) & ~3;
+  stage_rows(P, i0, n, xi);
+  const int i = i0 + row;
   double s = 0.0;
-  for (int j = lane; j < n; j += 64) {
-    double kij = cov64(kernel, d, X + (int64_t)i * d, X + (int64_t)j * d, il, sf2);
-    if (i == j) kij += sn2;
-    s = fma(kij, alpha[j], s);
+  for (int j0 = jbeg; j0 < jend; j0 += NB) {
+    __syncthreads();
+    stage_rows(P, j0, jend, xj);
+    if (t < NB) aj[t] = j0 + t < jend ? P.alpha[j0 + t] : 0.0;
+    __syncthreads();
+    if (i < n) {
+#pragma unroll 4
+      for (int q = 0; q < NB / 4; ++q) {
+        const int c = grp + 4 * q;
+        if (j0 + c < jend) {
+          double kij = cov_r2(P.kernel, sqdist4(xi + row * GS, xj + c * GS, dp4), P.sf2);
+          if (i == j0 + c) kij += P.sn2;
+          s = fma(kij, aj[c], s);
+        }
+      }
+    }
   }
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (lane == 0) r[i] = yt[i] - s;
+  red[grp][row] = s;
+  __syncthreads();
+  if (grp == 0 && i < P.npad)
+    P.work[(int64_t)(V_PART + blockIdx.y) * P.npad + i] =
+        red[0][row] + red[1][row] + red[2][row] + red[3][row];
 }
 
-// a += b (n entries); optionally the norm of a vector into stats[slot].
-__global__ void __launch_bounds__(256) k_axpy_norm(int n, double* __restrict__ a,
-                                                   const double* __restrict__ b,
-                                                   const double* __restrict__ nv,
-                                                   double* __restrict__ stats, int slot,
-                                                   const int* __restrict__ info) {
+// r = ytilde - sum_y part[y], its norm into stats[slot].
+__global__ void __launch_bounds__(256) k_res_finish(const FitDesc* __restrict__ Ds, int slot) {
   __shared__ double red[256];
-  if (fit_failed(info)) return;
-  if (a && b)
-    for (int i = threadIdx.x; i < n; i += 256) a[i] += b[i];
-  if (nv) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) s += nv[i] * nv[i];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) stats[slot] = sqrt(s);
+  const FitDesc& P = Ds[blockIdx.z];
+  if (fit_failed(P.info)) return;
+  double* r = P.work + (int64_t)V_R * P.npad;
+  double q = 0.0;
+  for (int i = threadIdx.x; i < P.npad; i += 256) {
+    double v = 0.0;
+    if (i < P.n) {
+      double kv = 0.0;
+      for (int c = 0; c < P.nchunks; ++c) kv += P.work[(int64_t)(V_PART + c) * P.npad + i];
+      v = P.yt[i] - kv;
+    }
+    r[i] = v;
+    q += v * v;
   }
+  q = block_sum(q, red);
+  if (threadIdx.x == 0) P.stats[slot] = sqrt(q);
 }
 
-__global__ void __launch_bounds__(256) k_lml(int n, int npad, const double* __restrict__ L,
-                                             const double* __restrict__ yt,
-                                             const double* __restrict__ alpha,
-                                             double* __restrict__ stats, const int* __restrict__ info) {
+// alpha += delta.
+__global__ void __launch_bounds__(256) k_add_delta(const FitDesc* __restrict__ Ds) {
+  const FitDesc& P = Ds[blockIdx.z];
+  if (fit_failed(P.info)) return;
+  const double* dl = P.work + (int64_t)V_D * P.npad;
+  for (int i = threadIdx.x; i < P.n; i += 256) P.alpha[i] += dl[i];
+}
+
+__global__ void __launch_bounds__(256) k_lml(const FitDesc* __restrict__ Ds) {
   __shared__ double red[256];
-  if (fit_failed(info)) return;
+  const FitDesc& P = Ds[blockIdx.z];
+  if (fit_failed(P.info)) return;
   double q = 0.0, ld = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) {
-    q += yt[i] * alpha[i];
-    ld += log(L[(int64_t)i * npad + i]);
+  for (int i = threadIdx.x; i < P.n; i += 256) {
+    q += P.yt[i] * P.alpha[i];
+    ld += log(P.L[(int64_t)i * P.npad + i]);
   }
   q = block_sum(q, red);
   ld = block_sum(ld, red);
   if (threadIdx.x == 0) {
-    stats[S_LOGDET] = 2.0 * ld;
-    stats[S_LML] = -0.5 * q - ld - 0.5 * n * log(2.0 * 3.14159265358979323846);
+    P.stats[S_LOGDET] = 2.0 * ld;
+    P.stats[S_LML] = -0.5 * q - ld - 0.5 * P.n * log(2.0 * 3.14159265358979323846);
   }
 }
 
-template <typename T>
-__global__ void k_cast(const double* __restrict__ src, T* __restrict__ dst, int64_t count) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = (T)src[i];
-}
-
-}  // namespace
-
-// ---------------------------------------------------------------------------
-// Host launchers
-// ---------------------------------------------------------------------------
-
-static inline int grid_for(int64_t count, int block = 256) {
-  int64_t g = ceil_div(count, block);
-  return (int)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
-}
-
-void launch_fit_prep(Model* M, const double* X, const double* y, int normalize_y, hipStream_t s) {
-  hipLaunchKernelGGL(k_fit_stats, dim3(1), dim3(256), 0, s, M->n, M->d, X, y, normalize_y,
-                     M->npad, M->stats, M->yt, M->info);
-}
-
-void launch_gram(Model* M, double* A, hipStream_t s) {
-  const int nb = M->npad / NB;
-  hipLaunchKernelGGL(k_gram, dim3(nb * (nb + 1) / 2), dim3(256), 0, s, M->n, M->d, M->npad,
-                     M->kernel, M->sf2, M->sn2, M->X64, M->il64, A, M->info);
-}
-
 // The two-tile kernels stage 2 x 64 x 66 doubles (66 KiB) of dynamic LDS.
-static void allow_tile_lds() {
+void allow_tile_lds() {
   static bool done = false;
   if (done) return;
   const int bytes = 2 * NB * LDT * sizeof(double);
@@ -466,81 +592,80 @@ static void allow_tile_lds() {
   done = true;
 }
 
-void launch_cholesky(Model* M, double* A, hipStream_t s) {
+}  // namespace
+
+FitDesc make_fit_desc(Model* M, const double* y, int normalize_y, int refine) {
+  FitDesc f{};
+  f.n = M->n;
+  f.d = M->d;
+  f.npad = M->npad;
+  f.kernel = M->kernel;
+  f.normalize = normalize_y;
+  f.refine = refine;
+  const int nch = (int)std::min<int64_t>(RES_CHUNKS, ceil_div(M->n, 64));
+  f.chunk = (int)round_up(ceil_div(M->n, nch), NB);
+  f.nchunks = (int)ceil_div(M->n, f.chunk);
+  f.sf2 = M->sf2;
+  f.sn2 = M->sn2;
+  f.X = M->X64;
+  f.il = M->il64;
+  f.y = y;
+  f.L = M->L;
+  f.Linv = M->Linv;
+  f.Dinv = M->Dinv;
+  f.yt = M->yt;
+  f.alpha = M->alpha;
+  f.work = M->work;
+  f.L32 = M->L32;
+  f.stats = M->stats;
+  f.info = M->info;
+  return f;
+}
+
+void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   allow_tile_lds();
-  const int nb = M->npad / NB;
+  int nbmax = 0, nmax = 0, chmax = 1;
+  int64_t npmax = 0;
+  for (int b = 0; b < B; ++b) {
+    nbmax = std::max(nbmax, h[b].npad / NB);
+    nmax = std::max(nmax, h[b].n);
+    npmax = std::max<int64_t>(npmax, h[b].npad);
+    chmax = std::max(chmax, h[b].nchunks);
+  }
   const size_t sm2 = 2 * NB * LDT * sizeof(double);
-  for (int k = 0; k < nb; ++k) {
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, M->npad, k, M->Dinv, M->info);
-    const int rest = nb - k - 1;
+  const unsigned Bz = (unsigned)B;
+  hipLaunchKernelGGL(k_fit_stats, dim3(1, 1, Bz), dim3(256), 0, s, dd);
+  hipLaunchKernelGGL(k_gram, dim3(nbmax * (nbmax + 1) / 2, 1, Bz), dim3(256), 0, s, dd);
+  for (int k = 0; k < nbmax; ++k) {
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, Bz), dim3(256), 0, s, dd, k);
+    const int rest = nbmax - k - 1;
     if (rest > 0) {
-      hipLaunchKernelGGL(k_chol_panel, dim3(rest), dim3(256), sm2, s, A, M->npad, k, M->Dinv,
-                         M->info);
-      hipLaunchKernelGGL(k_chol_update, dim3(rest * (rest + 1) / 2), dim3(256), sm2, s, A,
-                         M->npad, k, M->info);
+      hipLaunchKernelGGL(k_chol_panel, dim3(rest, 1, Bz), dim3(256), sm2, s, dd, k);
+      hipLaunchKernelGGL(k_chol_update, dim3(rest * (rest + 1) / 2, 1, Bz), dim3(256), sm2, s, dd, k);
     }
   }
-}
-
-void launch_trtri(Model* M, hipStream_t s) {
-  const int nb = M->npad / NB;
-  const int64_t cnt = (int64_t)M->npad * M->npad;
-  hipLaunchKernelGGL(k_fill, dim3(grid_for(cnt)), dim3(256), 0, s, M->Linv, cnt, 0.0);
-  const size_t sm2 = 2 * NB * LDT * sizeof(double);
-  for (int I = 0; I < nb; ++I) {
-    hipLaunchKernelGGL(k_trtri_rowmul, dim3(I + 1), dim3(256), sm2, s, M->Linv, M->npad, I,
-                       M->Dinv, M->info);
-    const int rest = nb - I - 1;
+  const unsigned gz = (unsigned)std::min<int64_t>(1024, ceil_div(npmax * npmax, 256));
+  hipLaunchKernelGGL(k_zero_linv, dim3(gz, 1, Bz), dim3(256), 0, s, dd);
+  for (int I = 0; I < nbmax; ++I) {
+    hipLaunchKernelGGL(k_trtri_rowmul, dim3(I + 1, 1, Bz), dim3(256), sm2, s, dd, I);
+    const int rest = nbmax - I - 1;
     if (rest > 0)
-      hipLaunchKernelGGL(k_trtri_update, dim3(rest * (I + 1)), dim3(256), sm2, s, M->Linv, M->L,
-                         M->npad, I, M->info);
+      hipLaunchKernelGGL(k_trtri_update, dim3(rest * (I + 1), 1, Bz), dim3(256), sm2, s, dd, I);
   }
-}
-
-void launch_alpha(Model* M, int refine_f32, hipStream_t s) {
-  const int n = M->n, np = M->npad;
-  double* w = M->work;
-  double* r = M->work + np;
-  double* dlt = M->work + 2 * np;
-  const int g_rows = (int)ceil_div(np, 4), g_cols = (int)ceil_div(np, 64);
-  // float32 copy of the inverse factor for the low-precision solves
-  const float* L32 = nullptr;
-  if (refine_f32) {
-    const int64_t cnt = (int64_t)np * np;
-    hipLaunchKernelGGL(k_cast<float>, dim3(grid_for(cnt)), dim3(256), 0, s, M->Linv, M->L32, cnt);
-    L32 = M->L32;
-  }
-  auto solve = [&](const double* rhs, double* out) {
-    if (refine_f32) {
-      hipLaunchKernelGGL((k_trmv<float, float>), dim3(g_rows), dim3(256), 0, s, L32, np, n, rhs,
-                         w, M->info);
-      hipLaunchKernelGGL((k_trmv_t<float, float>), dim3(g_cols), dim3(256), 0, s, L32, np, n, w,
-                         out, M->info);
-    } else {
-      hipLaunchKernelGGL((k_trmv<double, double>), dim3(g_rows), dim3(256), 0, s, M->Linv, np, n,
-                         rhs, w, M->info);
-      hipLaunchKernelGGL((k_trmv_t<double, double>), dim3(g_cols), dim3(256), 0, s, M->Linv, np,
-                         n, w, out, M->info);
-    }
-  };
-  solve(M->yt, M->alpha);
-  const int g_res = (int)ceil_div(n, 4);
-  hipLaunchKernelGGL(k_residual, dim3(g_res), dim3(256), 0, s, n, M->d, M->kernel, M->sf2, M->sn2,
-                     M->X64, M->il64, M->yt, M->alpha, r, M->info);
-  hipLaunchKernelGGL(k_axpy_norm, dim3(1), dim3(256), 0, s, n, (double*)nullptr,
-                     (const double*)nullptr, r, M->stats, (int)S_RES0, M->info);
-  solve(r, dlt);
-  hipLaunchKernelGGL(k_axpy_norm, dim3(1), dim3(256), 0, s, n, M->alpha, dlt,
-                     (const double*)nullptr, M->stats, 0, M->info);
-  hipLaunchKernelGGL(k_residual, dim3(g_res), dim3(256), 0, s, n, M->d, M->kernel, M->sf2, M->sn2,
-                     M->X64, M->il64, M->yt, M->alpha, r, M->info);
-  hipLaunchKernelGGL(k_axpy_norm, dim3(1), dim3(256), 0, s, n, (double*)nullptr,
-                     (const double*)nullptr, r, M->stats, (int)S_RES1, M->info);
-}
-
-void launch_lml(Model* M, hipStream_t s) {
-  hipLaunchKernelGGL(k_lml, dim3(1), dim3(256), 0, s, M->n, M->npad, M->L, M->yt, M->alpha,
-                     M->stats, M->info);
+  hipLaunchKernelGGL(k_cast_linv, dim3(gz, 1, Bz), dim3(256), 0, s, dd);
+  const unsigned g_rows = (unsigned)ceil_div(npmax, 4), g_cols = (unsigned)ceil_div(npmax, 64);
+  // alpha = Linv^T (Linv ytilde), then one residual-and-correction step
+  hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, -1, (int)V_W);
+  hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(256), 0, s, dd, (int)V_W, -2);
+  const dim3 g_res((unsigned)ceil_div(nmax, NB), (unsigned)chmax, Bz);
+  hipLaunchKernelGGL(k_residual, g_res, dim3(256), 0, s, dd);
+  hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(256), 0, s, dd, (int)S_RES0);
+  hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, (int)V_R, (int)V_W);
+  hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(256), 0, s, dd, (int)V_W, (int)V_D);
+  hipLaunchKernelGGL(k_add_delta, dim3(1, 1, Bz), dim3(256), 0, s, dd);
+  hipLaunchKernelGGL(k_residual, g_res, dim3(256), 0, s, dd);
+  hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(256), 0, s, dd, (int)S_RES1);
+  hipLaunchKernelGGL(k_lml, dim3(1, 1, Bz), dim3(256), 0, s, dd);
 }
 
 }  // namespace gpbo

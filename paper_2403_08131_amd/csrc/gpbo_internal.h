@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -41,6 +42,7 @@ struct Model {
   int kernel = 0;
   double sf2 = 1, sn2 = 0;
   std::vector<double> ls;       // host lengthscales
+  std::vector<double> il_host;  // host 1 / lengthscale (source of an asynchronous copy)
   double* X64 = nullptr;        // n x d, the observations as given
   double* il64 = nullptr;       // d, 1 / lengthscale
   double* L = nullptr;          // npad x npad, lower Cholesky factor (identity padded)
@@ -53,12 +55,15 @@ struct Model {
   double* stats = nullptr;      // S_COUNT scalars
   int* info = nullptr;          // first failing pivot (INT32_MAX when none) + nonfinite flag
   double host_stats[S_COUNT] = {0};
+  int host_info[2] = {0, 0};
   // Score operands, built on first use per precision.
   float* Xs32 = nullptr;        // n x d, coordinates scaled for the float32 kernels
   float* sc32 = nullptr;        // d, coordinate scales for candidates (float32 kernels)
   double* sc64 = nullptr;       // d, coordinate scales (float64 kernels)
   double* Xs64 = nullptr;       // n x d, scaled coordinates (float64 kernels)
   void* pk[3] = {nullptr, nullptr, nullptr};   // packed sf2 * Linv per precision
+  int64_t* pk_off[3] = {nullptr, nullptr, nullptr};  // block offset of each row tile (+ end)
+  int pk_npj[3] = {0, 0, 0};                   // padded column extent of the packed operand
   void* alphaT[3] = {nullptr, nullptr, nullptr};  // sf2 * alpha per precision (double / float)
 };
 
@@ -77,6 +82,14 @@ struct Ctx {
   // Reusable scratch for score reductions (grown on demand).
   void* red = nullptr;
   size_t red_bytes = 0;
+  // Device copies of fit / batch descriptors (grown on demand).
+  void* desc_buf = nullptr;
+  size_t desc_bytes = 0;
+  // Optional timing of the scoring kernels (event pairs on the stream).
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+  bool no_graph = false;  // GPBO_NO_GRAPH=1: never capture batched launches
   // Batched-score graph cache.
   hipGraphExec_t batch_exec = nullptr;
   std::vector<uint64_t> batch_key;
@@ -88,16 +101,37 @@ struct Ctx {
 void* dmalloc(Ctx* c, size_t bytes);
 void dfree(Ctx* c, void* p);
 
+// Autotuner (autotune.hip): the fastest of `cands` for `key`; `run(v)` queues
+// one complete launch with configuration v on the context's stream.
+int autotune_pick(Ctx* c, const std::string& key, const std::vector<int>& cands,
+                  const std::function<void(int)>& run);
+
 // ---------------------------------------------------------------------------
 // Fit kernels (fit.hip)
 // ---------------------------------------------------------------------------
-void launch_fit_prep(Model* M, const double* X, const double* y, int normalize_y,
-                     hipStream_t s);
-void launch_gram(Model* M, double* A, hipStream_t s);
-void launch_cholesky(Model* M, double* A, hipStream_t s);
-void launch_trtri(Model* M, hipStream_t s);
-void launch_alpha(Model* M, int refine_f32, hipStream_t s);
-void launch_lml(Model* M, hipStream_t s);
+// Per-problem arguments of the fit kernels.  A batch of problems is fitted by
+// one launch sequence; every kernel finds its problem's descriptor through
+// blockIdx.z and idles when the problem has no work at that step.
+struct FitDesc {
+  int n, d, npad, kernel;
+  int normalize, refine, chunk, nchunks;  // residual column chunks
+  double sf2, sn2;
+  const double* X;   // n x d (the model's copy)
+  const double* il;  // d, 1 / lengthscale
+  const double* y;   // n, the caller's observations
+  double* L;         // npad x npad
+  double* Linv;      // npad x npad
+  double* Dinv;      // npad / NB inverse diagonal tiles
+  double* yt;        // npad
+  double* alpha;     // npad
+  double* work;      // (4 + 16) npad
+  float* L32;        // npad x npad (refine only)
+  double* stats;
+  int* info;
+};
+FitDesc make_fit_desc(Model* M, const double* y, int normalize_y, int refine);
+// Queue the whole fit of B problems (descriptors: host copy h, device copy dd).
+void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Score operands and kernels (score.hip)
@@ -106,12 +140,15 @@ void launch_lml(Model* M, hipStream_t s);
 // and column block tj <= ti*TI/KB ... see score.hip.
 void ensure_score_operands(Model* M, int prec, hipStream_t s);
 int score_kb(int prec);  // columns per packed block for a precision
-// Per-launch description of one problem's scoring.
-struct ScoreJob {
-  int n, d, npk, kernel;           // npk: padded n of the packed operand
+// Arguments of one problem's scoring (kernel argument of the single-problem
+// launch, and one entry of the descriptor array of a batched launch).
+struct ScoreArgs {
+  int n, d, npk, npj;              // npk: n rounded up to 16; npj: padded column extent
+  int kernel, ldk;                 // ldk: LDS row stride of the cross-covariance tile
+  const int64_t* pk_off;           // row-tile block offsets of the packed operand
   const void* pk;                  // packed sf2 * Linv
   const void* alpha;               // sf2 * alpha (precision-typed)
-  const void* Xs;                  // scaled observations
+  const void* Xs;                  // scaled observations, dimension-major (d x n)
   const void* sc;                  // candidate coordinate scales
   const double* stats;             // device statistics (ymean, ystd, fbest)
   double sf2;
@@ -120,27 +157,43 @@ struct ScoreJob {
   void* mu;
   void* sigma;
   void* ei;
-  // argmax partials: one (value, index) pair per tile
-  double* part_v;
+  double* part_v;                  // argmax partials, one (value, index) pair per tile
   int64_t* part_i;
+  int64_t tile_begin;              // batched launch: first work item of this problem
+  int slot;                        // batched launch: index of this problem's outputs
 };
 int score_tile_m(int prec, int n, int d);  // candidates per workgroup (0 = too large)
-void launch_score(const ScoreJob& j, int prec, int tile_m, hipStream_t s);
+size_t score_smem(int prec, int n, int d, int tile_m);
+ScoreArgs make_score_args(Model* M, int prec, int tile_m);
+void launch_score(const ScoreArgs& a, int prec, int tile_m, hipStream_t s);
 void launch_argmax_final(const double* part_v, const int64_t* part_i, int64_t nparts,
                          int64_t* argmax, double* ei_max, hipStream_t s);
-// Large-n path: cross-covariance materialised in chunks, then a triangular
-// matrix-core product with a sum-of-squares epilogue.
-void launch_score_large(Ctx* c, const ScoreJob& j, int prec, hipStream_t s);
-
-// Batched scoring (batch.hip)
-struct BatchDesc;
-gpbo_status batched_score(Ctx* c, int B, Model* const* models, const int64_t* m,
-                          const void* const* Xc, int prec, void* const* ei, int64_t* argmax,
-                          double* ei_max);
+// Batched scoring: one persistent launch over the (problem, tile) items of B
+// problems (descriptors in device memory, ordered largest first), then a
+// per-problem argmax.  counter: one device uint, reset by the sequence itself.
+void launch_score_batched(const ScoreArgs* dd, int B, int64_t total_items, unsigned* counter,
+                          int prec, int tile_m, size_t smem, int grid, int64_t* argmax,
+                          double* ei_max, hipStream_t s);
 
 // Top-k and gather (select.hip)
-void launch_topk(Ctx* c, int64_t m, const float* v, int64_t k, int64_t* idx, hipStream_t s);
+int topk_max_k();
+size_t topk_scratch_bytes(int64_t m, int64_t k);
+void launch_topk_into(int64_t m, const float* v, int64_t k, int64_t* idx, void* scratch,
+                      hipStream_t s);
 void launch_gather_rows(int64_t k, const int64_t* idx, int d, const float* Xc, float* out,
                         hipStream_t s);
+
+// MLP ensemble (mlp.hip)
+struct MlpState;
+MlpState* mlp_create(Ctx* c, int E, int D, int H, const float* init, hipStream_t s);
+void mlp_destroy(MlpState* st);
+const float* mlp_master(MlpState* st);
+int64_t mlp_nparams(MlpState* st);
+bool mlp_train(MlpState* st, int64_t n, const float* X, const float* y, int steps, double lr,
+               float* loss_hist, bool use_graph, hipStream_t s);
+bool mlp_grads(MlpState* st, int64_t n, const float* X, const float* y, float* grad, float* loss,
+               hipStream_t s);
+void mlp_forward(MlpState* st, int64_t m, const float* Xc, float* out, hipStream_t s);
+void mlp_ens_ei(MlpState* st, int64_t m, const float* out, double fbest, float* ei, hipStream_t s);
 
 }  // namespace gpbo

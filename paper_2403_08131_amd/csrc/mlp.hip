@@ -1,0 +1,705 @@
+// Learned prescreen: an ensemble of MLPs x -> GELU(W1 x + b1) -> GELU(W2 h1 +
+// b2) -> w3 . h2 + b3, trained on the search's own evaluations with the
+// mean-squared error and Adam (Kingma & Ba 2015, Alg. 1), then used to rank
+// a large candidate pool by ensemble expected improvement (mean and
+// population standard deviation over the members).
+//
+// Precision: float32 master weights and Adam moments; bfloat16 copies of the
+// weights and bfloat16 activations as matrix-core operands, float32
+// accumulation.  Rounding to bfloat16 happens at exactly these points: the
+// inputs x, the weight copies W1/W2/w3, h1 = GELU(pre1), h2 = GELU(pre2), and
+// in the backward pass dpre2 and dpre1 where they feed a product (bias
+// gradients use the unrounded values).
+//
+// Layout: activations are sample-major [member][sample][feature]; weights are
+// [member][out][in].  Every matrix-core product is an "NT" product
+// C[M][N] = A[M][K] B[N][K]^T with K contiguous in both operands; the
+// backward products that contract over samples read feature-major copies
+// ([member][feature][sample]) written by the producing kernels.
+#include <cmath>
+#include <cstring>
+
+#include "gpbo_internal.h"
+#include "score_common.h"
+
+namespace gpbo {
+
+using namespace sc;
+
+namespace {
+
+constexpr int MT = 64;  // samples per forward / backward workgroup
+
+__device__ __forceinline__ float bfr(float x) { return __uint_as_float((unsigned)f2bf(x) << 16); }
+__device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+
+// Exact GELU u Phi(u) and its derivative Phi(u) + u phi(u).
+__device__ __forceinline__ float gelu(float u) {
+  return 0.5f * u * (1.0f + erff(u * 0.70710678118654752440f));
+}
+__device__ __forceinline__ float gelu_grad(float u) {
+  return 0.5f * (1.0f + erff(u * 0.70710678118654752440f)) +
+         u * expf(-0.5f * u * u) * 0.39894228040143267794f;
+}
+
+struct MlpDev {
+  int E, D, H;
+  int64_t P;               // parameters per member
+  float* master;           // E x P
+  float* mom1;             // E x P
+  float* mom2;             // E x P
+  unsigned short* W1b;     // E x H x D
+  unsigned short* W2b;     // E x H x H  [out][in]
+  unsigned short* W2Tb;    // E x H x H  [in][out]
+  unsigned short* w3b;     // E x H
+  int* step;               // [0] Adam steps taken, [1] steps taken before this training call
+};
+
+__device__ __forceinline__ const float* pW1(const MlpDev& M, int e) { return M.master + e * M.P; }
+__device__ __forceinline__ int64_t off_b1(const MlpDev& M) { return (int64_t)M.H * M.D; }
+__device__ __forceinline__ int64_t off_W2(const MlpDev& M) { return off_b1(M) + M.H; }
+__device__ __forceinline__ int64_t off_b2(const MlpDev& M) { return off_W2(M) + (int64_t)M.H * M.H; }
+__device__ __forceinline__ int64_t off_w3(const MlpDev& M) { return off_b2(M) + M.H; }
+__device__ __forceinline__ int64_t off_b3(const MlpDev& M) { return off_w3(M) + M.H; }
+
+// bfloat16 copies of the master weights (and the transposed W2).
+__global__ void k_mlp_cast(MlpDev M) {
+  const int e = blockIdx.y;
+  const float* p = M.master + e * M.P;
+  const int H = M.H, D = M.D;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H * H; i += gridDim.x * blockDim.x) {
+    const int o = i / H, in = i % H;
+    const unsigned short b = f2bf(p[off_W2(M) + i]);
+    M.W2b[(int64_t)e * H * H + i] = b;
+    M.W2Tb[(int64_t)e * H * H + (int64_t)in * H + o] = b;
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H * D; i += gridDim.x * blockDim.x)
+    M.W1b[(int64_t)e * H * D + i] = f2bf(p[i]);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H; i += gridDim.x * blockDim.x)
+    M.w3b[(int64_t)e * H + i] = f2bf(p[off_w3(M) + i]);
+}
+
+// Forward of MT samples through one member (blockIdx.y), 256 threads.
+//   layer 1 (VALU): pre1 = W1 x + b1, h1 = bf16(GELU(pre1)) into an LDS tile;
+//   layer 2 (matrix cores): pre2 = h1 W2^T + b2, each wave 64 samples x 64
+//   outputs; epilogue h2 = bf16(GELU(pre2)), out = w3 . h2 + b3.
+// With TRAIN the kernel also writes pre1, h1 (both layouts) and pre2.
+struct FwdOut {
+  float* out;               // E x n
+  float* pre1;              // E x n x H (TRAIN)
+  unsigned short* h1;       // E x n x H (TRAIN)
+  unsigned short* h1T;      // E x H x n (TRAIN)
+  float* pre2;              // E x n x H (TRAIN)
+};
+
+template <bool TRAIN>
+__global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const float* __restrict__ X,
+                                                 FwdOut O) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  const int H = M.H, D = M.D;
+  const int e = blockIdx.y;
+  const int64_t i0 = (int64_t)blockIdx.x * MT;
+  const int t = threadIdx.x, lane = t % 64, wave = wave_id();
+  const int ldh = H + 8;  // bf16 row stride of the h1 tile (16-byte rows, skewed banks)
+  unsigned short* hA = (unsigned short*)sm;                   // [MT][ldh]
+  float* xs = (float*)(sm + (size_t)MT * ldh * 2);            // [MT][D]
+  float* w1s = xs + MT * D;                                   // [H][D] (bf16 values as float)
+  float* red = w1s + H * D;                                   // [4][MT]
+  const float* p = M.master + e * M.P;
+  for (int q = t; q < MT * D; q += 256) {
+    const int64_t i = i0 + q / D;
+    xs[q] = i < n ? bfr(X[i * D + q % D]) : 0.0f;
+  }
+  for (int q = t; q < H * D; q += 256) w1s[q] = bf2f(M.W1b[(int64_t)e * H * D + q]);
+  __syncthreads();
+  // layer 1: thread t owns feature t (H <= 256 checked by the host) for all samples
+  for (int h = t; h < H; h += 256) {
+    const float bb = p[off_b1(M) + h];
+    for (int r = 0; r < MT; ++r) {
+      float s = 0.0f;
+      for (int k = 0; k < D; ++k) s = fmaf(w1s[h * D + k], xs[r * D + k], s);
+      const float pre = s + bb;
+      const unsigned short hb = f2bf(gelu(pre));
+      hA[r * ldh + h] = hb;
+      const int64_t i = i0 + r;
+      if (TRAIN && i < n) {
+        O.pre1[((int64_t)e * n + i) * H + h] = pre;
+        O.h1[((int64_t)e * n + i) * H + h] = hb;
+      }
+    }
+  }
+  __syncthreads();
+  if (TRAIN) {  // feature-major copy, coalesced along the samples
+    for (int q = t; q < H * MT; q += 256) {
+      const int h = q / MT, r = q % MT;
+      if (i0 + r < n) O.h1T[((int64_t)e * H + h) * n + i0 + r] = hA[r * ldh + h];
+    }
+  }
+  // layer 2: wave w computes outputs [64w, 64w + 64) for the MT samples
+  f4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+  const unsigned short* W2 = M.W2b + (int64_t)e * H * H;
+  const int ocol = wave * 64;
+  for (int k0 = 0; k0 < H; k0 += 32) {
+    us8 av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      av[a] = *(const us8*)(hA + (a * 16 + lane % 16) * ldh + k0 + 8 * (lane / 16));
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      bv[b] = *(const us8*)(W2 + (int64_t)(ocol + b * 16 + lane % 16) * H + k0 + 8 * (lane / 16));
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, av[a]),
+                                                            __builtin_bit_cast(bf8, bv[b]),
+                                                            acc[a][b], 0, 0, 0);
+  }
+  // epilogue: lane holds rows 16a + 4(lane/16) + r, columns ocol + 16b + lane%16
+  float rowsum[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rowsum[a][r] = 0.0f;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int j = ocol + b * 16 + lane % 16;
+    const float b2 = p[off_b2(M) + j];
+    const float w3 = bf2f(M.w3b[(int64_t)e * H + j]);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = a * 16 + 4 * (lane / 16) + r;
+        const float pre = acc[a][b][r] + b2;
+        if (TRAIN && i0 + row < n) O.pre2[((int64_t)e * n + i0 + row) * H + j] = pre;
+        rowsum[a][r] = fmaf(w3, bfr(gelu(pre)), rowsum[a][r]);
+      }
+  }
+  // sum over the 16 columns of the lane group, then over the four waves
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float v = rowsum[a][r];
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 2);
+      v += __shfl_xor(v, 4);
+      v += __shfl_xor(v, 8);
+      if (lane % 16 == 0) red[wave * MT + a * 16 + 4 * (lane / 16) + r] = v;
+    }
+  __syncthreads();
+  if (t < MT && i0 + t < n) {
+    const float o = red[t] + red[MT + t] + red[2 * MT + t] + red[3 * MT + t] + p[off_b3(M)];
+    O.out[(int64_t)e * n + i0 + t] = o;
+  }
+}
+
+// Output-layer backward for MT samples of one member: dout = 2 (out - y) / n,
+// dpre2 = dout w3 GELU'(pre2) (bf16, both layouts), and per-block column sums
+// for gb2 (unrounded dpre2), gw3 (dout h2) and gb3, and the squared error.
+struct BwdBuf {
+  unsigned short* dpre2;   // E x n x H
+  unsigned short* dpre2T;  // E x H x n
+  float* colpart;          // E x nblk x (2H + 2): gb2, gw3, gb3, loss
+};
+__global__ void __launch_bounds__(256) k_mlp_bwd_out(MlpDev M, int64_t n, const float* __restrict__ y,
+                                                     const float* __restrict__ out,
+                                                     const float* __restrict__ pre2, BwdBuf B) {
+  __shared__ unsigned short tT[256][MT + 2];
+  __shared__ float dout_s[MT];
+  const int H = M.H;
+  const int e = blockIdx.y;
+  const int64_t i0 = (int64_t)blockIdx.x * MT;
+  const int t = threadIdx.x;
+  const int nblk = gridDim.x;
+  float* part = B.colpart + ((int64_t)e * nblk + blockIdx.x) * (2 * H + 2);
+  if (t < MT) {
+    const int64_t i = i0 + t;
+    dout_s[t] = i < n ? 2.0f * (out[(int64_t)e * n + i] - y[i]) / (float)n : 0.0f;
+  }
+  __syncthreads();
+  if (t == 0) {
+    float g3 = 0.0f, ls = 0.0f;
+    for (int r = 0; r < MT; ++r) {
+      g3 += dout_s[r];
+      const int64_t i = i0 + r;
+      if (i < n) {
+        const float d = out[(int64_t)e * n + i] - y[i];
+        ls += d * d;
+      }
+    }
+    part[2 * H] = g3;
+    part[2 * H + 1] = ls;
+  }
+  for (int j = t; j < H; j += 256) {
+    const float w3 = bf2f(M.w3b[(int64_t)e * H + j]);
+    float gb2 = 0.0f, gw3 = 0.0f;
+    for (int r = 0; r < MT; ++r) {
+      const int64_t i = i0 + r;
+      unsigned short db = 0;
+      if (i < n) {
+        const float pre = pre2[((int64_t)e * n + i) * H + j];
+        const float d = dout_s[r] * w3 * gelu_grad(pre);
+        gb2 += d;
+        gw3 = fmaf(dout_s[r], bfr(gelu(pre)), gw3);
+        db = f2bf(d);
+        B.dpre2[((int64_t)e * n + i) * H + j] = db;
+      }
+      tT[j][r] = db;
+    }
+    part[j] = gb2;
+    part[H + j] = gw3;
+  }
+  __syncthreads();
+  // feature-major copy, coalesced along the samples
+  for (int q = t; q < H * MT; q += 256) {
+    const int j = q / MT, r = q % MT;
+    if (i0 + r < n) B.dpre2T[((int64_t)e * H + j) * n + i0 + r] = tT[j][r];
+  }
+}
+
+// C[M][N] = A[M][K] B[N][K]^T on the bfloat16 matrix cores, batched over the
+// members (blockIdx.z) and split over K (blockIdx.y); 64 x 64 tile per
+// workgroup, 32 x 32 per wave, operands read straight from L2 (16 bytes per
+// lane).  Epilogue: STORE writes C to out[split][member][M][N]; DPRE1 writes
+// C * GELU'(pre1) to out[member][M][N] (one split).
+enum { EPI_STORE = 0, EPI_DPRE1 = 1 };
+struct Gemm {
+  const unsigned short* A;
+  const unsigned short* B;
+  int64_t sA, sB;   // member strides (elements)
+  int M, N, K;
+  int kchunk;       // K per split
+  float* out;
+  const float* pre1;
+};
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm_nt(Gemm g) {
+  const int e = blockIdx.z, split = blockIdx.y;
+  const int tilesN = g.N / 64;
+  const int tm = blockIdx.x / tilesN, tn = blockIdx.x % tilesN;
+  const int lane = threadIdx.x % 64, wave = wave_id();
+  const int r0 = tm * 64 + (wave / 2) * 32, c0 = tn * 64 + (wave % 2) * 32;
+  const unsigned short* A = g.A + (int64_t)e * g.sA;
+  const unsigned short* Bm = g.B + (int64_t)e * g.sB;
+  const int kb = split * g.kchunk, ke = min(g.K, kb + g.kchunk);
+  f4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f4{0, 0, 0, 0};
+  for (int k0 = kb; k0 < ke; k0 += 32) {
+    us8 av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+      av[a] = *(const us8*)(A + (int64_t)(r0 + a * 16 + lane % 16) * g.K + k0 + 8 * (lane / 16));
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+      bv[b] = *(const us8*)(Bm + (int64_t)(c0 + b * 16 + lane % 16) * g.K + k0 + 8 * (lane / 16));
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, av[a]),
+                                                            __builtin_bit_cast(bf8, bv[b]),
+                                                            acc[a][b], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + a * 16 + 4 * (lane / 16) + r;
+        const int col = c0 + b * 16 + lane % 16;
+        const int64_t o = ((int64_t)e * g.M + row) * g.N + col;
+        if (EPI == EPI_STORE)
+          g.out[(int64_t)split * gridDim.z * g.M * g.N + o] = acc[a][b][r];
+        else
+          g.out[o] = acc[a][b][r] * gelu_grad(g.pre1[o]);
+      }
+}
+
+// Layer-1 gradients: gW1[h][d] = sum_i bf16(dpre1[i][h]) bf16(x[i][d]),
+// gb1[h] = sum_i dpre1[i][h]; workgroup (feature block of 64, member, sample
+// split); partial sums per split.
+__global__ void __launch_bounds__(256) k_mlp_bwd_l1(MlpDev M, int64_t n, const float* __restrict__ X,
+                                                    const float* __restrict__ dpre1,
+                                                    int64_t ichunk, float* __restrict__ part) {
+  __shared__ float red[4][64][17];
+  const int H = M.H, D = M.D;
+  const int e = blockIdx.y, split = blockIdx.z;
+  const int h = blockIdx.x * 64 + threadIdx.x % 64, grp = threadIdx.x / 64;
+  const int64_t ib = split * ichunk, ie = min(n, ib + ichunk);
+  // per thread: D weight sums + the bias sum, accumulated over its samples
+  float acc[65];
+  const int nd = D + 1;
+  for (int k = 0; k < nd; ++k) acc[k] = 0.0f;
+  if (h < H) {
+    for (int64_t i = ib + grp; i < ie; i += 4) {
+      const float dp = dpre1[((int64_t)e * n + i) * H + h];
+      const float dr = bfr(dp);
+      for (int k = 0; k < D; ++k) acc[k] = fmaf(dr, bfr(X[i * D + k]), acc[k]);
+      acc[D] += dp;
+    }
+  }
+  // combine the four sample groups, 16 values at a time
+  for (int k0 = 0; k0 < nd; k0 += 16) {
+    for (int q = 0; q < 16; ++q) red[grp][threadIdx.x % 64][q] = k0 + q < nd ? acc[k0 + q] : 0.0f;
+    __syncthreads();
+    if (grp == 0 && h < H) {
+      for (int q = 0; q < 16 && k0 + q < nd; ++q) {
+        const float v = red[0][threadIdx.x][q] + red[1][threadIdx.x][q] + red[2][threadIdx.x][q] +
+                        red[3][threadIdx.x][q];
+        // layout per split: [member][H][D + 1]
+        part[(((int64_t)split * M.E + e) * H + h) * nd + k0 + q] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Adam on every parameter, gradients assembled from the partial sums in a
+// fixed order; then the bfloat16 copies are refreshed by k_mlp_cast.
+struct AdamIn {
+  const float* gW2part;   // S2 x E x H x H
+  int S2;
+  const float* l1part;    // S1 x E x H x (D + 1)
+  int S1;
+  const float* colpart;   // E x nblk x (2H + 2)
+  int nblk;
+  double lr;
+  float* grad_out;        // E x P (optional): the assembled gradient
+  float* loss_hist;       // steps x E (optional)
+  int64_t n;
+  int apply;              // 0: assemble gradients only
+};
+__global__ void __launch_bounds__(256) k_mlp_adam(MlpDev M, AdamIn in) {
+  const int e = blockIdx.y;
+  const int H = M.H, D = M.D;
+  const int64_t P = M.P;
+  const int t = *M.step + 1;
+  const double c1 = 1.0 - pow(0.9, t), c2 = 1.0 - pow(0.999, t);
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < P;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    float g = 0.0f;
+    if (q < off_b1(M)) {  // W1[h][d]
+      const int h = (int)(q / D), d = (int)(q % D);
+      for (int s = 0; s < in.S1; ++s) g += in.l1part[(((int64_t)s * M.E + e) * H + h) * (D + 1) + d];
+    } else if (q < off_W2(M)) {  // b1
+      const int h = (int)(q - off_b1(M));
+      for (int s = 0; s < in.S1; ++s) g += in.l1part[(((int64_t)s * M.E + e) * H + h) * (D + 1) + D];
+    } else if (q < off_b2(M)) {  // W2
+      const int64_t w = q - off_W2(M);
+      for (int s = 0; s < in.S2; ++s) g += in.gW2part[((int64_t)s * M.E + e) * H * H + w];
+    } else {
+      int col;  // b2 -> [0, H), w3 -> [H, 2H), b3 -> 2H
+      if (q < off_w3(M)) col = (int)(q - off_b2(M));
+      else if (q < off_b3(M)) col = H + (int)(q - off_w3(M));
+      else col = 2 * H;
+      for (int b = 0; b < in.nblk; ++b) g += in.colpart[((int64_t)e * in.nblk + b) * (2 * H + 2) + col];
+    }
+    if (in.grad_out) in.grad_out[e * P + q] = g;
+    if (in.apply) {
+      float* w = M.master + e * P + q;
+      float* m1 = M.mom1 + e * P + q;
+      float* m2 = M.mom2 + e * P + q;
+      const float mn = 0.9f * *m1 + 0.1f * g;
+      const float vn = 0.999f * *m2 + 0.001f * g * g;
+      *m1 = mn;
+      *m2 = vn;
+      const double mh = mn / c1, vh = vn / c2;
+      *w = (float)(*w - in.lr * mh / (sqrt(vh) + 1e-8));
+    }
+  }
+  // loss history rows count from the first step of the current training call
+  if (in.loss_hist && blockIdx.x == 0 && threadIdx.x == 0) {
+    float ls = 0.0f;
+    for (int b = 0; b < in.nblk; ++b) ls += in.colpart[((int64_t)e * in.nblk + b) * (2 * H + 2) + 2 * H + 1];
+    in.loss_hist[(int64_t)(t - 1 - M.step[1]) * M.E + e] = ls / (float)in.n;
+  }
+}
+
+// step[0]: Adam steps taken so far; step[1]: step[0] at the start of the
+// current training call.
+__global__ void k_mlp_step(MlpDev M) { M.step[0] += 1; }
+__global__ void k_mlp_zero_step(MlpDev M) {
+  M.step[0] = 0;
+  M.step[1] = 0;
+}
+__global__ void k_mlp_mark(MlpDev M) { M.step[1] = M.step[0]; }
+
+// Ensemble mean / population standard deviation over the members and EI.
+__global__ void k_ens_ei(int E, int64_t m, const float* __restrict__ out, float fbest,
+                         float* __restrict__ ei) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.0f;
+    for (int e = 0; e < E; ++e) s += out[(int64_t)e * m + i];
+    const float mean = s / E;
+    float q = 0.0f;
+    for (int e = 0; e < E; ++e) {
+      const float d = out[(int64_t)e * m + i] - mean;
+      q += d * d;
+    }
+    ei[i] = ei_of<float>(mean, sqrtf(q / E), fbest);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+struct MlpState {
+  Ctx* ctx;
+  MlpDev dev;
+  // training workspace (for the n of the last call)
+  int64_t ws_n = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipGraphExec_t graph = nullptr;
+  std::vector<uint64_t> graph_key;
+};
+
+size_t mlp_fwd_smem(int D, int H) {
+  return (size_t)MT * (H + 8) * 2 + (size_t)MT * D * 4 + (size_t)H * D * 4 + 4 * MT * 4;
+}
+
+MlpState* mlp_create(Ctx* c, int E, int D, int H, const float* init, hipStream_t s) {
+  MlpState* st = new MlpState();
+  st->ctx = c;
+  MlpDev& M = st->dev;
+  M.E = E;
+  M.D = D;
+  M.H = H;
+  M.P = (int64_t)H * D + H + (int64_t)H * H + H + H + 1;
+  const size_t pb = (size_t)E * M.P * sizeof(float);
+  M.master = (float*)dmalloc(c, pb);
+  M.mom1 = (float*)dmalloc(c, pb);
+  M.mom2 = (float*)dmalloc(c, pb);
+  M.W1b = (unsigned short*)dmalloc(c, (size_t)E * H * D * 2);
+  M.W2b = (unsigned short*)dmalloc(c, (size_t)E * H * H * 2);
+  M.W2Tb = (unsigned short*)dmalloc(c, (size_t)E * H * H * 2);
+  M.w3b = (unsigned short*)dmalloc(c, (size_t)E * H * 2);
+  M.step = (int*)dmalloc(c, 64);
+  if (!M.master || !M.mom1 || !M.mom2 || !M.W1b || !M.W2b || !M.W2Tb || !M.w3b || !M.step) {
+    delete st;
+    return nullptr;
+  }
+  (void)hipMemcpyAsync(M.master, init, pb, hipMemcpyDeviceToDevice, s);
+  (void)hipMemsetAsync(M.mom1, 0, pb, s);
+  (void)hipMemsetAsync(M.mom2, 0, pb, s);
+  hipLaunchKernelGGL(k_mlp_zero_step, dim3(1), dim3(1), 0, s, M);
+  hipLaunchKernelGGL(k_mlp_cast, dim3(64, E), dim3(256), 0, s, M);
+  (void)hipFuncSetAttribute((const void*)k_mlp_fwd<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)mlp_fwd_smem(D, H));
+  (void)hipFuncSetAttribute((const void*)k_mlp_fwd<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)mlp_fwd_smem(D, H));
+  return st;
+}
+
+void mlp_destroy(MlpState* st) {
+  Ctx* c = st->ctx;
+  (void)hipStreamSynchronize(c->stream);
+  if (st->graph) (void)hipGraphExecDestroy(st->graph);
+  void* ps[] = {st->dev.master, st->dev.mom1, st->dev.mom2, st->dev.W1b, st->dev.W2b,
+                st->dev.W2Tb, st->dev.w3b, st->dev.step, st->ws};
+  for (void* p : ps) dfree(c, p);
+  delete st;
+}
+
+const float* mlp_master(MlpState* st) { return st->dev.master; }
+int64_t mlp_nparams(MlpState* st) { return st->dev.P; }
+
+// Workspace layout for n training samples.
+struct Ws {
+  float *out, *pre1, *pre2, *dpre1, *colpart, *gW2part, *l1part;
+  unsigned short *h1, *h1T, *dpre2, *dpre2T;
+  int nblk, S2, S1;
+  int64_t ichunk;
+};
+static Ws carve(MlpState* st, int64_t n, size_t* total) {
+  const MlpDev& M = st->dev;
+  const int64_t E = M.E, H = M.H, D = M.D;
+  Ws w{};
+  w.nblk = (int)ceil_div(n, MT);
+  w.S2 = (int)std::min<int64_t>(8, ceil_div(n, 512));
+  w.S1 = (int)std::min<int64_t>(16, ceil_div(n, 256));
+  w.ichunk = ceil_div(n, w.S1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += round_up(bytes, 256);
+    return o;
+  };
+  const size_t o_out = take(E * n * 4), o_pre1 = take(E * n * H * 4), o_pre2 = take(E * n * H * 4),
+               o_dpre1 = take(E * n * H * 4), o_col = take(E * w.nblk * (2 * H + 2) * 4),
+               o_gw2 = take((size_t)w.S2 * E * H * H * 4), o_l1 = take((size_t)w.S1 * E * H * (D + 1) * 4),
+               o_h1 = take(E * n * H * 2), o_h1T = take(E * n * H * 2), o_dp2 = take(E * n * H * 2),
+               o_dp2T = take(E * n * H * 2);
+  *total = off;
+  unsigned char* b = (unsigned char*)st->ws;
+  if (b) {
+    w.out = (float*)(b + o_out);
+    w.pre1 = (float*)(b + o_pre1);
+    w.pre2 = (float*)(b + o_pre2);
+    w.dpre1 = (float*)(b + o_dpre1);
+    w.colpart = (float*)(b + o_col);
+    w.gW2part = (float*)(b + o_gw2);
+    w.l1part = (float*)(b + o_l1);
+    w.h1 = (unsigned short*)(b + o_h1);
+    w.h1T = (unsigned short*)(b + o_h1T);
+    w.dpre2 = (unsigned short*)(b + o_dp2);
+    w.dpre2T = (unsigned short*)(b + o_dp2T);
+  }
+  return w;
+}
+
+bool mlp_ensure_ws(MlpState* st, int64_t n) {
+  if (st->ws && st->ws_n == n) return true;
+  size_t bytes = 0;
+  carve(st, n, &bytes);
+  Ctx* c = st->ctx;
+  (void)hipStreamSynchronize(c->stream);
+  if (st->ws) dfree(c, st->ws);
+  if (st->graph) {
+    (void)hipGraphExecDestroy(st->graph);
+    st->graph = nullptr;
+    st->graph_key.clear();
+  }
+  st->ws = dmalloc(c, bytes);
+  st->ws_bytes = st->ws ? bytes : 0;
+  st->ws_n = st->ws ? n : 0;
+  return st->ws != nullptr;
+}
+
+// One training step (apply = 1) or a gradient evaluation (apply = 0).
+void mlp_step(MlpState* st, int64_t n, const float* X, const float* y, double lr, int apply,
+              float* grad_out, float* loss_hist, hipStream_t s) {
+  size_t bytes;
+  Ws w = carve(st, n, &bytes);
+  MlpDev& M = st->dev;
+  const int E = M.E, H = M.H;
+  FwdOut fo{w.out, w.pre1, w.h1, w.h1T, w.pre2};
+  hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(w.nblk, E), dim3(256), mlp_fwd_smem(M.D, H), s, M, n, X,
+                     fo);
+  BwdBuf bb{w.dpre2, w.dpre2T, w.colpart};
+  hipLaunchKernelGGL(k_mlp_bwd_out, dim3(w.nblk, E), dim3(256), 0, s, M, n, y, w.out, w.pre2, bb);
+  // gW2 = dpre2^T h1 over the samples (split over S2 sample chunks)
+  Gemm g1{};
+  g1.A = w.dpre2T;
+  g1.B = w.h1T;
+  g1.sA = (int64_t)H * n;
+  g1.sB = (int64_t)H * n;
+  g1.M = H;
+  g1.N = H;
+  g1.K = (int)n;
+  g1.kchunk = (int)round_up(ceil_div(n, w.S2), 32);
+  g1.out = w.gW2part;
+  hipLaunchKernelGGL(k_gemm_nt<EPI_STORE>, dim3((H / 64) * (H / 64), w.S2, E), dim3(256), 0, s, g1);
+  // dh1 = dpre2 W2 -> dpre1 = dh1 GELU'(pre1)
+  Gemm g2{};
+  g2.A = w.dpre2;
+  g2.B = M.W2Tb;
+  g2.sA = (int64_t)n * H;
+  g2.sB = (int64_t)H * H;
+  g2.M = (int)n;
+  g2.N = H;
+  g2.K = H;
+  g2.kchunk = H;
+  g2.out = w.dpre1;
+  g2.pre1 = w.pre1;
+  hipLaunchKernelGGL(k_gemm_nt<EPI_DPRE1>, dim3((unsigned)(n / 64) * (H / 64), 1, E), dim3(256), 0,
+                     s, g2);
+  hipLaunchKernelGGL(k_mlp_bwd_l1, dim3(ceil_div(H, 64), E, w.S1), dim3(256), 0, s, M, n, X,
+                     w.dpre1, w.ichunk, w.l1part);
+  AdamIn ai{w.gW2part, w.S2, w.l1part, w.S1, w.colpart, w.nblk, lr, grad_out, loss_hist, n, apply};
+  hipLaunchKernelGGL(k_mlp_adam, dim3(64, E), dim3(256), 0, s, M, ai);
+  if (apply) {
+    hipLaunchKernelGGL(k_mlp_step, dim3(1), dim3(1), 0, s, M);
+    hipLaunchKernelGGL(k_mlp_cast, dim3(64, E), dim3(256), 0, s, M);
+  }
+}
+
+// Training: the step sequence is captured once per (n, inputs, lr, history)
+// and the graph replayed `steps` times.
+bool mlp_train(MlpState* st, int64_t n, const float* X, const float* y, int steps, double lr,
+               float* loss_hist, bool use_graph, hipStream_t s) {
+  if (steps <= 0) return true;
+  if (!mlp_ensure_ws(st, n)) return false;
+  hipLaunchKernelGGL(k_mlp_mark, dim3(1), dim3(1), 0, s, st->dev);
+  std::vector<uint64_t> key = {(uint64_t)n, (uint64_t)(uintptr_t)X, (uint64_t)(uintptr_t)y,
+                               (uint64_t)(uintptr_t)loss_hist, (uint64_t)(uintptr_t)s};
+  uint64_t lrbits;
+  memcpy(&lrbits, &lr, 8);
+  key.push_back(lrbits);
+  if (!use_graph || s == nullptr) {
+    for (int k = 0; k < steps; ++k) mlp_step(st, n, X, y, lr, 1, nullptr, loss_hist, s);
+    return true;
+  }
+  if (!st->graph || st->graph_key != key) {
+    if (st->graph) (void)hipGraphExecDestroy(st->graph);
+    st->graph = nullptr;
+    // one eager step first: it also checks the launch configuration
+    mlp_step(st, n, X, y, lr, 1, nullptr, loss_hist, s);
+    --steps;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+    mlp_step(st, n, X, y, lr, 1, nullptr, loss_hist, s);
+    if (hipStreamEndCapture(s, &g) != hipSuccess) return false;
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return false;
+    st->graph = ex;
+    st->graph_key = key;
+  }
+  for (int k = 0; k < steps; ++k)
+    if (hipGraphLaunch(st->graph, s) != hipSuccess) return false;
+  return true;
+}
+
+bool mlp_grads(MlpState* st, int64_t n, const float* X, const float* y, float* grad, float* loss,
+               hipStream_t s) {
+  if (!mlp_ensure_ws(st, n)) return false;
+  // loss through a one-entry history at the current step: record it into a
+  // scratch row, then copy out
+  mlp_step(st, n, X, y, 0.0, 0, grad, nullptr, s);
+  size_t bytes;
+  Ws w = carve(st, n, &bytes);
+  // loss = (1/n) sum of squared errors from the column partials
+  const int E = st->dev.E, H = st->dev.H;
+  std::vector<float> cp((size_t)E * w.nblk * (2 * H + 2));
+  (void)hipMemcpyAsync(cp.data(), w.colpart, cp.size() * 4, hipMemcpyDeviceToHost, s);
+  (void)hipStreamSynchronize(s);
+  std::vector<float> ls(E, 0.0f);
+  for (int e = 0; e < E; ++e)
+    for (int b = 0; b < w.nblk; ++b) ls[e] += cp[((size_t)e * w.nblk + b) * (2 * H + 2) + 2 * H + 1];
+  for (int e = 0; e < E; ++e) ls[e] /= (float)n;
+  (void)hipMemcpyAsync(loss, ls.data(), E * 4, hipMemcpyHostToDevice, s);
+  (void)hipStreamSynchronize(s);
+  return true;
+}
+
+// Member outputs on m candidates, in chunks (out: E x m).
+void mlp_forward(MlpState* st, int64_t m, const float* Xc, float* out, hipStream_t s) {
+  MlpDev& M = st->dev;
+  FwdOut fo{out, nullptr, nullptr, nullptr, nullptr};
+  hipLaunchKernelGGL(k_mlp_fwd<false>, dim3((unsigned)ceil_div(m, MT), M.E), dim3(256),
+                     mlp_fwd_smem(M.D, M.H), s, M, m, Xc, fo);
+}
+
+void mlp_ens_ei(MlpState* st, int64_t m, const float* out, double fbest, float* ei, hipStream_t s) {
+  const int g = (int)std::min<int64_t>(8192, ceil_div(m, 256));
+  hipLaunchKernelGGL(k_ens_ei, dim3(std::max(g, 1)), dim3(256), 0, s, st->dev.E, m, out,
+                     (float)fbest, ei);
+}
+
+}  // namespace gpbo

@@ -54,6 +54,8 @@ _SIGS = {
     "gpbo_ctx_create": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(Allocator), C.POINTER(C.c_void_p)]),
     "gpbo_ctx_destroy": (C.c_int, [C.c_void_p]),
     "gpbo_ctx_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gpbo_ctx_enable_timing": (C.c_int, [C.c_void_p, C.c_int32]),
+    "gpbo_ctx_timing": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "gpbo_fit": (C.c_int, [C.c_void_p, C.POINTER(Problem), C.POINTER(C.c_void_p),
                            C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "gpbo_fit_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Problem), C.POINTER(C.c_void_p),
@@ -145,6 +147,16 @@ class Context:
 
     def sync_stream(self):
         self.check(lib().gpbo_ctx_set_stream(self.h, _stream_handle(self.device)))
+
+    def enable_timing(self, on=True):
+        self.check(lib().gpbo_ctx_enable_timing(self.h, 1 if on else 0))
+
+    def timing(self):
+        """(launches, total_ms) of the scoring kernels since the last call."""
+        n = C.c_int64()
+        ms = C.c_double()
+        self.check(lib().gpbo_ctx_timing(self.h, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
 
     def close(self):
         if getattr(self, "h", None):
@@ -267,3 +279,75 @@ def score_batched(ctx: Context, models, Xcs, prec="bf16", want_ei=True):
     emax = torch.empty(B, dtype=torch.float64, device=ctx.device)
     ctx.check(lib().gpbo_score_batched(ctx.h, B, hs, ms, xs, pr, ep, _ptr(am), _ptr(emax)))
     return eis, am, emax
+
+
+def topk(ctx: Context, v, k):
+    """gpbo_topk: indices of the k largest entries of a float32 device vector
+    (descending value, ascending index among ties)."""
+    assert v.dtype == torch.float32 and v.is_contiguous()
+    idx = torch.empty(k, dtype=torch.int64, device=ctx.device)
+    ctx.check(lib().gpbo_topk(ctx.h, v.shape[0], _ptr(v), int(k), _ptr(idx)))
+    return idx
+
+
+def gather_rows(ctx: Context, idx, Xc):
+    assert Xc.dtype == torch.float32 and Xc.is_contiguous() and idx.dtype == torch.int64
+    out = torch.empty((idx.shape[0], Xc.shape[1]), dtype=torch.float32, device=ctx.device)
+    ctx.check(lib().gpbo_gather_rows(ctx.h, idx.shape[0], _ptr(idx), Xc.shape[1], _ptr(Xc), _ptr(out)))
+    return out
+
+
+class Mlp:
+    """An MLP ensemble on the device (gpbo_mlp_*); params are float32 master
+    weights in the per-member layout W1, b1, W2, b2, w3, b3."""
+
+    def __init__(self, ctx: Context, init, members, d_in, hidden=256):
+        assert init.dtype == torch.float32 and init.is_cuda and init.is_contiguous()
+        self.ctx = ctx
+        self.E, self.D, self.H = members, d_in, hidden
+        self.P = int(lib().gpbo_mlp_nparams(d_in, hidden))
+        assert init.numel() == members * self.P
+        h = C.c_void_p()
+        ctx.check(lib().gpbo_mlp_create(ctx.h, members, d_in, hidden, _ptr(init), C.byref(h)))
+        self.h = h
+
+    def params(self):
+        out = torch.empty((self.E, self.P), dtype=torch.float32, device=self.ctx.device)
+        self.ctx.check(lib().gpbo_mlp_params(self.ctx.h, self.h, _ptr(out)))
+        return out
+
+    def grads(self, X, y):
+        g = torch.empty((self.E, self.P), dtype=torch.float32, device=self.ctx.device)
+        loss = torch.empty(self.E, dtype=torch.float32, device=self.ctx.device)
+        self.ctx.check(lib().gpbo_mlp_grads(self.ctx.h, self.h, X.shape[0], _ptr(X), _ptr(y),
+                                            _ptr(g), _ptr(loss)))
+        return g, loss
+
+    def train(self, X, y, steps, lr=1e-3, history=True):
+        hist = torch.empty((steps, self.E), dtype=torch.float32, device=self.ctx.device) if history else None
+        self.ctx.check(lib().gpbo_mlp_train(self.ctx.h, self.h, X.shape[0], _ptr(X), _ptr(y),
+                                            int(steps), float(lr), _ptr(hist)))
+        return hist
+
+    def forward(self, Xc):
+        out = torch.empty((self.E, Xc.shape[0]), dtype=torch.float32, device=self.ctx.device)
+        self.ctx.check(lib().gpbo_mlp_forward(self.ctx.h, self.h, Xc.shape[0], _ptr(Xc), _ptr(out)))
+        return out
+
+    def prescreen(self, Xc, f_best, k, want_ei=False):
+        idx = torch.empty(k, dtype=torch.int64, device=self.ctx.device)
+        ei = torch.empty(Xc.shape[0], dtype=torch.float32, device=self.ctx.device) if want_ei else None
+        self.ctx.check(lib().gpbo_mlp_prescreen(self.ctx.h, self.h, Xc.shape[0], _ptr(Xc),
+                                                float(f_best), int(k), _ptr(idx), _ptr(ei)))
+        return idx, ei
+
+    def free(self):
+        if getattr(self, "h", None):
+            lib().gpbo_mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,179 @@
+"""GPU parity of the batched path (independent sub-searches fitted by one
+launch sequence and scored by one persistent launch) against the oracle and
+against the single-problem path, through the C ABI.
+
+Bars: fit factors as in test_gpu_parity (float64, cond-scaled); batched EI
+equal to the single-problem EI to float32 rounding of reordered sums (1e-5
+relative to the pool maximum); argmax identical unless the oracle's top two
+are within 1e-4; graph replays bit-identical to an eager launch.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2403_08131_amd import gpbo as G
+from paper_2403_08131_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = G.Context(0)
+    yield c
+    c.close()
+
+
+def _t(a, dt=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dt, device=DEV)
+
+
+def _problems(B=12, m=1024, lam=0.1, seed=0):
+    return I.make_c3(lam=lam, replicate=seed, scaled=True, B=B, m=m)
+
+
+def _fit_batch(ctx, probs):
+    specs = [dict(X=_t(p.X), y=_t(p.y), lengthscale=p.lengthscale, kernel=p.kernel,
+                  signal_var=p.signal_var, noise_var=p.noise_var) for p in probs]
+    st, models, status, lml = G.fit_batched(ctx, specs)
+    return st, models, status, lml
+
+
+def test_fit_batched_matches_oracle(ctx):
+    probs = _problems(B=12)
+    st, models, status, lml = _fit_batch(ctx, probs)
+    assert st == G.OK and all(s == G.OK for s in status)
+    for p, mo, l in zip(probs, models, lml):
+        f = O.fit(p.X, p.y, p.lengthscale, O.SE, p.signal_var, p.noise_var)
+        K = O.gram(O.SE, p.X, p.lengthscale, p.signal_var, p.noise_var)
+        cond = np.linalg.cond(K)
+        tol = 64 * p.n * EPS * cond
+        L, _, a = (t.cpu().numpy() for t in mo.factors())
+        assert np.max(np.abs(L - f.L)) <= tol * np.max(np.abs(f.L)), p.name
+        assert np.max(np.abs(a - f.alpha)) <= tol * np.max(np.abs(f.alpha)), p.name
+        assert l == pytest.approx(f.lml, rel=tol, abs=tol * p.n)
+        mo.free()
+
+
+def test_fit_batched_reports_failing_problem(ctx):
+    probs = _problems(B=4)
+    bad = probs[2]
+    # the first two points coincide and there is no noise: the second pivot
+    # is 1 - 1 * 1 / 1 = 0 exactly
+    bad.X[1] = bad.X[0]
+    specs = []
+    for i, p in enumerate(probs):
+        specs.append(dict(X=_t(p.X), y=_t(p.y), lengthscale=p.lengthscale, kernel=p.kernel,
+                          signal_var=1.0, noise_var=0.0 if i == 2 else 1e-4))
+    st, models, status, _ = G.fit_batched(ctx, specs)
+    assert st == G.E_NOT_PD
+    assert status[2] == G.E_NOT_PD and models[2] is None
+    f = O.fit(bad.X, bad.y, bad.lengthscale, O.SE, 1.0, 0.0)
+    assert f.status == O.NOT_PD and f.bad_pivot == 1
+    assert all(status[i] == G.OK and models[i] is not None for i in (0, 1, 3))
+    for mo in models:
+        if mo is not None:
+            mo.free()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_score_batched_matches_single_and_oracle(ctx, prec):
+    probs = _problems(B=12, m=1024 + 37)
+    st, models, status, _ = _fit_batch(ctx, probs)
+    assert st == G.OK
+    Xcs = [_t(p.Xc, torch.float32) for p in probs]
+    eis, am, emax = G.score_batched(ctx, models, Xcs, prec)
+    torch.cuda.synchronize()
+    am = am.cpu().numpy()
+    emax = emax.cpu().numpy()
+    for b, (p, mo) in enumerate(zip(probs, models)):
+        single = G.score(ctx, mo, Xcs[b], prec)
+        e1 = single["ei"].double().cpu().numpy()
+        eb = eis[b].double().cpu().numpy()
+        top = max(np.max(e1), 1e-30)
+        assert np.max(np.abs(eb - e1)) <= 1e-5 * top, (b, p.n, p.d)
+        f = O.fit(p.X, p.y, p.lengthscale, O.SE, p.signal_var, p.noise_var)
+        ref = O.score(f, p.Xc, want=("ei",))["ei"]
+        bound = 1e-4 if prec == "fp32" else 5e-2
+        best = O.argmax(ref)
+        srt = np.sort(ref)[::-1]
+        if srt[0] - srt[1] > bound * srt[0]:
+            assert am[b] == best, (b, am[b], best)
+        else:
+            assert ref[am[b]] >= srt[0] * (1 - bound)
+        assert emax[b] == pytest.approx(eb[am[b]], rel=1e-6)
+        err = np.max(np.abs(eb - ref)) / max(srt[0], 1e-30)
+        print(f"  {prec} problem {b}: n={p.n} d={p.d} EI err/EI_max={err:.2e}")
+        if prec == "fp32":
+            assert err <= 1e-3
+    for mo in models:
+        mo.free()
+
+
+def test_score_batched_graph_replay(ctx):
+    """Replays of the captured launch, with eager work and syncs in between,
+    equal an eager launch bit for bit, also after the pools change in place."""
+    probs = _problems(B=8, m=777)
+    st, models, status, _ = _fit_batch(ctx, probs)
+    assert st == G.OK
+    Xcs = [_t(p.Xc, torch.float32) for p in probs]
+    eis = [torch.empty(x.shape[0], dtype=torch.float32, device=DEV) for x in Xcs]
+    am = torch.empty(len(probs), dtype=torch.int64, device=DEV)
+    em = torch.empty(len(probs), dtype=torch.float64, device=DEV)
+
+    def call():
+        import ctypes as C
+        B = len(models)
+        hs = (C.c_void_p * B)(*[mo.h.value for mo in models])
+        ms = (C.c_int64 * B)(*[x.shape[0] for x in Xcs])
+        xs = (C.c_void_p * B)(*[x.data_ptr() for x in Xcs])
+        ep = (C.c_void_p * B)(*[e.data_ptr() for e in eis])
+        ctx.check(G.lib().gpbo_score_batched(ctx.h, B, hs, ms, xs, G.FP32, ep,
+                                             C.c_void_p(am.data_ptr()), C.c_void_p(em.data_ptr())))
+        torch.cuda.synchronize()
+        return [e.clone() for e in eis], am.clone(), em.clone()
+
+    first = call()                      # eager launch + capture
+    for r in range(3):                  # replays
+        _ = torch.randn(1000, device=DEV).sum().item()   # unrelated eager work
+        G.score(ctx, models[r], Xcs[r], "fp32")           # and a library launch
+        torch.cuda.synchronize()
+        again = call()
+        for a, b in zip(first[0], again[0]):
+            assert torch.equal(a, b)
+        assert torch.equal(first[1], again[1]) and torch.equal(first[2], again[2])
+    # change the pools in place: the replay must follow the new contents
+    rng = np.random.default_rng(5)
+    for x, p in zip(Xcs, probs):
+        x.copy_(_t(I.f32r(rng.uniform(0, 1, size=(x.shape[0], p.d))), torch.float32))
+    replay = call()
+    for b, mo in enumerate(models):
+        single = G.score(ctx, mo, Xcs[b], "fp32")
+        torch.cuda.synchronize()
+        top = float(single["ei"].max())
+        assert float((replay[0][b] - single["ei"]).abs().max()) <= 1e-5 * max(top, 1e-30)
+    for mo in models:
+        mo.free()
+
+
+def test_batched_full_c3_shape_smoke(ctx):
+    """The literal batch shape: 64 sub-searches, d in 2..12, n in 16..400,
+    8192 candidates each; every argmax is a valid index with finite EI."""
+    probs = I.make_c3(lam=0.5, replicate=0, B=64, m=8192)
+    st, models, status, _ = _fit_batch(ctx, probs)
+    assert st == G.OK
+    Xcs = [_t(p.Xc, torch.float32) for p in probs]
+    for prec in ("bf16", "fp32"):
+        eis, am, emax = G.score_batched(ctx, models, Xcs, prec)
+        torch.cuda.synchronize()
+        am = am.cpu().numpy()
+        assert np.all((am >= 0) & (am < 8192))
+        assert np.all(np.isfinite(emax.cpu().numpy()))
+        for b in (0, 17, 63):
+            e = eis[b].double().cpu().numpy()
+            assert np.isfinite(e).all() and e[am[b]] == e.max()
+    for mo in models:
+        mo.free()
