@@ -123,6 +123,8 @@ int32_t gpbo_version(void);
  * no usable device. */
 gpbo_status gpbo_ctx_create(int32_t device, void* stream, const gpbo_allocator* alloc,
                             gpbo_ctx* out);
+/* Waits for the context's stream, then frees every model and MLP still
+ * alive on the context (their handles become invalid) and the context. */
 gpbo_status gpbo_ctx_destroy(gpbo_ctx ctx);
 /* Replace the stream work is queued on. */
 gpbo_status gpbo_ctx_set_stream(gpbo_ctx ctx, void* stream);
@@ -133,6 +135,20 @@ gpbo_status gpbo_ctx_set_stream(gpbo_ctx ctx, void* stream);
  * resets both.  Either output may be NULL. */
 gpbo_status gpbo_ctx_enable_timing(gpbo_ctx ctx, int32_t enable);
 gpbo_status gpbo_ctx_timing(gpbo_ctx ctx, int64_t* launches, double* total_ms);
+/* Scoring path of gpbo_score (both compute the same quantities):
+ *   GPBO_PATH_AUTO  : fused for small n, chunked for large n (float32);
+ *   GPBO_PATH_FUSED : one kernel per candidate tile, cross-covariance in LDS;
+ *   GPBO_PATH_LARGE : float32 only; per candidate chunk the cross-covariance
+ *                     is written to a workspace and contracted with the
+ *                     packed inverse factor by a triangular matrix-core
+ *                     product (the timed kernel is that product).
+ * Returns GPBO_E_INVALID_ARG for an unknown path. */
+typedef enum gpbo_score_path {
+  GPBO_PATH_AUTO = 0,
+  GPBO_PATH_FUSED = 1,
+  GPBO_PATH_LARGE = 2
+} gpbo_score_path;
+gpbo_status gpbo_ctx_set_score_path(gpbo_ctx ctx, gpbo_score_path path);
 
 /* ---------------------------------------------------------------------- */
 /* Fit (training the surrogate, Sec. IV-D: cubic in n).                    */

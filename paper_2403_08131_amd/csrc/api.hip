@@ -45,11 +45,11 @@ struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) hipSetDevice(dev);
+    if (prev != dev) (void)hipSetDevice(dev);
   }
   ~DeviceGuard() {
     int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
   }
 };
 
@@ -252,6 +252,11 @@ gpbo_status gpbo_ctx_destroy(gpbo_ctx c) {
   if (!c) return GPBO_OK;
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
+  // objects still alive on the context go with it
+  for (void* p : std::vector<void*>(c->live_mlps.begin(), c->live_mlps.end()))
+    (void)gpbo_mlp_free((gpbo_mlp)p);
+  for (Model* M : std::vector<Model*>(c->live_models.begin(), c->live_models.end()))
+    (void)gpbo_model_free((gpbo_model)M);
   if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
   for (auto& pr : c->ev_pending) {
     c->ev_pool.push_back(pr.first);
@@ -274,6 +279,14 @@ gpbo_status gpbo_ctx_set_stream(gpbo_ctx c, void* stream) {
 gpbo_status gpbo_ctx_enable_timing(gpbo_ctx c, int32_t enable) {
   if (!c) return GPBO_E_INVALID_ARG;
   c->timing = enable != 0;
+  return GPBO_OK;
+}
+
+gpbo_status gpbo_ctx_set_score_path(gpbo_ctx c, gpbo_score_path path) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (path != GPBO_PATH_AUTO && path != GPBO_PATH_FUSED && path != GPBO_PATH_LARGE)
+    return fail(c, GPBO_E_INVALID_ARG, "unknown scoring path %d", (int)path);
+  c->score_path = (int)path;
   return GPBO_OK;
 }
 
@@ -328,6 +341,7 @@ gpbo_status gpbo_fit(gpbo_ctx c, const gpbo_problem* p, gpbo_model* out, double*
     return st;
   }
   if (lml) *lml = M->host_stats[S_LML];
+  c->live_models.insert(M);
   *out = M;
   return GPBO_OK;
 }
@@ -384,6 +398,7 @@ gpbo_status gpbo_fit_batched(gpbo_ctx c, int32_t B, const gpbo_problem* probs, g
       }
     } else {
       out[b] = ms[b];
+      c->live_models.insert(ms[b]);
       if (lml) lml[b] = ms[b]->host_stats[S_LML];
     }
   }
@@ -394,6 +409,7 @@ gpbo_status gpbo_model_free(gpbo_model M) {
   if (!M) return GPBO_OK;
   DeviceGuard g(M->ctx->device);
   (void)hipStreamSynchronize(M->ctx->stream);
+  M->ctx->live_models.erase(M);
   free_model_buffers(M);
   delete M;
   return GPBO_OK;
@@ -428,6 +444,9 @@ gpbo_status gpbo_model_factors(gpbo_ctx c, gpbo_model M, double* L, double* Linv
   return GPBO_OK;
 }
 
+// Above this many observations gpbo_score takes the chunked float32 path.
+constexpr int LARGE_N_MIN = 1024;
+
 static gpbo_status ensure_red(Ctx* c, size_t bytes) {
   if (c->red_bytes >= bytes) return GPBO_OK;
   if (c->red) {
@@ -455,20 +474,34 @@ gpbo_status gpbo_score(gpbo_ctx c, gpbo_model M, int64_t m, const void* Xc, gpbo
     return GPBO_OK;
   }
   const int tm = score_tile_m(prec, M->n, M->d);
-  if (tm == 0)
+  // Path: the chunked path for float32 once n is large (the fused kernel's
+  // LDS tile then holds too few candidates to amortise the inverse factor).
+  bool large = prec == GPBO_FP32 && (tm == 0 || M->n > LARGE_N_MIN);
+  if (c->score_path == GPBO_PATH_FUSED) large = false;
+  if (c->score_path == GPBO_PATH_LARGE) {
+    if (prec != GPBO_FP32)
+      return fail(c, GPBO_E_UNSUPPORTED, "the large-n scoring path is float32 only");
+    large = true;
+  }
+  if (!large && tm == 0)
     return fail(c, GPBO_E_UNSUPPORTED, "n=%d is too large for the fused scoring kernel at this precision",
                 M->n);
   ensure_score_operands(M, prec, s);
-  const int64_t tiles = ceil_div(m, tm);
+  const int npj = M->pk_npj[prec];
+  const int64_t tiles = large ? large_partials(npj, m) : ceil_div(m, tm);
+  const size_t part_bytes = round_up((size_t)tiles * 16, 256);
+  const size_t ws_bytes = large ? large_scratch_bytes(M->n, npj, m) : 0;
   double* pv = nullptr;
   int64_t* pi = nullptr;
-  if (argmax || ei_max) {
-    gpbo_status st = ensure_red(c, (size_t)tiles * 16);
+  if (argmax || ei_max || ws_bytes) {
+    gpbo_status st = ensure_red(c, part_bytes + ws_bytes);
     if (st != GPBO_OK) return st;
+  }
+  if (argmax || ei_max) {
     pv = (double*)c->red;
     pi = (int64_t*)((double*)c->red + tiles);
   }
-  ScoreArgs j = make_score_args(M, prec, tm);
+  ScoreArgs j = make_score_args(M, prec, large ? 0 : tm);
   j.m = m;
   j.Xc = Xc;
   j.mu = mu;
@@ -477,15 +510,29 @@ gpbo_status gpbo_score(gpbo_ctx c, gpbo_model M, int64_t m, const void* Xc, gpbo
   j.part_v = pv;
   j.part_i = pi;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (c->timing) {
+  if (c->timing && !large) {
     e0 = timing_event(c);
     e1 = timing_event(c);
     HIP_TRY(c, hipEventRecord(e0, s));
   }
-  launch_score(j, prec, tm, s);
-  if (c->timing) {
-    HIP_TRY(c, hipEventRecord(e1, s));
-    c->ev_pending.emplace_back(e0, e1);
+  if (large) {
+    launch_score_large(j, (char*)c->red + part_bytes, s, [&](int w) {
+      if (!c->timing) return;
+      if (w == 0) {
+        e0 = timing_event(c);
+        e1 = timing_event(c);
+        (void)hipEventRecord(e0, s);
+      } else {
+        (void)hipEventRecord(e1, s);
+        c->ev_pending.emplace_back(e0, e1);
+      }
+    });
+  } else {
+    launch_score(j, prec, tm, s);
+    if (c->timing) {
+      HIP_TRY(c, hipEventRecord(e1, s));
+      c->ev_pending.emplace_back(e0, e1);
+    }
   }
   if (pv) launch_argmax_final(pv, pi, tiles, argmax, ei_max, s);
   HIP_TRY(c, hipGetLastError());
@@ -674,12 +721,14 @@ gpbo_status gpbo_mlp_create(gpbo_ctx c, int32_t members, int32_t d_in, int32_t h
   if (!st) return fail(c, GPBO_E_OOM, "MLP allocation failed");
   HIP_TRY(c, hipGetLastError());
   *out = new gpbo_mlp_s{c, st, members, d_in, hidden};
+  c->live_mlps.insert(*out);
   return GPBO_OK;
 }
 
 gpbo_status gpbo_mlp_free(gpbo_mlp mlp) {
   if (!mlp) return GPBO_OK;
   DeviceGuard g(mlp->ctx->device);
+  mlp->ctx->live_mlps.erase(mlp);
   mlp_destroy(mlp->st);
   delete mlp;
   return GPBO_OK;

@@ -354,8 +354,10 @@ __global__ void __launch_bounds__(256) k_chol_panel(const FitDesc* __restrict__ 
 __global__ void __launch_bounds__(256) k_chol_update(const FitDesc* __restrict__ Ds, int k) {
   extern __shared__ double sm[];
   const FitDesc& P = Ds[blockIdx.z];
+  // rest < 0 for a smaller problem of a batch whose factorisation has ended
+  // (rest (rest + 1) / 2 would be positive again for rest <= -2).
   const int rest = P.npad / NB - k - 1;
-  if ((int)blockIdx.x >= rest * (rest + 1) / 2 || fit_failed(P.info)) return;
+  if (rest <= 0 || (int)blockIdx.x >= rest * (rest + 1) / 2 || fit_failed(P.info)) return;
   const int npad = P.npad;
   double* At = sm;
   double* Bt = sm + NB * LDT;

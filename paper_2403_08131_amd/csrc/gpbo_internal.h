@@ -7,6 +7,7 @@
 
 #include <functional>
 #include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/gpbo.h"
@@ -90,6 +91,10 @@ struct Ctx {
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
   bool no_graph = false;  // GPBO_NO_GRAPH=1: never capture batched launches
+  int score_path = 0;     // gpbo_score_path
+  // Models and MLPs alive on this context (destroyed with it).
+  std::unordered_set<Model*> live_models;
+  std::unordered_set<void*> live_mlps;
   // Batched-score graph cache.
   hipGraphExec_t batch_exec = nullptr;
   std::vector<uint64_t> batch_key;
@@ -166,6 +171,14 @@ int score_tile_m(int prec, int n, int d);  // candidates per workgroup (0 = too 
 size_t score_smem(int prec, int n, int d, int tile_m);
 ScoreArgs make_score_args(Model* M, int prec, int tile_m);
 void launch_score(const ScoreArgs& a, int prec, int tile_m, hipStream_t s);
+// Large-n float32 path (score_large.hip): workspace bytes, argmax partial
+// count, and the launch sequence (a.part_v may be NULL).
+size_t large_scratch_bytes(int n, int npj, int64_t m);
+int64_t large_partials(int npj, int64_t m);
+// mark(0) / mark(1) are called right before / after each launch of the
+// triangular product (the dominant kernel), for timing.
+void launch_score_large(const ScoreArgs& a, void* scratch, hipStream_t s,
+                        const std::function<void(int)>& mark);
 void launch_argmax_final(const double* part_v, const int64_t* part_i, int64_t nparts,
                          int64_t* argmax, double* ei_max, hipStream_t s);
 // Batched scoring: one persistent launch over the (problem, tile) items of B

@@ -1,0 +1,248 @@
+// Large-n scoring path (float32).  When n is large the cross-covariance tile
+// of a useful number of candidates no longer fits in LDS, so the inverse
+// factor would be re-streamed for every few candidates.  Instead, per chunk
+// of candidates (sized to stay resident in the last-level cache):
+//   1. k_kstar:    khat[c][j] = k(x*_c, x_j) / sf2 in float32 (VALU, lanes
+//                  over training points, as in the fused kernel) and partial
+//                  sums of (sf2 alpha_j) khat_cj per 256-point block;
+//   2. k_trigemm:  v = (sf2 L^-1) khat on the float32 matrix cores, only the
+//                  lower-triangular blocks, with a sum-of-squares epilogue:
+//                  one partial |v|^2 per (64-row block, candidate);
+//   3. k_finish:   mean, variance, EI, outputs and per-block argmax partials.
+// The GEMM maps workgroups to XCDs so that every row block of one candidate
+// block runs on the same XCD and reads that block's khat rows from one L2.
+#include <algorithm>
+#include <cmath>
+#include <functional>
+
+#include "score_common.h"
+
+namespace gpbo {
+
+using namespace sc;
+
+namespace {
+
+constexpr int KS_CG = 32;    // candidates per k_kstar workgroup
+constexpr int KS_J = 256;    // training points per k_kstar workgroup
+constexpr int GM_I = 64;     // inverse-factor rows per GEMM workgroup
+constexpr int GM_C = 128;    // candidates per GEMM workgroup
+
+template <int KERN>
+__global__ void __launch_bounds__(256) k_kstar(int n, int d, int npj, const float* __restrict__ XsT,
+                                               const float* __restrict__ sc,
+                                               const float* __restrict__ alpha, int64_t m,
+                                               int64_t cbeg, const float* __restrict__ Xc,
+                                               float* __restrict__ khat, int ldk,
+                                               float* __restrict__ mu_part, int64_t mc_pad) {
+  __shared__ __align__(16) float xcT[64 * KS_CG];  // [d][KS_CG], d <= 64
+  __shared__ float red[4][KS_CG];
+  const int t = threadIdx.x, lane = t % 64, wave = wave_id();
+  const int64_t cl0 = (int64_t)blockIdx.x * KS_CG;  // chunk-local first candidate
+  const int jb = blockIdx.y * KS_J;
+  for (int e = t; e < KS_CG * d; e += 256) {
+    const int c = e / d, k = e % d;
+    const int64_t gc = cbeg + cl0 + c;
+    xcT[k * KS_CG + c] = gc < m ? Xc[gc * d + k] * sc[k] : 0.0f;
+  }
+  __syncthreads();
+  const int j = jb + t;
+  const bool valid = j < n;
+  const float* xcol = XsT + (valid ? j : 0);
+  float r2[KS_CG];
+#pragma unroll
+  for (int c = 0; c < KS_CG; ++c) r2[c] = 0.0f;
+  float xnext = xcol[0];
+  for (int k = 0; k < d; ++k) {
+    const float xk = xnext;
+    if (k + 1 < d) xnext = xcol[(int64_t)(k + 1) * n];
+    const float* xr = xcT + k * KS_CG;
+#pragma unroll
+    for (int c = 0; c < KS_CG; c += 4) {
+      const f4 x4 = *(const f4*)(xr + c);
+      const float u0 = xk - x4[0], u1 = xk - x4[1], u2 = xk - x4[2], u3 = xk - x4[3];
+      r2[c] = fmaf(u0, u0, r2[c]);
+      r2[c + 1] = fmaf(u1, u1, r2[c + 1]);
+      r2[c + 2] = fmaf(u2, u2, r2[c + 2]);
+      r2[c + 3] = fmaf(u3, u3, r2[c + 3]);
+    }
+  }
+  const float aj = valid ? alpha[j] : 0.0f;
+  float macc[KS_CG];
+#pragma unroll
+  for (int c = 0; c < KS_CG; ++c) {
+    const float kv = valid ? cov_from_r2<KERN>(r2[c]) : 0.0f;
+    macc[c] = kv * aj;
+    if (j < npj && cl0 + c < mc_pad) khat[(cl0 + c) * ldk + j] = kv;
+  }
+  lane_transpose_sum<float, KS_CG>(macc, red[wave]);
+  __syncthreads();
+  if (t < KS_CG && cl0 + t < mc_pad)
+    mu_part[(int64_t)blockIdx.y * mc_pad + cl0 + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+}
+
+// Triangular product with sum-of-squares epilogue.  Workgroup: 64 rows of
+// the inverse factor (four 16-row tiles) x 128 candidates; wave (wi, wc)
+// owns row tiles 2wi, 2wi+1 of the block and candidates 64wc .. 64wc+63.
+__global__ void __launch_bounds__(256) k_trigemm(const float* __restrict__ khat, int ldk,
+                                                 const float* __restrict__ pk,
+                                                 const int64_t* __restrict__ pk_off, int ntiles,
+                                                 int nib, int ncb, float* __restrict__ ssq_part,
+                                                 int64_t mc_pad) {
+  __shared__ float red[2][GM_C];
+  const int lane = threadIdx.x % 64, wave = wave_id();
+  const int wi = wave / 2, wc = wave % 2;
+  // XCD-aware order: workgroup b runs on XCD b % 8; all row blocks of one
+  // candidate block share an XCD, heaviest row blocks first.
+  const int b = blockIdx.x;
+  const int xcd = b % 8, local = b / 8;
+  const int cb = (local / nib) * 8 + xcd;
+  const int I = nib - 1 - local % nib;
+  if (cb >= ncb) return;
+  const int ti0 = I * 4 + wi * 2, ti1 = ti0 + 1;
+  const int64_t cbase = (int64_t)cb * GM_C + wc * 64;
+  f4 acc[2][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[r][ct] = f4{0, 0, 0, 0};
+  if (ti0 < ntiles) {
+    const bool has1 = ti1 < ntiles;
+    const float* a0p = pk + pk_off[ti0] * 256 + lane * 4;
+    const float* a1p = has1 ? pk + pk_off[ti1] * 256 + lane * 4 : a0p;
+    const int nlast = has1 ? ti1 : ti0;  // last column block needed
+    const float* bp = khat + (cbase + lane % 16) * ldk + 4 * (lane / 16);
+    for (int tj = 0; tj <= nlast; ++tj) {
+      const f4 a0 = tj <= ti0 ? *(const f4*)(a0p + tj * 256) : f4{0, 0, 0, 0};
+      const f4 a1 = has1 ? *(const f4*)(a1p + tj * 256) : f4{0, 0, 0, 0};
+      f4 bv[4];
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) bv[ct] = *(const f4*)(bp + (int64_t)ct * 16 * ldk + tj * 16);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        Blk<GPBO_FP32>::mma(acc[0][ct], a0, bv[ct]);
+        Blk<GPBO_FP32>::mma(acc[1][ct], a1, bv[ct]);
+      }
+    }
+  }
+  // per candidate column: sum of squares over this wave's 32 rows
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    float v = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+      v += acc[r][ct][0] * acc[r][ct][0] + acc[r][ct][1] * acc[r][ct][1] +
+           acc[r][ct][2] * acc[r][ct][2] + acc[r][ct][3] * acc[r][ct][3];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    if (lane < 16) red[wi][wc * 64 + ct * 16 + lane] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < GM_C) {
+    const int64_t c = (int64_t)cb * GM_C + threadIdx.x;
+    if (c < mc_pad) ssq_part[(int64_t)I * mc_pad + c] = red[0][threadIdx.x] + red[1][threadIdx.x];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_finish(int64_t mc, int64_t mc_pad, int64_t cbeg, int njb,
+                                                int nib, const float* __restrict__ mu_part,
+                                                const float* __restrict__ ssq_part, double sf2,
+                                                const double* __restrict__ stats,
+                                                float* __restrict__ mu_out,
+                                                float* __restrict__ sigma_out,
+                                                float* __restrict__ ei_out,
+                                                double* __restrict__ part_v,
+                                                int64_t* __restrict__ part_i, int64_t pbase) {
+  __shared__ double wv[4];
+  __shared__ int64_t wi_[4];
+  const int64_t cl = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double bv = -INFINITY;
+  int64_t bi = -1;
+  if (cl < mc) {
+    float muz = 0.0f, vv = 0.0f;
+    for (int q = 0; q < njb; ++q) muz += mu_part[(int64_t)q * mc_pad + cl];
+    for (int q = 0; q < nib; ++q) vv += ssq_part[(int64_t)q * mc_pad + cl];
+    finish_candidate<float, float>(cbeg + cl, muz, vv, sf2, stats, mu_out, sigma_out, ei_out, bv,
+                                   bi);
+  }
+  wave_argmax(bv, bi);
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  if (lane == 0) {
+    wv[w] = bv;
+    wi_[w] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && part_v) {
+    double v = wv[0];
+    int64_t i = wi_[0];
+    for (int q = 1; q < 4; ++q)
+      if (better(wv[q], wi_[q], v, i)) {
+        v = wv[q];
+        i = wi_[q];
+      }
+    part_v[pbase + blockIdx.x] = v;
+    part_i[pbase + blockIdx.x] = i;
+  }
+}
+
+}  // namespace
+
+// Candidates per chunk: khat of a chunk stays within about 128 MiB.
+int64_t large_chunk(int npj, int64_t m) {
+  int64_t mc = (128ll << 20) / ((int64_t)npj * 4);
+  mc = std::max<int64_t>(GM_C, mc / GM_C * GM_C);
+  return std::min<int64_t>(mc, round_up(m, GM_C));
+}
+
+// Scratch bytes and argmax partial count of the large path for m candidates.
+size_t large_scratch_bytes(int n, int npj, int64_t m) {
+  const int64_t mc = large_chunk(npj, m);
+  const int njb = (int)ceil_div(npj, KS_J), nib = (int)ceil_div(round_up(n, 16) / 16, 4);
+  return (size_t)mc * npj * 4 + (size_t)(njb + nib) * mc * 4 + 256;
+}
+// Exactly the number of partials the launch sequence writes (one per
+// 256-candidate block of every chunk).
+int64_t large_partials(int npj, int64_t m) {
+  const int64_t mc = large_chunk(npj, m);
+  return (m / mc) * ceil_div(mc, 256) + ceil_div(m % mc, 256);
+}
+
+void launch_score_large(const ScoreArgs& a, void* scratch, hipStream_t s,
+                        const std::function<void(int)>& mark) {
+  const int n = a.n, d = a.d, npj = a.npj;
+  const int64_t m = a.m;
+  const int64_t mc = large_chunk(npj, m);
+  const int njb = (int)ceil_div(npj, KS_J);
+  const int ntiles = (int)round_up(n, 16) / 16;
+  const int nib = (int)ceil_div(ntiles, 4);
+  float* khat = (float*)scratch;
+  float* mu_part = khat + (size_t)mc * npj;
+  float* ssq_part = mu_part + (size_t)njb * mc;
+  int64_t pbase = 0;
+  for (int64_t cbeg = 0; cbeg < m; cbeg += mc) {
+    const int64_t mcur = std::min<int64_t>(mc, m - cbeg);
+    const int64_t mc_pad = round_up(mcur, GM_C);
+    const dim3 gk((unsigned)ceil_div(mc_pad, KS_CG), (unsigned)njb);
+    if (a.kernel == GPBO_KERNEL_SE)
+      hipLaunchKernelGGL(k_kstar<GPBO_KERNEL_SE>, gk, dim3(256), 0, s, n, d, npj,
+                         (const float*)a.Xs, (const float*)a.sc, (const float*)a.alpha, m, cbeg,
+                         (const float*)a.Xc, khat, npj, mu_part, mc_pad);
+    else
+      hipLaunchKernelGGL(k_kstar<GPBO_KERNEL_MATERN52>, gk, dim3(256), 0, s, n, d, npj,
+                         (const float*)a.Xs, (const float*)a.sc, (const float*)a.alpha, m, cbeg,
+                         (const float*)a.Xc, khat, npj, mu_part, mc_pad);
+    const int ncb = (int)(mc_pad / GM_C);
+    const int nwg = (int)round_up(ncb, 8) * nib;  // XCD-aware order pads to whole groups of 8
+    mark(0);
+    hipLaunchKernelGGL(k_trigemm, dim3(nwg), dim3(256), 0, s, khat, npj, (const float*)a.pk,
+                       a.pk_off, ntiles, nib, ncb, ssq_part, mc_pad);
+    mark(1);
+    const int nfb = (int)ceil_div(mcur, 256);
+    hipLaunchKernelGGL(k_finish, dim3(nfb), dim3(256), 0, s, mcur, mc_pad, cbeg, njb, nib, mu_part,
+                       ssq_part, a.sf2, a.stats, (float*)a.mu, (float*)a.sigma, (float*)a.ei,
+                       a.part_v, a.part_i, pbase);
+    pbase += nfb;
+  }
+}
+
+}  // namespace gpbo

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import torch
 
@@ -21,6 +22,8 @@ KERNEL_SE, KERNEL_MATERN52 = 0, 1
 FP64, FP32, BF16 = 0, 1, 2
 NSTATS = 7
 PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+PATH_AUTO, PATH_FUSED, PATH_LARGE = 0, 1, 2
+PATHS = {"auto": PATH_AUTO, "fused": PATH_FUSED, "large": PATH_LARGE}
 
 
 class GpboError(RuntimeError):
@@ -56,6 +59,7 @@ _SIGS = {
     "gpbo_ctx_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gpbo_ctx_enable_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "gpbo_ctx_timing": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "gpbo_ctx_set_score_path": (C.c_int, [C.c_void_p, C.c_int]),
     "gpbo_fit": (C.c_int, [C.c_void_p, C.POINTER(Problem), C.POINTER(C.c_void_p),
                            C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "gpbo_fit_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Problem), C.POINTER(C.c_void_p),
@@ -119,6 +123,7 @@ class Context:
 
     def __init__(self, device=0, use_torch_allocator=True):
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self._children = weakref.WeakSet()  # models and MLPs, freed before the context
         self._held = {}
         self._alloc = None
         if use_torch_allocator:
@@ -151,6 +156,10 @@ class Context:
     def enable_timing(self, on=True):
         self.check(lib().gpbo_ctx_enable_timing(self.h, 1 if on else 0))
 
+    def set_score_path(self, path="auto"):
+        """gpbo_ctx_set_score_path: "auto", "fused" or "large"."""
+        self.check(lib().gpbo_ctx_set_score_path(self.h, PATHS[path] if isinstance(path, str) else int(path)))
+
     def timing(self):
         """(launches, total_ms) of the scoring kernels since the last call."""
         n = C.c_int64()
@@ -160,6 +169,8 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            for ch in list(self._children):
+                ch.free()
             lib().gpbo_ctx_destroy(self.h)
             self.h = None
 
@@ -176,6 +187,7 @@ class Model:
     def __init__(self, ctx: Context, handle, n, d):
         self.ctx = ctx
         self.h = handle
+        ctx._children.add(self)
         self.n = n
         self.d = d
 
@@ -310,6 +322,7 @@ class Mlp:
         h = C.c_void_p()
         ctx.check(lib().gpbo_mlp_create(ctx.h, members, d_in, hidden, _ptr(init), C.byref(h)))
         self.h = h
+        ctx._children.add(self)
 
     def params(self):
         out = torch.empty((self.E, self.P), dtype=torch.float32, device=self.ctx.device)
