@@ -129,8 +129,10 @@ gpbo_status gpbo_ctx_destroy(gpbo_ctx ctx);
 /* Replace the stream work is queued on. */
 gpbo_status gpbo_ctx_set_stream(gpbo_ctx ctx, void* stream);
 /* Kernel timing.  While enabled, every launch of a candidate-scoring kernel
- * (the dominant kernel of gpbo_score) is bracketed by HIP events recorded on
- * the context's stream.  gpbo_ctx_timing synchronises the stream, returns the
+ * (the dominant kernel of gpbo_score: the fused kernel, or the triangular
+ * product of the large-n path) and of the network forward kernel
+ * (gpbo_mlp_forward, gpbo_mlp_prescreen) is bracketed by HIP events recorded
+ * on the context's stream.  gpbo_ctx_timing synchronises the stream, returns the
  * number of timed launches and their summed duration in milliseconds, and
  * resets both.  Either output may be NULL. */
 gpbo_status gpbo_ctx_enable_timing(gpbo_ctx ctx, int32_t enable);

@@ -744,6 +744,22 @@ gpbo_status gpbo_mlp_params(gpbo_ctx c, gpbo_mlp mlp, float* out) {
   return GPBO_OK;
 }
 
+// Network forward on the context's stream, bracketed by timing events when
+// kernel timing is enabled.
+static void timed_mlp_forward(Ctx* c, MlpState* st, int64_t m, const float* Xc, float* out) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->timing) {
+    e0 = timing_event(c);
+    e1 = timing_event(c);
+    (void)hipEventRecord(e0, c->stream);
+  }
+  mlp_forward(st, m, Xc, out, c->stream);
+  if (c->timing) {
+    (void)hipEventRecord(e1, c->stream);
+    c->ev_pending.emplace_back(e0, e1);
+  }
+}
+
 static gpbo_status check_train_args(Ctx* c, gpbo_mlp mlp, int32_t n, const float* X,
                                     const float* y) {
   if (!mlp || !X || !y) return fail(c, GPBO_E_INVALID_ARG, "mlp, X and y are required");
@@ -783,7 +799,7 @@ gpbo_status gpbo_mlp_forward(gpbo_ctx c, gpbo_mlp mlp, int64_t m, const float* X
   if (!mlp || m < 0 || (m > 0 && (!Xc || !out))) return fail(c, GPBO_E_INVALID_ARG, "invalid forward arguments");
   if (m == 0) return GPBO_OK;
   DeviceGuard g(c->device);
-  mlp_forward(mlp->st, m, Xc, out, c->stream);
+  timed_mlp_forward(c, mlp->st, m, Xc, out);
   HIP_TRY(c, hipGetLastError());
   return GPBO_OK;
 }
@@ -806,7 +822,7 @@ gpbo_status gpbo_mlp_prescreen(gpbo_ctx c, gpbo_mlp mlp, int64_t m, const float*
     dfree(c, scratch);
     return fail(c, GPBO_E_OOM, "prescreen scratch allocation failed");
   }
-  mlp_forward(mlp->st, m, Xc, outs, s);
+  timed_mlp_forward(c, mlp->st, m, Xc, outs);
   mlp_ens_ei(mlp->st, m, outs, f_best, ei, s);
   if (k > 0) launch_topk_into(m, ei, k, topk_idx, scratch, s);
   HIP_TRY(c, hipGetLastError());

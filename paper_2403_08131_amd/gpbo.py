@@ -313,6 +313,16 @@ class Mlp:
     """An MLP ensemble on the device (gpbo_mlp_*); params are float32 master
     weights in the per-member layout W1, b1, W2, b2, w3, b3."""
 
+    @staticmethod
+    def pack(W1, b1, W2, b2, w3, b3, device=None):
+        """Per-member arrays (W1 (E,H,D), b1 (E,H), W2 (E,H,H), b2 (E,H),
+        w3 (E,H), b3 (E,)) -> the (E, P) float32 device tensor the library
+        takes, in its documented per-member order."""
+        E = W1.shape[0]
+        parts = [torch.as_tensor(a, dtype=torch.float32).reshape(E, -1)
+                 for a in (W1, b1, W2, b2, w3, b3)]
+        return torch.cat(parts, dim=1).contiguous().to(device or torch.device("cuda", 0))
+
     def __init__(self, ctx: Context, init, members, d_in, hidden=256):
         assert init.dtype == torch.float32 and init.is_cuda and init.is_contiguous()
         self.ctx = ctx
