@@ -12,7 +12,7 @@
 // Layout: every n x n matrix is row-major with leading dimension npad =
 // round_up(n, 64) and is padded with the identity, so the blocked kernels
 // work on whole 64 x 64 tiles without bounds checks.  The factorisation is
-// right-looking: per 64-column block, one workgroup factors the diagonal tile
+// right-looking: per 64-column block, one wave factors the diagonal tile
 // (rows in registers) and inverts it, the panel below is multiplied by that
 // inverse, and the trailing lower triangle receives a rank-64 update.  The
 // inverse factor is formed the same way, as a blocked triangular solve
@@ -227,107 +227,105 @@ __device__ __forceinline__ void store_tile(double* __restrict__ C, int ld, const
     }
 }
 
-// Factor the diagonal tile (k, k), write L_kk and its inverse D_k.
-__global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ Ds, int k) {
-  // Thread (i, g): row i of the tile, columns l = g + 4q (q = 0..15) held in
-  // registers.  Column and row exchanges go through LDS in a permuted order,
-  // (l % 4) * 16 + l / 4, so a wave (fixed g) reads its 16 entries as one
-  // contiguous broadcast block.
-  __shared__ double T[NB][NB + 1];
-  __shared__ __align__(16) double xb[2][NB];
-  __shared__ double piv[NB];
+// Broadcast of lane l's double (l a compile-time constant in the callers).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Factor the diagonal tile (k, k), write L_kk and its inverse D_k.  One wave:
+// the 64 column steps of the tile are a dependency chain, so the kernel keeps
+// each step short -- no barrier between waves, no division.
+//   Factorisation: lane i holds the not yet final part of row i in
+//   registers.  Step j reads the pivot from lane j, forms 1/sqrt(pivot)
+//   (hardware estimate and two Newton steps), scales column j, writes the
+//   final entries L_ij to LDS, publishes the column and applies the rank-1
+//   update to the rows' remaining entries.
+//   Inverse: lane c solves L x = e_c by forward substitution (column c of
+//   L_kk^-1), reading the rows of L as LDS broadcasts.
+// LDS reads are issued in groups of eight values with scheduling barriers in
+// between, which bounds the registers in flight.
+__global__ void __launch_bounds__(64) k_potrf_diag(const FitDesc* __restrict__ Ds, int k) {
+  __shared__ __align__(16) double Ls[NB][LDT];
+  __shared__ __align__(16) double colb[2][NB];
+  __shared__ double rdiag[NB];
   const FitDesc& P = Ds[blockIdx.z];
   if (k >= P.npad / NB || fit_failed(P.info)) return;
   const int npad = P.npad;
-  int* info = P.info;
-  const int t = threadIdx.x;
-  const int i = t % NB;
-  const int g = __builtin_amdgcn_readfirstlane(t / NB);
-  const int pi_ = (i % 4) * 16 + i / 4;  // permuted slot of row i
+  const int i = threadIdx.x;
   double* Akk = P.L + (int64_t)k * NB * npad + k * NB;
-  {
-    double v[NB * NB / 256];
+  // coalesced rows into LDS, then row i into registers
+#pragma unroll 8
+  for (int r = 0; r < NB; ++r) Ls[r][i] = Akk[(int64_t)r * npad + i];
+  __syncthreads();
+  double a[NB];
 #pragma unroll
-    for (int q = 0; q < NB * NB / 256; ++q) {
-      const int e = t + 256 * q;
-      v[q] = Akk[(int64_t)(e / NB) * npad + e % NB];
-    }
-#pragma unroll
-    for (int q = 0; q < NB * NB / 256; ++q) {
-      const int e = t + 256 * q;
-      T[e / NB][e % NB] = v[q];
-    }
+  for (int c = 0; c < NB; c += 2) {
+    const double2 v = *(const double2*)&Ls[i][c];
+    a[c] = v.x;
+    a[c + 1] = v.y;
   }
   __syncthreads();
-  double a[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) a[q] = (g + 4 * q <= i) ? T[i][g + 4 * q] : 0.0;
-  // Right-looking elimination with unscaled columns: at step j the pivot is
-  // p = S_jj and S_il -= (S_ij / p) S_lj for l > j.  Column j is published by
-  // its owners before the barrier; the double buffer makes one barrier per
-  // step enough.
-#pragma unroll 1
+  int bad = -1;  // first pivot that is not positive and finite (uniform)
+#pragma clang loop unroll(full)
   for (int j = 0; j < NB; ++j) {
-    double* col = xb[j & 1];
-    if (g == (j & 3)) {
-      double v = 0.0;
+    double d = readlane_f64(a[j], j);
+    if (bad < 0 && !(d > 0.0 && isfinite(d))) bad = j;
+    if (bad >= 0) d = 1.0;  // keep the arithmetic finite; the tile is discarded
+    double y = __builtin_amdgcn_rsq(d);
+    y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
+    y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
+    double sq = d * y;
+    sq = fma(0.5 * y, fma(-sq, sq, d), sq);  // sqrt(d), corrected
+    const double c = i > j ? a[j] * y : (i == j ? sq : 0.0);
+    Ls[i][j] = c;
+    if (i == 0) rdiag[j] = 1.0 / sq;
+    if (j + 1 < NB) {
+      double* cb = colb[j & 1];
+      cb[i] = c;
+      __syncthreads();
 #pragma unroll
-      for (int q = 0; q < 16; ++q) v = (q == (j >> 2)) ? a[q] : v;
-      col[pi_] = v;
-    }
-    __syncthreads();
-    const double p = col[(j % 4) * 16 + j / 4];
-    if (!(p > 0.0) || !isfinite(p)) {
-      if (t == 0) atomicMin(&info[0], k * NB + j);
-      return;
-    }
-    if (t == 0) piv[j] = p;
-    const double f = col[pi_] / p;
-    const double* cg = col + g * 16;
+      for (int l0 = (j + 1) & ~7; l0 < NB; l0 += 8) {
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const double nv = fma(-f, cg[q], a[q]);
-      a[q] = (g + 4 * q > j) ? nv : a[q];
+        for (int q = 0; q < 8; q += 2) {
+          const double2 v = *(const double2*)&cb[l0 + q];
+          if (l0 + q > j) a[l0 + q] = fma(-c, v.x, a[l0 + q]);
+          if (l0 + q + 1 > j) a[l0 + q + 1] = fma(-c, v.y, a[l0 + q + 1]);
+        }
+      }
     }
   }
-  __syncthreads();
-  // L_il = S_il / sqrt(p_l) below the diagonal, sqrt(p_i) on it.
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int l = g + 4 * q;
-    T[i][l] = l < i ? a[q] / sqrt(piv[l]) : (l == i ? sqrt(piv[i]) : 0.0);
+  if (bad >= 0) {
+    if (i == 0) atomicMin(&P.info[0], k * NB + bad);
+    return;
   }
   __syncthreads();
-  // Inverse of L_kk by eliminating against the identity with unscaled rows:
-  // U_i -= (L_ij / L_jj) U_j for i > j (columns c <= j), then row i is
-  // scaled by 1 / L_ii.  Row j is published by its four owners.
-  double u[16];
+#pragma unroll 8
+  for (int r = 0; r < NB; ++r) Akk[(int64_t)r * npad + i] = Ls[r][i];
+  // column i of the inverse: x_r = (delta_ri - sum_{q<r} L_rq x_q) / L_rr
+  double x[NB];
+#pragma clang loop unroll(full)
+  for (int r = 0; r < NB; ++r) {
+    double s0 = r == i ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) u[q] = (g + 4 * q == i) ? 1.0 : 0.0;
-#pragma unroll 1
-  for (int j = 0; j < NB; ++j) {
-    double* row = xb[j & 1];
-    if (i == j) {
+    for (int q0 = 0; q0 < r; q0 += 8) {
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int q = 0; q < 16; ++q) row[g * 16 + q] = u[q];
+      for (int q = q0; q < q0 + 8; q += 2) {
+        if (q < r) {
+          const double2 l2 = *(const double2*)&Ls[r][q];
+          s0 = fma(-l2.x, x[q], s0);
+          if (q + 1 < r) s1 = fma(-l2.y, x[q + 1], s1);
+        }
+      }
     }
-    __syncthreads();
-    const double f = i > j ? T[i][j] / T[j][j] : 0.0;
-    const double* rg = row + g * 16;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const double nv = fma(-f, rg[q], u[q]);
-      u[q] = (g + 4 * q <= j) ? nv : u[q];
-    }
+    x[r] = (s0 + s1) * rdiag[r];
   }
   double* Dk = P.Dinv + (int64_t)k * NB * NB;
-  const double lii = T[i][i];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int c = g + 4 * q;
-    Dk[i * NB + c] = c <= i ? u[q] / lii : 0.0;
-  }
-  for (int e = t; e < NB * NB; e += 256) Akk[(int64_t)(e / NB) * npad + e % NB] = T[e / NB][e % NB];
+  for (int r = 0; r < NB; ++r) Dk[r * NB + i] = x[r];
 }
 
 // Panel: A_Ik <- A_Ik D_k^T for I > k.
@@ -639,7 +637,7 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   hipLaunchKernelGGL(k_fit_stats, dim3(1, 1, Bz), dim3(256), 0, s, dd);
   hipLaunchKernelGGL(k_gram, dim3(nbmax * (nbmax + 1) / 2, 1, Bz), dim3(256), 0, s, dd);
   for (int k = 0; k < nbmax; ++k) {
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, Bz), dim3(256), 0, s, dd, k);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, Bz), dim3(64), 0, s, dd, k);
     const int rest = nbmax - k - 1;
     if (rest > 0) {
       hipLaunchKernelGGL(k_chol_panel, dim3(rest, 1, Bz), dim3(256), sm2, s, dd, k);
