@@ -131,7 +131,7 @@ gpbo_status gpbo_ctx_set_stream(gpbo_ctx ctx, void* stream);
 /* Kernel timing.  While enabled, every launch of a candidate-scoring kernel
  * (the dominant kernel of gpbo_score: the fused kernel, or the triangular
  * product of the large-n path) and of the network forward kernel
- * (gpbo_mlp_forward, gpbo_mlp_prescreen) is bracketed by HIP events recorded
+ * (gpbo_mlp_forward, gpbo_mlp_prescreen*) is bracketed by HIP events recorded
  * on the context's stream.  gpbo_ctx_timing synchronises the stream, returns the
  * number of timed launches and their summed duration in milliseconds, and
  * resets both.  Either output may be NULL. */
@@ -256,6 +256,14 @@ gpbo_status gpbo_mlp_forward(gpbo_ctx ctx, gpbo_mlp mlp, int64_t m, const float*
  * ei_out (device m float) may be NULL.  Asynchronous. */
 gpbo_status gpbo_mlp_prescreen(gpbo_ctx ctx, gpbo_mlp mlp, int64_t m, const float* Xc,
                                double f_best, int64_t k, int64_t* topk_idx, float* ei_out);
+/* Prescreen by the ensemble's lower confidence bound: score = -(mean - kappa
+ * sd) (mean and population standard deviation over the members, in the
+ * network's output units; larger is better for minimisation), then the
+ * indices of the k largest scores (device int64, descending score, ascending
+ * index among ties).  kappa >= 0; kappa = 0 ranks by the predicted mean.
+ * score_out (device m float) may be NULL.  Asynchronous. */
+gpbo_status gpbo_mlp_prescreen_lcb(gpbo_ctx ctx, gpbo_mlp mlp, int64_t m, const float* Xc,
+                                   double kappa, int64_t k, int64_t* topk_idx, float* score_out);
 
 #ifdef __cplusplus
 }

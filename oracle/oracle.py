@@ -317,6 +317,14 @@ def ens_ei(out, fbest):
     return mu, sd, e
 
 
+def ens_lcb(out, kappa):
+    """Prescreen score from the ensemble's lower confidence bound, larger is
+    better for minimisation: -(mean - kappa * sd), with the member mean and
+    population standard deviation of ens_ei."""
+    mu, sd, _ = ens_ei(out, 0.0)
+    return -(mu - kappa * sd)
+
+
 def mlp_train(params, D, H, X, yt, steps, lr=1e-3, bf16=False, master_f32=False):
     """Full-batch Adam training of every member; returns (params, losses per step).
 

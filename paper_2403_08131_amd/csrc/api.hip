@@ -804,32 +804,50 @@ gpbo_status gpbo_mlp_forward(gpbo_ctx c, gpbo_mlp mlp, int64_t m, const float* X
   return GPBO_OK;
 }
 
-gpbo_status gpbo_mlp_prescreen(gpbo_ctx c, gpbo_mlp mlp, int64_t m, const float* Xc, double f_best,
-                               int64_t k, int64_t* topk_idx, float* ei_out) {
-  if (!c) return GPBO_E_INVALID_ARG;
+// Shared body of the two prescreen rules: member outputs, per-candidate score
+// (EI against f_best, or the negated lower confidence bound), top k.
+static gpbo_status prescreen(Ctx* c, gpbo_mlp mlp, int64_t m, const float* Xc, bool lcb,
+                             double arg, int64_t k, int64_t* topk_idx, float* score_out) {
   if (!mlp || m < 0 || k < 0 || k > m || (m > 0 && !Xc) || (k > 0 && !topk_idx))
     return fail(c, GPBO_E_INVALID_ARG, "invalid prescreen arguments");
+  if (lcb && !(arg >= 0.0)) return fail(c, GPBO_E_INVALID_ARG, "kappa must be >= 0");
   if (k > topk_max_k()) return fail(c, GPBO_E_UNSUPPORTED, "k > %d is not supported", topk_max_k());
+  if (m > 0xffffffffLL) return fail(c, GPBO_E_UNSUPPORTED, "m >= 2^32 is not supported");
   if (m == 0) return GPBO_OK;
   DeviceGuard g(c->device);
   hipStream_t s = c->stream;
   float* outs = (float*)dmalloc(c, (size_t)mlp->E * m * sizeof(float));
-  float* ei = ei_out ? ei_out : (float*)dmalloc(c, (size_t)m * sizeof(float));
+  float* sc = score_out ? score_out : (float*)dmalloc(c, (size_t)m * sizeof(float));
   void* scratch = k > 0 ? dmalloc(c, topk_scratch_bytes(m, k)) : nullptr;
-  if (!outs || !ei || (k > 0 && !scratch)) {
+  if (!outs || !sc || (k > 0 && !scratch)) {
     dfree(c, outs);
-    if (!ei_out) dfree(c, ei);
+    if (!score_out) dfree(c, sc);
     dfree(c, scratch);
     return fail(c, GPBO_E_OOM, "prescreen scratch allocation failed");
   }
   timed_mlp_forward(c, mlp->st, m, Xc, outs);
-  mlp_ens_ei(mlp->st, m, outs, f_best, ei, s);
-  if (k > 0) launch_topk_into(m, ei, k, topk_idx, scratch, s);
+  if (lcb)
+    mlp_ens_lcb(mlp->st, m, outs, arg, sc, s);
+  else
+    mlp_ens_ei(mlp->st, m, outs, arg, sc, s);
+  if (k > 0) launch_topk_into(m, sc, k, topk_idx, scratch, s);
   HIP_TRY(c, hipGetLastError());
   dfree(c, outs);
-  if (!ei_out) dfree(c, ei);
+  if (!score_out) dfree(c, sc);
   dfree(c, scratch);
   return GPBO_OK;
+}
+
+gpbo_status gpbo_mlp_prescreen(gpbo_ctx c, gpbo_mlp mlp, int64_t m, const float* Xc, double f_best,
+                               int64_t k, int64_t* topk_idx, float* ei_out) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  return prescreen(c, mlp, m, Xc, false, f_best, k, topk_idx, ei_out);
+}
+
+gpbo_status gpbo_mlp_prescreen_lcb(gpbo_ctx c, gpbo_mlp mlp, int64_t m, const float* Xc,
+                                   double kappa, int64_t k, int64_t* topk_idx, float* score_out) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  return prescreen(c, mlp, m, Xc, true, kappa, k, topk_idx, score_out);
 }
 
 }  // extern "C"

@@ -208,5 +208,7 @@ bool mlp_grads(MlpState* st, int64_t n, const float* X, const float* y, float* g
                hipStream_t s);
 void mlp_forward(MlpState* st, int64_t m, const float* Xc, float* out, hipStream_t s);
 void mlp_ens_ei(MlpState* st, int64_t m, const float* out, double fbest, float* ei, hipStream_t s);
+void mlp_ens_lcb(MlpState* st, int64_t m, const float* out, double kappa, float* score,
+                 hipStream_t s);
 
 }  // namespace gpbo

@@ -44,6 +44,7 @@ __device__ __forceinline__ float gelu_grad(float u) {
 
 struct MlpDev {
   int E, D, H;
+  int DP;                  // D rounded up to the matrix-core depth (32 or 64)
   int64_t P;               // parameters per member
   float* master;           // E x P
   float* mom1;             // E x P
@@ -79,10 +80,13 @@ __global__ void k_mlp_cast(MlpDev M) {
     M.w3b[(int64_t)e * H + i] = f2bf(p[off_w3(M) + i]);
 }
 
-// Forward of MT samples through one member (blockIdx.y), 256 threads.
-//   layer 1 (VALU): pre1 = W1 x + b1, h1 = bf16(GELU(pre1)) into an LDS tile;
-//   layer 2 (matrix cores): pre2 = h1 W2^T + b2, each wave 64 samples x 64
-//   outputs; epilogue h2 = bf16(GELU(pre2)), out = w3 . h2 + b3.
+// Forward of MT samples through one member (blockIdx.y), 256 threads, both
+// dense layers on the bfloat16 matrix cores:
+//   layer 1: pre1 = x W1^T + b1 (x and W1 staged in LDS, zero-padded to DP),
+//   each wave 64 samples x 64 hidden units; h1 = bf16(GELU(pre1)) into an
+//   LDS tile;
+//   layer 2: pre2 = h1 W2^T + b2, each wave 64 samples x 64 outputs;
+//   epilogue h2 = bf16(GELU(pre2)), out = w3 . h2 + b3.
 // With TRAIN the kernel also writes pre1, h1 (both layouts) and pre2.
 struct FwdOut {
   float* out;               // E x n
@@ -92,41 +96,73 @@ struct FwdOut {
   float* pre2;              // E x n x H (TRAIN)
 };
 
+__device__ __forceinline__ int fwd_ldx(int DP) { return DP + 8; }  // bf16 row stride of x / W1 tiles
+
 template <bool TRAIN>
 __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const float* __restrict__ X,
                                                  FwdOut O) {
   extern __shared__ __align__(16) unsigned char sm[];
-  const int H = M.H, D = M.D;
+  const int H = M.H, D = M.D, DP = M.DP;
   const int e = blockIdx.y;
   const int64_t i0 = (int64_t)blockIdx.x * MT;
   const int t = threadIdx.x, lane = t % 64, wave = wave_id();
   const int ldh = H + 8;  // bf16 row stride of the h1 tile (16-byte rows, skewed banks)
+  const int ldx = fwd_ldx(DP);
   unsigned short* hA = (unsigned short*)sm;                   // [MT][ldh]
-  float* xs = (float*)(sm + (size_t)MT * ldh * 2);            // [MT][D]
-  float* w1s = xs + MT * D;                                   // [H][D] (bf16 values as float)
-  float* red = w1s + H * D;                                   // [4][MT]
+  unsigned short* xb = hA + MT * ldh;                         // [MT][ldx]
+  unsigned short* w1 = xb + MT * ldx;                         // [H][ldx]
+  float* red = (float*)(w1 + H * ldx);                        // [4][MT]
   const float* p = M.master + e * M.P;
-  for (int q = t; q < MT * D; q += 256) {
-    const int64_t i = i0 + q / D;
-    xs[q] = i < n ? bfr(X[i * D + q % D]) : 0.0f;
+  for (int q = t; q < MT * DP; q += 256) {
+    const int r = q / DP, k = q % DP;
+    const int64_t i = i0 + r;
+    xb[r * ldx + k] = (i < n && k < D) ? f2bf(X[i * D + k]) : (unsigned short)0;
   }
-  for (int q = t; q < H * D; q += 256) w1s[q] = bf2f(M.W1b[(int64_t)e * H * D + q]);
+  for (int q = t; q < H * DP; q += 256) {
+    const int h = q / DP, k = q % DP;
+    w1[h * ldx + k] = k < D ? M.W1b[((int64_t)e * H + h) * D + k] : (unsigned short)0;
+  }
   __syncthreads();
-  // layer 1: thread t owns feature t (H <= 256 checked by the host) for all samples
-  for (int h = t; h < H; h += 256) {
+  const int ocol = wave * 64;  // this wave's 64 columns (hidden units / outputs)
+  f4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < DP; k0 += 32) {
+    us8 av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      av[a] = *(const us8*)(xb + (a * 16 + lane % 16) * ldx + k0 + 8 * (lane / 16));
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      bv[b] = *(const us8*)(w1 + (ocol + b * 16 + lane % 16) * ldx + k0 + 8 * (lane / 16));
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, av[a]),
+                                                            __builtin_bit_cast(bf8, bv[b]),
+                                                            acc[a][b], 0, 0, 0);
+  }
+  // layer-1 epilogue: lane holds samples 16a + 4(lane/16) + r, unit ocol + 16b + lane%16
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int h = ocol + b * 16 + lane % 16;
     const float bb = p[off_b1(M) + h];
-    for (int r = 0; r < MT; ++r) {
-      float s = 0.0f;
-      for (int k = 0; k < D; ++k) s = fmaf(w1s[h * D + k], xs[r * D + k], s);
-      const float pre = s + bb;
-      const unsigned short hb = f2bf(gelu(pre));
-      hA[r * ldh + h] = hb;
-      const int64_t i = i0 + r;
-      if (TRAIN && i < n) {
-        O.pre1[((int64_t)e * n + i) * H + h] = pre;
-        O.h1[((int64_t)e * n + i) * H + h] = hb;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = a * 16 + 4 * (lane / 16) + r;
+        const float pre = acc[a][b][r] + bb;
+        const unsigned short hb = f2bf(gelu(pre));
+        hA[row * ldh + h] = hb;
+        if (TRAIN && i0 + row < n) {
+          O.pre1[((int64_t)e * n + i0 + row) * H + h] = pre;
+          O.h1[((int64_t)e * n + i0 + row) * H + h] = hb;
+        }
       }
-    }
   }
   __syncthreads();
   if (TRAIN) {  // feature-major copy, coalesced along the samples
@@ -135,14 +171,12 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
       if (i0 + r < n) O.h1T[((int64_t)e * H + h) * n + i0 + r] = hA[r * ldh + h];
     }
   }
-  // layer 2: wave w computes outputs [64w, 64w + 64) for the MT samples
-  f4 acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+  // layer 2: wave w computes outputs [64w, 64w + 64) for the MT samples
   const unsigned short* W2 = M.W2b + (int64_t)e * H * H;
-  const int ocol = wave * 64;
   for (int k0 = 0; k0 < H; k0 += 32) {
     us8 av[4], bv[4];
 #pragma unroll
@@ -327,7 +361,9 @@ __global__ void __launch_bounds__(256) k_gemm_nt(Gemm g) {
 
 // Layer-1 gradients: gW1[h][d] = sum_i bf16(dpre1[i][h]) bf16(x[i][d]),
 // gb1[h] = sum_i dpre1[i][h]; workgroup (feature block of 64, member, sample
-// split); partial sums per split.
+// split); partial sums per split.  DP: D rounded up to a power of two, so
+// the accumulators stay in registers.
+template <int DP>
 __global__ void __launch_bounds__(256) k_mlp_bwd_l1(MlpDev M, int64_t n, const float* __restrict__ X,
                                                     const float* __restrict__ dpre1,
                                                     int64_t ichunk, float* __restrict__ part) {
@@ -337,20 +373,33 @@ __global__ void __launch_bounds__(256) k_mlp_bwd_l1(MlpDev M, int64_t n, const f
   const int h = blockIdx.x * 64 + threadIdx.x % 64, grp = threadIdx.x / 64;
   const int64_t ib = split * ichunk, ie = min(n, ib + ichunk);
   // per thread: D weight sums + the bias sum, accumulated over its samples
-  float acc[65];
-  const int nd = D + 1;
-  for (int k = 0; k < nd; ++k) acc[k] = 0.0f;
+  float acc[DP + 1];
+#pragma unroll
+  for (int k = 0; k <= DP; ++k) acc[k] = 0.0f;
   if (h < H) {
     for (int64_t i = ib + grp; i < ie; i += 4) {
       const float dp = dpre1[((int64_t)e * n + i) * H + h];
       const float dr = bfr(dp);
-      for (int k = 0; k < D; ++k) acc[k] = fmaf(dr, bfr(X[i * D + k]), acc[k]);
-      acc[D] += dp;
+      const float* xi = X + i * D;
+#pragma unroll
+      for (int k = 0; k < DP; ++k)
+        if (k < D) acc[k] = fmaf(dr, bfr(xi[k]), acc[k]);
+      acc[DP] += dp;
     }
   }
+  const int nd = D + 1;
   // combine the four sample groups, 16 values at a time
-  for (int k0 = 0; k0 < nd; k0 += 16) {
-    for (int q = 0; q < 16; ++q) red[grp][threadIdx.x % 64][q] = k0 + q < nd ? acc[k0 + q] : 0.0f;
+#pragma unroll
+  for (int k0 = 0; k0 < DP + 1; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      // column k of the output: weight sums for k < D, the bias sum at k = D
+      const int k = k0 + q;
+      float v = 0.0f;
+      if (k < D) v = acc[k < DP ? k : 0];
+      else if (k == D) v = acc[DP];
+      red[grp][threadIdx.x % 64][q] = v;
+    }
     __syncthreads();
     if (grp == 0 && h < H) {
       for (int q = 0; q < 16 && k0 + q < nd; ++q) {
@@ -451,6 +500,24 @@ __global__ void k_ens_ei(int E, int64_t m, const float* __restrict__ out, float 
   }
 }
 
+// Ensemble lower confidence bound as a score to maximise:
+// score = -(mean - kappa * sd), mean and population sd over the members.
+__global__ void k_ens_lcb(int E, int64_t m, const float* __restrict__ out, float kappa,
+                          float* __restrict__ score) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.0f;
+    for (int e = 0; e < E; ++e) s += out[(int64_t)e * m + i];
+    const float mean = s / E;
+    float q = 0.0f;
+    for (int e = 0; e < E; ++e) {
+      const float d = out[(int64_t)e * m + i] - mean;
+      q += d * d;
+    }
+    score[i] = -(mean - kappa * sqrtf(q / E));
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -468,8 +535,11 @@ struct MlpState {
   std::vector<uint64_t> graph_key;
 };
 
+int mlp_dp(int D) { return D <= 32 ? 32 : 64; }
+
 size_t mlp_fwd_smem(int D, int H) {
-  return (size_t)MT * (H + 8) * 2 + (size_t)MT * D * 4 + (size_t)H * D * 4 + 4 * MT * 4;
+  const int ldx = mlp_dp(D) + 8;
+  return (size_t)MT * (H + 8) * 2 + (size_t)MT * ldx * 2 + (size_t)H * ldx * 2 + 4 * MT * 4;
 }
 
 MlpState* mlp_create(Ctx* c, int E, int D, int H, const float* init, hipStream_t s) {
@@ -478,6 +548,7 @@ MlpState* mlp_create(Ctx* c, int E, int D, int H, const float* init, hipStream_t
   MlpDev& M = st->dev;
   M.E = E;
   M.D = D;
+  M.DP = mlp_dp(D);
   M.H = H;
   M.P = (int64_t)H * D + H + (int64_t)H * H + H + H + 1;
   const size_t pb = (size_t)E * M.P * sizeof(float);
@@ -618,8 +689,15 @@ void mlp_step(MlpState* st, int64_t n, const float* X, const float* y, double lr
   g2.pre1 = w.pre1;
   hipLaunchKernelGGL(k_gemm_nt<EPI_DPRE1>, dim3((unsigned)(n / 64) * (H / 64), 1, E), dim3(256), 0,
                      s, g2);
-  hipLaunchKernelGGL(k_mlp_bwd_l1, dim3(ceil_div(H, 64), E, w.S1), dim3(256), 0, s, M, n, X,
-                     w.dpre1, w.ichunk, w.l1part);
+  const dim3 g_l1((unsigned)ceil_div(H, 64), E, w.S1);
+  if (M.D <= 8)
+    hipLaunchKernelGGL(k_mlp_bwd_l1<8>, g_l1, dim3(256), 0, s, M, n, X, w.dpre1, w.ichunk, w.l1part);
+  else if (M.D <= 16)
+    hipLaunchKernelGGL(k_mlp_bwd_l1<16>, g_l1, dim3(256), 0, s, M, n, X, w.dpre1, w.ichunk, w.l1part);
+  else if (M.D <= 32)
+    hipLaunchKernelGGL(k_mlp_bwd_l1<32>, g_l1, dim3(256), 0, s, M, n, X, w.dpre1, w.ichunk, w.l1part);
+  else
+    hipLaunchKernelGGL(k_mlp_bwd_l1<64>, g_l1, dim3(256), 0, s, M, n, X, w.dpre1, w.ichunk, w.l1part);
   AdamIn ai{w.gW2part, w.S2, w.l1part, w.S1, w.colpart, w.nblk, lr, grad_out, loss_hist, n, apply};
   hipLaunchKernelGGL(k_mlp_adam, dim3(64, E), dim3(256), 0, s, M, ai);
   if (apply) {
@@ -700,6 +778,13 @@ void mlp_ens_ei(MlpState* st, int64_t m, const float* out, double fbest, float* 
   const int g = (int)std::min<int64_t>(8192, ceil_div(m, 256));
   hipLaunchKernelGGL(k_ens_ei, dim3(std::max(g, 1)), dim3(256), 0, s, st->dev.E, m, out,
                      (float)fbest, ei);
+}
+
+void mlp_ens_lcb(MlpState* st, int64_t m, const float* out, double kappa, float* score,
+                 hipStream_t s) {
+  const int g = (int)std::min<int64_t>(8192, ceil_div(m, 256));
+  hipLaunchKernelGGL(k_ens_lcb, dim3(std::max(g, 1)), dim3(256), 0, s, st->dev.E, m, out,
+                     (float)kappa, score);
 }
 
 }  // namespace gpbo

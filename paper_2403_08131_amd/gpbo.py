@@ -88,6 +88,8 @@ _SIGS = {
     "gpbo_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "gpbo_mlp_prescreen": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_double,
                                      C.c_int64, C.c_void_p, C.c_void_p]),
+    "gpbo_mlp_prescreen_lcb": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                         C.c_double, C.c_int64, C.c_void_p, C.c_void_p]),
 }
 
 
@@ -363,6 +365,15 @@ class Mlp:
         self.ctx.check(lib().gpbo_mlp_prescreen(self.ctx.h, self.h, Xc.shape[0], _ptr(Xc),
                                                 float(f_best), int(k), _ptr(idx), _ptr(ei)))
         return idx, ei
+
+    def prescreen_lcb(self, Xc, kappa, k, want_score=False):
+        """gpbo_mlp_prescreen_lcb: top-k by -(ensemble mean - kappa * sd)."""
+        assert Xc.dtype == torch.float32 and Xc.is_contiguous() and Xc.shape[1] == self.D
+        idx = torch.empty(k, dtype=torch.int64, device=self.ctx.device)
+        sc = torch.empty(Xc.shape[0], dtype=torch.float32, device=self.ctx.device) if want_score else None
+        self.ctx.check(lib().gpbo_mlp_prescreen_lcb(self.ctx.h, self.h, Xc.shape[0], _ptr(Xc),
+                                                    float(kappa), int(k), _ptr(idx), _ptr(sc)))
+        return idx, sc
 
     def free(self):
         if getattr(self, "h", None):

@@ -162,11 +162,32 @@ def test_mlp_training_reduces_loss_and_graph_replays(ctx):
     assert np.all(h1[19] < h1[0])
 
 
+def test_prescreen_lcb_matches_oracle_and_sort(ctx):
+    """The LCB score equals the oracle's on the device's member outputs to
+    float32 rounding, and the top-k indices equal a sort of the device's own
+    float32 scores by (score descending, index ascending)."""
+    flat = _init(11)
+    net = G.Mlp(ctx, torch.tensor(flat, dtype=torch.float32, device=DEV).contiguous(), E, D, H)
+    X, _, _ = _data(20000, seed=12)
+    Xd = torch.tensor(X, dtype=torch.float32, device=DEV)
+    outs = net.forward(Xd).double().cpu().numpy()
+    for kappa, k in ((0.0, 1), (0.5, 777), (2.0, 4096)):
+        idx, sc = net.prescreen_lcb(Xd, kappa, k, want_score=True)
+        sc = sc.cpu().numpy()
+        ref = O.ens_lcb(outs, kappa)
+        assert np.max(np.abs(sc - ref)) <= 1e-5 * np.max(np.abs(ref)), kappa
+        want = np.lexsort((np.arange(sc.size), -sc.astype(np.float64)))[:k]
+        assert np.array_equal(idx.cpu().numpy(), want), kappa
+    with pytest.raises(G.GpboError):
+        net.prescreen_lcb(Xd, -1.0, 4)
+    net.free()
+
+
 def test_prescreen_gain_over_random_subset(ctx):
     """The trained network's top-k, re-scored by the exact GP, finds a better
     candidate than a random subset of the same size (same re-score cost)."""
-    hits_net = hits_rand = 0
-    ratio_net, ratio_rand = [], []
+    hits_net = hits_rand = hits_lcb = 0
+    ratio_net, ratio_rand, ratio_lcb = [], [], []
     for seed in range(3):
         spec = I.spec_grouped(D, 0.1)
         r = np.random.default_rng(100 + seed)
@@ -192,18 +213,27 @@ def test_prescreen_gain_over_random_subset(ctx):
         sub = G.gather_rows(ctx, torch.tensor(idx, device=DEV), pool_d)
         rs = G.score(ctx, model, sub, "fp32")["ei"].double().cpu().numpy()
         b_star = int(idx[np.argmax(rs)])
+        idx_l, _ = net.prescreen_lcb(pool_d, 0.0, k)
+        idx_l = idx_l.cpu().numpy()
+        sub_l = G.gather_rows(ctx, torch.tensor(idx_l, device=DEV), pool_d)
+        rs_l = G.score(ctx, model, sub_l, "fp32")["ei"].double().cpu().numpy()
+        l_star = int(idx_l[np.argmax(rs_l)])
+        ratio_lcb.append(full[l_star] / full[a_star])
+        hits_lcb += l_star == a_star
         rnd = np.random.default_rng(200 + seed).choice(65536, k, replace=False)
         r_star = int(rnd[np.argmax(full[rnd])])
         hits_net += b_star == a_star
         hits_rand += r_star == a_star
         ratio_net.append(full[b_star] / full[a_star])
         ratio_rand.append(full[r_star] / full[a_star])
-        print(f"  seed {seed}: net {full[b_star] / full[a_star]:.3f} (hit {b_star == a_star}), "
+        print(f"  seed {seed}: net EI {full[b_star] / full[a_star]:.3f} (hit {b_star == a_star}), "
+              f"net mean {full[l_star] / full[a_star]:.3f} (hit {l_star == a_star}), "
               f"random {full[r_star] / full[a_star]:.3f} (hit {r_star == a_star})")
         net.free()
         model.free()
-    assert hits_net >= hits_rand
+    assert hits_net >= hits_rand and hits_lcb >= hits_rand
     assert np.mean(ratio_net) > np.mean(ratio_rand)
+    assert np.mean(ratio_lcb) > np.mean(ratio_rand)
 
 
 def test_context_close_frees_live_objects():

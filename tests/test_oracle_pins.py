@@ -559,3 +559,14 @@ def test_ensemble_ei_against_numpy():
         z = (-0.2 - mu[i]) / sd[i]
         want = (-0.2 - mu[i]) * scipy.stats.norm.cdf(z) + sd[i] * scipy.stats.norm.pdf(z)
         assert e[i] == pytest.approx(want, rel=1e-11)
+
+
+def test_ensemble_lcb_special_cases():
+    """kappa = 0 ranks by the negated mean; two members a -/+ delta give
+    -(a - kappa delta); a single member has zero spread."""
+    a = np.array([0.3, -1.2, 2.0])
+    dl = np.array([0.1, 0.5, 0.0])
+    out = np.stack([a - dl, a + dl])
+    assert np.allclose(O.ens_lcb(out, 0.0), -a, rtol=0, atol=1e-15)
+    assert np.allclose(O.ens_lcb(out, 2.0), -(a - 2.0 * dl), rtol=0, atol=1e-15)
+    assert np.allclose(O.ens_lcb(a[None, :], 3.0), -a, rtol=0, atol=1e-15)
