@@ -234,107 +234,149 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
-// Factor the diagonal tile (k, k), write L_kk and its inverse D_k.  One wave:
-// the 64 column steps of the tile are a dependency chain, so the kernel keeps
-// each step short -- no barrier between waves, no division.
-//   Factorisation: lane i holds the not yet final part of row i in
-//   registers.  Step j reads the pivot from lane j, forms 1/sqrt(pivot)
-//   (hardware estimate and two Newton steps), scales column j, writes the
-//   final entries L_ij to LDS, publishes the column and applies the rank-1
-//   update to the rows' remaining entries.
-//   Inverse: lane c solves L x = e_c by forward substitution (column c of
-//   L_kk^-1), reading the rows of L as LDS broadcasts.
-// LDS reads are issued in groups of eight values with scheduling barriers in
-// between, which bounds the registers in flight.
-__global__ void __launch_bounds__(64) k_potrf_diag(const FitDesc* __restrict__ Ds, int k) {
-  __shared__ __align__(16) double Ls[NB][LDT];
-  __shared__ __align__(16) double colb[2][NB];
-  __shared__ double rdiag[NB];
+// Factor the diagonal tile (k, k), write L_kk and its inverse D_k.
+//   Factorisation, one wave: the 64 column steps of the tile are a
+//   dependency chain, so it runs in a single wave, with no inter-wave
+//   barrier and no division on the chain.  Lane i holds the not yet final
+//   part of row i in registers.  Step j reads the pivot from lane j, forms
+//   1/sqrt(pivot) (hardware estimate and two Newton steps), scales column j,
+//   writes the final entries L_ij to LDS, publishes the column through LDS
+//   and applies the rank-1 update to the rows' remaining entries.
+//   Inverse, four waves: column c of L_kk^-1 by forward substitution,
+//   x_r = (delta_rc - sum_{q<r} L_rq x_q) / L_rr, with four lanes per column
+//   that split the sum by q mod 4 and combine it by lane exchanges; each
+//   lane keeps the 16 entries x_q of its residue class.
+__global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ Ds, int k) {
+  // One LDS block with the small arrays first, so that every address the
+  // factorisation's column reads use fits the 16-bit LDS instruction offset.
+  struct Lds {
+    double colb[2][NB];  // published column, double-buffered
+    double rdiag[NB];    // 1 / L_jj
+    int bad;
+    int pad[3];
+    double Ls[NB][LDT];  // the tile, then L_kk
+    double Xl[NB][LDT];  // the inverse, staged for a coalesced store
+  };
+  __shared__ __align__(16) Lds S;
+  auto& colb = S.colb;
+  auto& rdiag = S.rdiag;
+  auto& bad_s = S.bad;
+  auto& Ls = S.Ls;
+  auto& Xl = S.Xl;
   const FitDesc& P = Ds[blockIdx.z];
   if (k >= P.npad / NB || fit_failed(P.info)) return;
   const int npad = P.npad;
-  const int i = threadIdx.x;
-  double* Akk = P.L + (int64_t)k * NB * npad + k * NB;
-  // coalesced rows into LDS, then row i into registers
-#pragma unroll 8
-  for (int r = 0; r < NB; ++r) Ls[r][i] = Akk[(int64_t)r * npad + i];
-  __syncthreads();
-  double a[NB];
+  const int t = threadIdx.x, lane = t % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(t / 64);
+  {
+    // coalesced rows into LDS, all loads in flight before the first store
+    const double* Akk = P.L + (int64_t)k * NB * npad + k * NB;
+    double v[NB / 4];
 #pragma unroll
-  for (int c = 0; c < NB; c += 2) {
-    const double2 v = *(const double2*)&Ls[i][c];
-    a[c] = v.x;
-    a[c + 1] = v.y;
+    for (int q = 0; q < NB / 4; ++q) v[q] = Akk[(int64_t)(wave + 4 * q) * npad + lane];
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) Ls[wave + 4 * q][lane] = v[q];
   }
   __syncthreads();
-  int bad = -1;  // first pivot that is not positive and finite (uniform)
+  if (wave == 0) {
+    const int i = lane;
+    double a[NB];
+#pragma unroll
+    for (int c = 0; c < NB; c += 2) {
+      const double2 v = *(const double2*)&Ls[i][c];
+      a[c] = v.x;
+      a[c + 1] = v.y;
+    }
+    __builtin_amdgcn_wave_barrier();
+    int bad = -1;  // first pivot that is not positive and finite (uniform)
 #pragma clang loop unroll(full)
-  for (int j = 0; j < NB; ++j) {
-    double d = readlane_f64(a[j], j);
-    if (bad < 0 && !(d > 0.0 && isfinite(d))) bad = j;
-    if (bad >= 0) d = 1.0;  // keep the arithmetic finite; the tile is discarded
-    double y = __builtin_amdgcn_rsq(d);
-    y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
-    y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
-    double sq = d * y;
-    sq = fma(0.5 * y, fma(-sq, sq, d), sq);  // sqrt(d), corrected
-    const double c = i > j ? a[j] * y : (i == j ? sq : 0.0);
-    Ls[i][j] = c;
-    if (i == 0) rdiag[j] = 1.0 / sq;
-    if (j + 1 < NB) {
-      double* cb = colb[j & 1];
-      cb[i] = c;
-      __syncthreads();
+    for (int j = 0; j < NB; ++j) {
+      double d = readlane_f64(a[j], j);
+      if (bad < 0 && !(d > 0.0 && isfinite(d))) bad = j;
+      if (bad >= 0) d = 1.0;  // keep the arithmetic finite; the tile is discarded
+      double y = __builtin_amdgcn_rsq(d);
+      y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
+      y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
+      double sq = d * y;
+      sq = fma(0.5 * y, fma(-sq, sq, d), sq);  // sqrt(d), corrected
+      const double c = i > j ? a[j] * y : (i == j ? sq : 0.0);
+      Ls[i][j] = c;
+      if (i == 0) rdiag[j] = y;  // 1 / L_jj
+      if (j + 1 < NB) {
+        double* cb = colb[j & 1];
+        cb[i] = c;
+        // one wave: a wave-scope fence orders the column's LDS store before
+        // the reads below (and keeps the compiler from moving reads across
+        // steps)
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
-      for (int l0 = (j + 1) & ~7; l0 < NB; l0 += 8) {
-        __builtin_amdgcn_sched_barrier(0);
+        for (int l0 = (j + 1) & ~7; l0 < NB; l0 += 8) {
 #pragma unroll
-        for (int q = 0; q < 8; q += 2) {
-          const double2 v = *(const double2*)&cb[l0 + q];
-          if (l0 + q > j) a[l0 + q] = fma(-c, v.x, a[l0 + q]);
-          if (l0 + q + 1 > j) a[l0 + q + 1] = fma(-c, v.y, a[l0 + q + 1]);
+          for (int q = 0; q < 8; q += 2) {
+            const double2 v = *(const double2*)&cb[l0 + q];
+            if (l0 + q > j) a[l0 + q] = fma(-c, v.x, a[l0 + q]);
+            if (l0 + q + 1 > j) a[l0 + q + 1] = fma(-c, v.y, a[l0 + q + 1]);
+          }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       }
     }
+    if (lane == 0) bad_s = bad;
   }
-  if (bad >= 0) {
-    if (i == 0) atomicMin(&P.info[0], k * NB + bad);
+  __syncthreads();
+  if (bad_s >= 0) {
+    if (t == 0) atomicMin(&P.info[0], k * NB + bad_s);
     return;
   }
-  __syncthreads();
-#pragma unroll 8
-  for (int r = 0; r < NB; ++r) Akk[(int64_t)r * npad + i] = Ls[r][i];
-  // column i of the inverse: x_r = (delta_ri - sum_{q<r} L_rq x_q) / L_rr
-  double x[NB];
+  {
+    // addresses formed only now (a volatile read keeps the compiler from
+    // holding them in registers across the factorisation)
+    const int np2 = *(const volatile int*)&P.npad;
+    double* Akk = P.L + (int64_t)k * NB * np2 + k * NB;
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) {
+      const int r = wave + 4 * q;
+      Akk[(int64_t)r * np2 + lane] = Ls[r][lane];
+    }
+  }
+  // inverse: column c, residue class p of the summation index
+  const int c = wave * 16 + lane / 4, p = lane % 4;
+  double* Dk = P.Dinv + (int64_t)k * NB * NB;
+  double xs[NB / 4];  // xs[m] = x_{4m + p}
+#pragma unroll
+  for (int m = 0; m < NB / 4; ++m) xs[m] = 0.0;
 #pragma clang loop unroll(full)
   for (int r = 0; r < NB; ++r) {
-    double s0 = r == i ? 1.0 : 0.0, s1 = 0.0;
+    __builtin_amdgcn_sched_barrier(0);  // keeps each row's LDS reads near their use
+    double s = 0.0;
 #pragma unroll
-    for (int q0 = 0; q0 < r; q0 += 8) {
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int q = q0; q < q0 + 8; q += 2) {
-        if (q < r) {
-          const double2 l2 = *(const double2*)&Ls[r][q];
-          s0 = fma(-l2.x, x[q], s0);
-          if (q + 1 < r) s1 = fma(-l2.y, x[q + 1], s1);
-        }
-      }
+    for (int m = 0; 4 * m < r; ++m)
+      if (4 * m + p < r) s = fma(-Ls[r][4 * m + p], xs[m], s);
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    const double x = ((r == c ? 1.0 : 0.0) + s) * rdiag[r];
+    if (p == r % 4) {
+      xs[r / 4] = x;
+      Xl[r][c] = x;
     }
-    x[r] = (s0 + s1) * rdiag[r];
   }
-  double* Dk = P.Dinv + (int64_t)k * NB * NB;
+  __syncthreads();
 #pragma unroll
-  for (int r = 0; r < NB; ++r) Dk[r * NB + i] = x[r];
+  for (int q = 0; q < NB / 4; ++q) {
+    const int r = wave + 4 * q;
+    Dk[r * NB + lane] = Xl[r][lane];
+  }
 }
 
+// The tile operations of the factorisation and of the inverse factor.  The
+// inverse factor X = L^-1 is formed block row by block row in right-looking
+// order: step I sets X_IJ = D_I B_IJ (J <= I; B_II = I) and then
+// B_KJ -= L_KI X_IJ for K > I.  Step I needs only column block I of L and
+// D_I, so it runs inside the launches of the factorisation's step I + 1,
+// on workgroups of their own: no extra launch per step.
+
 // Panel: A_Ik <- A_Ik D_k^T for I > k.
-__global__ void __launch_bounds__(256) k_chol_panel(const FitDesc* __restrict__ Ds, int k) {
-  extern __shared__ double sm[];
-  const FitDesc& P = Ds[blockIdx.z];
-  const int nb = P.npad / NB;
-  const int I = k + 1 + blockIdx.x;
-  if (I >= nb || fit_failed(P.info)) return;
+__device__ __forceinline__ void panel_tile(const FitDesc& P, int k, int I, double* sm) {
   const int npad = P.npad;
   double* At = sm;
   double* Bt = sm + NB * LDT;
@@ -349,20 +391,10 @@ __global__ void __launch_bounds__(256) k_chol_panel(const FitDesc* __restrict__ 
 }
 
 // Trailing update: A_IJ -= A_Ik A_Jk^T for k < J <= I.
-__global__ void __launch_bounds__(256) k_chol_update(const FitDesc* __restrict__ Ds, int k) {
-  extern __shared__ double sm[];
-  const FitDesc& P = Ds[blockIdx.z];
-  // rest < 0 for a smaller problem of a batch whose factorisation has ended
-  // (rest (rest + 1) / 2 would be positive again for rest <= -2).
-  const int rest = P.npad / NB - k - 1;
-  if (rest <= 0 || (int)blockIdx.x >= rest * (rest + 1) / 2 || fit_failed(P.info)) return;
+__device__ __forceinline__ void update_tile(const FitDesc& P, int k, int I, int J, double* sm) {
   const int npad = P.npad;
   double* At = sm;
   double* Bt = sm + NB * LDT;
-  int I, J;
-  tri_index(blockIdx.x, I, J);
-  I += k + 1;
-  J += k + 1;
   load_tile(P.L + (int64_t)I * NB * npad + k * NB, npad, At, true);
   load_tile(P.L + (int64_t)J * NB * npad + k * NB, npad, Bt, true);
   __syncthreads();
@@ -371,12 +403,8 @@ __global__ void __launch_bounds__(256) k_chol_update(const FitDesc* __restrict__
   store_tile(P.L + (int64_t)I * NB * npad + J * NB, npad, acc, 1);
 }
 
-// Inverse factor, step I: row block I of X = L^-1 becomes D_I B_I (B_II = I).
-__global__ void __launch_bounds__(256) k_trtri_rowmul(const FitDesc* __restrict__ Ds, int I) {
-  extern __shared__ double sm[];
-  const FitDesc& P = Ds[blockIdx.z];
-  const int J = blockIdx.x;
-  if (I >= P.npad / NB || J > I || fit_failed(P.info)) return;
+// Inverse factor, step I: X_IJ = D_I B_IJ for J < I, X_II = D_I.
+__device__ __forceinline__ void rowmul_tile(const FitDesc& P, int I, int J, double* sm) {
   const int npad = P.npad;
   double* C = P.Linv + (int64_t)I * NB * npad + J * NB;
   const double* Dk = P.Dinv + (int64_t)I * NB * NB;
@@ -396,14 +424,8 @@ __global__ void __launch_bounds__(256) k_trtri_rowmul(const FitDesc* __restrict_
 }
 
 // Inverse factor, step I: B_KJ -= L_KI X_IJ for K > I, J <= I.
-__global__ void __launch_bounds__(256) k_trtri_update(const FitDesc* __restrict__ Ds, int I) {
-  extern __shared__ double sm[];
-  const FitDesc& P = Ds[blockIdx.z];
-  const int nb = P.npad / NB;
-  if (I >= nb - 1 || (int)blockIdx.x >= (nb - I - 1) * (I + 1) || fit_failed(P.info)) return;
+__device__ __forceinline__ void trtri_update_tile(const FitDesc& P, int I, int K, int J, double* sm) {
   const int npad = P.npad;
-  const int K = I + 1 + blockIdx.x / (I + 1);
-  const int J = blockIdx.x % (I + 1);
   double* At = sm;
   double* Bt = sm + NB * LDT;
   load_tile(P.L + (int64_t)K * NB * npad + I * NB, npad, At, true);
@@ -412,6 +434,49 @@ __global__ void __launch_bounds__(256) k_trtri_update(const FitDesc* __restrict_
   double acc[4][4] = {};
   tile_mac(At, Bt, acc);
   store_tile(P.Linv + (int64_t)K * NB * npad + J * NB, npad, acc, 1);
+}
+
+// Launch of step k (k <= nbmax): panel tiles of the factorisation (the first
+// npanel workgroups, npanel = nbmax - k - 1 for the largest problem) and the
+// row-multiply tiles of inverse step k - 1.
+__global__ void __launch_bounds__(256) k_chol_panel(const FitDesc* __restrict__ Ds, int k,
+                                                    int npanel) {
+  extern __shared__ double sm[];
+  const FitDesc& P = Ds[blockIdx.z];
+  if (fit_failed(P.info)) return;
+  const int nb = P.npad / NB;
+  const int bx = blockIdx.x;
+  if (bx < npanel) {
+    const int I = k + 1 + bx;
+    if (I < nb) panel_tile(P, k, I, sm);
+  } else {
+    const int I = k - 1, J = bx - npanel;
+    if (I >= 0 && I < nb && J <= I) rowmul_tile(P, I, J, sm);
+  }
+}
+
+// Launch of step k: trailing-update tiles of the factorisation (the first
+// nupd workgroups) and the update tiles of inverse step k - 1.
+__global__ void __launch_bounds__(256) k_chol_update(const FitDesc* __restrict__ Ds, int k,
+                                                     int nupd) {
+  extern __shared__ double sm[];
+  const FitDesc& P = Ds[blockIdx.z];
+  if (fit_failed(P.info)) return;
+  const int nb = P.npad / NB;
+  const int bx = blockIdx.x;
+  if (bx < nupd) {
+    // rest < 0 for a smaller problem of a batch whose factorisation has
+    // ended (rest (rest + 1) / 2 would be positive again for rest <= -2).
+    const int rest = nb - k - 1;
+    if (rest <= 0 || bx >= rest * (rest + 1) / 2) return;
+    int I, J;
+    tri_index(bx, I, J);
+    update_tile(P, k, I + k + 1, J + k + 1, sm);
+  } else {
+    const int I = k - 1, b = bx - nupd;
+    if (I < 0 || I >= nb - 1 || b >= (nb - I - 1) * (I + 1)) return;
+    trtri_update_tile(P, I, I + 1 + b / (I + 1), b % (I + 1), sm);
+  }
 }
 
 // Zero the inverse factor (and make the float32 copy when refining).
@@ -587,8 +652,6 @@ void allow_tile_lds() {
   const int bytes = 2 * NB * LDT * sizeof(double);
   (void)hipFuncSetAttribute((const void*)k_chol_panel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   (void)hipFuncSetAttribute((const void*)k_chol_update, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  (void)hipFuncSetAttribute((const void*)k_trtri_rowmul, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  (void)hipFuncSetAttribute((const void*)k_trtri_update, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   done = true;
 }
 
@@ -636,21 +699,21 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   const unsigned Bz = (unsigned)B;
   hipLaunchKernelGGL(k_fit_stats, dim3(1, 1, Bz), dim3(256), 0, s, dd);
   hipLaunchKernelGGL(k_gram, dim3(nbmax * (nbmax + 1) / 2, 1, Bz), dim3(256), 0, s, dd);
-  for (int k = 0; k < nbmax; ++k) {
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, Bz), dim3(64), 0, s, dd, k);
-    const int rest = nbmax - k - 1;
-    if (rest > 0) {
-      hipLaunchKernelGGL(k_chol_panel, dim3(rest, 1, Bz), dim3(256), sm2, s, dd, k);
-      hipLaunchKernelGGL(k_chol_update, dim3(rest * (rest + 1) / 2, 1, Bz), dim3(256), sm2, s, dd, k);
-    }
-  }
   const unsigned gz = (unsigned)std::min<int64_t>(1024, ceil_div(npmax * npmax, 256));
   hipLaunchKernelGGL(k_zero_linv, dim3(gz, 1, Bz), dim3(256), 0, s, dd);
-  for (int I = 0; I < nbmax; ++I) {
-    hipLaunchKernelGGL(k_trtri_rowmul, dim3(I + 1, 1, Bz), dim3(256), sm2, s, dd, I);
-    const int rest = nbmax - I - 1;
-    if (rest > 0)
-      hipLaunchKernelGGL(k_trtri_update, dim3(rest * (I + 1), 1, Bz), dim3(256), sm2, s, dd, I);
+  // step k: diagonal tile k; panel k with row multiply of inverse step k-1;
+  // trailing update k with the update of inverse step k-1; step nbmax
+  // finishes the inverse
+  for (int k = 0; k <= nbmax; ++k) {
+    if (k < nbmax) hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, Bz), dim3(256), 0, s, dd, k);
+    const int npanel = std::max(nbmax - k - 1, 0);
+    const int nrow = k;  // inverse step k - 1 has k tiles in its row
+    if (npanel + nrow > 0)
+      hipLaunchKernelGGL(k_chol_panel, dim3(npanel + nrow, 1, Bz), dim3(256), sm2, s, dd, k, npanel);
+    const int nupd = npanel * (npanel + 1) / 2;
+    const int ntri = k >= 1 ? (nbmax - k) * k : 0;  // inverse step k - 1: (nbmax-k) rows x k tiles
+    if (nupd + ntri > 0)
+      hipLaunchKernelGGL(k_chol_update, dim3(nupd + ntri, 1, Bz), dim3(256), sm2, s, dd, k, nupd);
   }
   hipLaunchKernelGGL(k_cast_linv, dim3(gz, 1, Bz), dim3(256), 0, s, dd);
   const unsigned g_rows = (unsigned)ceil_div(npmax, 4), g_cols = (unsigned)ceil_div(npmax, 64);
