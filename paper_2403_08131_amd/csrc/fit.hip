@@ -39,28 +39,24 @@ __device__ __forceinline__ bool fit_failed(const int* info) {
   return v[0] != INT_MAX || v[1] != 0;
 }
 
+// Workgroup reductions (256 threads): butterfly within each wave, then the
+// four wave results through LDS.
 __device__ __forceinline__ double block_sum(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x / 64;
+  if (threadIdx.x % 64 == 0) red[w] = v;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  double r = red[0];
+  const double r = (red[0] + red[1]) + (red[2] + red[3]);
   __syncthreads();
   return r;
 }
 
 __device__ __forceinline__ double block_min(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  const int w = threadIdx.x / 64;
+  if (threadIdx.x % 64 == 0) red[w] = v;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] = fmin(red[t], red[t + s]);
-    __syncthreads();
-  }
-  double r = red[0];
+  const double r = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
   __syncthreads();
   return r;
 }
@@ -234,21 +230,20 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
-// Factor the diagonal tile (k, k), write L_kk and its inverse D_k.
-//   Factorisation, one wave: the 64 column steps of the tile are a
-//   dependency chain, so it runs in a single wave, with no inter-wave
-//   barrier and no division on the chain.  Lane i holds the not yet final
-//   part of row i in registers.  Step j reads the pivot from lane j, forms
-//   1/sqrt(pivot) (hardware estimate and two Newton steps), scales column j,
-//   writes the final entries L_ij to LDS, publishes the column through LDS
-//   and applies the rank-1 update to the rows' remaining entries.
-//   Inverse, four waves: column c of L_kk^-1 by forward substitution,
-//   x_r = (delta_rc - sum_{q<r} L_rq x_q) / L_rr, with four lanes per column
-//   that split the sum by q mod 4 and combine it by lane exchanges; each
-//   lane keeps the 16 entries x_q of its residue class.
+// Factor the diagonal tile (k, k), write L_kk and its inverse D_k.  The 64
+// column steps of the tile are a dependency chain; the kernel keeps the chain
+// in one wave and gives the parallel parts to all four.
+//   Factorisation, blocked over four 16-column panels: wave 0 factors the
+//   64 x 16 panel (lane i holds row i's panel entries in registers; step j
+//   reads the pivot from lane j, forms 1/sqrt(pivot) from the hardware
+//   estimate and two Newton steps, scales column j, publishes it through LDS
+//   and updates the remaining panel columns); then all waves apply the
+//   panel's rank-16 update to the trailing lower triangle in LDS.
+//   Inverse, blocked over 16 x 16 blocks (see below).
 __global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ Ds, int k) {
   // One LDS block with the small arrays first, so that every address the
   // factorisation's column reads use fits the 16-bit LDS instruction offset.
+  constexpr int PW = 16;  // panel width of the blocked factorisation
   struct Lds {
     double colb[2][NB];  // published column, double-buffered
     double rdiag[NB];    // 1 / L_jj
@@ -256,6 +251,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ 
     int pad[3];
     double Ls[NB][LDT];  // the tile, then L_kk
     double Xl[NB][LDT];  // the inverse, staged for a coalesced store
+    double Tb[NB / PW][PW][PW];  // block products of the inverse
   };
   __shared__ __align__(16) Lds S;
   auto& colb = S.colb;
@@ -263,6 +259,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ 
   auto& bad_s = S.bad;
   auto& Ls = S.Ls;
   auto& Xl = S.Xl;
+  auto& Tb = S.Tb;
   const FitDesc& P = Ds[blockIdx.z];
   if (k >= P.npad / NB || fit_failed(P.info)) return;
   const int npad = P.npad;
@@ -278,51 +275,80 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ 
     for (int q = 0; q < NB / 4; ++q) Ls[wave + 4 * q][lane] = v[q];
   }
   __syncthreads();
-  if (wave == 0) {
-    const int i = lane;
-    double a[NB];
+  // Blocked over four 16-column panels: wave 0 factors the 64 x 16 panel
+  // (lane i = row i, 16 sequential column steps), then all waves apply the
+  // panel's rank-16 update to the trailing lower triangle in LDS.
+  int bad = -1;  // first pivot that is not positive and finite (uniform in wave 0)
 #pragma unroll
-    for (int c = 0; c < NB; c += 2) {
-      const double2 v = *(const double2*)&Ls[i][c];
-      a[c] = v.x;
-      a[c + 1] = v.y;
-    }
-    __builtin_amdgcn_wave_barrier();
-    int bad = -1;  // first pivot that is not positive and finite (uniform)
-#pragma clang loop unroll(full)
-    for (int j = 0; j < NB; ++j) {
-      double d = readlane_f64(a[j], j);
-      if (bad < 0 && !(d > 0.0 && isfinite(d))) bad = j;
-      if (bad >= 0) d = 1.0;  // keep the arithmetic finite; the tile is discarded
-      double y = __builtin_amdgcn_rsq(d);
-      y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
-      y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
-      double sq = d * y;
-      sq = fma(0.5 * y, fma(-sq, sq, d), sq);  // sqrt(d), corrected
-      const double c = i > j ? a[j] * y : (i == j ? sq : 0.0);
-      Ls[i][j] = c;
-      if (i == 0) rdiag[j] = y;  // 1 / L_jj
-      if (j + 1 < NB) {
-        double* cb = colb[j & 1];
-        cb[i] = c;
-        // one wave: a wave-scope fence orders the column's LDS store before
-        // the reads below (and keeps the compiler from moving reads across
-        // steps)
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  for (int p0 = 0; p0 < NB; p0 += PW) {
+    if (wave == 0) {
+      const int i = lane;
+      double r[PW];
 #pragma unroll
-        for (int l0 = (j + 1) & ~7; l0 < NB; l0 += 8) {
+      for (int q = 0; q < PW; q += 2) {
+        const double2 v = *(const double2*)&Ls[i][p0 + q];
+        r[q] = v.x;
+        r[q + 1] = v.y;
+      }
 #pragma unroll
-          for (int q = 0; q < 8; q += 2) {
-            const double2 v = *(const double2*)&cb[l0 + q];
-            if (l0 + q > j) a[l0 + q] = fma(-c, v.x, a[l0 + q]);
-            if (l0 + q + 1 > j) a[l0 + q + 1] = fma(-c, v.y, a[l0 + q + 1]);
-          }
+      for (int jj = 0; jj < PW; ++jj) {
+        const int j = p0 + jj;
+        double d = readlane_f64(r[jj], j);
+        if (bad < 0 && !(d > 0.0 && isfinite(d))) bad = j;
+        if (bad >= 0) d = 1.0;  // keep the arithmetic finite; the tile is discarded
+        double y = __builtin_amdgcn_rsq(d);
+        y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
+        y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
+        double sq = d * y;
+        sq = fma(0.5 * y, fma(-sq, sq, d), sq);  // sqrt(d), corrected
+        const double c = i > j ? r[jj] * y : (i == j ? sq : 0.0);
+        r[jj] = c;
+        if (i == 0) rdiag[j] = y;  // 1 / L_jj
+        if (jj + 1 < PW) {
+          double* cb = colb[jj & 1];
+          cb[i] = c;
+          // one wave: a wave-scope fence orders the column's LDS store
+          // before the reads below
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+          for (int q = jj + 1; q < PW; ++q) r[q] = fma(-c, cb[p0 + q], r[q]);
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      }
+      // the panel back to LDS; entries above the diagonal are zero
+#pragma unroll
+      for (int q = 0; q < PW; q += 2) {
+        double2 v;
+        v.x = p0 + q <= i ? r[q] : 0.0;
+        v.y = p0 + q + 1 <= i ? r[q + 1] : 0.0;
+        *(double2*)&Ls[i][p0 + q] = v;
       }
     }
-    if (lane == 0) bad_s = bad;
+    __syncthreads();
+    // rank-16 update of the trailing lower triangle: A_il -= sum_q L_iq L_lq
+    // for p0 + 16 <= l <= i; each thread takes a 1 x 2 pair of entries
+    const int m = NB - p0 - PW;
+    if (m > 0) {
+      const int half = m / 2;
+      for (int e = t; e < m * half; e += 256) {
+        const int ii = p0 + PW + e / half, l = p0 + PW + 2 * (e % half);
+        if (l > ii) continue;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < PW; q += 2) {
+          const double2 li = *(const double2*)&Ls[ii][p0 + q];
+          const double2 l0 = *(const double2*)&Ls[l][p0 + q];
+          const double2 l1 = *(const double2*)&Ls[l + 1][p0 + q];
+          s0 = fma(li.x, l0.x, fma(li.y, l0.y, s0));
+          s1 = fma(li.x, l1.x, fma(li.y, l1.y, s1));
+        }
+        Ls[ii][l] -= s0;
+        if (l + 1 <= ii) Ls[ii][l + 1] -= s1;
+      }
+    }
+    __syncthreads();
   }
+  if (t == 0) bad_s = bad;
   __syncthreads();
   if (bad_s >= 0) {
     if (t == 0) atomicMin(&P.info[0], k * NB + bad_s);
@@ -339,28 +365,58 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ 
       Akk[(int64_t)r * np2 + lane] = Ls[r][lane];
     }
   }
-  // inverse: column c, residue class p of the summation index
-  const int c = wave * 16 + lane / 4, p = lane % 4;
-  double* Dk = P.Dinv + (int64_t)k * NB * NB;
-  double xs[NB / 4];  // xs[m] = x_{4m + p}
+  // Inverse, blocked over 4 x 4 blocks of 16: the diagonal blocks by
+  // forward substitution (wave s inverts block s, lane = column), then the
+  // block diagonals d = 1, 2, 3 from
+  //   X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ   (I - J = d),
+  // every product staged in LDS and shared by all four waves.
+  for (int e = t; e < NB * NB; e += 256) Xl[e / NB][e % NB] = 0.0;
+  __syncthreads();
+  if (lane < PW) {
+    const int b0 = wave * PW, cc = lane;
+    double x[PW];
 #pragma unroll
-  for (int m = 0; m < NB / 4; ++m) xs[m] = 0.0;
-#pragma clang loop unroll(full)
-  for (int r = 0; r < NB; ++r) {
-    __builtin_amdgcn_sched_barrier(0);  // keeps each row's LDS reads near their use
-    double s = 0.0;
+    for (int r = 0; r < PW; ++r) {
+      double s0 = r == cc ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
-    for (int m = 0; 4 * m < r; ++m)
-      if (4 * m + p < r) s = fma(-Ls[r][4 * m + p], xs[m], s);
-    s += __shfl_xor(s, 1);
-    s += __shfl_xor(s, 2);
-    const double x = ((r == c ? 1.0 : 0.0) + s) * rdiag[r];
-    if (p == r % 4) {
-      xs[r / 4] = x;
-      Xl[r][c] = x;
+      for (int q = 0; q + 1 < r; q += 2) {
+        s0 = fma(-Ls[b0 + r][b0 + q], x[q], s0);
+        s1 = fma(-Ls[b0 + r][b0 + q + 1], x[q + 1], s1);
+      }
+      if (r & 1) s0 = fma(-Ls[b0 + r][b0 + r - 1], x[r - 1], s0);
+      x[r] = (s0 + s1) * rdiag[b0 + r];
+      Xl[b0 + r][b0 + cc] = x[r];
     }
   }
   __syncthreads();
+#pragma unroll
+  for (int dd = 1; dd < NB / PW; ++dd) {
+    const int nblk = NB / PW - dd;
+    // T_IJ = sum_{K=J}^{I-1} L_IK X_KJ for the blocks of this diagonal
+    for (int e = t; e < nblk * PW * PW; e += 256) {
+      const int J = e / (PW * PW), r = (e / PW) % PW, cc = e % PW, I = J + dd;
+      double s0 = 0.0, s1 = 0.0;
+      for (int q = J * PW; q < I * PW; q += 2) {
+        s0 = fma(Ls[I * PW + r][q], Xl[q][J * PW + cc], s0);
+        s1 = fma(Ls[I * PW + r][q + 1], Xl[q + 1][J * PW + cc], s1);
+      }
+      Tb[J][r][cc] = s0 + s1;
+    }
+    __syncthreads();
+    // X_IJ = -X_II T_IJ
+    for (int e = t; e < nblk * PW * PW; e += 256) {
+      const int J = e / (PW * PW), r = (e / PW) % PW, cc = e % PW, I = J + dd;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < PW; q += 2) {
+        s0 = fma(Xl[I * PW + r][I * PW + q], Tb[J][q][cc], s0);
+        s1 = fma(Xl[I * PW + r][I * PW + q + 1], Tb[J][q + 1][cc], s1);
+      }
+      Xl[I * PW + r][J * PW + cc] = -(s0 + s1);
+    }
+    __syncthreads();
+  }
+  double* Dk = P.Dinv + (int64_t)k * NB * NB;
 #pragma unroll
   for (int q = 0; q < NB / 4; ++q) {
     const int r = wave + 4 * q;
