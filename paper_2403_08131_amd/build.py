@@ -31,14 +31,28 @@ FLAGS = [
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    # kernel resource remarks: every kernel must run without private (scratch)
+    # memory, so a register spill shows up at build time, not as a slow run
+    cmd = [HIPCC, *FLAGS, "-Rpass-analysis=kernel-resource-usage", "-fno-caret-diagnostics", "-c", src,
+           "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
+    lines = [l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l]
+    spills, kernel = [], None
+    for l in lines:
+        if "Function Name:" in l:
+            kernel = l.split("Function Name:")[1].split("[")[0].strip()
+        elif "ScratchSize [bytes/lane]:" in l:
+            size = int(l.split("ScratchSize [bytes/lane]:")[1].split("[")[0])
+            if size:
+                spills.append((kernel, size))
     # the host pass does not know the device-only feature flag; drop that line
-    err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
+    err = "\n".join(l for l in lines if "remark:" not in l)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{err}")
     if err.strip():
         sys.stderr.write(err + "\n")
+    if spills:
+        raise RuntimeError(f"{src}: kernels use scratch memory (register spills): {spills}")
     return obj
 
 

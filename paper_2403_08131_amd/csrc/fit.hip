@@ -396,7 +396,9 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ 
     for (int e = t; e < nblk * PW * PW; e += 256) {
       const int J = e / (PW * PW), r = (e / PW) % PW, cc = e % PW, I = J + dd;
       double s0 = 0.0, s1 = 0.0;
-      for (int q = J * PW; q < I * PW; q += 2) {
+#pragma unroll
+      for (int qq = 0; qq < dd * PW; qq += 2) {
+        const int q = J * PW + qq;
         s0 = fma(Ls[I * PW + r][q], Xl[q][J * PW + cc], s0);
         s1 = fma(Ls[I * PW + r][q + 1], Xl[q + 1][J * PW + cc], s1);
       }
