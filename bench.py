@@ -309,7 +309,7 @@ def main():
     ctx = G.Context(0)
     ctx.set_score_path(args.path)
     path = args.path
-    if path == "auto":
+    if path == "auto":  # the library's own choice for these workloads
         path = "large" if prec == "fp32" and p.n > LARGE_N_MIN else "fused"
 
     def step():
@@ -377,7 +377,7 @@ def main():
         "error_vs_fp64": err,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "k_score_fused" if path == "fused" else "k_trigemm",
+                     "kernel": {"fused": "k_score_fused", "large": "k_trigemm"}[path],
                      "path": path, "flops_per_step": fl,
                      "flops_per_launch": fl * args.steps / max(launches, 1),
                      "avg_launch_ms": k_avg},

@@ -139,12 +139,14 @@ gpbo_status gpbo_ctx_enable_timing(gpbo_ctx ctx, int32_t enable);
 gpbo_status gpbo_ctx_timing(gpbo_ctx ctx, int64_t* launches, double* total_ms);
 /* Scoring path of gpbo_score (both compute the same quantities):
  *   GPBO_PATH_AUTO  : fused for small n, chunked for large n (float32);
- *   GPBO_PATH_FUSED : one kernel per candidate tile, cross-covariance in LDS;
+ *   GPBO_PATH_FUSED : one workgroup per candidate tile, cross-covariance in
+ *                     LDS, then the matrix-core product;
  *   GPBO_PATH_LARGE : float32 only; per candidate chunk the cross-covariance
  *                     is written to a workspace and contracted with the
  *                     packed inverse factor by a triangular matrix-core
  *                     product (the timed kernel is that product).
- * Returns GPBO_E_INVALID_ARG for an unknown path. */
+ * Returns GPBO_E_INVALID_ARG for an unknown path; gpbo_score returns
+ * GPBO_E_UNSUPPORTED when the forced path cannot take the problem. */
 typedef enum gpbo_score_path {
   GPBO_PATH_AUTO = 0,
   GPBO_PATH_FUSED = 1,

@@ -473,19 +473,18 @@ gpbo_status gpbo_score(gpbo_ctx c, gpbo_model M, int64_t m, const void* Xc, gpbo
     HIP_TRY(c, hipGetLastError());
     return GPBO_OK;
   }
-  const int tm = score_tile_m(prec, M->n, M->d);
   // Path: the chunked path for float32 once n is large (the fused kernel's
   // LDS tile then holds too few candidates to amortise the inverse factor).
-  bool large = prec == GPBO_FP32 && (tm == 0 || M->n > LARGE_N_MIN);
-  if (c->score_path == GPBO_PATH_FUSED) large = false;
-  if (c->score_path == GPBO_PATH_LARGE) {
-    if (prec != GPBO_FP32)
-      return fail(c, GPBO_E_UNSUPPORTED, "the large-n scoring path is float32 only");
-    large = true;
-  }
-  if (!large && tm == 0)
+  const int tm = score_tile_m(prec, M->n, M->d);
+  int path = c->score_path;
+  if (path == GPBO_PATH_AUTO)
+    path = prec == GPBO_FP32 && (tm == 0 || M->n > LARGE_N_MIN) ? GPBO_PATH_LARGE : GPBO_PATH_FUSED;
+  if (path == GPBO_PATH_LARGE && prec != GPBO_FP32)
+    return fail(c, GPBO_E_UNSUPPORTED, "the large-n scoring path is float32 only");
+  if (path == GPBO_PATH_FUSED && tm == 0)
     return fail(c, GPBO_E_UNSUPPORTED, "n=%d is too large for the fused scoring kernel at this precision",
                 M->n);
+  const bool large = path == GPBO_PATH_LARGE;
   ensure_score_operands(M, prec, s);
   const int npj = M->pk_npj[prec];
   const int64_t tiles = large ? large_partials(npj, m) : ceil_div(m, tm);

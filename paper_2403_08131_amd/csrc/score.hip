@@ -93,62 +93,56 @@ __global__ void k_scale_alpha(const double* __restrict__ a, int n, double sf2, T
 constexpr int FW = 8;        // waves per scoring workgroup
 constexpr int FT = FW * 64;  // threads per scoring workgroup
 
-// Score candidate tile `tile` of problem A (TM candidates from tile * TM).
-template <int P, int KERN, int TM>
-__device__ __forceinline__ void score_tile(const ScoreArgs& A, int64_t tile,
-                                           unsigned char* smem) {
+// The three phases of scoring one tile of TM candidates, written for a group
+// of NW waves (w: the wave's index in the group, 0 .. NW-1).
+
+// Scaled candidate tile, dimension-major: xcT[k][c] = Xc[c0 + c][k] sc[k].
+template <int P, int TM, int NW>
+__device__ __forceinline__ void stage_candidates(const ScoreArgs& A, int64_t tile,
+                                                 typename PT<P>::C* xcT, int tid) {
   using C = typename PT<P>::C;
-  using K = typename PT<P>::K;
-  using Acc = typename PT<P>::Acc;
   using In = typename PT<P>::In;
-  using V4 = typename PT<P>::V4;
-  constexpr int KB = PT<P>::KB;
-  constexpr int NCT = TM / 16;  // candidate tiles of 16 per workgroup
-  // candidates per register group in phase 1 (float64 halves it to avoid spills)
-  constexpr int CG = TM < (P == GPBO_FP64 ? 16 : 32) ? TM : (P == GPBO_FP64 ? 16 : 32);
-
-  const int n = A.n, d = A.d, npk = A.npk, npj = A.npj, ldk = A.ldk;
-  const int64_t m = A.m;
-  const int64_t* __restrict__ pk_off = A.pk_off;
-  const K* __restrict__ pk = (const K*)A.pk;
-  const Acc* __restrict__ alpha = (const Acc*)A.alpha;
-  const C* __restrict__ XsT = (const C*)A.Xs;
-  const C* __restrict__ sc = (const C*)A.sc;
+  const int d = A.d;
+  const int64_t c0 = tile * TM, m = A.m;
   const In* __restrict__ Xc = (const In*)A.Xc;
-
-  K* kt = (K*)smem;                                            // [TM][ldk]
-  C* xcT = (C*)(smem + (size_t)TM * ldk * sizeof(K));          // [d][TM]
-  Acc* mu_part = (Acc*)(xcT + round_up((int64_t)d * TM, 4));   // [FW][TM]
-  Acc* ssq_part = mu_part + FW * TM;                           // [FW][TM]
-
-  const int t = threadIdx.x;
-  const int lane = t % 64;
-  const int wave = wave_id();
-  const int64_t c0 = tile * TM;
-
-  // ---- scaled candidate tile, dimension-major ------------------------------
-  for (int e = t; e < TM * d; e += FT) {
+  const C* __restrict__ sc = (const C*)A.sc;
+  for (int e = tid; e < TM * d; e += NW * 64) {
     const int c = e / d, k = e % d;
     xcT[k * TM + c] = c0 + c < m ? (C)Xc[(c0 + c) * d + k] * sc[k] : C(0);
   }
-  __syncthreads();
+}
 
-  // ---- phase 1: cross-covariance tile + mean partials ----------------------
+// Phase 1: cross-covariance tile kt[c][j] and the mean partials
+// mu_part[w][c] of this wave's training points.
+// DMAX > 0: points of up to DMAX dimensions keep all coordinates in
+// registers; larger d (and DMAX = 0) stream them DC at a time.
+template <int P, int KERN, int TM, int NW, int DMAX>
+__device__ __forceinline__ void phase_cross(const ScoreArgs& A, typename PT<P>::K* kt,
+                                            const typename PT<P>::C* xcT,
+                                            typename PT<P>::Acc* mu_part, int w) {
+  using C = typename PT<P>::C;
+  using K = typename PT<P>::K;
+  using Acc = typename PT<P>::Acc;
+  using V4 = typename PT<P>::V4;
+  // candidates per register group (float64 halves it to avoid spills)
+  constexpr int CG = TM < (P == GPBO_FP64 ? 16 : 32) ? TM : (P == GPBO_FP64 ? 16 : 32);
+  const int n = A.n, d = A.d, npj = A.npj, ldk = A.ldk;
+  const Acc* __restrict__ alpha = (const Acc*)A.alpha;
+  const C* __restrict__ XsT = (const C*)A.Xs;
+  const int lane = threadIdx.x % 64;
   for (int cg = 0; cg < TM; cg += CG) {
     Acc macc[CG];
 #pragma unroll
     for (int c = 0; c < CG; ++c) macc[c] = 0;
-    for (int jb = wave * 64; jb < npj; jb += FT) {
+    for (int jb = w * 64; jb < npj; jb += NW * 64) {
       const int j = jb + lane;
       const bool valid = j < n;
       const C* xcol = XsT + (valid ? j : 0);
       C r2[CG];
 #pragma unroll
       for (int c = 0; c < CG; ++c) r2[c] = 0;
-      C xnext = xcol[0];
-      for (int k = 0; k < d; ++k) {
-        const C xk = xnext;
-        if (k + 1 < d) xnext = xcol[(int64_t)(k + 1) * n];
+      // squared distances to this lane's point, one input dimension at a time
+      auto dim = [&](C xk, int k) {
         const C* xr = xcT + k * TM + cg;
 #pragma unroll
         for (int c = 0; c < CG; c += 4) {
@@ -159,6 +153,35 @@ __device__ __forceinline__ void score_tile(const ScoreArgs& A, int64_t tile,
           r2[c + 2] = fma(u2, u2, r2[c + 2]);
           r2[c + 3] = fma(u3, u3, r2[c + 3]);
         }
+      };
+      if (DMAX > 0 && d <= DMAX) {
+        // all of the point's coordinates requested at once: one memory
+        // latency per point
+        C xp[DMAX > 0 ? DMAX : 1];
+#pragma unroll
+        for (int k = 0; k < DMAX; ++k)
+          if (k < d) xp[k] = xcol[(int64_t)k * n];
+#pragma unroll
+        for (int k = 0; k < DMAX; ++k)
+          if (k < d) dim(xp[k], k);
+      } else {
+        // DC coordinates at a time, the next DC requested before the
+        // current ones are used (indices past d are clamped to a valid
+        // address and never used)
+        constexpr int DC = 8;
+        C xa[DC];
+#pragma unroll
+        for (int u = 0; u < DC; ++u) xa[u] = xcol[(int64_t)min(u, d - 1) * n];
+        for (int k0 = 0; k0 < d; k0 += DC) {
+          C xb[DC];
+#pragma unroll
+          for (int u = 0; u < DC; ++u) xb[u] = xcol[(int64_t)min(k0 + DC + u, d - 1) * n];
+#pragma unroll
+          for (int u = 0; u < DC; ++u)
+            if (k0 + u < d) dim(xa[u], k0 + u);
+#pragma unroll
+          for (int u = 0; u < DC; ++u) xa[u] = xb[u];
+        }
       }
       const Acc aj = valid ? alpha[j] : Acc(0);
 #pragma unroll
@@ -168,51 +191,88 @@ __device__ __forceinline__ void score_tile(const ScoreArgs& A, int64_t tile,
         if (j < npj) kt[(cg + c) * ldk + j] = to_k<K, C>(kv);
       }
     }
-    lane_transpose_sum<Acc, CG>(macc, mu_part + wave * TM + cg);
+    lane_transpose_sum<Acc, CG>(macc, mu_part + w * TM + cg);
   }
-  __syncthreads();
+}
 
-  // ---- phase 2: v = (sf2 Linv) khat on the matrix cores ----------------------
+// Phase 2: v = (sf2 Linv) khat on the matrix cores; ssq_part[w][c] receives
+// this wave's sum of squares of v over its row tiles.  A wave takes RT
+// consecutive row tiles per pass so that every B operand read from the LDS
+// tile feeds RT products (with RT = 1 the LDS read rate, not the matrix
+// cores, bounds the phase); RT = 1 keeps the register count low.
+template <int P, int TM, int NW, int RT>
+__device__ __forceinline__ void phase_variance(const ScoreArgs& A, const typename PT<P>::K* kt,
+                                               typename PT<P>::Acc* ssq_part, int w) {
+  using K = typename PT<P>::K;
+  using Acc = typename PT<P>::Acc;
+  constexpr int KB = PT<P>::KB;
+  constexpr int NCT = TM / 16;  // candidate tiles of 16 per workgroup
+  constexpr int PF = Blk<P>::PF;
+  using V = typename Blk<P>::V;
+  const int npk = A.npk, ldk = A.ldk;
+  const int64_t* __restrict__ pk_off = A.pk_off;
+  const K* __restrict__ pk = (const K*)A.pk;
+  const int lane = threadIdx.x % 64;
+  const K* bbase = kt + (lane % 16) * ldk + (KB / 4) * (lane / 16);
   Acc ssq[NCT];
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct) ssq[ct] = 0;
   const int ntiles = npk / TI;
-  // balanced assignment: row tile t goes to wave s or 2FW-1-s, s = t mod 2FW
-  for (int ti = 0; ti < ntiles; ++ti) {
-    const int r = ti % (2 * FW);
-    if ((r < FW ? r : 2 * FW - 1 - r) != wave) continue;
-    const int64_t o0 = pk_off[ti];
-    const int nblk = (int)(pk_off[ti + 1] - o0);  // a multiple of PF
-    const K* ablk = pk + o0 * Blk<P>::EPB + lane * (KB / 4);
-    const K* bbase = kt + (lane % 16) * ldk + (KB / 4) * (lane / 16);
-    typename Blk<P>::Acc acc[NCT];
+  const int ngroups = (ntiles + RT - 1) / RT;
+  // balanced assignment: group g goes to wave s or 2NW-1-s, s = g mod 2NW
+  for (int g = 0; g < ngroups; ++g) {
+    const int r = g % (2 * NW);
+    if ((r < NW ? r : 2 * NW - 1 - r) != w) continue;
+    // row tiles RT g .. RT g + RT - 1; the last one may be missing; the
+    // block counts grow with the tile index, so the last valid tile's
+    // count bounds the loop and an earlier tile's part ends at a group
+    // boundary (counts are multiples of PF)
+    int nb[RT];
+    const K* ablk[RT];
+    bool has[RT];
+    int nblk = 0;
 #pragma unroll
-    for (int ct = 0; ct < NCT; ++ct) acc[ct] = typename Blk<P>::Acc{0, 0, 0, 0};
-    // The packed blocks stream from L2 one group ahead (the group after a
-    // tile's last one reads the next tile or the zero slack, never used).
-    constexpr int PF = Blk<P>::PF;
-    using V = typename Blk<P>::V;
-    // one pipeline group: B operands from LDS, then PF x NCT block products
-    auto group = [&](const V (&a)[PF], int tj0) {
-      V bv[PF][NCT];
+    for (int q = 0; q < RT; ++q) {
+      const int t = RT * g + q;
+      has[q] = t < ntiles;
+      const int tt = has[q] ? t : RT * g;
+      const int64_t o = pk_off[tt];
+      nb[q] = has[q] ? (int)(pk_off[tt + 1] - o) : 0;
+      ablk[q] = pk + o * Blk<P>::EPB + lane * (KB / 4);
+      nblk = nb[q] > nblk ? nb[q] : nblk;
+    }
+    typename Blk<P>::Acc acc[RT][NCT];
 #pragma unroll
-      for (int u = 0; u < PF; ++u)
+    for (int q = 0; q < RT; ++q)
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct)
-          bv[u][ct] = Blk<P>::load(bbase + ct * 16 * ldk + (tj0 + u) * KB);
+      for (int ct = 0; ct < NCT; ++ct) acc[q][ct] = typename Blk<P>::Acc{0, 0, 0, 0};
+    // one pipeline group: per block, the B operands from LDS, then the
+    // products of every row tile still inside its blocks
+    auto group = [&](const V (&a)[RT][PF], int tj0) {
 #pragma unroll
-      for (int u = 0; u < PF; ++u)
+      for (int u = 0; u < PF; ++u) {
+        V bv[NCT];
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) Blk<P>::mma(acc[ct], a[u], bv[u][ct]);
+        for (int ct = 0; ct < NCT; ++ct) bv[ct] = Blk<P>::load(bbase + ct * 16 * ldk + (tj0 + u) * KB);
+#pragma unroll
+        for (int kk = 0; kk < Blk<P>::KS; ++kk)
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+            for (int q = 0; q < RT; ++q)
+              if (tj0 < nb[q]) Blk<P>::mma_k(acc[q][ct], a[q][u], bv[ct], kk);
+      }
     };
-    auto fetch = [&](V (&a)[PF], int tj0) {
+    // The packed blocks stream from L2 one group ahead (a group past a
+    // tile's end reads the next tile or the zero slack and is not used).
+    auto fetch = [&](V (&a)[RT][PF], int tj0) {
 #pragma unroll
-      for (int u = 0; u < PF; ++u) a[u] = Blk<P>::load(ablk + (int64_t)(tj0 + u) * Blk<P>::EPB);
+      for (int q = 0; q < RT; ++q)
+#pragma unroll
+        for (int u = 0; u < PF; ++u) a[q][u] = Blk<P>::load(ablk[q] + (int64_t)(tj0 + u) * Blk<P>::EPB);
       __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the products
     };
-    // ping-pong buffers: the next group's A blocks are requested before the
-    // current group's products are issued
-    V ra[PF], rb[PF];
+    V ra[RT][PF], rb[RT][PF];
     fetch(ra, 0);
     for (int tj0 = 0; tj0 < nblk; tj0 += 2 * PF) {
       fetch(rb, tj0 + PF);
@@ -222,9 +282,11 @@ __device__ __forceinline__ void score_tile(const ScoreArgs& A, int64_t tile,
       group(rb, tj0 + PF);
     }
 #pragma unroll
-    for (int ct = 0; ct < NCT; ++ct)
-      ssq[ct] += acc[ct][0] * acc[ct][0] + acc[ct][1] * acc[ct][1] + acc[ct][2] * acc[ct][2] +
-                 acc[ct][3] * acc[ct][3];
+    for (int q = 0; q < RT; ++q)
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct)
+        ssq[ct] += acc[q][ct][0] * acc[q][ct][0] + acc[q][ct][1] * acc[q][ct][1] +
+                   acc[q][ct][2] * acc[q][ct][2] + acc[q][ct][3] * acc[q][ct][3];
   }
   // lanes l, l+16, l+32, l+48 hold rows of the same candidate column l % 16
 #pragma unroll
@@ -232,39 +294,69 @@ __device__ __forceinline__ void score_tile(const ScoreArgs& A, int64_t tile,
     Acc v = ssq[ct];
     v += __shfl_xor(v, 16);
     v += __shfl_xor(v, 32);
-    if (lane < 16) ssq_part[wave * TM + ct * 16 + lane] = v;
+    if (lane < 16) ssq_part[w * TM + ct * 16 + lane] = v;
   }
-  __syncthreads();
+}
 
-  // ---- phase 3: outputs and the tile's argmax ------------------------------
-  if (t < 64) {
-    double bv = -INFINITY;
-    int64_t bi = -1;
-    for (int c = t; c < TM; c += 64) {
-      const int64_t gc = c0 + c;
-      if (gc >= m) continue;
-      Acc muz = 0, vv = 0;
+// Phase 3 (one wave): outputs and the tile's argmax from the partials of
+// NW waves.
+template <int P, int TM, int NW>
+__device__ __forceinline__ void phase_finish(const ScoreArgs& A, int64_t tile,
+                                             const typename PT<P>::Acc* mu_part,
+                                             const typename PT<P>::Acc* ssq_part) {
+  using Acc = typename PT<P>::Acc;
+  using In = typename PT<P>::In;
+  const int lane = threadIdx.x % 64;
+  const int64_t c0 = tile * TM, m = A.m;
+  double bv = -INFINITY;
+  int64_t bi = -1;
+  for (int c = lane; c < TM; c += 64) {
+    const int64_t gc = c0 + c;
+    if (gc >= m) continue;
+    Acc muz = 0, vv = 0;
 #pragma unroll
-      for (int w = 0; w < FW; ++w) {
-        muz += mu_part[w * TM + c];
-        vv += ssq_part[w * TM + c];
-      }
-      finish_candidate<Acc, In>(gc, muz, vv, A.sf2, A.stats, (In*)A.mu, (In*)A.sigma, (In*)A.ei,
-                                bv, bi);
+    for (int w = 0; w < NW; ++w) {
+      muz += mu_part[w * TM + c];
+      vv += ssq_part[w * TM + c];
     }
-    wave_argmax(bv, bi);
-    if (t == 0 && A.part_v) {
-      A.part_v[tile] = bv;
-      A.part_i[tile] = bi;
-    }
+    finish_candidate<Acc, In>(gc, muz, vv, A.sf2, A.stats, (In*)A.mu, (In*)A.sigma, (In*)A.ei, bv,
+                              bi);
   }
+  wave_argmax(bv, bi);
+  if (lane == 0 && A.part_v) {
+    A.part_v[tile] = bv;
+    A.part_i[tile] = bi;
+  }
+}
+
+// Score candidate tile `tile` of problem A (TM candidates from tile * TM)
+// with all FW waves of the workgroup in every phase.
+template <int P, int KERN, int TM, int RT>
+__device__ __forceinline__ void score_tile(const ScoreArgs& A, int64_t tile,
+                                           unsigned char* smem) {
+  using C = typename PT<P>::C;
+  using K = typename PT<P>::K;
+  using Acc = typename PT<P>::Acc;
+  const int d = A.d, ldk = A.ldk;
+  K* kt = (K*)smem;                                            // [TM][ldk]
+  C* xcT = (C*)(smem + (size_t)TM * ldk * sizeof(K));          // [d][TM]
+  Acc* mu_part = (Acc*)(xcT + round_up((int64_t)d * TM, 4));   // [FW][TM]
+  Acc* ssq_part = mu_part + FW * TM;                           // [FW][TM]
+  const int wave = wave_id();
+  stage_candidates<P, TM, FW>(A, tile, xcT, threadIdx.x);
+  __syncthreads();
+  phase_cross<P, KERN, TM, FW, 0>(A, kt, xcT, mu_part, wave);
+  __syncthreads();
+  phase_variance<P, TM, FW, RT>(A, kt, ssq_part, wave);
+  __syncthreads();
+  if (wave == 0) phase_finish<P, TM, FW>(A, tile, mu_part, ssq_part);
 }
 
 template <int P, int KERN, int TM>
 __global__ void __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(1, 4)))
 k_score_fused(ScoreArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
-  score_tile<P, KERN, TM>(A, blockIdx.x, smem);
+  score_tile<P, KERN, TM, 2>(A, blockIdx.x, smem);
 }
 
 // Persistent batched scoring: items 0 .. total-1 enumerate (problem, tile)
@@ -290,9 +382,9 @@ k_score_batched(const ScoreArgs* __restrict__ descs, int B, int64_t total,
     }
     const ScoreArgs& A = descs[lo];
     if (A.kernel == GPBO_KERNEL_SE)
-      score_tile<P, GPBO_KERNEL_SE, TM>(A, item - A.tile_begin, smem);
+      score_tile<P, GPBO_KERNEL_SE, TM, 1>(A, item - A.tile_begin, smem);
     else
-      score_tile<P, GPBO_KERNEL_MATERN52, TM>(A, item - A.tile_begin, smem);
+      score_tile<P, GPBO_KERNEL_MATERN52, TM, 1>(A, item - A.tile_begin, smem);
     __syncthreads();  // the LDS tile is reused by the next item
   }
 }

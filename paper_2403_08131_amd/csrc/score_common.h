@@ -145,12 +145,15 @@ struct Blk<GPBO_FP32> {
   using Acc = f4;
   static constexpr int EPB = 64 * 4;
   static constexpr int PF = 4;  // blocks per pipeline group (row tiles are padded to a multiple)
+  static constexpr int KS = 4;  // matrix-core steps per block
   __device__ static __forceinline__ V load(const float* p) { return *(const f4*)p; }
+  // step kk of the block product (callers interleave independent accumulators)
+  __device__ static __forceinline__ void mma_k(Acc& c, const V& a, const V& b, int kk) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], b[kk], c, 0, 0, 0);
+  }
   __device__ static __forceinline__ void mma(Acc& c, const V& a, const V& b) {
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], c, 0, 0, 0);
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) mma_k(c, a, b, kk);
   }
 };
 template <>
@@ -159,11 +162,13 @@ struct Blk<GPBO_BF16> {
   using Acc = f4;
   static constexpr int EPB = 64 * 8;
   static constexpr int PF = 2;
+  static constexpr int KS = 1;
   __device__ static __forceinline__ V load(const unsigned short* p) { return *(const us8*)p; }
-  __device__ static __forceinline__ void mma(Acc& c, const V& a, const V& b) {
+  __device__ static __forceinline__ void mma_k(Acc& c, const V& a, const V& b, int) {
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
                                                 __builtin_bit_cast(bf8, b), c, 0, 0, 0);
   }
+  __device__ static __forceinline__ void mma(Acc& c, const V& a, const V& b) { mma_k(c, a, b, 0); }
 };
 struct dq {
   double2 lo, hi;
@@ -174,14 +179,18 @@ struct Blk<GPBO_FP64> {
   using Acc = d4;
   static constexpr int EPB = 64 * 4;
   static constexpr int PF = 2;
+  static constexpr int KS = 4;
   __device__ static __forceinline__ V load(const double* p) {
     return dq{*(const double2*)p, *(const double2*)(p + 2)};
   }
+  __device__ static __forceinline__ void mma_k(Acc& c, const V& a, const V& b, int kk) {
+    const double av = kk == 0 ? a.lo.x : kk == 1 ? a.lo.y : kk == 2 ? a.hi.x : a.hi.y;
+    const double bv = kk == 0 ? b.lo.x : kk == 1 ? b.lo.y : kk == 2 ? b.hi.x : b.hi.y;
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+  }
   __device__ static __forceinline__ void mma(Acc& c, const V& a, const V& b) {
-    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a.lo.x, b.lo.x, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a.lo.y, b.lo.y, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a.hi.x, b.hi.x, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a.hi.y, b.hi.y, c, 0, 0, 0);
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) mma_k(c, a, b, kk);
   }
 };
 

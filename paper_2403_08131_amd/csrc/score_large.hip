@@ -118,11 +118,15 @@ __global__ void __launch_bounds__(256) k_trigemm(const float* __restrict__ khat,
       f4 bv[4];
 #pragma unroll
       for (int ct = 0; ct < 4; ++ct) bv[ct] = *(const f4*)(bp + (int64_t)ct * 16 * ldk + tj * 16);
+      // step-major: consecutive matrix-core instructions update different
+      // accumulators
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        Blk<GPBO_FP32>::mma(acc[0][ct], a0, bv[ct]);
-        Blk<GPBO_FP32>::mma(acc[1][ct], a1, bv[ct]);
-      }
+      for (int kk = 0; kk < Blk<GPBO_FP32>::KS; ++kk)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+          Blk<GPBO_FP32>::mma_k(acc[0][ct], a0, bv[ct], kk);
+          Blk<GPBO_FP32>::mma_k(acc[1][ct], a1, bv[ct], kk);
+        }
     }
   }
   // per candidate column: sum of squares over this wave's 32 rows

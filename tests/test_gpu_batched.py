@@ -93,8 +93,10 @@ def test_score_batched_matches_single_and_oracle(ctx, prec):
         single = G.score(ctx, mo, Xcs[b], prec)
         e1 = single["ei"].double().cpu().numpy()
         eb = eis[b].double().cpu().numpy()
-        top = max(np.max(e1), 1e-30)
-        assert np.max(np.abs(eb - e1)) <= 1e-5 * top, (b, p.n, p.d)
+        # the single-problem path may split its partial sums differently:
+        # EI moves by at most |dmu| + |dsigma|
+        scale = float(single["mu"].abs().max()) + float(single["sigma"].abs().max())
+        assert np.max(np.abs(eb - e1)) <= 1e-5 * scale, (b, p.n, p.d)
         f = O.fit(p.X, p.y, p.lengthscale, O.SE, p.signal_var, p.noise_var)
         ref = O.score(f, p.Xc, want=("ei",))["ei"]
         bound = 1e-4 if prec == "fp32" else 5e-2

@@ -1,6 +1,6 @@
 """GPU parity of the large-n float32 scoring path (cross-covariance chunks in
 HBM, triangular matrix-core product with a sum-of-squares epilogue) against
-the float64 oracle, through the C ABI.
+the float64 oracle and the fused path, through the C ABI.
 
 Bars as for the fused float32 path: |dmu| / max(|mu|, s_y sf) <= 1e-4,
 |dsigma| / sigma <= 1e-4 where sigma^2 >= 1e-2 s_y^2 sf2, argmax identical
