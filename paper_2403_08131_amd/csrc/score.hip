@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <type_traits>
 
 #include "score_common.h"
 
@@ -223,23 +224,31 @@ __device__ __forceinline__ void phase_variance(const ScoreArgs& A, const typenam
   for (int g = 0; g < ngroups; ++g) {
     const int r = g % (2 * NW);
     if ((r < NW ? r : 2 * NW - 1 - r) != w) continue;
-    // row tiles RT g .. RT g + RT - 1; the last one may be missing; the
-    // block counts grow with the tile index, so the last valid tile's
-    // count bounds the loop and an earlier tile's part ends at a group
-    // boundary (counts are multiples of PF)
-    int nb[RT];
+    // row tiles RT g .. RT g + RT - 1.  Block counts grow with the tile
+    // index, so the last tile's count bounds the loop and every earlier
+    // tile ends at a group boundary (counts are multiples of PF): a group
+    // below the first tile's count multiplies every tile, one past it only
+    // the last.  With RT = 2 and the second tile missing, the first tile
+    // takes the last slot and the first slot stays empty.
+    static_assert(RT == 1 || RT == 2, "one or two row tiles per group");
     const K* ablk[RT];
-    bool has[RT];
-    int nblk = 0;
-#pragma unroll
-    for (int q = 0; q < RT; ++q) {
-      const int t = RT * g + q;
-      has[q] = t < ntiles;
-      const int tt = has[q] ? t : RT * g;
-      const int64_t o = pk_off[tt];
-      nb[q] = has[q] ? (int)(pk_off[tt + 1] - o) : 0;
-      ablk[q] = pk + o * Blk<P>::EPB + lane * (KB / 4);
-      nblk = nb[q] > nblk ? nb[q] : nblk;
+    int nfirst, nlast;
+    {
+      const int t0 = RT * g;
+      const int64_t o0 = pk_off[t0], o1 = pk_off[t0 + 1];
+      if (RT == 1) {
+        ablk[0] = pk + o0 * Blk<P>::EPB + lane * (KB / 4);
+        nfirst = nlast = (int)(o1 - o0);
+      } else if (t0 + 1 < ntiles) {
+        ablk[0] = pk + o0 * Blk<P>::EPB + lane * (KB / 4);
+        ablk[RT - 1] = pk + o1 * Blk<P>::EPB + lane * (KB / 4);
+        nfirst = (int)(o1 - o0);
+        nlast = (int)(pk_off[t0 + 2] - o1);
+      } else {
+        ablk[0] = ablk[RT - 1] = pk + o0 * Blk<P>::EPB + lane * (KB / 4);
+        nfirst = 0;
+        nlast = (int)(o1 - o0);
+      }
     }
     typename Blk<P>::Acc acc[RT][NCT];
 #pragma unroll
@@ -247,8 +256,9 @@ __device__ __forceinline__ void phase_variance(const ScoreArgs& A, const typenam
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) acc[q][ct] = typename Blk<P>::Acc{0, 0, 0, 0};
     // one pipeline group: per block, the B operands from LDS, then the
-    // products of every row tile still inside its blocks
-    auto group = [&](const V (&a)[RT][PF], int tj0) {
+    // products of tiles Q0 .. RT - 1
+    auto group = [&](const V (&a)[RT][PF], int tj0, auto q0) {
+      constexpr int Q0 = decltype(q0)::value;
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         V bv[NCT];
@@ -259,27 +269,35 @@ __device__ __forceinline__ void phase_variance(const ScoreArgs& A, const typenam
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
-            for (int q = 0; q < RT; ++q)
-              if (tj0 < nb[q]) Blk<P>::mma_k(acc[q][ct], a[q][u], bv[ct], kk);
+            for (int q = Q0; q < RT; ++q) Blk<P>::mma_k(acc[q][ct], a[q][u], bv[ct], kk);
       }
     };
-    // The packed blocks stream from L2 one group ahead (a group past a
-    // tile's end reads the next tile or the zero slack and is not used).
-    auto fetch = [&](V (&a)[RT][PF], int tj0) {
+    // The packed blocks stream from L2 one group ahead (a group past the
+    // last tile's end reads the next tile or the zero slack and is not used).
+    auto fetch = [&](V (&a)[RT][PF], int tj0, auto q0) {
+      constexpr int Q0 = decltype(q0)::value;
 #pragma unroll
-      for (int q = 0; q < RT; ++q)
+      for (int q = Q0; q < RT; ++q)
 #pragma unroll
         for (int u = 0; u < PF; ++u) a[q][u] = Blk<P>::load(ablk[q] + (int64_t)(tj0 + u) * Blk<P>::EPB);
       __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the products
     };
+    using All = std::integral_constant<int, 0>;
+    using Last = std::integral_constant<int, RT - 1>;
+    auto fetch_at = [&](V (&a)[RT][PF], int tj0) {
+      if (tj0 < nfirst) fetch(a, tj0, All{}); else fetch(a, tj0, Last{});
+    };
+    auto group_at = [&](const V (&a)[RT][PF], int tj0) {
+      if (tj0 < nfirst) group(a, tj0, All{}); else group(a, tj0, Last{});
+    };
     V ra[RT][PF], rb[RT][PF];
-    fetch(ra, 0);
-    for (int tj0 = 0; tj0 < nblk; tj0 += 2 * PF) {
-      fetch(rb, tj0 + PF);
-      group(ra, tj0);
-      if (tj0 + PF >= nblk) break;
-      fetch(ra, tj0 + 2 * PF);
-      group(rb, tj0 + PF);
+    fetch_at(ra, 0);
+    for (int tj0 = 0; tj0 < nlast; tj0 += 2 * PF) {
+      fetch_at(rb, tj0 + PF);
+      group_at(ra, tj0);
+      if (tj0 + PF >= nlast) break;
+      fetch_at(ra, tj0 + 2 * PF);
+      group_at(rb, tj0 + PF);
     }
 #pragma unroll
     for (int q = 0; q < RT; ++q)
@@ -356,7 +374,9 @@ template <int P, int KERN, int TM>
 __global__ void __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(1, 4)))
 k_score_fused(ScoreArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
-  score_tile<P, KERN, TM, 2>(A, blockIdx.x, smem);
+  // two float64 row tiles over 64 candidates exceed the register file
+  constexpr int RT = (P == GPBO_FP64 && TM == 64) ? 1 : 2;
+  score_tile<P, KERN, TM, RT>(A, blockIdx.x, smem);
 }
 
 // Persistent batched scoring: items 0 .. total-1 enumerate (problem, tile)

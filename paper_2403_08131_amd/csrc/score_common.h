@@ -213,8 +213,13 @@ __device__ __forceinline__ void lane_transpose_sum(A (&v)[N], A* dst) {
 #pragma unroll
     for (int k = 0; k < N / 2; ++k) {
       if (k < half) {
-        const A keep = upper ? v[k + half] : v[k];
-        const A send = upper ? v[k] : v[k + half];
+        // the empty asm keeps the two selects on registers: without it the
+        // compiler folds them into one runtime-indexed read of v[], lowered
+        // as a compare-and-select chain over the whole array
+        A lo = v[k], hi = v[k + half];
+        __asm__("" : "+v"(lo), "+v"(hi));
+        const A keep = upper ? hi : lo;
+        const A send = upper ? lo : hi;
         v[k] = keep + __shfl_xor(send, D);
       }
     }
