@@ -230,28 +230,45 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
+typedef double d4x __attribute__((ext_vector_type(4)));
+
+// 16 x 16 x 4 float64 matrix-core step: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; lane l holds D[l / 16 + 4 r][l % 16] in element r (rows
+// interleaved across the lane groups, unlike the 32-bit 16 x 16 forms).
+__device__ __forceinline__ d4x mma64(double a, double b, d4x c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // Factor the diagonal tile (k, k), write L_kk and its inverse D_k.  The 64
 // column steps of the tile are a dependency chain; the kernel keeps the chain
-// in one wave and gives the parallel parts to all four.
-//   Factorisation, blocked over four 16-column panels: wave 0 factors the
-//   64 x 16 panel (lane i holds row i's panel entries in registers; step j
-//   reads the pivot from lane j, forms 1/sqrt(pivot) from the hardware
-//   estimate and two Newton steps, scales column j, publishes it through LDS
-//   and updates the remaining panel columns); then all waves apply the
-//   panel's rank-16 update to the trailing lower triangle in LDS.
+// in one wave, trims that wave's instructions to the chain itself (a lone
+// wave issues about one instruction per four cycles) and gives the rest to
+// all four waves.
+//   Factorisation A = U diag(d)^-1 U^T, blocked over four 16-column panels:
+//   wave 0 factors the 64 x 16 panel with lane i holding row i's panel
+//   entries in registers.  Step j reads the pivot d_j = U_jj from lane j and,
+//   with 1/d_j from the hardware estimate and two Newton steps, updates the
+//   remaining panel columns by A_iq -= (U_ij / d_j) U_qj; column j + 1 goes
+//   to its own LDS slot as soon as its last update is done, so the LDS round
+//   trip overlaps the rest of the step.  Then all waves apply the panel's
+//   rank-16 update A_il -= sum_q U_iq U_lq / d_q to the trailing lower
+//   triangle on the float64 matrix cores.  At the end L_ij = U_ij / sqrt(d_j)
+//   (L_jj = sqrt(d_j)), one column per lane.
 //   Inverse, blocked over 16 x 16 blocks (see below).
 __global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ Ds, int k) {
   // One LDS block with the small arrays first, so that every address the
   // factorisation's column reads use fits the 16-bit LDS instruction offset.
   constexpr int PW = 16;  // panel width of the blocked factorisation
   struct Lds {
-    double colb[2][NB];  // published column, double-buffered
-    double rdiag[NB];    // 1 / L_jj
+    double colb[PW][NB];  // the panel's unscaled columns, one slot each
+    double piv[NB];       // pivots d_j
+    double pinv[NB];      // 1 / d_j
+    double rdiag[NB];     // 1 / L_jj
     int bad;
     int pad[3];
-    double Ls[NB][LDT];  // the tile, then L_kk
+    double Ls[NB][LDT];  // the tile, then U, then L_kk
     double Xl[NB][LDT];  // the inverse, staged for a coalesced store
-    double Tb[NB / PW][PW][PW];  // block products of the inverse
+    double Tb[NB / PW][PW][PW + 2];  // one block product per wave
   };
   __shared__ __align__(16) Lds S;
   auto& colb = S.colb;
@@ -265,6 +282,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ 
   const int npad = P.npad;
   const int t = threadIdx.x, lane = t % 64;
   const int wave = __builtin_amdgcn_readfirstlane(t / 64);
+  const int mr = lane % 16, mk = lane / 16;  // matrix-core operand row / k index
   {
     // coalesced rows into LDS, all loads in flight before the first store
     const double* Akk = P.L + (int64_t)k * NB * npad + k * NB;
@@ -275,11 +293,10 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ 
     for (int q = 0; q < NB / 4; ++q) Ls[wave + 4 * q][lane] = v[q];
   }
   __syncthreads();
-  // Blocked over four 16-column panels: wave 0 factors the 64 x 16 panel
-  // (lane i = row i, 16 sequential column steps), then all waves apply the
-  // panel's rank-16 update to the trailing lower triangle in LDS.
   int bad = -1;  // first pivot that is not positive and finite (uniform in wave 0)
-#pragma unroll
+  // The panel and inverse loops stay rolled: one copy of the loop body
+  // reaches the instruction cache instead of four straight-line copies.
+#pragma unroll 1
   for (int p0 = 0; p0 < NB; p0 += PW) {
     if (wave == 0) {
       const int i = lane;
@@ -290,60 +307,62 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ 
         r[q] = v.x;
         r[q + 1] = v.y;
       }
+      // a pivot that is not positive and finite is found after the panel;
+      // the arithmetic goes on meanwhile (the tile is then discarded)
+      colb[0][i] = r[0];
 #pragma unroll
-      for (int jj = 0; jj < PW; ++jj) {
-        const int j = p0 + jj;
-        double d = readlane_f64(r[jj], j);
-        if (bad < 0 && !(d > 0.0 && isfinite(d))) bad = j;
-        if (bad >= 0) d = 1.0;  // keep the arithmetic finite; the tile is discarded
-        double y = __builtin_amdgcn_rsq(d);
-        y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
-        y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
-        double sq = d * y;
-        sq = fma(0.5 * y, fma(-sq, sq, d), sq);  // sqrt(d), corrected
-        const double c = i > j ? r[jj] * y : (i == j ? sq : 0.0);
-        r[jj] = c;
-        if (i == 0) rdiag[j] = y;  // 1 / L_jj
-        if (jj + 1 < PW) {
-          double* cb = colb[jj & 1];
-          cb[i] = c;
-          // one wave: a wave-scope fence orders the column's LDS store
-          // before the reads below
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      for (int jj = 0; jj + 1 < PW; ++jj) {
+        const double d = readlane_f64(r[jj], p0 + jj);
+        // one wave: a wave-scope fence orders the column's LDS store before
+        // the reads below
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        double b[PW];
 #pragma unroll
-          for (int q = jj + 1; q < PW; ++q) r[q] = fma(-c, cb[p0 + q], r[q]);
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        }
+        for (int q = jj + 1; q < PW; ++q) b[q] = colb[jj][p0 + q];
+        double inv = __builtin_amdgcn_rcp(d);
+        inv = fma(inv, fma(-d, inv, 1.0), inv);
+        inv = fma(inv, fma(-d, inv, 1.0), inv);
+        const double ti = r[jj] * inv;
+        r[jj + 1] = fma(-ti, b[jj + 1], r[jj + 1]);
+        colb[jj + 1][i] = r[jj + 1];
+#pragma unroll
+        for (int q = jj + 2; q < PW; ++q) r[q] = fma(-ti, b[q], r[q]);
       }
-      // the panel back to LDS; entries above the diagonal are zero
 #pragma unroll
-      for (int q = 0; q < PW; q += 2) {
-        double2 v;
-        v.x = p0 + q <= i ? r[q] : 0.0;
-        v.y = p0 + q + 1 <= i ? r[q + 1] : 0.0;
-        *(double2*)&Ls[i][p0 + q] = v;
+      for (int q = 0; q < PW; q += 2) *(double2*)&Ls[i][p0 + q] = double2{r[q], r[q + 1]};
+      // pivots and their reciprocals, one per diagonal lane
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      const bool diag = i >= p0 && i < p0 + PW;
+      const double dv = colb[diag ? i - p0 : 0][i];
+      double inv = __builtin_amdgcn_rcp(dv);
+      inv = fma(inv, fma(-dv, inv, 1.0), inv);
+      inv = fma(inv, fma(-dv, inv, 1.0), inv);
+      if (diag) {
+        S.piv[i] = dv;
+        S.pinv[i] = inv;
       }
+      const unsigned long long badm = __ballot(diag && !(dv > 0.0 && isfinite(dv)));
+      if (bad < 0 && badm != 0) bad = __builtin_ctzll(badm);  // lane i holds column i
     }
     __syncthreads();
-    // rank-16 update of the trailing lower triangle: A_il -= sum_q L_iq L_lq
-    // for p0 + 16 <= l <= i; each thread takes a 1 x 2 pair of entries
-    const int m = NB - p0 - PW;
-    if (m > 0) {
-      const int half = m / 2;
-      for (int e = t; e < m * half; e += 256) {
-        const int ii = p0 + PW + e / half, l = p0 + PW + 2 * (e % half);
-        if (l > ii) continue;
-        double s0 = 0.0, s1 = 0.0;
+    // rank-16 update of the trailing lower triangle, A_il -= sum_q U_iq U_lq
+    // / d_q, one 16 x 16 block (I, J), I >= J, per wave and pass; the entries
+    // above the diagonal of a diagonal block are updated too and never read
+    const int nt = (NB - p0 - PW) / PW;
+    if (nt > 0) {
+      double w[PW / 4];
 #pragma unroll
-        for (int q = 0; q < PW; q += 2) {
-          const double2 li = *(const double2*)&Ls[ii][p0 + q];
-          const double2 l0 = *(const double2*)&Ls[l][p0 + q];
-          const double2 l1 = *(const double2*)&Ls[l + 1][p0 + q];
-          s0 = fma(li.x, l0.x, fma(li.y, l0.y, s0));
-          s1 = fma(li.x, l1.x, fma(li.y, l1.y, s1));
-        }
-        Ls[ii][l] -= s0;
-        if (l + 1 <= ii) Ls[ii][l + 1] -= s1;
+      for (int sk = 0; sk < PW / 4; ++sk) w[sk] = S.pinv[p0 + 4 * sk + mk];
+      for (int b = wave; b < nt * (nt + 1) / 2; b += 4) {
+        int I = 0, J = b;
+        while (J > I) J -= ++I;
+        const int r0 = p0 + PW * (I + 1), c0 = p0 + PW * (J + 1);
+        d4x acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int sk = 0; sk < PW / 4; ++sk)
+          acc = mma64(Ls[r0 + mr][p0 + 4 * sk + mk] * w[sk], Ls[c0 + mr][p0 + 4 * sk + mk], acc);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Ls[r0 + mk + 4 * e][c0 + mr] -= acc[e];
       }
     }
     __syncthreads();
@@ -355,21 +374,32 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ 
     return;
   }
   {
-    // addresses formed only now (a volatile read keeps the compiler from
+    // L = U diag(d)^-1/2: lane = column j; stored to LDS and to the factor
+    // (addresses formed only now: a volatile read keeps the compiler from
     // holding them in registers across the factorisation)
+    const double d = S.piv[lane];
+    double y = __builtin_amdgcn_rsq(d);
+    y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
+    y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
+    double sq = d * y;
+    sq = fma(0.5 * y, fma(-sq, sq, d), sq);  // sqrt(d), corrected
+    if (wave == 0) rdiag[lane] = y;          // 1 / L_jj
     const int np2 = *(const volatile int*)&P.npad;
     double* Akk = P.L + (int64_t)k * NB * np2 + k * NB;
 #pragma unroll
     for (int q = 0; q < NB / 4; ++q) {
       const int r = wave + 4 * q;
-      Akk[(int64_t)r * np2 + lane] = Ls[r][lane];
+      const double v = r > lane ? Ls[r][lane] * y : (r == lane ? sq : 0.0);
+      Ls[r][lane] = v;
+      Akk[(int64_t)r * np2 + lane] = v;
     }
   }
   // Inverse, blocked over 4 x 4 blocks of 16: the diagonal blocks by
   // forward substitution (wave s inverts block s, lane = column), then the
   // block diagonals d = 1, 2, 3 from
   //   X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ   (I - J = d),
-  // every product staged in LDS and shared by all four waves.
+  // wave J forming block (J + d, J) on the matrix cores, the inner sum
+  // staged through LDS to become the second product's B operand.
   for (int e = t; e < NB * NB; e += 256) Xl[e / NB][e % NB] = 0.0;
   __syncthreads();
   if (lane < PW) {
@@ -389,32 +419,27 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ 
     }
   }
   __syncthreads();
-#pragma unroll
+#pragma unroll 1
   for (int dd = 1; dd < NB / PW; ++dd) {
-    const int nblk = NB / PW - dd;
-    // T_IJ = sum_{K=J}^{I-1} L_IK X_KJ for the blocks of this diagonal
-    for (int e = t; e < nblk * PW * PW; e += 256) {
-      const int J = e / (PW * PW), r = (e / PW) % PW, cc = e % PW, I = J + dd;
-      double s0 = 0.0, s1 = 0.0;
+    if (wave < NB / PW - dd) {
+      const int J = wave, I = J + dd;
+      d4x tacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+      for (int K = 0; K < dd; ++K)
 #pragma unroll
-      for (int qq = 0; qq < dd * PW; qq += 2) {
-        const int q = J * PW + qq;
-        s0 = fma(Ls[I * PW + r][q], Xl[q][J * PW + cc], s0);
-        s1 = fma(Ls[I * PW + r][q + 1], Xl[q + 1][J * PW + cc], s1);
-      }
-      Tb[J][r][cc] = s0 + s1;
-    }
-    __syncthreads();
-    // X_IJ = -X_II T_IJ
-    for (int e = t; e < nblk * PW * PW; e += 256) {
-      const int J = e / (PW * PW), r = (e / PW) % PW, cc = e % PW, I = J + dd;
-      double s0 = 0.0, s1 = 0.0;
+        for (int sk = 0; sk < PW / 4; ++sk) {
+          const int kc = (J + K) * PW + 4 * sk + mk;
+          tacc = mma64(Ls[I * PW + mr][kc], Xl[kc][J * PW + mr], tacc);
+        }
 #pragma unroll
-      for (int q = 0; q < PW; q += 2) {
-        s0 = fma(Xl[I * PW + r][I * PW + q], Tb[J][q][cc], s0);
-        s1 = fma(Xl[I * PW + r][I * PW + q + 1], Tb[J][q + 1][cc], s1);
-      }
-      Xl[I * PW + r][J * PW + cc] = -(s0 + s1);
+      for (int e = 0; e < 4; ++e) Tb[wave][mk + 4 * e][mr] = tacc[e];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      d4x xacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int sk = 0; sk < PW / 4; ++sk)
+        xacc = mma64(Xl[I * PW + mr][I * PW + 4 * sk + mk], Tb[wave][4 * sk + mk][mr], xacc);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Xl[I * PW + mk + 4 * e][J * PW + mr] = -xacc[e];
     }
     __syncthreads();
   }
