@@ -55,15 +55,10 @@ struct DeviceGuard {
 
 void free_model_buffers(Model* M) {
   Ctx* c = M->ctx;
-  void* bufs[] = {M->X64, M->il64, M->L, M->Linv, M->Dinv, M->yt, M->alpha, M->work, M->L32,
-                  M->stats, M->info, M->Xs32, M->sc32, M->sc64, M->Xs64};
-  for (void* p : bufs)
-    if (p) dfree(c, p);
-  for (int i = 0; i < 3; ++i) {
-    if (M->pk[i]) dfree(c, M->pk[i]);
-    if (M->pk_off[i]) dfree(c, M->pk_off[i]);
-    if (M->alphaT[i]) dfree(c, M->alphaT[i]);
-  }
+  if (M->blk_fit) dfree(c, M->blk_fit);
+  if (M->blk_obs) dfree(c, M->blk_obs);
+  for (int i = 0; i < 3; ++i)
+    if (M->blk_score[i]) dfree(c, M->blk_score[i]);
 }
 
 gpbo_status check_problem(Ctx* c, const gpbo_problem* p) {
@@ -97,20 +92,28 @@ gpbo_status alloc_model(Ctx* c, const gpbo_problem* p, Model* M) {
   M->sn2 = p->noise_var;
   M->ls.assign(p->lengthscale, p->lengthscale + d);
   const size_t np = M->npad;
-  M->X64 = (double*)dmalloc(c, (size_t)n * d * sizeof(double));
-  M->il64 = (double*)dmalloc(c, d * sizeof(double));
-  M->L = (double*)dmalloc(c, np * np * sizeof(double));
-  M->Linv = (double*)dmalloc(c, np * np * sizeof(double));
-  M->Dinv = (double*)dmalloc(c, np * NB * sizeof(double));
-  M->yt = (double*)dmalloc(c, np * sizeof(double));
-  M->alpha = (double*)dmalloc(c, np * sizeof(double));
-  M->work = (double*)dmalloc(c, (4 + 16) * np * sizeof(double));  // 4 vectors + residual partials
-  M->stats = (double*)dmalloc(c, S_COUNT * sizeof(double));
-  M->info = (int*)dmalloc(c, 2 * sizeof(int));
-  if (p->refine_alpha) M->L32 = (float*)dmalloc(c, np * np * sizeof(float));
-  if (!M->X64 || !M->il64 || !M->L || !M->Linv || !M->Dinv || !M->yt || !M->alpha || !M->work ||
-      !M->stats || !M->info || (p->refine_alpha && !M->L32))
-    return fail(c, GPBO_E_OOM, "device allocation failed for a model with n=%d", n);
+  Carve cv;
+  const size_t oX = cv.take((size_t)n * d * sizeof(double)), oil = cv.take(d * sizeof(double)),
+               oL = cv.take(np * np * sizeof(double)), oLi = cv.take(np * np * sizeof(double)),
+               oD = cv.take(np * NB * sizeof(double)), oyt = cv.take(np * sizeof(double)),
+               oa = cv.take(np * sizeof(double)),
+               ow = cv.take((4 + 16) * np * sizeof(double)),  // 4 vectors + residual partials
+               ost = cv.take(S_COUNT * sizeof(double)), oin = cv.take(2 * sizeof(int)),
+               o32 = p->refine_alpha ? cv.take(np * np * sizeof(float)) : 0;
+  M->blk_fit = dmalloc(c, cv.bytes);
+  if (!M->blk_fit) return fail(c, GPBO_E_OOM, "device allocation failed for a model with n=%d", n);
+  char* b = (char*)M->blk_fit;
+  M->X64 = (double*)(b + oX);
+  M->il64 = (double*)(b + oil);
+  M->L = (double*)(b + oL);
+  M->Linv = (double*)(b + oLi);
+  M->Dinv = (double*)(b + oD);
+  M->yt = (double*)(b + oyt);
+  M->alpha = (double*)(b + oa);
+  M->work = (double*)(b + ow);
+  M->stats = (double*)(b + ost);
+  M->info = (int*)(b + oin);
+  if (p->refine_alpha) M->L32 = (float*)(b + o32);
   hipStream_t s = c->stream;
   M->il_host.resize(d);  // kept with the model: the copy below is asynchronous
   for (int k = 0; k < d; ++k) M->il_host[k] = 1.0 / p->lengthscale[k];
@@ -486,6 +489,8 @@ gpbo_status gpbo_score(gpbo_ctx c, gpbo_model M, int64_t m, const void* Xc, gpbo
                 M->n);
   const bool large = path == GPBO_PATH_LARGE;
   ensure_score_operands(M, prec, s);
+  if (!M->blk_obs || !M->blk_score[prec])
+    return fail(c, GPBO_E_OOM, "device allocation of the score operands failed (n=%d)", M->n);
   const int npj = M->pk_npj[prec];
   const int64_t tiles = large ? large_partials(npj, m) : ceil_div(m, tm);
   const size_t part_bytes = round_up((size_t)tiles * 16, 256);
@@ -579,7 +584,11 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
     if (score_smem(prec, nmax, dmax, tm) <= 160 * 1024) cands.push_back(tm);
   if (cands.empty())
     return fail(c, GPBO_E_UNSUPPORTED, "n=%d is too large for the batched scoring kernel", nmax);
-  for (int b = 0; b < B; ++b) ensure_score_operands(models[b], prec, s);
+  for (int b = 0; b < B; ++b) {
+    ensure_score_operands(models[b], prec, s);
+    if (!models[b]->blk_obs || !models[b]->blk_score[prec])
+      return fail(c, GPBO_E_OOM, "device allocation of the score operands failed (problem %d)", b);
+  }
   // problems in decreasing n: the costliest tiles are dispatched first
   std::vector<int> order(B);
   for (int b = 0; b < B; ++b) order[b] = b;

@@ -66,6 +66,23 @@ struct Model {
   int64_t* pk_off[3] = {nullptr, nullptr, nullptr};  // block offset of each row tile (+ end)
   int pk_npj[3] = {0, 0, 0};                   // padded column extent of the packed operand
   void* alphaT[3] = {nullptr, nullptr, nullptr};  // sf2 * alpha per precision (double / float)
+  // Every buffer above is carved out of one of these device allocations.
+  void* blk_fit = nullptr;                // X64 .. info, L32
+  void* blk_obs = nullptr;                // scales and scaled coordinates
+  void* blk_score[3] = {nullptr, nullptr, nullptr};  // pk, pk_off, alphaT per precision
+  std::vector<double> sc_host;            // sources of the asynchronous copies below
+  std::vector<float> sc32_host;
+  std::vector<int64_t> pk_off_host[3];
+};
+
+// Sub-buffers of one device allocation, each 256-byte aligned.
+struct Carve {
+  size_t bytes = 0;
+  size_t take(size_t b) {
+    const size_t o = bytes;
+    bytes += (b + 255) / 256 * 256;
+    return o;
+  }
 };
 
 struct Alloc {

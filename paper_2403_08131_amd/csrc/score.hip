@@ -547,47 +547,60 @@ void ensure_score_operands(Model* M, int prec, hipStream_t s) {
   const int n = M->n, d = M->d;
   if (!M->sc64) {
     // coordinate scales: 1/l for float64 and Matern; sqrt(log2(e)/2)/l for
-    // the float32 squared-exponential path (one exp2 per covariance)
-    std::vector<double> s64(d), s32(d);
+    // the float32 squared-exponential path (one exp2 per covariance); the
+    // host arrays live with the model, so no copy needs a synchronisation
+    M->sc_host.assign(2 * d, 0.0);
+    M->sc32_host.assign(d, 0.0f);
     for (int k = 0; k < d; ++k) {
-      s64[k] = 1.0 / M->ls[k];
-      s32[k] = (M->kernel == GPBO_KERNEL_SE ? std::sqrt(0.5 * 1.4426950408889634) : 1.0) / M->ls[k];
+      M->sc_host[k] = 1.0 / M->ls[k];
+      M->sc_host[d + k] =
+          (M->kernel == GPBO_KERNEL_SE ? std::sqrt(0.5 * 1.4426950408889634) : 1.0) / M->ls[k];
+      M->sc32_host[k] = (float)M->sc_host[d + k];
     }
-    std::vector<float> s32f(s32.begin(), s32.end());
-    M->sc64 = (double*)dmalloc(c, d * sizeof(double));
-    M->sc32 = (float*)dmalloc(c, d * sizeof(float));
-    double* s32d = (double*)dmalloc(c, d * sizeof(double));
-    (void)hipMemcpyAsync(M->sc64, s64.data(), d * sizeof(double), hipMemcpyHostToDevice, s);
-    (void)hipMemcpyAsync(M->sc32, s32f.data(), d * sizeof(float), hipMemcpyHostToDevice, s);
-    (void)hipMemcpyAsync(s32d, s32.data(), d * sizeof(double), hipMemcpyHostToDevice, s);
-    M->Xs64 = (double*)dmalloc(c, (size_t)n * d * sizeof(double));
-    M->Xs32 = (float*)dmalloc(c, (size_t)n * d * sizeof(float));
+    Carve cv;
+    const size_t o64 = cv.take(2 * d * sizeof(double)), o32 = cv.take(d * sizeof(float)),
+                 oX64 = cv.take((size_t)n * d * sizeof(double)),
+                 oX32 = cv.take((size_t)n * d * sizeof(float));
+    M->blk_obs = dmalloc(c, cv.bytes);
+    if (!M->blk_obs) return;  // the caller reports the missing operands
+    char* b = (char*)M->blk_obs;
+    M->sc64 = (double*)(b + o64);
+    M->sc32 = (float*)(b + o32);
+    M->Xs64 = (double*)(b + oX64);
+    M->Xs32 = (float*)(b + oX32);
+    (void)hipMemcpyAsync(M->sc64, M->sc_host.data(), 2 * d * sizeof(double), hipMemcpyHostToDevice, s);
+    (void)hipMemcpyAsync(M->sc32, M->sc32_host.data(), d * sizeof(float), hipMemcpyHostToDevice, s);
     const int g = (int)std::min<int64_t>(4096, ceil_div((int64_t)n * d, 256));
     hipLaunchKernelGGL(k_scale_obs_t<double>, dim3(g), dim3(256), 0, s, M->X64, M->sc64, n, d,
                        M->Xs64);
-    hipLaunchKernelGGL(k_scale_obs_t<float>, dim3(g), dim3(256), 0, s, M->X64, s32d, n, d,
+    hipLaunchKernelGGL(k_scale_obs_t<float>, dim3(g), dim3(256), 0, s, M->X64, M->sc64 + d, n, d,
                        M->Xs32);
-    (void)hipStreamSynchronize(s);
-    dfree(c, s32d);
   }
   if (!M->pk[prec]) {
-    const std::vector<int64_t> off = packed_offsets(n, prec);
+    M->pk_off_host[prec] = packed_offsets(n, prec);
+    const std::vector<int64_t>& off = M->pk_off_host[prec];
     const int ntiles = (int)off.size() - 1;
     const int64_t blocks = off.back() + prec_pf(prec);  // + zero slack for the pipelined loads
     const int kb = score_kb(prec);
     const int64_t count = blocks * TI * kb;
-    M->pk[prec] = dmalloc(c, count * score_esize(prec));
-    M->pk_off[prec] = (int64_t*)dmalloc(c, off.size() * sizeof(int64_t));
+    Carve cv;
+    const size_t opk = cv.take(count * score_esize(prec)),
+                 ooff = cv.take(off.size() * sizeof(int64_t)),
+                 oal = cv.take(n * (prec == GPBO_FP64 ? sizeof(double) : sizeof(float)));
+    M->blk_score[prec] = dmalloc(c, cv.bytes);
+    if (!M->blk_score[prec]) return;
+    char* b = (char*)M->blk_score[prec];
+    M->pk[prec] = b + opk;
+    M->pk_off[prec] = (int64_t*)(b + ooff);
+    M->alphaT[prec] = b + oal;
     M->pk_npj[prec] = packed_npj(n, prec);
     (void)hipMemcpyAsync(M->pk_off[prec], off.data(), off.size() * sizeof(int64_t),
                          hipMemcpyHostToDevice, s);
-    (void)hipStreamSynchronize(s);  // the host copy of the offsets goes out of scope
     const int64_t* doff = M->pk_off[prec];
     const int g = (int)std::min<int64_t>(8192, ceil_div(count, 256));
     if (prec == GPBO_FP64) {
       hipLaunchKernelGGL(k_pack<double>, dim3(g), dim3(256), 0, s, M->Linv, M->npad, n, M->sf2, kb,
                          doff, ntiles, (double*)M->pk[prec], blocks);
-      M->alphaT[prec] = dmalloc(c, n * sizeof(double));
       hipLaunchKernelGGL(k_scale_alpha<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, M->alpha,
                          n, M->sf2, (double*)M->alphaT[prec]);
     } else {
@@ -597,7 +610,6 @@ void ensure_score_operands(Model* M, int prec, hipStream_t s) {
       else
         hipLaunchKernelGGL(k_pack<unsigned short>, dim3(g), dim3(256), 0, s, M->Linv, M->npad, n,
                            M->sf2, kb, doff, ntiles, (unsigned short*)M->pk[prec], blocks);
-      M->alphaT[prec] = dmalloc(c, n * sizeof(float));
       hipLaunchKernelGGL(k_scale_alpha<float>, dim3(ceil_div(n, 256)), dim3(256), 0, s, M->alpha,
                          n, M->sf2, (float*)M->alphaT[prec]);
     }
