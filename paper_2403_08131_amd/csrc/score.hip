@@ -370,8 +370,12 @@ __device__ __forceinline__ void score_tile(const ScoreArgs& A, int64_t tile,
   if (wave == 0) phase_finish<P, TM, FW>(A, tile, mu_part, ssq_part);
 }
 
+// Below 64 candidates per workgroup the LDS tile leaves room for a second
+// workgroup per CU; at 128 registers or fewer (four waves per SIMD) it fits,
+// and one workgroup's cross-covariance phase overlaps the other's products.
 template <int P, int KERN, int TM>
-__global__ void __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(1, 4)))
+__global__ void __launch_bounds__(FT)
+    __attribute__((amdgpu_waves_per_eu((TM == 64 || P == GPBO_FP64) ? 1 : 4, 4)))
 k_score_fused(ScoreArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   // two float64 row tiles over 64 candidates exceed the register file
