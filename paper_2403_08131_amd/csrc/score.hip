@@ -231,34 +231,41 @@ __device__ __forceinline__ void phase_variance(const ScoreArgs& A, const typenam
     // the last.  With RT = 2 and the second tile missing, the first tile
     // takes the last slot and the first slot stays empty.
     static_assert(RT == 1 || RT == 2, "one or two row tiles per group");
+    constexpr int R = KB / TI;  // row tiles per column block
     const K* ablk[RT];
-    int nfirst, nlast;
+    int nfirst, nact[RT];  // nfirst: stored (PF-rounded) blocks of the first tile; nact: real blocks
     {
       const int t0 = RT * g;
       const int64_t o0 = pk_off[t0], o1 = pk_off[t0 + 1];
       if (RT == 1) {
         ablk[0] = pk + o0 * Blk<P>::EPB + lane * (KB / 4);
-        nfirst = nlast = (int)(o1 - o0);
+        nfirst = (int)(o1 - o0);
+        nact[0] = t0 / R + 1;
       } else if (t0 + 1 < ntiles) {
         ablk[0] = pk + o0 * Blk<P>::EPB + lane * (KB / 4);
         ablk[RT - 1] = pk + o1 * Blk<P>::EPB + lane * (KB / 4);
         nfirst = (int)(o1 - o0);
-        nlast = (int)(pk_off[t0 + 2] - o1);
+        nact[0] = t0 / R + 1;
+        nact[RT - 1] = (t0 + 1) / R + 1;
       } else {
         ablk[0] = ablk[RT - 1] = pk + o0 * Blk<P>::EPB + lane * (KB / 4);
         nfirst = 0;
-        nlast = (int)(o1 - o0);
+        nact[0] = 0;
+        nact[RT - 1] = t0 / R + 1;
       }
     }
+    const int nlast = nact[RT - 1];
     typename Blk<P>::Acc acc[RT][NCT];
 #pragma unroll
     for (int q = 0; q < RT; ++q)
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) acc[q][ct] = typename Blk<P>::Acc{0, 0, 0, 0};
     // one pipeline group: per block, the B operands from LDS, then the
-    // products of tiles Q0 .. RT - 1
-    auto group = [&](const V (&a)[RT][PF], int tj0, auto q0) {
+    // products of tiles Q0 .. RT - 1; a group that reaches past a tile's real
+    // blocks (the stored ones are rounded up to PF with zeros) skips them
+    auto group = [&](const V (&a)[RT][PF], int tj0, auto q0, auto full) {
       constexpr int Q0 = decltype(q0)::value;
+      constexpr bool FULL = decltype(full)::value;
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         V bv[NCT];
@@ -269,7 +276,8 @@ __device__ __forceinline__ void phase_variance(const ScoreArgs& A, const typenam
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
-            for (int q = Q0; q < RT; ++q) Blk<P>::mma_k(acc[q][ct], a[q][u], bv[ct], kk);
+            for (int q = Q0; q < RT; ++q)
+              if (FULL || tj0 + u < nact[q]) Blk<P>::mma_k(acc[q][ct], a[q][u], bv[ct], kk);
       }
     };
     // The packed blocks stream from L2 one group ahead (a group past the
@@ -284,11 +292,17 @@ __device__ __forceinline__ void phase_variance(const ScoreArgs& A, const typenam
     };
     using All = std::integral_constant<int, 0>;
     using Last = std::integral_constant<int, RT - 1>;
+    using Full = std::true_type;
+    using Part = std::false_type;
     auto fetch_at = [&](V (&a)[RT][PF], int tj0) {
       if (tj0 < nfirst) fetch(a, tj0, All{}); else fetch(a, tj0, Last{});
     };
     auto group_at = [&](const V (&a)[RT][PF], int tj0) {
-      if (tj0 < nfirst) group(a, tj0, All{}); else group(a, tj0, Last{});
+      if (tj0 < nfirst) {
+        if (tj0 + PF <= nact[0]) group(a, tj0, All{}, Full{}); else group(a, tj0, All{}, Part{});
+      } else {
+        if (tj0 + PF <= nlast) group(a, tj0, Last{}, Full{}); else group(a, tj0, Last{}, Part{});
+      }
     };
     V ra[RT][PF], rb[RT][PF];
     fetch_at(ra, 0);

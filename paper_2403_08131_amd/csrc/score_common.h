@@ -128,7 +128,7 @@ __device__ __forceinline__ bool better(double v, int64_t i, double bv, int64_t b
 __host__ __device__ __forceinline__ int tile_blocks(int t, int R, int PF) {
   return (t / R + 1 + PF - 1) / PF * PF;
 }
-__host__ __device__ __forceinline__ int prec_pf(int prec) { return prec == GPBO_FP32 ? 4 : 2; }
+__host__ __device__ __forceinline__ int prec_pf(int) { return 2; }
 
 // One packed 16 x KB block of the inverse factor (A operand) or of the
 // cross-covariance tile (B operand) as one lane holds it, and its
@@ -144,7 +144,7 @@ struct Blk<GPBO_FP32> {
   using V = f4;
   using Acc = f4;
   static constexpr int EPB = 64 * 4;
-  static constexpr int PF = 4;  // blocks per pipeline group (row tiles are padded to a multiple)
+  static constexpr int PF = 2;  // blocks per pipeline group (row tiles are padded to a multiple)
   static constexpr int KS = 4;  // matrix-core steps per block
   __device__ static __forceinline__ V load(const float* p) { return *(const f4*)p; }
   // step kk of the block product (callers interleave independent accumulators)
