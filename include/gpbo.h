@@ -130,9 +130,10 @@ gpbo_status gpbo_ctx_destroy(gpbo_ctx ctx);
 gpbo_status gpbo_ctx_set_stream(gpbo_ctx ctx, void* stream);
 /* Kernel timing.  While enabled, every launch of a candidate-scoring kernel
  * (the dominant kernel of gpbo_score: the fused kernel, or the triangular
- * product of the large-n path) and of the network forward kernel
- * (gpbo_mlp_forward, gpbo_mlp_prescreen*) is bracketed by HIP events recorded
- * on the context's stream.  gpbo_ctx_timing synchronises the stream, returns the
+ * product of the large-n path; the persistent kernel of gpbo_score_batched,
+ * which then launches eagerly instead of replaying its graph) and of the
+ * network forward kernel (gpbo_mlp_forward, gpbo_mlp_prescreen*) is bracketed
+ * by HIP events recorded on the context's stream.  gpbo_ctx_timing synchronises the stream, returns the
  * number of timed launches and their summed duration in milliseconds, and
  * resets both.  Either output may be NULL. */
 gpbo_status gpbo_ctx_enable_timing(gpbo_ctx ctx, int32_t enable);
@@ -171,7 +172,8 @@ gpbo_status gpbo_fit(gpbo_ctx ctx, const gpbo_problem* prob, gpbo_model* out, do
  * of different n and d are factored together, largest first.  SYNCHRONISES
  * once.  status (host, B) receives each problem's status; lml (host, B) may be
  * NULL.  Returns GPBO_OK when every problem fitted, else the first failing
- * problem's status (the models of failed problems are NULL). */
+ * problem's status (the models of failed problems are NULL).  The models of
+ * one call share one device allocation, released with the last of them. */
 gpbo_status gpbo_fit_batched(gpbo_ctx ctx, int32_t B, const gpbo_problem* probs,
                              gpbo_model* out, double* lml, int32_t* status);
 

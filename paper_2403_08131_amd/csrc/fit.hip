@@ -61,7 +61,8 @@ __device__ __forceinline__ double block_min(double v, double* red) {
   return r;
 }
 
-// Normalisation statistics, finiteness check and the normalised targets.
+// The model's copies of the observations and inverse lengthscales,
+// normalisation statistics, finiteness check and the normalised targets.
 __global__ void __launch_bounds__(256) k_fit_stats(const FitDesc* __restrict__ D) {
   __shared__ double red[256];
   __shared__ int bad;
@@ -71,7 +72,12 @@ __global__ void __launch_bounds__(256) k_fit_stats(const FitDesc* __restrict__ D
   if (t == 0) bad = 0;
   __syncthreads();
   int b = 0;
-  for (int64_t i = t; i < (int64_t)n * d; i += 256) b |= !isfinite(P.X[i]);
+  for (int64_t i = t; i < (int64_t)n * d; i += 256) {
+    const double x = P.Xsrc[i];
+    b |= !isfinite(x);
+    P.X[i] = x;
+  }
+  for (int k = t; k < d; k += 256) P.il[k] = P.ilsrc[k];
   for (int i = t; i < n; i += 256) b |= !isfinite(P.y[i]);
   if (b) atomicOr(&bad, 1);
   double s = 0.0;
@@ -740,7 +746,8 @@ void allow_tile_lds() {
 
 }  // namespace
 
-FitDesc make_fit_desc(Model* M, const double* y, int normalize_y, int refine) {
+FitDesc make_fit_desc(Model* M, const double* X, const double* il, const double* y,
+                      int normalize_y, int refine) {
   FitDesc f{};
   f.n = M->n;
   f.d = M->d;
@@ -753,6 +760,8 @@ FitDesc make_fit_desc(Model* M, const double* y, int normalize_y, int refine) {
   f.nchunks = (int)ceil_div(M->n, f.chunk);
   f.sf2 = M->sf2;
   f.sn2 = M->sn2;
+  f.Xsrc = X;
+  f.ilsrc = il;
   f.X = M->X64;
   f.il = M->il64;
   f.y = y;

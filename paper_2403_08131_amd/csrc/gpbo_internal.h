@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <functional>
+#include <memory>
 #include <string>
 #include <unordered_set>
 #include <vector>
@@ -43,7 +44,6 @@ struct Model {
   int kernel = 0;
   double sf2 = 1, sn2 = 0;
   std::vector<double> ls;       // host lengthscales
-  std::vector<double> il_host;  // host 1 / lengthscale (source of an asynchronous copy)
   double* X64 = nullptr;        // n x d, the observations as given
   double* il64 = nullptr;       // d, 1 / lengthscale
   double* L = nullptr;          // npad x npad, lower Cholesky factor (identity padded)
@@ -66,14 +66,20 @@ struct Model {
   int64_t* pk_off[3] = {nullptr, nullptr, nullptr};  // block offset of each row tile (+ end)
   int pk_npj[3] = {0, 0, 0};                   // padded column extent of the packed operand
   void* alphaT[3] = {nullptr, nullptr, nullptr};  // sf2 * alpha per precision (double / float)
-  // Every buffer above is carved out of one of these device allocations.
-  void* blk_fit = nullptr;                // X64 .. info, L32
-  void* blk_obs = nullptr;                // scales and scaled coordinates
-  void* blk_score[3] = {nullptr, nullptr, nullptr};  // pk, pk_off, alphaT per precision
-  std::vector<double> sc_host;            // sources of the asynchronous copies below
-  std::vector<float> sc32_host;
-  std::vector<int64_t> pk_off_host[3];
+  // Every buffer above lives in one of these device allocations.  A batch of
+  // models shares one allocation per group (fit; score operands), held by
+  // reference: it is released with the last model that uses it.
+  std::shared_ptr<void> blk_fit;          // X64 .. info, L32
+  std::shared_ptr<void> blk_obs;          // scales and scaled coordinates
+  std::shared_ptr<void> blk_score[3];     // pk, pk_off, alphaT per precision
+  // Host sources of the asynchronous uploads of the group this model was
+  // prepared with (kept until the last model of the group is freed).
+  std::shared_ptr<std::vector<unsigned char>> host_stage;
 };
+
+// A device allocation released through the context's allocator when the last
+// reference goes.
+std::shared_ptr<void> dshared(Ctx* c, size_t bytes);
 
 // Sub-buffers of one device allocation, each 256-byte aligned.
 struct Carve {
@@ -138,8 +144,10 @@ struct FitDesc {
   int n, d, npad, kernel;
   int normalize, refine, chunk, nchunks;  // residual column chunks
   double sf2, sn2;
-  const double* X;   // n x d (the model's copy)
-  const double* il;  // d, 1 / lengthscale
+  const double* Xsrc;   // n x d, the caller's observations (copied to X by the first kernel)
+  const double* ilsrc;  // d, 1 / lengthscale staged with the descriptors (copied to il)
+  double* X;            // n x d (the model's copy)
+  double* il;           // d, 1 / lengthscale (the model's copy)
   const double* y;   // n, the caller's observations
   double* L;         // npad x npad
   double* Linv;      // npad x npad
@@ -151,7 +159,8 @@ struct FitDesc {
   double* stats;
   int* info;
 };
-FitDesc make_fit_desc(Model* M, const double* y, int normalize_y, int refine);
+FitDesc make_fit_desc(Model* M, const double* X, const double* il, const double* y,
+                      int normalize_y, int refine);
 // Queue the whole fit of B problems (descriptors: host copy h, device copy dd).
 void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s);
 
@@ -160,7 +169,10 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s);
 // ---------------------------------------------------------------------------
 // Packed layout of sf2 * Linv for the matrix cores: for row tile ti (TI rows)
 // and column block tj <= ti*TI/KB ... see score.hip.
-void ensure_score_operands(Model* M, int prec, hipStream_t s);
+// Builds the missing score operands of `models` for `prec` (one device
+// allocation and one upload for all of them); afterwards a model whose
+// blk_obs / blk_score[prec] is still empty could not be allocated.
+void ensure_score_operands(Ctx* c, Model* const* models, int B, int prec, hipStream_t s);
 int score_kb(int prec);  // columns per packed block for a precision
 // Arguments of one problem's scoring (kernel argument of the single-problem
 // launch, and one entry of the descriptor array of a batched launch).
@@ -201,9 +213,12 @@ void launch_argmax_final(const double* part_v, const int64_t* part_i, int64_t np
 // Batched scoring: one persistent launch over the (problem, tile) items of B
 // problems (descriptors in device memory, ordered largest first), then a
 // per-problem argmax.  counter: one device uint, reset by the sequence itself.
+// mark (may be NULL): (*mark)(0) / (*mark)(1) right before / after the
+// scoring kernel, for timing.
 void launch_score_batched(const ScoreArgs* dd, int B, int64_t total_items, unsigned* counter,
                           int prec, int tile_m, size_t smem, int grid, int64_t* argmax,
-                          double* ei_max, hipStream_t s);
+                          double* ei_max, hipStream_t s,
+                          const std::function<void(int)>* mark = nullptr);
 
 // Top-k and gather (select.hip)
 int topk_max_k();

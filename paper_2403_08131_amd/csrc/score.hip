@@ -31,6 +31,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
+#include <functional>
+#include <memory>
 #include <type_traits>
 
 #include "score_common.h"
@@ -41,17 +44,42 @@ using namespace sc;
 
 namespace {
 
+// Per-problem arguments of the score-operand preparation kernels (problem
+// blockIdx.y of a launch).
+struct PrepDesc {
+  int n, d, npad, ntiles, kb;
+  int obs;             // build the scaled observations
+  double sf2;
+  const double* Linv;  // npad x npad
+  const double* X;     // n x d
+  const double* alpha; // n
+  const double* sc;    // 2d: 1 / l, then the float32 kernels' scales
+  double* Xs64;        // d x n
+  float* Xs32;         // d x n
+  const int64_t* off;  // ntiles + 1 row-tile block offsets (NULL: no packed operand)
+  void* pk;            // packed blocks (+ PF zero slack blocks)
+  int64_t blocks;      // stored blocks including the slack
+  void* alphaT;        // sf2 * alpha, precision-typed
+};
+
 // Packed sf2 * Linv: row tile ti, column block tj holds a 16 x KB block in
 // the lane order of Blk (off[t] .. off[t+1] are the blocks of row tile t;
-// blocks past off[ntiles] are zero slack for the pipelined loads).
-template <typename K>
-__global__ void k_pack(const double* __restrict__ Linv, int npad, int n, double sf2, int KB,
-                       const int64_t* __restrict__ off, int ntiles, K* __restrict__ out,
-                       int64_t total_blocks) {
-  const int per = KB / 4;
-  const int64_t cnt = total_blocks * 64 * per;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt;
+// blocks past off[ntiles] are zero slack for the pipelined loads); then
+// sf2 * alpha.  K: element type of the packed operand, A: of alpha.
+template <typename K, typename A>
+__global__ void __launch_bounds__(256) k_prep_pack(const PrepDesc* __restrict__ D) {
+  const PrepDesc& P = D[blockIdx.y];
+  if (!P.off) return;
+  const int per = P.kb / 4, n = P.n, ntiles = P.ntiles;
+  const int64_t cnt = P.blocks * 64 * per;
+  const int64_t* __restrict__ off = P.off;
+  K* __restrict__ out = (K*)P.pk;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt + n;
        e += (int64_t)gridDim.x * blockDim.x) {
+    if (e >= cnt) {
+      ((A*)P.alphaT)[e - cnt] = (A)(P.sf2 * P.alpha[e - cnt]);
+      continue;
+    }
     const int64_t blk = e / (64 * per);
     const int w = (int)(e % (64 * per));
     const int lane = w / per, q = w % per;
@@ -65,28 +93,26 @@ __global__ void k_pack(const double* __restrict__ Linv, int npad, int n, double 
       const int ti = lo;
       const int tj = (int)(blk - off[ti]);
       const int i = ti * TI + lane % 16;
-      const int j = tj * KB + per * (lane / 16) + q;
-      if (i < n && j < n && j <= i) v = sf2 * Linv[(int64_t)i * npad + j];
+      const int j = tj * P.kb + per * (lane / 16) + q;
+      if (i < n && j < n && j <= i) v = P.sf2 * P.Linv[(int64_t)i * P.npad + j];
     }
     store_elem(out + e, v);
   }
 }
 
-// Transposed scaled coordinates of the observations: XsT[k][j] = X[j][k] sc[k].
-template <typename T>
-__global__ void k_scale_obs_t(const double* __restrict__ X, const double* __restrict__ sc, int n,
-                              int d, T* __restrict__ XsT) {
+// Transposed scaled coordinates of the observations, both precisions:
+// Xs64[k][j] = X[j][k] / l_k, Xs32[k][j] = X[j][k] sc[d + k].
+__global__ void __launch_bounds__(256) k_prep_obs(const PrepDesc* __restrict__ D) {
+  const PrepDesc& P = D[blockIdx.y];
+  if (!P.obs) return;
+  const int n = P.n, d = P.d;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)n * d;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t k = e / n, j = e % n;
-    XsT[e] = (T)(X[j * d + k] * sc[k]);
+    const double x = P.X[j * d + k];
+    P.Xs64[e] = x * P.sc[k];
+    P.Xs32[e] = (float)(x * P.sc[d + k]);
   }
-}
-
-template <typename T>
-__global__ void k_scale_alpha(const double* __restrict__ a, int n, double sf2, T* __restrict__ o) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    o[i] = (T)(sf2 * a[i]);
 }
 
 // Eight waves share one LDS tile; LDS allows at most two workgroups per CU,
@@ -506,22 +532,26 @@ void launch_fused_tm(const ScoreArgs& a, int tm, size_t smem, hipStream_t s) {
 
 template <int P, int TM>
 void launch_batched_t(const ScoreArgs* dd, int B, int64_t total, unsigned* counter, size_t smem,
-                      int grid, int64_t* argmax, double* ei_max, hipStream_t s) {
+                      int grid, int64_t* argmax, double* ei_max, hipStream_t s,
+                      const std::function<void(int)>* mark) {
   allow_smem(k_score_batched<P, TM>, smem);
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
+  if (mark) (*mark)(0);
   hipLaunchKernelGGL((k_score_batched<P, TM>), dim3(grid), dim3(FT), smem, s, dd, B, total,
                      counter);
+  if (mark) (*mark)(1);
   if (argmax || ei_max)
     hipLaunchKernelGGL(k_argmax_batched<TM>, dim3(B), dim3(256), 0, s, dd, argmax, ei_max);
 }
 
 template <int P>
 void launch_batched_tm(const ScoreArgs* dd, int B, int64_t total, unsigned* counter, int tm,
-                       size_t smem, int grid, int64_t* argmax, double* ei_max, hipStream_t s) {
+                       size_t smem, int grid, int64_t* argmax, double* ei_max, hipStream_t s,
+                       const std::function<void(int)>* mark) {
   switch (tm) {
-    case 16: launch_batched_t<P, 16>(dd, B, total, counter, smem, grid, argmax, ei_max, s); break;
-    case 32: launch_batched_t<P, 32>(dd, B, total, counter, smem, grid, argmax, ei_max, s); break;
-    default: launch_batched_t<P, 64>(dd, B, total, counter, smem, grid, argmax, ei_max, s); break;
+    case 16: launch_batched_t<P, 16>(dd, B, total, counter, smem, grid, argmax, ei_max, s, mark); break;
+    case 32: launch_batched_t<P, 32>(dd, B, total, counter, smem, grid, argmax, ei_max, s, mark); break;
+    default: launch_batched_t<P, 64>(dd, B, total, counter, smem, grid, argmax, ei_max, s, mark); break;
   }
 }
 
@@ -560,77 +590,127 @@ std::vector<int64_t> packed_offsets(int n, int prec) {
   return off;
 }
 
-void ensure_score_operands(Model* M, int prec, hipStream_t s) {
-  Ctx* c = M->ctx;
-  const int n = M->n, d = M->d;
-  if (!M->sc64) {
-    // coordinate scales: 1/l for float64 and Matern; sqrt(log2(e)/2)/l for
-    // the float32 squared-exponential path (one exp2 per covariance); the
-    // host arrays live with the model, so no copy needs a synchronisation
-    M->sc_host.assign(2 * d, 0.0);
-    M->sc32_host.assign(d, 0.0f);
-    for (int k = 0; k < d; ++k) {
-      M->sc_host[k] = 1.0 / M->ls[k];
-      M->sc_host[d + k] =
-          (M->kernel == GPBO_KERNEL_SE ? std::sqrt(0.5 * 1.4426950408889634) : 1.0) / M->ls[k];
-      M->sc32_host[k] = (float)M->sc_host[d + k];
-    }
-    Carve cv;
-    const size_t o64 = cv.take(2 * d * sizeof(double)), o32 = cv.take(d * sizeof(float)),
-                 oX64 = cv.take((size_t)n * d * sizeof(double)),
-                 oX32 = cv.take((size_t)n * d * sizeof(float));
-    M->blk_obs = dmalloc(c, cv.bytes);
-    if (!M->blk_obs) return;  // the caller reports the missing operands
-    char* b = (char*)M->blk_obs;
-    M->sc64 = (double*)(b + o64);
-    M->sc32 = (float*)(b + o32);
-    M->Xs64 = (double*)(b + oX64);
-    M->Xs32 = (float*)(b + oX32);
-    (void)hipMemcpyAsync(M->sc64, M->sc_host.data(), 2 * d * sizeof(double), hipMemcpyHostToDevice, s);
-    (void)hipMemcpyAsync(M->sc32, M->sc32_host.data(), d * sizeof(float), hipMemcpyHostToDevice, s);
-    const int g = (int)std::min<int64_t>(4096, ceil_div((int64_t)n * d, 256));
-    hipLaunchKernelGGL(k_scale_obs_t<double>, dim3(g), dim3(256), 0, s, M->X64, M->sc64, n, d,
-                       M->Xs64);
-    hipLaunchKernelGGL(k_scale_obs_t<float>, dim3(g), dim3(256), 0, s, M->X64, M->sc64 + d, n, d,
-                       M->Xs32);
+void ensure_score_operands(Ctx* c, Model* const* models, int B, int prec, hipStream_t s) {
+  // what each model lacks
+  std::vector<Model*> need;
+  for (int b = 0; b < B; ++b) {
+    Model* M = models[b];
+    if (!M->blk_obs || !M->blk_score[prec])
+      if (std::find(need.begin(), need.end(), M) == need.end()) need.push_back(M);
   }
-  if (!M->pk[prec]) {
-    M->pk_off_host[prec] = packed_offsets(n, prec);
-    const std::vector<int64_t>& off = M->pk_off_host[prec];
-    const int ntiles = (int)off.size() - 1;
-    const int64_t blocks = off.back() + prec_pf(prec);  // + zero slack for the pipelined loads
-    const int kb = score_kb(prec);
-    const int64_t count = blocks * TI * kb;
-    Carve cv;
-    const size_t opk = cv.take(count * score_esize(prec)),
-                 ooff = cv.take(off.size() * sizeof(int64_t)),
-                 oal = cv.take(n * (prec == GPBO_FP64 ? sizeof(double) : sizeof(float)));
-    M->blk_score[prec] = dmalloc(c, cv.bytes);
-    if (!M->blk_score[prec]) return;
-    char* b = (char*)M->blk_score[prec];
-    M->pk[prec] = b + opk;
-    M->pk_off[prec] = (int64_t*)(b + ooff);
-    M->alphaT[prec] = b + oal;
-    M->pk_npj[prec] = packed_npj(n, prec);
-    (void)hipMemcpyAsync(M->pk_off[prec], off.data(), off.size() * sizeof(int64_t),
-                         hipMemcpyHostToDevice, s);
-    const int64_t* doff = M->pk_off[prec];
-    const int g = (int)std::min<int64_t>(8192, ceil_div(count, 256));
-    if (prec == GPBO_FP64) {
-      hipLaunchKernelGGL(k_pack<double>, dim3(g), dim3(256), 0, s, M->Linv, M->npad, n, M->sf2, kb,
-                         doff, ntiles, (double*)M->pk[prec], blocks);
-      hipLaunchKernelGGL(k_scale_alpha<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, M->alpha,
-                         n, M->sf2, (double*)M->alphaT[prec]);
-    } else {
-      if (prec == GPBO_FP32)
-        hipLaunchKernelGGL(k_pack<float>, dim3(g), dim3(256), 0, s, M->Linv, M->npad, n, M->sf2,
-                           kb, doff, ntiles, (float*)M->pk[prec], blocks);
-      else
-        hipLaunchKernelGGL(k_pack<unsigned short>, dim3(g), dim3(256), 0, s, M->Linv, M->npad, n,
-                           M->sf2, kb, doff, ntiles, (unsigned short*)M->pk[prec], blocks);
-      hipLaunchKernelGGL(k_scale_alpha<float>, dim3(ceil_div(n, 256)), dim3(256), 0, s, M->alpha,
-                         n, M->sf2, (float*)M->alphaT[prec]);
+  if (need.empty()) return;
+  const int nb = (int)need.size();
+  const int kb = score_kb(prec), PF = prec_pf(prec);
+  const size_t es = score_esize(prec), as = prec == GPBO_FP64 ? sizeof(double) : sizeof(float);
+  // Layout: the uploaded part (descriptors, coordinate scales, row-tile
+  // offsets), then the built part (scaled observations, packed operand,
+  // scaled alpha) of every model in one device allocation.
+  Carve up;
+  const size_t odesc = up.take(nb * sizeof(PrepDesc));
+  struct Part {
+    bool obs, score;
+    std::vector<int64_t> off;
+    size_t osc, ooff, oX64, oX32, opk, oal;
+  };
+  std::vector<Part> parts(nb);
+  for (int k = 0; k < nb; ++k) {
+    Model* M = need[k];
+    Part& q = parts[k];
+    q.obs = !M->blk_obs;
+    q.score = !M->blk_score[prec];
+    if (q.obs) q.osc = up.take(3 * M->d * sizeof(double));  // 2d doubles + d floats
+    if (q.score) {
+      q.off = packed_offsets(M->n, prec);
+      q.ooff = up.take(q.off.size() * sizeof(int64_t));
     }
+  }
+  const size_t up_bytes = up.bytes;
+  Carve cv = up;
+  for (int k = 0; k < nb; ++k) {
+    Model* M = need[k];
+    Part& q = parts[k];
+    if (q.obs) {
+      q.oX64 = cv.take((size_t)M->n * M->d * sizeof(double));
+      q.oX32 = cv.take((size_t)M->n * M->d * sizeof(float));
+    }
+    if (q.score) {
+      q.opk = cv.take((size_t)(q.off.back() + PF) * TI * kb * es);
+      q.oal = cv.take(M->n * as);
+    }
+  }
+  std::shared_ptr<void> grp = dshared(c, cv.bytes);
+  if (!grp) return;  // the caller reports the missing operands
+  char* g = (char*)grp.get();
+  auto stage = std::make_shared<std::vector<unsigned char>>(up_bytes);
+  unsigned char* h = stage->data();
+  PrepDesc* hd = (PrepDesc*)(h + odesc);
+  int64_t max_elems = 0;
+  bool any_obs = false, any_score = false;
+  for (int k = 0; k < nb; ++k) {
+    Model* M = need[k];
+    Part& q = parts[k];
+    const int n = M->n, d = M->d;
+    PrepDesc pd{};
+    pd.n = n;
+    pd.d = d;
+    pd.npad = M->npad;
+    pd.kb = kb;
+    pd.sf2 = M->sf2;
+    pd.Linv = M->Linv;
+    pd.X = M->X64;
+    pd.alpha = M->alpha;
+    if (q.obs) {
+      // coordinate scales: 1/l for float64 and Matern; sqrt(log2(e)/2)/l for
+      // the float32 squared-exponential path (one exp2 per covariance)
+      double* sc = (double*)(h + q.osc);
+      float* sc32 = (float*)(sc + 2 * d);
+      for (int j = 0; j < d; ++j) {
+        sc[j] = 1.0 / M->ls[j];
+        sc[d + j] = (M->kernel == GPBO_KERNEL_SE ? std::sqrt(0.5 * 1.4426950408889634) : 1.0) / M->ls[j];
+        sc32[j] = (float)sc[d + j];
+      }
+      M->sc64 = (double*)(g + q.osc);
+      M->sc32 = (float*)(M->sc64 + 2 * d);
+      M->Xs64 = (double*)(g + q.oX64);
+      M->Xs32 = (float*)(g + q.oX32);
+      M->blk_obs = std::shared_ptr<void>(grp, g + q.oX64);
+      pd.obs = 1;
+      pd.sc = M->sc64;
+      pd.Xs64 = M->Xs64;
+      pd.Xs32 = M->Xs32;
+      max_elems = std::max<int64_t>(max_elems, (int64_t)n * d);
+      any_obs = true;
+    }
+    if (q.score) {
+      std::memcpy(h + q.ooff, q.off.data(), q.off.size() * sizeof(int64_t));
+      M->pk[prec] = g + q.opk;
+      M->pk_off[prec] = (int64_t*)(g + q.ooff);
+      M->alphaT[prec] = g + q.oal;
+      M->pk_npj[prec] = packed_npj(n, prec);
+      M->blk_score[prec] = std::shared_ptr<void>(grp, g + q.opk);
+      pd.ntiles = (int)q.off.size() - 1;
+      pd.off = M->pk_off[prec];
+      pd.pk = M->pk[prec];
+      pd.blocks = q.off.back() + PF;  // + zero slack for the pipelined loads
+      pd.alphaT = M->alphaT[prec];
+      max_elems = std::max<int64_t>(max_elems, pd.blocks * TI * kb + n);
+      any_score = true;
+    }
+    hd[k] = pd;
+    M->host_stage = stage;  // the upload's source lives as long as the group
+  }
+  (void)hipMemcpyAsync(g, h, up_bytes, hipMemcpyHostToDevice, s);
+  const PrepDesc* dd = (const PrepDesc*)(g + odesc);
+  const dim3 grid((unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, ceil_div(max_elems, 256))),
+                  (unsigned)nb);
+  if (any_obs) hipLaunchKernelGGL(k_prep_obs, grid, dim3(256), 0, s, dd);
+  if (any_score) {
+    if (prec == GPBO_FP64)
+      hipLaunchKernelGGL((k_prep_pack<double, double>), grid, dim3(256), 0, s, dd);
+    else if (prec == GPBO_FP32)
+      hipLaunchKernelGGL((k_prep_pack<float, float>), grid, dim3(256), 0, s, dd);
+    else
+      hipLaunchKernelGGL((k_prep_pack<unsigned short, float>), grid, dim3(256), 0, s, dd);
   }
 }
 
@@ -689,16 +769,16 @@ void launch_argmax_final(const double* pv, const int64_t* pi, int64_t np, int64_
 
 void launch_score_batched(const ScoreArgs* dd, int B, int64_t total, unsigned* counter, int prec,
                           int tm, size_t smem, int grid, int64_t* argmax, double* ei_max,
-                          hipStream_t s) {
+                          hipStream_t s, const std::function<void(int)>* mark) {
   switch (prec) {
     case GPBO_FP64:
-      launch_batched_tm<GPBO_FP64>(dd, B, total, counter, tm, smem, grid, argmax, ei_max, s);
+      launch_batched_tm<GPBO_FP64>(dd, B, total, counter, tm, smem, grid, argmax, ei_max, s, mark);
       break;
     case GPBO_FP32:
-      launch_batched_tm<GPBO_FP32>(dd, B, total, counter, tm, smem, grid, argmax, ei_max, s);
+      launch_batched_tm<GPBO_FP32>(dd, B, total, counter, tm, smem, grid, argmax, ei_max, s, mark);
       break;
     default:
-      launch_batched_tm<GPBO_BF16>(dd, B, total, counter, tm, smem, grid, argmax, ei_max, s);
+      launch_batched_tm<GPBO_BF16>(dd, B, total, counter, tm, smem, grid, argmax, ei_max, s, mark);
       break;
   }
 }

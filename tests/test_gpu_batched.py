@@ -161,6 +161,43 @@ def test_score_batched_graph_replay(ctx):
         mo.free()
 
 
+def test_score_batched_graph_replay_after_refit(ctx):
+    """The next iteration of a search: the same batch shape with refitted
+    models and new pools (other tensors) replays the captured launch; every
+    replay equals the single-problem results of its own models and pools."""
+    import ctypes as C
+    probs = _problems(B=6, m=901, seed=3)
+    am = torch.empty(len(probs), dtype=torch.int64, device=DEV)
+    em = torch.empty(len(probs), dtype=torch.float64, device=DEV)
+    rng = np.random.default_rng(11)
+    for it in range(4):
+        if it:  # new observations and pools, same shapes
+            for p in probs:
+                p.y = p.y + rng.normal(0.0, 0.1, size=p.y.shape)
+                p.Xc = I.f32r(rng.uniform(0, 1, size=p.Xc.shape))
+        st, models, status, _ = _fit_batch(ctx, probs)
+        assert st == G.OK
+        Xcs = [_t(p.Xc, torch.float32) for p in probs]
+        eis = [torch.empty(x.shape[0], dtype=torch.float32, device=DEV) for x in Xcs]
+        B = len(models)
+        hs = (C.c_void_p * B)(*[mo.h.value for mo in models])
+        ms = (C.c_int64 * B)(*[x.shape[0] for x in Xcs])
+        xs = (C.c_void_p * B)(*[x.data_ptr() for x in Xcs])
+        ep = (C.c_void_p * B)(*[e.data_ptr() for e in eis])
+        ctx.check(G.lib().gpbo_score_batched(ctx.h, B, hs, ms, xs, G.FP32, ep,
+                                             C.c_void_p(am.data_ptr()), C.c_void_p(em.data_ptr())))
+        torch.cuda.synchronize()
+        amh = am.cpu().numpy()
+        for b, mo in enumerate(models):
+            single = G.score(ctx, mo, Xcs[b], "fp32")
+            torch.cuda.synchronize()
+            top = float(single["ei"].max())
+            assert float((eis[b] - single["ei"]).abs().max()) <= 1e-5 * max(top, 1e-30), (it, b)
+            assert float(eis[b][amh[b]]) == float(eis[b].max()), (it, b)
+        for mo in models:
+            mo.free()
+
+
 def test_batched_full_c3_shape_smoke(ctx):
     """The literal batch shape: 64 sub-searches, d in 2..12, n in 16..400,
     8192 candidates each; every argmax is a valid index with finite EI."""
