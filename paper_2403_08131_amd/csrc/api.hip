@@ -597,8 +597,9 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
     dmax = std::max(dmax, models[b]->d);
   }
   std::vector<int> cands;
+  // (the batched kernel also holds a 2 KB table of problem starts in LDS)
   for (int tm : {64, 32, 16})
-    if (score_smem(prec, nmax, dmax, tm) <= 160 * 1024) cands.push_back(tm);
+    if (score_smem(prec, nmax, dmax, tm) + 4096 <= 160 * 1024) cands.push_back(tm);
   if (cands.empty())
     return fail(c, GPBO_E_UNSUPPORTED, "n=%d is too large for the batched scoring kernel", nmax);
   {
@@ -655,6 +656,13 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
   char kbuf[160];
   snprintf(kbuf, sizeof kbuf, "batched:gfx950:hip%d:p%d:B%d:n%d:d%d", HIP_VERSION, (int)prec, B,
            (int)round_up(nmax, 64), dmax);
+  {
+    int64_t max_items = 0;
+    for (int b = 0; b < B; ++b) max_items += ceil_div(m[b], 16);
+    if (max_items + grid >= (int64_t)INT_MAX)
+      return fail(c, GPBO_E_UNSUPPORTED, "too many candidate tiles in one batch (%lld)",
+                  (long long)max_items);
+  }
   std::vector<ScoreArgs> hh;  // source of the descriptor copies of the timing runs
   bool tuned = false;
   const int tm = autotune_pick(c, kbuf, cands, [&](int cand) {
@@ -676,6 +684,9 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
   int64_t total = 0;
   size_t smem = 0;
   build(tm, h, total, smem);
+  // work items are counted in 32 bits (every workgroup pops one past the end)
+  if (total + grid >= (int64_t)INT_MAX)
+    return fail(c, GPBO_E_UNSUPPORTED, "too many candidate tiles in one batch (%lld)", (long long)total);
   HIP_TRY(c, hipMemcpyAsync(dd, h.data(), h.size() * sizeof(ScoreArgs), hipMemcpyHostToDevice, s));
   const std::vector<uint64_t> key = {(uint64_t)B, (uint64_t)prec, (uint64_t)tm, (uint64_t)total,
                                      (uint64_t)smem, (uint64_t)grid,

@@ -139,11 +139,25 @@ __device__ __forceinline__ void stage_candidates(const ScoreArgs& A, int64_t til
   }
 }
 
+// Waves of the cross-covariance phase that share a candidate group: the
+// number of 64-point blocks of the tile, rounded up to a power of two, at
+// most NW.  The other NW / WP wave slots take other candidate groups, so a
+// small problem still keeps every wave busy.
+template <int NW>
+__device__ __forceinline__ int cross_wp(int npj) {
+  const int pb = (npj + 63) / 64;
+  int wp = 1;
+  while (wp < pb && wp < NW) wp *= 2;
+  return wp;
+}
+
 // Phase 1: cross-covariance tile kt[c][j] and the mean partials
-// mu_part[w][c] of this wave's training points.
+// mu_part[r][c], r = the 64-point-block residue of the wave (rows
+// 0 .. cross_wp - 1).  Wave w takes point blocks w mod WP (stride WP) of the
+// candidate groups of CG candidates numbered w / WP (stride NW / WP).
 // DMAX > 0: points of up to DMAX dimensions keep all coordinates in
 // registers; larger d (and DMAX = 0) stream them DC at a time.
-template <int P, int KERN, int TM, int NW, int DMAX>
+template <int P, int KERN, int TM, int NW, int DMAX, int CG0 = 0, bool SPLIT = false>
 __device__ __forceinline__ void phase_cross(const ScoreArgs& A, typename PT<P>::K* kt,
                                             const typename PT<P>::C* xcT,
                                             typename PT<P>::Acc* mu_part, int w) {
@@ -152,16 +166,24 @@ __device__ __forceinline__ void phase_cross(const ScoreArgs& A, typename PT<P>::
   using Acc = typename PT<P>::Acc;
   using V4 = typename PT<P>::V4;
   // candidates per register group (float64 halves it to avoid spills)
-  constexpr int CG = TM < (P == GPBO_FP64 ? 16 : 32) ? TM : (P == GPBO_FP64 ? 16 : 32);
+  constexpr int CGD = P == GPBO_FP64 ? 16 : 32;
+  constexpr int CGM = CG0 > 0 ? CG0 : CGD;
+  constexpr int CG = TM < CGM ? TM : CGM;
   const int n = A.n, d = A.d, npj = A.npj, ldk = A.ldk;
   const Acc* __restrict__ alpha = (const Acc*)A.alpha;
   const C* __restrict__ XsT = (const C*)A.Xs;
   const int lane = threadIdx.x % 64;
-  for (int cg = 0; cg < TM; cg += CG) {
+  const int wp = SPLIT ? cross_wp<NW>(npj) : NW;
+  // (cg0, cgs): first candidate group and stride; (pr, wp): point-block
+  // residue and stride.  The full-width case (wp == NW) is a separate copy
+  // with the candidate loop known at compile time; SPLIT = false (one
+  // problem per launch) keeps only that copy.
+  auto body = [&](const int cg0, const int cgs, const int pr, const int pws) {
+  for (int cg = cg0; cg < TM; cg += cgs) {
     Acc macc[CG];
 #pragma unroll
     for (int c = 0; c < CG; ++c) macc[c] = 0;
-    for (int jb = w * 64; jb < npj; jb += NW * 64) {
+    for (int jb = pr * 64; jb < npj; jb += pws * 64) {
       const int j = jb + lane;
       const bool valid = j < n;
       const C* xcol = XsT + (valid ? j : 0);
@@ -218,8 +240,13 @@ __device__ __forceinline__ void phase_cross(const ScoreArgs& A, typename PT<P>::
         if (j < npj) kt[(cg + c) * ldk + j] = to_k<K, C>(kv);
       }
     }
-    lane_transpose_sum<Acc, CG>(macc, mu_part + w * TM + cg);
+    lane_transpose_sum<Acc, CG>(macc, mu_part + pr * TM + cg);
   }
+  };
+  if (!SPLIT || wp == NW)
+    body(0, CG, w, NW);
+  else
+    body((w / wp) * CG, (NW / wp) * CG, w % wp, wp);
 }
 
 // Phase 2: v = (sf2 Linv) khat on the matrix cores; ssq_part[w][c] receives
@@ -358,7 +385,7 @@ __device__ __forceinline__ void phase_variance(const ScoreArgs& A, const typenam
 
 // Phase 3 (one wave): outputs and the tile's argmax from the partials of
 // NW waves.
-template <int P, int TM, int NW>
+template <int P, int TM, int NW, bool SPLIT = false>
 __device__ __forceinline__ void phase_finish(const ScoreArgs& A, int64_t tile,
                                              const typename PT<P>::Acc* mu_part,
                                              const typename PT<P>::Acc* ssq_part) {
@@ -366,6 +393,7 @@ __device__ __forceinline__ void phase_finish(const ScoreArgs& A, int64_t tile,
   using In = typename PT<P>::In;
   const int lane = threadIdx.x % 64;
   const int64_t c0 = tile * TM, m = A.m;
+  const int wp = SPLIT ? cross_wp<NW>(A.npj) : NW;  // rows of mu_part written by phase 1
   double bv = -INFINITY;
   int64_t bi = -1;
   for (int c = lane; c < TM; c += 64) {
@@ -374,7 +402,7 @@ __device__ __forceinline__ void phase_finish(const ScoreArgs& A, int64_t tile,
     Acc muz = 0, vv = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-      muz += mu_part[w * TM + c];
+      if (w < wp) muz += mu_part[w * TM + c];
       vv += ssq_part[w * TM + c];
     }
     finish_candidate<Acc, In>(gc, muz, vv, A.sf2, A.stats, (In*)A.mu, (In*)A.sigma, (In*)A.ei, bv,
@@ -389,7 +417,7 @@ __device__ __forceinline__ void phase_finish(const ScoreArgs& A, int64_t tile,
 
 // Score candidate tile `tile` of problem A (TM candidates from tile * TM)
 // with all FW waves of the workgroup in every phase.
-template <int P, int KERN, int TM, int RT>
+template <int P, int KERN, int TM, int RT, int CG = 0, bool SPLIT = false>
 __device__ __forceinline__ void score_tile(const ScoreArgs& A, int64_t tile,
                                            unsigned char* smem) {
   using C = typename PT<P>::C;
@@ -403,11 +431,11 @@ __device__ __forceinline__ void score_tile(const ScoreArgs& A, int64_t tile,
   const int wave = wave_id();
   stage_candidates<P, TM, FW>(A, tile, xcT, threadIdx.x);
   __syncthreads();
-  phase_cross<P, KERN, TM, FW, 0>(A, kt, xcT, mu_part, wave);
+  phase_cross<P, KERN, TM, FW, 0, CG, SPLIT>(A, kt, xcT, mu_part, wave);
   __syncthreads();
   phase_variance<P, TM, FW, RT>(A, kt, ssq_part, wave);
   __syncthreads();
-  if (wave == 0) phase_finish<P, TM, FW>(A, tile, mu_part, ssq_part);
+  if (wave == 0) phase_finish<P, TM, FW, SPLIT>(A, tile, mu_part, ssq_part);
 }
 
 // Below 64 candidates per workgroup the LDS tile leaves room for a second
@@ -426,30 +454,70 @@ k_score_fused(ScoreArgs A) {
 // Persistent batched scoring: items 0 .. total-1 enumerate (problem, tile)
 // pairs, problem b owning items [tile_begin_b, tile_begin_{b+1}).  Every
 // workgroup pops items until the counter passes the total, so all of them
-// reach the exit.
+// reach the exit; the next item is popped while the current one is scored.
+// Problem starts of up to BT_MAX problems are looked up in LDS.  Candidate
+// groups of 16 keep every wave of the cross-covariance phase busy on the
+// small problems of a batch.
+constexpr int BT_MAX = 256;
+
+// The same address, known to the compiler as device-global memory (a round
+// trip through the global address space), so loads and stores through it are
+// global rather than flat instructions.
+template <typename T>
+__device__ __forceinline__ T* global_ptr(T* p) {
+  __attribute__((address_space(1))) T* g = (__attribute__((address_space(1))) T*)p;
+  __asm__("" : "+s"(g));  // keeps the cast pair from being folded away
+  return (T*)g;
+}
 template <int P, int TM>
 __global__ void __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(1, 4)))
 k_score_batched(const ScoreArgs* __restrict__ descs, int B, int64_t total,
                 unsigned* __restrict__ counter) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int64_t item_s;
+  __shared__ int64_t begin_s[BT_MAX];
+  const bool lds_table = B <= BT_MAX;
+  if (lds_table)
+    for (int b = threadIdx.x; b < B; b += FT) begin_s[b] = descs[b].tile_begin;
+  if (threadIdx.x == 0) item_s = (int64_t)atomicAdd(counter, 1u);
+  __syncthreads();
   for (;;) {
-    if (threadIdx.x == 0) item_s = (int64_t)atomicAdd(counter, 1u);
-    __syncthreads();
-    const int64_t item = item_s;
-    __syncthreads();
+    // item and problem are the same for the whole workgroup: kept in scalar
+    // registers, so the descriptor's fields are scalar loads
+    const int64_t item = (int64_t)__builtin_amdgcn_readfirstlane((int)item_s);
     if (item >= total) break;
+    unsigned nxt = 0;
+    if (threadIdx.x == 0) nxt = atomicAdd(counter, 1u);
     int lo = 0, hi = B - 1;  // problem: largest b with tile_begin <= item
     while (lo < hi) {
       const int mid = (lo + hi + 1) / 2;
-      if (descs[mid].tile_begin <= item) lo = mid; else hi = mid - 1;
+      const int64_t tb = lds_table ? begin_s[mid] : descs[mid].tile_begin;
+      if (tb <= item) lo = mid; else hi = mid - 1;
+      lo = __builtin_amdgcn_readfirstlane(lo);
+      hi = __builtin_amdgcn_readfirstlane(hi);
     }
-    const ScoreArgs& A = descs[lo];
+    ScoreArgs A = descs[lo];
+    // the descriptor's pointers are device-global memory: loads through them
+    // become global (not flat) loads, with their own wait counter
+    A.Xc = global_ptr(A.Xc);
+    A.mu = global_ptr(A.mu);
+    A.sigma = global_ptr(A.sigma);
+    A.Xs = global_ptr(A.Xs);
+    A.sc = global_ptr(A.sc);
+    A.alpha = global_ptr(A.alpha);
+    A.pk = global_ptr(A.pk);
+    A.pk_off = global_ptr(A.pk_off);
+    A.stats = global_ptr(A.stats);
+    A.ei = global_ptr(A.ei);
+    A.part_v = global_ptr(A.part_v);
+    A.part_i = global_ptr(A.part_i);
     if (A.kernel == GPBO_KERNEL_SE)
-      score_tile<P, GPBO_KERNEL_SE, TM, 1>(A, item - A.tile_begin, smem);
+      score_tile<P, GPBO_KERNEL_SE, TM, 1, 16, true>(A, item - A.tile_begin, smem);
     else
-      score_tile<P, GPBO_KERNEL_MATERN52, TM, 1>(A, item - A.tile_begin, smem);
-    __syncthreads();  // the LDS tile is reused by the next item
+      score_tile<P, GPBO_KERNEL_MATERN52, TM, 1, 16, true>(A, item - A.tile_begin, smem);
+    __syncthreads();  // item_s and the LDS tile are reused by the next item
+    if (threadIdx.x == 0) item_s = (int64_t)nxt;
+    __syncthreads();
   }
 }
 
