@@ -58,10 +58,11 @@ struct Model {
   double host_stats[S_COUNT] = {0};
   int host_info[2] = {0, 0};
   // Score operands, built on first use per precision.
-  float* Xs32 = nullptr;        // n x d, coordinates scaled for the float32 kernels
+  int nx = 0;                   // row stride of Xs32 / Xs64 (n padded with far-away points)
+  float* Xs32 = nullptr;        // d x nx, coordinates scaled for the float32 kernels
   float* sc32 = nullptr;        // d, coordinate scales for candidates (float32 kernels)
   double* sc64 = nullptr;       // d, coordinate scales (float64 kernels)
-  double* Xs64 = nullptr;       // n x d, scaled coordinates (float64 kernels)
+  double* Xs64 = nullptr;       // d x nx, scaled coordinates (float64 kernels)
   void* pk[3] = {nullptr, nullptr, nullptr};   // packed sf2 * Linv per precision
   int64_t* pk_off[3] = {nullptr, nullptr, nullptr};  // block offset of each row tile (+ end)
   int pk_npj[3] = {0, 0, 0};                   // padded column extent of the packed operand
@@ -178,11 +179,12 @@ int score_kb(int prec);  // columns per packed block for a precision
 // launch, and one entry of the descriptor array of a batched launch).
 struct ScoreArgs {
   int n, d, npk, npj;              // npk: n rounded up to 16; npj: padded column extent
+  int nx;                          // row stride of Xs; columns n .. nx-1 are padding points
   int kernel, ldk;                 // ldk: LDS row stride of the cross-covariance tile
   const int64_t* pk_off;           // row-tile block offsets of the packed operand
   const void* pk;                  // packed sf2 * Linv
   const void* alpha;               // sf2 * alpha (precision-typed)
-  const void* Xs;                  // scaled observations, dimension-major (d x n)
+  const void* Xs;                  // scaled observations, dimension-major (d x nx)
   const void* sc;                  // candidate coordinate scales
   const double* stats;             // device statistics (ymean, ystd, fbest)
   double sf2;

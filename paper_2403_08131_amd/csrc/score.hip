@@ -47,20 +47,25 @@ namespace {
 // Per-problem arguments of the score-operand preparation kernels (problem
 // blockIdx.y of a launch).
 struct PrepDesc {
-  int n, d, npad, ntiles, kb;
+  int n, d, npad, ntiles, kb, nx;
   int obs;             // build the scaled observations
   double sf2;
   const double* Linv;  // npad x npad
   const double* X;     // n x d
   const double* alpha; // n
   const double* sc;    // 2d: 1 / l, then the float32 kernels' scales
-  double* Xs64;        // d x n
-  float* Xs32;         // d x n
+  double* Xs64;        // d x nx
+  float* Xs32;         // d x nx
   const int64_t* off;  // ntiles + 1 row-tile block offsets (NULL: no packed operand)
   void* pk;            // packed blocks (+ PF zero slack blocks)
   int64_t blocks;      // stored blocks including the slack
-  void* alphaT;        // sf2 * alpha, precision-typed
+  void* alphaT;        // sf2 * alpha, precision-typed, nx (zero padded)
 };
+
+// Scaled coordinate of the padding points (columns n .. nx-1 of the scaled
+// observations): far enough that every covariance with them is exactly 0,
+// small enough that squared distances over 64 dimensions stay finite.
+constexpr double kPadCoord = 1e15;
 
 // Packed sf2 * Linv: row tile ti, column block tj holds a 16 x KB block in
 // the lane order of Blk (off[t] .. off[t+1] are the blocks of row tile t;
@@ -74,10 +79,11 @@ __global__ void __launch_bounds__(256) k_prep_pack(const PrepDesc* __restrict__ 
   const int64_t cnt = P.blocks * 64 * per;
   const int64_t* __restrict__ off = P.off;
   K* __restrict__ out = (K*)P.pk;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt + n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cnt + P.nx;
        e += (int64_t)gridDim.x * blockDim.x) {
     if (e >= cnt) {
-      ((A*)P.alphaT)[e - cnt] = (A)(P.sf2 * P.alpha[e - cnt]);
+      const int j = (int)(e - cnt);
+      ((A*)P.alphaT)[j] = j < n ? (A)(P.sf2 * P.alpha[j]) : A(0);
       continue;
     }
     const int64_t blk = e / (64 * per);
@@ -101,17 +107,23 @@ __global__ void __launch_bounds__(256) k_prep_pack(const PrepDesc* __restrict__ 
 }
 
 // Transposed scaled coordinates of the observations, both precisions:
-// Xs64[k][j] = X[j][k] / l_k, Xs32[k][j] = X[j][k] sc[d + k].
+// Xs64[k][j] = X[j][k] / l_k, Xs32[k][j] = X[j][k] sc[d + k]; padding points
+// past n.
 __global__ void __launch_bounds__(256) k_prep_obs(const PrepDesc* __restrict__ D) {
   const PrepDesc& P = D[blockIdx.y];
   if (!P.obs) return;
-  const int n = P.n, d = P.d;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)n * d;
+  const int n = P.n, d = P.d, nx = P.nx;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)nx * d;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t k = e / n, j = e % n;
-    const double x = P.X[j * d + k];
-    P.Xs64[e] = x * P.sc[k];
-    P.Xs32[e] = (float)(x * P.sc[d + k]);
+    const int64_t k = e / nx, j = e % nx;
+    if (j < n) {
+      const double x = P.X[j * d + k];
+      P.Xs64[e] = x * P.sc[k];
+      P.Xs32[e] = (float)(x * P.sc[d + k]);
+    } else {
+      P.Xs64[e] = kPadCoord;
+      P.Xs32[e] = (float)kPadCoord;
+    }
   }
 }
 
@@ -169,7 +181,7 @@ __device__ __forceinline__ void phase_cross(const ScoreArgs& A, typename PT<P>::
   constexpr int CGD = P == GPBO_FP64 ? 16 : 32;
   constexpr int CGM = CG0 > 0 ? CG0 : CGD;
   constexpr int CG = TM < CGM ? TM : CGM;
-  const int n = A.n, d = A.d, npj = A.npj, ldk = A.ldk;
+  const int d = A.d, npj = A.npj, ldk = A.ldk, nx = A.nx;
   const Acc* __restrict__ alpha = (const Acc*)A.alpha;
   const C* __restrict__ XsT = (const C*)A.Xs;
   const int lane = threadIdx.x % 64;
@@ -184,9 +196,9 @@ __device__ __forceinline__ void phase_cross(const ScoreArgs& A, typename PT<P>::
 #pragma unroll
     for (int c = 0; c < CG; ++c) macc[c] = 0;
     for (int jb = pr * 64; jb < npj; jb += pws * 64) {
+      // columns past n are padding points (zero covariance, zero alpha)
       const int j = jb + lane;
-      const bool valid = j < n;
-      const C* xcol = XsT + (valid ? j : 0);
+      const C* xcol = XsT + j;
       C r2[CG];
 #pragma unroll
       for (int c = 0; c < CG; ++c) r2[c] = 0;
@@ -209,7 +221,7 @@ __device__ __forceinline__ void phase_cross(const ScoreArgs& A, typename PT<P>::
         C xp[DMAX > 0 ? DMAX : 1];
 #pragma unroll
         for (int k = 0; k < DMAX; ++k)
-          if (k < d) xp[k] = xcol[(int64_t)k * n];
+          if (k < d) xp[k] = xcol[(int64_t)k * nx];
 #pragma unroll
         for (int k = 0; k < DMAX; ++k)
           if (k < d) dim(xp[k], k);
@@ -220,11 +232,11 @@ __device__ __forceinline__ void phase_cross(const ScoreArgs& A, typename PT<P>::
         constexpr int DC = 8;
         C xa[DC];
 #pragma unroll
-        for (int u = 0; u < DC; ++u) xa[u] = xcol[(int64_t)min(u, d - 1) * n];
+        for (int u = 0; u < DC; ++u) xa[u] = xcol[(int64_t)min(u, d - 1) * nx];
         for (int k0 = 0; k0 < d; k0 += DC) {
           C xb[DC];
 #pragma unroll
-          for (int u = 0; u < DC; ++u) xb[u] = xcol[(int64_t)min(k0 + DC + u, d - 1) * n];
+          for (int u = 0; u < DC; ++u) xb[u] = xcol[(int64_t)min(k0 + DC + u, d - 1) * nx];
 #pragma unroll
           for (int u = 0; u < DC; ++u)
             if (k0 + u < d) dim(xa[u], k0 + u);
@@ -232,12 +244,12 @@ __device__ __forceinline__ void phase_cross(const ScoreArgs& A, typename PT<P>::
           for (int u = 0; u < DC; ++u) xa[u] = xb[u];
         }
       }
-      const Acc aj = valid ? alpha[j] : Acc(0);
+      const Acc aj = alpha[j];
 #pragma unroll
       for (int c = 0; c < CG; ++c) {
-        const C kv = valid ? cov_from_r2<KERN>(r2[c]) : C(0);
+        const C kv = cov_from_r2<KERN>(r2[c]);
         macc[c] = fma((Acc)kv, aj, macc[c]);
-        if (j < npj) kt[(cg + c) * ldk + j] = to_k<K, C>(kv);
+        kt[(cg + c) * ldk + j] = to_k<K, C>(kv);  // rows hold whole 64-point blocks
       }
     }
     lane_transpose_sum<Acc, CG>(macc, mu_part + pr * TM + cg);
@@ -635,11 +647,12 @@ int packed_npj(int n, int prec) {
   return tile_blocks(ntiles - 1, score_kb(prec) / TI, prec_pf(prec)) * score_kb(prec);
 }
 
-// LDS row stride (elements) of the khat tile: rows 16-byte aligned and offset
-// by 16 bytes modulo 128 so the 16 rows read by one matrix-core operand load
-// fall in different banks.
+// LDS row stride (elements) of the khat tile: whole 64-point blocks (the
+// cross-covariance phase writes every lane of a block), rows 16-byte aligned
+// and offset by 16 bytes modulo 128 so the 16 rows read by one matrix-core
+// operand load fall in different banks.
 int kt_stride(int prec, int npj) {
-  const int64_t bytes = round_up(npj * (int64_t)score_esize(prec), 128) + 16;
+  const int64_t bytes = round_up(round_up(npj, 64) * (int64_t)score_esize(prec), 128) + 16;
   return (int)(bytes / score_esize(prec));
 }
 
@@ -657,6 +670,11 @@ std::vector<int64_t> packed_offsets(int n, int prec) {
   for (int t = 0; t < ntiles; ++t) off[t + 1] = off[t] + tile_blocks(t, R, PF);
   return off;
 }
+
+// Row stride of the scaled observations: n rounded up to whole 64-point
+// blocks, plus one block, which covers the packed column extent of every
+// precision rounded up to 64.
+static int score_nx(int n) { return (int)round_up(n, 64) + 64; }
 
 void ensure_score_operands(Ctx* c, Model* const* models, int B, int prec, hipStream_t s) {
   // what each model lacks
@@ -697,13 +715,14 @@ void ensure_score_operands(Ctx* c, Model* const* models, int B, int prec, hipStr
   for (int k = 0; k < nb; ++k) {
     Model* M = need[k];
     Part& q = parts[k];
+    const int nx = score_nx(M->n);
     if (q.obs) {
-      q.oX64 = cv.take((size_t)M->n * M->d * sizeof(double));
-      q.oX32 = cv.take((size_t)M->n * M->d * sizeof(float));
+      q.oX64 = cv.take((size_t)nx * M->d * sizeof(double));
+      q.oX32 = cv.take((size_t)nx * M->d * sizeof(float));
     }
     if (q.score) {
       q.opk = cv.take((size_t)(q.off.back() + PF) * TI * kb * es);
-      q.oal = cv.take(M->n * as);
+      q.oal = cv.take(nx * as);
     }
   }
   std::shared_ptr<void> grp = dshared(c, cv.bytes);
@@ -721,6 +740,7 @@ void ensure_score_operands(Ctx* c, Model* const* models, int B, int prec, hipStr
     PrepDesc pd{};
     pd.n = n;
     pd.d = d;
+    pd.nx = score_nx(n);
     pd.npad = M->npad;
     pd.kb = kb;
     pd.sf2 = M->sf2;
@@ -737,6 +757,7 @@ void ensure_score_operands(Ctx* c, Model* const* models, int B, int prec, hipStr
         sc[d + j] = (M->kernel == GPBO_KERNEL_SE ? std::sqrt(0.5 * 1.4426950408889634) : 1.0) / M->ls[j];
         sc32[j] = (float)sc[d + j];
       }
+      M->nx = pd.nx;
       M->sc64 = (double*)(g + q.osc);
       M->sc32 = (float*)(M->sc64 + 2 * d);
       M->Xs64 = (double*)(g + q.oX64);
@@ -746,7 +767,7 @@ void ensure_score_operands(Ctx* c, Model* const* models, int B, int prec, hipStr
       pd.sc = M->sc64;
       pd.Xs64 = M->Xs64;
       pd.Xs32 = M->Xs32;
-      max_elems = std::max<int64_t>(max_elems, (int64_t)n * d);
+      max_elems = std::max<int64_t>(max_elems, (int64_t)pd.nx * d);
       any_obs = true;
     }
     if (q.score) {
@@ -761,7 +782,7 @@ void ensure_score_operands(Ctx* c, Model* const* models, int B, int prec, hipStr
       pd.pk = M->pk[prec];
       pd.blocks = q.off.back() + PF;  // + zero slack for the pipelined loads
       pd.alphaT = M->alphaT[prec];
-      max_elems = std::max<int64_t>(max_elems, pd.blocks * TI * kb + n);
+      max_elems = std::max<int64_t>(max_elems, pd.blocks * TI * kb + pd.nx);
       any_score = true;
     }
     hd[k] = pd;
@@ -798,6 +819,7 @@ ScoreArgs make_score_args(Model* M, int prec, int tm) {
   a.d = M->d;
   a.npk = (int)round_up(M->n, TI);
   a.npj = M->pk_npj[prec];
+  a.nx = M->nx;
   a.kernel = M->kernel;
   a.ldk = kt_stride(prec, a.npj);
   a.pk_off = M->pk_off[prec];

@@ -29,7 +29,8 @@ constexpr int GM_I = 64;     // inverse-factor rows per GEMM workgroup
 constexpr int GM_C = 128;    // candidates per GEMM workgroup
 
 template <int KERN>
-__global__ void __launch_bounds__(256) k_kstar(int n, int d, int npj, const float* __restrict__ XsT,
+__global__ void __launch_bounds__(256) k_kstar(int n, int d, int npj, int nx,
+                                               const float* __restrict__ XsT,
                                                const float* __restrict__ sc,
                                                const float* __restrict__ alpha, int64_t m,
                                                int64_t cbeg, const float* __restrict__ Xc,
@@ -55,7 +56,7 @@ __global__ void __launch_bounds__(256) k_kstar(int n, int d, int npj, const floa
   float xnext = xcol[0];
   for (int k = 0; k < d; ++k) {
     const float xk = xnext;
-    if (k + 1 < d) xnext = xcol[(int64_t)(k + 1) * n];
+    if (k + 1 < d) xnext = xcol[(int64_t)(k + 1) * nx];
     const float* xr = xcT + k * KS_CG;
 #pragma unroll
     for (int c = 0; c < KS_CG; c += 4) {
@@ -228,11 +229,11 @@ void launch_score_large(const ScoreArgs& a, void* scratch, hipStream_t s,
     const int64_t mc_pad = round_up(mcur, GM_C);
     const dim3 gk((unsigned)ceil_div(mc_pad, KS_CG), (unsigned)njb);
     if (a.kernel == GPBO_KERNEL_SE)
-      hipLaunchKernelGGL(k_kstar<GPBO_KERNEL_SE>, gk, dim3(256), 0, s, n, d, npj,
+      hipLaunchKernelGGL(k_kstar<GPBO_KERNEL_SE>, gk, dim3(256), 0, s, n, d, npj, a.nx,
                          (const float*)a.Xs, (const float*)a.sc, (const float*)a.alpha, m, cbeg,
                          (const float*)a.Xc, khat, npj, mu_part, mc_pad);
     else
-      hipLaunchKernelGGL(k_kstar<GPBO_KERNEL_MATERN52>, gk, dim3(256), 0, s, n, d, npj,
+      hipLaunchKernelGGL(k_kstar<GPBO_KERNEL_MATERN52>, gk, dim3(256), 0, s, n, d, npj, a.nx,
                          (const float*)a.Xs, (const float*)a.sc, (const float*)a.alpha, m, cbeg,
                          (const float*)a.Xc, khat, npj, mu_part, mc_pad);
     const int ncb = (int)(mc_pad / GM_C);
