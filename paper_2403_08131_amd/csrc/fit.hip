@@ -61,8 +61,9 @@ __device__ __forceinline__ double block_min(double v, double* red) {
   return r;
 }
 
-// The model's copies of the observations and inverse lengthscales,
-// normalisation statistics, finiteness check and the normalised targets.
+// The model's copy of the inverse lengthscales, normalisation statistics,
+// finiteness check of y and the normalised targets (X is copied and checked
+// by the Gram kernel's diagonal tiles).
 __global__ void __launch_bounds__(256) k_fit_stats(const FitDesc* __restrict__ D) {
   __shared__ double red[256];
   __shared__ int bad;
@@ -72,11 +73,6 @@ __global__ void __launch_bounds__(256) k_fit_stats(const FitDesc* __restrict__ D
   if (t == 0) bad = 0;
   __syncthreads();
   int b = 0;
-  for (int64_t i = t; i < (int64_t)n * d; i += 256) {
-    const double x = P.Xsrc[i];
-    b |= !isfinite(x);
-    P.X[i] = x;
-  }
   for (int k = t; k < d; k += 256) P.il[k] = P.ilsrc[k];
   for (int i = t; i < n; i += 256) b |= !isfinite(P.y[i]);
   if (b) atomicOr(&bad, 1);
@@ -126,12 +122,14 @@ __device__ __forceinline__ double sqdist4(const double* a, const double* b, int 
   return (s0 + s1) + (s2 + s3);
 }
 
-// Stage 64 scaled coordinate rows starting at row r0 (rows >= lim are zero).
-__device__ __forceinline__ void stage_rows(const FitDesc& P, int r0, int lim, double* dst) {
+// Stage 64 scaled coordinate rows of X (n x d) starting at row r0 (rows >=
+// lim are zero).
+__device__ __forceinline__ void stage_rows(const FitDesc& P, const double* X, int r0, int lim,
+                                           double* dst) {
   const int dp4 = (P.d + 3) & ~3;
   for (int e = threadIdx.x; e < NB * dp4; e += blockDim.x) {
     const int r = e / dp4, k = e % dp4;
-    dst[r * GS + k] = (r0 + r < lim && k < P.d) ? P.X[(int64_t)(r0 + r) * P.d + k] * P.il[k] : 0.0;
+    dst[r * GS + k] = (r0 + r < lim && k < P.d) ? X[(int64_t)(r0 + r) * P.d + k] * P.il[k] : 0.0;
   }
 }
 
@@ -146,6 +144,8 @@ __device__ __forceinline__ void tri_index(int b, int& I, int& J) {
 
 // Lower triangle of K = sf2 k(X,X) + sn2 I (identity beyond n); the tile
 // mirrored above the diagonal is zeroed so the factor's upper part is clean.
+// The coordinates are read from the caller's X; the diagonal tiles also copy
+// their 64 rows into the model and flag non-finite values.
 __global__ void __launch_bounds__(256) k_gram(const FitDesc* __restrict__ D) {
   __shared__ double xi[NB * GS], xj[NB * GS];
   const FitDesc& P = D[blockIdx.z];
@@ -154,8 +154,18 @@ __global__ void __launch_bounds__(256) k_gram(const FitDesc* __restrict__ D) {
   const int n = P.n, npad = P.npad;
   int I, J;
   tri_index(blockIdx.x, I, J);
-  stage_rows(P, I * NB, n, xi);
-  stage_rows(P, J * NB, n, xj);
+  if (I == J) {
+    const int64_t e0 = (int64_t)I * NB * P.d, e1 = (int64_t)min(n, (I + 1) * NB) * P.d;
+    int bad = 0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+      const double x = P.Xsrc[e];
+      bad |= !isfinite(x);
+      P.X[e] = x;
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(P.info + 1, 1);
+  }
+  stage_rows(P, P.Xsrc, I * NB, n, xi);
+  stage_rows(P, P.Xsrc, J * NB, n, xj);
   __syncthreads();
   const int dp4 = (P.d + 3) & ~3;
 #pragma unroll 4
@@ -622,31 +632,40 @@ __global__ void __launch_bounds__(256) k_trmv(const FitDesc* __restrict__ Ds, in
 }
 
 // y = Linv^T x: y_j = sum_{i >= j} Linv_ij x_i.  A workgroup owns 64 columns;
-// its four waves split the rows and combine in LDS.
-__global__ void __launch_bounds__(256) k_trmv_t(const FitDesc* __restrict__ Ds, int xv, int yv) {
-  __shared__ double red[4][64];
+// its 16 waves take every 16th row from the block's first column on, all
+// lanes of a wave reading the same row (one coalesced load), and combine in
+// LDS.
+constexpr int TRMV_T_WAVES = 16;
+__global__ void __launch_bounds__(64 * TRMV_T_WAVES) k_trmv_t(const FitDesc* __restrict__ Ds,
+                                                              int xv, int yv) {
+  __shared__ double red[TRMV_T_WAVES][64];
   const FitDesc& P = Ds[blockIdx.z];
   if ((int)blockIdx.x * 64 >= P.npad || fit_failed(P.info)) return;
   const int n = P.n, npad = P.npad;
   const double* x = wvec(P, xv);
   double* y = wvec(P, yv);
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-  const int j = blockIdx.x * 64 + lane;
+  const int j0 = blockIdx.x * 64, j = j0 + lane;
   double s = 0.0;
-  if (j < n) {
-    if (P.refine) {
-      float sf = 0.0f;
-#pragma unroll 8
-      for (int i = j + w; i < n; i += 4) sf += P.L32[(int64_t)i * npad + j] * (float)x[i];
-      s = sf;
-    } else {
-#pragma unroll 8
-      for (int i = j + w; i < n; i += 4) s += P.Linv[(int64_t)i * npad + j] * x[i];
-    }
+  if (P.refine) {
+    float sf = 0.0f;
+#pragma unroll 4
+    for (int i = j0 + w; i < n; i += TRMV_T_WAVES)
+      if (i >= j) sf += P.L32[(int64_t)i * npad + j] * (float)x[i];
+    s = sf;
+  } else {
+#pragma unroll 4
+    for (int i = j0 + w; i < n; i += TRMV_T_WAVES)
+      if (i >= j) s += P.Linv[(int64_t)i * npad + j] * x[i];
   }
   red[w][lane] = s;
   __syncthreads();
-  if (w == 0) y[j] = j < n ? red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane] : 0.0;
+  if (w == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < TRMV_T_WAVES; ++q) t += red[q][lane];
+    y[j] = j < n ? t : 0.0;
+  }
 }
 
 // Partial products of K alpha, K recomputed in float64 exactly as the Gram
@@ -661,12 +680,12 @@ __global__ void __launch_bounds__(256) k_residual(const FitDesc* __restrict__ Ds
   const int t = threadIdx.x, row = t % NB, grp = t / NB;
   const int jbeg = blockIdx.y * P.chunk, jend = min(n, jbeg + P.chunk);
   const int dp4 = (P.d + 3) & ~3;
-  stage_rows(P, i0, n, xi);
+  stage_rows(P, P.X, i0, n, xi);
   const int i = i0 + row;
   double s = 0.0;
   for (int j0 = jbeg; j0 < jend; j0 += NB) {
     __syncthreads();
-    stage_rows(P, j0, jend, xj);
+    stage_rows(P, P.X, j0, jend, xj);
     if (t < NB) aj[t] = j0 + t < jend ? P.alpha[j0 + t] : 0.0;
     __syncthreads();
     if (i < n) {
@@ -811,12 +830,12 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   const unsigned g_rows = (unsigned)ceil_div(npmax, 4), g_cols = (unsigned)ceil_div(npmax, 64);
   // alpha = Linv^T (Linv ytilde), then one residual-and-correction step
   hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, -1, (int)V_W);
-  hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(256), 0, s, dd, (int)V_W, -2);
+  hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(64 * TRMV_T_WAVES), 0, s, dd, (int)V_W, -2);
   const dim3 g_res((unsigned)ceil_div(nmax, NB), (unsigned)chmax, Bz);
   hipLaunchKernelGGL(k_residual, g_res, dim3(256), 0, s, dd);
   hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(256), 0, s, dd, (int)S_RES0);
   hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, (int)V_R, (int)V_W);
-  hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(256), 0, s, dd, (int)V_W, (int)V_D);
+  hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(64 * TRMV_T_WAVES), 0, s, dd, (int)V_W, (int)V_D);
   hipLaunchKernelGGL(k_add_delta, dim3(1, 1, Bz), dim3(256), 0, s, dd);
   hipLaunchKernelGGL(k_residual, g_res, dim3(256), 0, s, dd);
   hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(256), 0, s, dd, (int)S_RES1);

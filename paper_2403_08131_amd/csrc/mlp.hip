@@ -33,13 +33,31 @@ constexpr int MT = 64;  // samples per forward / backward workgroup
 __device__ __forceinline__ float bfr(float x) { return __uint_as_float((unsigned)f2bf(x) << 16); }
 __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
 
-// Exact GELU u Phi(u) and its derivative Phi(u) + u phi(u).
-__device__ __forceinline__ float gelu(float u) {
-  return 0.5f * u * (1.0f + erff(u * 0.70710678118654752440f));
+// GELU u Phi(u) and its derivative Phi(u) + u phi(u), with the normal CDF
+// from the rational approximation of erf of Abramowitz & Stegun (1964),
+// formula 7.1.26: for x >= 0, erf x = 1 - t (a1 + t (a2 + t (a3 + t (a4 +
+// t a5)))) exp(-x^2), t = 1 / (1 + p x), absolute error <= 1.5e-7 -- far
+// below the bfloat16 rounding the activations receive next.  Branch-free;
+// exp(-u^2 / 2) is shared with the density.
+struct NormalCdf {
+  float Phi, e;  // Phi(u) and exp(-u^2 / 2)
+};
+__device__ __forceinline__ NormalCdf normal_cdf(float u) {
+  const float x = fabsf(u) * 0.70710678118654752440f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+  float q = fmaf(t, 1.061405429f, -1.453152027f);
+  q = fmaf(t, q, 1.421413741f);
+  q = fmaf(t, q, -0.284496736f);
+  q = fmaf(t, q, 0.254829592f);
+  q *= t;
+  const float e = __builtin_amdgcn_exp2f(-x * x * 1.44269504088896340736f);
+  const float tail = 0.5f * q * e;  // Phi(-|u|)
+  return {u >= 0.0f ? 1.0f - tail : tail, e};
 }
+__device__ __forceinline__ float gelu(float u) { return u * normal_cdf(u).Phi; }
 __device__ __forceinline__ float gelu_grad(float u) {
-  return 0.5f * (1.0f + erff(u * 0.70710678118654752440f)) +
-         u * expf(-0.5f * u * u) * 0.39894228040143267794f;
+  const NormalCdf c = normal_cdf(u);
+  return c.Phi + u * c.e * 0.39894228040143267794f;
 }
 
 struct MlpDev {

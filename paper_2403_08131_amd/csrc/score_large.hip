@@ -107,28 +107,51 @@ __global__ void __launch_bounds__(256) k_trigemm(const float* __restrict__ khat,
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[r][ct] = f4{0, 0, 0, 0};
+  const bool has1 = ti1 < ntiles;  // without it acc[1] is computed but not used
   if (ti0 < ntiles) {
-    const bool has1 = ti1 < ntiles;
     const float* a0p = pk + pk_off[ti0] * 256 + lane * 4;
     const float* a1p = has1 ? pk + pk_off[ti1] * 256 + lane * 4 : a0p;
     const int nlast = has1 ? ti1 : ti0;  // last column block needed
     const float* bp = khat + (cbase + lane % 16) * ldk + 4 * (lane / 16);
-    for (int tj = 0; tj <= nlast; ++tj) {
-      const f4 a0 = tj <= ti0 ? *(const f4*)(a0p + tj * 256) : f4{0, 0, 0, 0};
-      const f4 a1 = has1 ? *(const f4*)(a1p + tj * 256) : f4{0, 0, 0, 0};
-      f4 bv[4];
+    // operands of column block tj in one of two register buffers; block
+    // tj + 1 goes to the other buffer before the products of block tj, so its
+    // loads are in flight meanwhile.  The loads are unconditional (no branch
+    // for the wait counters to merge over): row tile ti0's stored blocks are
+    // padded with zero blocks up to an even count, so its block ti0 + 1 is a
+    // zero block, and the prefetch past the last block re-reads the last one.
+    f4 a0[2], a1[2], bv[2][4];
+    auto load = [&](int tj, int q) {
+      a0[q] = *(const f4*)(a0p + tj * 256);
+      a1[q] = *(const f4*)(a1p + tj * 256);
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) bv[ct] = *(const f4*)(bp + (int64_t)ct * 16 * ldk + tj * 16);
-      // step-major: consecutive matrix-core instructions update different
-      // accumulators
+      for (int ct = 0; ct < 4; ++ct)
+        bv[q][ct] = *(const f4*)(bp + (int64_t)ct * 16 * ldk + tj * 16);
+    };
+    // step-major: consecutive matrix-core instructions update different
+    // accumulators
+    auto mma = [&](int q) {
 #pragma unroll
       for (int kk = 0; kk < Blk<GPBO_FP32>::KS; ++kk)
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
-          Blk<GPBO_FP32>::mma_k(acc[0][ct], a0, bv[ct], kk);
-          Blk<GPBO_FP32>::mma_k(acc[1][ct], a1, bv[ct], kk);
+          Blk<GPBO_FP32>::mma_k(acc[0][ct], a0[q], bv[q][ct], kk);
+          Blk<GPBO_FP32>::mma_k(acc[1][ct], a1[q], bv[q][ct], kk);
         }
+    };
+    // Pairs of blocks per iteration, the loop body one basic block (a branch
+    // inside it would let the compiler sink each prefetch down to its use);
+    // an odd last block is multiplied after the loop from buffer 0.
+    load(0, 0);
+    int tj = 0;
+    for (; tj + 1 <= nlast; tj += 2) {
+      load(tj + 1, 1);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(0);
+      load(min(tj + 2, nlast), 0);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(1);
     }
+    if (tj <= nlast) mma(0);
   }
   // per candidate column: sum of squares over this wave's 32 rows
 #pragma unroll
@@ -136,8 +159,9 @@ __global__ void __launch_bounds__(256) k_trigemm(const float* __restrict__ khat,
     float v = 0.0f;
 #pragma unroll
     for (int r = 0; r < 2; ++r)
-      v += acc[r][ct][0] * acc[r][ct][0] + acc[r][ct][1] * acc[r][ct][1] +
-           acc[r][ct][2] * acc[r][ct][2] + acc[r][ct][3] * acc[r][ct][3];
+      if (r == 0 || has1)
+        v += acc[r][ct][0] * acc[r][ct][0] + acc[r][ct][1] * acc[r][ct][1] +
+             acc[r][ct][2] * acc[r][ct][2] + acc[r][ct][3] * acc[r][ct][3];
     v += __shfl_xor(v, 16);
     v += __shfl_xor(v, 32);
     if (lane < 16) red[wi][wc * 64 + ct * 16 + lane] = v;

@@ -138,6 +138,14 @@ def test_fit_nonfinite_and_invalid(ctx):
     with pytest.raises(G.GpboError) as e:
         G.fit(ctx, _t(X), _t(y), [0.5, -1.0, 0.5])
     assert e.value.status == G.E_INVALID_ARG
+    # a non-finite coordinate in a later 64-row block of X
+    X2 = np.random.default_rng(1).uniform(size=(200, 3))
+    X2[150, 1] = np.inf
+    with pytest.raises(G.GpboError) as e:
+        G.fit(ctx, _t(X2), _t(np.ones(200)), [0.5] * 3)
+    assert e.value.status == G.E_NONFINITE
+    X2[150, 1] = 0.5  # the same context fits a clean problem afterwards
+    G.fit(ctx, _t(X2), _t(np.arange(200.0)), [0.5] * 3).free()
 
 
 # ---------------------------------------------------------------------------
