@@ -51,6 +51,20 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return r;
 }
 
+// The same sum for a workgroup of NW waves.
+template <int NW>
+__device__ __forceinline__ double block_sum_w(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x / 64;
+  if (threadIdx.x % 64 == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) r += red[q];
+  __syncthreads();
+  return r;
+}
+
 __device__ __forceinline__ double block_min(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
   const int w = threadIdx.x / 64;
@@ -707,14 +721,18 @@ __global__ void __launch_bounds__(256) k_residual(const FitDesc* __restrict__ Ds
         red[0][row] + red[1][row] + red[2][row] + red[3][row];
 }
 
-// r = ytilde - sum_y part[y], its norm into stats[slot].
-__global__ void __launch_bounds__(256) k_res_finish(const FitDesc* __restrict__ Ds, int slot) {
-  __shared__ double red[256];
+// r = ytilde - sum_y part[y], its norm into stats[slot].  One workgroup of
+// 16 waves per problem (the partial columns of a row are summed by its
+// thread).
+constexpr int RESF_W = 16;
+__global__ void __launch_bounds__(64 * RESF_W) k_res_finish(const FitDesc* __restrict__ Ds,
+                                                            int slot) {
+  __shared__ double red[RESF_W];
   const FitDesc& P = Ds[blockIdx.z];
   if (fit_failed(P.info)) return;
   double* r = P.work + (int64_t)V_R * P.npad;
   double q = 0.0;
-  for (int i = threadIdx.x; i < P.npad; i += 256) {
+  for (int i = threadIdx.x; i < P.npad; i += 64 * RESF_W) {
     double v = 0.0;
     if (i < P.n) {
       double kv = 0.0;
@@ -724,7 +742,7 @@ __global__ void __launch_bounds__(256) k_res_finish(const FitDesc* __restrict__ 
     r[i] = v;
     q += v * v;
   }
-  q = block_sum(q, red);
+  q = block_sum_w<RESF_W>(q, red);
   if (threadIdx.x == 0) P.stats[slot] = sqrt(q);
 }
 
@@ -833,12 +851,12 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(64 * TRMV_T_WAVES), 0, s, dd, (int)V_W, -2);
   const dim3 g_res((unsigned)ceil_div(nmax, NB), (unsigned)chmax, Bz);
   hipLaunchKernelGGL(k_residual, g_res, dim3(256), 0, s, dd);
-  hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(256), 0, s, dd, (int)S_RES0);
+  hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(64 * RESF_W), 0, s, dd, (int)S_RES0);
   hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, (int)V_R, (int)V_W);
   hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(64 * TRMV_T_WAVES), 0, s, dd, (int)V_W, (int)V_D);
   hipLaunchKernelGGL(k_add_delta, dim3(1, 1, Bz), dim3(256), 0, s, dd);
   hipLaunchKernelGGL(k_residual, g_res, dim3(256), 0, s, dd);
-  hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(256), 0, s, dd, (int)S_RES1);
+  hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(64 * RESF_W), 0, s, dd, (int)S_RES1);
   hipLaunchKernelGGL(k_lml, dim3(1, 1, Bz), dim3(256), 0, s, dd);
 }
 

@@ -25,7 +25,7 @@ namespace {
 
 constexpr int KS_CG = 32;    // candidates per k_kstar workgroup
 constexpr int KS_J = 256;    // training points per k_kstar workgroup
-constexpr int GM_I = 64;     // inverse-factor rows per GEMM workgroup
+constexpr int GM_I = 128;    // inverse-factor rows per GEMM workgroup (8 row tiles)
 constexpr int GM_C = 128;    // candidates per GEMM workgroup
 
 template <int KERN>
@@ -82,76 +82,91 @@ __global__ void __launch_bounds__(256) k_kstar(int n, int d, int npj, int nx,
     mu_part[(int64_t)blockIdx.y * mc_pad + cl0 + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
 }
 
-// Triangular product with sum-of-squares epilogue.  Workgroup: 64 rows of
-// the inverse factor (four 16-row tiles) x 128 candidates; wave (wi, wc)
-// owns row tiles 2wi, 2wi+1 of the block and candidates 64wc .. 64wc+63.
-__global__ void __launch_bounds__(256) k_trigemm(const float* __restrict__ khat, int ldk,
-                                                 const float* __restrict__ pk,
-                                                 const int64_t* __restrict__ pk_off, int ntiles,
-                                                 int nib, int ncb, float* __restrict__ ssq_part,
-                                                 int64_t mc_pad) {
-  __shared__ float red[2][GM_C];
-  const int lane = threadIdx.x % 64, wave = wave_id();
-  const int wi = wave / 2, wc = wave % 2;
+// Triangular product with sum-of-squares epilogue.  Workgroup: 128 rows of
+// the inverse factor (eight 16-row tiles) x 128 candidates, eight waves; wave
+// (wp, wc) owns row tiles 2wp, 2wp + 1 of the block and candidates
+// 64wc .. 64wc + 63.  Per 16-column block tj of the contraction, the eight
+// packed A blocks of the row tiles and the 128 x 16 khat block are staged in
+// LDS (each loaded from L2 once per workgroup, not once per wave), double
+// buffered: block tj + 1 is loaded from memory while the products of block
+// tj run from LDS, then stored, one barrier per block.
+constexpr int TG_W = 8;          // waves per workgroup
+constexpr int TG_LDB = 20;       // LDS row stride (floats) of a staged khat row: 16 + 4 (banks)
+__global__ void __launch_bounds__(64 * TG_W) k_trigemm(const float* __restrict__ khat, int ldk,
+                                                       const float* __restrict__ pk,
+                                                       const int64_t* __restrict__ pk_off,
+                                                       int ntiles, int nib, int ncb,
+                                                       float* __restrict__ ssq_part,
+                                                       int64_t mc_pad) {
+  __shared__ __align__(16) float as[2][8][256];       // packed A blocks, lane order
+  __shared__ __align__(16) float bs[2][GM_C][TG_LDB];  // khat rows of the block
+  __shared__ float red[4][GM_C];
+  const int t = threadIdx.x, lane = t % 64, wave = wave_id();
+  const int wp = wave / 2, wc = wave % 2;
   // XCD-aware order: workgroup b runs on XCD b % 8; all row blocks of one
   // candidate block share an XCD, heaviest row blocks first.
   const int b = blockIdx.x;
   const int xcd = b % 8, local = b / 8;
   const int cb = (local / nib) * 8 + xcd;
   const int I = nib - 1 - local % nib;
-  if (cb >= ncb) return;
-  const int ti0 = I * 4 + wi * 2, ti1 = ti0 + 1;
-  const int64_t cbase = (int64_t)cb * GM_C + wc * 64;
+  if (cb >= ncb) return;  // whole workgroup: no barrier is skipped by part of it
+  const int tlast = min(I * 8 + 7, ntiles - 1);  // last column block any row of the block needs
+  const int ti0 = I * 8 + 2 * wp, ti1 = ti0 + 1;
+  const bool has0 = ti0 < ntiles, has1 = ti1 < ntiles;
+  const int nl = has1 ? ti1 : ti0;  // this wave's last column block
+  // staging roles: A -- tile sr = t / 64 of the block, lane sl = t % 64;
+  // B -- candidate row t / 4, quarter t % 4 of the 16 columns
+  const int sr = t / 64, sti = I * 8 + sr;
+  const float* ap = pk + (sti < ntiles ? pk_off[sti] * 256 : 0) + lane * 4;
+  const float* bp = khat + ((int64_t)cb * GM_C + t / 4) * ldk + 4 * (t % 4);
+  auto fetch = [&](int tj, f4& av, f4& bv) {
+    av = (sti < ntiles && tj <= sti) ? *(const f4*)(ap + (int64_t)tj * 256) : f4{0, 0, 0, 0};
+    bv = *(const f4*)(bp + tj * 16);
+  };
+  auto stage = [&](int q, const f4& av, const f4& bv) {
+    *(f4*)&as[q][sr][lane * 4] = av;
+    *(f4*)&bs[q][t / 4][4 * (t % 4)] = bv;
+  };
   f4 acc[2][4];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[r][ct] = f4{0, 0, 0, 0};
-  const bool has1 = ti1 < ntiles;  // without it acc[1] is computed but not used
-  if (ti0 < ntiles) {
-    const float* a0p = pk + pk_off[ti0] * 256 + lane * 4;
-    const float* a1p = has1 ? pk + pk_off[ti1] * 256 + lane * 4 : a0p;
-    const int nlast = has1 ? ti1 : ti0;  // last column block needed
-    const float* bp = khat + (cbase + lane % 16) * ldk + 4 * (lane / 16);
-    // operands of column block tj in one of two register buffers; block
-    // tj + 1 goes to the other buffer before the products of block tj, so its
-    // loads are in flight meanwhile.  The loads are unconditional (no branch
-    // for the wait counters to merge over): row tile ti0's stored blocks are
-    // padded with zero blocks up to an even count, so its block ti0 + 1 is a
-    // zero block, and the prefetch past the last block re-reads the last one.
-    f4 a0[2], a1[2], bv[2][4];
-    auto load = [&](int tj, int q) {
-      a0[q] = *(const f4*)(a0p + tj * 256);
-      a1[q] = *(const f4*)(a1p + tj * 256);
+  // products of block tj from buffer q (step-major: consecutive matrix-core
+  // instructions update different accumulators)
+  auto mma = [&](int q) {
+    const f4 a0 = *(const f4*)&as[q][2 * wp][lane * 4];
+    const f4 a1 = *(const f4*)&as[q][2 * wp + 1][lane * 4];
+    f4 bv[4];
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct)
-        bv[q][ct] = *(const f4*)(bp + (int64_t)ct * 16 * ldk + tj * 16);
-    };
-    // step-major: consecutive matrix-core instructions update different
-    // accumulators
-    auto mma = [&](int q) {
+    for (int ct = 0; ct < 4; ++ct)
+      bv[ct] = *(const f4*)&bs[q][wc * 64 + ct * 16 + lane % 16][4 * (lane / 16)];
 #pragma unroll
-      for (int kk = 0; kk < Blk<GPBO_FP32>::KS; ++kk)
+    for (int kk = 0; kk < Blk<GPBO_FP32>::KS; ++kk)
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-          Blk<GPBO_FP32>::mma_k(acc[0][ct], a0[q], bv[q][ct], kk);
-          Blk<GPBO_FP32>::mma_k(acc[1][ct], a1[q], bv[q][ct], kk);
-        }
-    };
-    // Pairs of blocks per iteration, the loop body one basic block (a branch
-    // inside it would let the compiler sink each prefetch down to its use);
-    // an odd last block is multiplied after the loop from buffer 0.
-    load(0, 0);
-    int tj = 0;
-    for (; tj + 1 <= nlast; tj += 2) {
-      load(tj + 1, 1);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(0);
-      load(min(tj + 2, nlast), 0);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(1);
-    }
-    if (tj <= nlast) mma(0);
+      for (int ct = 0; ct < 4; ++ct) {
+        Blk<GPBO_FP32>::mma_k(acc[0][ct], a0, bv[ct], kk);
+        Blk<GPBO_FP32>::mma_k(acc[1][ct], a1, bv[ct], kk);
+      }
+  };
+  {
+    f4 av, bv;
+    fetch(0, av, bv);
+    stage(0, av, bv);
+  }
+  __syncthreads();
+  // two blocks per iteration so the buffer index is a constant
+  for (int tj = 0; tj <= tlast; tj += 2) {
+    f4 av, bv;
+    if (tj + 1 <= tlast) fetch(tj + 1, av, bv);
+    if (has0 && tj <= nl) mma(0);
+    if (tj + 1 > tlast) break;
+    stage(1, av, bv);
+    __syncthreads();
+    if (tj + 2 <= tlast) fetch(tj + 2, av, bv);
+    if (has0 && tj + 1 <= nl) mma(1);
+    if (tj + 2 <= tlast) stage(0, av, bv);
+    __syncthreads();
   }
   // per candidate column: sum of squares over this wave's 32 rows
 #pragma unroll
@@ -159,17 +174,18 @@ __global__ void __launch_bounds__(256) k_trigemm(const float* __restrict__ khat,
     float v = 0.0f;
 #pragma unroll
     for (int r = 0; r < 2; ++r)
-      if (r == 0 || has1)
+      if (r == 0 ? has0 : has1)
         v += acc[r][ct][0] * acc[r][ct][0] + acc[r][ct][1] * acc[r][ct][1] +
              acc[r][ct][2] * acc[r][ct][2] + acc[r][ct][3] * acc[r][ct][3];
     v += __shfl_xor(v, 16);
     v += __shfl_xor(v, 32);
-    if (lane < 16) red[wi][wc * 64 + ct * 16 + lane] = v;
+    if (lane < 16) red[wp][wc * 64 + ct * 16 + lane] = v;
   }
   __syncthreads();
-  if (threadIdx.x < GM_C) {
-    const int64_t c = (int64_t)cb * GM_C + threadIdx.x;
-    if (c < mc_pad) ssq_part[(int64_t)I * mc_pad + c] = red[0][threadIdx.x] + red[1][threadIdx.x];
+  if (t < GM_C) {
+    const int64_t c = (int64_t)cb * GM_C + t;
+    if (c < mc_pad)
+      ssq_part[(int64_t)I * mc_pad + c] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
   }
 }
 
@@ -226,7 +242,7 @@ int64_t large_chunk(int npj, int64_t m) {
 // Scratch bytes and argmax partial count of the large path for m candidates.
 size_t large_scratch_bytes(int n, int npj, int64_t m) {
   const int64_t mc = large_chunk(npj, m);
-  const int njb = (int)ceil_div(npj, KS_J), nib = (int)ceil_div(round_up(n, 16) / 16, 4);
+  const int njb = (int)ceil_div(npj, KS_J), nib = (int)ceil_div(round_up(n, 16) / 16, GM_I / 16);
   return (size_t)mc * npj * 4 + (size_t)(njb + nib) * mc * 4 + 256;
 }
 // Exactly the number of partials the launch sequence writes (one per
@@ -243,7 +259,7 @@ void launch_score_large(const ScoreArgs& a, void* scratch, hipStream_t s,
   const int64_t mc = large_chunk(npj, m);
   const int njb = (int)ceil_div(npj, KS_J);
   const int ntiles = (int)round_up(n, 16) / 16;
-  const int nib = (int)ceil_div(ntiles, 4);
+  const int nib = (int)ceil_div(ntiles, GM_I / 16);
   float* khat = (float*)scratch;
   float* mu_part = khat + (size_t)mc * npj;
   float* ssq_part = mu_part + (size_t)njb * mc;
@@ -263,7 +279,7 @@ void launch_score_large(const ScoreArgs& a, void* scratch, hipStream_t s,
     const int ncb = (int)(mc_pad / GM_C);
     const int nwg = (int)round_up(ncb, 8) * nib;  // XCD-aware order pads to whole groups of 8
     mark(0);
-    hipLaunchKernelGGL(k_trigemm, dim3(nwg), dim3(256), 0, s, khat, npj, (const float*)a.pk,
+    hipLaunchKernelGGL(k_trigemm, dim3(nwg), dim3(64 * TG_W), 0, s, khat, npj, (const float*)a.pk,
                        a.pk_off, ntiles, nib, ncb, ssq_part, mc_pad);
     mark(1);
     const int nfb = (int)ceil_div(mcur, 256);
