@@ -85,21 +85,25 @@ __global__ void __launch_bounds__(256) k_kstar(int n, int d, int npj, int nx,
 // Triangular product with sum-of-squares epilogue.  Workgroup: 128 rows of
 // the inverse factor (eight 16-row tiles) x 128 candidates, eight waves; wave
 // (wp, wc) owns row tiles 2wp, 2wp + 1 of the block and candidates
-// 64wc .. 64wc + 63.  Per 16-column block tj of the contraction, the eight
-// packed A blocks of the row tiles and the 128 x 16 khat block are staged in
-// LDS (each loaded from L2 once per workgroup, not once per wave), double
-// buffered: block tj + 1 is loaded from memory while the products of block
-// tj run from LDS, then stored, one barrier per block.
+// 64wc .. 64wc + 63.  Per stage of two 16-column blocks of the contraction,
+// the packed A blocks of the eight row tiles and the 128 x 32 khat block are
+// staged in LDS (each loaded from L2 once per workgroup, not once per wave),
+// double buffered: stage s + 1 is loaded from memory while the products of
+// stage s run from LDS, then stored, one barrier per stage.
 constexpr int TG_W = 8;          // waves per workgroup
-constexpr int TG_LDB = 20;       // LDS row stride (floats) of a staged khat row: 16 + 4 (banks)
+constexpr int TG_LDB = 36;       // LDS row stride (floats) of a staged khat row: 32 + 4 (banks)
+constexpr int TG_AS = 2 * 8 * 2 * 256;        // floats of staged A: [stage][tile][block][256]
+constexpr int TG_BS = 2 * GM_C * TG_LDB;      // floats of staged khat: [stage][cand][TG_LDB]
+constexpr size_t TG_LDS = (size_t)(TG_AS + TG_BS) * sizeof(float);
 __global__ void __launch_bounds__(64 * TG_W) k_trigemm(const float* __restrict__ khat, int ldk,
                                                        const float* __restrict__ pk,
                                                        const int64_t* __restrict__ pk_off,
                                                        int ntiles, int nib, int ncb,
                                                        float* __restrict__ ssq_part,
                                                        int64_t mc_pad) {
-  __shared__ __align__(16) float as[2][8][256];       // packed A blocks, lane order
-  __shared__ __align__(16) float bs[2][GM_C][TG_LDB];  // khat rows of the block
+  extern __shared__ __align__(16) float tg_lds[];
+  float* as = tg_lds;           // [2][8][2][256]
+  float* bs = tg_lds + TG_AS;   // [2][GM_C][TG_LDB]
   __shared__ float red[4][GM_C];
   const int t = threadIdx.x, lane = t % 64, wave = wave_id();
   const int wp = wave / 2, wc = wave % 2;
@@ -114,33 +118,44 @@ __global__ void __launch_bounds__(64 * TG_W) k_trigemm(const float* __restrict__
   const int ti0 = I * 8 + 2 * wp, ti1 = ti0 + 1;
   const bool has0 = ti0 < ntiles, has1 = ti1 < ntiles;
   const int nl = has1 ? ti1 : ti0;  // this wave's last column block
-  // staging roles: A -- tile sr = t / 64 of the block, lane sl = t % 64;
-  // B -- candidate row t / 4, quarter t % 4 of the 16 columns
+  // staging roles: A -- tile sr = t / 64 of the block, lane t % 64, both
+  // blocks of the stage; khat -- candidate row t / 4, columns 4(t % 4) of
+  // each of the two blocks
   const int sr = t / 64, sti = I * 8 + sr;
   const float* ap = pk + (sti < ntiles ? pk_off[sti] * 256 : 0) + lane * 4;
   const float* bp = khat + ((int64_t)cb * GM_C + t / 4) * ldk + 4 * (t % 4);
-  auto fetch = [&](int tj, f4& av, f4& bv) {
-    av = (sti < ntiles && tj <= sti) ? *(const f4*)(ap + (int64_t)tj * 256) : f4{0, 0, 0, 0};
-    bv = *(const f4*)(bp + tj * 16);
+  const f4 zero = {0, 0, 0, 0};
+  // blocks past a tile's own (and khat blocks past the last) are zeros
+  auto fetch = [&](int tj, f4 (&av)[2], f4 (&bv)[2]) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int bj = tj + u;
+      av[u] = (sti < ntiles && bj <= sti) ? *(const f4*)(ap + (int64_t)bj * 256) : zero;
+      bv[u] = bj <= tlast ? *(const f4*)(bp + bj * 16) : zero;
+    }
   };
-  auto stage = [&](int q, const f4& av, const f4& bv) {
-    *(f4*)&as[q][sr][lane * 4] = av;
-    *(f4*)&bs[q][t / 4][4 * (t % 4)] = bv;
+  auto stage = [&](int q, const f4 (&av)[2], const f4 (&bv)[2]) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      *(f4*)&as[((q * 8 + sr) * 2 + u) * 256 + lane * 4] = av[u];
+      *(f4*)&bs[(q * GM_C + t / 4) * TG_LDB + 16 * u + 4 * (t % 4)] = bv[u];
+    }
   };
   f4 acc[2][4];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) acc[r][ct] = f4{0, 0, 0, 0};
-  // products of block tj from buffer q (step-major: consecutive matrix-core
-  // instructions update different accumulators)
-  auto mma = [&](int q) {
-    const f4 a0 = *(const f4*)&as[q][2 * wp][lane * 4];
-    const f4 a1 = *(const f4*)&as[q][2 * wp + 1][lane * 4];
+    for (int ct = 0; ct < 4; ++ct) acc[r][ct] = zero;
+  // products of block u of the stage in buffer q (step-major: consecutive
+  // matrix-core instructions update different accumulators)
+  auto mma = [&](int q, int u) {
+    const f4 a0 = *(const f4*)&as[((q * 8 + 2 * wp) * 2 + u) * 256 + lane * 4];
+    const f4 a1 = *(const f4*)&as[((q * 8 + 2 * wp + 1) * 2 + u) * 256 + lane * 4];
     f4 bv[4];
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct)
-      bv[ct] = *(const f4*)&bs[q][wc * 64 + ct * 16 + lane % 16][4 * (lane / 16)];
+      bv[ct] = *(const f4*)&bs[(q * GM_C + wc * 64 + ct * 16 + lane % 16) * TG_LDB + 16 * u +
+                               4 * (lane / 16)];
 #pragma unroll
     for (int kk = 0; kk < Blk<GPBO_FP32>::KS; ++kk)
 #pragma unroll
@@ -149,23 +164,27 @@ __global__ void __launch_bounds__(64 * TG_W) k_trigemm(const float* __restrict__
         Blk<GPBO_FP32>::mma_k(acc[1][ct], a1, bv[ct], kk);
       }
   };
+  auto mma_stage = [&](int q, int tj) {
+    if (has0 && tj <= nl) mma(q, 0);
+    if (has0 && tj + 1 <= nl) mma(q, 1);
+  };
   {
-    f4 av, bv;
+    f4 av[2], bv[2];
     fetch(0, av, bv);
     stage(0, av, bv);
   }
   __syncthreads();
-  // two blocks per iteration so the buffer index is a constant
-  for (int tj = 0; tj <= tlast; tj += 2) {
-    f4 av, bv;
-    if (tj + 1 <= tlast) fetch(tj + 1, av, bv);
-    if (has0 && tj <= nl) mma(0);
-    if (tj + 1 > tlast) break;
+  // two stages (four blocks) per iteration so the buffer index is a constant
+  for (int tj = 0; tj <= tlast; tj += 4) {
+    f4 av[2], bv[2];
+    if (tj + 2 <= tlast) fetch(tj + 2, av, bv);
+    mma_stage(0, tj);
+    if (tj + 2 > tlast) break;
     stage(1, av, bv);
     __syncthreads();
-    if (tj + 2 <= tlast) fetch(tj + 2, av, bv);
-    if (has0 && tj + 1 <= nl) mma(1);
-    if (tj + 2 <= tlast) stage(0, av, bv);
+    if (tj + 4 <= tlast) fetch(tj + 4, av, bv);
+    mma_stage(1, tj + 2);
+    if (tj + 4 <= tlast) stage(0, av, bv);
     __syncthreads();
   }
   // per candidate column: sum of squares over this wave's 32 rows
@@ -279,7 +298,12 @@ void launch_score_large(const ScoreArgs& a, void* scratch, hipStream_t s,
     const int ncb = (int)(mc_pad / GM_C);
     const int nwg = (int)round_up(ncb, 8) * nib;  // XCD-aware order pads to whole groups of 8
     mark(0);
-    hipLaunchKernelGGL(k_trigemm, dim3(nwg), dim3(64 * TG_W), 0, s, khat, npj, (const float*)a.pk,
+    static const bool lds_set = [] {
+      return hipFuncSetAttribute((const void*)k_trigemm, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)TG_LDS) == hipSuccess;
+    }();
+    (void)lds_set;
+    hipLaunchKernelGGL(k_trigemm, dim3(nwg), dim3(64 * TG_W), TG_LDS, s, khat, npj, (const float*)a.pk,
                        a.pk_off, ntiles, nib, ncb, ssq_part, mc_pad);
     mark(1);
     const int nfb = (int)ceil_div(mcur, 256);

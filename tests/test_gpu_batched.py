@@ -206,6 +206,8 @@ def test_batched_full_c3_shape_smoke(ctx):
     assert st == G.OK
     Xcs = [_t(p.Xc, torch.float32) for p in probs]
     for prec in ("bf16", "fp32"):
+        # the second precision reuses the scaled observations built by the
+        # first and adds only its own packed operand
         eis, am, emax = G.score_batched(ctx, models, Xcs, prec)
         torch.cuda.synchronize()
         am = am.cpu().numpy()
@@ -214,5 +216,9 @@ def test_batched_full_c3_shape_smoke(ctx):
         for b in (0, 17, 63):
             e = eis[b].double().cpu().numpy()
             assert np.isfinite(e).all() and e[am[b]] == e.max()
+            single = G.score(ctx, models[b], Xcs[b], prec)
+            torch.cuda.synchronize()
+            scale = float(single["mu"].abs().max()) + float(single["sigma"].abs().max())
+            assert np.max(np.abs(e - single["ei"].double().cpu().numpy())) <= 1e-5 * scale, (prec, b)
     for mo in models:
         mo.free()
