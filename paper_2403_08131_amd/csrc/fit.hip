@@ -195,7 +195,11 @@ __global__ void __launch_bounds__(256) k_gram(const FitDesc* __restrict__ D) {
     }
     if (j > i) v = 0.0;
     P.L[(int64_t)i * npad + j] = v;
-    if (I != J) P.L[(int64_t)(J * NB + c) * npad + (I * NB + r)] = 0.0;
+    P.Linv[(int64_t)i * npad + j] = 0.0;  // the inverse factor starts from zero
+    if (I != J) {
+      P.L[(int64_t)(J * NB + c) * npad + (I * NB + r)] = 0.0;
+      P.Linv[(int64_t)(J * NB + c) * npad + (I * NB + r)] = 0.0;
+    }
   }
 }
 
@@ -592,15 +596,7 @@ __global__ void __launch_bounds__(256) k_chol_update(const FitDesc* __restrict__
   }
 }
 
-// Zero the inverse factor (and make the float32 copy when refining).
-__global__ void __launch_bounds__(256) k_zero_linv(const FitDesc* __restrict__ Ds) {
-  const FitDesc& P = Ds[blockIdx.z];
-  const int64_t cnt = (int64_t)P.npad * P.npad;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt;
-       i += (int64_t)gridDim.x * blockDim.x)
-    P.Linv[i] = 0.0;
-}
-
+// The float32 copy of the inverse factor (refinement only).
 __global__ void __launch_bounds__(256) k_cast_linv(const FitDesc* __restrict__ Ds) {
   const FitDesc& P = Ds[blockIdx.z];
   if (!P.refine || fit_failed(P.info)) return;
@@ -611,7 +607,7 @@ __global__ void __launch_bounds__(256) k_cast_linv(const FitDesc* __restrict__ D
 }
 
 // Vectors of the alpha solve, by index into the work area.
-enum { V_W = 0, V_R = 1, V_D = 2, V_PART = 4 };
+enum { V_W = 0, V_R = 1, V_PART = 4 };
 __device__ __forceinline__ double* wvec(const FitDesc& P, int v) {
   return v < 0 ? (v == -1 ? P.yt : P.alpha) : P.work + (int64_t)v * P.npad;
 }
@@ -650,8 +646,9 @@ __global__ void __launch_bounds__(256) k_trmv(const FitDesc* __restrict__ Ds, in
 // lanes of a wave reading the same row (one coalesced load), and combine in
 // LDS.
 constexpr int TRMV_T_WAVES = 16;
+// accumulate = 1: y += Linv^T x (the correction step of alpha).
 __global__ void __launch_bounds__(64 * TRMV_T_WAVES) k_trmv_t(const FitDesc* __restrict__ Ds,
-                                                              int xv, int yv) {
+                                                              int xv, int yv, int accumulate) {
   __shared__ double red[TRMV_T_WAVES][64];
   const FitDesc& P = Ds[blockIdx.z];
   if ((int)blockIdx.x * 64 >= P.npad || fit_failed(P.info)) return;
@@ -678,7 +675,7 @@ __global__ void __launch_bounds__(64 * TRMV_T_WAVES) k_trmv_t(const FitDesc* __r
     double t = 0.0;
 #pragma unroll
     for (int q = 0; q < TRMV_T_WAVES; ++q) t += red[q][lane];
-    y[j] = j < n ? t : 0.0;
+    y[j] = j < n ? (accumulate ? y[j] + t : t) : 0.0;
   }
 }
 
@@ -724,12 +721,27 @@ __global__ void __launch_bounds__(256) k_residual(const FitDesc* __restrict__ Ds
 // r = ytilde - sum_y part[y], its norm into stats[slot].  One workgroup of
 // 16 waves per problem (the partial columns of a row are summed by its
 // thread).
+// With lml = 1 it also writes the log marginal likelihood and log det K:
+// LML = -ytilde^T alpha / 2 - sum log L_ii - n/2 log 2 pi.
 constexpr int RESF_W = 16;
 __global__ void __launch_bounds__(64 * RESF_W) k_res_finish(const FitDesc* __restrict__ Ds,
-                                                            int slot) {
+                                                            int slot, int lml) {
   __shared__ double red[RESF_W];
   const FitDesc& P = Ds[blockIdx.z];
   if (fit_failed(P.info)) return;
+  if (lml) {
+    double q = 0.0, ld = 0.0;
+    for (int i = threadIdx.x; i < P.n; i += 64 * RESF_W) {
+      q += P.yt[i] * P.alpha[i];
+      ld += log(P.L[(int64_t)i * P.npad + i]);
+    }
+    q = block_sum_w<RESF_W>(q, red);
+    ld = block_sum_w<RESF_W>(ld, red);
+    if (threadIdx.x == 0) {
+      P.stats[S_LOGDET] = 2.0 * ld;
+      P.stats[S_LML] = -0.5 * q - ld - 0.5 * P.n * log(2.0 * 3.14159265358979323846);
+    }
+  }
   double* r = P.work + (int64_t)V_R * P.npad;
   double q = 0.0;
   for (int i = threadIdx.x; i < P.npad; i += 64 * RESF_W) {
@@ -744,31 +756,6 @@ __global__ void __launch_bounds__(64 * RESF_W) k_res_finish(const FitDesc* __res
   }
   q = block_sum_w<RESF_W>(q, red);
   if (threadIdx.x == 0) P.stats[slot] = sqrt(q);
-}
-
-// alpha += delta.
-__global__ void __launch_bounds__(256) k_add_delta(const FitDesc* __restrict__ Ds) {
-  const FitDesc& P = Ds[blockIdx.z];
-  if (fit_failed(P.info)) return;
-  const double* dl = P.work + (int64_t)V_D * P.npad;
-  for (int i = threadIdx.x; i < P.n; i += 256) P.alpha[i] += dl[i];
-}
-
-__global__ void __launch_bounds__(256) k_lml(const FitDesc* __restrict__ Ds) {
-  __shared__ double red[256];
-  const FitDesc& P = Ds[blockIdx.z];
-  if (fit_failed(P.info)) return;
-  double q = 0.0, ld = 0.0;
-  for (int i = threadIdx.x; i < P.n; i += 256) {
-    q += P.yt[i] * P.alpha[i];
-    ld += log(P.L[(int64_t)i * P.npad + i]);
-  }
-  q = block_sum(q, red);
-  ld = block_sum(ld, red);
-  if (threadIdx.x == 0) {
-    P.stats[S_LOGDET] = 2.0 * ld;
-    P.stats[S_LML] = -0.5 * q - ld - 0.5 * P.n * log(2.0 * 3.14159265358979323846);
-  }
 }
 
 // The two-tile kernels stage 2 x 64 x 66 doubles (66 KiB) of dynamic LDS.
@@ -829,7 +816,6 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   hipLaunchKernelGGL(k_fit_stats, dim3(1, 1, Bz), dim3(256), 0, s, dd);
   hipLaunchKernelGGL(k_gram, dim3(nbmax * (nbmax + 1) / 2, 1, Bz), dim3(256), 0, s, dd);
   const unsigned gz = (unsigned)std::min<int64_t>(1024, ceil_div(npmax * npmax, 256));
-  hipLaunchKernelGGL(k_zero_linv, dim3(gz, 1, Bz), dim3(256), 0, s, dd);
   // step k: diagonal tile k; panel k with row multiply of inverse step k-1;
   // trailing update k with the update of inverse step k-1; step nbmax
   // finishes the inverse
@@ -844,20 +830,21 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
     if (nupd + ntri > 0)
       hipLaunchKernelGGL(k_chol_update, dim3(nupd + ntri, 1, Bz), dim3(256), sm2, s, dd, k, nupd);
   }
-  hipLaunchKernelGGL(k_cast_linv, dim3(gz, 1, Bz), dim3(256), 0, s, dd);
+  bool any_refine = false;
+  for (int b = 0; b < B; ++b) any_refine |= h[b].refine != 0;
+  if (any_refine) hipLaunchKernelGGL(k_cast_linv, dim3(gz, 1, Bz), dim3(256), 0, s, dd);
   const unsigned g_rows = (unsigned)ceil_div(npmax, 4), g_cols = (unsigned)ceil_div(npmax, 64);
   // alpha = Linv^T (Linv ytilde), then one residual-and-correction step
   hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, -1, (int)V_W);
-  hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(64 * TRMV_T_WAVES), 0, s, dd, (int)V_W, -2);
+  hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(64 * TRMV_T_WAVES), 0, s, dd, (int)V_W, -2, 0);
   const dim3 g_res((unsigned)ceil_div(nmax, NB), (unsigned)chmax, Bz);
   hipLaunchKernelGGL(k_residual, g_res, dim3(256), 0, s, dd);
-  hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(64 * RESF_W), 0, s, dd, (int)S_RES0);
+  hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(64 * RESF_W), 0, s, dd, (int)S_RES0, 0);
   hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, (int)V_R, (int)V_W);
-  hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(64 * TRMV_T_WAVES), 0, s, dd, (int)V_W, (int)V_D);
-  hipLaunchKernelGGL(k_add_delta, dim3(1, 1, Bz), dim3(256), 0, s, dd);
+  // alpha += Linv^T (Linv r)
+  hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(64 * TRMV_T_WAVES), 0, s, dd, (int)V_W, -2, 1);
   hipLaunchKernelGGL(k_residual, g_res, dim3(256), 0, s, dd);
-  hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(64 * RESF_W), 0, s, dd, (int)S_RES1);
-  hipLaunchKernelGGL(k_lml, dim3(1, 1, Bz), dim3(256), 0, s, dd);
+  hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(64 * RESF_W), 0, s, dd, (int)S_RES1, 1);
 }
 
 }  // namespace gpbo

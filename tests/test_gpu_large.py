@@ -91,6 +91,27 @@ def test_large_path_matches_oracle_and_fused(ctx, n, m_cand):
     m.free()
 
 
+def test_large_path_matern(ctx):
+    """The Matern-5/2 kernel on the large path (forced at a ragged n) against
+    the oracle and the fused path."""
+    import dataclasses
+    p = I.make_config("c5-s", n=333, m=2500, d=7)
+    p = dataclasses.replace(p, kernel=I.KERNEL_MATERN52)
+    f, m = _fit_both(ctx, p, refine=False)
+    ref = O.score(f, p.Xc)
+    Xc = _t(p.Xc, torch.float32)
+    for path in ("large", "fused"):
+        print(f"large-path Matern n={p.n} m={p.m} path={path}", flush=True)
+        ctx.set_score_path(path)
+        out = G.score(ctx, m, Xc, "fp32")
+        e_mu, e_sg, e_ei = _errors(ref, out, f, p.signal_var)
+        print(f"  {path}: e_mu={e_mu:.3e} e_sigma={e_sg:.3e} e_ei={e_ei:.3e}")
+        assert e_mu <= TOL and e_sg <= TOL, (path, e_mu, e_sg)
+        _check_argmax(ref["ei"], int(out["argmax"].item()), TOL)
+    ctx.set_score_path("auto")
+    m.free()
+
+
 def test_large_path_rejects_other_precisions(ctx):
     p = I.make_config("c5-s", n=64, m=10, d=5)
     _, m = _fit_both(ctx, p, refine=False)
