@@ -168,6 +168,21 @@ gpbo_status gpbo_ctx_set_score_path(gpbo_ctx ctx, gpbo_score_path path);
 gpbo_status gpbo_fit(gpbo_ctx ctx, const gpbo_problem* prob, gpbo_model* out, double* lml,
                      int32_t* bad_pivot);
 
+/* The same fit without the synchronisation: the work is queued on the
+ * context's stream and *out receives the model at once, so a Bayesian-
+ * optimisation step can queue the fit and the scoring of the next pool back
+ * to back and synchronise once.  The factorisation's status is not known
+ * yet: gpbo_model_status (which synchronises the stream) returns GPBO_OK,
+ * GPBO_E_NOT_PD (with *bad_pivot) or GPBO_E_NONFINITE, and *lml (host, may be
+ * NULL).  Scores of a model whose status is not GPBO_OK are undefined.
+ * Unlike gpbo_fit, the caller's X and y are read by the queued work: they
+ * must stay allocated and unchanged until the stream has run the fit (for
+ * instance until gpbo_model_status returns).
+ * Returns GPBO_E_INVALID_ARG / GPBO_E_UNSUPPORTED / GPBO_E_OOM as gpbo_fit
+ * does for problems rejected before any work is queued. */
+gpbo_status gpbo_fit_async(gpbo_ctx ctx, const gpbo_problem* prob, gpbo_model* out);
+gpbo_status gpbo_model_status(gpbo_ctx ctx, gpbo_model model, int32_t* bad_pivot, double* lml);
+
 /* Fit B independent sub-searches (Sec. IV-D runs them in parallel).  Problems
  * of different n and d are factored together, largest first.  SYNCHRONISES
  * once.  status (host, B) receives each problem's status; lml (host, B) may be

@@ -114,7 +114,8 @@ static_assert(S_COUNT * sizeof(double) + 2 * sizeof(int) <= STATUS_SLOT, "status
 // statistics.  status[b] receives each problem's result; on return the
 // stream is synchronised.  Models whose status is not OK still hold their
 // buffers (the caller frees them).
-gpbo_status fit_group(Ctx* c, int B, const gpbo_problem* probs, Model* const* ms, int32_t* status) {
+gpbo_status fit_group(Ctx* c, int B, const gpbo_problem* probs, Model* const* ms, int32_t* status,
+                      bool sync = true) {
   std::vector<int> order;  // problems to fit, by decreasing n
   for (int b = 0; b < B; ++b)
     if (ms[b] && status[b] == GPBO_OK) order.push_back(b);
@@ -190,6 +191,11 @@ gpbo_status fit_group(Ctx* c, int B, const gpbo_problem* probs, Model* const* ms
   // a copy from pageable memory has consumed its source when it returns
   HIP_TRY(c, hipMemcpyAsync(c->desc_buf, up.data(), up_bytes, hipMemcpyHostToDevice, c->stream));
   launch_fit(hd.data(), (const FitDesc*)c->desc_buf, nb, c->stream);
+  if (!sync) {  // the statistics are read when the caller asks for the status
+    for (int k = 0; k < nb; ++k) ms[order[k]]->pending = true;
+    HIP_TRY(c, hipGetLastError());
+    return GPBO_OK;
+  }
   std::vector<unsigned char> st_h(nb * STATUS_SLOT);
   HIP_TRY(c, hipMemcpyAsync(st_h.data(), g + ostat, st_h.size(), hipMemcpyDeviceToHost, c->stream));
   hipError_t e = hipStreamSynchronize(c->stream);
@@ -211,6 +217,19 @@ gpbo_status fit_status(Ctx* c, Model* M, int32_t* bad_pivot) {
     return fail(c, GPBO_E_NOT_PD, "K is not positive definite: pivot %d", M->host_info[0]);
   }
   if (bad_pivot) *bad_pivot = -1;
+  return GPBO_OK;
+}
+
+// Read the statistics and status of an asynchronously fitted model
+// (synchronises the context's stream).
+gpbo_status resolve_pending(Ctx* c, Model* M) {
+  if (!M->pending) return GPBO_OK;
+  HIP_TRY(c, hipMemcpyAsync(M->host_stats, M->stats, sizeof M->host_stats, hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(M->host_info, M->info, sizeof M->host_info, hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  M->pending = false;
   return GPBO_OK;
 }
 
@@ -399,6 +418,40 @@ gpbo_status gpbo_fit(gpbo_ctx c, const gpbo_problem* p, gpbo_model* out, double*
   return GPBO_OK;
 }
 
+gpbo_status gpbo_fit_async(gpbo_ctx c, const gpbo_problem* p, gpbo_model* out) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (!out) return fail(c, GPBO_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  gpbo_status st = check_problem(c, p);
+  if (st != GPBO_OK) return st;
+  DeviceGuard g(c->device);
+  gpbo_model M = new (std::nothrow) gpbo_model_s();
+  if (!M) return fail(c, GPBO_E_OOM, "host allocation failed");
+  Model* ms[1] = {M};
+  int32_t status[1] = {GPBO_OK};
+  st = fit_group(c, 1, p, ms, status, false);
+  if (st == GPBO_OK) st = (gpbo_status)status[0];
+  if (st != GPBO_OK) {
+    (void)hipStreamSynchronize(c->stream);
+    free_model_buffers(M);
+    delete M;
+    return st;
+  }
+  c->live_models.insert(M);
+  *out = M;
+  return GPBO_OK;
+}
+
+gpbo_status gpbo_model_status(gpbo_ctx c, gpbo_model M, int32_t* bad_pivot, double* lml) {
+  if (!c || !M) return GPBO_E_INVALID_ARG;
+  DeviceGuard g(c->device);
+  gpbo_status st = resolve_pending(c, M);
+  if (st != GPBO_OK) return st;
+  st = fit_status(c, M, bad_pivot);
+  if (st == GPBO_OK && lml) *lml = M->host_stats[S_LML];
+  return st;
+}
+
 gpbo_status gpbo_fit_batched(gpbo_ctx c, int32_t B, const gpbo_problem* probs, gpbo_model* out,
                              double* lml, int32_t* status) {
   if (!c) return GPBO_E_INVALID_ARG;
@@ -448,6 +501,11 @@ gpbo_status gpbo_model_free(gpbo_model M) {
 
 gpbo_status gpbo_model_stats(gpbo_model M, double* stats) {
   if (!M || !stats) return GPBO_E_INVALID_ARG;
+  if (M->pending) {
+    DeviceGuard g(M->ctx->device);
+    gpbo_status st = resolve_pending(M->ctx, M);
+    if (st != GPBO_OK) return st;
+  }
   for (int i = 0; i < GPBO_NSTATS; ++i) stats[i] = M->host_stats[i];
   return GPBO_OK;
 }

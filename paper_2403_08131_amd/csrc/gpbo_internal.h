@@ -57,6 +57,7 @@ struct Model {
   int* info = nullptr;          // first failing pivot (INT32_MAX when none) + nonfinite flag
   double host_stats[S_COUNT] = {0};
   int host_info[2] = {0, 0};
+  bool pending = false;         // fitted asynchronously; host_stats / host_info not read yet
   // Score operands, built on first use per precision.
   int nx = 0;                   // row stride of Xs32 / Xs64 (n padded with far-away points)
   float* Xs32 = nullptr;        // d x nx, coordinates scaled for the float32 kernels

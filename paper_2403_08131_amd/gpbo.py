@@ -64,6 +64,9 @@ _SIGS = {
                            C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "gpbo_fit_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Problem), C.POINTER(C.c_void_p),
                                    C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "gpbo_fit_async": (C.c_int, [C.c_void_p, C.POINTER(Problem), C.POINTER(C.c_void_p)]),
+    "gpbo_model_status": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_double)]),
     "gpbo_model_free": (C.c_int, [C.c_void_p]),
     "gpbo_model_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "gpbo_model_shape": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
@@ -207,6 +210,18 @@ class Model:
         self.ctx.check(lib().gpbo_model_factors(self.ctx.h, self.h, _ptr(L), _ptr(Li), _ptr(a)))
         return L, Li, a
 
+    def status(self):
+        """gpbo_model_status: raises GpboError (with .bad_pivot on NOT_PD) if
+        the fit failed; returns the log marginal likelihood otherwise."""
+        bad = C.c_int32(-1)
+        lml = C.c_double()
+        st = lib().gpbo_model_status(self.ctx.h, self.h, C.byref(bad), C.byref(lml))
+        if st != OK:
+            err = GpboError(st, lib().gpbo_last_error(self.ctx.h).decode())
+            err.bad_pivot = bad.value
+            raise err
+        return lml.value
+
     def free(self):
         if self.h:
             lib().gpbo_model_free(self.h)
@@ -241,6 +256,18 @@ def fit(ctx: Context, X, y, lengthscale, kernel=KERNEL_SE, signal_var=1.0, noise
         err = GpboError(st, lib().gpbo_last_error(ctx.h).decode())
         err.bad_pivot = bad.value
         raise err
+    return Model(ctx, h, X.shape[0], X.shape[1])
+
+
+def fit_async(ctx: Context, X, y, lengthscale, kernel=KERNEL_SE, signal_var=1.0, noise_var=1e-4,
+              normalize_y=True, refine_alpha=False):
+    """gpbo_fit_async: queues the fit without synchronising and returns the
+    :class:`Model` at once; call ``Model.status()`` (which synchronises)
+    before trusting its scores.  X and y must stay unchanged until the stream
+    has run the fit."""
+    p, _keep = _problem(X, y, lengthscale, kernel, signal_var, noise_var, normalize_y, refine_alpha)
+    h = C.c_void_p()
+    ctx.check(lib().gpbo_fit_async(ctx.h, C.byref(p), C.byref(h)))
     return Model(ctx, h, X.shape[0], X.shape[1])
 
 

@@ -127,6 +127,41 @@ def test_fit_not_pd_reports_pivot(ctx):
     assert e.value.bad_pivot == f.bad_pivot == 2
 
 
+def test_fit_async_matches_fit_and_reports_status(ctx):
+    """gpbo_fit_async queues the same work as gpbo_fit: the scores of a model
+    fitted either way are bit-identical, its status and LML agree, and a
+    failing factorisation (or a non-finite y) is reported by the status call."""
+    p = I.make_config("c2-s", n=300, m=2000)
+    X, y = _t(p.X), _t(p.y)
+    Xc = _t(p.Xc, torch.float32)
+    ms = G.fit(ctx, X, y, p.lengthscale, p.kernel, p.signal_var, p.noise_var)
+    lml_sync = ms.stats()["lml"]
+    ref = G.score(ctx, ms, Xc, "fp32")
+    ma = G.fit_async(ctx, X, y, p.lengthscale, p.kernel, p.signal_var, p.noise_var)
+    out = G.score(ctx, ma, Xc, "fp32")  # queued behind the fit, no synchronisation between
+    assert ma.status() == lml_sync
+    torch.cuda.synchronize()
+    for k in ("mu", "sigma", "ei", "argmax"):
+        assert torch.equal(out[k], ref[k]), k
+    assert ma.stats()["lml"] == lml_sync
+    ms.free()
+    ma.free()
+    # NOT_PD: a repeated point without noise
+    Xb = np.array([[0.1, 0.2], [0.5, 0.9], [0.1, 0.2], [0.7, 0.3]])
+    yb = np.array([1.0, 2.0, 1.5, 0.3])
+    mb = G.fit_async(ctx, _t(Xb), _t(yb), [0.5, 0.5], G.KERNEL_SE, 1.0, 0.0)
+    with pytest.raises(G.GpboError) as e:
+        mb.status()
+    assert e.value.status == G.E_NOT_PD and e.value.bad_pivot == 2
+    mb.free()
+    yb[1] = np.nan
+    mn = G.fit_async(ctx, _t(Xb), _t(yb), [0.5, 0.5], G.KERNEL_SE, 1.0, 1e-4)
+    with pytest.raises(G.GpboError) as e:
+        mn.status()
+    assert e.value.status == G.E_NONFINITE
+    mn.free()
+
+
 def test_fit_nonfinite_and_invalid(ctx):
     X = np.random.default_rng(0).uniform(size=(10, 3))
     y = np.ones(10)
