@@ -270,10 +270,11 @@ def run_c3(args):
     """Batched independent sub-searches: three launches of 64 problems each
     (coupling lambda = 0, 0.1, 0.5, one per launch), d in {2..12}, n in
     [16, 400], 8192 candidates per problem.  One step fits all problems of a
-    launch (one float64 launch sequence) and scores all their pools with one
-    persistent BF16 matrix-core launch (replayed from its HIP graph: the
-    batch shape repeats from step to step), then reads the 64 argmaxes back;
-    three launches per step.  `value` = candidates scored per second of whole
+    launch (one float64 launch sequence, queued without synchronising) and
+    scores all their pools with one persistent BF16 matrix-core launch
+    (replayed from its HIP graph: the batch shape repeats from step to step),
+    for the three launches, then reads the 3 x 64 argmaxes back and checks
+    the fits' statuses.  `value` = candidates scored per second of whole
     steps.  The scoring kernel's own time is taken in a second pass with
     kernel timing on (eager launches bracketed by HIP events)."""
     import ctypes as C
@@ -308,18 +309,26 @@ def run_c3(args):
                                              C.c_void_p(bt["em"].data_ptr())))
 
     def step(keep=False):
-        picks, kept = [], []
+        # the three batched fits and scorings are queued back to back; one
+        # synchronisation reads the argmaxes, then the fits' statuses (one
+        # copy per batch)
+        kept = []
         for bt in batches:
-            st, models, status, _ = G.fit_batched(ctx, bt["specs"])
+            st, models, status, _ = G.fit_batched(ctx, bt["specs"], sync=False)
             if st != G.OK:
                 raise SystemExit(f"batched fit failed: {status}")
             launch(bt, models)
-            picks.append(bt["am"].cpu())  # the next configuration of every sub-search
-            if keep:
-                kept.append(models)
-            else:
+            kept.append(models)
+        picks = [bt["am"].cpu() for bt in batches]  # the next configuration of every sub-search
+        for models in kept:
+            st, status, _ = G.status_batched(ctx, models)
+            if st != G.OK:
+                raise SystemExit(f"batched fit failed: {status}")
+        if not keep:
+            for models in kept:
                 for mo in models:
                     mo.free()
+            kept = []
         return picks, kept
 
     for _ in range(args.warmup):

@@ -182,6 +182,17 @@ gpbo_status gpbo_fit(gpbo_ctx ctx, const gpbo_problem* prob, gpbo_model* out, do
  * does for problems rejected before any work is queued. */
 gpbo_status gpbo_fit_async(gpbo_ctx ctx, const gpbo_problem* prob, gpbo_model* out);
 gpbo_status gpbo_model_status(gpbo_ctx ctx, gpbo_model model, int32_t* bad_pivot, double* lml);
+/* gpbo_fit_batched without the synchronisation, in the same way: status[b]
+ * (host, B) reports only the checks made before any work is queued; the
+ * factorisation status of each model comes from gpbo_model_status (the first
+ * such call for a model of the batch reads the statuses of the whole batch
+ * with one copy). */
+gpbo_status gpbo_fit_batched_async(gpbo_ctx ctx, int32_t B, const gpbo_problem* probs,
+                                   gpbo_model* out, int32_t* status);
+/* gpbo_model_status of B models: status (host, B) and lml (host, B, may be
+ * NULL; NaN where the fit failed).  Returns the first failing status. */
+gpbo_status gpbo_model_status_batched(gpbo_ctx ctx, int32_t B, const gpbo_model* models,
+                                      int32_t* status, double* lml);
 
 /* Fit B independent sub-searches (Sec. IV-D runs them in parallel).  Problems
  * of different n and d are factored together, largest first.  SYNCHRONISES

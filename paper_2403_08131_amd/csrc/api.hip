@@ -191,8 +191,16 @@ gpbo_status fit_group(Ctx* c, int B, const gpbo_problem* probs, Model* const* ms
   // a copy from pageable memory has consumed its source when it returns
   HIP_TRY(c, hipMemcpyAsync(c->desc_buf, up.data(), up_bytes, hipMemcpyHostToDevice, c->stream));
   launch_fit(hd.data(), (const FitDesc*)c->desc_buf, nb, c->stream);
-  if (!sync) {  // the statistics are read when the caller asks for the status
-    for (int k = 0; k < nb; ++k) ms[order[k]]->pending = true;
+  if (!sync) {  // the statistics are read when the caller asks for a status
+    auto gs = std::make_shared<Model::GroupStatus>();
+    gs->dev = (const unsigned char*)(g + ostat);
+    gs->nb = nb;
+    for (int k = 0; k < nb; ++k) {
+      Model* M = ms[order[k]];
+      M->pending = true;
+      M->gstat = gs;
+      M->gslot = k;
+    }
     HIP_TRY(c, hipGetLastError());
     return GPBO_OK;
   }
@@ -224,12 +232,19 @@ gpbo_status fit_status(Ctx* c, Model* M, int32_t* bad_pivot) {
 // (synchronises the context's stream).
 gpbo_status resolve_pending(Ctx* c, Model* M) {
   if (!M->pending) return GPBO_OK;
-  HIP_TRY(c, hipMemcpyAsync(M->host_stats, M->stats, sizeof M->host_stats, hipMemcpyDeviceToHost,
-                            c->stream));
-  HIP_TRY(c, hipMemcpyAsync(M->host_info, M->info, sizeof M->host_info, hipMemcpyDeviceToHost,
-                            c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  Model::GroupStatus& gs = *M->gstat;
+  if (!gs.read) {  // every model of the fit call at once
+    gs.host.resize((size_t)gs.nb * STATUS_SLOT);
+    HIP_TRY(c, hipMemcpyAsync(gs.host.data(), gs.dev, gs.host.size(), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    gs.read = true;
+  }
+  const unsigned char* slot = gs.host.data() + (size_t)M->gslot * STATUS_SLOT;
+  std::memcpy(M->host_stats, slot, sizeof M->host_stats);
+  std::memcpy(M->host_info, slot + S_COUNT * sizeof(double), sizeof M->host_info);
   M->pending = false;
+  M->gstat.reset();
   return GPBO_OK;
 }
 
@@ -340,7 +355,8 @@ gpbo_status gpbo_ctx_destroy(gpbo_ctx c) {
     (void)gpbo_mlp_free((gpbo_mlp)p);
   for (Model* M : std::vector<Model*>(c->live_models.begin(), c->live_models.end()))
     (void)gpbo_model_free((gpbo_model)M);
-  if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
+  for (auto& kv : c->batch_graphs) (void)hipGraphExecDestroy(kv.second);
+  c->batch_graphs.clear();
   for (auto& pr : c->ev_pending) {
     c->ev_pool.push_back(pr.first);
     c->ev_pool.push_back(pr.second);
@@ -440,6 +456,59 @@ gpbo_status gpbo_fit_async(gpbo_ctx c, const gpbo_problem* p, gpbo_model* out) {
   c->live_models.insert(M);
   *out = M;
   return GPBO_OK;
+}
+
+gpbo_status gpbo_fit_batched_async(gpbo_ctx c, int32_t B, const gpbo_problem* probs,
+                                   gpbo_model* out, int32_t* status) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (B < 0 || (B > 0 && (!probs || !out || !status)))
+    return fail(c, GPBO_E_INVALID_ARG, "invalid batch arguments");
+  DeviceGuard g(c->device);
+  std::vector<gpbo_model> ms(B, nullptr);
+  gpbo_status first = GPBO_OK;
+  for (int b = 0; b < B; ++b) {
+    out[b] = nullptr;
+    status[b] = check_problem(c, &probs[b]);
+    if (status[b] == GPBO_OK) {
+      ms[b] = new (std::nothrow) gpbo_model_s();
+      if (!ms[b]) status[b] = GPBO_E_OOM;
+    }
+  }
+  std::vector<Model*> mp(ms.begin(), ms.end());
+  gpbo_status gst = fit_group(c, B, probs, mp.data(), status, false);
+  for (int b = 0; b < B; ++b) {
+    if (ms[b] && status[b] == GPBO_OK && gst != GPBO_OK) status[b] = gst;
+    if (status[b] != GPBO_OK) {
+      if (first == GPBO_OK) first = (gpbo_status)status[b];
+      if (ms[b]) {
+        (void)hipStreamSynchronize(c->stream);
+        free_model_buffers(ms[b]);
+        delete ms[b];
+        ms[b] = nullptr;
+      }
+    } else {
+      out[b] = ms[b];
+      c->live_models.insert(ms[b]);
+    }
+  }
+  return first;
+}
+
+gpbo_status gpbo_model_status_batched(gpbo_ctx c, int32_t B, const gpbo_model* models,
+                                      int32_t* status, double* lml) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (B < 0 || (B > 0 && (!models || !status)))
+    return fail(c, GPBO_E_INVALID_ARG, "invalid batch arguments");
+  DeviceGuard g(c->device);
+  gpbo_status first = GPBO_OK;
+  for (int b = 0; b < B; ++b) {
+    gpbo_status st = models[b] ? resolve_pending(c, models[b]) : GPBO_E_INVALID_ARG;
+    if (st == GPBO_OK) st = fit_status(c, models[b], nullptr);
+    status[b] = st;
+    if (lml) lml[b] = st == GPBO_OK ? models[b]->host_stats[S_LML] : NAN;
+    if (st != GPBO_OK && first == GPBO_OK) first = st;
+  }
+  return first;
 }
 
 gpbo_status gpbo_model_status(gpbo_ctx c, gpbo_model M, int32_t* bad_pivot, double* lml) {
@@ -752,10 +821,12 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
                                      (uint64_t)(uintptr_t)s, (uint64_t)(uintptr_t)base};
   // With kernel timing on, every call launches eagerly so that events can
   // bracket the scoring kernel alone.
-  if (c->batch_exec && key == c->batch_key && !c->timing) {
-    HIP_TRY(c, hipGraphLaunch(c->batch_exec, s));
-    return GPBO_OK;
-  }
+  if (!c->timing)
+    for (auto& kv : c->batch_graphs)
+      if (kv.first == key) {
+        HIP_TRY(c, hipGraphLaunch(kv.second, s));
+        return GPBO_OK;
+      }
   // an eager launch (it also sets the kernels' LDS limits), then the capture
   hipEvent_t e0 = nullptr;
   const std::function<void(int)> mark = [&](int w) {
@@ -772,10 +843,10 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
                        c->timing ? &mark : nullptr);
   HIP_TRY(c, hipGetLastError());
   if (c->timing || s == nullptr || c->no_graph) return GPBO_OK;
-  if (c->batch_exec) {
-    (void)hipGraphExecDestroy(c->batch_exec);
-    c->batch_exec = nullptr;
-    c->batch_key.clear();
+  constexpr size_t kMaxGraphs = 8;
+  if (c->batch_graphs.size() >= kMaxGraphs) {  // the oldest goes
+    (void)hipGraphExecDestroy(c->batch_graphs.front().second);
+    c->batch_graphs.erase(c->batch_graphs.begin());
   }
   hipGraph_t graph = nullptr;
   HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -785,8 +856,7 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
   hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e == hipSuccess) {
-    c->batch_exec = exec;
-    c->batch_key = key;
+    c->batch_graphs.emplace_back(key, exec);
   }
   return GPBO_OK;
 }

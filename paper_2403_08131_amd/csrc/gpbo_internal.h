@@ -58,6 +58,16 @@ struct Model {
   double host_stats[S_COUNT] = {0};
   int host_info[2] = {0, 0};
   bool pending = false;         // fitted asynchronously; host_stats / host_info not read yet
+  // Status region of the asynchronous fit call this model came from (shared
+  // by its models: the first status request reads all of them at once).
+  struct GroupStatus {
+    const unsigned char* dev = nullptr;  // nb slots on the device
+    int nb = 0;
+    bool read = false;
+    std::vector<unsigned char> host;     // nb slots once read
+  };
+  std::shared_ptr<GroupStatus> gstat;
+  int gslot = 0;
   // Score operands, built on first use per precision.
   int nx = 0;                   // row stride of Xs32 / Xs64 (n padded with far-away points)
   float* Xs32 = nullptr;        // d x nx, coordinates scaled for the float32 kernels
@@ -121,8 +131,9 @@ struct Ctx {
   std::unordered_set<Model*> live_models;
   std::unordered_set<void*> live_mlps;
   // Batched-score graph cache.
-  hipGraphExec_t batch_exec = nullptr;
-  std::vector<uint64_t> batch_key;
+  // Batched-score graphs by launch shape (a few shapes alternate in a loop
+  // over several batches), most recently captured last.
+  std::vector<std::pair<std::vector<uint64_t>, hipGraphExec_t>> batch_graphs;
   void* batch_buf = nullptr;
   size_t batch_buf_bytes = 0;
 };

@@ -65,6 +65,10 @@ _SIGS = {
     "gpbo_fit_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Problem), C.POINTER(C.c_void_p),
                                    C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "gpbo_fit_async": (C.c_int, [C.c_void_p, C.POINTER(Problem), C.POINTER(C.c_void_p)]),
+    "gpbo_fit_batched_async": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Problem),
+                                         C.POINTER(C.c_void_p), C.POINTER(C.c_int32)]),
+    "gpbo_model_status_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p),
+                                            C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "gpbo_model_status": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
                                     C.POINTER(C.c_double)]),
     "gpbo_model_free": (C.c_int, [C.c_void_p]),
@@ -271,8 +275,11 @@ def fit_async(ctx: Context, X, y, lengthscale, kernel=KERNEL_SE, signal_var=1.0,
     return Model(ctx, h, X.shape[0], X.shape[1])
 
 
-def fit_batched(ctx: Context, problems):
-    """gpbo_fit_batched on a list of dicts with the :func:`fit` arguments."""
+def fit_batched(ctx: Context, problems, sync=True):
+    """gpbo_fit_batched on a list of dicts with the :func:`fit` arguments.
+    With sync=False, gpbo_fit_batched_async: the statuses returned are those
+    of the checks made before queueing (``Model.status()`` gives the
+    factorisation's) and the LML list is empty."""
     B = len(problems)
     arr = (Problem * B)()
     keep = []
@@ -285,10 +292,24 @@ def fit_batched(ctx: Context, problems):
     hs = (C.c_void_p * B)()
     lml = (C.c_double * B)()
     status = (C.c_int32 * B)()
-    st = lib().gpbo_fit_batched(ctx.h, B, arr, hs, lml, status)
+    if sync:
+        st = lib().gpbo_fit_batched(ctx.h, B, arr, hs, lml, status)
+    else:
+        st = lib().gpbo_fit_batched_async(ctx.h, B, arr, hs, status)
+        lml = []
     models = [Model(ctx, C.c_void_p(hs[b]), pr["X"].shape[0], pr["X"].shape[1]) if status[b] == OK
               else None for b, pr in enumerate(problems)]
     return st, models, list(status), list(lml)
+
+
+def status_batched(ctx: Context, models):
+    """gpbo_model_status_batched: (first failing status, statuses, LMLs)."""
+    B = len(models)
+    hs = (C.c_void_p * B)(*[mo.h.value if isinstance(mo.h, C.c_void_p) else mo.h for mo in models])
+    status = (C.c_int32 * B)()
+    lml = (C.c_double * B)()
+    st = lib().gpbo_model_status_batched(ctx.h, B, hs, status, lml)
+    return st, list(status), list(lml)
 
 
 def score(ctx: Context, model: Model, Xc, prec="fp32", want=("mu", "sigma", "ei"), reduce=True):

@@ -198,6 +198,43 @@ def test_score_batched_graph_replay_after_refit(ctx):
             mo.free()
 
 
+def test_score_batched_alternating_shapes_replay(ctx):
+    """Two batches of different shapes and output buffers scored in turn
+    (A, B, A, B, A): each call after the first of its shape replays its own
+    cached graph, and every result equals the single-problem path."""
+    import ctypes as C
+    batches = []
+    for seed, B, m in ((5, 4, 513), (6, 7, 1100)):
+        probs = _problems(B=B, m=m, seed=seed)
+        st, models, _, _ = _fit_batch(ctx, probs)
+        assert st == G.OK
+        Xcs = [_t(p.Xc, torch.float32) for p in probs]
+        eis = [torch.empty(x.shape[0], dtype=torch.float32, device=DEV) for x in Xcs]
+        am = torch.empty(B, dtype=torch.int64, device=DEV)
+        em = torch.empty(B, dtype=torch.float64, device=DEV)
+        singles = [G.score(ctx, mo, x, "fp32")["ei"] for mo, x in zip(models, Xcs)]
+        batches.append((models, Xcs, eis, am, em, singles))
+    for it in range(5):
+        models, Xcs, eis, am, em, singles = batches[it % 2]
+        B = len(models)
+        for e in eis:
+            e.fill_(float("nan"))
+        hs = (C.c_void_p * B)(*[mo.h.value for mo in models])
+        ms = (C.c_int64 * B)(*[x.shape[0] for x in Xcs])
+        xs = (C.c_void_p * B)(*[x.data_ptr() for x in Xcs])
+        ep = (C.c_void_p * B)(*[e.data_ptr() for e in eis])
+        ctx.check(G.lib().gpbo_score_batched(ctx.h, B, hs, ms, xs, G.FP32, ep,
+                                             C.c_void_p(am.data_ptr()), C.c_void_p(em.data_ptr())))
+        torch.cuda.synchronize()
+        for b in range(B):
+            top = float(singles[b].max())
+            assert float((eis[b] - singles[b]).abs().max()) <= 1e-5 * max(top, 1e-30), (it, b)
+            assert int(am[b]) == int(torch.argmax(eis[b])) or float(eis[b][am[b]]) == float(eis[b].max())
+    for models, *_ in batches:
+        for mo in models:
+            mo.free()
+
+
 def test_score_batched_mixed_kernels(ctx):
     """One persistent launch over problems of both kernels (every other
     problem Matern-5/2): each equals its single-problem result, and its
@@ -228,6 +265,42 @@ def test_score_batched_mixed_kernels(ctx):
         else:
             assert ref[am[b]] >= srt[0] * (1 - 1e-4)
     for mo in models:
+        mo.free()
+
+
+def test_fit_batched_async_matches_sync(ctx):
+    """gpbo_fit_batched_async + gpbo_model_status_batched: the same models as
+    the synchronous batched fit (bit-identical scores, equal LMLs), with a
+    failing problem reported by the status call."""
+    probs = _problems(B=5, m=600, seed=7)
+    specs = [dict(X=_t(p.X), y=_t(p.y), lengthscale=p.lengthscale, kernel=p.kernel,
+                  signal_var=p.signal_var, noise_var=p.noise_var) for p in probs]
+    st, m_sync, _, lml_sync = G.fit_batched(ctx, specs)
+    assert st == G.OK
+    st, m_async, status, _ = G.fit_batched(ctx, specs, sync=False)
+    assert st == G.OK and all(s == G.OK for s in status)
+    Xcs = [_t(p.Xc, torch.float32) for p in probs]
+    outs = [G.score(ctx, mo, x, "fp32") for mo, x in zip(m_async, Xcs)]  # queued behind the fit
+    st, status, lml = G.status_batched(ctx, m_async)
+    assert st == G.OK and lml == lml_sync
+    for mo, x, o in zip(m_sync, Xcs, outs):
+        ref = G.score(ctx, mo, x, "fp32")
+        torch.cuda.synchronize()
+        assert torch.equal(o["ei"], ref["ei"]) and torch.equal(o["argmax"], ref["argmax"])
+    for mo in m_sync + m_async:
+        mo.free()
+    # problem 2 made singular: repeated point, no noise
+    bad = probs[2]
+    Xb = bad.X.copy()
+    Xb[1] = Xb[0]
+    specs[2] = dict(X=_t(Xb), y=_t(bad.y), lengthscale=bad.lengthscale, kernel=bad.kernel,
+                    signal_var=1.0, noise_var=0.0)
+    st, m_async, status, _ = G.fit_batched(ctx, specs, sync=False)
+    assert st == G.OK
+    st, status, lml = G.status_batched(ctx, m_async)
+    assert st == G.E_NOT_PD and status[2] == G.E_NOT_PD and np.isnan(lml[2])
+    assert all(status[b] == G.OK for b in (0, 1, 3, 4))
+    for mo in m_async:
         mo.free()
 
 
