@@ -125,19 +125,23 @@ def _stream_handle(device):
 
 
 class Context:
-    """A gpbo context on one device and torch's current stream.
+    """A gpbo context on one device and torch's current stream (at creation,
+    or at the last :meth:`sync_stream`).
 
     The library's own buffers come from torch's caching allocator through the
-    allocator callbacks below."""
+    allocator callbacks below, allocated on the context's stream so that the
+    allocator reuses them in that stream's order."""
 
     def __init__(self, device=0, use_torch_allocator=True):
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self._children = weakref.WeakSet()  # models and MLPs, freed before the context
         self._held = {}
         self._alloc = None
+        self._tstream = torch.cuda.current_stream(self.device)
         if use_torch_allocator:
             def _a(nbytes, stream, user):
-                t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+                with torch.cuda.stream(self._tstream):
+                    t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
                 p = t.data_ptr()
                 self._held[p] = t
                 return p
@@ -160,6 +164,8 @@ class Context:
             raise GpboError(st, lib().gpbo_last_error(self.h).decode())
 
     def sync_stream(self):
+        """Move the context to torch's current stream."""
+        self._tstream = torch.cuda.current_stream(self.device)
         self.check(lib().gpbo_ctx_set_stream(self.h, _stream_handle(self.device)))
 
     def enable_timing(self, on=True):
