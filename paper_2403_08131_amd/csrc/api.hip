@@ -844,7 +844,8 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
   HIP_TRY(c, hipGetLastError());
   if (c->timing || s == nullptr || c->no_graph) return GPBO_OK;
   constexpr size_t kMaxGraphs = 8;
-  if (c->batch_graphs.size() >= kMaxGraphs) {  // the oldest goes
+  if (c->batch_graphs.size() >= kMaxGraphs) {  // the oldest goes, once it has run
+    HIP_TRY(c, hipStreamSynchronize(s));
     (void)hipGraphExecDestroy(c->batch_graphs.front().second);
     c->batch_graphs.erase(c->batch_graphs.begin());
   }
