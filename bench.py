@@ -276,7 +276,9 @@ def run_c4(args):
         "prescreen_rank_of_full_gp_choice": ranks,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAKS["bf16"],
                      "unit": "TFLOP/s", "frac": achieved / PEAKS["bf16"], "traffic": None,
-                     "kernel": "k_mlp_fwd", "flops_per_launch": r["fl"], "avg_launch_ms": fwd_avg},
+                     "kernel": "k_mlp_fwd", "flops_per_launch": r["fl"], "avg_launch_ms": fwd_avg,
+                     "note": "the GELU epilogues on the vector ALU, not the matrix cores, bound "
+                             "the network forward"},
     }
     ctx_net.close()
     ctx.close()
@@ -439,7 +441,9 @@ def run_c3(args):
         "error_vs_fp64": errs,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAKS[prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAKS[prec], "traffic": None, "kernel": "k_score_batched",
-                     "flops_per_launch": fl_launch, "avg_launch_ms": k_avg},
+                     "flops_per_launch": fl_launch, "avg_launch_ms": k_avg,
+                     "note": "the vector ALU (distances, exp2 per candidate-point pair), not the "
+                             "matrix cores, bounds this kernel at these small n and d"},
     }
     ctx.close()
     print(json.dumps(res), flush=True)
