@@ -136,12 +136,13 @@ __device__ __forceinline__ double sqdist4(const double* a, const double* b, int 
   return (s0 + s1) + (s2 + s3);
 }
 
-// Stage 64 scaled coordinate rows of X (n x d) starting at row r0 (rows >=
+// Stage R scaled coordinate rows of X (n x d) starting at row r0 (rows >=
 // lim are zero).
+template <int R = NB>
 __device__ __forceinline__ void stage_rows(const FitDesc& P, const double* X, int r0, int lim,
                                            double* dst) {
   const int dp4 = (P.d + 3) & ~3;
-  for (int e = threadIdx.x; e < NB * dp4; e += blockDim.x) {
+  for (int e = threadIdx.x; e < R * dp4; e += blockDim.x) {
     const int r = e / dp4, k = e % dp4;
     dst[r * GS + k] = (r0 + r < lim && k < P.d) ? X[(int64_t)(r0 + r) * P.d + k] * P.il[k] : 0.0;
   }
@@ -156,20 +157,28 @@ __device__ __forceinline__ void tri_index(int b, int& I, int& J) {
   J = b - i * (i + 1) / 2;
 }
 
+// Rows of a tile handled by one workgroup of the Gram and residual kernels:
+// four workgroups per 64 x 64 tile keep four times as many waves busy on
+// what is a latency-bound float64 loop.
+constexpr int KR = 16;
+
 // Lower triangle of K = sf2 k(X,X) + sn2 I (identity beyond n); the tile
 // mirrored above the diagonal is zeroed so the factor's upper part is clean.
-// The coordinates are read from the caller's X; the diagonal tiles also copy
-// their 64 rows into the model and flag non-finite values.
+// Workgroup 4b + h covers rows 16h..16h+15 of tile b (I, J).  The
+// coordinates are read from the caller's X; the diagonal tiles also copy
+// their rows into the model and flag non-finite values.
 __global__ void __launch_bounds__(256) k_gram(const FitDesc* __restrict__ D) {
-  __shared__ double xi[NB * GS], xj[NB * GS];
+  __shared__ double xi[KR * GS], xj[NB * GS];
   const FitDesc& P = D[blockIdx.z];
   const int nb = P.npad / NB;
-  if ((int)blockIdx.x >= nb * (nb + 1) / 2 || fit_failed(P.info)) return;
+  const int tile = blockIdx.x / (NB / KR), h = blockIdx.x % (NB / KR);
+  if (tile >= nb * (nb + 1) / 2 || fit_failed(P.info)) return;
   const int n = P.n, npad = P.npad;
   int I, J;
-  tri_index(blockIdx.x, I, J);
+  tri_index(tile, I, J);
+  const int r0 = I * NB + KR * h;  // first row of this workgroup
   if (I == J) {
-    const int64_t e0 = (int64_t)I * NB * P.d, e1 = (int64_t)min(n, (I + 1) * NB) * P.d;
+    const int64_t e0 = (int64_t)min(n, r0) * P.d, e1 = (int64_t)min(n, r0 + KR) * P.d;
     int bad = 0;
     for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
       const double x = P.Xsrc[e];
@@ -178,14 +187,23 @@ __global__ void __launch_bounds__(256) k_gram(const FitDesc* __restrict__ D) {
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(P.info + 1, 1);
   }
-  stage_rows(P, P.Xsrc, I * NB, n, xi);
+  stage_rows<KR>(P, P.Xsrc, r0, n, xi);
   stage_rows(P, P.Xsrc, J * NB, n, xj);
+  if (I != J) {
+    // mirrored block: rows J*64 .. J*64+63, columns r0 .. r0+15
+#pragma unroll
+    for (int e = threadIdx.x; e < NB * KR; e += 256) {
+      const int64_t o = (int64_t)(J * NB + e / KR) * npad + r0 + e % KR;
+      P.L[o] = 0.0;
+      P.Linv[o] = 0.0;
+    }
+  }
   __syncthreads();
   const int dp4 = (P.d + 3) & ~3;
-#pragma unroll 4
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+#pragma unroll
+  for (int e = threadIdx.x; e < KR * NB; e += 256) {
     const int r = e / NB, c = e % NB;
-    const int i = I * NB + r, j = J * NB + c;
+    const int i = r0 + r, j = J * NB + c;
     double v;
     if (i < n && j < n) {
       v = (j <= i) ? cov_r2(P.kernel, sqdist4(xi + r * GS, xj + c * GS, dp4), P.sf2) : 0.0;
@@ -196,10 +214,6 @@ __global__ void __launch_bounds__(256) k_gram(const FitDesc* __restrict__ D) {
     if (j > i) v = 0.0;
     P.L[(int64_t)i * npad + j] = v;
     P.Linv[(int64_t)i * npad + j] = 0.0;  // the inverse factor starts from zero
-    if (I != J) {
-      P.L[(int64_t)(J * NB + c) * npad + (I * NB + r)] = 0.0;
-      P.Linv[(int64_t)(J * NB + c) * npad + (I * NB + r)] = 0.0;
-    }
   }
 }
 
@@ -226,37 +240,6 @@ __device__ __forceinline__ void load_tile(const double* __restrict__ src, int ld
   }
 }
 
-// acc[4][4] += sum_q At[q][r] * Bt[q][c] for r = 4*ty + i, c = 4*tx + j.
-__device__ __forceinline__ void tile_mac(const double* At, const double* Bt, double acc[4][4]) {
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-#pragma unroll 4
-  for (int q = 0; q < NB; ++q) {
-    const double2 a01 = *(const double2*)&At[q * LDT + 4 * ty];
-    const double2 a23 = *(const double2*)&At[q * LDT + 4 * ty + 2];
-    const double2 b01 = *(const double2*)&Bt[q * LDT + 4 * tx];
-    const double2 b23 = *(const double2*)&Bt[q * LDT + 4 * tx + 2];
-    const double a[4] = {a01.x, a01.y, a23.x, a23.y};
-    const double b[4] = {b01.x, b01.y, b23.x, b23.y};
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-  }
-}
-
-// C tile = acc (mode 0) or C -= acc (mode 1).
-__device__ __forceinline__ void store_tile(double* __restrict__ C, int ld, const double acc[4][4],
-                                           int mode) {
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      double* p = &C[(int64_t)(4 * ty + i) * ld + 4 * tx + j];
-      *p = mode == 0 ? acc[i][j] : *p - acc[i][j];
-    }
-}
-
 // Broadcast of lane l's double (l a compile-time constant in the callers).
 __device__ __forceinline__ double readlane_f64(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
@@ -271,6 +254,46 @@ typedef double d4x __attribute__((ext_vector_type(4)));
 // interleaved across the lane groups, unlike the 32-bit 16 x 16 forms).
 __device__ __forceinline__ d4x mma64(double a, double b, d4x c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// The 64 x 64 product C[r][c] = sum_q At[q][r] Bt[q][c] on the float64
+// matrix cores: wave w forms rows 16w..16w+15 as four 16 x 16 blocks, column
+// block c in acc[c] (80 LDS reads per lane instead of the 512 of an outer
+// product on the vector ALUs).
+__device__ __forceinline__ void tile_mac(const double* At, const double* Bt, d4x acc[4]) {
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int mr = lane % 16, mk = lane / 16;
+#pragma unroll 4
+  for (int s = 0; s < NB / 4; ++s) {
+    const int q = 4 * s + mk;
+    const double a = At[q * LDT + 16 * w + mr];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = mma64(a, Bt[q * LDT + 16 * c + mr], acc[c]);
+  }
+}
+
+// The C tile's entries in the product's register layout: lane l holds row
+// 16w + l/16 + 4e, column 16c + l%16 in v[c][e].  An update loads them
+// before its product, so the loads overlap the staging and the product.
+__device__ __forceinline__ void load_acc(const double* __restrict__ C, int ld, double v[4][4]) {
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int mr = lane % 16, mk = lane / 16;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[c][e] = C[(int64_t)(16 * w + mk + 4 * e) * ld + 16 * c + mr];
+}
+
+// C tile = acc, or C = old - acc when old is given (same layout).
+__device__ __forceinline__ void store_tile(double* __restrict__ C, int ld, const d4x acc[4],
+                                           const double (*old)[4] = nullptr) {
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int mr = lane % 16, mk = lane / 16;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      C[(int64_t)(16 * w + mk + 4 * e) * ld + 16 * c + mr] = old ? old[c][e] - acc[c][e] : acc[c][e];
 }
 
 // Factor the diagonal tile (k, k), write L_kk and its inverse D_k.  The 64
@@ -501,10 +524,10 @@ __device__ __forceinline__ void panel_tile(const FitDesc& P, int k, int I, doubl
   load_tile(Pk, npad, At, true);
   load_tile(P.Dinv + (int64_t)k * NB * NB, NB, Bt, true);
   __syncthreads();
-  double acc[4][4] = {};
+  d4x acc[4] = {};
   tile_mac(At, Bt, acc);
   __syncthreads();
-  store_tile(Pk, npad, acc, 0);
+  store_tile(Pk, npad, acc);
 }
 
 // Trailing update: A_IJ -= A_Ik A_Jk^T for k < J <= I.
@@ -512,12 +535,15 @@ __device__ __forceinline__ void update_tile(const FitDesc& P, int k, int I, int 
   const int npad = P.npad;
   double* At = sm;
   double* Bt = sm + NB * LDT;
+  double* C = P.L + (int64_t)I * NB * npad + J * NB;
   load_tile(P.L + (int64_t)I * NB * npad + k * NB, npad, At, true);
   load_tile(P.L + (int64_t)J * NB * npad + k * NB, npad, Bt, true);
+  double old[4][4];
+  load_acc(C, npad, old);
   __syncthreads();
-  double acc[4][4] = {};
+  d4x acc[4] = {};
   tile_mac(At, Bt, acc);
-  store_tile(P.L + (int64_t)I * NB * npad + J * NB, npad, acc, 1);
+  store_tile(C, npad, acc, old);
 }
 
 // Inverse factor, step I: X_IJ = D_I B_IJ for J < I, X_II = D_I.
@@ -534,10 +560,10 @@ __device__ __forceinline__ void rowmul_tile(const FitDesc& P, int I, int J, doub
   load_tile(Dk, NB, At, true);
   load_tile(C, npad, Bt, false);
   __syncthreads();
-  double acc[4][4] = {};
+  d4x acc[4] = {};
   tile_mac(At, Bt, acc);
   __syncthreads();
-  store_tile(C, npad, acc, 0);
+  store_tile(C, npad, acc);
 }
 
 // Inverse factor, step I: B_KJ -= L_KI X_IJ for K > I, J <= I.
@@ -545,12 +571,15 @@ __device__ __forceinline__ void trtri_update_tile(const FitDesc& P, int I, int K
   const int npad = P.npad;
   double* At = sm;
   double* Bt = sm + NB * LDT;
+  double* C = P.Linv + (int64_t)K * NB * npad + J * NB;
   load_tile(P.L + (int64_t)K * NB * npad + I * NB, npad, At, true);
   load_tile(P.Linv + (int64_t)I * NB * npad + J * NB, npad, Bt, false);
+  double old[4][4];
+  load_acc(C, npad, old);
   __syncthreads();
-  double acc[4][4] = {};
+  d4x acc[4] = {};
   tile_mac(At, Bt, acc);
-  store_tile(P.Linv + (int64_t)K * NB * npad + J * NB, npad, acc, 1);
+  store_tile(C, npad, acc, old);
 }
 
 // Launch of step k (k <= nbmax): panel tiles of the factorisation (the first
@@ -680,18 +709,20 @@ __global__ void __launch_bounds__(64 * TRMV_T_WAVES) k_trmv_t(const FitDesc* __r
 }
 
 // Partial products of K alpha, K recomputed in float64 exactly as the Gram
-// kernel builds it.  Workgroup (x, y) owns rows 64x..64x+63 and the column
-// chunk y; 64-column tiles of the chunk are staged in LDS.
+// kernel builds it.  Workgroup (x, y) owns rows 16x..16x+15 and the column
+// chunk y; 64-column tiles of the chunk are staged in LDS, thread t takes
+// row t % 16 and every 16th column of a tile from t / 16 on.
 __global__ void __launch_bounds__(256) k_residual(const FitDesc* __restrict__ Ds) {
-  __shared__ double xi[NB * GS], xj[NB * GS], aj[NB], red[4][NB];
+  constexpr int NG = 256 / KR;  // column groups
+  __shared__ double xi[KR * GS], xj[NB * GS], aj[NB], red[NG][KR];
   const FitDesc& P = Ds[blockIdx.z];
   const int n = P.n;
-  const int i0 = blockIdx.x * NB;
+  const int i0 = blockIdx.x * KR;
   if (i0 >= n || (int)blockIdx.y >= P.nchunks || fit_failed(P.info)) return;
-  const int t = threadIdx.x, row = t % NB, grp = t / NB;
+  const int t = threadIdx.x, row = t % KR, grp = t / KR;
   const int jbeg = blockIdx.y * P.chunk, jend = min(n, jbeg + P.chunk);
   const int dp4 = (P.d + 3) & ~3;
-  stage_rows(P, P.X, i0, n, xi);
+  stage_rows<KR>(P, P.X, i0, n, xi);
   const int i = i0 + row;
   double s = 0.0;
   for (int j0 = jbeg; j0 < jend; j0 += NB) {
@@ -700,9 +731,9 @@ __global__ void __launch_bounds__(256) k_residual(const FitDesc* __restrict__ Ds
     if (t < NB) aj[t] = j0 + t < jend ? P.alpha[j0 + t] : 0.0;
     __syncthreads();
     if (i < n) {
-#pragma unroll 4
-      for (int q = 0; q < NB / 4; ++q) {
-        const int c = grp + 4 * q;
+#pragma unroll
+      for (int q = 0; q < NB / NG; ++q) {
+        const int c = grp + NG * q;
         if (j0 + c < jend) {
           double kij = cov_r2(P.kernel, sqdist4(xi + row * GS, xj + c * GS, dp4), P.sf2);
           if (i == j0 + c) kij += P.sn2;
@@ -713,9 +744,12 @@ __global__ void __launch_bounds__(256) k_residual(const FitDesc* __restrict__ Ds
   }
   red[grp][row] = s;
   __syncthreads();
-  if (grp == 0 && i < P.npad)
-    P.work[(int64_t)(V_PART + blockIdx.y) * P.npad + i] =
-        red[0][row] + red[1][row] + red[2][row] + red[3][row];
+  if (grp == 0 && i < P.npad) {
+    double v = 0.0;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) v += red[g][row];
+    P.work[(int64_t)(V_PART + blockIdx.y) * P.npad + i] = v;
+  }
 }
 
 // r = ytilde - sum_y part[y], its norm into stats[slot].  One workgroup of
@@ -814,7 +848,7 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   const size_t sm2 = 2 * NB * LDT * sizeof(double);
   const unsigned Bz = (unsigned)B;
   hipLaunchKernelGGL(k_fit_stats, dim3(1, 1, Bz), dim3(256), 0, s, dd);
-  hipLaunchKernelGGL(k_gram, dim3(nbmax * (nbmax + 1) / 2, 1, Bz), dim3(256), 0, s, dd);
+  hipLaunchKernelGGL(k_gram, dim3(nbmax * (nbmax + 1) / 2 * (NB / KR), 1, Bz), dim3(256), 0, s, dd);
   const unsigned gz = (unsigned)std::min<int64_t>(1024, ceil_div(npmax * npmax, 256));
   // step k: diagonal tile k; panel k with row multiply of inverse step k-1;
   // trailing update k with the update of inverse step k-1; step nbmax
@@ -837,7 +871,7 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   // alpha = Linv^T (Linv ytilde), then one residual-and-correction step
   hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, -1, (int)V_W);
   hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(64 * TRMV_T_WAVES), 0, s, dd, (int)V_W, -2, 0);
-  const dim3 g_res((unsigned)ceil_div(nmax, NB), (unsigned)chmax, Bz);
+  const dim3 g_res((unsigned)ceil_div(nmax, KR), (unsigned)chmax, Bz);
   hipLaunchKernelGGL(k_residual, g_res, dim3(256), 0, s, dd);
   hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(64 * RESF_W), 0, s, dd, (int)S_RES0, 0);
   hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, (int)V_R, (int)V_W);
