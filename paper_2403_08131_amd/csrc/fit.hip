@@ -296,6 +296,26 @@ __device__ __forceinline__ void store_tile(double* __restrict__ C, int ld, const
       C[(int64_t)(16 * w + mk + 4 * e) * ld + 16 * c + mr] = old ? old[c][e] - acc[c][e] : acc[c][e];
 }
 
+constexpr int PW = 16;  // panel width of the blocked factorisation
+// LDS of the diagonal-tile step, small arrays first, so that every address
+// the factorisation's column reads use fits the 16-bit LDS instruction
+// offset.  The panel columns (factorisation) and the block products
+// (inverse) share their space: 78,352 bytes, two workgroups per CU.
+struct DiagLds {
+  union {
+    double colb[PW][NB];             // the panel's unscaled columns, one slot each
+    double Tb[NB / PW][PW][PW + 2];  // one block product per wave
+  };
+  double piv[NB];    // pivots d_j
+  double pinv[NB];   // 1 / d_j
+  double rdiag[NB];  // 1 / L_jj
+  int bad;
+  int pad[3];
+  double Ls[NB][LDT];  // the tile, then U, then L_kk
+  double Xl[NB][LDT];  // the inverse, staged for a coalesced store
+};
+static_assert(sizeof(DiagLds) == 78352 && 2 * sizeof(DiagLds) <= 160 * 1024, "diagonal-step LDS");
+
 // Factor the diagonal tile (k, k), write L_kk and its inverse D_k.  The 64
 // column steps of the tile are a dependency chain; the kernel keeps the chain
 // in one wave, trims that wave's instructions to the chain itself (a lone
@@ -312,30 +332,13 @@ __device__ __forceinline__ void store_tile(double* __restrict__ C, int ld, const
 //   triangle on the float64 matrix cores.  At the end L_ij = U_ij / sqrt(d_j)
 //   (L_jj = sqrt(d_j)), one column per lane.
 //   Inverse, blocked over 16 x 16 blocks (see below).
-__global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ Ds, int k) {
-  // One LDS block with the small arrays first, so that every address the
-  // factorisation's column reads use fits the 16-bit LDS instruction offset.
-  constexpr int PW = 16;  // panel width of the blocked factorisation
-  struct Lds {
-    double colb[PW][NB];  // the panel's unscaled columns, one slot each
-    double piv[NB];       // pivots d_j
-    double pinv[NB];      // 1 / d_j
-    double rdiag[NB];     // 1 / L_jj
-    int bad;
-    int pad[3];
-    double Ls[NB][LDT];  // the tile, then U, then L_kk
-    double Xl[NB][LDT];  // the inverse, staged for a coalesced store
-    double Tb[NB / PW][PW][PW + 2];  // one block product per wave
-  };
-  __shared__ __align__(16) Lds S;
+__device__ __forceinline__ void potrf_diag_tile(const FitDesc& P, int k, DiagLds& S) {
   auto& colb = S.colb;
   auto& rdiag = S.rdiag;
   auto& bad_s = S.bad;
   auto& Ls = S.Ls;
   auto& Xl = S.Xl;
   auto& Tb = S.Tb;
-  const FitDesc& P = Ds[blockIdx.z];
-  if (k >= P.npad / NB || fit_failed(P.info)) return;
   const int npad = P.npad;
   const int t = threadIdx.x, lane = t % 64;
   const int wave = __builtin_amdgcn_readfirstlane(t / 64);
@@ -508,6 +511,13 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ 
   }
 }
 
+__global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ Ds, int k) {
+  __shared__ __align__(16) DiagLds S;
+  const FitDesc& P = Ds[blockIdx.z];
+  if (k >= P.npad / NB || fit_failed(P.info)) return;
+  potrf_diag_tile(P, k, S);
+}
+
 // The tile operations of the factorisation and of the inverse factor.  The
 // inverse factor X = L^-1 is formed block row by block row in right-looking
 // order: step I sets X_IJ = D_I B_IJ (J <= I; B_II = I) and then
@@ -602,7 +612,10 @@ __global__ void __launch_bounds__(256) k_chol_panel(const FitDesc* __restrict__ 
 }
 
 // Launch of step k: trailing-update tiles of the factorisation (the first
-// nupd workgroups) and the update tiles of inverse step k - 1.
+// nupd workgroups) and the update tiles of inverse step k - 1.  Look-ahead:
+// the workgroup that updates the next diagonal tile (k + 1, k + 1) goes on to
+// factor and invert it, so step k + 1 needs no launch of its own for it and
+// starts as soon as that one tile is done.
 __global__ void __launch_bounds__(256) k_chol_update(const FitDesc* __restrict__ Ds, int k,
                                                      int nupd) {
   extern __shared__ double sm[];
@@ -618,6 +631,12 @@ __global__ void __launch_bounds__(256) k_chol_update(const FitDesc* __restrict__
     int I, J;
     tri_index(bx, I, J);
     update_tile(P, k, I + k + 1, J + k + 1, sm);
+    if (bx == 0) {
+      // tile (k + 1, k + 1): its update is stored; the barrier makes the
+      // stores visible to the whole workgroup and frees the staging LDS
+      __syncthreads();
+      potrf_diag_tile(P, k + 1, *reinterpret_cast<DiagLds*>(sm));
+    }
   } else {
     const int I = k - 1, b = bx - nupd;
     if (I < 0 || I >= nb - 1 || b >= (nb - I - 1) * (I + 1)) return;
@@ -687,16 +706,16 @@ __global__ void __launch_bounds__(64 * TRMV_T_WAVES) k_trmv_t(const FitDesc* __r
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
   const int j0 = blockIdx.x * 64, j = j0 + lane;
   double s = 0.0;
+  // the inverse factor is exactly zero above its diagonal, so the rows i < j
+  // of the first block add zeros and need no test
   if (P.refine) {
     float sf = 0.0f;
-#pragma unroll 4
-    for (int i = j0 + w; i < n; i += TRMV_T_WAVES)
-      if (i >= j) sf += P.L32[(int64_t)i * npad + j] * (float)x[i];
+#pragma unroll 8
+    for (int i = j0 + w; i < n; i += TRMV_T_WAVES) sf += P.L32[(int64_t)i * npad + j] * (float)x[i];
     s = sf;
   } else {
-#pragma unroll 4
-    for (int i = j0 + w; i < n; i += TRMV_T_WAVES)
-      if (i >= j) s += P.Linv[(int64_t)i * npad + j] * x[i];
+#pragma unroll 8
+    for (int i = j0 + w; i < n; i += TRMV_T_WAVES) s += P.Linv[(int64_t)i * npad + j] * x[i];
   }
   red[w][lane] = s;
   __syncthreads();
@@ -792,13 +811,15 @@ __global__ void __launch_bounds__(64 * RESF_W) k_res_finish(const FitDesc* __res
   if (threadIdx.x == 0) P.stats[slot] = sqrt(q);
 }
 
-// The two-tile kernels stage 2 x 64 x 66 doubles (66 KiB) of dynamic LDS.
+// The two-tile kernels stage 2 x 64 x 66 doubles (66 KiB) of dynamic LDS;
+// the update kernel takes the diagonal step's 76.5 KiB.
 void allow_tile_lds() {
   static bool done = false;
   if (done) return;
   const int bytes = 2 * NB * LDT * sizeof(double);
   (void)hipFuncSetAttribute((const void*)k_chol_panel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  (void)hipFuncSetAttribute((const void*)k_chol_update, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute((const void*)k_chol_update, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sizeof(DiagLds));
   done = true;
 }
 
@@ -850,11 +871,13 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   hipLaunchKernelGGL(k_fit_stats, dim3(1, 1, Bz), dim3(256), 0, s, dd);
   hipLaunchKernelGGL(k_gram, dim3(nbmax * (nbmax + 1) / 2 * (NB / KR), 1, Bz), dim3(256), 0, s, dd);
   const unsigned gz = (unsigned)std::min<int64_t>(1024, ceil_div(npmax * npmax, 256));
-  // step k: diagonal tile k; panel k with row multiply of inverse step k-1;
-  // trailing update k with the update of inverse step k-1; step nbmax
-  // finishes the inverse
+  // step k: diagonal tile k (a launch of its own for k = 0, else factored by
+  // the update launch of step k - 1); panel k with row multiply of inverse
+  // step k-1; trailing update k with the update of inverse step k-1 and the
+  // diagonal tile k + 1; step nbmax finishes the inverse
+  const size_t smu = sizeof(DiagLds);
   for (int k = 0; k <= nbmax; ++k) {
-    if (k < nbmax) hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, Bz), dim3(256), 0, s, dd, k);
+    if (k == 0) hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, Bz), dim3(256), 0, s, dd, k);
     const int npanel = std::max(nbmax - k - 1, 0);
     const int nrow = k;  // inverse step k - 1 has k tiles in its row
     if (npanel + nrow > 0)
@@ -862,7 +885,7 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
     const int nupd = npanel * (npanel + 1) / 2;
     const int ntri = k >= 1 ? (nbmax - k) * k : 0;  // inverse step k - 1: (nbmax-k) rows x k tiles
     if (nupd + ntri > 0)
-      hipLaunchKernelGGL(k_chol_update, dim3(nupd + ntri, 1, Bz), dim3(256), sm2, s, dd, k, nupd);
+      hipLaunchKernelGGL(k_chol_update, dim3(nupd + ntri, 1, Bz), dim3(256), smu, s, dd, k, nupd);
   }
   bool any_refine = false;
   for (int b = 0; b < B; ++b) any_refine |= h[b].refine != 0;

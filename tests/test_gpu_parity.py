@@ -266,3 +266,39 @@ def test_score_noise_free_interpolation(ctx):
     assert np.max(np.abs(out["mu"].cpu().numpy() - y)) <= 1e-8 * np.max(np.abs(y))
     assert np.max(out["sigma"].cpu().numpy()) <= 1e-4
     m.free()
+
+
+@pytest.mark.gpu
+def test_fit_not_pd_in_a_later_diagonal_tile(ctx):
+    """A zero pivot in the third 64-row block (index 130) is found by the
+    diagonal step of that block, for a single fit, an asynchronous fit and a
+    batch in which the other problems still fit.  The points are so far
+    apart for the lengthscale that every other covariance underflows to
+    zero, so K is the identity apart from the duplicated pair and the
+    pivot of the copy is exactly zero."""
+    rng = np.random.default_rng(31)
+    n, d = 300, 5
+    X = rng.uniform(0.0, 1.0, (n, d))
+    X[130] = X[5]
+    y = rng.standard_normal(n)
+    ls = [0.001] * d
+    f = O.fit(X, y, ls, O.SE, 1.0, 0.0)
+    assert f.status == O.NOT_PD and f.bad_pivot == 130
+    with pytest.raises(G.GpboError) as e:
+        G.fit(ctx, _t(X), _t(y), ls, G.KERNEL_SE, 1.0, 0.0)
+    assert e.value.status == G.E_NOT_PD and e.value.bad_pivot == 130
+    ma = G.fit_async(ctx, _t(X), _t(y), ls, G.KERNEL_SE, 1.0, 0.0)
+    with pytest.raises(G.GpboError) as e:
+        ma.status()
+    assert e.value.status == G.E_NOT_PD and e.value.bad_pivot == 130
+    ma.free()
+    good = I.make_config("c2-s", n=260, m=16)
+    specs = [dict(X=_t(good.X), y=_t(good.y), lengthscale=good.lengthscale, kernel=good.kernel,
+                  signal_var=good.signal_var, noise_var=good.noise_var),
+             dict(X=_t(X), y=_t(y), lengthscale=ls, kernel=G.KERNEL_SE, signal_var=1.0,
+                  noise_var=0.0)]
+    st, models, status, lml = G.fit_batched(ctx, specs)
+    assert st == G.E_NOT_PD and status == [G.OK, G.E_NOT_PD] and models[1] is None
+    fo = O.fit(good.X, good.y, good.lengthscale, good.kernel, good.signal_var, good.noise_var)
+    assert lml[0] == pytest.approx(fo.lml, rel=1e-8, abs=1e-8 * good.n)
+    models[0].free()
