@@ -310,7 +310,8 @@ struct DiagLds {
   double pinv[NB];   // 1 / d_j
   double rdiag[NB];  // 1 / L_jj
   int bad;
-  int pad[3];
+  int npad_s;          // the row stride and the tile's address, for the
+  double* tile_s;      // store after the factorisation (see there)
   double Ls[NB][LDT];  // the tile, then U, then L_kk
   double Xl[NB][LDT];  // the inverse, staged for a coalesced store
 };
@@ -332,7 +333,10 @@ static_assert(sizeof(DiagLds) == 78352 && 2 * sizeof(DiagLds) <= 160 * 1024, "di
 //   triangle on the float64 matrix cores.  At the end L_ij = U_ij / sqrt(d_j)
 //   (L_jj = sqrt(d_j)), one column per lane.
 //   Inverse, blocked over 16 x 16 blocks (see below).
-__device__ __forceinline__ void potrf_diag_tile(const FitDesc& P, int k, DiagLds& S) {
+// With staged set, the caller has already written the tile to S.Ls (and
+// synchronised the workgroup).
+__device__ __forceinline__ void potrf_diag_tile(const FitDesc& P, int k, DiagLds& S,
+                                                bool staged = false) {
   auto& colb = S.colb;
   auto& rdiag = S.rdiag;
   auto& bad_s = S.bad;
@@ -346,11 +350,17 @@ __device__ __forceinline__ void potrf_diag_tile(const FitDesc& P, int k, DiagLds
   {
     // coalesced rows into LDS, all loads in flight before the first store
     const double* Akk = P.L + (int64_t)k * NB * npad + k * NB;
-    double v[NB / 4];
+    if (!staged) {
+      double v[NB / 4];
 #pragma unroll
-    for (int q = 0; q < NB / 4; ++q) v[q] = Akk[(int64_t)(wave + 4 * q) * npad + lane];
+      for (int q = 0; q < NB / 4; ++q) v[q] = Akk[(int64_t)(wave + 4 * q) * npad + lane];
 #pragma unroll
-    for (int q = 0; q < NB / 4; ++q) Ls[wave + 4 * q][lane] = v[q];
+      for (int q = 0; q < NB / 4; ++q) Ls[wave + 4 * q][lane] = v[q];
+    }
+    if (t == 0) {
+      S.npad_s = npad;
+      S.tile_s = P.L + (int64_t)k * NB * npad + k * NB;
+    }
   }
   __syncthreads();
   int bad = -1;  // first pivot that is not positive and finite (uniform in wave 0)
@@ -434,9 +444,8 @@ __device__ __forceinline__ void potrf_diag_tile(const FitDesc& P, int k, DiagLds
     return;
   }
   {
-    // L = U diag(d)^-1/2: lane = column j; stored to LDS and to the factor
-    // (addresses formed only now: a volatile read keeps the compiler from
-    // holding them in registers across the factorisation)
+    // L = U diag(d)^-1/2: lane = column j, in LDS (stored to the factor at
+    // the end: a barrier waits for the stores issued before it)
     const double d = S.piv[lane];
     double y = __builtin_amdgcn_rsq(d);
     y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
@@ -444,14 +453,10 @@ __device__ __forceinline__ void potrf_diag_tile(const FitDesc& P, int k, DiagLds
     double sq = d * y;
     sq = fma(0.5 * y, fma(-sq, sq, d), sq);  // sqrt(d), corrected
     if (wave == 0) rdiag[lane] = y;          // 1 / L_jj
-    const int np2 = *(const volatile int*)&P.npad;
-    double* Akk = P.L + (int64_t)k * NB * np2 + k * NB;
 #pragma unroll
     for (int q = 0; q < NB / 4; ++q) {
       const int r = wave + 4 * q;
-      const double v = r > lane ? Ls[r][lane] * y : (r == lane ? sq : 0.0);
-      Ls[r][lane] = v;
-      Akk[(int64_t)r * np2 + lane] = v;
+      Ls[r][lane] = r > lane ? Ls[r][lane] * y : (r == lane ? sq : 0.0);
     }
   }
   // Inverse, blocked over 4 x 4 blocks of 16: the diagonal blocks by
@@ -503,10 +508,16 @@ __device__ __forceinline__ void potrf_diag_tile(const FitDesc& P, int k, DiagLds
     }
     __syncthreads();
   }
+  // L_kk and D_k to memory (addresses formed only now: a volatile LDS read
+  // keeps the compiler from holding them in registers across the
+  // factorisation)
+  const int np2 = *(const volatile int*)&S.npad_s;
+  double* Akk = *(double* const volatile*)&S.tile_s;
   double* Dk = P.Dinv + (int64_t)k * NB * NB;
 #pragma unroll
   for (int q = 0; q < NB / 4; ++q) {
     const int r = wave + 4 * q;
+    Akk[(int64_t)r * np2 + lane] = Ls[r][lane];
     Dk[r * NB + lane] = Xl[r][lane];
   }
 }
@@ -628,15 +639,32 @@ __global__ void __launch_bounds__(256) k_chol_update(const FitDesc* __restrict__
     // ended (rest (rest + 1) / 2 would be positive again for rest <= -2).
     const int rest = nb - k - 1;
     if (rest <= 0 || bx >= rest * (rest + 1) / 2) return;
+    if (bx == 0) {
+      // tile (k + 1, k + 1): updated in registers and handed to the
+      // diagonal step through LDS, never stored in between
+      const int npad = P.npad, I = k + 1;
+      double* At = sm;
+      load_tile(P.L + (int64_t)I * NB * npad + k * NB, npad, At, true);
+      double old[4][4];
+      load_acc(P.L + (int64_t)I * NB * npad + I * NB, npad, old);
+      __syncthreads();
+      d4x acc[4] = {};
+      tile_mac(At, At, acc);
+      __syncthreads();  // the staging area becomes the diagonal step's LDS
+      DiagLds& S = *reinterpret_cast<DiagLds*>(sm);
+      const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          S.Ls[16 * w + lane / 16 + 4 * e][16 * c + lane % 16] = old[c][e] - acc[c][e];
+      __syncthreads();
+      potrf_diag_tile(P, I, S, true);
+      return;
+    }
     int I, J;
     tri_index(bx, I, J);
     update_tile(P, k, I + k + 1, J + k + 1, sm);
-    if (bx == 0) {
-      // tile (k + 1, k + 1): its update is stored; the barrier makes the
-      // stores visible to the whole workgroup and frees the staging LDS
-      __syncthreads();
-      potrf_diag_tile(P, k + 1, *reinterpret_cast<DiagLds*>(sm));
-    }
   } else {
     const int I = k - 1, b = bx - nupd;
     if (I < 0 || I >= nb - 1 || b >= (nb - I - 1) * (I + 1)) return;
