@@ -536,19 +536,52 @@ __global__ void __launch_bounds__(256) k_potrf_diag(const FitDesc* __restrict__ 
 // D_I, so it runs inside the launches of the factorisation's step I + 1,
 // on workgroups of their own: no extra launch per step.
 
-// Panel: A_Ik <- A_Ik D_k^T for I > k.
-__device__ __forceinline__ void panel_tile(const FitDesc& P, int k, int I, double* sm) {
-  const int npad = P.npad;
+// One 16 x 16 block per wave of the product C[r][c] = sum_q At[q][r]
+// Bt[q][c]: rows rb..rb+15, columns cb..cb+15 (register layout of
+// load_acc).
+__device__ __forceinline__ d4x block_mac(const double* At, const double* Bt, int rb, int cb) {
+  const int lane = threadIdx.x % 64, mr = lane % 16, mk = lane / 16;
+  d4x acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int s = 0; s < NB / 4; ++s) {
+    const int q = 4 * s + mk;
+    acc = mma64(At[q * LDT + rb + mr], Bt[q * LDT + cb + mr], acc);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ void store_block(double* __restrict__ C, int ld, d4x acc, int rb, int cb) {
+  const int lane = threadIdx.x % 64, mr = lane % 16, mk = lane / 16;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) C[(int64_t)(rb + mk + 4 * e) * ld + cb + mr] = acc[e];
+}
+
+// The panel and the inverse's row multiply are split over four workgroups
+// per tile (h = 0..3), so that their launches, which lie on the
+// factorisation's critical path, each take a quarter of the matrix work.
+// Each workgroup reads and writes only its own slice of the tile it
+// overwrites.
+
+// Panel: A_Ik <- A_Ik D_k^T for I > k; workgroup h takes rows 16h..16h+15.
+__device__ __forceinline__ void panel_tile(const FitDesc& P, int k, int I, int h, double* sm) {
+  const int npad = P.npad, t = threadIdx.x, w = t / 64;
   double* At = sm;
   double* Bt = sm + NB * LDT;
   double* Pk = P.L + (int64_t)I * NB * npad + k * NB;
-  load_tile(Pk, npad, At, true);
+  double v[NB / 16];
+#pragma unroll
+  for (int q = 0; q < NB / 16; ++q) {  // rows 16h.. of A_Ik, transposed into At
+    const int e = t + 256 * q, r = 16 * h + e / NB, c = e % NB;
+    v[q] = Pk[(int64_t)r * npad + c];
+  }
   load_tile(P.Dinv + (int64_t)k * NB * NB, NB, Bt, true);
+#pragma unroll
+  for (int q = 0; q < NB / 16; ++q) {
+    const int e = t + 256 * q, r = 16 * h + e / NB, c = e % NB;
+    At[c * LDT + r] = v[q];
+  }
   __syncthreads();
-  d4x acc[4] = {};
-  tile_mac(At, Bt, acc);
-  __syncthreads();
-  store_tile(Pk, npad, acc);
+  store_block(Pk, npad, block_mac(At, Bt, 16 * h, 16 * w), 16 * h, 16 * w);
 }
 
 // Trailing update: A_IJ -= A_Ik A_Jk^T for k < J <= I.
@@ -567,24 +600,35 @@ __device__ __forceinline__ void update_tile(const FitDesc& P, int k, int I, int 
   store_tile(C, npad, acc, old);
 }
 
-// Inverse factor, step I: X_IJ = D_I B_IJ for J < I, X_II = D_I.
-__device__ __forceinline__ void rowmul_tile(const FitDesc& P, int I, int J, double* sm) {
-  const int npad = P.npad;
+// Inverse factor, step I: X_IJ = D_I B_IJ for J < I, X_II = D_I;
+// workgroup h takes columns 16h..16h+15.
+__device__ __forceinline__ void rowmul_tile(const FitDesc& P, int I, int J, int h, double* sm) {
+  const int npad = P.npad, t = threadIdx.x, w = t / 64;
   double* C = P.Linv + (int64_t)I * NB * npad + J * NB;
   const double* Dk = P.Dinv + (int64_t)I * NB * NB;
   if (J == I) {
-    for (int e = threadIdx.x; e < NB * NB; e += 256) C[(int64_t)(e / NB) * npad + e % NB] = Dk[e];
+    for (int e = t; e < NB * 16; e += 256) {
+      const int r = e / 16, c = 16 * h + e % 16;
+      C[(int64_t)r * npad + c] = Dk[r * NB + c];
+    }
     return;
   }
   double* At = sm;
   double* Bt = sm + NB * LDT;
+  double v[NB / 16];
+#pragma unroll
+  for (int q = 0; q < NB / 16; ++q) {  // columns 16h.. of B_IJ into Bt
+    const int e = t + 256 * q, r = e / 16, c = 16 * h + e % 16;
+    v[q] = C[(int64_t)r * npad + c];
+  }
   load_tile(Dk, NB, At, true);
-  load_tile(C, npad, Bt, false);
+#pragma unroll
+  for (int q = 0; q < NB / 16; ++q) {
+    const int e = t + 256 * q, r = e / 16, c = 16 * h + e % 16;
+    Bt[r * LDT + c] = v[q];
+  }
   __syncthreads();
-  d4x acc[4] = {};
-  tile_mac(At, Bt, acc);
-  __syncthreads();
-  store_tile(C, npad, acc);
+  store_block(C, npad, block_mac(At, Bt, 16 * w, 16 * h), 16 * w, 16 * h);
 }
 
 // Inverse factor, step I: B_KJ -= L_KI X_IJ for K > I, J <= I.
@@ -612,13 +656,13 @@ __global__ void __launch_bounds__(256) k_chol_panel(const FitDesc* __restrict__ 
   const FitDesc& P = Ds[blockIdx.z];
   if (fit_failed(P.info)) return;
   const int nb = P.npad / NB;
-  const int bx = blockIdx.x;
+  const int bx = blockIdx.x / 4, h = blockIdx.x % 4;  // tile, quarter
   if (bx < npanel) {
     const int I = k + 1 + bx;
-    if (I < nb) panel_tile(P, k, I, sm);
+    if (I < nb) panel_tile(P, k, I, h, sm);
   } else {
     const int I = k - 1, J = bx - npanel;
-    if (I >= 0 && I < nb && J <= I) rowmul_tile(P, I, J, sm);
+    if (I >= 0 && I < nb && J <= I) rowmul_tile(P, I, J, h, sm);
   }
 }
 
@@ -909,7 +953,7 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
     const int npanel = std::max(nbmax - k - 1, 0);
     const int nrow = k;  // inverse step k - 1 has k tiles in its row
     if (npanel + nrow > 0)
-      hipLaunchKernelGGL(k_chol_panel, dim3(npanel + nrow, 1, Bz), dim3(256), sm2, s, dd, k, npanel);
+      hipLaunchKernelGGL(k_chol_panel, dim3(4 * (npanel + nrow), 1, Bz), dim3(256), sm2, s, dd, k, npanel);
     const int nupd = npanel * (npanel + 1) / 2;
     const int ntri = k >= 1 ? (nbmax - k) * k : 0;  // inverse step k - 1: (nbmax-k) rows x k tiles
     if (nupd + ntri > 0)
