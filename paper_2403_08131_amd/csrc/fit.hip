@@ -453,10 +453,16 @@ __device__ __forceinline__ void potrf_diag_tile(const FitDesc& P, int k, DiagLds
     double sq = d * y;
     sq = fma(0.5 * y, fma(-sq, sq, d), sq);  // sqrt(d), corrected
     if (wave == 0) rdiag[lane] = y;          // 1 / L_jj
+    // all reads first and selects rather than branches: one LDS round trip
+    // instead of one per row
+    double u[NB / 4];
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) u[q] = Ls[wave + 4 * q][lane];
 #pragma unroll
     for (int q = 0; q < NB / 4; ++q) {
       const int r = wave + 4 * q;
-      Ls[r][lane] = r > lane ? Ls[r][lane] * y : (r == lane ? sq : 0.0);
+      const double lo = u[q] * y, dg = r == lane ? sq : 0.0;
+      Ls[r][lane] = r > lane ? lo : dg;
     }
   }
   // Inverse, blocked over 4 x 4 blocks of 16: the diagonal blocks by
@@ -465,7 +471,8 @@ __device__ __forceinline__ void potrf_diag_tile(const FitDesc& P, int k, DiagLds
   //   X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ   (I - J = d),
   // wave J forming block (J + d, J) on the matrix cores, the inner sum
   // staged through LDS to become the second product's B operand.
-  for (int e = t; e < NB * NB; e += 256) Xl[e / NB][e % NB] = 0.0;
+#pragma unroll
+  for (int q = 0; q < NB * NB / 256; ++q) Xl[wave + 4 * q][lane] = 0.0;
   __syncthreads();
   if (lane < PW) {
     const int b0 = wave * PW, cc = lane;
