@@ -768,41 +768,45 @@ __global__ void __launch_bounds__(256) k_trmv(const FitDesc* __restrict__ Ds, in
   if (lane == 0) y[row] = row < n ? r : 0.0;
 }
 
-// y = Linv^T x: y_j = sum_{i >= j} Linv_ij x_i.  A workgroup owns 64 columns;
-// its 16 waves take every 16th row from the block's first column on, all
-// lanes of a wave reading the same row (one coalesced load), and combine in
-// LDS.
-constexpr int TRMV_T_WAVES = 16;
+// y = Linv^T x: y_j = sum_{i >= j} Linv_ij x_i.  A workgroup owns 16
+// columns; each load of a wave covers 4 rows x 16 columns (four 128-byte
+// segments), the 64 row slots of the 16 waves take every 64th row from the
+// block's first column on, and the slots are combined through LDS.  (The
+// inverse factor is exactly zero above its diagonal, so the rows i < j of
+// the first block add zeros and need no test.)
+constexpr int TRMV_T_WAVES = 16, TT_COLS = 16, TT_SLOTS = TRMV_T_WAVES * 64 / TT_COLS;
 // accumulate = 1: y += Linv^T x (the correction step of alpha).
 __global__ void __launch_bounds__(64 * TRMV_T_WAVES) k_trmv_t(const FitDesc* __restrict__ Ds,
                                                               int xv, int yv, int accumulate) {
-  __shared__ double red[TRMV_T_WAVES][64];
+  __shared__ double red[TT_SLOTS][TT_COLS];
   const FitDesc& P = Ds[blockIdx.z];
-  if ((int)blockIdx.x * 64 >= P.npad || fit_failed(P.info)) return;
+  if ((int)blockIdx.x * TT_COLS >= P.npad || fit_failed(P.info)) return;
   const int n = P.n, npad = P.npad;
   const double* x = wvec(P, xv);
   double* y = wvec(P, yv);
-  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-  const int j0 = blockIdx.x * 64, j = j0 + lane;
+  const int t = threadIdx.x, c = t % TT_COLS, g = t / TT_COLS;  // column, row slot
+  const int j0 = blockIdx.x * TT_COLS, j = j0 + c;
   double s = 0.0;
-  // the inverse factor is exactly zero above its diagonal, so the rows i < j
-  // of the first block add zeros and need no test
   if (P.refine) {
     float sf = 0.0f;
-#pragma unroll 8
-    for (int i = j0 + w; i < n; i += TRMV_T_WAVES) sf += P.L32[(int64_t)i * npad + j] * (float)x[i];
+#pragma unroll 4
+    for (int i = j0 + g; i < n; i += TT_SLOTS) sf += P.L32[(int64_t)i * npad + j] * (float)x[i];
     s = sf;
   } else {
-#pragma unroll 8
-    for (int i = j0 + w; i < n; i += TRMV_T_WAVES) s += P.Linv[(int64_t)i * npad + j] * x[i];
+#pragma unroll 4
+    for (int i = j0 + g; i < n; i += TT_SLOTS) s += P.Linv[(int64_t)i * npad + j] * x[i];
   }
-  red[w][lane] = s;
+  red[g][c] = s;
   __syncthreads();
-  if (w == 0) {
-    double t = 0.0;
+  if (t < 64) {
+    // lane (c, part) sums slots part*16 .. part*16+15, then the four parts
+    const int part = t / TT_COLS;
+    double u = 0.0;
 #pragma unroll
-    for (int q = 0; q < TRMV_T_WAVES; ++q) t += red[q][lane];
-    y[j] = j < n ? (accumulate ? y[j] + t : t) : 0.0;
+    for (int q = 0; q < TT_SLOTS / 4; ++q) u += red[part * (TT_SLOTS / 4) + q][c];
+    u += __shfl_xor(u, 16);
+    u += __shfl_xor(u, 32);
+    if (t < TT_COLS) y[j] = j < n ? (accumulate ? y[j] + u : u) : 0.0;
   }
 }
 
@@ -969,7 +973,7 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   bool any_refine = false;
   for (int b = 0; b < B; ++b) any_refine |= h[b].refine != 0;
   if (any_refine) hipLaunchKernelGGL(k_cast_linv, dim3(gz, 1, Bz), dim3(256), 0, s, dd);
-  const unsigned g_rows = (unsigned)ceil_div(npmax, 4), g_cols = (unsigned)ceil_div(npmax, 64);
+  const unsigned g_rows = (unsigned)ceil_div(npmax, 4), g_cols = (unsigned)ceil_div(npmax, TT_COLS);
   // alpha = Linv^T (Linv ytilde), then one residual-and-correction step
   hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, -1, (int)V_W);
   hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(64 * TRMV_T_WAVES), 0, s, dd, (int)V_W, -2, 0);
