@@ -304,6 +304,9 @@ def run_c3(args):
     prec = args.prec or "bf16"
     pr = G.PREC[prec]
     dev = torch.device("cuda", 0)
+    # a created stream: the library replays its launch graphs only there
+    # (the legacy default stream cannot be captured)
+    torch.cuda.set_stream(torch.cuda.Stream(device=dev))
     ctx = G.Context(0)
     batches = []
     for lam in (0.0, 0.1, 0.5):

@@ -22,9 +22,18 @@ EPS = np.finfo(np.float64).eps
 
 @pytest.fixture(scope="module")
 def ctx():
+    # a stream of its own: the library captures and replays its launch
+    # graphs only on a created stream (the legacy default stream, handle 0,
+    # cannot be captured), so the replay tests below run the graph path
+    prev = torch.cuda.current_stream(DEV)
+    s = torch.cuda.Stream(device=DEV)
+    assert s.cuda_stream != 0
+    torch.cuda.set_stream(s)
     c = G.Context(0)
     yield c
     c.close()
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(prev)
 
 
 def _t(a, dt=torch.float64):
