@@ -120,7 +120,11 @@ int32_t gpbo_version(void);
 
 /* Create a context on HIP device `device`, queuing work on `stream` (a
  * hipStream_t; NULL = the default stream).  Returns GPBO_E_HIP when there is
- * no usable device. */
+ * no usable device.  Launch graphs (the fit's launch sequence, batched
+ * scoring, network training) are captured and replayed only on a created
+ * stream: the legacy default stream cannot be captured, and there every
+ * call launches eagerly (same results).  The environment variable
+ * GPBO_NO_GRAPH=1 at creation turns replay off. */
 gpbo_status gpbo_ctx_create(int32_t device, void* stream, const gpbo_allocator* alloc,
                             gpbo_ctx* out);
 /* Waits for the context's stream, then frees every model and MLP still
@@ -235,8 +239,10 @@ gpbo_status gpbo_score(gpbo_ctx ctx, gpbo_model model, int64_t m, const void* Xc
  * m, Xc, ei: host arrays of B entries (Xc[b], ei[b] are device pointers as
  * in gpbo_score; ei[b] or the whole ei array may be NULL).  argmax and ei_max
  * are device arrays of B entries.  prec is GPBO_FP32 or GPBO_BF16.  The
- * launch sequence is captured in a HIP graph on first use and replayed while
- * the same models, pools and outputs are passed again.  Asynchronous. */
+ * launch sequence is captured in a HIP graph on first use of a batch shape
+ * (B, precision, tile, candidate tiles, outputs) and replayed for later calls
+ * of that shape, also with other models and pools: the kernels read them from
+ * descriptors uploaded by each call.  Up to 8 shapes are kept.  Asynchronous. */
 gpbo_status gpbo_score_batched(gpbo_ctx ctx, int32_t B, const gpbo_model* models,
                                const int64_t* m, const void* const* Xc, gpbo_precision prec,
                                void* const* ei, int64_t* argmax, double* ei_max);

@@ -102,6 +102,43 @@ FitLayout fit_layout(int n, int d, bool refine) {
   return f;
 }
 
+// The fit's launch sequence (descriptors already uploaded to dd in stream
+// order).  On a created stream it is captured once per launch shape and
+// replayed after that: the kernels read everything problem-specific from
+// the descriptors, so the next fit of a search with the same sizes replays
+// the 28-launch sequence (n = 512) as one graph launch.  The legacy default
+// stream cannot be captured; there every call launches eagerly.
+gpbo_status run_fit(Ctx* c, const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
+  std::vector<uint64_t> key = fit_launch_shape(h, B);
+  key.push_back((uint64_t)(uintptr_t)dd);
+  key.push_back((uint64_t)(uintptr_t)s);
+  if (s != nullptr && !c->no_graph)
+    for (auto& kv : c->fit_graphs)
+      if (kv.first == key) {
+        HIP_TRY(c, hipGraphLaunch(kv.second, s));
+        return GPBO_OK;
+      }
+  // an eager launch (it also sets the kernels' LDS limits), then the capture
+  launch_fit(h, dd, B, s);
+  HIP_TRY(c, hipGetLastError());
+  if (s == nullptr || c->no_graph) return GPBO_OK;
+  constexpr size_t kMaxGraphs = 8;
+  if (c->fit_graphs.size() >= kMaxGraphs) {  // the oldest goes, once it has run
+    HIP_TRY(c, hipStreamSynchronize(s));
+    (void)hipGraphExecDestroy(c->fit_graphs.front().second);
+    c->fit_graphs.erase(c->fit_graphs.begin());
+  }
+  hipGraph_t graph = nullptr;
+  HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  launch_fit(h, dd, B, s);
+  HIP_TRY(c, hipStreamEndCapture(s, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e == hipSuccess) c->fit_graphs.emplace_back(key, exec);
+  return GPBO_OK;
+}
+
 // Per-model slot of the status region at the start of a fit allocation:
 // S_COUNT statistics, then the two info words.
 constexpr size_t STATUS_SLOT = 128;
@@ -190,7 +227,10 @@ gpbo_status fit_group(Ctx* c, int B, const gpbo_problem* probs, Model* const* ms
   std::memcpy(up.data(), hd.data(), nb * sizeof(FitDesc));
   // a copy from pageable memory has consumed its source when it returns
   HIP_TRY(c, hipMemcpyAsync(c->desc_buf, up.data(), up_bytes, hipMemcpyHostToDevice, c->stream));
-  launch_fit(hd.data(), (const FitDesc*)c->desc_buf, nb, c->stream);
+  {
+    const gpbo_status st = run_fit(c, hd.data(), (const FitDesc*)c->desc_buf, nb, c->stream);
+    if (st != GPBO_OK) return st;
+  }
   if (!sync) {  // the statistics are read when the caller asks for a status
     auto gs = std::make_shared<Model::GroupStatus>();
     gs->dev = (const unsigned char*)(g + ostat);
@@ -357,6 +397,8 @@ gpbo_status gpbo_ctx_destroy(gpbo_ctx c) {
     (void)gpbo_model_free((gpbo_model)M);
   for (auto& kv : c->batch_graphs) (void)hipGraphExecDestroy(kv.second);
   c->batch_graphs.clear();
+  for (auto& kv : c->fit_graphs) (void)hipGraphExecDestroy(kv.second);
+  c->fit_graphs.clear();
   for (auto& pr : c->ev_pending) {
     c->ev_pool.push_back(pr.first);
     c->ev_pool.push_back(pr.second);

@@ -939,6 +939,20 @@ FitDesc make_fit_desc(Model* M, const double* X, const double* il, const double*
   return f;
 }
 
+std::vector<uint64_t> fit_launch_shape(const FitDesc* h, int B) {
+  int nbmax = 0, nmax = 0, chmax = 1, refine = 0;
+  int64_t npmax = 0;
+  for (int b = 0; b < B; ++b) {
+    nbmax = std::max(nbmax, h[b].npad / NB);
+    nmax = std::max(nmax, h[b].n);
+    npmax = std::max<int64_t>(npmax, h[b].npad);
+    chmax = std::max(chmax, h[b].nchunks);
+    refine |= h[b].refine != 0;
+  }
+  return {(uint64_t)B, (uint64_t)nbmax, (uint64_t)npmax, (uint64_t)ceil_div(nmax, KR),
+          (uint64_t)chmax, (uint64_t)refine};
+}
+
 void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   allow_tile_lds();
   int nbmax = 0, nmax = 0, chmax = 1;

@@ -134,6 +134,7 @@ struct Ctx {
   // Batched-score graphs by launch shape (a few shapes alternate in a loop
   // over several batches), most recently captured last.
   std::vector<std::pair<std::vector<uint64_t>, hipGraphExec_t>> batch_graphs;
+  std::vector<std::pair<std::vector<uint64_t>, hipGraphExec_t>> fit_graphs;
   void* batch_buf = nullptr;
   size_t batch_buf_bytes = 0;
 };
@@ -176,6 +177,9 @@ FitDesc make_fit_desc(Model* M, const double* X, const double* il, const double*
                       int normalize_y, int refine);
 // Queue the whole fit of B problems (descriptors: host copy h, device copy dd).
 void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s);
+// What the grids and arguments of that launch sequence depend on besides the
+// descriptor pointer: equal shapes launch identical sequences.
+std::vector<uint64_t> fit_launch_shape(const FitDesc* h, int B);
 
 // ---------------------------------------------------------------------------
 // Score operands and kernels (score.hip)

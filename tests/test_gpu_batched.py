@@ -337,3 +337,40 @@ def test_batched_full_c3_shape_smoke(ctx):
             assert np.max(np.abs(e - single["ei"].double().cpu().numpy())) <= 1e-5 * scale, (prec, b)
     for mo in models:
         mo.free()
+
+
+def test_fit_graph_replay_matches_eager(ctx):
+    """Fits of one shape after the first replay the captured fit sequence
+    (this module's context is on a created stream): the factors, the inverse
+    factor, alpha and the LML equal those of a context that launches eagerly
+    (GPBO_NO_GRAPH=1) bit for bit, for new data of the same shape, with a
+    fit of another shape (its own graph) in between, and for an
+    asynchronous fit."""
+    import os
+    os.environ["GPBO_NO_GRAPH"] = "1"
+    try:
+        eager = G.Context(0)
+    finally:
+        del os.environ["GPBO_NO_GRAPH"]
+    rng = np.random.default_rng(5)
+    base = I.make_config("c2-s", n=300, m=16)
+    other = I.make_config("c2-s", n=130, m=16, replicate=1)
+    for it in range(4):
+        y = base.y + (rng.normal(0.0, 0.1, size=base.y.shape) if it else 0.0)
+        args = (_t(base.X), _t(y), base.lengthscale, base.kernel, base.signal_var, base.noise_var)
+        mg = G.fit_async(ctx, *args) if it == 3 else G.fit(ctx, *args)
+        me = G.fit(eager, *args)
+        lml_g = mg.status()
+        fg, fe = mg.factors(), me.factors()
+        torch.cuda.synchronize()
+        for u, v in zip(fg, fe):
+            assert torch.equal(u, v), it
+        assert lml_g == me.stats()["lml"], it
+        f = O.fit(base.X, y, base.lengthscale, base.kernel, base.signal_var, base.noise_var)
+        assert lml_g == pytest.approx(f.lml, rel=1e-8, abs=1e-8 * base.n), it
+        mo = G.fit(ctx, _t(other.X), _t(other.y), other.lengthscale, other.kernel,
+                   other.signal_var, other.noise_var)
+        mo.free()
+        mg.free()
+        me.free()
+    eager.close()
