@@ -102,6 +102,28 @@ FitLayout fit_layout(int n, int d, bool refine) {
   return f;
 }
 
+hipEvent_t timing_event(Ctx* c);
+
+// A pinned host chunk of at least `bytes` from the context's pool (a new
+// hipHostMalloc only when none fits); *got receives its size.
+unsigned char* pinned_acquire(Ctx* c, size_t bytes, size_t* got) {
+  for (size_t i = 0; i < c->pinned_pool.size(); ++i)
+    if (c->pinned_pool[i].first >= bytes) {
+      const auto pr = c->pinned_pool[i];
+      c->pinned_pool.erase(c->pinned_pool.begin() + (std::ptrdiff_t)i);
+      *got = pr.first;
+      return pr.second;
+    }
+  const size_t sz = round_up(bytes, 4096);
+  void* p = nullptr;
+  if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  *got = sz;
+  return (unsigned char*)p;
+}
+
 // The fit's launch sequence (descriptors already uploaded to dd in stream
 // order).  On a created stream it is captured once per launch shape and
 // replayed after that: the kernels read everything problem-specific from
@@ -201,6 +223,8 @@ gpbo_status fit_group(Ctx* c, int B, const gpbo_problem* probs, Model* const* ms
     const FitLayout& f = lay[k];
     char* b = g + obase[k];
     M->ctx = c;
+    M->alloc_stream = c->stream;
+    M->alloc_mixed = false;
     M->n = p.n;
     M->d = p.d;
     M->npad = (int)round_up(p.n, NB);
@@ -235,6 +259,16 @@ gpbo_status fit_group(Ctx* c, int B, const gpbo_problem* probs, Model* const* ms
     auto gs = std::make_shared<Model::GroupStatus>();
     gs->dev = (const unsigned char*)(g + ostat);
     gs->nb = nb;
+    gs->ctx = c;
+    size_t got = 0;
+    gs->pinned = pinned_acquire(c, (size_t)nb * STATUS_SLOT, &got);
+    if (gs->pinned) {
+      gs->pinned_bytes = got;
+      HIP_TRY(c, hipMemcpyAsync(gs->pinned, gs->dev, (size_t)nb * STATUS_SLOT,
+                                hipMemcpyDeviceToHost, c->stream));
+      gs->ev = timing_event(c);
+      if (gs->ev) HIP_TRY(c, hipEventRecord(gs->ev, c->stream));
+    }
     for (int k = 0; k < nb; ++k) {
       Model* M = ms[order[k]];
       M->pending = true;
@@ -275,9 +309,14 @@ gpbo_status resolve_pending(Ctx* c, Model* M) {
   Model::GroupStatus& gs = *M->gstat;
   if (!gs.read) {  // every model of the fit call at once
     gs.host.resize((size_t)gs.nb * STATUS_SLOT);
-    HIP_TRY(c, hipMemcpyAsync(gs.host.data(), gs.dev, gs.host.size(), hipMemcpyDeviceToHost,
-                              c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (gs.pinned && gs.ev) {  // copied behind the fit already
+      HIP_TRY(c, hipEventSynchronize(gs.ev));
+      std::memcpy(gs.host.data(), gs.pinned, gs.host.size());
+    } else {
+      HIP_TRY(c, hipMemcpyAsync(gs.host.data(), gs.dev, gs.host.size(), hipMemcpyDeviceToHost,
+                                c->stream));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
     gs.read = true;
   }
   const unsigned char* slot = gs.host.data() + (size_t)M->gslot * STATUS_SLOT;
@@ -320,6 +359,19 @@ void dfree(Ctx* c, void* p) {
     c->alloc.free(p, c->stream, c->alloc.user);
   else
     (void)hipFree(p);
+}
+
+// A later copy into a returned chunk is queued on the same stream behind
+// any copy still in flight, and its reader waits for its own event.
+Model::GroupStatus::~GroupStatus() {
+  if (!ctx) return;
+  if (pinned) {
+    if (ctx->pinned_pool.size() < 64)
+      ctx->pinned_pool.emplace_back(pinned_bytes, pinned);
+    else
+      (void)hipHostFree(pinned);
+  }
+  if (ev) ctx->ev_pool.push_back(ev);
 }
 
 std::shared_ptr<void> dshared(Ctx* c, size_t bytes) {
@@ -404,6 +456,7 @@ gpbo_status gpbo_ctx_destroy(gpbo_ctx c) {
     c->ev_pool.push_back(pr.second);
   }
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  for (auto& pr : c->pinned_pool) (void)hipHostFree(pr.second);
   if (c->red) dfree(c, c->red);
   if (c->desc_buf) dfree(c, c->desc_buf);
   if (c->batch_buf) dfree(c, c->batch_buf);
@@ -603,7 +656,13 @@ gpbo_status gpbo_fit_batched(gpbo_ctx c, int32_t B, const gpbo_problem* probs, g
 gpbo_status gpbo_model_free(gpbo_model M) {
   if (!M) return GPBO_OK;
   DeviceGuard g(M->ctx->device);
-  (void)hipStreamSynchronize(M->ctx->stream);
+  // With the context's allocator the buffers return in the order of the
+  // stream they were allocated on, behind the work queued there; a wait is
+  // needed only when some of them came from another stream than the one the
+  // model's work is queued on now (or without an allocator: hipFree).
+  const Ctx* c = M->ctx;
+  if (!c->has_alloc || M->alloc_mixed || M->alloc_stream != c->stream)
+    (void)hipStreamSynchronize(c->stream);
   M->ctx->live_models.erase(M);
   free_model_buffers(M);
   delete M;

@@ -58,6 +58,10 @@ struct Model {
   double host_stats[S_COUNT] = {0};
   int host_info[2] = {0, 0};
   bool pending = false;         // fitted asynchronously; host_stats / host_info not read yet
+  // Stream the model's device buffers were allocated on, and whether a later
+  // allocation for it used another one (then freeing it waits for the stream).
+  hipStream_t alloc_stream = nullptr;
+  bool alloc_mixed = false;
   // Status region of the asynchronous fit call this model came from (shared
   // by its models: the first status request reads all of them at once).
   struct GroupStatus {
@@ -65,6 +69,15 @@ struct Model {
     int nb = 0;
     bool read = false;
     std::vector<unsigned char> host;     // nb slots once read
+    // The slots copied to pinned host memory right behind the fit, in stream
+    // order, with an event after the copy: a status request then waits for
+    // the event instead of starting a copy and a stream synchronisation
+    // (pinned = nullptr: the request copies and synchronises).
+    Ctx* ctx = nullptr;
+    unsigned char* pinned = nullptr;
+    size_t pinned_bytes = 0;
+    hipEvent_t ev = nullptr;
+    ~GroupStatus();  // returns the pinned chunk and the event to the context
   };
   std::shared_ptr<GroupStatus> gstat;
   int gslot = 0;
@@ -124,6 +137,7 @@ struct Ctx {
   // Optional timing of the scoring kernels (event pairs on the stream).
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<size_t, unsigned char*>> pinned_pool;  // free pinned chunks (size, ptr)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
   bool no_graph = false;  // GPBO_NO_GRAPH=1: never capture batched launches
   int score_path = 0;     // gpbo_score_path

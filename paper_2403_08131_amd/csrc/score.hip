@@ -685,6 +685,8 @@ void ensure_score_operands(Ctx* c, Model* const* models, int B, int prec, hipStr
       if (std::find(need.begin(), need.end(), M) == need.end()) need.push_back(M);
   }
   if (need.empty()) return;
+  for (Model* M : need)
+    if (M->alloc_stream != s) M->alloc_mixed = true;
   const int nb = (int)need.size();
   const int kb = score_kb(prec), PF = prec_pf(prec);
   const size_t es = score_esize(prec), as = prec == GPBO_FP64 ? sizeof(double) : sizeof(float);

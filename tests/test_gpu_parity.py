@@ -302,3 +302,34 @@ def test_fit_not_pd_in_a_later_diagonal_tile(ctx):
     fo = O.fit(good.X, good.y, good.lengthscale, good.kernel, good.signal_var, good.noise_var)
     assert lml[0] == pytest.approx(fo.lml, rel=1e-8, abs=1e-8 * good.n)
     models[0].free()
+
+
+def test_free_without_wait_keeps_queued_work_correct(ctx):
+    """gpbo_model_free hands the buffers back to the allocator in stream
+    order without waiting for the stream: a model freed right after its
+    scoring was queued, and a second model fitted at once (into the memory
+    the allocator hands out again), both score exactly as with a
+    synchronisation before each free."""
+    p1 = I.make_config("c2-s", n=300, m=3000)
+    p2 = I.make_config("c2-s", n=300, m=3000, replicate=1)
+    Xc1, Xc2 = _t(p1.Xc, torch.float32), _t(p2.Xc, torch.float32)
+
+    def args(p):
+        return (_t(p.X), _t(p.y), p.lengthscale, p.kernel, p.signal_var, p.noise_var)
+
+    refs = []
+    for p, Xc in ((p1, Xc1), (p2, Xc2)):
+        m = G.fit(ctx, *args(p))
+        refs.append(G.score(ctx, m, Xc, "fp32"))
+        torch.cuda.synchronize()
+        m.free()
+    m1 = G.fit_async(ctx, *args(p1))
+    o1 = G.score(ctx, m1, Xc1, "fp32")
+    m1.free()  # its fit and scoring are still queued
+    m2 = G.fit_async(ctx, *args(p2))
+    o2 = G.score(ctx, m2, Xc2, "fp32")
+    m2.free()
+    torch.cuda.synchronize()
+    for o, r in ((o1, refs[0]), (o2, refs[1])):
+        for k in ("mu", "sigma", "ei", "argmax"):
+            assert torch.equal(o[k], r[k]), k
