@@ -38,7 +38,7 @@ PEAKS = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}  # dense matrix-core TFLOP
 # runs of this benchmark, scaled by the same counters on a plain copy of known
 # size.  Valid only while the kernel source is unchanged (hash below).
 TRAFFIC = {
-    "kernel_sha": "045d53f7954dac00",
+    "kernel_sha": "70a733d845078fc0",
     "workload": "c2",
     "fetch_kib": 5028.0,       # FETCH_SIZE per dispatch of k_score_fused
     "write_kib": 896.0,        # WRITE_SIZE per dispatch
