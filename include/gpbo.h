@@ -207,6 +207,11 @@ gpbo_status gpbo_model_status_batched(gpbo_ctx ctx, int32_t B, const gpbo_model*
 gpbo_status gpbo_fit_batched(gpbo_ctx ctx, int32_t B, const gpbo_problem* probs,
                              gpbo_model* out, double* lml, int32_t* status);
 
+/* Release a model (NULL is ignored).  Work still queued that uses it may
+ * run on: with a context allocator the buffers go back in the order of the
+ * stream they were allocated on, without a wait, when that is the stream
+ * the model's work is queued on; otherwise (another stream since, or
+ * hipFree) the call first waits for the context's stream. */
 gpbo_status gpbo_model_free(gpbo_model model);
 /* Host copy of the GPBO_NSTATS scalars (synchronises). */
 gpbo_status gpbo_model_stats(gpbo_model model, double* stats);
