@@ -64,10 +64,19 @@ typedef enum { GPBO_KERNEL_SE = 0, GPBO_KERNEL_MATERN52 = 1 } gpbo_kernel;
  * products).  The fit is always float64.
  *   FP64: everything in float64; outputs are double.
  *   FP32: cross-covariance in float32, posterior products on float32 matrix
- *         cores with float32 accumulation; outputs are float.
+ *         cores with float32 accumulation; outputs are float.  A model whose
+ *         K is ill-conditioned (model statistic [7] above
+ *         GPBO_ESCALATE_KINV) is scored with float64 arithmetic instead --
+ *         float64 cross-covariance, mean and matrix-core products, same
+ *         float inputs and outputs -- so that the posterior mean and
+ *         standard deviation stay within 1e-4 (relative) of float64.  The
+ *         decision is taken on the device when the fit's statistics have
+ *         not been read yet.  The large-n path (gpbo_ctx_set_score_path)
+ *         does not escalate.
  *   BF16: cross-covariance computed in float32 and rounded to bfloat16, the
  *         inverse Cholesky factor rounded to bfloat16, products on bfloat16
- *         matrix cores with float32 accumulation; outputs are float.        */
+ *         matrix cores with float32 accumulation; outputs are float.  No
+ *         escalation: errors grow with the conditioning of K.              */
 typedef enum { GPBO_FP64 = 0, GPBO_FP32 = 1, GPBO_BF16 = 2 } gpbo_precision;
 
 /* Optional device allocator.  alloc returns device memory of at least `bytes`
@@ -108,8 +117,14 @@ typedef struct {
 /* Scalars of a fitted model, in the order of gpbo_model_stats:
  * [0] mean of y, [1] scale s_y, [2] f_best = min y, [3] log marginal
  * likelihood of the normalised y, [4] log det K, [5] residual norm
- * |ytilde - K alpha| before refinement, [6] the same after refinement. */
-#define GPBO_NSTATS 7
+ * |ytilde - K alpha| before refinement, [6] the same after refinement,
+ * [7] the mean diagonal of signal_var * K^-1, i.e. signal_var trace(K^-1) / n
+ * (each (K^-1)_ii is the reciprocal of the leave-one-out predictive variance
+ * at x_i; large values mean nearly redundant observations and an
+ * ill-conditioned K).  GPBO_FP32 scoring escalates a model to float64
+ * arithmetic when [7] exceeds GPBO_ESCALATE_KINV (see gpbo_precision). */
+#define GPBO_NSTATS 8
+#define GPBO_ESCALATE_KINV 8.0
 
 const char* gpbo_status_string(gpbo_status s);
 /* Description of the last failure on ctx (or of the last failed context
@@ -232,25 +247,38 @@ gpbo_status gpbo_model_factors(gpbo_ctx ctx, gpbo_model model, double* L, double
  *        (EI = max(f_best - mu, 0) when sigma = 0)
  * Xc: device, m x d, double for GPBO_FP64, float otherwise.
  * mu, sigma, ei: device, m each, double for GPBO_FP64, float otherwise; each
- * may be NULL.  argmax (device int64) and ei_max (device double): the index
- * of the largest EI (lowest index among ties) and its value; both may be
- * NULL, in which case no reduction runs.  m = 0 is allowed (argmax = -1).
- * Asynchronous. */
+ * may be NULL.  argmax (int64) and ei_max (double): the index of the
+ * largest EI (lowest index among ties; NaN never wins) and its value; both
+ * may be NULL, in which case no reduction runs.  Each may be device memory
+ * (written by the queued work: the call is asynchronous) or host memory
+ * (the call then SYNCHRONISES the stream and writes it before returning).
+ * m = 0 is allowed (argmax = -1, ei_max = -inf).
+ * With the environment variable GPBO_DEBUG=1 at context creation the pool
+ * is first checked for NaN and infinity (GPBO_E_NONFINITE; this check
+ * synchronises the stream). */
 gpbo_status gpbo_score(gpbo_ctx ctx, gpbo_model model, int64_t m, const void* Xc,
                        gpbo_precision prec, void* mu, void* sigma, void* ei, int64_t* argmax,
                        double* ei_max);
 
-/* Score B models, each on its own candidate pool, in one persistent launch.
- * m, Xc, ei: host arrays of B entries (Xc[b], ei[b] are device pointers as
- * in gpbo_score; ei[b] or the whole ei array may be NULL).  argmax and ei_max
- * are device arrays of B entries.  prec is GPBO_FP32 or GPBO_BF16.  The
- * launch sequence is captured in a HIP graph on first use of a batch shape
- * (B, precision, tile, candidate tiles, outputs) and replayed for later calls
- * of that shape, also with other models and pools: the kernels read them from
- * descriptors uploaded by each call.  Up to 8 shapes are kept.  Asynchronous. */
+/* Score B models, each on its own candidate pool, in one persistent launch
+ * (the paper runs independent sub-searches in parallel, Sec. IV-D), with
+ * the quantities of gpbo_score per problem.
+ * m, Xc, mu, sigma, ei: host arrays of B entries (Xc[b], mu[b], sigma[b],
+ * ei[b] are device pointers typed as in gpbo_score; any output entry, or a
+ * whole output array, may be NULL).  argmax and ei_max: arrays of B entries,
+ * device memory (asynchronous) or host memory (the call synchronises), each
+ * may be NULL.  With GPBO_FP32, problems above the escalation threshold are
+ * scored by a second persistent launch in float64 arithmetic (see
+ * gpbo_precision); the split is made on the device.  The launch sequence is
+ * captured in a HIP graph on first use of a batch shape (B, precision,
+ * tiles, candidate tiles, outputs) and replayed for later calls of that
+ * shape, also with other models and pools: the kernels read them from
+ * descriptors uploaded by each call.  Up to 8 shapes are kept.  GPBO_DEBUG
+ * checks every pool as gpbo_score does. */
 gpbo_status gpbo_score_batched(gpbo_ctx ctx, int32_t B, const gpbo_model* models,
                                const int64_t* m, const void* const* Xc, gpbo_precision prec,
-                               void* const* ei, int64_t* argmax, double* ei_max);
+                               void* const* mu, void* const* sigma, void* const* ei,
+                               int64_t* argmax, double* ei_max);
 
 /* Top k of v (device, m floats) by (value descending, index ascending); idx
  * is a device array of k int64.  NaN entries never rank.  Asynchronous. */

@@ -145,8 +145,9 @@ gpbo_status run_fit(Ctx* c, const FitDesc* h, const FitDesc* dd, int B, hipStrea
   HIP_TRY(c, hipGetLastError());
   if (s == nullptr || c->no_graph) return GPBO_OK;
   constexpr size_t kMaxGraphs = 8;
-  if (c->fit_graphs.size() >= kMaxGraphs) {  // the oldest goes, once it has run
-    HIP_TRY(c, hipStreamSynchronize(s));
+  if (c->fit_graphs.size() >= kMaxGraphs) {
+    // the oldest goes once every stream it may have been launched on has run it
+    HIP_TRY(c, hipDeviceSynchronize());
     (void)hipGraphExecDestroy(c->fit_graphs.front().second);
     c->fit_graphs.erase(c->fit_graphs.begin());
   }
@@ -365,6 +366,10 @@ void dfree(Ctx* c, void* p) {
 // any copy still in flight, and its reader waits for its own event.
 Model::GroupStatus::~GroupStatus() {
   if (!ctx) return;
+  // the copy into the chunk may still be in flight (a model freed without
+  // asking for its status): the chunk is reused only once it has landed
+  if (pinned && ev && hipEventQuery(ev) != hipSuccess) (void)hipEventSynchronize(ev);
+  if (pinned && !ev) (void)hipStreamSynchronize(ctx->stream);
   if (pinned) {
     if (ctx->pinned_pool.size() < 64)
       ctx->pinned_pool.emplace_back(pinned_bytes, pinned);
@@ -430,6 +435,7 @@ gpbo_status gpbo_ctx_create(int32_t device, void* stream, const gpbo_allocator* 
   c->stream = (hipStream_t)stream;
   c->num_cu = prop.multiProcessorCount;
   if (const char* ng = std::getenv("GPBO_NO_GRAPH")) c->no_graph = ng[0] == '1';
+  if (const char* dbg = std::getenv("GPBO_DEBUG")) c->debug = dbg[0] == '1';
   if (alloc) {
     c->alloc = *alloc;
     c->has_alloc = true;
@@ -690,6 +696,7 @@ gpbo_status gpbo_model_shape(gpbo_model M, int32_t* n, int32_t* d) {
 gpbo_status gpbo_model_factors(gpbo_ctx c, gpbo_model M, double* L, double* Linv, double* alpha) {
   if (!c || !M) return GPBO_E_INVALID_ARG;
   DeviceGuard g(c->device);
+  if (M->alloc_stream != c->stream) M->alloc_mixed = true;
   const size_t n = M->n, np = M->npad;
   if (L)
     HIP_TRY(c, hipMemcpy2DAsync(L, n * sizeof(double), M->L, np * sizeof(double), n * sizeof(double),
@@ -717,6 +724,40 @@ static gpbo_status ensure_red(Ctx* c, size_t bytes) {
   return c->red ? GPBO_OK : fail(c, GPBO_E_OOM, "scratch allocation of %zu bytes failed", bytes);
 }
 
+// Whether a kernel may write to p: device (or managed) memory.  Anything else
+// (pageable or pinned host memory) is written by a copy after the stream is
+// synchronised.
+static bool device_writable(const void* p) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();  // ordinary host memory: not known to HIP
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// A model touched on another stream than the one its buffers came from is
+// freed only after a wait (gpbo_model_free).
+static void note_stream(Model* M, hipStream_t s) {
+  if (M->alloc_stream != s) M->alloc_mixed = true;
+}
+
+// GPBO_DEBUG: reject candidate pools that hold NaN or infinity
+// (synchronises).  flag: a device int of scratch.
+static gpbo_status debug_check_pool(Ctx* c, const void* Xc, int64_t count, bool dbl, int* flag,
+                                    int which) {
+  launch_check_finite(Xc, count, dbl ? 1 : 0, flag, c->stream);
+  int h = 0;
+  HIP_TRY(c, hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (h) {
+    if (which >= 0)
+      return fail(c, GPBO_E_NONFINITE, "candidate pool %d holds a non-finite value", which);
+    return fail(c, GPBO_E_NONFINITE, "the candidate pool holds a non-finite value");
+  }
+  return GPBO_OK;
+}
+
 gpbo_status gpbo_score(gpbo_ctx c, gpbo_model M, int64_t m, const void* Xc, gpbo_precision prec,
                        void* mu, void* sigma, void* ei, int64_t* argmax, double* ei_max) {
   if (!c) return GPBO_E_INVALID_ARG;
@@ -727,9 +768,25 @@ gpbo_status gpbo_score(gpbo_ctx c, gpbo_model M, int64_t m, const void* Xc, gpbo
     return fail(c, GPBO_E_INVALID_ARG, "unknown precision %d", (int)prec);
   DeviceGuard g(c->device);
   hipStream_t s = c->stream;
-  if (m == 0) {
-    if (argmax || ei_max) launch_argmax_final(nullptr, nullptr, 0, argmax, ei_max, s);
+  note_stream(M, s);
+  // argmax / ei_max in host memory: the reduction writes device scratch,
+  // copied out after a synchronisation
+  const bool host_am = argmax && !device_writable(argmax);
+  const bool host_em = ei_max && !device_writable(ei_max);
+  const bool host_out = host_am || host_em;
+  if (m == 0) {  // argmax -1, EI maximum -inf
+    if (!argmax && !ei_max) return GPBO_OK;
+    gpbo_status st = ensure_red(c, 256);
+    if (st != GPBO_OK) return st;
+    int64_t* am0 = host_am ? (int64_t*)c->red : argmax;
+    double* em0 = host_em ? (double*)((char*)c->red + 8) : ei_max;
+    launch_argmax_final(nullptr, nullptr, 0, am0, em0, s);
     HIP_TRY(c, hipGetLastError());
+    if (host_out) {
+      if (host_am) HIP_TRY(c, hipMemcpyAsync(argmax, am0, 8, hipMemcpyDeviceToHost, s));
+      if (host_em) HIP_TRY(c, hipMemcpyAsync(ei_max, em0, 8, hipMemcpyDeviceToHost, s));
+      HIP_TRY(c, hipStreamSynchronize(s));
+    }
     return GPBO_OK;
   }
   // Path: the chunked path for float32 once n is large (the fused kernel's
@@ -744,34 +801,59 @@ gpbo_status gpbo_score(gpbo_ctx c, gpbo_model M, int64_t m, const void* Xc, gpbo
     return fail(c, GPBO_E_UNSUPPORTED, "n=%d is too large for the fused scoring kernel at this precision",
                 M->n);
   const bool large = path == GPBO_PATH_LARGE;
+  // Escalation of the fused float32 path to float64 arithmetic on an
+  // ill-conditioned K: decided here when the fit's statistics are known,
+  // else on the device (both kernels queued, one of them idles).
+  const int tm64 = prec == GPBO_FP32 && !large ? score_tile_m64(M->n, M->d) : 0;
+  int esc = 0;  // 0: float32 only; 1: float64 only; 2: decided on the device
+  if (tm64 > 0) esc = M->pending ? 2 : (escalate_fp64(M->host_stats[S_KINV]) ? 1 : 0);
   {
     Model* one[1] = {M};
-    ensure_score_operands(c, one, 1, prec, s);
+    if (esc != 1) ensure_score_operands(c, one, 1, prec, s);
+    if (esc != 0) ensure_score_operands(c, one, 1, GPBO_FP64, s);
   }
-  if (!M->blk_obs || !M->blk_score[prec])
+  if (!M->blk_obs || (esc != 1 && !M->blk_score[prec]) || (esc != 0 && !M->blk_score[GPBO_FP64]))
     return fail(c, GPBO_E_OOM, "device allocation of the score operands failed (n=%d)", M->n);
-  const int npj = M->pk_npj[prec];
-  const int64_t tiles = large ? large_partials(npj, m) : ceil_div(m, tm);
+  const int npj = M->pk_npj[esc == 1 ? GPBO_FP64 : prec];
+  const int64_t tiles32 = large ? large_partials(npj, m) : (esc == 1 ? 0 : ceil_div(m, tm));
+  const int64_t tiles64 = esc != 0 ? ceil_div(m, tm64) : 0;
+  const int64_t tiles = std::max(tiles32, tiles64);
   const size_t part_bytes = round_up((size_t)tiles * 16, 256);
   const size_t ws_bytes = large ? large_scratch_bytes(M->n, npj, m) : 0;
-  double* pv = nullptr;
-  int64_t* pi = nullptr;
-  if (argmax || ei_max || ws_bytes) {
-    gpbo_status st = ensure_red(c, part_bytes + ws_bytes);
+  const size_t tail_bytes = 256;  // host-output staging and the debug flag
+  gpbo_status st = ensure_red(c, part_bytes + ws_bytes + tail_bytes);
+  if (st != GPBO_OK) return st;
+  char* tail = (char*)c->red + part_bytes + ws_bytes;
+  int64_t* am_dev = host_am ? (int64_t*)tail : argmax;
+  double* em_dev = host_em ? (double*)(tail + 8) : ei_max;
+  if (c->debug && m > 0) {
+    st = debug_check_pool(c, Xc, m * M->d, prec == GPBO_FP64, (int*)(tail + 16), -1);
     if (st != GPBO_OK) return st;
   }
-  if (argmax || ei_max) {
+  auto finish_host = [&]() -> gpbo_status {
+    if (!host_out) return GPBO_OK;
+    if (host_am) HIP_TRY(c, hipMemcpyAsync(argmax, am_dev, 8, hipMemcpyDeviceToHost, s));
+    if (host_em) HIP_TRY(c, hipMemcpyAsync(ei_max, em_dev, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return GPBO_OK;
+  };
+  double* pv = nullptr;
+  int64_t* pi = nullptr;
+  if (am_dev || em_dev) {
     pv = (double*)c->red;
     pi = (int64_t*)((double*)c->red + tiles);
   }
-  ScoreArgs j = make_score_args(M, prec, large ? 0 : tm);
-  j.m = m;
-  j.Xc = Xc;
-  j.mu = mu;
-  j.sigma = sigma;
-  j.ei = ei;
-  j.part_v = pv;
-  j.part_i = pi;
+  auto args = [&](int p, int t) {
+    ScoreArgs j = make_score_args(M, p, t);
+    j.m = m;
+    j.Xc = Xc;
+    j.mu = mu;
+    j.sigma = sigma;
+    j.ei = ei;
+    j.part_v = pv;
+    j.part_i = pi;
+    return j;
+  };
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->timing && !large) {
     e0 = timing_event(c);
@@ -779,7 +861,7 @@ gpbo_status gpbo_score(gpbo_ctx c, gpbo_model M, int64_t m, const void* Xc, gpbo
     HIP_TRY(c, hipEventRecord(e0, s));
   }
   if (large) {
-    launch_score_large(j, (char*)c->red + part_bytes, s, [&](int w) {
+    launch_score_large(args(prec, 0), (char*)c->red + part_bytes, s, [&](int w) {
       if (!c->timing) return;
       if (w == 0) {
         e0 = timing_event(c);
@@ -791,20 +873,26 @@ gpbo_status gpbo_score(gpbo_ctx c, gpbo_model M, int64_t m, const void* Xc, gpbo
       }
     });
   } else {
-    launch_score(j, prec, tm, s);
+    if (esc == 0) launch_score(args(prec, tm), prec, tm, s);
+    else if (esc == 1) launch_score(args(GPBO_FP64, tm64), P_F64IO32, tm64, s);
+    else launch_score_escalated(args(prec, tm), tm, args(GPBO_FP64, tm64), tm64, s);
     if (c->timing) {
       HIP_TRY(c, hipEventRecord(e1, s));
       c->ev_pending.emplace_back(e0, e1);
     }
   }
-  if (pv) launch_argmax_final(pv, pi, tiles, argmax, ei_max, s);
+  if (pv) {
+    if (esc == 2) launch_argmax_gated(pv, pi, tiles32, tiles64, M->stats, am_dev, em_dev, s);
+    else launch_argmax_final(pv, pi, esc == 1 ? tiles64 : tiles32, am_dev, em_dev, s);
+  }
   HIP_TRY(c, hipGetLastError());
-  return GPBO_OK;
+  return finish_host();
 }
 
 gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, const int64_t* m,
-                               const void* const* Xc, gpbo_precision prec, void* const* ei,
-                               int64_t* argmax, double* ei_max) {
+                               const void* const* Xc, gpbo_precision prec, void* const* mu,
+                               void* const* sigma, void* const* ei, int64_t* argmax,
+                               double* ei_max) {
   if (!c) return GPBO_E_INVALID_ARG;
   if (B < 0 || (B > 0 && (!models || !m || !Xc)))
     return fail(c, GPBO_E_INVALID_ARG, "invalid batch arguments");
@@ -817,6 +905,9 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
     if (!models[b]) return fail(c, GPBO_E_INVALID_ARG, "model %d is NULL", b);
     if (m[b] < 0 || (m[b] > 0 && !Xc[b])) return fail(c, GPBO_E_INVALID_ARG, "pool %d is invalid", b);
   }
+  for (int b = 0; b < B; ++b) note_stream(models[b], s);
+  const bool host_am = argmax && !device_writable(argmax);
+  const bool host_em = ei_max && !device_writable(ei_max);
   // Tile size: every candidate tile size whose LDS footprint fits the largest
   // problem is a candidate; the autotuner times them on this batch shape once.
   int nmax = 0, dmax = 0;
@@ -830,22 +921,46 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
     if (score_smem(prec, nmax, dmax, tm) + 4096 <= 160 * 1024) cands.push_back(tm);
   if (cands.empty())
     return fail(c, GPBO_E_UNSUPPORTED, "n=%d is too large for the batched scoring kernel", nmax);
+  // The float32 path escalates ill-conditioned problems to float64
+  // arithmetic (a second persistent launch over those problems, chosen on
+  // the device from each fit's conditioning statistic): its tile size is the
+  // largest with two workgroups per CU, else one.
+  int tm64 = 0, per_cu64 = 0;
+  size_t smem64 = 0;
+  if (prec == GPBO_FP32) {
+    for (int pc : {2, 1}) {
+      for (int tm : {32, 16})
+        if (pc * (score_smem(GPBO_FP64, nmax, dmax, tm) + 4096) <= 160 * 1024) {
+          tm64 = tm;
+          per_cu64 = pc;
+          break;
+        }
+      if (tm64) break;
+    }
+  }
+  const bool esc = tm64 > 0;
   {
     std::vector<Model*> mp(models, models + B);
     ensure_score_operands(c, mp.data(), B, prec, s);
+    if (esc) ensure_score_operands(c, mp.data(), B, GPBO_FP64, s);
   }
   for (int b = 0; b < B; ++b)
-    if (!models[b]->blk_obs || !models[b]->blk_score[prec])
+    if (!models[b]->blk_obs || !models[b]->blk_score[prec] ||
+        (esc && !models[b]->blk_score[GPBO_FP64]))
       return fail(c, GPBO_E_OOM, "device allocation of the score operands failed (problem %d)", b);
   // problems in decreasing n: the costliest tiles are dispatched first
   std::vector<int> order(B);
   for (int b = 0; b < B; ++b) order[b] = b;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return models[a]->n > models[b]->n; });
-  int64_t max_tiles = 0;
-  for (int b = 0; b < B; ++b) max_tiles += ceil_div(std::max<int64_t>(m[b], 1), 16);
+  // argmax partials: room for the smallest tile (16 candidates) of every problem
+  std::vector<int64_t> poff(B + 1, 0);
+  for (int k = 0; k < B; ++k) poff[k + 1] = poff[k] + ceil_div(m[order[k]], 16);
+  const int64_t max_tiles = poff[B];
   const size_t desc_bytes = round_up(B * sizeof(ScoreArgs), 256);
-  const size_t need = desc_bytes + 256 + (size_t)max_tiles * 16;
+  const size_t plan_bytes = round_up(batch_plan_bytes(B), 256);
+  const size_t out_bytes = round_up((size_t)B * 16 + 16, 256);  // host-output staging, debug flag
+  const size_t need = 2 * desc_bytes + 256 + plan_bytes + out_bytes + (size_t)max_tiles * 16;
   if (c->batch_buf_bytes < need) {
     HIP_TRY(c, hipStreamSynchronize(s));
     if (c->batch_buf) dfree(c, c->batch_buf);
@@ -855,51 +970,91 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
   }
   unsigned char* base = (unsigned char*)c->batch_buf;
   ScoreArgs* dd = (ScoreArgs*)base;
-  unsigned* counter = (unsigned*)(base + desc_bytes);
-  double* pv = (double*)(base + desc_bytes + 256);
+  ScoreArgs* dd64 = (ScoreArgs*)(base + desc_bytes);
+  unsigned* counters = (unsigned*)(base + 2 * desc_bytes);
+  void* plan = base + 2 * desc_bytes + 256;
+  unsigned char* outs = base + 2 * desc_bytes + 256 + plan_bytes;
+  double* pv = (double*)(outs + out_bytes);
   int64_t* pi = (int64_t*)(pv + max_tiles);
-  auto build = [&](int tm, std::vector<ScoreArgs>& h, int64_t& total, size_t& smem) {
+  int64_t* am_dev = host_am ? (int64_t*)outs : argmax;
+  double* em_dev = host_em ? (double*)(outs + 8 * (size_t)B) : ei_max;
+  if (c->debug)
+    for (int b = 0; b < B; ++b)
+      if (m[b] > 0) {
+        const gpbo_status st = debug_check_pool(c, Xc[b], m[b] * models[b]->d, prec == GPBO_FP64,
+                                                (int*)(outs + 16 * (size_t)B), b);
+        if (st != GPBO_OK) return st;
+      }
+  auto build = [&](int tm, std::vector<ScoreArgs>& h, std::vector<ScoreArgs>& h64, size_t& smem) {
     h.clear();
-    total = 0;
+    h64.clear();
     smem = 0;
     for (int k = 0; k < B; ++k) {
       const int b = order[k];
       ScoreArgs a = make_score_args(models[b], prec, tm);
       a.m = m[b];
       a.Xc = Xc[b];
-      a.mu = nullptr;
-      a.sigma = nullptr;
+      a.mu = mu ? mu[b] : nullptr;
+      a.sigma = sigma ? sigma[b] : nullptr;
       a.ei = ei ? ei[b] : nullptr;
-      a.part_v = pv + total;
-      a.part_i = pi + total;
-      a.tile_begin = total;
+      a.part_v = pv + poff[k];
+      a.part_i = pi + poff[k];
       a.slot = b;
-      total += ceil_div(m[b], tm);
       smem = std::max(smem, score_smem(prec, a.n, a.d, tm));
       h.push_back(a);
+      if (esc) {
+        ScoreArgs a64 = make_score_args(models[b], GPBO_FP64, tm64);
+        a64.m = a.m;
+        a64.Xc = a.Xc;
+        a64.mu = a.mu;
+        a64.sigma = a.sigma;
+        a64.ei = a.ei;
+        a64.part_v = a.part_v;
+        a64.part_i = a.part_i;
+        a64.slot = b;
+        smem64 = std::max(smem64, score_smem(GPBO_FP64, a64.n, a64.d, tm64));
+        h64.push_back(a64);
+      }
     }
   };
   const int per_cu = 2;  // LDS-limited residency of the scoring workgroup
-  const int grid = c->num_cu * per_cu;
-  char kbuf[160];
-  snprintf(kbuf, sizeof kbuf, "batched:gfx950:hip%d:p%d:B%d:n%d:d%d", HIP_VERSION, (int)prec, B,
-           (int)round_up(nmax, 64), dmax);
+  BatchLaunch L;
+  L.dd = dd;
+  L.dd64 = esc ? dd64 : nullptr;
+  L.B = B;
+  L.prec = prec;
+  L.tm64 = esc ? tm64 : 16;
+  L.grid = c->num_cu * per_cu;
+  L.grid64 = c->num_cu * std::max(per_cu64, 1);
+  L.plan = plan;
+  L.counters = counters;
+  L.argmax = am_dev;
+  L.ei_max = em_dev;
   {
     int64_t max_items = 0;
     for (int b = 0; b < B; ++b) max_items += ceil_div(m[b], 16);
-    if (max_items + grid >= (int64_t)INT_MAX)
+    if (max_items + std::max(L.grid, L.grid64) >= (int64_t)INT_MAX)
       return fail(c, GPBO_E_UNSUPPORTED, "too many candidate tiles in one batch (%lld)",
                   (long long)max_items);
   }
-  std::vector<ScoreArgs> hh;  // source of the descriptor copies of the timing runs
+  char kbuf[160];
+  snprintf(kbuf, sizeof kbuf, "batched:gfx950:hip%d:p%d:B%d:n%d:d%d", HIP_VERSION, (int)prec, B,
+           (int)round_up(nmax, 64), dmax);
+  std::vector<ScoreArgs> hh, hh64;  // sources of the descriptor copies of the timing runs
   bool tuned = false;
   const int tm = autotune_pick(c, kbuf, cands, [&](int cand) {
-    int64_t tot;
     size_t sm;
     (void)hipStreamSynchronize(s);  // hh is reused by the next run
-    build(cand, hh, tot, sm);
+    build(cand, hh, hh64, sm);
     (void)hipMemcpyAsync(dd, hh.data(), hh.size() * sizeof(ScoreArgs), hipMemcpyHostToDevice, s);
-    launch_score_batched(dd, B, tot, counter, prec, cand, sm, grid, argmax, ei_max, s);
+    if (esc)
+      (void)hipMemcpyAsync(dd64, hh64.data(), hh64.size() * sizeof(ScoreArgs),
+                           hipMemcpyHostToDevice, s);
+    BatchLaunch T = L;
+    T.tm = cand;
+    T.smem = sm;
+    T.smem64 = smem64;
+    launch_score_batched(T, s);
     tuned = true;
   });
   if (tuned) HIP_TRY(c, hipStreamSynchronize(s));
@@ -908,25 +1063,35 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
   // The launch sequence reads everything problem-specific from them, so its
   // graph depends only on the batch shape below: calls with new models or
   // pools of the same shape (the next iteration of a search) replay it.
-  std::vector<ScoreArgs> h;
-  int64_t total = 0;
+  std::vector<ScoreArgs> h, h64;
   size_t smem = 0;
-  build(tm, h, total, smem);
-  // work items are counted in 32 bits (every workgroup pops one past the end)
-  if (total + grid >= (int64_t)INT_MAX)
-    return fail(c, GPBO_E_UNSUPPORTED, "too many candidate tiles in one batch (%lld)", (long long)total);
+  build(tm, h, h64, smem);
+  L.tm = tm;
+  L.smem = smem;
+  L.smem64 = smem64;
   HIP_TRY(c, hipMemcpyAsync(dd, h.data(), h.size() * sizeof(ScoreArgs), hipMemcpyHostToDevice, s));
-  const std::vector<uint64_t> key = {(uint64_t)B, (uint64_t)prec, (uint64_t)tm, (uint64_t)total,
-                                     (uint64_t)smem, (uint64_t)grid,
-                                     (uint64_t)(uintptr_t)argmax, (uint64_t)(uintptr_t)ei_max,
+  if (esc)
+    HIP_TRY(c, hipMemcpyAsync(dd64, h64.data(), h64.size() * sizeof(ScoreArgs),
+                              hipMemcpyHostToDevice, s));
+  auto finish_host = [&]() -> gpbo_status {
+    if (!host_am && !host_em) return GPBO_OK;
+    if (host_am) HIP_TRY(c, hipMemcpyAsync(argmax, am_dev, 8 * (size_t)B, hipMemcpyDeviceToHost, s));
+    if (host_em) HIP_TRY(c, hipMemcpyAsync(ei_max, em_dev, 8 * (size_t)B, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return GPBO_OK;
+  };
+  const std::vector<uint64_t> key = {(uint64_t)B, (uint64_t)prec, (uint64_t)tm, (uint64_t)tm64,
+                                     (uint64_t)max_tiles, (uint64_t)smem, (uint64_t)smem64,
+                                     (uint64_t)L.grid, (uint64_t)L.grid64,
+                                     (uint64_t)(uintptr_t)am_dev, (uint64_t)(uintptr_t)em_dev,
                                      (uint64_t)(uintptr_t)s, (uint64_t)(uintptr_t)base};
   // With kernel timing on, every call launches eagerly so that events can
-  // bracket the scoring kernel alone.
+  // bracket the scoring kernels alone.
   if (!c->timing)
     for (auto& kv : c->batch_graphs)
       if (kv.first == key) {
         HIP_TRY(c, hipGraphLaunch(kv.second, s));
-        return GPBO_OK;
+        return finish_host();
       }
   // an eager launch (it also sets the kernels' LDS limits), then the capture
   hipEvent_t e0 = nullptr;
@@ -940,19 +1105,19 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
       c->ev_pending.emplace_back(e0, e1);
     }
   };
-  launch_score_batched(dd, B, total, counter, prec, tm, smem, grid, argmax, ei_max, s,
-                       c->timing ? &mark : nullptr);
+  launch_score_batched(L, s, c->timing ? &mark : nullptr);
   HIP_TRY(c, hipGetLastError());
-  if (c->timing || s == nullptr || c->no_graph) return GPBO_OK;
+  if (c->timing || s == nullptr || c->no_graph) return finish_host();
   constexpr size_t kMaxGraphs = 8;
-  if (c->batch_graphs.size() >= kMaxGraphs) {  // the oldest goes, once it has run
-    HIP_TRY(c, hipStreamSynchronize(s));
+  if (c->batch_graphs.size() >= kMaxGraphs) {
+    // the oldest goes once every stream it may have been launched on has run it
+    HIP_TRY(c, hipDeviceSynchronize());
     (void)hipGraphExecDestroy(c->batch_graphs.front().second);
     c->batch_graphs.erase(c->batch_graphs.begin());
   }
   hipGraph_t graph = nullptr;
   HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  launch_score_batched(dd, B, total, counter, prec, tm, smem, grid, argmax, ei_max, s);
+  launch_score_batched(L, s);
   HIP_TRY(c, hipStreamEndCapture(s, &graph));
   hipGraphExec_t exec = nullptr;
   hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -960,7 +1125,7 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
   if (e == hipSuccess) {
     c->batch_graphs.emplace_back(key, exec);
   }
-  return GPBO_OK;
+  return finish_host();
 }
 
 gpbo_status gpbo_topk(gpbo_ctx c, int64_t m, const float* v, int64_t k, int64_t* idx) {

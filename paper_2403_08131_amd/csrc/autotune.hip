@@ -10,6 +10,7 @@
 // value is not among the current candidates is ignored.
 #include <cstdio>
 #include <cstdlib>
+#include <filesystem>
 #include <fstream>
 #include <map>
 #include <mutex>
@@ -55,10 +56,10 @@ void save_cache() {
   const std::string path = cache_path();
   if (path.empty()) return;
   const size_t slash = path.rfind('/');
-  if (slash != std::string::npos) {
-    const std::string dir = path.substr(0, slash);
-    std::string cmd = "mkdir -p '" + dir + "' 2>/dev/null";
-    (void)std::system(cmd.c_str());
+  if (slash != std::string::npos && slash > 0) {
+    // create the directory chain with mkdir(2); the library starts no process
+    std::error_code ec;
+    std::filesystem::create_directories(path.substr(0, slash), ec);
   }
   const std::string tmp = path + ".tmp";
   {

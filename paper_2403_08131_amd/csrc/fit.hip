@@ -733,15 +733,19 @@ __global__ void __launch_bounds__(256) k_cast_linv(const FitDesc* __restrict__ D
     P.L32[i] = (float)P.Linv[i];
 }
 
-// Vectors of the alpha solve, by index into the work area.
-enum { V_W = 0, V_R = 1, V_PART = 4 };
+// Vectors of the alpha solve, by index into the work area (V_Q: the row
+// sums of squares of the inverse factor).
+enum { V_W = 0, V_R = 1, V_Q = 2, V_PART = 4 };
 __device__ __forceinline__ double* wvec(const FitDesc& P, int v) {
   return v < 0 ? (v == -1 ? P.yt : P.alpha) : P.work + (int64_t)v * P.npad;
 }
 
 // y = Linv x (lower triangular; float64, or the float32 copy with float32
-// accumulation when refining).  One wave per row.
-__global__ void __launch_bounds__(256) k_trmv(const FitDesc* __restrict__ Ds, int xv, int yv) {
+// accumulation when refining).  One wave per row.  With ssq = 1 the row's
+// sum of squares sum_j Linv_ij^2 also goes to work vector V_Q: summed over
+// the rows it is trace(K^-1) = |Linv|_F^2.
+__global__ void __launch_bounds__(256) k_trmv(const FitDesc* __restrict__ Ds, int xv, int yv,
+                                              int ssq) {
   const FitDesc& P = Ds[blockIdx.z];
   const int lane = threadIdx.x % 64;
   const int row = blockIdx.x * 4 + threadIdx.x / 64;
@@ -749,23 +753,40 @@ __global__ void __launch_bounds__(256) k_trmv(const FitDesc* __restrict__ Ds, in
   const int n = P.n, npad = P.npad;
   const double* x = wvec(P, xv);
   double* y = wvec(P, yv);
-  double r = 0.0;
+  double r = 0.0, q = 0.0;
   if (P.refine) {
-    float s = 0.0f;
+    float s = 0.0f, s2 = 0.0f;
     if (row < n)
 #pragma unroll 8
-      for (int j = lane; j <= row; j += 64) s += P.L32[(int64_t)row * npad + j] * (float)x[j];
+      for (int j = lane; j <= row; j += 64) {
+        const float l = P.L32[(int64_t)row * npad + j];
+        s += l * (float)x[j];
+        if (ssq) s2 = fmaf(l, l, s2);
+      }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (ssq)
+      for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
     r = s;
+    q = s2;
   } else {
-    double s = 0.0;
+    double s = 0.0, s2 = 0.0;
     if (row < n)
 #pragma unroll 8
-      for (int j = lane; j <= row; j += 64) s += P.Linv[(int64_t)row * npad + j] * x[j];
+      for (int j = lane; j <= row; j += 64) {
+        const double l = P.Linv[(int64_t)row * npad + j];
+        s += l * x[j];
+        if (ssq) s2 = fma(l, l, s2);
+      }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (ssq)
+      for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
     r = s;
+    q = s2;
   }
-  if (lane == 0) y[row] = row < n ? r : 0.0;
+  if (lane == 0) {
+    y[row] = row < n ? r : 0.0;
+    if (ssq) P.work[(int64_t)V_Q * npad + row] = row < n ? q : 0.0;
+  }
 }
 
 // y = Linv^T x: y_j = sum_{i >= j} Linv_ij x_i.  A workgroup owns 16
@@ -858,7 +879,11 @@ __global__ void __launch_bounds__(256) k_residual(const FitDesc* __restrict__ Ds
 // 16 waves per problem (the partial columns of a row are summed by its
 // thread).
 // With lml = 1 it also writes the log marginal likelihood and log det K:
-// LML = -ytilde^T alpha / 2 - sum log L_ii - n/2 log 2 pi.
+// LML = -ytilde^T alpha / 2 - sum log L_ii - n/2 log 2 pi, and the mean
+// diagonal of sf2 K^-1 (sf2 trace(K^-1) / n, from the row sums of squares of
+// the inverse factor): (K^-1)_ii is the reciprocal of the leave-one-out
+// predictive variance at x_i, so the mean is large when observations are
+// nearly redundant, i.e. when K is ill-conditioned.
 constexpr int RESF_W = 16;
 __global__ void __launch_bounds__(64 * RESF_W) k_res_finish(const FitDesc* __restrict__ Ds,
                                                             int slot, int lml) {
@@ -866,16 +891,19 @@ __global__ void __launch_bounds__(64 * RESF_W) k_res_finish(const FitDesc* __res
   const FitDesc& P = Ds[blockIdx.z];
   if (fit_failed(P.info)) return;
   if (lml) {
-    double q = 0.0, ld = 0.0;
+    double q = 0.0, ld = 0.0, tr = 0.0;
     for (int i = threadIdx.x; i < P.n; i += 64 * RESF_W) {
       q += P.yt[i] * P.alpha[i];
       ld += log(P.L[(int64_t)i * P.npad + i]);
+      tr += P.work[(int64_t)V_Q * P.npad + i];
     }
     q = block_sum_w<RESF_W>(q, red);
     ld = block_sum_w<RESF_W>(ld, red);
+    tr = block_sum_w<RESF_W>(tr, red);
     if (threadIdx.x == 0) {
       P.stats[S_LOGDET] = 2.0 * ld;
       P.stats[S_LML] = -0.5 * q - ld - 0.5 * P.n * log(2.0 * 3.14159265358979323846);
+      P.stats[S_KINV] = P.sf2 * tr / P.n;
     }
   }
   double* r = P.work + (int64_t)V_R * P.npad;
@@ -989,12 +1017,12 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   if (any_refine) hipLaunchKernelGGL(k_cast_linv, dim3(gz, 1, Bz), dim3(256), 0, s, dd);
   const unsigned g_rows = (unsigned)ceil_div(npmax, 4), g_cols = (unsigned)ceil_div(npmax, TT_COLS);
   // alpha = Linv^T (Linv ytilde), then one residual-and-correction step
-  hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, -1, (int)V_W);
+  hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, -1, (int)V_W, 1);
   hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(64 * TRMV_T_WAVES), 0, s, dd, (int)V_W, -2, 0);
   const dim3 g_res((unsigned)ceil_div(nmax, KR), (unsigned)chmax, Bz);
   hipLaunchKernelGGL(k_residual, g_res, dim3(256), 0, s, dd);
   hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(64 * RESF_W), 0, s, dd, (int)S_RES0, 0);
-  hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, (int)V_R, (int)V_W);
+  hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, (int)V_R, (int)V_W, 0);
   // alpha += Linv^T (Linv r)
   hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(64 * TRMV_T_WAVES), 0, s, dd, (int)V_W, -2, 1);
   hipLaunchKernelGGL(k_residual, g_res, dim3(256), 0, s, dd);

@@ -33,8 +33,29 @@ enum StatIdx {
   S_LOGDET = 4,
   S_RES0 = 5,
   S_RES1 = 6,
+  S_KINV = 7,  // mean diagonal of sf2 K^-1 (conditioning measure)
   S_COUNT = 8
 };
+
+// Precision escalation of the float32 scoring path.  Contractions in float32
+// carry relative errors of a few units of 2^-24 in the cross-covariance and
+// the inverse-factor products; the posterior mean and variance amplify them
+// by the conditioning of K.  The fit measures that conditioning as the mean
+// diagonal of sf2 K^-1 (stats[S_KINV]; each (K^-1)_ii is the reciprocal of
+// the leave-one-out predictive variance at x_i).  Above the threshold the
+// float32 path scores the problem with float64 arithmetic instead (same
+// inputs and output types).  The threshold is calibrated against the float64
+// definition on the seeded batched workloads (192 sub-searches, d = 2..12,
+// n = 16..400, literal lengthscales): every problem below it stays within
+// 2e-5 of the float64 posterior with float32 arithmetic, and every problem
+// whose float32 error exceeds 3e-5 lies above it.
+constexpr double kEscalateKinv = 8.0;
+static_assert(kEscalateKinv == GPBO_ESCALATE_KINV, "escalation threshold of the header");
+// Internal precision of an escalated float32 problem: float64 arithmetic and
+// float64 operands (packed inverse factor, alpha, scaled observations), with
+// the float32 candidate coordinates and outputs of the float32 path.
+constexpr int P_F64IO32 = 3;
+__host__ __device__ inline bool escalate_fp64(double kinv) { return kinv > kEscalateKinv; }
 
 struct Ctx;
 
@@ -140,6 +161,7 @@ struct Ctx {
   std::vector<std::pair<size_t, unsigned char*>> pinned_pool;  // free pinned chunks (size, ptr)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
   bool no_graph = false;  // GPBO_NO_GRAPH=1: never capture batched launches
+  bool debug = false;     // GPBO_DEBUG=1: scoring checks its candidates for non-finite values
   int score_path = 0;     // gpbo_score_path
   // Models and MLPs alive on this context (destroyed with it).
   std::unordered_set<Model*> live_models;
@@ -225,8 +247,9 @@ struct ScoreArgs {
   void* ei;
   double* part_v;                  // argmax partials, one (value, index) pair per tile
   int64_t* part_i;
-  int64_t tile_begin;              // batched launch: first work item of this problem
   int slot;                        // batched launch: index of this problem's outputs
+  int gate;                        // single launch: 0 = always score; 1 = only if the model
+                                   // is not escalated to float64; 2 = only if it is
 };
 int score_tile_m(int prec, int n, int d);  // candidates per workgroup (0 = too large)
 size_t score_smem(int prec, int n, int d, int tile_m);
@@ -242,15 +265,46 @@ void launch_score_large(const ScoreArgs& a, void* scratch, hipStream_t s,
                         const std::function<void(int)>& mark);
 void launch_argmax_final(const double* part_v, const int64_t* part_i, int64_t nparts,
                          int64_t* argmax, double* ei_max, hipStream_t s);
-// Batched scoring: one persistent launch over the (problem, tile) items of B
-// problems (descriptors in device memory, ordered largest first), then a
-// per-problem argmax.  counter: one device uint, reset by the sequence itself.
-// mark (may be NULL): (*mark)(0) / (*mark)(1) right before / after the
-// scoring kernel, for timing.
-void launch_score_batched(const ScoreArgs* dd, int B, int64_t total_items, unsigned* counter,
-                          int prec, int tile_m, size_t smem, int grid, int64_t* argmax,
-                          double* ei_max, hipStream_t s,
+// The float32 path escalated to float64 arithmetic on one problem (single
+// launch, gate 0 or 2): candidates per workgroup and LDS bytes.
+int score_tile_m64(int n, int d);
+// Single launch of the float32 path when the model's escalation is decided
+// on the device (its fit's statistics not read yet): the float32 kernel
+// (gate 1) and the float64 kernel (gate 2) are both queued and each
+// workgroup of the one that does not apply returns at once.
+void launch_score_escalated(const ScoreArgs& a32, int tm32, const ScoreArgs& a64, int tm64,
+                            hipStream_t s);
+// Final argmax over the partials of whichever kernel ran.
+void launch_argmax_gated(const double* part_v, const int64_t* part_i, int64_t np32, int64_t np64,
+                         const double* stats, int64_t* argmax, double* ei_max, hipStream_t s);
+
+// Batched scoring: a plan kernel sorts the problems into the launch
+// precision's class and (float32 only) the float64 escalation class and
+// numbers each class's (problem, tile) work items; one persistent launch per
+// class pops them; a per-problem argmax follows.
+struct BatchLaunch {
+  const ScoreArgs* dd = nullptr;    // B descriptors in the launch precision (device)
+  const ScoreArgs* dd64 = nullptr;  // B float64 descriptors of the same problems (device), or
+                                    // NULL: no escalation
+  int B = 0;
+  int prec = GPBO_FP32;
+  int tm = 32, tm64 = 16;           // candidates per work item of each class
+  size_t smem = 0, smem64 = 0;      // dynamic LDS of each class's kernel
+  int grid = 0, grid64 = 0;         // persistent workgroups of each class
+  void* plan = nullptr;             // device plan area, batch_plan_bytes(B)
+  unsigned* counters = nullptr;     // two device work counters (reset by the sequence)
+  int64_t* argmax = nullptr;        // device, B (may be NULL)
+  double* ei_max = nullptr;         // device, B (may be NULL)
+};
+size_t batch_plan_bytes(int B);
+// mark (may be NULL): (*mark)(0) / (*mark)(1) right before the first and
+// after the last scoring kernel, for timing.
+void launch_score_batched(const BatchLaunch& L, hipStream_t s,
                           const std::function<void(int)>* mark = nullptr);
+
+// Sets *flag (device int, cleared by the launch) when any of the count
+// values at p (float, or double when is_double) is a NaN or an infinity.
+void launch_check_finite(const void* p, int64_t count, int is_double, int* flag, hipStream_t s);
 
 // Top-k and gather (select.hip)
 int topk_max_k();

@@ -178,7 +178,7 @@ __device__ __forceinline__ void phase_cross(const ScoreArgs& A, typename PT<P>::
   using Acc = typename PT<P>::Acc;
   using V4 = typename PT<P>::V4;
   // candidates per register group (float64 halves it to avoid spills)
-  constexpr int CGD = P == GPBO_FP64 ? 16 : 32;
+  constexpr int CGD = arith64(P) ? 16 : 32;
   constexpr int CGM = CG0 > 0 ? CG0 : CGD;
   constexpr int CG = TM < CGM ? TM : CGM;
   const int d = A.d, npj = A.npj, ldk = A.ldk, nx = A.nx;
@@ -455,16 +455,20 @@ __device__ __forceinline__ void score_tile(const ScoreArgs& A, int64_t tile,
 // and one workgroup's cross-covariance phase overlaps the other's products.
 template <int P, int KERN, int TM>
 __global__ void __launch_bounds__(FT)
-    __attribute__((amdgpu_waves_per_eu((TM == 64 || P == GPBO_FP64) ? 1 : 4, 4)))
+    __attribute__((amdgpu_waves_per_eu((TM == 64 || arith64(P)) ? 1 : 4, 4)))
 k_score_fused(ScoreArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
+  // the float32 path of a model whose escalation is decided here: the
+  // kernel that does not apply returns at once
+  if (A.gate && escalate_fp64(A.stats[S_KINV]) != (A.gate == 2)) return;
   // two float64 row tiles over 64 candidates exceed the register file
-  constexpr int RT = (P == GPBO_FP64 && TM == 64) ? 1 : 2;
+  constexpr int RT = (arith64(P) && TM == 64) ? 1 : 2;
   score_tile<P, KERN, TM, RT>(A, blockIdx.x, smem);
 }
 
-// Persistent batched scoring: items 0 .. total-1 enumerate (problem, tile)
-// pairs, problem b owning items [tile_begin_b, tile_begin_{b+1}).  Every
+// Persistent batched scoring over the work items of one class of a plan:
+// items 0 .. total-1 enumerate (problem, tile) pairs, the k-th problem of the
+// class (descriptor idx[k]) owning items [begin[k], begin[k+1]).  Every
 // workgroup pops items until the counter passes the total, so all of them
 // reach the exit; the next item is popped while the current one is scored.
 // Problem starts of up to BT_MAX problems are looked up in LDS.  Candidate
@@ -481,17 +485,119 @@ __device__ __forceinline__ T* global_ptr(T* p) {
   __asm__("" : "+s"(g));  // keeps the cast pair from being folded away
   return (T*)g;
 }
+
+// Device plan of a batched launch (batch_plan_bytes(B) bytes): per class c
+// (0: the launch precision, 1: the float64 escalation of the float32 path)
+// the number of problems and work items, the problems' descriptor indices
+// and first items; per descriptor, the tile count of its argmax partials.
+struct PlanHdr {
+  int count[2];
+  int pad[2];
+  int64_t total[2];
+};
+struct PlanView {
+  PlanHdr* hdr;
+  int* idx;         // [2][B]
+  int64_t* begin;   // [2][B]
+  int64_t* nparts;  // [B]
+};
+__host__ __device__ inline PlanView plan_view(void* base, int B) {
+  PlanView v;
+  char* p = (char*)base;
+  v.hdr = (PlanHdr*)p;
+  p += sizeof(PlanHdr);
+  v.idx = (int*)p;
+  p += round_up(2 * (int64_t)B * sizeof(int), 16);
+  v.begin = (int64_t*)p;
+  p += 2 * (int64_t)B * sizeof(int64_t);
+  v.nparts = (int64_t*)p;
+  return v;
+}
+
+// One workgroup: each problem's class (escalate = 1: from its fit's
+// conditioning statistic), then per class an ordered prefix sum of the work
+// items over chunks of 256 problems (descriptor order, i.e. largest first,
+// is kept within each class).
+__global__ void __launch_bounds__(256) k_plan_batched(const ScoreArgs* __restrict__ dd, int B,
+                                                      int tm0, int tm1, int escalate, void* plan) {
+  __shared__ int64_t sc[2][256];
+  __shared__ int sn[2][256];
+  __shared__ int64_t run_items[2];
+  __shared__ int run_count[2];
+  const PlanView v = plan_view(plan, B);
+  const int t = threadIdx.x;
+  if (t < 2) {
+    run_items[t] = 0;
+    run_count[t] = 0;
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < B; k0 += 256) {
+    const int k = k0 + t;
+    int cls = 0;
+    int64_t items = 0;
+    if (k < B) {
+      const ScoreArgs& A = dd[k];
+      cls = escalate && escalate_fp64(A.stats[S_KINV]) ? 1 : 0;
+      items = (A.m + (cls ? tm1 : tm0) - 1) / (cls ? tm1 : tm0);
+      v.nparts[k] = items;
+    }
+    // inclusive scans of (is in class c) and (items if in class c)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      sn[c][t] = (k < B && cls == c) ? 1 : 0;
+      sc[c][t] = (k < B && cls == c) ? items : 0;
+    }
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      int a0 = 0, a1 = 0;
+      int64_t b0 = 0, b1 = 0;
+      if (t >= o) {
+        a0 = sn[0][t - o];
+        a1 = sn[1][t - o];
+        b0 = sc[0][t - o];
+        b1 = sc[1][t - o];
+      }
+      __syncthreads();
+      sn[0][t] += a0;
+      sn[1][t] += a1;
+      sc[0][t] += b0;
+      sc[1][t] += b1;
+      __syncthreads();
+    }
+    if (k < B) {
+      const int pos = run_count[cls] + sn[cls][t] - 1;
+      v.idx[cls * B + pos] = k;
+      v.begin[cls * B + pos] = run_items[cls] + sc[cls][t] - items;
+    }
+    __syncthreads();
+    if (t < 2) {
+      run_count[t] += sn[t][255];
+      run_items[t] += sc[t][255];
+    }
+    __syncthreads();
+  }
+  if (t < 2) {
+    v.hdr->count[t] = run_count[t];
+    v.hdr->total[t] = run_items[t];
+  }
+}
+
 template <int P, int TM>
 __global__ void __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(1, 4)))
-k_score_batched(const ScoreArgs* __restrict__ descs, int B, int64_t total,
+k_score_batched(const ScoreArgs* __restrict__ descs, int B, int cls, const void* plan,
                 unsigned* __restrict__ counter) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int64_t item_s;
   __shared__ int64_t begin_s[BT_MAX];
-  const bool lds_table = B <= BT_MAX;
+  const PlanView v = plan_view(const_cast<void*>(plan), B);
+  const int cnt = __builtin_amdgcn_readfirstlane(v.hdr->count[cls]);
+  const int64_t total = v.hdr->total[cls];
+  const int* __restrict__ idx = v.idx + cls * B;
+  const int64_t* __restrict__ begin = v.begin + cls * B;
+  const bool lds_table = cnt <= BT_MAX;
   if (lds_table)
-    for (int b = threadIdx.x; b < B; b += FT) begin_s[b] = descs[b].tile_begin;
-  if (threadIdx.x == 0) item_s = (int64_t)atomicAdd(counter, 1u);
+    for (int b = threadIdx.x; b < cnt; b += FT) begin_s[b] = begin[b];
+  if (threadIdx.x == 0) item_s = total > 0 ? (int64_t)atomicAdd(counter, 1u) : 0;
   __syncthreads();
   for (;;) {
     // item and problem are the same for the whole workgroup: kept in scalar
@@ -500,15 +606,16 @@ k_score_batched(const ScoreArgs* __restrict__ descs, int B, int64_t total,
     if (item >= total) break;
     unsigned nxt = 0;
     if (threadIdx.x == 0) nxt = atomicAdd(counter, 1u);
-    int lo = 0, hi = B - 1;  // problem: largest b with tile_begin <= item
+    int lo = 0, hi = cnt - 1;  // largest k with begin[k] <= item
     while (lo < hi) {
       const int mid = (lo + hi + 1) / 2;
-      const int64_t tb = lds_table ? begin_s[mid] : descs[mid].tile_begin;
+      const int64_t tb = lds_table ? begin_s[mid] : begin[mid];
       if (tb <= item) lo = mid; else hi = mid - 1;
       lo = __builtin_amdgcn_readfirstlane(lo);
       hi = __builtin_amdgcn_readfirstlane(hi);
     }
-    ScoreArgs A = descs[lo];
+    const int64_t tile = item - (lds_table ? begin_s[lo] : begin[lo]);
+    ScoreArgs A = descs[__builtin_amdgcn_readfirstlane(idx[lo])];
     // the descriptor's pointers are device-global memory: loads through them
     // become global (not flat) loads, with their own wait counter
     A.Xc = global_ptr(A.Xc);
@@ -524,16 +631,19 @@ k_score_batched(const ScoreArgs* __restrict__ descs, int B, int64_t total,
     A.part_v = global_ptr(A.part_v);
     A.part_i = global_ptr(A.part_i);
     if (A.kernel == GPBO_KERNEL_SE)
-      score_tile<P, GPBO_KERNEL_SE, TM, 1, 16, true>(A, item - A.tile_begin, smem);
+      score_tile<P, GPBO_KERNEL_SE, TM, 1, 16, true>(A, tile, smem);
     else
-      score_tile<P, GPBO_KERNEL_MATERN52, TM, 1, 16, true>(A, item - A.tile_begin, smem);
+      score_tile<P, GPBO_KERNEL_MATERN52, TM, 1, 16, true>(A, tile, smem);
     __syncthreads();  // item_s and the LDS tile are reused by the next item
     if (threadIdx.x == 0) item_s = (int64_t)nxt;
     __syncthreads();
   }
 }
 
-__global__ void k_reset_counter(unsigned* c) { *c = 0u; }
+__global__ void k_reset_counters(unsigned* c) {
+  c[0] = 0u;
+  c[1] = 0u;
+}
 
 // Block-wide (value, index) maximum over np partials.
 __device__ __forceinline__ void block_argmax(const double* __restrict__ pv,
@@ -577,13 +687,25 @@ __global__ void __launch_bounds__(256) k_argmax_final(const double* __restrict__
   block_argmax(pv, pi, np, argmax, ei_max);
 }
 
-// One workgroup per problem of a batch.
-template <int TM>
-__global__ void __launch_bounds__(256) k_argmax_batched(const ScoreArgs* __restrict__ descs,
+// The single float32 launch whose escalation was decided on the device:
+// the partials of whichever kernel ran.
+__global__ void __launch_bounds__(256) k_argmax_gated(const double* __restrict__ pv,
+                                                      const int64_t* __restrict__ pi, int64_t np32,
+                                                      int64_t np64, const double* __restrict__ stats,
+                                                      int64_t* __restrict__ argmax,
+                                                      double* __restrict__ ei_max) {
+  block_argmax(pv, pi, escalate_fp64(stats[S_KINV]) ? np64 : np32, argmax, ei_max);
+}
+
+// One workgroup per problem of a batch (descriptor blockIdx.x; its tile
+// count from the plan).
+__global__ void __launch_bounds__(256) k_argmax_batched(const ScoreArgs* __restrict__ descs, int B,
+                                                        const void* plan,
                                                         int64_t* __restrict__ argmax,
                                                         double* __restrict__ ei_max) {
   const ScoreArgs& A = descs[blockIdx.x];
-  block_argmax(A.part_v, A.part_i, (A.m + TM - 1) / TM, argmax ? argmax + A.slot : nullptr,
+  const PlanView v = plan_view(const_cast<void*>(plan), B);
+  block_argmax(A.part_v, A.part_i, v.nparts[blockIdx.x], argmax ? argmax + A.slot : nullptr,
                ei_max ? ei_max + A.slot : nullptr);
 }
 
@@ -611,33 +733,26 @@ void launch_fused_tm(const ScoreArgs& a, int tm, size_t smem, hipStream_t s) {
 }
 
 template <int P, int TM>
-void launch_batched_t(const ScoreArgs* dd, int B, int64_t total, unsigned* counter, size_t smem,
-                      int grid, int64_t* argmax, double* ei_max, hipStream_t s,
-                      const std::function<void(int)>* mark) {
+void launch_batched_t(const ScoreArgs* dd, int B, int cls, void* plan, unsigned* counter,
+                      size_t smem, int grid, hipStream_t s) {
   allow_smem(k_score_batched<P, TM>, smem);
-  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
-  if (mark) (*mark)(0);
-  hipLaunchKernelGGL((k_score_batched<P, TM>), dim3(grid), dim3(FT), smem, s, dd, B, total,
-                     counter);
-  if (mark) (*mark)(1);
-  if (argmax || ei_max)
-    hipLaunchKernelGGL(k_argmax_batched<TM>, dim3(B), dim3(256), 0, s, dd, argmax, ei_max);
+  hipLaunchKernelGGL((k_score_batched<P, TM>), dim3(grid), dim3(FT), smem, s, dd, B, cls,
+                     (const void*)plan, counter);
 }
 
 template <int P>
-void launch_batched_tm(const ScoreArgs* dd, int B, int64_t total, unsigned* counter, int tm,
-                       size_t smem, int grid, int64_t* argmax, double* ei_max, hipStream_t s,
-                       const std::function<void(int)>* mark) {
+void launch_batched_tm(const ScoreArgs* dd, int B, int cls, void* plan, unsigned* counter, int tm,
+                       size_t smem, int grid, hipStream_t s) {
   switch (tm) {
-    case 16: launch_batched_t<P, 16>(dd, B, total, counter, smem, grid, argmax, ei_max, s, mark); break;
-    case 32: launch_batched_t<P, 32>(dd, B, total, counter, smem, grid, argmax, ei_max, s, mark); break;
-    default: launch_batched_t<P, 64>(dd, B, total, counter, smem, grid, argmax, ei_max, s, mark); break;
+    case 16: launch_batched_t<P, 16>(dd, B, cls, plan, counter, smem, grid, s); break;
+    case 32: launch_batched_t<P, 32>(dd, B, cls, plan, counter, smem, grid, s); break;
+    default: launch_batched_t<P, 64>(dd, B, cls, plan, counter, smem, grid, s); break;
   }
 }
 
 }  // namespace
 
-size_t score_esize(int prec) { return prec == GPBO_FP64 ? 8 : prec == GPBO_FP32 ? 4 : 2; }
+size_t score_esize(int prec) { return arith64(prec) ? 8 : prec == GPBO_FP32 ? 4 : 2; }
 int score_kb(int prec) { return prec == GPBO_BF16 ? 32 : 16; }
 
 // Column extent of the packed operand: the widest (last) row tile's padded
@@ -657,7 +772,7 @@ int kt_stride(int prec, int npj) {
 }
 
 size_t score_smem(int prec, int n, int d, int tm) {
-  const size_t csz = prec == GPBO_FP64 ? 8 : 4;
+  const size_t csz = arith64(prec) ? 8 : 4;
   return (size_t)tm * kt_stride(prec, packed_npj(n, prec)) * score_esize(prec) +
          (size_t)round_up((int64_t)d * tm, 4) * csz + 2 * FW * (size_t)tm * csz;
 }
@@ -805,6 +920,8 @@ void ensure_score_operands(Ctx* c, Model* const* models, int B, int prec, hipStr
   }
 }
 
+int score_tile_m64(int n, int d) { return score_tile_m(GPBO_FP64, n, d); }
+
 int score_tile_m(int prec, int n, int d) {
   // Largest tile whose LDS footprint allows two workgroups per CU, else one.
   const size_t lds = 160 * 1024;
@@ -847,6 +964,10 @@ void launch_score(const ScoreArgs& a, int prec, int tm, hipStream_t s) {
       if (se) launch_fused_tm<GPBO_FP32, GPBO_KERNEL_SE>(a, tm, smem, s);
       else launch_fused_tm<GPBO_FP32, GPBO_KERNEL_MATERN52>(a, tm, smem, s);
       break;
+    case P_F64IO32:
+      if (se) launch_fused_tm<P_F64IO32, GPBO_KERNEL_SE>(a, tm, smem, s);
+      else launch_fused_tm<P_F64IO32, GPBO_KERNEL_MATERN52>(a, tm, smem, s);
+      break;
     default:
       if (se) launch_fused_tm<GPBO_BF16, GPBO_KERNEL_SE>(a, tm, smem, s);
       else launch_fused_tm<GPBO_BF16, GPBO_KERNEL_MATERN52>(a, tm, smem, s);
@@ -854,25 +975,76 @@ void launch_score(const ScoreArgs& a, int prec, int tm, hipStream_t s) {
   }
 }
 
+void launch_score_escalated(const ScoreArgs& a32, int tm32, const ScoreArgs& a64, int tm64,
+                            hipStream_t s) {
+  ScoreArgs a = a32, b = a64;
+  a.gate = 1;
+  b.gate = 2;
+  launch_score(a, GPBO_FP32, tm32, s);
+  launch_score(b, P_F64IO32, tm64, s);
+}
+
 void launch_argmax_final(const double* pv, const int64_t* pi, int64_t np, int64_t* argmax,
                          double* ei_max, hipStream_t s) {
   hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(256), 0, s, pv, pi, np, argmax, ei_max);
 }
 
-void launch_score_batched(const ScoreArgs* dd, int B, int64_t total, unsigned* counter, int prec,
-                          int tm, size_t smem, int grid, int64_t* argmax, double* ei_max,
-                          hipStream_t s, const std::function<void(int)>* mark) {
-  switch (prec) {
+void launch_argmax_gated(const double* pv, const int64_t* pi, int64_t np32, int64_t np64,
+                         const double* stats, int64_t* argmax, double* ei_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_argmax_gated, dim3(1), dim3(256), 0, s, pv, pi, np32, np64, stats, argmax,
+                     ei_max);
+}
+
+__global__ void __launch_bounds__(256) k_check_finite(const void* __restrict__ p, int64_t count,
+                                                      int is_double, int* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = is_double ? ((const double*)p)[i] : (double)((const float*)p)[i];
+    bad |= !(v - v == 0.0);  // NaN and +-inf give NaN
+  }
+  if (__any(bad) && threadIdx.x % 64 == 0) atomicOr(flag, 1);
+}
+
+__global__ void k_clear_flag(int* flag) { *flag = 0; }
+
+void launch_check_finite(const void* p, int64_t count, int is_double, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, s, flag);
+  if (count <= 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(1024, ceil_div(count, 256));
+  hipLaunchKernelGGL(k_check_finite, dim3(grid), dim3(256), 0, s, p, count, is_double, flag);
+}
+
+size_t batch_plan_bytes(int B) {
+  return sizeof(PlanHdr) + round_up(2 * (int64_t)B * sizeof(int), 16) +
+         3 * (int64_t)B * sizeof(int64_t);
+}
+
+void launch_score_batched(const BatchLaunch& L, hipStream_t s,
+                          const std::function<void(int)>* mark) {
+  const bool esc = L.dd64 != nullptr;
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(1), 0, s, L.counters);
+  hipLaunchKernelGGL(k_plan_batched, dim3(1), dim3(256), 0, s, L.dd, L.B, L.tm, L.tm64,
+                     esc ? 1 : 0, L.plan);
+  if (mark) (*mark)(0);
+  switch (L.prec) {
     case GPBO_FP64:
-      launch_batched_tm<GPBO_FP64>(dd, B, total, counter, tm, smem, grid, argmax, ei_max, s, mark);
+      launch_batched_tm<GPBO_FP64>(L.dd, L.B, 0, L.plan, L.counters, L.tm, L.smem, L.grid, s);
       break;
     case GPBO_FP32:
-      launch_batched_tm<GPBO_FP32>(dd, B, total, counter, tm, smem, grid, argmax, ei_max, s, mark);
+      launch_batched_tm<GPBO_FP32>(L.dd, L.B, 0, L.plan, L.counters, L.tm, L.smem, L.grid, s);
       break;
     default:
-      launch_batched_tm<GPBO_BF16>(dd, B, total, counter, tm, smem, grid, argmax, ei_max, s, mark);
+      launch_batched_tm<GPBO_BF16>(L.dd, L.B, 0, L.plan, L.counters, L.tm, L.smem, L.grid, s);
       break;
   }
+  if (esc)
+    launch_batched_tm<P_F64IO32>(L.dd64, L.B, 1, L.plan, L.counters + 1, L.tm64, L.smem64,
+                                 L.grid64, s);
+  if (mark) (*mark)(1);
+  if (L.argmax || L.ei_max)
+    hipLaunchKernelGGL(k_argmax_batched, dim3(L.B), dim3(256), 0, s, L.dd, L.B,
+                       (const void*)L.plan, L.argmax, L.ei_max);
 }
 
 }  // namespace gpbo

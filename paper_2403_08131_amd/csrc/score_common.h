@@ -47,6 +47,20 @@ struct PT<GPBO_BF16> {
   static constexpr int KB = 32;
 };
 
+// Escalated float32 scoring (P_F64IO32): float64 arithmetic and operands,
+// float32 candidate coordinates and outputs.
+template <>
+struct PT<P_F64IO32> {
+  using In = float;
+  using C = double;
+  using K = double;
+  using Acc = double;
+  using V4 = d4;
+  static constexpr int KB = 16;
+};
+// Float64 arithmetic (either input type).
+__host__ __device__ constexpr bool arith64(int P) { return P == GPBO_FP64 || P == P_F64IO32; }
+
 // float32 -> bfloat16 bits, round to nearest even (NaN kept quiet).
 __device__ __forceinline__ unsigned short f2bf(float f) {
   unsigned int u = __float_as_uint(f);
@@ -199,6 +213,9 @@ struct Blk<GPBO_FP64> {
     for (int kk = 0; kk < KS; ++kk) mma_k(c, a, b, kk);
   }
 };
+
+template <>
+struct Blk<P_F64IO32> : Blk<GPBO_FP64> {};
 
 // Transpose-reduction of N per-lane partial sums over the 64 lanes of a wave:
 // log2 N halving exchanges leave each lane with one entry summed over 64/N...

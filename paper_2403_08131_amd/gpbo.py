@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libgpbo.so")
 OK, E_INVALID_ARG, E_NOT_PD, E_NONFINITE, E_OOM, E_HIP, E_UNSUPPORTED = range(7)
 KERNEL_SE, KERNEL_MATERN52 = 0, 1
 FP64, FP32, BF16 = 0, 1, 2
-NSTATS = 7
+NSTATS = 8
+ESCALATE_KINV = 8.0
 PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 PATH_AUTO, PATH_FUSED, PATH_LARGE = 0, 1, 2
 PATHS = {"auto": PATH_AUTO, "fused": PATH_FUSED, "large": PATH_LARGE}
@@ -79,6 +80,7 @@ _SIGS = {
                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gpbo_score_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p),
                                      C.POINTER(C.c_int64), C.POINTER(C.c_void_p), C.c_int,
+                                     C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]),
     "gpbo_topk": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     "gpbo_gather_rows": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
@@ -209,7 +211,7 @@ class Model:
     def stats(self):
         s = (C.c_double * NSTATS)()
         self.ctx.check(lib().gpbo_model_stats(self.h, s))
-        keys = ("ymean", "ystd", "fbest", "lml", "logdet", "res0", "res1")
+        keys = ("ymean", "ystd", "fbest", "lml", "logdet", "res0", "res1", "kinv")
         return dict(zip(keys, list(s)))
 
     def factors(self):
@@ -318,13 +320,26 @@ def status_batched(ctx: Context, models):
     return st, list(status), list(lml)
 
 
-def score(ctx: Context, model: Model, Xc, prec="fp32", want=("mu", "sigma", "ei"), reduce=True):
-    """gpbo_score: posterior mean, sd, EI (device tensors) and the argmax."""
+def score(ctx: Context, model: Model, Xc, prec="fp32", want=("mu", "sigma", "ei"), reduce=True,
+          host_argmax=False):
+    """gpbo_score: posterior mean, sd, EI (device tensors) and the argmax.
+
+    host_argmax=True passes host buffers for argmax and ei_max (the library
+    then synchronises and fills them): out["argmax"] is an int and
+    out["ei_max"] a float."""
     pr = PREC[prec] if isinstance(prec, str) else int(prec)
     odt = torch.float64 if pr == FP64 else torch.float32
     assert Xc.dtype == odt and Xc.is_contiguous() and Xc.shape[1] == model.d
     m = Xc.shape[0]
     out = {k: torch.empty(m, dtype=odt, device=ctx.device) for k in want}
+    if reduce and host_argmax:
+        am_h, em_h = C.c_int64(-2), C.c_double(0.0)
+        ctx.check(lib().gpbo_score(ctx.h, model.h, m, _ptr(Xc), pr, _ptr(out.get("mu")),
+                                   _ptr(out.get("sigma")), _ptr(out.get("ei")), C.byref(am_h),
+                                   C.byref(em_h)))
+        out["argmax"] = am_h.value
+        out["ei_max"] = em_h.value
+        return out
     am = torch.empty(1, dtype=torch.int64, device=ctx.device) if reduce else None
     emax = torch.empty(1, dtype=torch.float64, device=ctx.device) if reduce else None
     ctx.check(lib().gpbo_score(ctx.h, model.h, m, _ptr(Xc), pr, _ptr(out.get("mu")),
@@ -335,18 +350,37 @@ def score(ctx: Context, model: Model, Xc, prec="fp32", want=("mu", "sigma", "ei"
     return out
 
 
-def score_batched(ctx: Context, models, Xcs, prec="bf16", want_ei=True):
+def _ptr_array(ts):
+    if ts is None:
+        return None
+    return (C.c_void_p * len(ts))(*[None if t is None else t.data_ptr() for t in ts])
+
+
+def score_batched(ctx: Context, models, Xcs, prec="bf16", want=("ei",), host_argmax=False):
+    """gpbo_score_batched: per problem the outputs named in ``want`` (any of
+    "mu", "sigma", "ei"; float32 device tensors) and the argmax / EI maximum
+    of every problem (device tensors, or numpy arrays with host_argmax).
+    Returns (outs, argmax, ei_max) with outs a dict of per-problem lists."""
     pr = PREC[prec] if isinstance(prec, str) else int(prec)
     B = len(models)
     hs = (C.c_void_p * B)(*[mo.h.value if isinstance(mo.h, C.c_void_p) else mo.h for mo in models])
     ms = (C.c_int64 * B)(*[x.shape[0] for x in Xcs])
     xs = (C.c_void_p * B)(*[x.data_ptr() for x in Xcs])
-    eis = [torch.empty(x.shape[0], dtype=torch.float32, device=ctx.device) for x in Xcs] if want_ei else None
-    ep = (C.c_void_p * B)(*[e.data_ptr() for e in eis]) if want_ei else None
-    am = torch.empty(B, dtype=torch.int64, device=ctx.device)
-    emax = torch.empty(B, dtype=torch.float64, device=ctx.device)
-    ctx.check(lib().gpbo_score_batched(ctx.h, B, hs, ms, xs, pr, ep, _ptr(am), _ptr(emax)))
-    return eis, am, emax
+    odt = torch.float64 if pr == FP64 else torch.float32
+    outs = {k: [torch.empty(x.shape[0], dtype=odt, device=ctx.device) for x in Xcs] for k in want}
+    if host_argmax:
+        import numpy as np
+        am = np.empty(B, dtype=np.int64)
+        emax = np.empty(B, dtype=np.float64)
+        amp, emp = C.c_void_p(am.ctypes.data), C.c_void_p(emax.ctypes.data)
+    else:
+        am = torch.empty(B, dtype=torch.int64, device=ctx.device)
+        emax = torch.empty(B, dtype=torch.float64, device=ctx.device)
+        amp, emp = _ptr(am), _ptr(emax)
+    ctx.check(lib().gpbo_score_batched(ctx.h, B, hs, ms, xs, pr, _ptr_array(outs.get("mu")),
+                                       _ptr_array(outs.get("sigma")), _ptr_array(outs.get("ei")),
+                                       amp, emp))
+    return outs, am, emax
 
 
 def topk(ctx: Context, v, k):

@@ -72,3 +72,16 @@ def test_null_handles_are_rejected(lib):
     assert lib.gpbo_score(None, None, 0, None, 1, None, None, None, None, None) == 1
     assert lib.gpbo_ctx_destroy(None) == 0
     assert lib.gpbo_model_free(None) == 0
+
+
+def test_library_starts_no_process():
+    """The library runs inside processes that drive the GPU: no shell, fork or
+    exec of another program from its sources."""
+    csrc = os.path.join(ROOT, "paper_2403_08131_amd", "csrc")
+    bad = re.compile(r"\b(system|popen|fork|vfork|execv|execvp|execl|execlp|posix_spawn)\s*\(")
+    hits = []
+    for name in sorted(os.listdir(csrc)):
+        text = open(os.path.join(csrc, name)).read()
+        text = re.sub(r"//[^\n]*", "", text)
+        hits += [(name, m.group(0)) for m in bad.finditer(text)]
+    assert not hits, hits

@@ -44,6 +44,18 @@ def _problems(B=12, m=1024, lam=0.1, seed=0):
     return I.make_c3(lam=lam, replicate=seed, scaled=True, B=B, m=m)
 
 
+def _e_mu_sigma(ref, mu, sg, f, sf2):
+    """R9 errors: |dmu| / max(|mu|, s_y sf) and |dsigma| / sigma over the
+    candidates with sigma^2 >= 1e-2 s_y^2 sf2."""
+    mu = mu.double().cpu().numpy()
+    sg = sg.double().cpu().numpy()
+    scale = f.ystd * np.sqrt(sf2)
+    e_mu = np.max(np.abs(mu - ref["mu"]) / np.maximum(np.abs(ref["mu"]), scale))
+    floor = ref["sigma"] ** 2 >= 1e-2 * scale ** 2
+    e_sg = np.max(np.abs(sg - ref["sigma"])[floor] / ref["sigma"][floor]) if floor.any() else 0.0
+    return e_mu, e_sg
+
+
 def _fit_batch(ctx, probs):
     specs = [dict(X=_t(p.X), y=_t(p.y), lengthscale=p.lengthscale, kernel=p.kernel,
                   signal_var=p.signal_var, noise_var=p.noise_var) for p in probs]
@@ -94,7 +106,8 @@ def test_score_batched_matches_single_and_oracle(ctx, prec):
     st, models, status, _ = _fit_batch(ctx, probs)
     assert st == G.OK
     Xcs = [_t(p.Xc, torch.float32) for p in probs]
-    eis, am, emax = G.score_batched(ctx, models, Xcs, prec)
+    outs, am, emax = G.score_batched(ctx, models, Xcs, prec, want=("mu", "sigma", "ei"))
+    eis = outs["ei"]
     torch.cuda.synchronize()
     am = am.cpu().numpy()
     emax = emax.cpu().numpy()
@@ -107,7 +120,18 @@ def test_score_batched_matches_single_and_oracle(ctx, prec):
         scale = float(single["mu"].abs().max()) + float(single["sigma"].abs().max())
         assert np.max(np.abs(eb - e1)) <= 1e-5 * scale, (b, p.n, p.d)
         f = O.fit(p.X, p.y, p.lengthscale, O.SE, p.signal_var, p.noise_var)
-        ref = O.score(f, p.Xc, want=("ei",))["ei"]
+        full = O.score(f, p.Xc)
+        ref = full["ei"]
+        # the batched kernel's own mean and standard deviation (R9 bars)
+        e_mu, e_sg = _e_mu_sigma(full, outs["mu"][b], outs["sigma"][b], f, p.signal_var)
+        print(f"  {prec} problem {b}: e_mu={e_mu:.2e} e_sigma={e_sg:.2e}")
+        if prec == "fp32":
+            assert e_mu <= 1e-4 and e_sg <= 1e-4, (b, e_mu, e_sg)
+        else:
+            # bfloat16 errors are stated, not gated (R9): sigma near training
+            # points comes from sf2 - |v|^2 with 8-bit operands and can
+            # cancel to 0; the mean keeps a loose sanity bound
+            assert e_mu <= 5e-2, (b, e_mu)
         bound = 1e-4 if prec == "fp32" else 5e-2
         best = O.argmax(ref)
         srt = np.sort(ref)[::-1]
@@ -142,7 +166,7 @@ def test_score_batched_graph_replay(ctx):
         ms = (C.c_int64 * B)(*[x.shape[0] for x in Xcs])
         xs = (C.c_void_p * B)(*[x.data_ptr() for x in Xcs])
         ep = (C.c_void_p * B)(*[e.data_ptr() for e in eis])
-        ctx.check(G.lib().gpbo_score_batched(ctx.h, B, hs, ms, xs, G.FP32, ep,
+        ctx.check(G.lib().gpbo_score_batched(ctx.h, B, hs, ms, xs, G.FP32, None, None, ep,
                                              C.c_void_p(am.data_ptr()), C.c_void_p(em.data_ptr())))
         torch.cuda.synchronize()
         return [e.clone() for e in eis], am.clone(), em.clone()
@@ -193,7 +217,7 @@ def test_score_batched_graph_replay_after_refit(ctx):
         ms = (C.c_int64 * B)(*[x.shape[0] for x in Xcs])
         xs = (C.c_void_p * B)(*[x.data_ptr() for x in Xcs])
         ep = (C.c_void_p * B)(*[e.data_ptr() for e in eis])
-        ctx.check(G.lib().gpbo_score_batched(ctx.h, B, hs, ms, xs, G.FP32, ep,
+        ctx.check(G.lib().gpbo_score_batched(ctx.h, B, hs, ms, xs, G.FP32, None, None, ep,
                                              C.c_void_p(am.data_ptr()), C.c_void_p(em.data_ptr())))
         torch.cuda.synchronize()
         amh = am.cpu().numpy()
@@ -232,7 +256,7 @@ def test_score_batched_alternating_shapes_replay(ctx):
         ms = (C.c_int64 * B)(*[x.shape[0] for x in Xcs])
         xs = (C.c_void_p * B)(*[x.data_ptr() for x in Xcs])
         ep = (C.c_void_p * B)(*[e.data_ptr() for e in eis])
-        ctx.check(G.lib().gpbo_score_batched(ctx.h, B, hs, ms, xs, G.FP32, ep,
+        ctx.check(G.lib().gpbo_score_batched(ctx.h, B, hs, ms, xs, G.FP32, None, None, ep,
                                              C.c_void_p(am.data_ptr()), C.c_void_p(em.data_ptr())))
         torch.cuda.synchronize()
         for b in range(B):
@@ -256,7 +280,8 @@ def test_score_batched_mixed_kernels(ctx):
     st, models, status, _ = G.fit_batched(ctx, specs)
     assert st == G.OK
     Xcs = [_t(p.Xc, torch.float32) for p in probs]
-    eis, am, _ = G.score_batched(ctx, models, Xcs, "fp32")
+    outs, am, _ = G.score_batched(ctx, models, Xcs, "fp32")
+    eis = outs["ei"]
     torch.cuda.synchronize()
     am = am.cpu().numpy()
     for b, (p, mo, k) in enumerate(zip(probs, models, kinds)):
@@ -323,7 +348,8 @@ def test_batched_full_c3_shape_smoke(ctx):
     for prec in ("bf16", "fp32"):
         # the second precision reuses the scaled observations built by the
         # first and adds only its own packed operand
-        eis, am, emax = G.score_batched(ctx, models, Xcs, prec)
+        outs, am, emax = G.score_batched(ctx, models, Xcs, prec)
+        eis = outs["ei"]
         torch.cuda.synchronize()
         am = am.cpu().numpy()
         assert np.all((am >= 0) & (am < 8192))
@@ -374,3 +400,49 @@ def test_fit_graph_replay_matches_eager(ctx):
         mg.free()
         me.free()
     eager.close()
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.1, 0.5])
+def test_batched_literal_c3_fp32_meets_the_bar(ctx, lam):
+    """The batched workload as drawn (64 sub-searches, d in 2..12, n in
+    16..400, literal log-uniform [0.05, 1] lengthscales, 8192 candidates
+    each), float32 path: the persistent kernels' own mu and sigma of every
+    problem within 1e-4 of the float64 oracle (R9) over the whole pool, and
+    every argmax per R8.  Low-dimensional problems with many points have
+    cond(K) up to ~1e6 here; the fit's conditioning statistic routes them to
+    the float64 launch, every other problem stays in float32.  The conditioning
+    statistic itself (signal_var * trace(K^-1) / n) is checked against an
+    explicit inverse of the oracle's Gram matrix."""
+    probs = I.make_c3(lam=lam, replicate=0, scaled=False, B=64, m=8192)
+    print(f"literal c3 lambda={lam}: fitting 64 problems", flush=True)
+    st, models, status, _ = _fit_batch(ctx, probs)
+    assert st == G.OK
+    Xcs = [_t(p.Xc, torch.float32) for p in probs]
+    outs, am, emax = G.score_batched(ctx, models, Xcs, "fp32", want=("mu", "sigma", "ei"),
+                                     host_argmax=True)
+    torch.cuda.synchronize()
+    n_esc = 0
+    worst = (0.0, 0.0, 0.0)
+    for b, (p, mo) in enumerate(zip(probs, models)):
+        f = O.fit(p.X, p.y, p.lengthscale, O.SE, p.signal_var, p.noise_var)
+        K = O.gram(O.SE, p.X, p.lengthscale, p.signal_var, p.noise_var)
+        kinv = p.signal_var * np.trace(np.linalg.inv(K)) / p.n
+        s = mo.stats()
+        assert s["kinv"] == pytest.approx(kinv, rel=1e-6), b
+        n_esc += s["kinv"] > G.ESCALATE_KINV
+        ref = O.score(f, p.Xc)
+        e_mu, e_sg = _e_mu_sigma(ref, outs["mu"][b], outs["sigma"][b], f, p.signal_var)
+        ei = outs["ei"][b].double().cpu().numpy()
+        e_ei = np.max(np.abs(ei - ref["ei"])) / max(ref["ei"].max(), 1e-300)
+        worst = tuple(max(u, v) for u, v in zip(worst, (e_mu, e_sg, e_ei)))
+        assert e_mu <= 1e-4 and e_sg <= 1e-4, (b, p.n, p.d, s["kinv"], e_mu, e_sg)
+        srt = np.sort(ref["ei"])[::-1]
+        if srt[0] - srt[1] > 1e-4 * srt[0]:
+            assert am[b] == O.argmax(ref["ei"]), (b, am[b], O.argmax(ref["ei"]))
+        else:
+            assert ref["ei"][am[b]] >= srt[0] * (1 - 1e-4), b
+        assert emax[b] == pytest.approx(float(ei[am[b]]), rel=1e-6)
+    print(f"  lambda={lam}: {n_esc} of 64 escalated to float64; worst e_mu={worst[0]:.2e} "
+          f"e_sigma={worst[1]:.2e} |dEI|/EI_max={worst[2]:.2e}", flush=True)
+    for mo in models:
+        mo.free()
