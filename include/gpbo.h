@@ -316,6 +316,15 @@ gpbo_status gpbo_mlp_grads(gpbo_ctx ctx, gpbo_mlp mlp, int32_t n, const float* X
  * HIP graph and replayed.  Asynchronous. */
 gpbo_status gpbo_mlp_train(gpbo_ctx ctx, gpbo_mlp mlp, int32_t n, const float* X,
                            const float* y, int32_t steps, double lr, float* loss_hist);
+/* `steps` Adam steps as gpbo_mlp_train, on the observations of a fitted
+ * model: inputs its X (cast to float32), targets its normalised y (the
+ * fit's z-score, or centring with normalize_y = 0), so that the network
+ * learns the same targets as the Gaussian process; its outputs are then in
+ * the model's normalised units.  The model's n must be a multiple of 64 and
+ * its d equal to d_in.  Queued behind the model's fit on the context's
+ * stream (an asynchronous fit needs no status call first).  Asynchronous. */
+gpbo_status gpbo_mlp_train_model(gpbo_ctx ctx, gpbo_mlp mlp, gpbo_model model, int32_t steps,
+                                 double lr, float* loss_hist);
 /* Member outputs on m candidates: out is device members x m float. */
 gpbo_status gpbo_mlp_forward(gpbo_ctx ctx, gpbo_mlp mlp, int64_t m, const float* Xc,
                              float* out);

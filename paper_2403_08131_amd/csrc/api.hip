@@ -1254,6 +1254,24 @@ gpbo_status gpbo_mlp_train(gpbo_ctx c, gpbo_mlp mlp, int32_t n, const float* X, 
   return GPBO_OK;
 }
 
+gpbo_status gpbo_mlp_train_model(gpbo_ctx c, gpbo_mlp mlp, gpbo_model M, int32_t steps, double lr,
+                                 float* loss_hist) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (!mlp || !M) return fail(c, GPBO_E_INVALID_ARG, "mlp and model are required");
+  if (M->d != mlp->D)
+    return fail(c, GPBO_E_INVALID_ARG, "model has d=%d, the network d_in=%d", M->d, mlp->D);
+  if (M->n % 64 != 0)
+    return fail(c, GPBO_E_INVALID_ARG,
+                "training sample count must be a positive multiple of 64 (the model has n=%d)", M->n);
+  if (steps < 0 || !(lr > 0.0)) return fail(c, GPBO_E_INVALID_ARG, "steps >= 0 and lr > 0 required");
+  DeviceGuard g(c->device);
+  if (M->alloc_stream != c->stream) M->alloc_mixed = true;
+  if (!mlp_train_model(mlp->st, M, steps, lr, loss_hist, !c->no_graph, c->stream))
+    return fail(c, GPBO_E_OOM, "MLP training data or launch failed");
+  HIP_TRY(c, hipGetLastError());
+  return GPBO_OK;
+}
+
 gpbo_status gpbo_mlp_forward(gpbo_ctx c, gpbo_mlp mlp, int64_t m, const float* Xc, float* out) {
   if (!c) return GPBO_E_INVALID_ARG;
   if (!mlp || m < 0 || (m > 0 && (!Xc || !out))) return fail(c, GPBO_E_INVALID_ARG, "invalid forward arguments");

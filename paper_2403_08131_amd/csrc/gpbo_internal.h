@@ -324,6 +324,9 @@ bool mlp_train(MlpState* st, int64_t n, const float* X, const float* y, int step
                float* loss_hist, bool use_graph, hipStream_t s);
 bool mlp_grads(MlpState* st, int64_t n, const float* X, const float* y, float* grad, float* loss,
                hipStream_t s);
+// Training on a fitted model's own observations (its X and normalised y).
+bool mlp_train_model(MlpState* st, const Model* M, int steps, double lr, float* loss_hist,
+                     bool use_graph, hipStream_t s);
 void mlp_forward(MlpState* st, int64_t m, const float* Xc, float* out, hipStream_t s);
 void mlp_ens_ei(MlpState* st, int64_t m, const float* out, double fbest, float* ei, hipStream_t s);
 void mlp_ens_lcb(MlpState* st, int64_t m, const float* out, double kappa, float* score,

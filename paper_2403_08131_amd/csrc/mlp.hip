@@ -549,6 +549,9 @@ struct MlpState {
   int64_t ws_n = 0;
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // float32 training data taken from a fitted model (mlp_train_model)
+  float* data = nullptr;
+  size_t data_bytes = 0;
   hipGraphExec_t graph = nullptr;
   std::vector<uint64_t> graph_key;
 };
@@ -599,7 +602,7 @@ void mlp_destroy(MlpState* st) {
   (void)hipStreamSynchronize(c->stream);
   if (st->graph) (void)hipGraphExecDestroy(st->graph);
   void* ps[] = {st->dev.master, st->dev.mom1, st->dev.mom2, st->dev.W1b, st->dev.W2b,
-                st->dev.W2Tb, st->dev.w3b, st->dev.step, st->ws};
+                st->dev.W2Tb, st->dev.w3b, st->dev.step, st->ws, st->data};
   for (void* p : ps) dfree(c, p);
   delete st;
 }
@@ -760,6 +763,39 @@ bool mlp_train(MlpState* st, int64_t n, const float* X, const float* y, int step
   for (int k = 0; k < steps; ++k)
     if (hipGraphLaunch(st->graph, s) != hipSuccess) return false;
   return true;
+}
+
+// The model's observations as float32 training data: inputs X (n x d) and
+// targets ytilde (the fit's normalised observations).
+__global__ void __launch_bounds__(256) k_model_data(const double* __restrict__ X,
+                                                    const double* __restrict__ yt, int64_t n, int d,
+                                                    float* __restrict__ X32, float* __restrict__ y32) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * (d + 1);
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < n * d) X32[i] = (float)X[i];
+    else y32[i - n * d] = (float)yt[i - n * d];
+  }
+}
+
+bool mlp_train_model(MlpState* st, const Model* M, int steps, double lr, float* loss_hist,
+                     bool use_graph, hipStream_t s) {
+  const int64_t n = M->n;
+  const int d = M->d;
+  const size_t bytes = (size_t)(n * d + n) * sizeof(float);
+  if (st->data_bytes < bytes) {
+    if (st->data) {
+      (void)hipStreamSynchronize(s);
+      dfree(st->ctx, st->data);
+    }
+    st->data = (float*)dmalloc(st->ctx, bytes);
+    st->data_bytes = st->data ? bytes : 0;
+    if (!st->data) return false;
+  }
+  float* X32 = st->data;
+  float* y32 = st->data + n * d;
+  const unsigned grid = (unsigned)std::min<int64_t>(1024, ceil_div(n * (d + 1), 256));
+  hipLaunchKernelGGL(k_model_data, dim3(grid), dim3(256), 0, s, M->X64, M->yt, n, d, X32, y32);
+  return mlp_train(st, n, X32, y32, steps, lr, loss_hist, use_graph, s);
 }
 
 bool mlp_grads(MlpState* st, int64_t n, const float* X, const float* y, float* grad, float* loss,

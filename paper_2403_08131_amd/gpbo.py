@@ -94,6 +94,8 @@ _SIGS = {
                                  C.c_void_p, C.c_void_p]),
     "gpbo_mlp_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                  C.c_int32, C.c_double, C.c_void_p]),
+    "gpbo_mlp_train_model": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
+                                       C.c_void_p]),
     "gpbo_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "gpbo_mlp_prescreen": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_double,
                                      C.c_int64, C.c_void_p, C.c_void_p]),
@@ -440,6 +442,13 @@ class Mlp:
         hist = torch.empty((steps, self.E), dtype=torch.float32, device=self.ctx.device) if history else None
         self.ctx.check(lib().gpbo_mlp_train(self.ctx.h, self.h, X.shape[0], _ptr(X), _ptr(y),
                                             int(steps), float(lr), _ptr(hist)))
+        return hist
+
+    def train_on_model(self, model, steps, lr=1e-3, history=True):
+        """gpbo_mlp_train_model: train on a fitted model's X and normalised y."""
+        hist = torch.empty((steps, self.E), dtype=torch.float32, device=self.ctx.device) if history else None
+        self.ctx.check(lib().gpbo_mlp_train_model(self.ctx.h, self.h, model.h, int(steps), float(lr),
+                                                  _ptr(hist)))
         return hist
 
     def forward(self, Xc):

@@ -169,3 +169,44 @@ def test_c5_multi_chunk_equals_single_chunks(ctx, c5_full):
         part = G.score(ctx, m, Xc[lo:hi].contiguous(), "fp32")
         for k in ("mu", "sigma", "ei"):
             assert torch.equal(whole[k][lo:hi], part[k]), (k, lo)
+
+
+def test_c5_full_pool_argmax_against_oracle(ctx, c5_full):
+    """The argmax over all 262,144 candidates against the oracle's argmax
+    over all of them (R8), and the oracle's EI of the device's pick."""
+    p, f, m = c5_full
+    ctx.set_score_path("auto")
+    out = G.score(ctx, m, _t(p.Xc, torch.float32), "fp32", want=("ei",), host_argmax=True)
+    print("c5-s full pool: oracle scoring 262144 candidates", flush=True)
+    ref_ei = O.score(f, p.Xc, want=("ei",))["ei"]
+    am = out["argmax"]
+    print(f"  device argmax {am}, oracle argmax {O.argmax(ref_ei)}; "
+          f"|dEI|/EI_max {np.max(np.abs(out['ei'].double().cpu().numpy() - ref_ei)) / ref_ei.max():.2e}")
+    _check_argmax(ref_ei, am, TOL)
+    assert out["ei_max"] == pytest.approx(float(out["ei"][am].item()), rel=1e-6)
+
+
+def test_c4_gp_large_path_at_n4096(ctx):
+    """The exact GP of the learned-prescreen workload (d=20, n=4096
+    evaluations, lengthscales x sqrt(d)) on the large-n path: mu and sigma
+    on 512 candidates spread over the 1,048,576-row pool within 1e-4 of the
+    oracle, and the argmax over a 4096-row re-score set (the size the
+    prescreen hands to the GP) equal to the oracle's over the same rows."""
+    p = I.make_config("c4")
+    print("c4 GP: oracle fit at n=4096", flush=True)
+    f, m = _fit_both(ctx, p, refine=False)
+    Xc = _t(p.Xc, torch.float32)
+    out = G.score(ctx, m, Xc, "fp32")
+    rows = np.unique(np.concatenate([np.linspace(0, p.m - 1, 500).astype(np.int64),
+                                     [int(out["argmax"].item())]]))
+    ref = O.score(f, p.Xc[rows])
+    e_mu, e_sg, e_ei = _errors(ref, out, f, p.signal_var, rows)
+    print(f"  c4 GP sampled {rows.size}: e_mu={e_mu:.3e} e_sigma={e_sg:.3e} e_ei={e_ei:.3e}")
+    assert e_mu <= TOL and e_sg <= TOL
+    # re-score set: 4096 rows of the pool, scored on the same path
+    sub_rows = np.random.default_rng(4).choice(p.m, 4096, replace=False)
+    sub = _t(p.Xc[sub_rows], torch.float32)
+    rs = G.score(ctx, m, sub, "fp32", host_argmax=True)
+    ref_sub = O.score(f, p.Xc[sub_rows], want=("ei",))["ei"]
+    _check_argmax(ref_sub, rs["argmax"], TOL)
+    m.free()

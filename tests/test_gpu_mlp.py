@@ -162,6 +162,30 @@ def test_mlp_training_reduces_loss_and_graph_replays(ctx):
     assert np.all(h1[19] < h1[0])
 
 
+def test_prescreen_ei_matches_oracle_and_sort(ctx):
+    """gpbo_mlp_prescreen: the ensemble EI (member mean, population standard
+    deviation, EI against f_best) of every candidate equals the oracle's
+    ens_ei on the device's member outputs to float32 evaluation error, and
+    the top-k indices equal a sort of the device's own float32 EI."""
+    flat = _init(13)
+    net = G.Mlp(ctx, torch.tensor(flat, dtype=torch.float32, device=DEV).contiguous(), E, D, H)
+    X, _, _ = _data(30000, seed=14)
+    Xd = torch.tensor(X, dtype=torch.float32, device=DEV)
+    outs = net.forward(Xd).double().cpu().numpy()
+    for fbest, k in ((float(np.quantile(outs.mean(0), 0.01)), 1),
+                     (float(np.quantile(outs.mean(0), 0.2)), 999),
+                     (float(outs.mean(0).min()) - 0.5, 4096)):
+        idx, ei = net.prescreen(Xd, fbest, k, want_ei=True)
+        ei = ei.double().cpu().numpy()
+        _, _, ref = O.ens_ei(outs, fbest)
+        err = np.max(np.abs(ei - ref)) / np.max(ref)
+        print(f"  prescreen EI f_best={fbest:.3f}: max |dEI| / EI_max = {err:.2e}")
+        assert err <= 1e-5, fbest
+        want = np.lexsort((np.arange(ei.size), -ei))[:k]
+        assert np.array_equal(idx.cpu().numpy(), want), fbest
+    net.free()
+
+
 def test_prescreen_lcb_matches_oracle_and_sort(ctx):
     """The LCB score equals the oracle's on the device's member outputs to
     float32 rounding, and the top-k indices equal a sort of the device's own
@@ -247,3 +271,39 @@ def test_context_close_frees_live_objects():
     assert model.h is None and net.h is None
     model.free()
     net.free()
+
+
+def test_train_on_model_equals_explicit_targets(ctx):
+    """gpbo_mlp_train_model trains on a fitted model's own observations: the
+    same parameters and loss history, bit for bit, as gpbo_mlp_train on X
+    cast to float32 and the fit's z-scored y (checked against the oracle's
+    normalisation) passed explicitly."""
+    p = I.make_config("c4", n=512, m=16)
+    X = torch.tensor(p.X, device=DEV)
+    y = torch.tensor(p.y, device=DEV)
+    model = G.fit(ctx, X, y, p.lengthscale, p.kernel, p.signal_var, p.noise_var)
+    s = model.stats()
+    f = O.fit(p.X, p.y, p.lengthscale, O.SE, p.signal_var, p.noise_var)
+    assert s["ymean"] == pytest.approx(f.ymean, rel=1e-14)
+    assert s["ystd"] == pytest.approx(f.ystd, rel=1e-13)
+    # the fit's own statistics, applied as the fit applies them
+    yt = ((p.y - s["ymean"]) / s["ystd"]).astype(np.float32)
+    flat = torch.tensor(_init(21), dtype=torch.float32, device=DEV).contiguous()
+    a = G.Mlp(ctx, flat, E, D, H)
+    b = G.Mlp(ctx, flat, E, D, H)
+    ha = a.train_on_model(model, steps=30, lr=1e-3)
+    hb = b.train(torch.tensor(p.X, dtype=torch.float32, device=DEV).contiguous(),
+                 torch.tensor(yt, device=DEV), steps=30, lr=1e-3)
+    torch.cuda.synchronize()
+    assert torch.equal(ha, hb)
+    assert torch.equal(a.params(), b.params())
+    with pytest.raises(G.GpboError):  # n must be a multiple of 64
+        q = I.make_config("c4", n=500, m=16)
+        m2 = G.fit(ctx, torch.tensor(q.X, device=DEV), torch.tensor(q.y, device=DEV), q.lengthscale)
+        try:
+            a.train_on_model(m2, steps=1)
+        finally:
+            m2.free()
+    a.free()
+    b.free()
+    model.free()

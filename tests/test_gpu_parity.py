@@ -65,6 +65,22 @@ def _errors(ref, out, fit, sf2):
     return e_mu, e_sg, e_ei, int((~floor).sum())
 
 
+def _check_ei(ref, out, fit, sf2, bound):
+    """EI follows from mu and sigma with |dEI/dmu| = Phi(z) <= 1 and
+    |dEI/dsigma| = phi(z) <= 1/sqrt(2 pi): per candidate |dEI| is at most
+    |dmu| + 0.4 |dsigma| plus the rounding of EI itself; over the pool the
+    error relative to the largest EI is gated at `bound`."""
+    mu = out["mu"].double().cpu().numpy()
+    sg = out["sigma"].double().cpu().numpy()
+    ei = out["ei"].double().cpu().numpy()
+    top = max(np.max(ref["ei"]), 1e-300)
+    lip = np.abs(mu - ref["mu"]) + 0.4 * np.abs(sg - ref["sigma"]) + 1e-6 * top
+    assert np.all(np.abs(ei - ref["ei"]) <= lip * (1 + 1e-6))
+    e_ei = np.max(np.abs(ei - ref["ei"])) / top
+    assert e_ei <= bound, e_ei
+    return e_ei
+
+
 def _check_argmax(ref_ei, am, emax, bound):
     order = np.argsort(-ref_ei, kind="stable")
     best = O.argmax(ref_ei)
@@ -199,6 +215,7 @@ def test_score_c1_fp64_and_fp32(ctx):
         e_mu, e_sg, e_ei, below = _errors(ref, out, f, p.signal_var)
         print(f"  c1 {prec}: e_mu={e_mu:.3e} e_sigma={e_sg:.3e} e_ei={e_ei:.3e} below={below}")
         assert e_mu <= tol and e_sg <= tol
+        _check_ei(ref, out, f, p.signal_var, 1e-3 if prec == "fp32" else 1e-9)
         am = int(out["argmax"].item())
         _check_argmax(ref["ei"], am, float(out["ei_max"].item()), tol)
         assert float(out["ei_max"].item()) == pytest.approx(ref["ei"][am], rel=max(tol, 1e-6) * 10)
@@ -215,7 +232,25 @@ def test_score_c2s_fp32_ragged(ctx, m_cand):
     e_mu, e_sg, e_ei, below = _errors(ref, out, f, p.signal_var)
     print(f"  c2-s fp32 m={m_cand}: e_mu={e_mu:.3e} e_sigma={e_sg:.3e} e_ei={e_ei:.3e}")
     assert e_mu <= 1e-4 and e_sg <= 1e-4
+    _check_ei(ref, out, f, p.signal_var, 1e-3)
     _check_argmax(ref["ei"], int(out["argmax"].item()), float(out["ei_max"].item()), 1e-4)
+    m.free()
+
+
+def test_score_c2s_full_pool_argmax(ctx):
+    """d=20, n=512, all 65,536 candidates (lengthscales x sqrt(d)): the
+    argmax over the whole pool against the oracle's over the whole pool
+    (R8), with mu, sigma and EI element by element."""
+    p = I.make_config("c2-s")
+    f, m = _fit_both(ctx, p)
+    print("c2-s full pool: oracle scoring 65536 candidates", flush=True)
+    ref = O.score(f, p.Xc)
+    out = G.score(ctx, m, _t(p.Xc, torch.float32), "fp32", host_argmax=True)
+    e_mu, e_sg, e_ei, below = _errors(ref, out, f, p.signal_var)
+    print(f"  c2-s full: e_mu={e_mu:.3e} e_sigma={e_sg:.3e} e_ei={e_ei:.3e} below floor {below}")
+    assert e_mu <= 1e-4 and e_sg <= 1e-4
+    _check_ei(ref, out, f, p.signal_var, 1e-3)
+    _check_argmax(ref["ei"], out["argmax"], out["ei_max"], 1e-4)
     m.free()
 
 
@@ -263,8 +298,27 @@ def test_score_noise_free_interpolation(ctx):
     y = np.sin(4 * X[:, 0]) + X[:, 1] * X[:, 2]
     m = G.fit(ctx, _t(X), _t(y), [0.3, 0.3, 0.3], G.KERNEL_MATERN52, 1.0, 0.0)
     out = G.score(ctx, m, _t(X), "fp64")
-    assert np.max(np.abs(out["mu"].cpu().numpy() - y)) <= 1e-8 * np.max(np.abs(y))
-    assert np.max(out["sigma"].cpu().numpy()) <= 1e-4
+    assert np.max(np.abs(out["mu"].cpu().numpy() - y)) <= 1e-10 * np.max(np.abs(y))
+    assert np.max(out["sigma"].cpu().numpy() ** 2) <= 1e-10
+    m.free()
+
+
+def test_fit_refinement_on_ill_conditioned_k(ctx):
+    """R16 at cond(K) ~ 7e5 (two dimensions, 269 points, literal
+    lengthscales): float32 products with the float32 inverse factor, one
+    float64 residual and a float32 correction reduce |ytilde - K alpha| by
+    at least 100x (or to 1e-10 |ytilde|)."""
+    p = I.make_c3(lam=0.0, replicate=0, scaled=False, B=64, m=16)[42]
+    cond = _cond(p)
+    assert cond >= 1e5
+    f, m = _fit_both(ctx, p, refine=True)
+    s = m.stats()
+    ynorm = np.linalg.norm((p.y - p.y.mean()) / p.y.std())
+    _, _, a = m.factors()
+    err = np.max(np.abs(a.cpu().numpy() - f.alpha)) / np.max(np.abs(f.alpha))
+    print(f"refinement at cond {cond:.2e}: residual {s['res0']:.3e} -> {s['res1']:.3e} "
+          f"(|ytilde| {ynorm:.3e}), alpha error {err:.2e}")
+    assert s["res1"] <= s["res0"] / 100 or s["res1"] <= 1e-10 * ynorm
     m.free()
 
 
