@@ -216,6 +216,50 @@ void oracle_score(int n, int d, const double* X, int kernel, const double* ls,
   }
 }
 
+/*
+ * Posterior mean and an upper bound of the standard deviation and of EI for
+ * m candidates, from the fit alone (no triangular solve):
+ *   mu as in oracle_score;
+ *   conditioning on fewer observations never lowers the posterior variance
+ *   of the latent function, and conditioning on the single noisy
+ *   observation y_i gives  var_i = sf2 - k(x*, x_i)^2 / (sf2 + sn2);  the
+ *   smallest of these (the observation with the largest covariance) bounds
+ *   the full posterior variance from above:
+ *     var_ub_z = max(sf2 - max_i k(x*, x_i)^2 / (sf2 + sn2), 0);
+ *   sigma_ub = s_y sqrt(var_ub_z);
+ *   EI grows with sigma (dEI/dsigma = phi(z) > 0), so
+ *     ei_ub = EI(mu, sigma_ub, f_best) >= EI(mu, sigma, f_best).
+ * Any output may be NULL.  nthreads <= 0 keeps the OpenMP default.
+ */
+void oracle_score_bound(int n, int d, const double* X, int kernel, const double* ls, double sf2,
+                        double sn2, const double* alpha, const double* stats, int64_t m,
+                        const double* Xc, double* mu, double* sigma_ub, double* ei_ub,
+                        int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+  const double ymean = stats[0], sy = stats[1], fbest = stats[2];
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < m; ++j) {
+    const double* xs = Xc + (size_t)j * d;
+    double muz = 0.0, kmax = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double k = oracle_kernel(kernel, d, xs, X + (size_t)i * d, ls, sf2);
+      muz += k * alpha[i];
+      if (k > kmax) kmax = k;
+    }
+    double varz = sf2 - kmax * kmax / (sf2 + sn2);
+    if (varz < 0.0) varz = 0.0;
+    const double mj = ymean + sy * muz;
+    const double sj = sy * sqrt(varz);
+    if (mu) mu[j] = mj;
+    if (sigma_ub) sigma_ub[j] = sj;
+    if (ei_ub) ei_ub[j] = oracle_ei(mj, sj, fbest);
+  }
+}
+
 int oracle_max_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -75,6 +75,9 @@ def lib():
         L.oracle_score.restype = None
         L.oracle_score.argtypes = [C.c_int, C.c_int, dp, C.c_int, dp, C.c_double, dp, dp,
                                    dp, C.c_int64, dp, dp, dp, dp, C.c_int]
+        L.oracle_score_bound.restype = None
+        L.oracle_score_bound.argtypes = [C.c_int, C.c_int, dp, C.c_int, dp, C.c_double, C.c_double,
+                                         dp, dp, C.c_int64, dp, dp, dp, dp, C.c_int]
         L.oracle_max_threads.restype = C.c_int
         L.oracle_max_threads.argtypes = []
         L.oracle_argmax.restype = C.c_int64
@@ -218,6 +221,24 @@ def score(f: Fit, Xc, nthreads=0, want=("mu", "sigma", "ei")):
     s, ps = _d(f.stats)
     lib().oracle_score(X.shape[0], X.shape[1], px, int(f.kernel), pl, float(f.sf2), pL, pa,
                        ps, m, pc, ptrs[0], ptrs[1], ptrs[2], int(nthreads))
+    return out
+
+
+def score_bound(f: Fit, Xc, nthreads=0):
+    """Posterior mean, the nearest-observation upper bound of the standard
+    deviation and the EI upper bound it implies (see gp_oracle.c)."""
+    Xc, pc = _d(Xc)
+    m = Xc.shape[0]
+    out = {k: np.empty(m) for k in ("mu", "sigma_ub", "ei_ub")}
+    X, px = _d(f.X)
+    ls, pl = _d(f.ls)
+    a, pa = _d(f.alpha)
+    s, ps = _d(f.stats)
+    dp = C.POINTER(C.c_double)
+    lib().oracle_score_bound(X.shape[0], X.shape[1], px, int(f.kernel), pl, float(f.sf2),
+                             float(f.sn2), pa, ps, m, pc, out["mu"].ctypes.data_as(dp),
+                             out["sigma_ub"].ctypes.data_as(dp), out["ei_ub"].ctypes.data_as(dp),
+                             int(nthreads))
     return out
 
 

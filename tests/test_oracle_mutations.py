@@ -36,6 +36,8 @@ MUTATIONS = {
     "argmax_last_tie": ("if (best < 0 || v[j] > v[best]) best = j;\n  }\n  return best;",
                         "if (best < 0 || v[j] >= v[best]) best = j;\n  }\n  return best;"),
     "ens_sample_std": ("sqrt(q / E)", "sqrt(q / (E - 1))"),
+    "bound_drop_noise": ("kmax * kmax / (sf2 + sn2)", "kmax * kmax / sf2"),
+    "bound_min_k": ("if (k > kmax) kmax = k;", "if (kmax == 0.0 || k < kmax) kmax = k;"),
     "w2_transposed": ("s += rnd(W2[(size_t)h * H + k], bf16) * h1[k];",
                       "s += rnd(W2[(size_t)k * H + h], bf16) * h1[k];"),
 }

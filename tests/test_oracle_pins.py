@@ -279,6 +279,53 @@ def test_posterior_n1_closed_form():
     assert s2["mu"][0] == pytest.approx(want, rel=1e-14)
 
 
+def test_score_bound_n1_equals_posterior():
+    """One observation: the nearest-observation bound is the posterior itself
+    (the single-point conditional variance sf2 - k^2 / (sf2 + sn2))."""
+    x1 = np.array([[0.2, 0.7]])
+    f = O.fit(x1, np.array([2.5]), [0.4, 0.9], O.SE, 1.3, 0.2, normalize_y=False)
+    xs = np.array([[0.5, 0.1], [0.2, 0.7], [0.9, 0.95]])
+    s = O.score(f, xs)
+    b = O.score_bound(f, xs)
+    assert np.allclose(b["mu"], s["mu"], rtol=1e-15, atol=0)
+    assert np.allclose(b["sigma_ub"], s["sigma"], rtol=1e-14, atol=0)
+    assert np.allclose(b["ei_ub"], s["ei"], rtol=1e-13, atol=0)
+
+
+def test_score_bound_n2_brute_force():
+    """Two observations: the bound is the smaller of the two single-point
+    conditional variances, written out by hand, and it is not below the
+    two-point posterior variance."""
+    X = np.array([[0.1, 0.3], [0.6, 0.4]])
+    y = np.array([1.0, -0.5])
+    ls, sf2, sn2 = [0.3, 0.5], 0.8, 0.05
+    f = O.fit(X, y, ls, O.MATERN52, sf2, sn2)
+    xs = np.array([[0.2, 0.3], [0.5, 0.5], [0.35, 0.35]])
+    b = O.score_bound(f, xs)
+    s = O.score(f, xs)
+    for j in range(3):
+        k = [O.kernel(O.MATERN52, xs[j], X[i], ls, sf2) for i in range(2)]
+        v1 = [sf2 - ki * ki / (sf2 + sn2) for ki in k]
+        want = f.ystd * math.sqrt(min(v1))
+        assert b["sigma_ub"][j] == pytest.approx(want, rel=1e-14)
+        assert b["sigma_ub"][j] >= s["sigma"][j]
+        assert b["ei_ub"][j] == pytest.approx(O.ei(b["mu"][j], b["sigma_ub"][j], f.fbest), rel=1e-14)
+
+
+def test_score_bound_dominates_posterior():
+    r = _rng(21)
+    X = r.uniform(0, 1, (40, 3))
+    y = r.normal(size=40)
+    f = O.fit(X, y, [0.3, 0.5, 0.4], O.SE, 1.2, 1e-3)
+    Xc = r.uniform(0, 1, (300, 3))
+    s = O.score(f, Xc)
+    b = O.score_bound(f, Xc)
+    assert np.allclose(b["mu"], s["mu"], rtol=1e-13, atol=1e-13)
+    assert np.all(b["sigma_ub"] >= s["sigma"] * (1 - 1e-12))
+    assert np.all(b["ei_ub"] >= s["ei"] * (1 - 1e-12) - 1e-15)
+    assert np.any(b["sigma_ub"] > s["sigma"] * 1.01)  # a bound, not an identity
+
+
 def test_posterior_far_field_is_prior():
     r = _rng(11)
     X = r.uniform(0, 1, (15, 3))
