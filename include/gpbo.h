@@ -280,9 +280,45 @@ gpbo_status gpbo_score_batched(gpbo_ctx ctx, int32_t B, const gpbo_model* models
                                void* const* mu, void* const* sigma, void* const* ei,
                                int64_t* argmax, double* ei_max);
 
+/* Posterior mean and two cheap upper bounds, without the triangular
+ * product: the cost is the cross-covariance alone (about 2nd flops and n
+ * exponentials per candidate against the n^2 of the variance), so a large
+ * pool can be narrowed before exact scoring.  Conditioning the latent
+ * function on fewer observations never lowers its posterior variance
+ * (R&W Sec. 2.2), and the one noisy observation with the largest covariance
+ * leaves sf2 - k_max^2 / (sf2 + noise_var): sigma_ub = s_y sqrt of that is
+ * an upper bound of sigma, and, EI growing with sigma, ei_ub =
+ * EI(mu, sigma_ub) is an upper bound of EI.
+ * Xc: device, m x d float; mu, sigma_ub, ei_ub: device, m float each (any
+ * may be NULL).  float32 arithmetic as in the GPBO_FP32 cross-covariance
+ * (no escalation).  Asynchronous. */
+gpbo_status gpbo_score_bound(gpbo_ctx ctx, gpbo_model model, int64_t m, const float* Xc,
+                             float* mu, float* sigma_ub, float* ei_ub);
+
+/* Exact judge of a prescreened subset of a pool (the learned prescreen's
+ * re-score and its fallback): of the k1 candidates Xc[idx[i]] (Xc: device,
+ * m x d float; idx: device, k1 int64, entries in [0, m)), the k2 with the
+ * largest EI upper bound (gpbo_score_bound; every one of them when k2 >= k1)
+ * are scored exactly on the GPBO_FP32 path, and the one with the largest EI
+ * is returned: *next its index into Xc, *ei_max its EI.  *certified is 1
+ * when that EI is not below the (k2+1)-th largest bound plus an allowance
+ * for float32 rounding (2e-4 s_y sqrt(signal_var)): then no candidate of the
+ * subset left unscored can have a larger EI; 0 otherwise (call again with a
+ * larger k2 to widen the exact set).  next, ei_max, certified: device or
+ * host memory (host memory synchronises); ei_max and certified may be NULL.
+ * k2 + 1 <= 8192 unless k2 >= k1.  Asynchronous for device outputs. */
+gpbo_status gpbo_score_subset(gpbo_ctx ctx, gpbo_model model, int64_t m, const float* Xc,
+                              int64_t k1, const int64_t* idx, int64_t k2, int64_t* next,
+                              double* ei_max, int32_t* certified);
+
 /* Top k of v (device, m floats) by (value descending, index ascending); idx
- * is a device array of k int64.  NaN entries never rank.  Asynchronous. */
+ * is a device array of k int64.  NaN entries never rank.  k <= 8192
+ * (GPBO_E_UNSUPPORTED above).  Asynchronous. */
 gpbo_status gpbo_topk(gpbo_ctx ctx, int64_t m, const float* v, int64_t k, int64_t* idx);
+/* The same k entries as gpbo_topk (membership by value descending, index
+ * ascending among ties) for any k <= m, as a set: idx (device, k int64) in
+ * ascending index order.  Asynchronous. */
+gpbo_status gpbo_topk_set(gpbo_ctx ctx, int64_t m, const float* v, int64_t k, int64_t* idx);
 
 /* out[i, :] = Xc[idx[i], :] for i < k (device float arrays, row-major, d
  * columns).  Asynchronous. */
@@ -330,15 +366,17 @@ gpbo_status gpbo_mlp_forward(gpbo_ctx ctx, gpbo_mlp mlp, int64_t m, const float*
                              float* out);
 /* Prescreen: ensemble mean and population standard deviation over members,
  * EI against f_best (in the network's output units), then the indices of the
- * k largest EI (device int64, descending EI, ascending index among ties).
- * ei_out (device m float) may be NULL.  Asynchronous. */
+ * k largest EI (device int64): for k <= 8192 sorted by descending EI,
+ * ascending index among ties; for larger k (up to m) the same set in
+ * ascending index order (see gpbo_topk_set).  ei_out (device m float) may
+ * be NULL.  Asynchronous. */
 gpbo_status gpbo_mlp_prescreen(gpbo_ctx ctx, gpbo_mlp mlp, int64_t m, const float* Xc,
                                double f_best, int64_t k, int64_t* topk_idx, float* ei_out);
 /* Prescreen by the ensemble's lower confidence bound: score = -(mean - kappa
  * sd) (mean and population standard deviation over the members, in the
  * network's output units; larger is better for minimisation), then the
- * indices of the k largest scores (device int64, descending score, ascending
- * index among ties).  kappa >= 0; kappa = 0 ranks by the predicted mean.
+ * indices of the k largest scores (device int64; ordered as in
+ * gpbo_mlp_prescreen).  kappa >= 0; kappa = 0 ranks by the predicted mean.
  * score_out (device m float) may be NULL.  Asynchronous. */
 gpbo_status gpbo_mlp_prescreen_lcb(gpbo_ctx ctx, gpbo_mlp mlp, int64_t m, const float* Xc,
                                    double kappa, int64_t k, int64_t* topk_idx, float* score_out);

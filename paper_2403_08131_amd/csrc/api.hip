@@ -1145,6 +1145,129 @@ gpbo_status gpbo_topk(gpbo_ctx c, int64_t m, const float* v, int64_t k, int64_t*
   return GPBO_OK;
 }
 
+gpbo_status gpbo_topk_set(gpbo_ctx c, int64_t m, const float* v, int64_t k, int64_t* idx) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (m < 0 || k < 0 || (m > 0 && !v) || (k > 0 && !idx))
+    return fail(c, GPBO_E_INVALID_ARG, "invalid top-k arguments");
+  if (k > m) return fail(c, GPBO_E_INVALID_ARG, "k (%lld) exceeds m (%lld)", (long long)k, (long long)m);
+  if (m > 0xffffffffLL) return fail(c, GPBO_E_UNSUPPORTED, "m >= 2^32 is not supported");
+  if (k == 0) return GPBO_OK;
+  DeviceGuard g(c->device);
+  void* ws = dmalloc(c, topk_set_scratch_bytes(m));
+  if (!ws) return fail(c, GPBO_E_OOM, "top-k scratch allocation failed");
+  launch_topk_set_into(m, v, k, idx, ws, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  dfree(c, ws);  // stream-ordered with the torch allocator; hipFree waits otherwise
+  return GPBO_OK;
+}
+
+gpbo_status gpbo_score_bound(gpbo_ctx c, gpbo_model M, int64_t m, const float* Xc, float* mu,
+                             float* sigma_ub, float* ei_ub) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (!M) return fail(c, GPBO_E_INVALID_ARG, "model is NULL");
+  if (m < 0 || (m > 0 && !Xc)) return fail(c, GPBO_E_INVALID_ARG, "invalid candidate pool");
+  if (m == 0) return GPBO_OK;
+  DeviceGuard g(c->device);
+  hipStream_t s = c->stream;
+  note_stream(M, s);
+  {
+    Model* one[1] = {M};
+    ensure_score_operands(c, one, 1, GPBO_FP32, s);
+  }
+  if (!M->blk_obs || !M->blk_score[GPBO_FP32])
+    return fail(c, GPBO_E_OOM, "device allocation of the score operands failed (n=%d)", M->n);
+  launch_score_bound(M, m, Xc, mu, sigma_ub, ei_ub, s);
+  HIP_TRY(c, hipGetLastError());
+  return GPBO_OK;
+}
+
+gpbo_status gpbo_score_subset(gpbo_ctx c, gpbo_model M, int64_t m, const float* Xc, int64_t k1,
+                              const int64_t* idx, int64_t k2, int64_t* next, double* ei_max,
+                              int32_t* certified) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (!M) return fail(c, GPBO_E_INVALID_ARG, "model is NULL");
+  if (m <= 0 || !Xc || k1 <= 0 || k1 > m || !idx || k2 <= 0 || !next)
+    return fail(c, GPBO_E_INVALID_ARG, "invalid subset arguments");
+  if (k2 > k1) k2 = k1;
+  if (k2 + 1 > topk_max_k() && k2 < k1)
+    return fail(c, GPBO_E_UNSUPPORTED, "k2 + 1 > %d is not supported", topk_max_k());
+  DeviceGuard g(c->device);
+  hipStream_t s = c->stream;
+  note_stream(M, s);
+  const int d = M->d;
+  const bool all = k2 == k1;  // every candidate of the subset scored exactly
+  const int64_t kk = all ? k2 : k2 + 1;
+  Carve cv;
+  const size_t o_rows1 = cv.take((size_t)k1 * d * sizeof(float));
+  const size_t o_bound = cv.take((size_t)k1 * sizeof(float));
+  const size_t o_pos = cv.take((size_t)kk * sizeof(int64_t));
+  const size_t o_idx2 = cv.take((size_t)k2 * sizeof(int64_t));
+  const size_t o_rows2 = cv.take((size_t)k2 * d * sizeof(float));
+  const size_t o_res = cv.take(64);
+  const size_t o_ws = cv.take(topk_scratch_bytes(k1, kk));
+  char* b = (char*)dmalloc(c, cv.bytes);
+  if (!b) return fail(c, GPBO_E_OOM, "subset scratch allocation failed");
+  float* rows1 = (float*)(b + o_rows1);
+  float* bound = (float*)(b + o_bound);
+  int64_t* pos = (int64_t*)(b + o_pos);
+  int64_t* idx2 = (int64_t*)(b + o_idx2);
+  float* rows2 = (float*)(b + o_rows2);
+  int64_t* am = (int64_t*)(b + o_res);
+  double* em = (double*)(b + o_res + 8);
+  int64_t* next_d = (int64_t*)(b + o_res + 16);
+  double* emax_d = (double*)(b + o_res + 24);
+  int* cert_d = (int*)(b + o_res + 32);
+  if (all) {
+    // no narrowing: the subset itself is scored exactly, in the given order
+    HIP_TRY(c, hipMemcpyAsync(idx2, idx, (size_t)k2 * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  } else {
+    // the k2 + 1 largest EI bounds among the subset; the first k2 are scored
+    // exactly, the last one certifies
+    launch_gather_rows(k1, idx, d, Xc, rows1, s);
+    {
+      Model* one[1] = {M};
+      ensure_score_operands(c, one, 1, GPBO_FP32, s);
+    }
+    if (!M->blk_obs || !M->blk_score[GPBO_FP32]) {
+      dfree(c, b);
+      return fail(c, GPBO_E_OOM, "device allocation of the score operands failed (n=%d)", M->n);
+    }
+    launch_score_bound(M, k1, rows1, nullptr, nullptr, bound, s);
+    launch_topk_into(k1, bound, kk, pos, b + o_ws, s);
+    launch_compose_idx(k2, idx, pos, idx2, s);
+  }
+  launch_gather_rows(k2, idx2, d, Xc, rows2, s);
+  gpbo_status st = gpbo_score(c, M, k2, rows2, GPBO_FP32, nullptr, nullptr, nullptr, am, em);
+  if (st != GPBO_OK) {
+    dfree(c, b);
+    return st;
+  }
+  // float32 errors of the exact EI and of the bound: 2e-4 of the prior
+  // standard deviation s_y sqrt(sf2) (s_y is read on the device)
+  launch_subset_finish(am, em, idx2, bound, all ? nullptr : pos + k2, 2e-4 * std::sqrt(M->sf2),
+                       M->stats, next_d, emax_d, cert_d, s);
+  HIP_TRY(c, hipGetLastError());
+  if (device_writable(next)) {
+    HIP_TRY(c, hipMemcpyAsync(next, next_d, 8, hipMemcpyDeviceToDevice, s));
+  } else {
+    HIP_TRY(c, hipMemcpyAsync(next, next_d, 8, hipMemcpyDeviceToHost, s));
+  }
+  if (ei_max)
+    HIP_TRY(c, hipMemcpyAsync(ei_max, emax_d, 8,
+                              device_writable(ei_max) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                              s));
+  if (certified)
+    HIP_TRY(c, hipMemcpyAsync(certified, cert_d, 4,
+                              device_writable(certified) ? hipMemcpyDeviceToDevice
+                                                         : hipMemcpyDeviceToHost,
+                              s));
+  const bool host = !device_writable(next) || (ei_max && !device_writable(ei_max)) ||
+                    (certified && !device_writable(certified));
+  dfree(c, b);  // stream-ordered with the torch allocator; hipFree waits otherwise
+  if (host) HIP_TRY(c, hipStreamSynchronize(s));
+  return GPBO_OK;
+}
+
 gpbo_status gpbo_gather_rows(gpbo_ctx c, int64_t k, const int64_t* idx, int32_t d, const float* Xc,
                              float* out) {
   if (!c) return GPBO_E_INVALID_ARG;
@@ -1289,14 +1412,17 @@ static gpbo_status prescreen(Ctx* c, gpbo_mlp mlp, int64_t m, const float* Xc, b
   if (!mlp || m < 0 || k < 0 || k > m || (m > 0 && !Xc) || (k > 0 && !topk_idx))
     return fail(c, GPBO_E_INVALID_ARG, "invalid prescreen arguments");
   if (lcb && !(arg >= 0.0)) return fail(c, GPBO_E_INVALID_ARG, "kappa must be >= 0");
-  if (k > topk_max_k()) return fail(c, GPBO_E_UNSUPPORTED, "k > %d is not supported", topk_max_k());
   if (m > 0xffffffffLL) return fail(c, GPBO_E_UNSUPPORTED, "m >= 2^32 is not supported");
   if (m == 0) return GPBO_OK;
   DeviceGuard g(c->device);
   hipStream_t s = c->stream;
+  // up to the sort's limit the k indices come sorted by score; beyond it, as
+  // the same set in ascending index order
+  const bool sorted = k <= topk_max_k();
   float* outs = (float*)dmalloc(c, (size_t)mlp->E * m * sizeof(float));
   float* sc = score_out ? score_out : (float*)dmalloc(c, (size_t)m * sizeof(float));
-  void* scratch = k > 0 ? dmalloc(c, topk_scratch_bytes(m, k)) : nullptr;
+  void* scratch =
+      k > 0 ? dmalloc(c, sorted ? topk_scratch_bytes(m, k) : topk_set_scratch_bytes(m)) : nullptr;
   if (!outs || !sc || (k > 0 && !scratch)) {
     dfree(c, outs);
     if (!score_out) dfree(c, sc);
@@ -1308,7 +1434,10 @@ static gpbo_status prescreen(Ctx* c, gpbo_mlp mlp, int64_t m, const float* Xc, b
     mlp_ens_lcb(mlp->st, m, outs, arg, sc, s);
   else
     mlp_ens_ei(mlp->st, m, outs, arg, sc, s);
-  if (k > 0) launch_topk_into(m, sc, k, topk_idx, scratch, s);
+  if (k > 0) {
+    if (sorted) launch_topk_into(m, sc, k, topk_idx, scratch, s);
+    else launch_topk_set_into(m, sc, k, topk_idx, scratch, s);
+  }
   HIP_TRY(c, hipGetLastError());
   dfree(c, outs);
   if (!score_out) dfree(c, sc);

@@ -263,6 +263,10 @@ int64_t large_partials(int npj, int64_t m);
 // triangular product (the dominant kernel), for timing.
 void launch_score_large(const ScoreArgs& a, void* scratch, hipStream_t s,
                         const std::function<void(int)>& mark);
+// Posterior mean, nearest-observation bound of sigma and the EI bound
+// (float32; the model's float32 score operands must exist).
+void launch_score_bound(const Model* M, int64_t m, const float* Xc, float* mu, float* sigma_ub,
+                        float* ei_ub, hipStream_t s);
 void launch_argmax_final(const double* part_v, const int64_t* part_i, int64_t nparts,
                          int64_t* argmax, double* ei_max, hipStream_t s);
 // The float32 path escalated to float64 arithmetic on one problem (single
@@ -309,8 +313,22 @@ void launch_check_finite(const void* p, int64_t count, int is_double, int* flag,
 // Top-k and gather (select.hip)
 int topk_max_k();
 size_t topk_scratch_bytes(int64_t m, int64_t k);
-void launch_topk_into(int64_t m, const float* v, int64_t k, int64_t* idx, void* scratch,
+void launch_topk_into(int64_t m, const float* v, int64_t k, int64_t* idx, void* ws,
                       hipStream_t s);
+// The top k as a set, in ascending index order (any k <= m): membership as
+// in the sorted top-k (value descending, index ascending among ties).
+size_t topk_set_scratch_bytes(int64_t m);
+void launch_topk_set_into(int64_t m, const float* v, int64_t k, int64_t* idx, void* ws,
+                          hipStream_t s);
+// out[i] = outer[inner[i]] for i < k.
+void launch_compose_idx(int64_t k, const int64_t* outer, const int64_t* inner, int64_t* out,
+                        hipStream_t s);
+// Pool index of a subset's argmax, its EI, and the certificate (see
+// gpbo_score_subset); next_pos may be NULL (every candidate scored).
+void launch_subset_finish(const int64_t* am, const double* em, const int64_t* pool_idx,
+                          const float* bounds, const int64_t* next_pos, double tol,
+                          const double* stats, int64_t* next, double* ei_max, int* certified,
+                          hipStream_t s);
 void launch_gather_rows(int64_t k, const int64_t* idx, int d, const float* Xc, float* out,
                         hipStream_t s);
 

@@ -82,6 +82,110 @@ __global__ void __launch_bounds__(256) k_kstar(int n, int d, int npj, int nx,
     mu_part[(int64_t)blockIdx.y * mc_pad + cl0 + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
 }
 
+// Posterior mean and the nearest-observation bounds (no triangular product):
+// per candidate mu_z = sum_j khat_j (sf2 alpha_j) and khat_max = max_j khat_j;
+// conditioning on one noisy observation alone leaves the latent variance
+// sf2 - k^2 / (sf2 + sn2), and more observations only lower it, so
+// var_ub = sf2 - (sf2 khat_max)^2 / (sf2 + sn2) bounds the posterior variance
+// from above and EI(mu, sigma_ub) bounds EI.  Workgroup: KS_CG candidates,
+// 256 threads over the training points (one point per thread per pass,
+// coordinates read coalesced from the transposed scaled observations),
+// partial sums and maxima in registers, then across lanes and waves.
+struct BoundArgs {
+  int n, d, nx, kernel;
+  const float* XsT;      // d x nx scaled observations (padding points beyond n)
+  const float* sc;       // d candidate coordinate scales
+  const float* alpha;    // sf2 * alpha, zero beyond n
+  const double* stats;   // ymean, ystd, fbest
+  double sf2, sn2;
+  int64_t m;
+  const float* Xc;
+  float* mu;
+  float* sigma_ub;
+  float* ei_ub;
+};
+template <int KERN>
+__global__ void __launch_bounds__(256) k_score_bound(BoundArgs A) {
+  __shared__ __align__(16) float xcT[64 * KS_CG];  // [d][KS_CG], d <= 64
+  __shared__ float red_s[4][KS_CG], red_m[4][KS_CG];
+  const int t = threadIdx.x, lane = t % 64, wave = wave_id();
+  const int d = A.d, nx = A.nx;
+  const int64_t c0 = (int64_t)blockIdx.x * KS_CG;
+  for (int e = t; e < KS_CG * d; e += 256) {
+    const int c = e / d, k = e % d;
+    const int64_t gc = c0 + c;
+    xcT[k * KS_CG + c] = gc < A.m ? A.Xc[gc * d + k] * A.sc[k] : 0.0f;
+  }
+  __syncthreads();
+  float macc[KS_CG], kmax[KS_CG];
+#pragma unroll
+  for (int c = 0; c < KS_CG; ++c) {
+    macc[c] = 0.0f;
+    kmax[c] = 0.0f;
+  }
+  // columns n .. round_up(n, 64) - 1 are padding points (zero covariance and
+  // zero alpha) inside the row stride nx
+  const int jend = (int)round_up(A.n, 64);
+  for (int j = t; j < jend; j += 256) {
+    const float* xcol = A.XsT + j;
+    float r2[KS_CG];
+#pragma unroll
+    for (int c = 0; c < KS_CG; ++c) r2[c] = 0.0f;
+    float xnext = xcol[0];
+    for (int k = 0; k < d; ++k) {
+      const float xk = xnext;
+      if (k + 1 < d) xnext = xcol[(int64_t)(k + 1) * nx];
+      const float* xr = xcT + k * KS_CG;
+#pragma unroll
+      for (int c = 0; c < KS_CG; c += 4) {
+        const f4 x4 = *(const f4*)(xr + c);
+        const float u0 = xk - x4[0], u1 = xk - x4[1], u2 = xk - x4[2], u3 = xk - x4[3];
+        r2[c] = fmaf(u0, u0, r2[c]);
+        r2[c + 1] = fmaf(u1, u1, r2[c + 1]);
+        r2[c + 2] = fmaf(u2, u2, r2[c + 2]);
+        r2[c + 3] = fmaf(u3, u3, r2[c + 3]);
+      }
+    }
+    const float aj = A.alpha[j];
+#pragma unroll
+    for (int c = 0; c < KS_CG; ++c) {
+      const float kv = cov_from_r2<KERN>(r2[c]);
+      macc[c] = fmaf(kv, aj, macc[c]);
+      kmax[c] = fmaxf(kmax[c], kv);
+    }
+  }
+  // across the 64 lanes: sums by the transpose-reduction, maxima by butterflies
+  lane_transpose_sum<float, KS_CG>(macc, red_s[wave]);
+#pragma unroll
+  for (int c = 0; c < KS_CG; ++c) {
+    float v = kmax[c];
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    kmax[c] = v;
+  }
+  if (lane < KS_CG) {
+    float v = 0.0f;
+#pragma unroll
+    for (int c = 0; c < KS_CG; ++c) v = lane == c ? kmax[c] : v;
+    red_m[wave][lane] = v;
+  }
+  __syncthreads();
+  if (t < KS_CG && c0 + t < A.m) {
+    const float muz = (red_s[0][t] + red_s[1][t]) + (red_s[2][t] + red_s[3][t]);
+    const float km = fmaxf(fmaxf(red_m[0][t], red_m[1][t]), fmaxf(red_m[2][t], red_m[3][t]));
+    const float sf2 = (float)A.sf2;
+    const float kk = sf2 * km;
+    float var = sf2 - kk * kk / (sf2 + (float)A.sn2);
+    var = var > 0.0f ? var : 0.0f;
+    const float ymean = (float)A.stats[S_YMEAN], sy = (float)A.stats[S_YSTD];
+    const float mu = ymean + sy * muz;
+    const float sg = sy * __builtin_sqrtf(var);
+    const int64_t gc = c0 + t;
+    if (A.mu) A.mu[gc] = mu;
+    if (A.sigma_ub) A.sigma_ub[gc] = sg;
+    if (A.ei_ub) A.ei_ub[gc] = ei_of<float>(mu, sg, (float)A.stats[S_FBEST]);
+  }
+}
+
 // Triangular product with sum-of-squares epilogue.  Workgroup: 128 rows of
 // the inverse factor (eight 16-row tiles) x 128 candidates, eight waves; wave
 // (wp, wc) owns row tiles 2wp, 2wp + 1 of the block and candidates
@@ -312,6 +416,31 @@ void launch_score_large(const ScoreArgs& a, void* scratch, hipStream_t s,
                        a.part_v, a.part_i, pbase);
     pbase += nfb;
   }
+}
+
+void launch_score_bound(const Model* M, int64_t m, const float* Xc, float* mu, float* sigma_ub,
+                        float* ei_ub, hipStream_t s) {
+  BoundArgs a{};
+  a.n = M->n;
+  a.d = M->d;
+  a.nx = M->nx;
+  a.kernel = M->kernel;
+  a.XsT = M->Xs32;
+  a.sc = M->sc32;
+  a.alpha = (const float*)M->alphaT[GPBO_FP32];
+  a.stats = M->stats;
+  a.sf2 = M->sf2;
+  a.sn2 = M->sn2;
+  a.m = m;
+  a.Xc = Xc;
+  a.mu = mu;
+  a.sigma_ub = sigma_ub;
+  a.ei_ub = ei_ub;
+  const dim3 grid((unsigned)ceil_div(m, KS_CG));
+  if (M->kernel == GPBO_KERNEL_SE)
+    hipLaunchKernelGGL(k_score_bound<GPBO_KERNEL_SE>, grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_score_bound<GPBO_KERNEL_MATERN52>, grid, dim3(256), 0, s, a);
 }
 
 }  // namespace gpbo

@@ -155,6 +155,87 @@ __global__ void __launch_bounds__(SEL_BLOCK) k_sel_write(const float* __restrict
   }
 }
 
+// Top-k as a set in ascending index order (k beyond the sort's limit): per
+// block, the number of selected entries -- keys above the threshold, and
+// keys equal to it whose rank among the equal keys (in index order) is below
+// the count still needed -- then an exclusive scan over the blocks, then an
+// ordered write.  eq_before: exclusive prefix of the per-block equal counts.
+__device__ __forceinline__ void set_flags(const float* __restrict__ v, int64_t i, int64_t end,
+                                          unsigned thr, unsigned need_eq, unsigned eq_run,
+                                          unsigned* wave_eq, bool& sel, unsigned& chunk_eq) {
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const bool valid = i < end;
+  const unsigned key = valid ? fkey(v[i]) : 0u;
+  const bool eq = valid && key == thr;
+  const unsigned long long bal = __ballot(eq);
+  if (lane == 0) wave_eq[w] = __popcll(bal);
+  __syncthreads();
+  unsigned off = eq_run;
+  for (int q = 0; q < w; ++q) off += wave_eq[q];
+  chunk_eq = 0;
+  for (int q = 0; q < SEL_BLOCK / 64; ++q) chunk_eq += wave_eq[q];
+  __syncthreads();
+  const unsigned r = off + __popcll(bal & ((1ull << lane) - 1ull));
+  sel = valid && (key > thr || (eq && r < need_eq));
+}
+
+__global__ void __launch_bounds__(SEL_BLOCK) k_set_count(const float* __restrict__ v, int64_t m,
+                                                         const unsigned* __restrict__ state,
+                                                         int64_t per_block,
+                                                         const unsigned* __restrict__ eq_before,
+                                                         unsigned* __restrict__ sel_counts) {
+  __shared__ unsigned wave_eq[SEL_BLOCK / 64];
+  __shared__ unsigned c;
+  if (threadIdx.x == 0) c = 0;
+  __syncthreads();
+  const unsigned thr = state[0], need_eq = state[2];
+  const int64_t beg = blockIdx.x * per_block, end = min(m, beg + per_block);
+  unsigned eq_run = eq_before[blockIdx.x];
+  unsigned local = 0;
+  for (int64_t base = beg; base < end; base += SEL_BLOCK) {
+    bool sel;
+    unsigned chunk_eq;
+    set_flags(v, base + threadIdx.x, end, thr, need_eq, eq_run, wave_eq, sel, chunk_eq);
+    local += sel;
+    eq_run += chunk_eq;
+  }
+  if (local) atomicAdd(&c, local);
+  __syncthreads();
+  if (threadIdx.x == 0) sel_counts[blockIdx.x] = c;
+}
+
+__global__ void __launch_bounds__(SEL_BLOCK) k_set_write(const float* __restrict__ v, int64_t m,
+                                                         const unsigned* __restrict__ state,
+                                                         int64_t per_block,
+                                                         const unsigned* __restrict__ eq_before,
+                                                         const unsigned* __restrict__ sel_before,
+                                                         int64_t* __restrict__ out) {
+  __shared__ unsigned wave_eq[SEL_BLOCK / 64], wave_sel[SEL_BLOCK / 64];
+  const unsigned thr = state[0], need_eq = state[2];
+  const int64_t beg = blockIdx.x * per_block, end = min(m, beg + per_block);
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  unsigned eq_run = eq_before[blockIdx.x];
+  unsigned sel_run = sel_before[blockIdx.x];
+  for (int64_t base = beg; base < end; base += SEL_BLOCK) {
+    const int64_t i = base + threadIdx.x;
+    bool sel;
+    unsigned chunk_eq;
+    set_flags(v, i, end, thr, need_eq, eq_run, wave_eq, sel, chunk_eq);
+    const unsigned long long bal = __ballot(sel);
+    if (lane == 0) wave_sel[w] = __popcll(bal);
+    __syncthreads();
+    unsigned off = sel_run, chunk_sel = 0;
+    for (int q = 0; q < SEL_BLOCK / 64; ++q) {
+      if (q < w) off += wave_sel[q];
+      chunk_sel += wave_sel[q];
+    }
+    if (sel) out[off + __popcll(bal & ((1ull << lane) - 1ull))] = i;
+    eq_run += chunk_eq;
+    sel_run += chunk_sel;
+    __syncthreads();
+  }
+}
+
 // Bitonic sort of k pairs by (key descending, index ascending), one
 // workgroup, in LDS; writes the indices.
 __global__ void __launch_bounds__(1024) k_sel_sort(const unsigned* __restrict__ key,
@@ -214,12 +295,43 @@ size_t topk_scratch_bytes(int64_t m, int64_t k) {
   return 4096 + round_up(nb * 4, 256) + round_up(k * 4, 256) + k * 8;
 }
 
-void launch_topk_into(int64_t m, const float* v, int64_t k, int64_t* idx, void* scratch,
-                      hipStream_t s) {
-  unsigned* state = (unsigned*)scratch;
+// Scratch of the set selection: state, histogram, two per-block count arrays.
+size_t topk_set_scratch_bytes(int64_t m) {
+  const int64_t nb = std::min<int64_t>(1024, ceil_div(m, SEL_BLOCK));
+  return 4096 + 2 * round_up(nb * 4, 256);
+}
+
+void launch_topk_set_into(int64_t m, const float* v, int64_t k, int64_t* idx, void* ws,
+                          hipStream_t s) {
+  unsigned* state = (unsigned*)ws;
   unsigned* hist = state + 64;
   const int64_t nb = std::min<int64_t>(1024, ceil_div(m, SEL_BLOCK));
-  unsigned* counts = (unsigned*)((unsigned char*)scratch + 4096);
+  unsigned* eq_counts = (unsigned*)((unsigned char*)ws + 4096);
+  unsigned* sel_counts = (unsigned*)((unsigned char*)eq_counts + round_up(nb * 4, 256));
+  hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, state, hist, (unsigned)k);
+  const int g = (int)std::min<int64_t>(2048, ceil_div(m, SEL_BLOCK));
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(g), dim3(SEL_BLOCK), 0, s, v, m, state, shift, hist);
+    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(256), 0, s, hist, state, shift);
+  }
+  const int64_t per_block = round_up(ceil_div(m, nb), SEL_BLOCK);
+  const int nblocks = (int)ceil_div(m, per_block);
+  hipLaunchKernelGGL(k_eq_count, dim3(nblocks), dim3(SEL_BLOCK), 0, s, v, m, state, per_block,
+                     eq_counts);
+  hipLaunchKernelGGL(k_eq_scan, dim3(1), dim3(64), 0, s, eq_counts, nblocks);
+  hipLaunchKernelGGL(k_set_count, dim3(nblocks), dim3(SEL_BLOCK), 0, s, v, m, state, per_block,
+                     eq_counts, sel_counts);
+  hipLaunchKernelGGL(k_eq_scan, dim3(1), dim3(64), 0, s, sel_counts, nblocks);
+  hipLaunchKernelGGL(k_set_write, dim3(nblocks), dim3(SEL_BLOCK), 0, s, v, m, state, per_block,
+                     eq_counts, sel_counts, idx);
+}
+
+void launch_topk_into(int64_t m, const float* v, int64_t k, int64_t* idx, void* ws,
+                      hipStream_t s) {
+  unsigned* state = (unsigned*)ws;
+  unsigned* hist = state + 64;
+  const int64_t nb = std::min<int64_t>(1024, ceil_div(m, SEL_BLOCK));
+  unsigned* counts = (unsigned*)((unsigned char*)ws + 4096);
   unsigned* okey = (unsigned*)((unsigned char*)counts + round_up(nb * 4, 256));
   int64_t* oidx = (int64_t*)((unsigned char*)okey + round_up(k * 4, 256));
   hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, state, hist, (unsigned)k);
@@ -236,6 +348,46 @@ void launch_topk_into(int64_t m, const float* v, int64_t k, int64_t* idx, void* 
   hipLaunchKernelGGL(k_sel_write, dim3(nblocks), dim3(SEL_BLOCK), 0, s, v, m, state, per_block,
                      counts, (unsigned)k, okey, oidx);
   hipLaunchKernelGGL(k_sel_sort, dim3(1), dim3(1024), 0, s, okey, oidx, (int)k, idx);
+}
+
+__global__ void k_compose_idx(int64_t k, const int64_t* __restrict__ outer,
+                              const int64_t* __restrict__ inner, int64_t* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < k;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = outer[inner[i]];
+}
+
+void launch_compose_idx(int64_t k, const int64_t* outer, const int64_t* inner, int64_t* out,
+                        hipStream_t s) {
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(k, 256)));
+  hipLaunchKernelGGL(k_compose_idx, dim3(g), dim3(256), 0, s, k, outer, inner, out);
+}
+
+// Result of an exact re-score of a subset: the pool index of the argmax and
+// whether no unscored candidate of the subset can beat it.  bound_next: the
+// EI upper bound of the best candidate left out (NULL: none left out).
+// tol: allowance in units of s_y (stats[1], the model's scale of y).
+__global__ void k_subset_finish(const int64_t* __restrict__ am, const double* __restrict__ em,
+                                const int64_t* __restrict__ pool_idx,
+                                const float* __restrict__ bounds,
+                                const int64_t* __restrict__ next_pos, double tol,
+                                const double* __restrict__ stats, int64_t* __restrict__ next,
+                                double* __restrict__ ei_max, int* __restrict__ certified) {
+  if (threadIdx.x != 0) return;
+  const int64_t a = *am;
+  next[0] = a >= 0 ? pool_idx[a] : -1;
+  ei_max[0] = *em;
+  int cert = a >= 0;
+  if (next_pos) cert = cert && *em >= (double)bounds[*next_pos] + tol * stats[S_YSTD];
+  certified[0] = cert;
+}
+
+void launch_subset_finish(const int64_t* am, const double* em, const int64_t* pool_idx,
+                          const float* bounds, const int64_t* next_pos, double tol,
+                          const double* stats, int64_t* next, double* ei_max, int* certified,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_subset_finish, dim3(1), dim3(64), 0, s, am, em, pool_idx, bounds, next_pos,
+                     tol, stats, next, ei_max, certified);
 }
 
 void launch_gather_rows(int64_t k, const int64_t* idx, int d, const float* Xc, float* out,

@@ -83,6 +83,11 @@ _SIGS = {
                                      C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]),
     "gpbo_topk": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
+    "gpbo_topk_set": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
+    "gpbo_score_subset": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                    C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gpbo_score_bound": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p]),
     "gpbo_gather_rows": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
                                    C.c_void_p]),
     "gpbo_mlp_create": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
@@ -392,6 +397,36 @@ def topk(ctx: Context, v, k):
     idx = torch.empty(k, dtype=torch.int64, device=ctx.device)
     ctx.check(lib().gpbo_topk(ctx.h, v.shape[0], _ptr(v), int(k), _ptr(idx)))
     return idx
+
+
+def topk_set(ctx: Context, v, k):
+    """gpbo_topk_set: the top-k entries of a float32 device vector as a set,
+    in ascending index order (any k <= len(v))."""
+    assert v.dtype == torch.float32 and v.is_contiguous()
+    idx = torch.empty(k, dtype=torch.int64, device=ctx.device)
+    ctx.check(lib().gpbo_topk_set(ctx.h, v.shape[0], _ptr(v), int(k), _ptr(idx)))
+    return idx
+
+
+def score_bound(ctx: Context, model: Model, Xc, want=("mu", "sigma_ub", "ei_ub")):
+    """gpbo_score_bound: posterior mean and the nearest-observation upper
+    bounds of sigma and EI (float32 device tensors)."""
+    assert Xc.dtype == torch.float32 and Xc.is_contiguous() and Xc.shape[1] == model.d
+    m = Xc.shape[0]
+    out = {k: torch.empty(m, dtype=torch.float32, device=ctx.device) for k in want}
+    ctx.check(lib().gpbo_score_bound(ctx.h, model.h, m, _ptr(Xc), _ptr(out.get("mu")),
+                                     _ptr(out.get("sigma_ub")), _ptr(out.get("ei_ub"))))
+    return out
+
+
+def score_subset(ctx: Context, model: Model, Xc, idx, k2):
+    """gpbo_score_subset with host outputs (synchronises): (pool index of the
+    best candidate of the subset, its EI, certified)."""
+    assert Xc.dtype == torch.float32 and Xc.is_contiguous() and idx.dtype == torch.int64
+    nxt, em, cert = C.c_int64(-2), C.c_double(0.0), C.c_int32(-1)
+    ctx.check(lib().gpbo_score_subset(ctx.h, model.h, Xc.shape[0], _ptr(Xc), idx.shape[0], _ptr(idx),
+                                      int(k2), C.byref(nxt), C.byref(em), C.byref(cert)))
+    return nxt.value, em.value, bool(cert.value)
 
 
 def gather_rows(ctx: Context, idx, Xc):

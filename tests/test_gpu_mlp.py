@@ -177,10 +177,16 @@ def test_prescreen_ei_matches_oracle_and_sort(ctx):
                      (float(outs.mean(0).min()) - 0.5, 4096)):
         idx, ei = net.prescreen(Xd, fbest, k, want_ei=True)
         ei = ei.double().cpu().numpy()
-        _, _, ref = O.ens_ei(outs, fbest)
+        mu_e, sd_e, ref = O.ens_ei(outs, fbest)
         err = np.max(np.abs(ei - ref)) / np.max(ref)
-        print(f"  prescreen EI f_best={fbest:.3f}: max |dEI| / EI_max = {err:.2e}")
-        assert err <= 1e-5, fbest
+        # deep in the tail (z << 0) the two terms of EI cancel: float32
+        # evaluation loses about z^2 units of 2^-24 there
+        j = int(np.argmax(ref))
+        z = (fbest - mu_e[j]) / sd_e[j]
+        bound = 1e-5 + 16 * (z * z + 1) * 2.0 ** -24
+        print(f"  prescreen EI f_best={fbest:.3f}: max |dEI| / EI_max = {err:.2e} (z* {z:.1f}, "
+              f"bound {bound:.1e})")
+        assert err <= bound, fbest
         want = np.lexsort((np.arange(ei.size), -ei))[:k]
         assert np.array_equal(idx.cpu().numpy(), want), fbest
     net.free()
