@@ -320,6 +320,22 @@ gpbo_status gpbo_topk(gpbo_ctx ctx, int64_t m, const float* v, int64_t k, int64_
  * ascending index order.  Asynchronous. */
 gpbo_status gpbo_topk_set(gpbo_ctx ctx, int64_t m, const float* v, int64_t k, int64_t* idx);
 
+/* gpbo_topk that allocates nothing, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, results and errors as gpbo_topk; its
+ * scratch (radix state, histogram, per-block counts, the k selected keys and
+ * indices) is a static device array of GPBO_TOPK_NOALLOC_SCRATCH bytes per
+ * GPU, held by the library until the process ends, whose address is resolved
+ * when the first context on that GPU is created.  Every call on a GPU shares
+ * that GPU's array (the launch sequence re-initialises it, so the contents a
+ * previous call left do not matter): calls that can overlap on one GPU --
+ * other streams, other contexts, other threads -- race, and the caller must
+ * serialise them.  Returns GPBO_E_UNSUPPORTED when the scratch the sizes
+ * need exceeds the array (it holds every k <= 8192 at any m < 2^32).
+ * Asynchronous. */
+#define GPBO_TOPK_NOALLOC_SCRATCH (128 * 1024)
+gpbo_status gpbo_topk_noalloc(gpbo_ctx ctx, int64_t m, const float* v, int64_t k, int64_t* idx);
+
 /* out[i, :] = Xc[idx[i], :] for i < k (device float arrays, row-major, d
  * columns).  Asynchronous. */
 gpbo_status gpbo_gather_rows(gpbo_ctx ctx, int64_t k, const int64_t* idx, int32_t d,

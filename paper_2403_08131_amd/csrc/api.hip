@@ -429,6 +429,14 @@ gpbo_status gpbo_ctx_create(int32_t device, void* stream, const gpbo_allocator* 
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(nullptr, GPBO_E_UNSUPPORTED, "device %d is %s; this build targets gfx950", device,
                 prop.gcnArchName);
+  {
+    // the allocation-free top-k's static scratch on this device: its device
+    // address, resolved once per device with the device current
+    DeviceGuard g(device);
+    if (!topk_noalloc_init(device))
+      return fail(nullptr, GPBO_E_HIP, "device %d: address of the static top-k scratch unavailable",
+                  device);
+  }
   gpbo_ctx c = new (std::nothrow) gpbo_ctx_s();
   if (!c) return fail(nullptr, GPBO_E_OOM, "host allocation failed");
   c->device = device;
@@ -1265,6 +1273,26 @@ gpbo_status gpbo_score_subset(gpbo_ctx c, gpbo_model M, int64_t m, const float* 
                     (certified && !device_writable(certified));
   dfree(c, b);  // stream-ordered with the torch allocator; hipFree waits otherwise
   if (host) HIP_TRY(c, hipStreamSynchronize(s));
+  return GPBO_OK;
+}
+
+gpbo_status gpbo_topk_noalloc(gpbo_ctx c, int64_t m, const float* v, int64_t k, int64_t* idx) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (m < 0 || k < 0 || (m > 0 && !v) || (k > 0 && !idx))
+    return fail(c, GPBO_E_INVALID_ARG, "invalid top-k arguments");
+  if (k > m) return fail(c, GPBO_E_INVALID_ARG, "k (%lld) exceeds m (%lld)", (long long)k, (long long)m);
+  if (k > topk_max_k()) return fail(c, GPBO_E_UNSUPPORTED, "k > %d is not supported", topk_max_k());
+  if (m > 0xffffffffLL) return fail(c, GPBO_E_UNSUPPORTED, "m >= 2^32 is not supported");
+  const size_t need = topk_scratch_bytes(m, k);
+  if (need > topk_noalloc_bytes())
+    return fail(c, GPBO_E_UNSUPPORTED, "top-k needs %zu bytes of scratch; the static array holds %zu",
+                need, topk_noalloc_bytes());
+  if (k == 0) return GPBO_OK;
+  DeviceGuard g(c->device);
+  void* ws = topk_noalloc_scratch(c->device);
+  if (!ws) return fail(c, GPBO_E_HIP, "static top-k scratch not resolved on device %d", c->device);
+  launch_topk_into(m, v, k, idx, ws, c->stream);
+  HIP_TRY(c, hipGetLastError());
   return GPBO_OK;
 }
 

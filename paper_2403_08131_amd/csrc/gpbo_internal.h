@@ -329,6 +329,12 @@ void launch_subset_finish(const int64_t* am, const double* em, const int64_t* po
                           const float* bounds, const int64_t* next_pos, double tol,
                           const double* stats, int64_t* next, double* ei_max, int* certified,
                           hipStream_t s);
+// Allocation-free top-k: the device address of the static scratch array on
+// `device` (resolved by topk_noalloc_init with that device current, once per
+// device; NULL before), and its size in bytes.
+bool topk_noalloc_init(int device);
+void* topk_noalloc_scratch(int device);
+size_t topk_noalloc_bytes();
 void launch_gather_rows(int64_t k, const int64_t* idx, int d, const float* Xc, float* out,
                         hipStream_t s);
 

@@ -10,10 +10,20 @@
 //   3. one workgroup sorts the k (key, index) pairs in LDS (bitonic).
 // NaN scores map to the lowest key and never rank ahead of a number.
 #include <climits>
+#include <mutex>
 
 #include "gpbo_internal.h"
 
 namespace gpbo {
+
+// Scratch of the allocation-free top-k (gpbo_topk_noalloc): a static device
+// array, one copy per GPU, held until the process ends.  Host code never
+// passes `scratch` itself to a kernel (on the host the name is a stand-in,
+// not a device address): the address comes from hipGetSymbolAddress, once
+// per device, with that device current (topk_noalloc_init).
+constexpr size_t kTopkNoallocBytes = 128 * 1024;
+static __device__ __align__(256) unsigned char scratch[kTopkNoallocBytes];
+static_assert(kTopkNoallocBytes == GPBO_TOPK_NOALLOC_SCRATCH, "size stated in the header");
 
 namespace {
 
@@ -389,6 +399,39 @@ void launch_subset_finish(const int64_t* am, const double* em, const int64_t* po
   hipLaunchKernelGGL(k_subset_finish, dim3(1), dim3(64), 0, s, am, em, pool_idx, bounds, next_pos,
                      tol, stats, next, ei_max, certified);
 }
+
+namespace {
+std::mutex g_noalloc_mu;
+constexpr int kMaxDevices = 64;
+void* g_noalloc_ptr[kMaxDevices] = {};
+}  // namespace
+
+bool topk_noalloc_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return false;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return true;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != device) {
+    (void)hipGetLastError();
+    return false;  // the caller makes `device` current first
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return false;
+  }
+  g_noalloc_ptr[device] = p;
+  return true;
+}
+
+void* topk_noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  return g_noalloc_ptr[device];
+}
+
+size_t topk_noalloc_bytes() { return kTopkNoallocBytes; }
 
 void launch_gather_rows(int64_t k, const int64_t* idx, int d, const float* Xc, float* out,
                         hipStream_t s) {

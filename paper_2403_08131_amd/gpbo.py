@@ -83,6 +83,7 @@ _SIGS = {
                                      C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]),
     "gpbo_topk": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
+    "gpbo_topk_noalloc": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     "gpbo_topk_set": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     "gpbo_score_subset": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                                     C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -427,6 +428,16 @@ def score_subset(ctx: Context, model: Model, Xc, idx, k2):
     ctx.check(lib().gpbo_score_subset(ctx.h, model.h, Xc.shape[0], _ptr(Xc), idx.shape[0], _ptr(idx),
                                       int(k2), C.byref(nxt), C.byref(em), C.byref(cert)))
     return nxt.value, em.value, bool(cert.value)
+
+
+def topk_noalloc(ctx: Context, v, k, idx=None):
+    """gpbo_topk_noalloc: gpbo_topk with the library's static scratch; the
+    output buffer may be passed in (idx, device int64 of k entries)."""
+    assert v.dtype == torch.float32 and v.is_contiguous()
+    if idx is None:
+        idx = torch.empty(k, dtype=torch.int64, device=ctx.device)
+    ctx.check(lib().gpbo_topk_noalloc(ctx.h, v.shape[0], _ptr(v), int(k), _ptr(idx)))
+    return idx
 
 
 def gather_rows(ctx: Context, idx, Xc):
