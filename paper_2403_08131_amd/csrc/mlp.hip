@@ -329,6 +329,8 @@ struct Gemm {
   int kchunk;       // K per split
   float* out;
   const float* pre1;
+  unsigned short* dpre1T;  // DPRE1: bf16(dpre1), feature-major [member][N][M]
+  float* b1part;           // DPRE1: per 32-row block column sums of dpre1 [member][M/32][N]
 };
 template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm_nt(Gemm g) {
@@ -361,73 +363,58 @@ __global__ void __launch_bounds__(256) k_gemm_nt(Gemm g) {
                                                             __builtin_bit_cast(bf8, bv[b]),
                                                             acc[a][b], 0, 0, 0);
   }
+  if (EPI == EPI_STORE) {
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + a * 16 + 4 * (lane / 16) + r;
+          const int col = c0 + b * 16 + lane % 16;
+          const int64_t o = ((int64_t)e * g.M + row) * g.N + col;
+          g.out[(int64_t)split * gridDim.z * g.M * g.N + o] = acc[a][b][r];
+        }
+    return;
+  }
+  // dpre1 = dh1 GELU'(pre1): rows are samples, columns hidden units.  The
+  // bfloat16 value feeds the layer-1 weight gradient (an NT product over
+  // samples, so it is stored feature-major: each lane's four consecutive
+  // samples are one 8-byte store); the unrounded value feeds the bias
+  // gradient as column sums over this wave's 32 samples.
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int col = c0 + b * 16 + lane % 16;
+    float csum = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int row0 = r0 + a * 16 + 4 * (lane / 16);
+      unsigned short q[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = r0 + a * 16 + 4 * (lane / 16) + r;
-        const int col = c0 + b * 16 + lane % 16;
-        const int64_t o = ((int64_t)e * g.M + row) * g.N + col;
-        if (EPI == EPI_STORE)
-          g.out[(int64_t)split * gridDim.z * g.M * g.N + o] = acc[a][b][r];
-        else
-          g.out[o] = acc[a][b][r] * gelu_grad(g.pre1[o]);
+        const int64_t o = ((int64_t)e * g.M + row0 + r) * g.N + col;
+        const float v = acc[a][b][r] * gelu_grad(g.pre1[o]);
+        csum += v;
+        q[r] = f2bf(v);
       }
+      const uint2 pk = make_uint2((unsigned)q[0] | ((unsigned)q[1] << 16),
+                                  (unsigned)q[2] | ((unsigned)q[3] << 16));
+      *(uint2*)(g.dpre1T + ((int64_t)e * g.N + col) * g.M + row0) = pk;
+    }
+    csum += __shfl_xor(csum, 16);
+    csum += __shfl_xor(csum, 32);
+    if (lane < 16) g.b1part[((int64_t)e * (g.M / 32) + r0 / 32) * g.N + col] = csum;
+  }
 }
 
-// Layer-1 gradients: gW1[h][d] = sum_i bf16(dpre1[i][h]) bf16(x[i][d]),
-// gb1[h] = sum_i dpre1[i][h]; workgroup (feature block of 64, member, sample
-// split); partial sums per split.  DP: D rounded up to a power of two, so
-// the accumulators stay in registers.
-template <int DP>
-__global__ void __launch_bounds__(256) k_mlp_bwd_l1(MlpDev M, int64_t n, const float* __restrict__ X,
-                                                    const float* __restrict__ dpre1,
-                                                    int64_t ichunk, float* __restrict__ part) {
-  __shared__ float red[4][64][17];
-  const int H = M.H, D = M.D;
-  const int e = blockIdx.y, split = blockIdx.z;
-  const int h = blockIdx.x * 64 + threadIdx.x % 64, grp = threadIdx.x / 64;
-  const int64_t ib = split * ichunk, ie = min(n, ib + ichunk);
-  // per thread: D weight sums + the bias sum, accumulated over its samples
-  float acc[DP + 1];
-#pragma unroll
-  for (int k = 0; k <= DP; ++k) acc[k] = 0.0f;
-  if (h < H) {
-    for (int64_t i = ib + grp; i < ie; i += 4) {
-      const float dp = dpre1[((int64_t)e * n + i) * H + h];
-      const float dr = bfr(dp);
-      const float* xi = X + i * D;
-#pragma unroll
-      for (int k = 0; k < DP; ++k)
-        if (k < D) acc[k] = fmaf(dr, bfr(xi[k]), acc[k]);
-      acc[DP] += dp;
-    }
-  }
-  const int nd = D + 1;
-  // combine the four sample groups, 16 values at a time
-#pragma unroll
-  for (int k0 = 0; k0 < DP + 1; k0 += 16) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      // column k of the output: weight sums for k < D, the bias sum at k = D
-      const int k = k0 + q;
-      float v = 0.0f;
-      if (k < D) v = acc[k < DP ? k : 0];
-      else if (k == D) v = acc[DP];
-      red[grp][threadIdx.x % 64][q] = v;
-    }
-    __syncthreads();
-    if (grp == 0 && h < H) {
-      for (int q = 0; q < 16 && k0 + q < nd; ++q) {
-        const float v = red[0][threadIdx.x][q] + red[1][threadIdx.x][q] + red[2][threadIdx.x][q] +
-                        red[3][threadIdx.x][q];
-        // layout per split: [member][H][D + 1]
-        part[(((int64_t)split * M.E + e) * H + h) * nd + k0 + q] = v;
-      }
-    }
-    __syncthreads();
+// Layer-1 inputs for the weight-gradient product: bf16(x) feature-major,
+// xT[k][i] for k < D, zero rows up to DX (the product's 64-column tile).
+__global__ void __launch_bounds__(256) k_mlp_xt(const float* __restrict__ X, int64_t n, int D,
+                                                int DX, unsigned short* __restrict__ xT) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)DX * n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = e / n, i = e % n;
+    xT[e] = k < D ? f2bf(X[i * D + k]) : (unsigned short)0;
   }
 }
 
@@ -436,8 +423,10 @@ __global__ void __launch_bounds__(256) k_mlp_bwd_l1(MlpDev M, int64_t n, const f
 struct AdamIn {
   const float* gW2part;   // S2 x E x H x H
   int S2;
-  const float* l1part;    // S1 x E x H x (D + 1)
-  int S1;
+  const float* l1part;    // S1 x E x H x DX (weight sums, columns < D used)
+  int S1, DX;
+  const float* b1part;    // E x (n / 32) x H (bias sums of dpre1)
+  int nb1;
   const float* colpart;   // E x nblk x (2H + 2)
   int nblk;
   double lr;
@@ -457,10 +446,10 @@ __global__ void __launch_bounds__(256) k_mlp_adam(MlpDev M, AdamIn in) {
     float g = 0.0f;
     if (q < off_b1(M)) {  // W1[h][d]
       const int h = (int)(q / D), d = (int)(q % D);
-      for (int s = 0; s < in.S1; ++s) g += in.l1part[(((int64_t)s * M.E + e) * H + h) * (D + 1) + d];
+      for (int s = 0; s < in.S1; ++s) g += in.l1part[(((int64_t)s * M.E + e) * H + h) * in.DX + d];
     } else if (q < off_W2(M)) {  // b1
       const int h = (int)(q - off_b1(M));
-      for (int s = 0; s < in.S1; ++s) g += in.l1part[(((int64_t)s * M.E + e) * H + h) * (D + 1) + D];
+      for (int b = 0; b < in.nb1; ++b) g += in.b1part[((int64_t)e * in.nb1 + b) * H + h];
     } else if (q < off_b2(M)) {  // W2
       const int64_t w = q - off_W2(M);
       for (int s = 0; s < in.S2; ++s) g += in.gW2part[((int64_t)s * M.E + e) * H * H + w];
@@ -612,10 +601,9 @@ int64_t mlp_nparams(MlpState* st) { return st->dev.P; }
 
 // Workspace layout for n training samples.
 struct Ws {
-  float *out, *pre1, *pre2, *dpre1, *colpart, *gW2part, *l1part;
-  unsigned short *h1, *h1T, *dpre2, *dpre2T;
-  int nblk, S2, S1;
-  int64_t ichunk;
+  float *out, *pre1, *pre2, *b1part, *colpart, *gW2part, *l1part;
+  unsigned short *h1, *h1T, *dpre2, *dpre2T, *dpre1T, *xT;
+  int nblk, S2, S1, DX;
 };
 static Ws carve(MlpState* st, int64_t n, size_t* total) {
   const MlpDev& M = st->dev;
@@ -623,8 +611,8 @@ static Ws carve(MlpState* st, int64_t n, size_t* total) {
   Ws w{};
   w.nblk = (int)ceil_div(n, MT);
   w.S2 = (int)std::min<int64_t>(8, ceil_div(n, 512));
-  w.S1 = (int)std::min<int64_t>(16, ceil_div(n, 256));
-  w.ichunk = ceil_div(n, w.S1);
+  w.S1 = (int)std::min<int64_t>(8, ceil_div(n, 512));
+  w.DX = 64;  // the weight-gradient product's column tile (D <= 64)
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -632,17 +620,19 @@ static Ws carve(MlpState* st, int64_t n, size_t* total) {
     return o;
   };
   const size_t o_out = take(E * n * 4), o_pre1 = take(E * n * H * 4), o_pre2 = take(E * n * H * 4),
-               o_dpre1 = take(E * n * H * 4), o_col = take(E * w.nblk * (2 * H + 2) * 4),
-               o_gw2 = take((size_t)w.S2 * E * H * H * 4), o_l1 = take((size_t)w.S1 * E * H * (D + 1) * 4),
+               o_b1 = take(E * (n / 32) * H * 4), o_col = take(E * w.nblk * (2 * H + 2) * 4),
+               o_gw2 = take((size_t)w.S2 * E * H * H * 4), o_l1 = take((size_t)w.S1 * E * H * w.DX * 4),
                o_h1 = take(E * n * H * 2), o_h1T = take(E * n * H * 2), o_dp2 = take(E * n * H * 2),
-               o_dp2T = take(E * n * H * 2);
+               o_dp2T = take(E * n * H * 2), o_dp1T = take(E * n * H * 2),
+               o_xT = take((size_t)w.DX * n * 2);
+  (void)D;
   *total = off;
   unsigned char* b = (unsigned char*)st->ws;
   if (b) {
     w.out = (float*)(b + o_out);
     w.pre1 = (float*)(b + o_pre1);
     w.pre2 = (float*)(b + o_pre2);
-    w.dpre1 = (float*)(b + o_dpre1);
+    w.b1part = (float*)(b + o_b1);
     w.colpart = (float*)(b + o_col);
     w.gW2part = (float*)(b + o_gw2);
     w.l1part = (float*)(b + o_l1);
@@ -650,6 +640,8 @@ static Ws carve(MlpState* st, int64_t n, size_t* total) {
     w.h1T = (unsigned short*)(b + o_h1T);
     w.dpre2 = (unsigned short*)(b + o_dp2);
     w.dpre2T = (unsigned short*)(b + o_dp2T);
+    w.dpre1T = (unsigned short*)(b + o_dp1T);
+    w.xT = (unsigned short*)(b + o_xT);
   }
   return w;
 }
@@ -706,25 +698,42 @@ void mlp_step(MlpState* st, int64_t n, const float* X, const float* y, double lr
   g2.N = H;
   g2.K = H;
   g2.kchunk = H;
-  g2.out = w.dpre1;
+  g2.out = nullptr;
   g2.pre1 = w.pre1;
+  g2.dpre1T = w.dpre1T;
+  g2.b1part = w.b1part;
   hipLaunchKernelGGL(k_gemm_nt<EPI_DPRE1>, dim3((unsigned)(n / 64) * (H / 64), 1, E), dim3(256), 0,
                      s, g2);
-  const dim3 g_l1((unsigned)ceil_div(H, 64), E, w.S1);
-  if (M.D <= 8)
-    hipLaunchKernelGGL(k_mlp_bwd_l1<8>, g_l1, dim3(256), 0, s, M, n, X, w.dpre1, w.ichunk, w.l1part);
-  else if (M.D <= 16)
-    hipLaunchKernelGGL(k_mlp_bwd_l1<16>, g_l1, dim3(256), 0, s, M, n, X, w.dpre1, w.ichunk, w.l1part);
-  else if (M.D <= 32)
-    hipLaunchKernelGGL(k_mlp_bwd_l1<32>, g_l1, dim3(256), 0, s, M, n, X, w.dpre1, w.ichunk, w.l1part);
-  else
-    hipLaunchKernelGGL(k_mlp_bwd_l1<64>, g_l1, dim3(256), 0, s, M, n, X, w.dpre1, w.ichunk, w.l1part);
-  AdamIn ai{w.gW2part, w.S2, w.l1part, w.S1, w.colpart, w.nblk, lr, grad_out, loss_hist, n, apply};
+  // gW1 = dpre1^T x over the samples (bf16 operands, split over S1 chunks);
+  // x^T is shared by the members
+  Gemm g3{};
+  g3.A = w.dpre1T;
+  g3.B = w.xT;
+  g3.sA = (int64_t)H * n;
+  g3.sB = 0;
+  g3.M = H;
+  g3.N = w.DX;
+  g3.K = (int)n;
+  g3.kchunk = (int)round_up(ceil_div(n, w.S1), 32);
+  g3.out = w.l1part;
+  hipLaunchKernelGGL(k_gemm_nt<EPI_STORE>, dim3((H / 64) * (w.DX / 64), w.S1, E), dim3(256), 0, s, g3);
+  AdamIn ai{w.gW2part, w.S2, w.l1part, w.S1, w.DX, w.b1part, (int)(n / 32), w.colpart, w.nblk,
+            lr, grad_out, loss_hist, n, apply};
   hipLaunchKernelGGL(k_mlp_adam, dim3(64, E), dim3(256), 0, s, M, ai);
   if (apply) {
     hipLaunchKernelGGL(k_mlp_step, dim3(1), dim3(1), 0, s, M);
     hipLaunchKernelGGL(k_mlp_cast, dim3(64, E), dim3(256), 0, s, M);
   }
+}
+
+// bf16(x) feature-major for the layer-1 weight gradient: the training data
+// are fixed over the steps of a call, so this runs once per call, ahead of
+// the (captured) steps.
+static void mlp_prepare_x(MlpState* st, int64_t n, const float* X, hipStream_t s) {
+  size_t bytes;
+  Ws w = carve(st, n, &bytes);
+  const unsigned g = (unsigned)std::min<int64_t>(1024, ceil_div((int64_t)w.DX * n, 256));
+  hipLaunchKernelGGL(k_mlp_xt, dim3(g), dim3(256), 0, s, X, n, st->dev.D, w.DX, w.xT);
 }
 
 // Training: the step sequence is captured once per (n, inputs, lr, history)
@@ -733,6 +742,7 @@ bool mlp_train(MlpState* st, int64_t n, const float* X, const float* y, int step
                float* loss_hist, bool use_graph, hipStream_t s) {
   if (steps <= 0) return true;
   if (!mlp_ensure_ws(st, n)) return false;
+  mlp_prepare_x(st, n, X, s);
   hipLaunchKernelGGL(k_mlp_mark, dim3(1), dim3(1), 0, s, st->dev);
   std::vector<uint64_t> key = {(uint64_t)n, (uint64_t)(uintptr_t)X, (uint64_t)(uintptr_t)y,
                                (uint64_t)(uintptr_t)loss_hist, (uint64_t)(uintptr_t)s};
@@ -801,6 +811,7 @@ bool mlp_train_model(MlpState* st, const Model* M, int steps, double lr, float* 
 bool mlp_grads(MlpState* st, int64_t n, const float* X, const float* y, float* grad, float* loss,
                hipStream_t s) {
   if (!mlp_ensure_ws(st, n)) return false;
+  mlp_prepare_x(st, n, X, s);
   // loss through a one-entry history at the current step: record it into a
   // scratch row, then copy out
   mlp_step(st, n, X, y, 0.0, 0, grad, nullptr, s);
