@@ -79,3 +79,44 @@ def test_pins_catch_planted_mistakes():
     assert codes.pop("clean") == 0
     survivors = [k for k, c in codes.items() if c == 0]
     assert not survivors, f"pins did not catch: {survivors}"
+
+
+PLAN_MUTATIONS = {
+    "sens_no_abs": ("acc += abs((base[r] - out[j, i, r]) / base[r])",
+                    "acc += (base[r] - out[j, i, r]) / base[r]"),
+    "sens_no_mean": ("S[r, j] = acc / V", "S[r, j] = acc"),
+    "influence_min": ("top = max(own) if own else 0.0", "top = min(own) if own else 0.0"),
+    "cut_below": ("if r != o and I[r, j] >= cutoff:", "if r != o and I[r, j] <= cutoff:"),
+    "cap_smallest": ("key=lambda j: (-score[j], j)", "key=lambda j: (score[j], j)"),
+    "merge_one_way": ("                adj[r].add(o)\n", ""),
+}
+
+
+@pytest.mark.slow
+def test_plan_pins_catch_planted_mistakes():
+    """The same check for the planning oracle (oracle/plan.py): each planted
+    mistake must fail a pin of tests/test_oracle_plan.py."""
+    src = os.path.join(ROOT, "oracle", "plan.py")
+    with open(src) as f:
+        text = f.read()
+    pins = os.path.join(ROOT, "tests", "test_oracle_plan.py")
+    survivors = []
+    with tempfile.TemporaryDirectory() as tmp:
+        for name, (old, new) in list(PLAN_MUTATIONS.items()) + [("clean", ("", ""))]:
+            pkg = os.path.join(tmp, name, "oracle")
+            os.makedirs(pkg)
+            open(os.path.join(pkg, "__init__.py"), "w").close()
+            if name != "clean":
+                assert text.count(old) >= 1, name
+            with open(os.path.join(pkg, "plan.py"), "w") as f:
+                f.write(text.replace(old, new, 1) if name != "clean" else text)
+            env = dict(os.environ, PYTHONPATH=os.path.join(tmp, name) + os.pathsep + ROOT)
+            r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                                "--rootdir", os.path.join(tmp, name), pins],
+                               cwd=os.path.join(tmp, name), env=env, capture_output=True, text=True,
+                               timeout=600)
+            if name == "clean":
+                assert r.returncode == 0, r.stdout[-2000:]
+            elif r.returncode == 0:
+                survivors.append(name)
+    assert not survivors, f"plan pins did not catch: {survivors}"
