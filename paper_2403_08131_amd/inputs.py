@@ -254,6 +254,98 @@ def mlp_init(rng, members=5, d_in=20, hidden=256):
     }
 
 
+# --------------------------------------------------------------------------
+# The paper's own 20-dimensional synthetic family (Sec. III-C, Fig. 1,
+# Table I): four groups ("routines") of five parameters each on [-50, 50],
+# Group 3 defined per case, the objective the sum of log |group output|.
+# --------------------------------------------------------------------------
+
+PAPER_BOUNDS = (-50.0, 50.0)
+PAPER_GROUPS = [list(range(0, 5)), list(range(5, 10)), list(range(10, 15)), list(range(15, 20))]
+
+
+def paper_groups(X, case, noise_std=0.0, rng=None):
+    """Outputs of the four groups of the paper's synthetic function for the
+    rows of X (..., 20), in the paper's notation:
+      G1 = sum_{i=0}^{3} (x_i - x_{i+1})^2 + sum_{i=0}^{4} A_i
+      G2 = sum_{k=5}^{8} (x_k - x_{k+1})^4 + sum_{k=5}^{9} A_k
+      G3 = the Table I formula of the case (u = 10..14, v = 15..19; Cases 4
+           and 5 pair v = u + 5)
+      G4 = sum_{v=15}^{19} 1 / x_v
+    with A_i = 10 cos(2 pi (x_i - 1)) + eps; eps ~ N(0, noise_std^2) on every
+    A_i and once on each of G3 and G4.  Returns an array (..., 4)."""
+    X = np.asarray(X, dtype=np.float64)
+    shape = X.shape[:-1]
+
+    def eps(k=1):
+        if noise_std == 0.0:
+            return 0.0
+        return rng.normal(0.0, noise_std, size=shape + ((k,) if k > 1 else ()))
+
+    def A(idx):
+        a = 10.0 * np.cos(2.0 * math.pi * (X[..., idx] - 1.0))
+        e = eps(len(idx))
+        return np.sum(a + e, axis=-1)
+
+    g1 = np.sum((X[..., 0:4] - X[..., 1:5]) ** 2, axis=-1) + A(list(range(0, 5)))
+    g2 = np.sum((X[..., 5:9] - X[..., 6:10]) ** 4, axis=-1) + A(list(range(5, 10)))
+    u = X[..., 10:15]
+    v = X[..., 15:20]
+    if case == 1:
+        g3 = np.sum(u, axis=-1) + np.sum(np.cos(2.0 * math.pi * v), axis=-1)
+    elif case == 2:
+        g3 = np.sum(u * u, axis=-1) + np.sum(v, axis=-1)
+    elif case == 3:
+        g3 = np.sum(u * u, axis=-1) + np.sum(v * v, axis=-1)
+    elif case == 4:
+        g3 = np.sum((u * v ** 4) ** 2, axis=-1)
+    elif case == 5:
+        g3 = np.sum((u * v ** 8) ** 2, axis=-1)
+    else:
+        raise ValueError(f"case must be 1..5, got {case}")
+    g3 = g3 + eps()
+    g4 = np.sum(1.0 / v, axis=-1) + eps()
+    return np.stack([g1, g2, g3, g4], axis=-1)
+
+
+def paper_objective(X, case, noise_std=0.0, rng=None):
+    """F = sum over the four groups of log |G_g| (the paper applies the log to
+    the absolute value of each group's result)."""
+    return np.sum(np.log(np.abs(paper_groups(X, case, noise_std, rng))), axis=-1)
+
+
+def sensitivity_sweep(x0, V=100, step=1.1, bounds=PAPER_BOUNDS):
+    """The configurations of the paper's one-at-a-time sensitivity sweep
+    (Sec. IV-B): from the baseline x0 (d,), V variations per parameter, each
+    multiplying the parameter by `step` relative to the preceding variation,
+    clamped to the domain.  Returns (d, V, d): sweep[j, i] is x0 with
+    parameter j at its (i+1)-th variation."""
+    x0 = np.asarray(x0, dtype=np.float64)
+    d = x0.shape[0]
+    out = np.repeat(np.repeat(x0[None, None, :], V, axis=1), d, axis=0)
+    for j in range(d):
+        vals = x0[j] * step ** np.arange(1, V + 1)
+        out[j, :, j] = np.clip(vals, bounds[0], bounds[1])
+    return out
+
+
+def make_paper_case(case, replicate=0, n=200, m=65536):
+    """Observations and a candidate pool on the paper's family for one case:
+    a baseline configuration for the sensitivity analysis, n uniform
+    observations of F and m uniform candidates on [-50, 50]^20."""
+    r_base, r_x, r_noise, r_c, _, _ = _streams(6, replicate * 8 + case)
+    lo, hi = PAPER_BOUNDS
+    x0 = f32r(r_base.uniform(lo, hi, size=20))
+    X = f32r(r_x.uniform(lo, hi, size=(n, 20)))
+    y = paper_objective(X, case, NOISE_STD, r_noise)
+    Xc = f32r(r_c.uniform(lo, hi, size=(m, 20)))
+    p = Problem(f"paper-case{case}", 20, X, y, Xc, np.full(20, 25.0), 1.0, NOISE_VAR, KERNEL_SE,
+                None)
+    p.extra["x0"] = x0
+    p.extra["case"] = case
+    return p
+
+
 def make_config(name, replicate=0, **kw):
     if name == "c1":
         return make_c1(replicate, **kw)
