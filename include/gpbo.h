@@ -342,6 +342,34 @@ gpbo_status gpbo_gather_rows(gpbo_ctx ctx, int64_t k, const int64_t* idx, int32_
                              const float* Xc, float* out);
 
 /* ---------------------------------------------------------------------- */
+/* Interdependence analysis: the set of searches (Sec. IV-B to IV-D).      */
+/* Host computations on host arrays; no device work, no context.          */
+/* ---------------------------------------------------------------------- */
+/* Sensitivity of R routines to P parameters from a one-at-a-time sweep
+ * (Sec. IV-B): from a baseline configuration, V variations of each parameter
+ * alone; S[r * P + j] = (1/V) sum_i |(base[r] - out[(j * V + i) * R + r]) /
+ * base[r]|, the mean relative change of routine r's output (its runtime, or
+ * any objective) when parameter j varies.  base: host, R outputs at the
+ * baseline; out: host, P x V x R outputs at the variations; S: host, R x P.
+ * GPBO_E_INVALID_ARG for a zero or non-finite baseline output. */
+gpbo_status gpbo_sensitivity(int32_t P, int32_t R, int32_t V, const double* base,
+                             const double* out, double* S);
+/* The set of searches from the sensitivities (Sec. IV-C, IV-D).  owner[j]
+ * (host, P) is the routine parameter j belongs to.  The influence of j on
+ * routine r is S[r][j] relative to r's most sensitive own parameter; an
+ * influence of at least `cutoff` (e.g. 0.25) on another routine links the two
+ * routines, and linked routines are tuned in one merged search.  A search of
+ * more than max_dims parameters (the paper uses 10) keeps the most
+ * influential ones (largest influence on any routine of the search, lower
+ * index among ties); the others are fixed at their defaults.  Outputs
+ * (host): routine_search (R) the search of each routine, numbered in order
+ * of each search's lowest routine; param_search (P) the search of each
+ * parameter or -1 when the cap dropped it; *n_searches. */
+gpbo_status gpbo_plan_searches(int32_t P, int32_t R, const double* S, const int32_t* owner,
+                               double cutoff, int32_t max_dims, int32_t* routine_search,
+                               int32_t* param_search, int32_t* n_searches);
+
+/* ---------------------------------------------------------------------- */
 /* Learned prescreen: an ensemble of MLPs d_in -> H -> H -> 1 (GELU),        */
 /* bfloat16 weights and activations on the matrix cores with float32         */
 /* accumulation, float32 master weights and Adam state.                      */

@@ -91,6 +91,10 @@ _SIGS = {
                                    C.c_void_p, C.c_void_p]),
     "gpbo_gather_rows": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
                                    C.c_void_p]),
+    "gpbo_sensitivity": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]),
+    "gpbo_plan_searches": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
+                                     C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gpbo_mlp_create": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                   C.POINTER(C.c_void_p)]),
     "gpbo_mlp_free": (C.c_int, [C.c_void_p]),
@@ -445,6 +449,35 @@ def gather_rows(ctx: Context, idx, Xc):
     out = torch.empty((idx.shape[0], Xc.shape[1]), dtype=torch.float32, device=ctx.device)
     ctx.check(lib().gpbo_gather_rows(ctx.h, idx.shape[0], _ptr(idx), Xc.shape[1], _ptr(Xc), _ptr(out)))
     return out
+
+
+def sensitivity(base, out):
+    """gpbo_sensitivity on host arrays: base (R,), out (P, V, R) -> S (R, P)."""
+    import numpy as np
+    base = np.ascontiguousarray(base, dtype=np.float64)
+    out = np.ascontiguousarray(out, dtype=np.float64)
+    P, V, R = out.shape
+    S = np.empty((R, P))
+    st = lib().gpbo_sensitivity(P, R, V, base.ctypes.data, out.ctypes.data, S.ctypes.data)
+    if st != OK:
+        raise GpboError(st, "gpbo_sensitivity")
+    return S
+
+
+def plan_searches(S, owner, cutoff=0.25, max_dims=10):
+    """gpbo_plan_searches: (routine_search (R,), param_search (P,), n_searches)."""
+    import numpy as np
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    R, P = S.shape
+    own = np.ascontiguousarray(owner, dtype=np.int32)
+    rs = np.empty(R, dtype=np.int32)
+    ps = np.empty(P, dtype=np.int32)
+    n = C.c_int32()
+    st = lib().gpbo_plan_searches(P, R, S.ctypes.data, own.ctypes.data, float(cutoff), int(max_dims),
+                                  rs.ctypes.data, ps.ctypes.data, C.byref(n))
+    if st != OK:
+        raise GpboError(st, "gpbo_plan_searches")
+    return rs, ps, n.value
 
 
 class Mlp:
