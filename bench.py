@@ -257,7 +257,8 @@ def run_c4(args):
                  Xc=torch.tensor(p.Xc, dtype=torch.float32, device=dev))
         model = G.fit(ctx, r["X"], r["y"], p.lengthscale, p.kernel, p.signal_var, p.noise_var)
         init = I.mlp_init(p.extra["init_rng"], E, p.d, H)
-        net = G.Mlp(ctx, G.Mlp.pack(**init, device=dev), E, p.d, H)
+        # the network lives on the network's context (its stream)
+        net = G.Mlp(ctx_net, G.Mlp.pack(**init, device=dev), E, p.d, H)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         hist = net.train_on_model(model, steps=args.train_steps, lr=args.lr)
