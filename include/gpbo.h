@@ -301,12 +301,14 @@ gpbo_status gpbo_score_bound(gpbo_ctx ctx, gpbo_model model, int64_t m, const fl
  * largest EI upper bound (gpbo_score_bound; every one of them when k2 >= k1)
  * are scored exactly on the GPBO_FP32 path, and the one with the largest EI
  * is returned: *next its index into Xc, *ei_max its EI.  *certified is 1
- * when that EI is not below the (k2+1)-th largest bound plus an allowance
- * for float32 rounding (2e-4 s_y sqrt(signal_var)): then no candidate of the
+ * when that EI is not below the k2-th largest bound (the smallest bound
+ * scored; every unscored bound is at most that) plus an allowance for
+ * float32 rounding (2e-4 s_y sqrt(signal_var)): then no candidate of the
  * subset left unscored can have a larger EI; 0 otherwise (call again with a
- * larger k2 to widen the exact set).  next, ei_max, certified: device or
+ * larger k2 to widen the exact set).  Candidates with equal bounds at the
+ * threshold are taken in index order.  next, ei_max, certified: device or
  * host memory (host memory synchronises); ei_max and certified may be NULL.
- * k2 + 1 <= 8192 unless k2 >= k1.  Asynchronous for device outputs. */
+ * Asynchronous for device outputs. */
 gpbo_status gpbo_score_subset(gpbo_ctx ctx, gpbo_model model, int64_t m, const float* Xc,
                               int64_t k1, const int64_t* idx, int64_t k2, int64_t* next,
                               double* ei_max, int32_t* certified);

@@ -1197,22 +1197,19 @@ gpbo_status gpbo_score_subset(gpbo_ctx c, gpbo_model M, int64_t m, const float* 
   if (m <= 0 || !Xc || k1 <= 0 || k1 > m || !idx || k2 <= 0 || !next)
     return fail(c, GPBO_E_INVALID_ARG, "invalid subset arguments");
   if (k2 > k1) k2 = k1;
-  if (k2 + 1 > topk_max_k() && k2 < k1)
-    return fail(c, GPBO_E_UNSUPPORTED, "k2 + 1 > %d is not supported", topk_max_k());
   DeviceGuard g(c->device);
   hipStream_t s = c->stream;
   note_stream(M, s);
   const int d = M->d;
   const bool all = k2 == k1;  // every candidate of the subset scored exactly
-  const int64_t kk = all ? k2 : k2 + 1;
   Carve cv;
   const size_t o_rows1 = cv.take((size_t)k1 * d * sizeof(float));
   const size_t o_bound = cv.take((size_t)k1 * sizeof(float));
-  const size_t o_pos = cv.take((size_t)kk * sizeof(int64_t));
+  const size_t o_pos = cv.take((size_t)k2 * sizeof(int64_t));
   const size_t o_idx2 = cv.take((size_t)k2 * sizeof(int64_t));
   const size_t o_rows2 = cv.take((size_t)k2 * d * sizeof(float));
   const size_t o_res = cv.take(64);
-  const size_t o_ws = cv.take(topk_scratch_bytes(k1, kk));
+  const size_t o_ws = cv.take(topk_set_scratch_bytes(k1));
   char* b = (char*)dmalloc(c, cv.bytes);
   if (!b) return fail(c, GPBO_E_OOM, "subset scratch allocation failed");
   float* rows1 = (float*)(b + o_rows1);
@@ -1229,8 +1226,9 @@ gpbo_status gpbo_score_subset(gpbo_ctx c, gpbo_model M, int64_t m, const float* 
     // no narrowing: the subset itself is scored exactly, in the given order
     HIP_TRY(c, hipMemcpyAsync(idx2, idx, (size_t)k2 * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
   } else {
-    // the k2 + 1 largest EI bounds among the subset; the first k2 are scored
-    // exactly, the last one certifies
+    // the k2 largest EI bounds among the subset (as a set; the selection's
+    // threshold, the k2-th largest bound, certifies: no unscored bound is
+    // above it)
     launch_gather_rows(k1, idx, d, Xc, rows1, s);
     {
       Model* one[1] = {M};
@@ -1241,7 +1239,7 @@ gpbo_status gpbo_score_subset(gpbo_ctx c, gpbo_model M, int64_t m, const float* 
       return fail(c, GPBO_E_OOM, "device allocation of the score operands failed (n=%d)", M->n);
     }
     launch_score_bound(M, k1, rows1, nullptr, nullptr, bound, s);
-    launch_topk_into(k1, bound, kk, pos, b + o_ws, s);
+    launch_topk_set_into(k1, bound, k2, pos, b + o_ws, s);
     launch_compose_idx(k2, idx, pos, idx2, s);
   }
   launch_gather_rows(k2, idx2, d, Xc, rows2, s);
@@ -1252,8 +1250,8 @@ gpbo_status gpbo_score_subset(gpbo_ctx c, gpbo_model M, int64_t m, const float* 
   }
   // float32 errors of the exact EI and of the bound: 2e-4 of the prior
   // standard deviation s_y sqrt(sf2) (s_y is read on the device)
-  launch_subset_finish(am, em, idx2, bound, all ? nullptr : pos + k2, 2e-4 * std::sqrt(M->sf2),
-                       M->stats, next_d, emax_d, cert_d, s);
+  launch_subset_finish(am, em, idx2, all ? nullptr : topk_set_threshold(b + o_ws),
+                       2e-4 * std::sqrt(M->sf2), M->stats, next_d, emax_d, cert_d, s);
   HIP_TRY(c, hipGetLastError());
   if (device_writable(next)) {
     HIP_TRY(c, hipMemcpyAsync(next, next_d, 8, hipMemcpyDeviceToDevice, s));

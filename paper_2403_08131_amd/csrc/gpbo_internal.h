@@ -324,11 +324,14 @@ void launch_topk_set_into(int64_t m, const float* v, int64_t k, int64_t* idx, vo
 void launch_compose_idx(int64_t k, const int64_t* outer, const int64_t* inner, int64_t* out,
                         hipStream_t s);
 // Pool index of a subset's argmax, its EI, and the certificate (see
-// gpbo_score_subset); next_pos may be NULL (every candidate scored).
+// gpbo_score_subset); thr_key (the top-k set selection's threshold key in its
+// scratch, launch_topk_set_threshold) may be NULL (every candidate scored).
 void launch_subset_finish(const int64_t* am, const double* em, const int64_t* pool_idx,
-                          const float* bounds, const int64_t* next_pos, double tol,
-                          const double* stats, int64_t* next, double* ei_max, int* certified,
-                          hipStream_t s);
+                          const unsigned* thr_key, double tol, const double* stats, int64_t* next,
+                          double* ei_max, int* certified, hipStream_t s);
+// Where launch_topk_set_into leaves the order-preserving key of the k-th
+// largest value (the selection threshold) in its scratch.
+const unsigned* topk_set_threshold(const void* ws);
 // Allocation-free top-k: the device address of the static scratch array on
 // `device` (resolved by topk_noalloc_init with that device current, once per
 // device; NULL before), and its size in bytes.

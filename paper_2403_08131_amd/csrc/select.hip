@@ -311,6 +311,8 @@ size_t topk_set_scratch_bytes(int64_t m) {
   return 4096 + 2 * round_up(nb * 4, 256);
 }
 
+const unsigned* topk_set_threshold(const void* ws) { return (const unsigned*)ws; }
+
 void launch_topk_set_into(int64_t m, const float* v, int64_t k, int64_t* idx, void* ws,
                           hipStream_t s) {
   unsigned* state = (unsigned*)ws;
@@ -373,14 +375,20 @@ void launch_compose_idx(int64_t k, const int64_t* outer, const int64_t* inner, i
   hipLaunchKernelGGL(k_compose_idx, dim3(g), dim3(256), 0, s, k, outer, inner, out);
 }
 
+// The float whose order-preserving key is `key` (inverse of fkey).
+__device__ __forceinline__ float key_float(unsigned key) {
+  return __uint_as_float((key & 0x80000000u) ? (key & 0x7fffffffu) : ~key);
+}
+
 // Result of an exact re-score of a subset: the pool index of the argmax and
-// whether no unscored candidate of the subset can beat it.  bound_next: the
-// EI upper bound of the best candidate left out (NULL: none left out).
-// tol: allowance in units of s_y (stats[1], the model's scale of y).
+// whether no unscored candidate of the subset can beat it.  thr_key: the
+// order-preserving key of the smallest EI bound that was scored (the
+// selection threshold; NULL when every candidate was scored): every
+// unscored candidate's bound is at most that value.  tol: allowance in
+// units of s_y (stats[1], the model's scale of y).
 __global__ void k_subset_finish(const int64_t* __restrict__ am, const double* __restrict__ em,
                                 const int64_t* __restrict__ pool_idx,
-                                const float* __restrict__ bounds,
-                                const int64_t* __restrict__ next_pos, double tol,
+                                const unsigned* __restrict__ thr_key, double tol,
                                 const double* __restrict__ stats, int64_t* __restrict__ next,
                                 double* __restrict__ ei_max, int* __restrict__ certified) {
   if (threadIdx.x != 0) return;
@@ -388,16 +396,15 @@ __global__ void k_subset_finish(const int64_t* __restrict__ am, const double* __
   next[0] = a >= 0 ? pool_idx[a] : -1;
   ei_max[0] = *em;
   int cert = a >= 0;
-  if (next_pos) cert = cert && *em >= (double)bounds[*next_pos] + tol * stats[S_YSTD];
+  if (thr_key) cert = cert && *em >= (double)key_float(*thr_key) + tol * stats[S_YSTD];
   certified[0] = cert;
 }
 
 void launch_subset_finish(const int64_t* am, const double* em, const int64_t* pool_idx,
-                          const float* bounds, const int64_t* next_pos, double tol,
-                          const double* stats, int64_t* next, double* ei_max, int* certified,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_subset_finish, dim3(1), dim3(64), 0, s, am, em, pool_idx, bounds, next_pos,
-                     tol, stats, next, ei_max, certified);
+                          const unsigned* thr_key, double tol, const double* stats, int64_t* next,
+                          double* ei_max, int* certified, hipStream_t s) {
+  hipLaunchKernelGGL(k_subset_finish, dim3(1), dim3(64), 0, s, am, em, pool_idx, thr_key, tol,
+                     stats, next, ei_max, certified);
 }
 
 namespace {
