@@ -159,6 +159,39 @@ int oracle_fit(int n, int d, const double* X, const double* y, int kernel,
   return st;
 }
 
+/*
+ * Rank-one extension of a Cholesky factor: the re-training step of the
+ * Bayesian-optimisation loop (Sec. III-A) when one evaluated configuration is
+ * added and the hyperparameters stay fixed.  With K = L L^T and the bordered
+ * matrix K' = [[K, k], [k^T, kappa]], the factor of K' with positive diagonal
+ * is unique, and its last row follows from the block product:
+ *   L' = [[L, 0], [l^T, delta]],   L l = k,   delta = sqrt(kappa - l^T l).
+ * L is n x n (row-major, lower), Lout receives the (n+1) x (n+1) factor.
+ * Returns OR_NOT_PD (bad = n) when kappa - l^T l is not positive.
+ */
+int oracle_chol_append(int n, const double* L, const double* k, double kappa, double* Lout,
+                       int* bad) {
+  const int n1 = n + 1;
+  double* l = (double*)malloc(sizeof(double) * (n > 0 ? n : 1));
+  oracle_forward_sub(n, L, k, l);
+  double ll = 0.0;
+  for (int j = 0; j < n; ++j) ll += l[j] * l[j];
+  const double d2 = kappa - ll;
+  if (!(d2 > 0.0) || !isfinite(d2)) {
+    free(l);
+    if (bad) *bad = n;
+    return OR_NOT_PD;
+  }
+  memset(Lout, 0, sizeof(double) * (size_t)n1 * n1);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) Lout[(size_t)i * n1 + j] = L[(size_t)i * n + j];
+  for (int j = 0; j < n; ++j) Lout[(size_t)n * n1 + j] = l[j];
+  Lout[(size_t)n * n1 + n] = sqrt(d2);
+  free(l);
+  if (bad) *bad = -1;
+  return OR_OK;
+}
+
 /* Expected improvement for minimisation (Jones et al. 1998):
  *   sigma > 0:  EI = (f - mu) Phi(z) + sigma phi(z),  z = (f - mu) / sigma
  *   sigma = 0:  EI = max(f - mu, 0)                                       */

@@ -67,6 +67,8 @@ def lib():
         L.oracle_forward_sub.argtypes = [C.c_int, dp, dp, dp]
         L.oracle_back_sub.restype = None
         L.oracle_back_sub.argtypes = [C.c_int, dp, dp, dp]
+        L.oracle_chol_append.restype = C.c_int
+        L.oracle_chol_append.argtypes = [C.c_int, dp, dp, C.c_double, dp, ip]
         L.oracle_fit.restype = C.c_int
         L.oracle_fit.argtypes = [C.c_int, C.c_int, dp, dp, C.c_int, dp, C.c_double,
                                  C.c_double, C.c_int, dp, dp, dp, ip]
@@ -161,6 +163,19 @@ def back_sub(L, z):
     x = np.empty_like(z)
     lib().oracle_back_sub(L.shape[0], pl, pz, x.ctypes.data_as(C.POINTER(C.c_double)))
     return x
+
+
+def chol_append(L, k, kappa):
+    """Factor of the bordered matrix [[K, k], [k^T, kappa]] from the factor L
+    of K (see oracle_chol_append).  Returns (status, L', bad_pivot)."""
+    L, pL = _d(L)
+    k, pk = _d(k)
+    n = L.shape[0]
+    out = np.empty((n + 1, n + 1))
+    bad = C.c_int(-1)
+    st = lib().oracle_chol_append(n, pL, pk, float(kappa),
+                                  out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(bad))
+    return st, out, bad.value
 
 
 class Fit:

@@ -38,6 +38,8 @@ MUTATIONS = {
     "ens_sample_std": ("sqrt(q / E)", "sqrt(q / (E - 1))"),
     "bound_drop_noise": ("kmax * kmax / (sf2 + sn2)", "kmax * kmax / sf2"),
     "bound_min_k": ("if (k > kmax) kmax = k;", "if (kmax == 0.0 || k < kmax) kmax = k;"),
+    "append_back_sub": ("oracle_forward_sub(n, L, k, l);", "oracle_back_sub(n, L, k, l);"),
+    "append_no_sqrt": ("Lout[(size_t)n * n1 + n] = sqrt(d2);", "Lout[(size_t)n * n1 + n] = d2;"),
     "w2_transposed": ("s += rnd(W2[(size_t)h * H + k], bf16) * h1[k];",
                       "s += rnd(W2[(size_t)k * H + h], bf16) * h1[k];"),
 }
@@ -120,3 +122,47 @@ def test_plan_pins_catch_planted_mistakes():
             elif r.returncode == 0:
                 survivors.append(name)
     assert not survivors, f"plan pins did not catch: {survivors}"
+
+
+BO_MUTATIONS = {
+    "pick_argmin": ("j = O.argmax(ei)", "j = int(np.argmin(ei))"),
+    "pick_first_row": ("x = P[j].copy()", "x = P[0].copy()"),
+    "no_normalize": ("f = O.fit(X, y, ls, kind, sf2, sn2, normalize_y)",
+                     "f = O.fit(X, y, ls, kind, sf2, sn2, False)"),
+    "stale_objective": ("y = np.append(y, float(objective(x)))",
+                        "y = np.append(y, float(objective(P[0])))"),
+    "fit_initial_only": ("f = O.fit(X, y, ls, kind, sf2, sn2, normalize_y)",
+                         "f = O.fit(X[:len(X0)], y[:len(X0)], ls, kind, sf2, sn2, normalize_y)"),
+}
+
+
+@pytest.mark.slow
+def test_bo_pins_catch_planted_mistakes():
+    """The same check for the loop oracle (oracle/bo.py) and its pins in
+    tests/test_oracle_bo.py."""
+    src = os.path.join(ROOT, "oracle", "bo.py")
+    with open(src) as f:
+        text = f.read()
+    pins = os.path.join(ROOT, "tests", "test_oracle_bo.py")
+    survivors = []
+    with tempfile.TemporaryDirectory() as tmp:
+        for name, (old, new) in list(BO_MUTATIONS.items()) + [("clean", ("", ""))]:
+            pkg = os.path.join(tmp, name, "oracle")
+            os.makedirs(pkg)
+            open(os.path.join(pkg, "__init__.py"), "w").close()
+            for aux in ("oracle.py", "gp_oracle.c", "liboracle.so"):
+                os.symlink(os.path.join(ROOT, "oracle", aux), os.path.join(pkg, aux))
+            if name != "clean":
+                assert text.count(old) >= 1, name
+            with open(os.path.join(pkg, "bo.py"), "w") as f:
+                f.write(text.replace(old, new, 1) if name != "clean" else text)
+            env = dict(os.environ, PYTHONPATH=os.path.join(tmp, name) + os.pathsep + ROOT)
+            r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                                "--rootdir", os.path.join(tmp, name), pins],
+                               cwd=os.path.join(tmp, name), env=env, capture_output=True, text=True,
+                               timeout=600)
+            if name == "clean":
+                assert r.returncode == 0, r.stdout[-2000:]
+            elif r.returncode == 0:
+                survivors.append(name)
+    assert not survivors, f"bo pins did not catch: {survivors}"

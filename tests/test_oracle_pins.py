@@ -143,6 +143,38 @@ def test_cholesky_not_pd_reports_pivot():
     assert st == O.NOT_PD and bad == 1
 
 
+@pytest.mark.parametrize("n", [0, 1, 7, 33])
+@pytest.mark.parametrize("kind", [O.SE, O.MATERN52])
+def test_chol_append_equals_factor_of_bordered_matrix(n, kind):
+    """The Cholesky factor with positive diagonal is unique, so extending the
+    factor of K by one row must give the factor of the bordered matrix."""
+    rng = np.random.default_rng(300 + n + 10 * kind)
+    X = rng.uniform(size=(n + 1, 3))
+    K = O.gram(kind, X, [0.4, 0.7, 1.1], 1.3, 1e-3)
+    st, Lf, _ = O.cholesky(K)
+    assert st == O.OK
+    L = Lf[:n, :n] if n else np.zeros((0, 0))
+    st, La, bad = O.chol_append(L, K[n, :n], K[n, n])
+    assert st == O.OK and bad == -1
+    np.testing.assert_allclose(La, Lf, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(La @ La.T, K, rtol=0, atol=1e-13)
+    assert np.all(np.triu(La, 1) == 0.0)
+
+
+def test_chol_append_n0_is_sqrt_and_not_pd_reports_new_index():
+    st, La, _ = O.chol_append(np.zeros((0, 0)), np.zeros(0), 6.25)
+    assert st == O.OK and La.shape == (1, 1) and La[0, 0] == 2.5
+    # bordered matrix [[4, 2], [2, 0.5]] has determinant -2: not positive definite
+    st, _, bad = O.chol_append(np.array([[2.0]]), np.array([2.0]), 0.5)
+    assert st == O.NOT_PD and bad == 1
+    # [[4, 2], [2, 1]] is singular: the new pivot is exactly zero
+    st, _, bad = O.chol_append(np.array([[2.0]]), np.array([2.0]), 1.0)
+    assert st == O.NOT_PD and bad == 1
+    # [[4, 2], [2, 2]]: l = 1, delta = 1
+    st, La, _ = O.chol_append(np.array([[2.0]]), np.array([2.0]), 2.0)
+    assert st == O.OK and np.array_equal(La, np.array([[2.0, 0.0], [1.0, 1.0]]))
+
+
 def test_triangular_solves_residual():
     K = _spd(9, 11)
     _, L, _ = O.cholesky(K)
