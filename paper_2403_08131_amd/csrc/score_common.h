@@ -61,13 +61,15 @@ struct PT<P_F64IO32> {
 // Float64 arithmetic (either input type).
 __host__ __device__ constexpr bool arith64(int P) { return P == GPBO_FP64 || P == P_F64IO32; }
 
-// float32 -> bfloat16 bits, round to nearest even (NaN kept quiet).
+// float32 -> bfloat16 bits, round to nearest even (NaN kept quiet; an
+// infinity, whose low bits are zero, passes the rounding unchanged).
+// Branch-free: both results are formed and one is selected, so a wave does
+// not split its execution mask per element.
 __device__ __forceinline__ unsigned short f2bf(float f) {
-  unsigned int u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u)
-    return (unsigned short)((u >> 16) | ((u & 0x7fffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+  const unsigned int u = __float_as_uint(f);
+  const unsigned int rounded = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  const unsigned int quiet = (u >> 16) | 0x40u;
+  return (unsigned short)(f != f ? quiet : rounded);
 }
 // The same rounding by the hardware conversion (v_cvt_pk_bf16_f32).  Faster
 // in the cross-covariance tile of the scoring kernels; measured slower than
