@@ -222,6 +222,35 @@ gpbo_status gpbo_model_status_batched(gpbo_ctx ctx, int32_t B, const gpbo_model*
 gpbo_status gpbo_fit_batched(gpbo_ctx ctx, int32_t B, const gpbo_problem* probs,
                              gpbo_model* out, double* lml, int32_t* status);
 
+/* Rank-one update: the re-training step of the optimisation loop (Sec. III-A
+ * retrains the surrogate after each evaluation; Sec. IV-D gives every search
+ * a budget of evaluations) when the hyperparameters stay fixed.  Adds one
+ * evaluated configuration to each of B fitted models: K gains a row and a
+ * column k = k(X, x_new), kappa = signal_var + noise_var; L gains the row
+ * [l^T, delta] with l = L^-1 k and delta = sqrt(kappa - l^T l), and L^-1 the
+ * row [-(L^-T l)^T / delta, 1 / delta] -- O(n^2) per model instead of the
+ * O(n^3) refit.  y is normalised again over the n + 1 values, and alpha, the
+ * log marginal likelihood and the statistics are recomputed as the fit
+ * computes them (with its refinement option).  The result equals a refit on
+ * the n + 1 observations up to rounding.
+ * models: B distinct models of ctx.  x_new: device, B rows of ldx float64
+ * (row b holds model b's d values, ldx >= every d).  y_new: device, B
+ * float64.  Both are read by the queued work: keep them allocated and
+ * unchanged until the stream has run it.
+ * ASYNCHRONOUS like gpbo_fit_batched_async: gpbo_model_status then reports
+ * GPBO_E_NOT_PD with bad_pivot = the old n when the new pivot is not
+ * positive (a repeated configuration with noise_var = 0, for instance) and
+ * GPBO_E_NONFINITE for a non-finite x_new or y_new; such a model stays failed
+ * (fit it again), and so does a model whose fit had failed.  The model's n
+ * counts the new row either way.  A model whose 64-row padding is full moves
+ * to buffers one tile larger (a device allocation and a copy on the device);
+ * score operands built earlier are rebuilt by the next scoring call.
+ * Returns GPBO_E_INVALID_ARG (NULL, repeated or foreign models, ldx too
+ * small, host pointers), GPBO_E_UNSUPPORTED (n would exceed 65536) or
+ * GPBO_E_OOM before any work is queued. */
+gpbo_status gpbo_append_batched(gpbo_ctx ctx, int32_t B, const gpbo_model* models,
+                                const double* x_new, int32_t ldx, const double* y_new);
+
 /* Release a model (NULL is ignored).  Work still queued that uses it may
  * run on: with a context allocator the buffers go back in the order of the
  * stream they were allocated on, without a wait, when that is the stream

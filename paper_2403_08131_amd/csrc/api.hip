@@ -82,14 +82,17 @@ gpbo_status check_problem(Ctx* c, const gpbo_problem* p) {
 
 // Byte offsets of one model's buffers inside its part of a fit allocation.
 struct FitLayout {
-  size_t oX, oil, oL, oLi, oD, oyt, oa, ow, o32, bytes;
+  size_t oX, oy, oil, oL, oLi, oD, oyt, oa, ow, o32, bytes;
 };
 
+// X and y take npad rows so that rank-one appends fill the padding before
+// the buffers have to grow.
 FitLayout fit_layout(int n, int d, bool refine) {
   const size_t np = round_up(n, NB);
   Carve cv;
   FitLayout f;
-  f.oX = cv.take((size_t)n * d * sizeof(double));
+  f.oX = cv.take(np * d * sizeof(double));
+  f.oy = cv.take(np * sizeof(double));
   f.oil = cv.take(d * sizeof(double));
   f.oL = cv.take(np * np * sizeof(double));
   f.oLi = cv.take(np * np * sizeof(double));
@@ -230,10 +233,13 @@ gpbo_status fit_group(Ctx* c, int B, const gpbo_problem* probs, Model* const* ms
     M->d = p.d;
     M->npad = (int)round_up(p.n, NB);
     M->kernel = p.kernel;
+    M->normalize = p.normalize_y ? 1 : 0;
+    M->refine = p.refine_alpha ? 1 : 0;
     M->sf2 = p.signal_var;
     M->sn2 = p.noise_var;
     M->ls.assign(p.lengthscale, p.lengthscale + p.d);
     M->X64 = (double*)(b + f.oX);
+    M->y64 = (double*)(b + f.oy);
     M->il64 = (double*)(b + f.oil);
     M->L = (double*)(b + f.oL);
     M->Linv = (double*)(b + f.oLi);
@@ -719,6 +725,9 @@ gpbo_status gpbo_model_factors(gpbo_ctx c, gpbo_model M, double* L, double* Linv
 }
 
 // Above this many observations gpbo_score takes the chunked float32 path.
+static gpbo_status wait_before_release(Ctx* c, const Model* M);
+static gpbo_status ensure_desc(Ctx* c, size_t bytes);
+
 constexpr int LARGE_N_MIN = 1024;
 
 static gpbo_status ensure_red(Ctx* c, size_t bytes) {
@@ -748,6 +757,186 @@ static bool device_writable(const void* p) {
 // freed only after a wait (gpbo_model_free).
 static void note_stream(Model* M, hipStream_t s) {
   if (M->alloc_stream != s) M->alloc_mixed = true;
+}
+
+// Buffers of M that may still be read by queued work are released only
+// after a wait when the stream order does not cover it (see gpbo_model_free).
+static gpbo_status wait_before_release(Ctx* c, const Model* M) {
+  if (!c->has_alloc || M->alloc_mixed || M->alloc_stream != c->stream)
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return GPBO_OK;
+}
+
+// The descriptor buffer holds at least `bytes` (a larger one replaces it
+// once the work that reads the old one has run).
+static gpbo_status ensure_desc(Ctx* c, size_t bytes) {
+  if (c->desc_bytes >= bytes) return GPBO_OK;
+  if (c->desc_buf) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dfree(c, c->desc_buf);
+  }
+  c->desc_buf = dmalloc(c, bytes);
+  c->desc_bytes = c->desc_buf ? bytes : 0;
+  return c->desc_buf ? GPBO_OK : fail(c, GPBO_E_OOM, "descriptor allocation failed");
+}
+
+gpbo_status gpbo_append_batched(gpbo_ctx c, int32_t B, const gpbo_model* models,
+                                const double* x_new, int32_t ldx, const double* y_new) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (B < 0 || (B > 0 && (!models || !x_new || !y_new)))
+    return fail(c, GPBO_E_INVALID_ARG, "invalid batch arguments");
+  if (B == 0) return GPBO_OK;
+  DeviceGuard g(c->device);
+  if (!device_writable(x_new) || !device_writable(y_new))
+    return fail(c, GPBO_E_INVALID_ARG, "x_new and y_new must be device memory");
+  std::vector<Model*> ms(B);
+  for (int b = 0; b < B; ++b) {
+    Model* M = models[b];
+    if (!M) return fail(c, GPBO_E_INVALID_ARG, "model %d is NULL", b);
+    if (M->ctx != c) return fail(c, GPBO_E_INVALID_ARG, "model %d belongs to another context", b);
+    for (int a = 0; a < b; ++a)
+      if (ms[a] == M) return fail(c, GPBO_E_INVALID_ARG, "model %d appears twice in the batch", b);
+    if (ldx < M->d)
+      return fail(c, GPBO_E_INVALID_ARG, "ldx %d is smaller than model %d's d = %d", ldx, b, M->d);
+    if (M->n + 1 > 65536)
+      return fail(c, GPBO_E_UNSUPPORTED, "model %d would exceed n = 65536", b);
+    ms[b] = M;
+  }
+  // Models whose padding is full move to buffers one tile larger (one
+  // allocation for all of them, filled on the device).
+  std::vector<int> grow;
+  for (int b = 0; b < B; ++b)
+    if (ms[b]->n + 1 > ms[b]->npad) grow.push_back(b);
+  if (!grow.empty()) {
+    const int ng = (int)grow.size();
+    Carve cv;
+    const size_t ostat = cv.take((size_t)ng * STATUS_SLOT);
+    std::vector<FitLayout> lay(ng);
+    std::vector<size_t> base(ng);
+    for (int k = 0; k < ng; ++k) {
+      const Model* M = ms[grow[k]];
+      lay[k] = fit_layout(M->npad + 1, M->d, M->refine != 0);
+      base[k] = cv.take(lay[k].bytes);
+    }
+    std::shared_ptr<void> grp = dshared(c, cv.bytes);
+    if (!grp) return fail(c, GPBO_E_OOM, "device allocation of %zu bytes failed", cv.bytes);
+    char* gb = (char*)grp.get();
+    std::vector<GrowDesc> gd(ng);
+    int np_max = 0;
+    for (int k = 0; k < ng; ++k) {
+      const Model* M = ms[grow[k]];
+      const FitLayout& f = lay[k];
+      char* p = gb + base[k];
+      GrowDesc& G = gd[k];
+      G.n = M->n;
+      G.d = M->d;
+      G.np_old = M->npad;
+      G.np_new = (int)round_up(M->npad + 1, NB);
+      np_max = std::max(np_max, G.np_new);
+      G.X = M->X64;
+      G.il = M->il64;
+      G.y = M->y64;
+      G.L = M->L;
+      G.Linv = M->Linv;
+      G.stats = M->stats;
+      G.info = M->info;
+      G.X2 = (double*)(p + f.oX);
+      G.il2 = (double*)(p + f.oil);
+      G.y2 = (double*)(p + f.oy);
+      G.L2 = (double*)(p + f.oL);
+      G.Linv2 = (double*)(p + f.oLi);
+      G.stats2 = (double*)(gb + ostat + k * STATUS_SLOT);
+      G.info2 = (int*)(gb + ostat + k * STATUS_SLOT + S_COUNT * sizeof(double));
+    }
+    {
+      const gpbo_status st = ensure_desc(c, ng * sizeof(GrowDesc));
+      if (st != GPBO_OK) return st;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->desc_buf, gd.data(), ng * sizeof(GrowDesc), hipMemcpyHostToDevice,
+                              c->stream));
+    launch_grow((const GrowDesc*)c->desc_buf, ng, np_max, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    for (int k = 0; k < ng; ++k) {
+      Model* M = ms[grow[k]];
+      const FitLayout& f = lay[k];
+      char* p = gb + base[k];
+      {
+        const gpbo_status st = wait_before_release(c, M);
+        if (st != GPBO_OK) return st;
+      }
+      M->npad = gd[k].np_new;
+      M->X64 = gd[k].X2;
+      M->y64 = gd[k].y2;
+      M->il64 = gd[k].il2;
+      M->L = gd[k].L2;
+      M->Linv = gd[k].Linv2;
+      M->Dinv = (double*)(p + f.oD);
+      M->yt = (double*)(p + f.oyt);
+      M->alpha = (double*)(p + f.oa);
+      M->work = (double*)(p + f.ow);
+      M->L32 = M->refine ? (float*)(p + f.o32) : nullptr;
+      M->stats = gd[k].stats2;
+      M->info = gd[k].info2;
+      M->blk_fit = std::shared_ptr<void>(grp, p);
+      M->alloc_stream = c->stream;
+    }
+  }
+  // Descriptors of the models as they are (float64 products, no
+  // refinement), then of the extended models.
+  std::vector<FitDesc> hd(2 * (size_t)B);
+  for (int b = 0; b < B; ++b) {
+    Model* M = ms[b];
+    FitDesc o = make_fit_desc(M, M->X64, M->il64, M->y64, M->normalize, 0);
+    o.xnew = x_new + (int64_t)b * ldx;
+    o.ynew = y_new + b;
+    hd[b] = o;
+    M->n += 1;
+    FitDesc nw = make_fit_desc(M, M->X64, M->il64, M->y64, M->normalize, M->refine);
+    nw.append = 1;
+    hd[B + b] = nw;
+  }
+  {
+    const gpbo_status st = ensure_desc(c, hd.size() * sizeof(FitDesc));
+    if (st != GPBO_OK) return st;
+  }
+  const FitDesc* dd = (const FitDesc*)c->desc_buf;
+  HIP_TRY(c, hipMemcpyAsync(c->desc_buf, hd.data(), hd.size() * sizeof(FitDesc),
+                            hipMemcpyHostToDevice, c->stream));
+  launch_append(hd.data(), dd, hd.data() + B, dd + B, B, c->stream);
+  // The statistics of the extended models, read when a status is asked for.
+  std::shared_ptr<void> sreg = dshared(c, (size_t)B * STATUS_SLOT);
+  if (!sreg) return fail(c, GPBO_E_OOM, "status allocation failed");
+  launch_status_copy(dd + B, B, (unsigned char*)sreg.get(), (int)STATUS_SLOT, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  auto gs = std::make_shared<Model::GroupStatus>();
+  gs->dev = (const unsigned char*)sreg.get();
+  gs->nb = B;
+  gs->ctx = c;
+  gs->hold = sreg;
+  size_t got = 0;
+  gs->pinned = pinned_acquire(c, (size_t)B * STATUS_SLOT, &got);
+  if (gs->pinned) {
+    gs->pinned_bytes = got;
+    HIP_TRY(c, hipMemcpyAsync(gs->pinned, gs->dev, (size_t)B * STATUS_SLOT, hipMemcpyDeviceToHost,
+                              c->stream));
+    gs->ev = timing_event(c);
+    if (gs->ev) HIP_TRY(c, hipEventRecord(gs->ev, c->stream));
+  }
+  for (int b = 0; b < B; ++b) {
+    Model* M = ms[b];
+    // the score operands describe the old observations: rebuilt on next use
+    if (M->blk_obs || M->blk_score[0] || M->blk_score[1] || M->blk_score[2]) {
+      const gpbo_status st = wait_before_release(c, M);
+      if (st != GPBO_OK) return st;
+      M->blk_obs.reset();
+      for (int i = 0; i < 3; ++i) M->blk_score[i].reset();
+    }
+    note_stream(M, c->stream);
+    M->pending = true;
+    M->gstat = gs;
+    M->gslot = b;
+  }
+  return GPBO_OK;
 }
 
 // GPBO_DEBUG: reject candidate pools that hold NaN or infinity

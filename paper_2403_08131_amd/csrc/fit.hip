@@ -101,14 +101,20 @@ __global__ void __launch_bounds__(256) k_fit_stats(const FitDesc* __restrict__ D
   for (int i = t; i < n; i += 256) mn = fmin(mn, P.y[i]);
   mn = block_min(mn, red);
   for (int i = t; i < P.npad; i += 256) P.yt[i] = i < n ? (P.y[i] - mean) / sy : 0.0;
+  if (P.ymod != P.y)
+    for (int i = t; i < n; i += 256) P.ymod[i] = P.y[i];
   if (t < S_COUNT) P.stats[t] = 0.0;
   __syncthreads();
   if (t == 0) {
     P.stats[S_YMEAN] = mean;
     P.stats[S_YSTD] = sy;
     P.stats[S_FBEST] = mn;
-    P.info[0] = INT_MAX;
-    P.info[1] = bad;
+    if (!P.append) {
+      P.info[0] = INT_MAX;
+      P.info[1] = bad;
+    } else if (bad) {
+      P.info[1] = 1;
+    }
   }
 }
 
@@ -922,6 +928,132 @@ __global__ void __launch_bounds__(64 * RESF_W) k_res_finish(const FitDesc* __res
   if (threadIdx.x == 0) P.stats[slot] = sqrt(q);
 }
 
+// ---------------------------------------------------------------------------
+// Rank-one append (the re-training step of the optimisation loop with fixed
+// hyperparameters): K grows by one row and column, and so do L and L^-1.
+// The descriptors of the first three kernels describe the models before the
+// append (n = old number of observations).
+// ---------------------------------------------------------------------------
+
+// A block-uniform reading of the failure flags (another workgroup of the
+// same launch may set them while this one runs).
+__device__ __forceinline__ bool block_failed(const int* info, int* flag) {
+  if (threadIdx.x == 0) *flag = fit_failed(info) ? 1 : 0;
+  __syncthreads();
+  const bool f = *flag != 0;
+  __syncthreads();
+  return f;
+}
+
+// The new column of K, k_j = k(x_j, x_new) for j < n, into work vector V_W
+// (coordinates scaled and distances summed as the Gram kernel does); the
+// first workgroup also copies the configuration and its value into the
+// model and flags a non-finite one.
+__global__ void __launch_bounds__(256) k_append_k(const FitDesc* __restrict__ Ds) {
+  __shared__ double xs[GRAM_DMAX + 4];
+  __shared__ int flag;
+  const FitDesc& P = Ds[blockIdx.z];
+  const int n = P.n, d = P.d, t = threadIdx.x;
+  if ((int)blockIdx.x * 256 >= max(n, 1) || block_failed(P.info, &flag)) return;
+  const int dp4 = (d + 3) & ~3;
+  for (int k = t; k < dp4; k += 256) xs[k] = k < d ? P.xnew[k] * P.il[k] : 0.0;
+  if (blockIdx.x == 0) {
+    int bad = 0;
+    for (int k = t; k < d; k += 256) {
+      const double v = P.xnew[k];
+      P.X[(int64_t)n * d + k] = v;
+      bad |= !isfinite(v);
+    }
+    if (t == 0) {
+      const double v = *P.ynew;
+      P.ymod[n] = v;
+      bad |= !isfinite(v);
+    }
+    if (bad) atomicOr(&P.info[1], 1);
+  }
+  __syncthreads();
+  const int j = blockIdx.x * 256 + t;
+  if (j >= n) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  const double* xj = P.X + (int64_t)j * d;
+  for (int k = 0; k < dp4; k += 4) {
+    const double u0 = (k < d ? xj[k] * P.il[k] : 0.0) - xs[k];
+    const double u1 = (k + 1 < d ? xj[k + 1] * P.il[k + 1] : 0.0) - xs[k + 1];
+    const double u2 = (k + 2 < d ? xj[k + 2] * P.il[k + 2] : 0.0) - xs[k + 2];
+    const double u3 = (k + 3 < d ? xj[k + 3] * P.il[k + 3] : 0.0) - xs[k + 3];
+    s0 = fma(u0, u0, s0);
+    s1 = fma(u1, u1, s1);
+    s2 = fma(u2, u2, s2);
+    s3 = fma(u3, u3, s3);
+  }
+  P.work[(int64_t)V_W * P.npad + j] = cov_r2(P.kernel, (s0 + s1) + (s2 + s3), P.sf2);
+}
+
+// With l = L^-1 k (work V_R) and v = L^-T l (work V_Q), the bordered
+// factor and its inverse gain the rows
+//   L[n]    = [l^T, delta],           delta = sqrt(kappa - l^T l),
+//   L^-1[n] = [-v^T / delta, 1/delta]  (block substitution),
+// where kappa = sf2 + sn2 is K's new diagonal entry.  Every workgroup forms
+// l^T l in the same order, so all of them take the same decision; a pivot
+// that is not positive marks the model as failed at index n (NOT_PD).
+__global__ void __launch_bounds__(256) k_append_row(const FitDesc* __restrict__ Ds) {
+  __shared__ double red[4];
+  __shared__ int flag;
+  const FitDesc& P = Ds[blockIdx.z];
+  const int n = P.n, npad = P.npad, t = threadIdx.x;
+  if ((int)blockIdx.x * 256 > n || block_failed(P.info, &flag)) return;
+  const double* l = P.work + (int64_t)V_R * npad;
+  const double* v = P.work + (int64_t)V_Q * npad;
+  double q = 0.0;
+  for (int i = t; i < n; i += 256) q = fma(l[i], l[i], q);
+  q = block_sum(q, red);
+  const double d2 = (P.sf2 + P.sn2) - q;
+  if (!(d2 > 0.0) || !isfinite(d2)) {
+    if (blockIdx.x == 0 && t == 0) P.info[0] = n;
+    return;
+  }
+  const double delta = sqrt(d2), rdelta = 1.0 / delta;
+  const int j = blockIdx.x * 256 + t;
+  if (j < n) {
+    P.L[(int64_t)n * npad + j] = l[j];
+    P.Linv[(int64_t)n * npad + j] = -v[j] * rdelta;
+  } else if (j == n) {
+    P.L[(int64_t)n * npad + n] = delta;
+    P.Linv[(int64_t)n * npad + n] = rdelta;
+  }
+}
+
+// Copy of a model into larger buffers (see GrowDesc).
+__global__ void __launch_bounds__(256) k_grow(const GrowDesc* __restrict__ Ds) {
+  const GrowDesc& G = Ds[blockIdx.z];
+  const int64_t t0 = (int64_t)blockIdx.x * 256 + threadIdx.x, st = (int64_t)gridDim.x * 256;
+  const int64_t nn = (int64_t)G.np_new * G.np_new;
+  for (int64_t e = t0; e < nn; e += st) {
+    const int64_t i = e / G.np_new, j = e % G.np_new;
+    const bool in = i < G.np_old && j < G.np_old;
+    const double id = i == j ? 1.0 : 0.0;
+    G.L2[e] = in ? G.L[i * G.np_old + j] : id;
+    G.Linv2[e] = in ? G.Linv[i * G.np_old + j] : id;
+  }
+  for (int64_t e = t0; e < (int64_t)G.n * G.d; e += st) G.X2[e] = G.X[e];
+  for (int64_t e = t0; e < G.n; e += st) G.y2[e] = G.y[e];
+  for (int64_t e = t0; e < G.d; e += st) G.il2[e] = G.il[e];
+  if (t0 < S_COUNT) G.stats2[t0] = G.stats[t0];
+  if (t0 < 2) G.info2[t0] = G.info[t0];
+}
+
+// The statistics and flags of each model into one contiguous region (slot
+// bytes apart) for a single read-back.
+__global__ void __launch_bounds__(64) k_status_copy(const FitDesc* __restrict__ Ds,
+                                                    unsigned char* out, int slot) {
+  const FitDesc& P = Ds[blockIdx.x];
+  double* st = (double*)(out + (int64_t)blockIdx.x * slot);
+  int* inf = (int*)(st + S_COUNT);
+  const int t = threadIdx.x;
+  if (t < S_COUNT) st[t] = P.stats[t];
+  if (t < 2) inf[t] = P.info[t];
+}
+
 // The two-tile kernels stage 2 x 64 x 66 doubles (66 KiB) of dynamic LDS;
 // the update kernel takes the diagonal step's 76.5 KiB.
 void allow_tile_lds() {
@@ -955,6 +1087,10 @@ FitDesc make_fit_desc(Model* M, const double* X, const double* il, const double*
   f.X = M->X64;
   f.il = M->il64;
   f.y = y;
+  f.ymod = M->y64;
+  f.xnew = nullptr;
+  f.ynew = nullptr;
+  f.append = 0;
   f.L = M->L;
   f.Linv = M->Linv;
   f.Dinv = M->Dinv;
@@ -981,21 +1117,16 @@ std::vector<uint64_t> fit_launch_shape(const FitDesc* h, int B) {
           (uint64_t)chmax, (uint64_t)refine};
 }
 
+void launch_solve(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s);
+
 void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   allow_tile_lds();
-  int nbmax = 0, nmax = 0, chmax = 1;
-  int64_t npmax = 0;
-  for (int b = 0; b < B; ++b) {
-    nbmax = std::max(nbmax, h[b].npad / NB);
-    nmax = std::max(nmax, h[b].n);
-    npmax = std::max<int64_t>(npmax, h[b].npad);
-    chmax = std::max(chmax, h[b].nchunks);
-  }
+  int nbmax = 0;
+  for (int b = 0; b < B; ++b) nbmax = std::max(nbmax, h[b].npad / NB);
   const size_t sm2 = 2 * NB * LDT * sizeof(double);
   const unsigned Bz = (unsigned)B;
   hipLaunchKernelGGL(k_fit_stats, dim3(1, 1, Bz), dim3(256), 0, s, dd);
   hipLaunchKernelGGL(k_gram, dim3(nbmax * (nbmax + 1) / 2 * (NB / KR), 1, Bz), dim3(256), 0, s, dd);
-  const unsigned gz = (unsigned)std::min<int64_t>(1024, ceil_div(npmax * npmax, 256));
   // step k: diagonal tile k (a launch of its own for k = 0, else factored by
   // the update launch of step k - 1); panel k with row multiply of inverse
   // step k-1; trailing update k with the update of inverse step k-1 and the
@@ -1012,8 +1143,24 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
     if (nupd + ntri > 0)
       hipLaunchKernelGGL(k_chol_update, dim3(nupd + ntri, 1, Bz), dim3(256), smu, s, dd, k, nupd);
   }
+  launch_solve(h, dd, B, s);
+}
+
+// alpha = K^-1 ytilde from the inverse factor with one refinement step, the
+// log marginal likelihood and the statistics (the fit's last stage, and the
+// whole recomputation after a rank-one append).
+void launch_solve(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
+  int nmax = 0, chmax = 1;
+  int64_t npmax = 0;
   bool any_refine = false;
-  for (int b = 0; b < B; ++b) any_refine |= h[b].refine != 0;
+  for (int b = 0; b < B; ++b) {
+    nmax = std::max(nmax, h[b].n);
+    npmax = std::max<int64_t>(npmax, h[b].npad);
+    chmax = std::max(chmax, h[b].nchunks);
+    any_refine |= h[b].refine != 0;
+  }
+  const unsigned Bz = (unsigned)B;
+  const unsigned gz = (unsigned)std::min<int64_t>(1024, ceil_div(npmax * npmax, 256));
   if (any_refine) hipLaunchKernelGGL(k_cast_linv, dim3(gz, 1, Bz), dim3(256), 0, s, dd);
   const unsigned g_rows = (unsigned)ceil_div(npmax, 4), g_cols = (unsigned)ceil_div(npmax, TT_COLS);
   // alpha = Linv^T (Linv ytilde), then one residual-and-correction step
@@ -1027,6 +1174,43 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(64 * TRMV_T_WAVES), 0, s, dd, (int)V_W, -2, 1);
   hipLaunchKernelGGL(k_residual, g_res, dim3(256), 0, s, dd);
   hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(64 * RESF_W), 0, s, dd, (int)S_RES1, 1);
+}
+
+}  // namespace gpbo
+
+namespace gpbo {
+
+void launch_append(const FitDesc* hold, const FitDesc* dold, const FitDesc* hnew,
+                   const FitDesc* dnew, int B, hipStream_t s) {
+  int nmax = 0;
+  int64_t npmax = 0;
+  for (int b = 0; b < B; ++b) {
+    nmax = std::max(nmax, hold[b].n);
+    npmax = std::max<int64_t>(npmax, hold[b].npad);
+  }
+  const unsigned Bz = (unsigned)B;
+  hipLaunchKernelGGL(k_append_k, dim3((unsigned)ceil_div(std::max(nmax, 1), 256), 1, Bz), dim3(256),
+                     0, s, dold);
+  // l = L^-1 k, v = L^-T l (float64: the old descriptors never refine)
+  hipLaunchKernelGGL(k_trmv, dim3((unsigned)ceil_div(npmax, 4), 1, Bz), dim3(256), 0, s, dold,
+                     (int)V_W, (int)V_R, 0);
+  hipLaunchKernelGGL(k_trmv_t, dim3((unsigned)ceil_div(npmax, TT_COLS), 1, Bz),
+                     dim3(64 * TRMV_T_WAVES), 0, s, dold, (int)V_R, (int)V_Q, 0);
+  hipLaunchKernelGGL(k_append_row, dim3((unsigned)ceil_div(nmax + 1, 256), 1, Bz), dim3(256), 0, s,
+                     dold);
+  // normalisation over the n + 1 values, then alpha, the LML and statistics
+  hipLaunchKernelGGL(k_fit_stats, dim3(1, 1, Bz), dim3(256), 0, s, dnew);
+  launch_solve(hnew, dnew, B, s);
+}
+
+void launch_grow(const GrowDesc* dd, int B, int np_new_max, hipStream_t s) {
+  const unsigned gx =
+      (unsigned)std::min<int64_t>(1024, ceil_div((int64_t)np_new_max * np_new_max, 256));
+  hipLaunchKernelGGL(k_grow, dim3(gx, 1, (unsigned)B), dim3(256), 0, s, dd);
+}
+
+void launch_status_copy(const FitDesc* dd, int B, unsigned char* out, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_status_copy, dim3((unsigned)B), dim3(64), 0, s, dd, out, slot);
 }
 
 }  // namespace gpbo

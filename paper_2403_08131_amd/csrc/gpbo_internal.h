@@ -63,9 +63,11 @@ struct Model {
   Ctx* ctx = nullptr;
   int n = 0, d = 0, npad = 0;  // npad = round_up(n, NB)
   int kernel = 0;
+  int normalize = 1, refine = 0;  // the fit's options (kept for rank-one appends)
   double sf2 = 1, sn2 = 0;
   std::vector<double> ls;       // host lengthscales
-  double* X64 = nullptr;        // n x d, the observations as given
+  double* X64 = nullptr;        // npad x d, the observations as given (n rows used)
+  double* y64 = nullptr;        // npad, the observed values as given (n used)
   double* il64 = nullptr;       // d, 1 / lengthscale
   double* L = nullptr;          // npad x npad, lower Cholesky factor (identity padded)
   double* Linv = nullptr;       // npad x npad, lower inverse factor
@@ -90,6 +92,7 @@ struct Model {
     int nb = 0;
     bool read = false;
     std::vector<unsigned char> host;     // nb slots once read
+    std::shared_ptr<void> hold;          // device region of the slots when it is not the fit's
     // The slots copied to pinned host memory right behind the fit, in stream
     // order, with an event after the copy: a status request then waits for
     // the event instead of starting a copy and a stream synchronisation
@@ -199,6 +202,13 @@ struct FitDesc {
   double* X;            // n x d (the model's copy)
   double* il;           // d, 1 / lengthscale (the model's copy)
   const double* y;   // n, the caller's observations
+  double* ymod;      // the model's copy of y (npad; written when it is not y itself)
+  // Rank-one append (gpbo_append_batched): the new configuration (d) and
+  // value, and append = 1 on the descriptor of the extended model (the
+  // statistics kernel then keeps an earlier failure instead of clearing it).
+  const double* xnew;
+  const double* ynew;
+  int append;
   double* L;         // npad x npad
   double* Linv;      // npad x npad
   double* Dinv;      // npad / NB inverse diagonal tiles
@@ -213,6 +223,24 @@ FitDesc make_fit_desc(Model* M, const double* X, const double* il, const double*
                       int normalize_y, int refine);
 // Queue the whole fit of B problems (descriptors: host copy h, device copy dd).
 void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s);
+// Queue the rank-one append of one configuration to each of B fitted models:
+// dold describes the models as fitted (n = old size, float64 products),
+// dnew the extended models (n + 1; the model's own X, y and refinement).
+void launch_append(const FitDesc* hold, const FitDesc* dold, const FitDesc* hnew,
+                   const FitDesc* dnew, int B, hipStream_t s);
+// Copy of a fitted model's buffers into larger ones (room for more rows):
+// X, the inverse lengthscales, y and the status slot verbatim, L and L^-1
+// into the wider row stride with the identity beyond the old padding.
+struct GrowDesc {
+  int n, d, np_old, np_new;
+  const double *X, *il, *y, *L, *Linv, *stats;
+  const int* info;
+  double *X2, *il2, *y2, *L2, *Linv2, *stats2;
+  int* info2;
+};
+void launch_grow(const GrowDesc* dd, int B, int np_new_max, hipStream_t s);
+// Each model's statistics and info words into out + b * slot.
+void launch_status_copy(const FitDesc* dd, int B, unsigned char* out, int slot, hipStream_t s);
 // What the grids and arguments of that launch sequence depend on besides the
 // descriptor pointer: equal shapes launch identical sequences.
 std::vector<uint64_t> fit_launch_shape(const FitDesc* h, int B);

@@ -73,6 +73,8 @@ _SIGS = {
     "gpbo_model_status": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
                                     C.POINTER(C.c_double)]),
     "gpbo_model_free": (C.c_int, [C.c_void_p]),
+    "gpbo_append_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p,
+                                      C.c_int32, C.c_void_p]),
     "gpbo_model_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "gpbo_model_shape": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "gpbo_model_factors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -320,6 +322,22 @@ def fit_batched(ctx: Context, problems, sync=True):
     models = [Model(ctx, C.c_void_p(hs[b]), pr["X"].shape[0], pr["X"].shape[1]) if status[b] == OK
               else None for b, pr in enumerate(problems)]
     return st, models, list(status), list(lml)
+
+
+def append_batched(ctx: Context, models, x_new, y_new):
+    """gpbo_append_batched: add row b of ``x_new`` (device float64, B x ldx,
+    ldx >= every model's d) with value ``y_new[b]`` (device float64, B) to
+    model b, queued without synchronising (``Model.status()`` reports the
+    outcome).  x_new and y_new must stay unchanged until the stream has run
+    the update."""
+    B = len(models)
+    assert x_new.dtype == torch.float64 and y_new.dtype == torch.float64
+    assert x_new.is_cuda and y_new.is_cuda and x_new.is_contiguous() and y_new.is_contiguous()
+    assert x_new.dim() == 2 and x_new.shape[0] == B and y_new.numel() == B
+    hs = (C.c_void_p * B)(*[mo.h.value if isinstance(mo.h, C.c_void_p) else mo.h for mo in models])
+    ctx.check(lib().gpbo_append_batched(ctx.h, B, hs, _ptr(x_new), int(x_new.shape[1]), _ptr(y_new)))
+    for mo in models:
+        mo.n += 1
 
 
 def status_batched(ctx: Context, models):

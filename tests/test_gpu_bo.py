@@ -1,0 +1,201 @@
+"""GPU parity of the rank-one update (gpbo_append_batched) and of the
+optimisation-loop driver against the float64 oracle, through the C ABI.
+
+Bars:
+* an appended model equals the oracle's fit on the n + 1 observations: L,
+  alpha, LML and log det within 64 n eps cond(K) (relative; the inverse
+  factor within that times cond(K)), the normalisation statistics to
+  rounding, f_best exactly;
+* the driver's picks equal the oracle loop's (float64 scoring) at every
+  iteration whose top two oracle EI values are more than 1e-6 apart
+  (relative); the seeds below have no closer pair.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bo as OBO
+from oracle import oracle as O
+from paper_2403_08131_amd import bo as BO
+from paper_2403_08131_amd import gpbo as G
+from paper_2403_08131_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+DEV = torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = G.Context(0)
+    yield c
+    c.close()
+
+
+def _t(a, dt=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dt, device=DEV)
+
+
+def _okind(k):
+    return O.SE if k == G.KERNEL_SE else O.MATERN52
+
+
+def _objective(x):
+    x = np.asarray(x, dtype=np.float64)
+    return float(np.sum((x - 0.3) ** 2) + 0.5 * np.sin(7.0 * x[0]) + 0.2 * np.cos(5.0 * x[-1]))
+
+
+def _data(n, d, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(size=(n, d))
+    y = np.array([_objective(x) for x in X]) + 0.01 * rng.standard_normal(n)
+    return X, y
+
+
+def _check_against_oracle(m, X, y, ls, kind, sf2, sn2, normalize=True):
+    n = X.shape[0]
+    f = O.fit(X, y, ls, _okind(kind), sf2, sn2, normalize)
+    assert f.status == O.OK
+    cond = np.linalg.cond(O.gram(_okind(kind), X, ls, sf2, sn2))
+    tol = 64 * n * EPS * cond
+    L, Li, a = (t.cpu().numpy() for t in m.factors())
+    s = m.stats()
+    assert L.shape == (n, n)
+    assert np.max(np.abs(L - f.L)) <= tol * np.max(np.abs(f.L))
+    Li_ref = np.linalg.inv(f.L)  # test-side reference for the inverse factor
+    assert np.max(np.abs(Li - Li_ref)) <= tol * cond * np.max(np.abs(Li_ref))
+    assert np.max(np.abs(a - f.alpha)) <= tol * max(np.max(np.abs(f.alpha)), 1.0)
+    assert s["lml"] == pytest.approx(f.lml, rel=tol, abs=tol * n)
+    assert s["logdet"] == pytest.approx(f.logdet, rel=tol, abs=tol * n)
+    assert s["ymean"] == pytest.approx(f.ymean, rel=1e-13, abs=1e-15)
+    assert s["ystd"] == pytest.approx(f.ystd, rel=1e-13)
+    assert s["fbest"] == f.fbest
+    return f, cond
+
+
+@pytest.mark.parametrize("n0,kind,refine,normalize", [
+    (5, G.KERNEL_SE, False, True),
+    (63, G.KERNEL_MATERN52, False, True),   # fills the last padded row
+    (64, G.KERNEL_SE, False, True),         # grows the buffers by one tile
+    (130, G.KERNEL_SE, True, True),         # float32 products + refinement
+    (300, G.KERNEL_MATERN52, False, False),
+])
+def test_append_equals_refit(ctx, n0, kind, refine, normalize):
+    d = 4
+    print(f"append n0={n0} kernel={kind} refine={refine}", flush=True)
+    X, y = _data(n0 + 1, d, 40 + n0)
+    ls, sf2, sn2 = [0.4, 0.6, 0.5, 0.8], 1.0, 1e-4
+    m = G.fit(ctx, _t(X[:n0]), _t(y[:n0]), ls, kind, sf2, sn2, normalize_y=normalize,
+              refine_alpha=refine)
+    G.append_batched(ctx, [m], _t(X[n0:n0 + 1]), _t(y[n0:n0 + 1]))
+    m.status()
+    assert m.n == n0 + 1
+    _check_against_oracle(m, X, y, ls, kind, sf2, sn2, normalize)
+    m.free()
+
+
+def test_sequence_of_batched_appends_crossing_tiles(ctx):
+    """Three models of different d and n, 70 appends each (every model
+    crosses a 64-row tile), one batched call per step; each model ends equal
+    to the oracle's fit on all its observations."""
+    specs = [(5, 2), (40, 3), (60, 6)]
+    data = [_data(n0 + 70, d, 7 + d) for n0, d in specs]
+    ls = [np.full(d, 0.5) for _, d in specs]
+    probs = [dict(X=_t(X[:n0]), y=_t(y[:n0]), lengthscale=list(l), signal_var=1.0, noise_var=1e-3)
+             for (n0, d), (X, y), l in zip(specs, data, ls)]
+    st, models, _, _ = G.fit_batched(ctx, probs)
+    assert st == G.OK
+    dmax = max(d for _, d in specs)
+    for t in range(70):
+        xn = np.zeros((3, dmax))
+        yn = np.zeros(3)
+        for b, ((n0, d), (X, y)) in enumerate(zip(specs, data)):
+            xn[b, :d] = X[n0 + t]
+            yn[b] = y[n0 + t]
+        G.append_batched(ctx, models, _t(xn), _t(yn))
+    st, status, _ = G.status_batched(ctx, models)
+    assert st == G.OK, status
+    for b, ((n0, d), (X, y)) in enumerate(zip(specs, data)):
+        _check_against_oracle(models[b], X, y, ls[b], G.KERNEL_SE, 1.0, 1e-3)
+        models[b].free()
+
+
+def test_append_then_score_matches_oracle_posterior(ctx):
+    X, y = _data(41, 3, 99)
+    ls = [0.3, 0.5, 0.7]
+    m = G.fit(ctx, _t(X[:40]), _t(y[:40]), ls, G.KERNEL_SE, 1.0, 1e-4)
+    Xc = np.random.default_rng(3).uniform(size=(2048, 3))
+    G.score(ctx, m, _t(Xc), prec="fp64")  # builds the score operands of the 40-point model
+    G.append_batched(ctx, [m], _t(X[40:41]), _t(y[40:41]))
+    m.status()
+    f = O.fit(X, y, ls, O.SE, 1.0, 1e-4)
+    ref = O.score(f, Xc)
+    out = G.score(ctx, m, _t(Xc), prec="fp64")
+    scale = f.ystd
+    assert np.max(np.abs(out["mu"].cpu().numpy() - ref["mu"])) <= 1e-9 * scale
+    assert np.max(np.abs(out["sigma"].cpu().numpy() - ref["sigma"])) <= 1e-9 * scale
+    assert int(out["argmax"]) == O.argmax(ref["ei"])
+    out32 = G.score(ctx, m, _t(Xc, torch.float32), prec="fp32")
+    sg = ref["sigma"]
+    ok = sg > 0.1 * scale
+    e_mu = np.max(np.abs(out32["mu"].double().cpu().numpy() - ref["mu"])) / scale
+    e_sg = np.max(np.abs(out32["sigma"].double().cpu().numpy()[ok] - sg[ok]) / sg[ok])
+    assert e_mu <= 1e-4 and e_sg <= 1e-4, (e_mu, e_sg)
+    m.free()
+
+
+def test_append_repeated_point_without_noise_is_not_pd(ctx):
+    """n = 1, signal_var 1, noise 0: K = [1], L = [1]; appending the same
+    configuration gives the pivot 1 - 1 = 0 exactly."""
+    x = np.array([[0.25, 0.75]])
+    m = G.fit(ctx, _t(x), _t([1.0]), [0.5, 0.5], G.KERNEL_SE, 1.0, 0.0)
+    G.append_batched(ctx, [m], _t(x), _t([2.0]))
+    with pytest.raises(G.GpboError) as e:
+        m.status()
+    assert e.value.status == G.E_NOT_PD and e.value.bad_pivot == 1
+    m.free()
+
+
+def test_append_nonfinite_value_is_reported(ctx):
+    X, y = _data(10, 2, 5)
+    m = G.fit(ctx, _t(X[:9]), _t(y[:9]), [0.5, 0.5], G.KERNEL_SE, 1.0, 1e-4)
+    G.append_batched(ctx, [m], _t(X[9:10]), _t([np.nan]))
+    with pytest.raises(G.GpboError) as e:
+        m.status()
+    assert e.value.status == G.E_NONFINITE
+    m.free()
+
+
+def test_append_rejects_bad_arguments(ctx):
+    X, y = _data(6, 2, 8)
+    m = G.fit(ctx, _t(X[:5]), _t(y[:5]), [0.5, 0.5], G.KERNEL_SE, 1.0, 1e-4)
+    with pytest.raises(G.GpboError):
+        G.append_batched(ctx, [m, m], _t(np.zeros((2, 2))), _t([0.0, 0.0]))
+    xs = _t(X[5:6])
+    hs = (G.C.c_void_p * 1)(m.h.value if isinstance(m.h, G.C.c_void_p) else m.h)
+    assert G.lib().gpbo_append_batched(ctx.h, 1, hs, G._ptr(xs), 1, G._ptr(_t([0.0]))) == \
+        G.E_INVALID_ARG  # ldx smaller than d
+    m.free()
+
+
+@pytest.mark.parametrize("dims,seed", [((2, 3), 11), ((4,), 23)])
+def test_driver_picks_equal_oracle_loop(ctx, dims, seed):
+    rng = np.random.default_rng(seed)
+    searches, init, pool_sets = [], [], []
+    for d in dims:
+        searches.append(BO.Search(dims=list(range(d)), lo=np.zeros(d), hi=np.ones(d),
+                                  lengthscale=np.full(d, 0.35), noise_var=1e-4))
+        init.append(rng.uniform(size=(5, d)))
+        pool_sets.append([rng.uniform(size=(256, d)) for _ in range(10 * d - 5)])
+    print(f"driver parity dims={dims}", flush=True)
+    res = BO.run(ctx, searches, lambda b, X: [_objective(x) for x in X], init=init,
+                 pools=lambda t, b: _t(pool_sets[b][t]), prec="fp64")
+    for b, d in enumerate(dims):
+        ref = OBO.search(_objective, init[b], [_objective(x) for x in init[b]], pool_sets[b],
+                         np.full(d, 0.35), O.SE, 1.0, 1e-4)
+        assert min(ref["ei_gap"]) > 1e-6, "seed gives a near-tie; choose another"
+        assert res[b].picks == ref["picks"]
+        np.testing.assert_allclose(res[b].ei_max, ref["ei_max"], rtol=1e-8, atol=1e-14)
+        np.testing.assert_array_equal(res[b].X, ref["X"])
+        assert res[b].X.shape[0] == 10 * d
