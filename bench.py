@@ -584,6 +584,126 @@ def run_c3(args):
     print(json.dumps(res), flush=True)
 
 
+def run_bo(args):
+    """The whole optimisation on the paper's synthetic family (Sec. III-C,
+    Table I case ``--case``): the interdependence analysis plans the searches
+    (Sec. IV-B to IV-D), then every strategy runs its searches to the budget
+    (5 initial configurations, 10 evaluations per parameter) through the
+    batched driver -- one batched scoring call and one batched rank-one
+    update per iteration.  Strategies, as in the paper's Table III:
+    independent (one search per group), merged (the planner's searches) and
+    joint (all 20 parameters in one search).  The parameters a search does
+    not tune stay at the baseline configuration; at the end each strategy's
+    best values are combined into one configuration and F is evaluated there.
+    The metric is search iterations per second (one iteration of one search:
+    its pool scored, its argmax evaluated, its model updated)."""
+    import torch
+    from paper_2403_08131_amd import bo as BO
+    from paper_2403_08131_amd import gpbo as G
+    from paper_2403_08131_amd import inputs as I
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_stream(torch.cuda.Stream(device=dev))
+    ctx = G.Context(0)
+    case = args.case
+    rng = np.random.default_rng(4000 + case)
+    lo, hi = I.PAPER_BOUNDS
+    x0 = I.f32r(rng.uniform(lo, hi, 20))
+    sw = I.sensitivity_sweep(x0)
+    S = G.sensitivity(I.paper_groups(x0, case), I.paper_groups(sw, case))
+    owner = [j // 5 for j in range(20)]
+    _, ps, nsearch = G.plan_searches(S, owner)
+    plans = {
+        "independent": [list(range(5 * g, 5 * g + 5)) for g in range(4)],
+        "merged": [[j for j in range(20) if ps[j] == k] for k in range(nsearch)],
+        "joint": [list(range(20))],
+    }
+    prec = args.prec or "fp32"
+
+    def evaluate_for(dims_list):
+        def ev(b, X):
+            Xf = np.repeat(x0[None, :], X.shape[0], axis=0)
+            Xf[:, dims_list[b]] = X
+            return I.paper_objective(Xf, case)
+        return ev
+
+    out = {}
+    total_iters, total_s = 0, 0.0
+    for name, dims_list in plans.items():
+        searches = [BO.Search(dims=dl, lo=np.full(len(dl), lo), hi=np.full(len(dl), hi),
+                              lengthscale=np.full(len(dl), 25.0), noise_var=1e-4)
+                     for dl in dims_list]
+        ev = evaluate_for(dims_list)
+        if name == "independent":  # warm-up: builds, graphs, allocator pools
+            BO.run(ctx, searches[:1], ev, pool_size=args.pool, prec=prec, seed=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = BO.run(ctx, searches, ev, pool_size=args.pool, prec=prec, seed=case)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        iters = sum(len(r.picks) for r in res)
+        steps = max(len(r.picks) for r in res)
+        xc = x0.copy()
+        for dl, r in zip(dims_list, res):
+            xc[dl] = r.best[0]
+        out[name] = {"searches": [len(dl) for dl in dims_list], "evaluations": sum(r.y.size for r in res),
+                     "F_combined": float(I.paper_objective(xc[None, :], case)[0]),
+                     "best_per_search": [round(r.best[1], 4) for r in res],
+                     "wall_s": dt, "loop_steps": steps, "ms_per_loop_step": dt / steps * 1e3,
+                     "search_iterations": iters}
+        total_iters += iters
+        total_s += dt
+    # the merged plan again with a batched refit instead of the rank-one
+    # update (same pools and picks up to rounding), and the oracle's loop of
+    # its first search on the host
+    dims_list = plans["merged"]
+    searches = [BO.Search(dims=dl, lo=np.full(len(dl), lo), hi=np.full(len(dl), hi),
+                          lengthscale=np.full(len(dl), 25.0), noise_var=1e-4) for dl in dims_list]
+    ev = evaluate_for(dims_list)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rr = BO.run(ctx, searches, ev, pool_size=args.pool, prec=prec, seed=case, update="refit")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    steps = max(len(r.picks) for r in rr)
+    out["merged"]["refit_instead_of_update"] = {
+        "wall_s": dt, "ms_per_loop_step": dt / steps * 1e3,
+        "F_combined_same": bool(np.allclose([r.best[1] for r in rr],
+                                            out["merged"]["best_per_search"], atol=1e-4))}
+    cpu = None
+    if not args.no_cpu:
+        from oracle import bo as OBO
+        from oracle import oracle as O
+        s0 = searches[0]
+        g = np.random.default_rng(7)
+        X0 = g.uniform(lo, hi, size=(5, s0.d))
+        ev0 = lambda x: float(ev(0, x[None, :])[0])
+        pools = [g.uniform(lo, hi, size=(args.pool, s0.d)) for _ in range(10 * s0.d - 5)]
+        t0 = time.perf_counter()
+        OBO.search(ev0, X0, [ev0(x) for x in X0], pools, s0.lengthscale, O.SE, 1.0, 1e-4)
+        tc = time.perf_counter() - t0
+        cpu = {"value": len(pools) / tc, "unit": "search-iterations/s", "cores": cpu_threads(),
+               "kind": "oracle", "cpu": cpu_model(),
+               "sample": f"the oracle's loop (refit, float64 EI over {args.pool} candidates) of the "
+                         f"first planned search, d={s0.d}, {len(pools)} iterations"}
+    res = {
+        "metric": "BO search iterations/s (batched EI scoring + rank-one update per iteration)",
+        "value": total_iters / total_s, "unit": "search-iterations/s", "n_gpus": 1,
+        "steps": sum(v["loop_steps"] for v in out.values()), "warmup": 1,
+        "ms_per_step": total_s / sum(v["loop_steps"] for v in out.values()) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": f"bo: the paper's 20-parameter synthetic family, case {case}; "
+                               f"independent / merged (planned) / joint searches, 5 initial "
+                               f"configurations, 10 evaluations per parameter, pools of {args.pool} "
+                               f"uniform candidates, {prec} scoring",
+                   "case": case, "pool": args.pool, "planned_searches": plans["merged"]},
+        "strategies": out,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -602,6 +722,8 @@ def main():
     ap.add_argument("--k1", type=int, default=65536, help="c4: candidates the network keeps")
     ap.add_argument("--k2", type=int, default=4096, help="c4: candidates the judge scores exactly")
     ap.add_argument("--lr", type=float, default=3e-3, help="c4: Adam learning rate")
+    ap.add_argument("--case", type=int, default=3, help="bo: case of the paper's family (1..5)")
+    ap.add_argument("--pool", type=int, default=4096, help="bo: candidates per search and iteration")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes three times "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -624,6 +746,8 @@ def main():
         return run_c4(args)
     if args.workload == "c3":
         return run_c3(args)
+    if args.workload == "bo":
+        return run_bo(args)
 
     import torch
     from paper_2403_08131_amd import gpbo as G

@@ -67,7 +67,7 @@ def _uniform_pool(gen, m, s: Search, device, dtype):
 
 
 def run(ctx: G.Context, searches, evaluate, n_init=5, evals_per_dim=10, pool_size=4096,
-        prec="fp64", init=None, pools=None, seed=0):
+        prec="fp64", init=None, pools=None, seed=0, update="append"):
     """Run every search to its budget.
 
     evaluate(b, X) -> values: the objective of search b at the rows of X
@@ -77,6 +77,8 @@ def run(ctx: G.Context, searches, evaluate, n_init=5, evals_per_dim=10, pool_siz
     pools(t, b) -> device tensor (m x d_b): optional candidate pool of search
       b at iteration t, float64 for prec "fp64" else float32 (default:
       ``pool_size`` uniform candidates).
+    update: "append" (rank-one update of the fitted models) or "refit" (a
+      batched fit on all observations every iteration; for comparison).
     Returns a list of :class:`Result`, one per search."""
     dev = ctx.device
     B = len(searches)
@@ -119,8 +121,19 @@ def run(ctx: G.Context, searches, evaluate, n_init=5, evals_per_dim=10, pool_siz
                 r.y = np.append(r.y, yn[k])
                 r.picks.append(int(am[k]))
                 r.ei_max.append(float(em[k]))
-            G.append_batched(ctx, [models[b] for b in act], xn,
-                             torch.as_tensor(yn, dtype=torch.float64, device=dev))
+            if update == "append":
+                G.append_batched(ctx, [models[b] for b in act], xn,
+                                 torch.as_tensor(yn, dtype=torch.float64, device=dev))
+            else:
+                for b in act:
+                    models[b].free()
+                    probs[b]["X"] = torch.as_tensor(res[b].X, device=dev).contiguous()
+                    probs[b]["y"] = torch.as_tensor(res[b].y, device=dev).contiguous()
+                st, fresh, status, _ = G.fit_batched(ctx, [probs[b] for b in act])
+                if st != G.OK:
+                    raise G.GpboError(st, f"refit failed: statuses {status}")
+                for k, b in enumerate(act):
+                    models[b] = fresh[k]
         st, status, _ = G.status_batched(ctx, models)
         if st != G.OK:
             raise G.GpboError(st, f"rank-one update failed: statuses {status}")
