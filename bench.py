@@ -634,8 +634,9 @@ def run_bo(args):
                               lengthscale=np.full(len(dl), 25.0), noise_var=1e-4)
                      for dl in dims_list]
         ev = evaluate_for(dims_list)
-        if name == "independent":  # warm-up: builds, graphs, allocator pools
-            BO.run(ctx, searches[:1], ev, pool_size=args.pool, prec=prec, seed=1)
+        # warm-up with other pools: autotuned batched-scoring shapes, captured
+        # launch graphs and allocator pools for this strategy's batch shapes
+        BO.run(ctx, searches, ev, pool_size=args.pool, prec=prec, seed=1000 + case)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = BO.run(ctx, searches, ev, pool_size=args.pool, prec=prec, seed=case)
@@ -723,7 +724,7 @@ def main():
     ap.add_argument("--k2", type=int, default=4096, help="c4: candidates the judge scores exactly")
     ap.add_argument("--lr", type=float, default=3e-3, help="c4: Adam learning rate")
     ap.add_argument("--case", type=int, default=3, help="bo: case of the paper's family (1..5)")
-    ap.add_argument("--pool", type=int, default=4096, help="bo: candidates per search and iteration")
+    ap.add_argument("--pool", type=int, default=65536, help="bo: candidates per search and iteration")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes three times "
                          "(calibrates the HBM byte counters of a profiler run)")

@@ -367,6 +367,18 @@ gpbo_status gpbo_topk_set(gpbo_ctx ctx, int64_t m, const float* v, int64_t k, in
 #define GPBO_TOPK_NOALLOC_SCRATCH (128 * 1024)
 gpbo_status gpbo_topk_noalloc(gpbo_ctx ctx, int64_t m, const float* v, int64_t k, int64_t* idx);
 
+/* The next configuration of each of B searches after a batched scoring call
+ * (the acquisition's choice, Sec. III-A): x_next[b, :d_b] = Xc[b][argmax[b],
+ * :] widened to float64, zero from column d_b to ldx - 1, where d_b is model
+ * b's dimension.  models, m, Xc: as passed to gpbo_score_batched (Xc[b]
+ * float64 for GPBO_FP64, float otherwise).  argmax: device, B int64 (as
+ * gpbo_score_batched writes it); an index outside [0, m[b]) -- the -1 of an
+ * empty pool -- gives a row of NaN.  x_next: device, B x ldx float64,
+ * ldx >= every d_b.  Asynchronous: queue it behind the scoring call and copy
+ * x_next to the host once, instead of reading B rows one by one. */
+gpbo_status gpbo_next_batched(gpbo_ctx ctx, int32_t B, const gpbo_model* models, const int64_t* m,
+                              const void* const* Xc, gpbo_precision prec, const int64_t* argmax,
+                              int32_t ldx, double* x_next);
 /* out[i, :] = Xc[idx[i], :] for i < k (device float arrays, row-major, d
  * columns).  Asynchronous. */
 gpbo_status gpbo_gather_rows(gpbo_ctx ctx, int64_t k, const int64_t* idx, int32_t d,

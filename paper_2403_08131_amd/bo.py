@@ -101,29 +101,42 @@ def run(ctx: G.Context, searches, evaluate, n_init=5, evals_per_dim=10, pool_siz
         raise G.GpboError(st, f"initial fit failed: statuses {status}")
     iters = [max(evals_per_dim * s.d - res[b].X.shape[0], 0) for b, s in enumerate(searches)]
     dmax = max(s.d for s in searches)
+    # per iteration: scoring, the chosen rows and their read-back queued back
+    # to back with one synchronisation; the values go up with the update
+    stream = torch.cuda.current_stream(dev)
+    xn = torch.zeros((B, dmax), dtype=torch.float64, device=dev)
+    yd_new = torch.zeros(B, dtype=torch.float64, device=dev)
+    xh = torch.empty((B, dmax), dtype=torch.float64, pin_memory=True)
+    amh = torch.empty(B, dtype=torch.int64, pin_memory=True)
+    emh = torch.empty(B, dtype=torch.float64, pin_memory=True)
+    yh = torch.empty(B, dtype=torch.float64, pin_memory=True)
     try:
         for t in range(max(iters) if iters else 0):
             act = [b for b in range(B) if t < iters[b]]
+            na = len(act)
+            ma = [models[b] for b in act]
             P = [pools(t, b) if pools is not None else
                  _uniform_pool(gen, pool_size, searches[b], dev, pdt) for b in act]
-            _, am, em = G.score_batched(ctx, [models[b] for b in act], P, prec=prec, want=(),
-                                        host_argmax=True)
-            xn = torch.zeros((len(act), dmax), dtype=torch.float64, device=dev)
+            _, am, em = G.score_batched(ctx, ma, P, prec=prec, want=())
+            G.next_batched(ctx, ma, P, prec, am, xn[:na])
+            xh[:na].copy_(xn[:na], non_blocking=True)
+            amh[:na].copy_(am, non_blocking=True)
+            emh[:na].copy_(em, non_blocking=True)
+            stream.synchronize()
+            xv, amv, emv = xh.numpy(), amh.numpy(), emh.numpy()
+            yv = yh.numpy()
             for k, b in enumerate(act):
-                xn[k, :searches[b].d] = P[k][int(am[k])].to(torch.float64)
-            xh = xn.cpu().numpy()
-            yn = np.empty(len(act))
-            for k, b in enumerate(act):
-                x = xh[k, :searches[b].d].copy()
-                yn[k] = float(np.asarray(evaluate(b, x[None, :]), dtype=np.float64).reshape(-1)[0])
+                x = xv[k, :searches[b].d].copy()
+                yv[k] = float(np.asarray(evaluate(b, x[None, :]), dtype=np.float64).reshape(-1)[0])
                 r = res[b]
                 r.X = np.vstack([r.X, x[None, :]])
-                r.y = np.append(r.y, yn[k])
-                r.picks.append(int(am[k]))
-                r.ei_max.append(float(em[k]))
+                r.y = np.append(r.y, yv[k])
+                r.picks.append(int(amv[k]))
+                r.ei_max.append(float(emv[k]))
             if update == "append":
-                G.append_batched(ctx, [models[b] for b in act], xn,
-                                 torch.as_tensor(yn, dtype=torch.float64, device=dev))
+                # yh is rewritten only after the next iteration's synchronisation
+                yd_new[:na].copy_(yh[:na], non_blocking=True)
+                G.append_batched(ctx, ma, xn[:na], yd_new[:na])
             else:
                 for b in act:
                     models[b].free()

@@ -165,6 +165,40 @@ gpbo_status run_fit(Ctx* c, const FitDesc* h, const FitDesc* dd, int B, hipStrea
   return GPBO_OK;
 }
 
+// The rank-one append's launch sequence (descriptors of the models before
+// and after at dd and dd + B), captured and replayed like the fit's: its
+// grids depend on the padded sizes only, so the iterations of a search
+// replay one graph until its padding fills.
+gpbo_status run_append(Ctx* c, const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
+  std::vector<uint64_t> key = append_launch_shape(h + B, B);
+  key.push_back((uint64_t)(uintptr_t)dd);
+  key.push_back((uint64_t)(uintptr_t)s);
+  if (s != nullptr && !c->no_graph)
+    for (auto& kv : c->fit_graphs)
+      if (kv.first == key) {
+        HIP_TRY(c, hipGraphLaunch(kv.second, s));
+        return GPBO_OK;
+      }
+  launch_append(h, dd, h + B, dd + B, B, s);
+  HIP_TRY(c, hipGetLastError());
+  if (s == nullptr || c->no_graph) return GPBO_OK;
+  constexpr size_t kMaxGraphs = 8;
+  if (c->fit_graphs.size() >= kMaxGraphs) {
+    HIP_TRY(c, hipDeviceSynchronize());
+    (void)hipGraphExecDestroy(c->fit_graphs.front().second);
+    c->fit_graphs.erase(c->fit_graphs.begin());
+  }
+  hipGraph_t graph = nullptr;
+  HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  launch_append(h, dd, h + B, dd + B, B, s);
+  HIP_TRY(c, hipStreamEndCapture(s, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e == hipSuccess) c->fit_graphs.emplace_back(key, exec);
+  return GPBO_OK;
+}
+
 // Per-model slot of the status region at the start of a fit allocation:
 // S_COUNT statistics, then the two info words.
 constexpr size_t STATUS_SLOT = 128;
@@ -902,7 +936,10 @@ gpbo_status gpbo_append_batched(gpbo_ctx c, int32_t B, const gpbo_model* models,
   const FitDesc* dd = (const FitDesc*)c->desc_buf;
   HIP_TRY(c, hipMemcpyAsync(c->desc_buf, hd.data(), hd.size() * sizeof(FitDesc),
                             hipMemcpyHostToDevice, c->stream));
-  launch_append(hd.data(), dd, hd.data() + B, dd + B, B, c->stream);
+  {
+    const gpbo_status st = run_append(c, hd.data(), dd, B, c->stream);
+    if (st != GPBO_OK) return st;
+  }
   // The statistics of the extended models, read when a status is asked for.
   std::shared_ptr<void> sreg = dshared(c, (size_t)B * STATUS_SLOT);
   if (!sreg) return fail(c, GPBO_E_OOM, "status allocation failed");
@@ -1491,6 +1528,30 @@ gpbo_status gpbo_gather_rows(gpbo_ctx c, int64_t k, const int64_t* idx, int32_t 
   if (k == 0) return GPBO_OK;
   DeviceGuard g(c->device);
   launch_gather_rows(k, idx, d, Xc, out, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  return GPBO_OK;
+}
+
+gpbo_status gpbo_next_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, const int64_t* m,
+                              const void* const* Xc, gpbo_precision prec, const int64_t* argmax,
+                              int32_t ldx, double* x_next) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (B < 0 || (B > 0 && (!models || !m || !Xc || !argmax || !x_next)))
+    return fail(c, GPBO_E_INVALID_ARG, "invalid batch arguments");
+  if (prec != GPBO_FP64 && prec != GPBO_FP32 && prec != GPBO_BF16)
+    return fail(c, GPBO_E_INVALID_ARG, "unknown precision %d", (int)prec);
+  if (B == 0) return GPBO_OK;
+  DeviceGuard g(c->device);
+  if (!device_writable(argmax) || !device_writable(x_next))
+    return fail(c, GPBO_E_INVALID_ARG, "argmax and x_next must be device memory");
+  std::vector<int> d(B);
+  for (int b = 0; b < B; ++b) {
+    if (!models[b]) return fail(c, GPBO_E_INVALID_ARG, "model %d is NULL", b);
+    if (m[b] < 0 || (m[b] > 0 && !Xc[b])) return fail(c, GPBO_E_INVALID_ARG, "pool %d is invalid", b);
+    d[b] = models[b]->d;
+    if (ldx < d[b]) return fail(c, GPBO_E_INVALID_ARG, "ldx %d is smaller than model %d's d", ldx, b);
+  }
+  launch_next_rows(B, Xc, m, d.data(), prec == GPBO_FP64 ? 1 : 0, argmax, ldx, x_next, c->stream);
   HIP_TRY(c, hipGetLastError());
   return GPBO_OK;
 }

@@ -1149,12 +1149,14 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
 // alpha = K^-1 ytilde from the inverse factor with one refinement step, the
 // log marginal likelihood and the statistics (the fit's last stage, and the
 // whole recomputation after a rank-one append).
+// The grids depend on the padded sizes only (workgroups past a problem's n
+// return at once), so a search that grows inside its padding replays the
+// same captured sequence.
 void launch_solve(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
-  int nmax = 0, chmax = 1;
+  int chmax = 1;
   int64_t npmax = 0;
   bool any_refine = false;
   for (int b = 0; b < B; ++b) {
-    nmax = std::max(nmax, h[b].n);
     npmax = std::max<int64_t>(npmax, h[b].npad);
     chmax = std::max(chmax, h[b].nchunks);
     any_refine |= h[b].refine != 0;
@@ -1166,7 +1168,7 @@ void launch_solve(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   // alpha = Linv^T (Linv ytilde), then one residual-and-correction step
   hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, -1, (int)V_W, 1);
   hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(64 * TRMV_T_WAVES), 0, s, dd, (int)V_W, -2, 0);
-  const dim3 g_res((unsigned)ceil_div(nmax, KR), (unsigned)chmax, Bz);
+  const dim3 g_res((unsigned)ceil_div(npmax, KR), (unsigned)chmax, Bz);
   hipLaunchKernelGGL(k_residual, g_res, dim3(256), 0, s, dd);
   hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(64 * RESF_W), 0, s, dd, (int)S_RES0, 0);
   hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, (int)V_R, (int)V_W, 0);
@@ -1180,24 +1182,31 @@ void launch_solve(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
 
 namespace gpbo {
 
-void launch_append(const FitDesc* hold, const FitDesc* dold, const FitDesc* hnew,
-                   const FitDesc* dnew, int B, hipStream_t s) {
-  int nmax = 0;
+std::vector<uint64_t> append_launch_shape(const FitDesc* hnew, int B) {
+  int chmax = 1, refine = 0;
   int64_t npmax = 0;
   for (int b = 0; b < B; ++b) {
-    nmax = std::max(nmax, hold[b].n);
-    npmax = std::max<int64_t>(npmax, hold[b].npad);
+    npmax = std::max<int64_t>(npmax, hnew[b].npad);
+    chmax = std::max(chmax, hnew[b].nchunks);
+    refine |= hnew[b].refine != 0;
   }
+  return {0xA99E4Dull, (uint64_t)B, (uint64_t)npmax, (uint64_t)chmax, (uint64_t)refine};
+}
+
+// Grids from the padded sizes only, as in launch_solve (n + 1 <= npad).
+void launch_append(const FitDesc* hold, const FitDesc* dold, const FitDesc* hnew,
+                   const FitDesc* dnew, int B, hipStream_t s) {
+  int64_t npmax = 0;
+  for (int b = 0; b < B; ++b) npmax = std::max<int64_t>(npmax, hold[b].npad);
   const unsigned Bz = (unsigned)B;
-  hipLaunchKernelGGL(k_append_k, dim3((unsigned)ceil_div(std::max(nmax, 1), 256), 1, Bz), dim3(256),
-                     0, s, dold);
+  const unsigned gpad = (unsigned)ceil_div(npmax, 256);
+  hipLaunchKernelGGL(k_append_k, dim3(gpad, 1, Bz), dim3(256), 0, s, dold);
   // l = L^-1 k, v = L^-T l (float64: the old descriptors never refine)
   hipLaunchKernelGGL(k_trmv, dim3((unsigned)ceil_div(npmax, 4), 1, Bz), dim3(256), 0, s, dold,
                      (int)V_W, (int)V_R, 0);
   hipLaunchKernelGGL(k_trmv_t, dim3((unsigned)ceil_div(npmax, TT_COLS), 1, Bz),
                      dim3(64 * TRMV_T_WAVES), 0, s, dold, (int)V_R, (int)V_Q, 0);
-  hipLaunchKernelGGL(k_append_row, dim3((unsigned)ceil_div(nmax + 1, 256), 1, Bz), dim3(256), 0, s,
-                     dold);
+  hipLaunchKernelGGL(k_append_row, dim3(gpad, 1, Bz), dim3(256), 0, s, dold);
   // normalisation over the n + 1 values, then alpha, the LML and statistics
   hipLaunchKernelGGL(k_fit_stats, dim3(1, 1, Bz), dim3(256), 0, s, dnew);
   launch_solve(hnew, dnew, B, s);

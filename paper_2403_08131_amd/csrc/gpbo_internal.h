@@ -228,6 +228,8 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s);
 // dnew the extended models (n + 1; the model's own X, y and refinement).
 void launch_append(const FitDesc* hold, const FitDesc* dold, const FitDesc* hnew,
                    const FitDesc* dnew, int B, hipStream_t s);
+// What that launch sequence depends on besides the descriptor pointers.
+std::vector<uint64_t> append_launch_shape(const FitDesc* hnew, int B);
 // Copy of a fitted model's buffers into larger ones (room for more rows):
 // X, the inverse lengthscales, y and the status slot verbatim, L and L^-1
 // into the wider row stride with the identity beyond the old padding.
@@ -366,6 +368,13 @@ const unsigned* topk_set_threshold(const void* ws);
 bool topk_noalloc_init(int device);
 void* topk_noalloc_scratch(int device);
 size_t topk_noalloc_bytes();
+// Row argmax[b] of pool X[b] (m[b] rows of d[b] columns, float64 when dbl
+// else float32) widened to float64 into row b of out (ldx columns, zero
+// padded; NaN for an index outside the pool).  One launch per NEXT_MAX
+// searches.
+constexpr int NEXT_MAX = 64;
+void launch_next_rows(int B, const void* const* X, const int64_t* m, const int* d, int dbl,
+                      const int64_t* am, int ldx, double* out, hipStream_t s);
 void launch_gather_rows(int64_t k, const int64_t* idx, int d, const float* Xc, float* out,
                         hipStream_t s);
 

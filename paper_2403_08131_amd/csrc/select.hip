@@ -294,6 +294,29 @@ __global__ void k_gather_rows(int64_t k, const int64_t* __restrict__ idx, int d,
   }
 }
 
+// The chosen configuration of each of up to NEXT_MAX searches: row argmax[b]
+// of search b's pool, widened to float64, into row b of out (ldx columns,
+// zero beyond the search's d; a row of NaN for an index outside the pool,
+// such as the -1 of an empty pool).
+struct NextArgs {
+  const void* X[NEXT_MAX];
+  int64_t m[NEXT_MAX];
+  int d[NEXT_MAX];
+};
+__global__ void __launch_bounds__(64) k_next_rows(NextArgs A, int dbl, const int64_t* __restrict__ am,
+                                                  int ldx, double* __restrict__ out) {
+  const int b = blockIdx.x, k = threadIdx.x;
+  const int d = A.d[b];
+  const int64_t i = am[b];
+  for (int c = k; c < ldx; c += 64) {
+    double v = 0.0;
+    if (c < d)
+      v = (i < 0 || i >= A.m[b]) ? __builtin_nan("")
+                : dbl ? ((const double*)A.X[b])[i * d + c] : (double)((const float*)A.X[b])[i * d + c];
+    out[(int64_t)b * ldx + c] = v;
+  }
+}
+
 }  // namespace
 
 int topk_max_k() { return SEL_MAXK; }
@@ -439,6 +462,21 @@ void* topk_noalloc_scratch(int device) {
 }
 
 size_t topk_noalloc_bytes() { return kTopkNoallocBytes; }
+
+void launch_next_rows(int B, const void* const* X, const int64_t* m, const int* d, int dbl,
+                      const int64_t* am, int ldx, double* out, hipStream_t s) {
+  for (int b0 = 0; b0 < B; b0 += NEXT_MAX) {
+    const int nb = std::min(NEXT_MAX, B - b0);
+    NextArgs A{};
+    for (int q = 0; q < nb; ++q) {
+      A.X[q] = X[b0 + q];
+      A.m[q] = m[b0 + q];
+      A.d[q] = d[b0 + q];
+    }
+    hipLaunchKernelGGL(k_next_rows, dim3(nb), dim3(64), 0, s, A, dbl, am + b0, ldx,
+                       out + (int64_t)b0 * ldx);
+  }
+}
 
 void launch_gather_rows(int64_t k, const int64_t* idx, int d, const float* Xc, float* out,
                         hipStream_t s) {

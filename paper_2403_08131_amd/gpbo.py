@@ -73,6 +73,9 @@ _SIGS = {
     "gpbo_model_status": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
                                     C.POINTER(C.c_double)]),
     "gpbo_model_free": (C.c_int, [C.c_void_p]),
+    "gpbo_next_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p),
+                                    C.POINTER(C.c_int64), C.POINTER(C.c_void_p), C.c_int, C.c_void_p,
+                                    C.c_int32, C.c_void_p]),
     "gpbo_append_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p,
                                       C.c_int32, C.c_void_p]),
     "gpbo_model_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
@@ -338,6 +341,20 @@ def append_batched(ctx: Context, models, x_new, y_new):
     ctx.check(lib().gpbo_append_batched(ctx.h, B, hs, _ptr(x_new), int(x_new.shape[1]), _ptr(y_new)))
     for mo in models:
         mo.n += 1
+
+
+def next_batched(ctx: Context, models, Xcs, prec, argmax, out):
+    """gpbo_next_batched: row argmax[b] of pool Xcs[b] into row b of ``out``
+    (device float64, B x ldx), queued on the context's stream."""
+    pr = PREC[prec] if isinstance(prec, str) else int(prec)
+    B = len(models)
+    assert out.dtype == torch.float64 and out.is_contiguous() and out.shape[0] == B
+    assert argmax.dtype == torch.int64 and argmax.is_cuda
+    hs = (C.c_void_p * B)(*[mo.h.value if isinstance(mo.h, C.c_void_p) else mo.h for mo in models])
+    ms = (C.c_int64 * B)(*[x.shape[0] for x in Xcs])
+    xs = (C.c_void_p * B)(*[x.data_ptr() for x in Xcs])
+    ctx.check(lib().gpbo_next_batched(ctx.h, B, hs, ms, xs, pr, _ptr(argmax), int(out.shape[1]),
+                                      _ptr(out)))
 
 
 def status_batched(ctx: Context, models):

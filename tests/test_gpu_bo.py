@@ -179,6 +179,30 @@ def test_append_rejects_bad_arguments(ctx):
     m.free()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_next_batched_gathers_the_chosen_rows(ctx, prec):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    rng = np.random.default_rng(17)
+    models, pools = [], []
+    for d, m in ((2, 50), (5, 300), (3, 1)):
+        X, y = _data(8, d, d)
+        models.append(G.fit(ctx, _t(X), _t(y), [0.5] * d, G.KERNEL_SE, 1.0, 1e-4))
+        pools.append(_t(rng.uniform(size=(m, d)), dt))
+    am = torch.tensor([49, 123, -1], dtype=torch.int64, device=DEV)
+    out = torch.full((3, 6), 7.0, dtype=torch.float64, device=DEV)
+    G.next_batched(ctx, models, pools, prec, am, out)
+    o = out.cpu().numpy()
+    np.testing.assert_array_equal(o[0, :2], pools[0][49].double().cpu().numpy())
+    np.testing.assert_array_equal(o[1, :5], pools[1][123].double().cpu().numpy())
+    assert np.all(np.isnan(o[2, :3]))
+    assert np.all(o[0, 2:] == 0.0) and o[1, 5] == 0.0 and np.all(o[2, 3:] == 0.0)
+    am2 = torch.tensor([50, 0, 0], dtype=torch.int64, device=DEV)  # 50 is outside pool 0
+    G.next_batched(ctx, models, pools, prec, am2, out)
+    assert np.all(np.isnan(out[0, :2].cpu().numpy()))
+    for mo in models:
+        mo.free()
+
+
 @pytest.mark.parametrize("dims,seed", [((2, 3), 11), ((4,), 23)])
 def test_driver_picks_equal_oracle_loop(ctx, dims, seed):
     rng = np.random.default_rng(seed)
