@@ -192,6 +192,79 @@ int oracle_chol_append(int n, const double* L, const double* k, double kappa, do
   return OR_OK;
 }
 
+/*
+ * Gradient of the log marginal likelihood with respect to the log
+ * hyperparameters theta = (log l_1 .. log l_d, log sf2, log sn2), for the
+ * hyperparameter fitting the surrogate's training performs (Sec. IV-D trains
+ * a Gaussian process on each search's evaluations):
+ *   dLML/dtheta_j = 1/2 tr((alpha alpha^T - K^-1) dK/dtheta_j)
+ * (Rasmussen & Williams 2006, eq. 5.9), with ytilde held fixed, and
+ *   dK_il/dlog l_k = [SE]       k_f(r) (x_ik - x_lk)^2 / l_k^2
+ *                    [Matern52] sf2 (5/3) (1 + sqrt5 r) e^{-sqrt5 r} (x_ik - x_lk)^2 / l_k^2
+ *   dK/dlog sf2 = K - sn2 I,      dK/dlog sn2 = sn2 I
+ * (the chain rule through r = |(x_i - x_l) / l| of eqs. 4.9 and 4.17).
+ * K^-1 is formed column by column from the Cholesky factor.  grad has d + 2
+ * entries; *lml receives the log marginal likelihood.  Returns the fit's
+ * status (OR_NOT_PD: no gradient).
+ */
+int oracle_lml_grad(int n, int d, const double* X, const double* y, int kernel, const double* ls,
+                    double sf2, double sn2, int normalize_y, double* grad, double* lml) {
+  double* L = (double*)malloc(sizeof(double) * (size_t)n * n);
+  double* alpha = (double*)malloc(sizeof(double) * n);
+  double stats[5];
+  int bad = -1;
+  int st = oracle_fit(n, d, X, y, kernel, ls, sf2, sn2, normalize_y, L, alpha, stats, &bad);
+  if (st != OR_OK) {
+    free(L);
+    free(alpha);
+    return st;
+  }
+  *lml = stats[3];
+  double* Kinv = (double*)malloc(sizeof(double) * (size_t)n * n);
+  double* e = (double*)malloc(sizeof(double) * n);
+  double* z = (double*)malloc(sizeof(double) * n);
+  double* col = (double*)malloc(sizeof(double) * n);
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i) e[i] = i == j ? 1.0 : 0.0;
+    oracle_forward_sub(n, L, e, z);
+    oracle_back_sub(n, L, z, col);
+    for (int i = 0; i < n; ++i) Kinv[(size_t)i * n + j] = col[i];
+  }
+  for (int j = 0; j < d + 2; ++j) grad[j] = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int l = 0; l < n; ++l) {
+      const double w = alpha[i] * alpha[l] - Kinv[(size_t)i * n + l];
+      const double* xi = X + (size_t)i * d;
+      const double* xl = X + (size_t)l * d;
+      double r2 = 0.0;
+      for (int k = 0; k < d; ++k) {
+        const double t = (xi[k] - xl[k]) / ls[k];
+        r2 += t * t;
+      }
+      const double kf = oracle_kernel(kernel, d, xi, xl, ls, sf2);
+      double dr;  /* dK/d(r^2 / 2) up to the sign: the factor of (x_ik - x_lk)^2 / l_k^2 */
+      if (kernel == OR_SE) {
+        dr = kf;
+      } else {
+        const double r = sqrt(r2);
+        dr = sf2 * (5.0 / 3.0) * (1.0 + sqrt(5.0) * r) * exp(-sqrt(5.0) * r);
+      }
+      for (int k = 0; k < d; ++k) {
+        const double t = (xi[k] - xl[k]) / ls[k];
+        grad[k] += 0.5 * w * dr * t * t;
+      }
+      grad[d] += 0.5 * w * kf;
+      if (i == l) grad[d + 1] += 0.5 * w * sn2;
+    }
+  free(L);
+  free(alpha);
+  free(Kinv);
+  free(e);
+  free(z);
+  free(col);
+  return OR_OK;
+}
+
 /* Expected improvement for minimisation (Jones et al. 1998):
  *   sigma > 0:  EI = (f - mu) Phi(z) + sigma phi(z),  z = (f - mu) / sigma
  *   sigma = 0:  EI = max(f - mu, 0)                                       */

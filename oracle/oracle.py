@@ -69,6 +69,9 @@ def lib():
         L.oracle_back_sub.argtypes = [C.c_int, dp, dp, dp]
         L.oracle_chol_append.restype = C.c_int
         L.oracle_chol_append.argtypes = [C.c_int, dp, dp, C.c_double, dp, ip]
+        L.oracle_lml_grad.restype = C.c_int
+        L.oracle_lml_grad.argtypes = [C.c_int, C.c_int, dp, dp, C.c_int, dp, C.c_double,
+                                      C.c_double, C.c_int, dp, dp]
         L.oracle_fit.restype = C.c_int
         L.oracle_fit.argtypes = [C.c_int, C.c_int, dp, dp, C.c_int, dp, C.c_double,
                                  C.c_double, C.c_int, dp, dp, dp, ip]
@@ -176,6 +179,22 @@ def chol_append(L, k, kappa):
     st = lib().oracle_chol_append(n, pL, pk, float(kappa),
                                   out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(bad))
     return st, out, bad.value
+
+
+def lml_grad(X, y, ls, kind=SE, sf2=1.0, sn2=1e-4, normalize_y=True):
+    """Gradient of the log marginal likelihood with respect to (log l_1..d,
+    log sf2, log sn2) and the LML itself (see oracle_lml_grad).  Returns
+    (status, grad, lml)."""
+    X, px = _d(X)
+    y, py = _d(y)
+    n, d = X.shape
+    ls, pl = _d(np.broadcast_to(np.asarray(ls, dtype=np.float64), (d,)))
+    g = np.zeros(d + 2)
+    lml = C.c_double(np.nan)
+    st = lib().oracle_lml_grad(n, d, px, py, int(kind), pl, float(sf2), float(sn2),
+                               1 if normalize_y else 0, g.ctypes.data_as(C.POINTER(C.c_double)),
+                               C.byref(lml))
+    return st, g, lml.value
 
 
 class Fit:

@@ -40,6 +40,13 @@ MUTATIONS = {
     "bound_min_k": ("if (k > kmax) kmax = k;", "if (kmax == 0.0 || k < kmax) kmax = k;"),
     "append_back_sub": ("oracle_forward_sub(n, L, k, l);", "oracle_back_sub(n, L, k, l);"),
     "append_no_sqrt": ("Lout[(size_t)n * n1 + n] = sqrt(d2);", "Lout[(size_t)n * n1 + n] = d2;"),
+    "grad_double": ("grad[k] += 0.5 * w * dr * t * t;", "grad[k] += w * dr * t * t;"),
+    "grad_kinv_sign": ("const double w = alpha[i] * alpha[l] - Kinv[(size_t)i * n + l];",
+                       "const double w = alpha[i] * alpha[l] + Kinv[(size_t)i * n + l];"),
+    "grad_matern_drop": ("dr = sf2 * (5.0 / 3.0) * (1.0 + sqrt(5.0) * r) * exp(-sqrt(5.0) * r);",
+                         "dr = sf2 * (5.0 / 3.0) * exp(-sqrt(5.0) * r);"),
+    "grad_noise_sf2": ("if (i == l) grad[d + 1] += 0.5 * w * sn2;",
+                       "if (i == l) grad[d + 1] += 0.5 * w * sf2;"),
     "w2_transposed": ("s += rnd(W2[(size_t)h * H + k], bf16) * h1[k];",
                       "s += rnd(W2[(size_t)k * H + h], bf16) * h1[k];"),
 }
@@ -136,17 +143,17 @@ BO_MUTATIONS = {
 }
 
 
-@pytest.mark.slow
-def test_bo_pins_catch_planted_mistakes():
-    """The same check for the loop oracle (oracle/bo.py) and its pins in
-    tests/test_oracle_bo.py."""
-    src = os.path.join(ROOT, "oracle", "bo.py")
+def _python_survivors(module, pins_file, mutations):
+    """Plant each mutation in a copy of oracle/<module> (the rest of the
+    oracle package linked in) and run the pins; returns the mutations no pin
+    caught (the unaltered copy must pass)."""
+    src = os.path.join(ROOT, "oracle", module)
     with open(src) as f:
         text = f.read()
-    pins = os.path.join(ROOT, "tests", "test_oracle_bo.py")
+    pins = os.path.join(ROOT, "tests", pins_file)
     survivors = []
     with tempfile.TemporaryDirectory() as tmp:
-        for name, (old, new) in list(BO_MUTATIONS.items()) + [("clean", ("", ""))]:
+        for name, (old, new) in list(mutations.items()) + [("clean", ("", ""))]:
             pkg = os.path.join(tmp, name, "oracle")
             os.makedirs(pkg)
             open(os.path.join(pkg, "__init__.py"), "w").close()
@@ -154,7 +161,7 @@ def test_bo_pins_catch_planted_mistakes():
                 os.symlink(os.path.join(ROOT, "oracle", aux), os.path.join(pkg, aux))
             if name != "clean":
                 assert text.count(old) >= 1, name
-            with open(os.path.join(pkg, "bo.py"), "w") as f:
+            with open(os.path.join(pkg, module), "w") as f:
                 f.write(text.replace(old, new, 1) if name != "clean" else text)
             env = dict(os.environ, PYTHONPATH=os.path.join(tmp, name) + os.pathsep + ROOT)
             r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
@@ -165,4 +172,29 @@ def test_bo_pins_catch_planted_mistakes():
                 assert r.returncode == 0, r.stdout[-2000:]
             elif r.returncode == 0:
                 survivors.append(name)
+    return survivors
+
+
+@pytest.mark.slow
+def test_bo_pins_catch_planted_mistakes():
+    """The same check for the loop oracle (oracle/bo.py) and its pins in
+    tests/test_oracle_bo.py."""
+    survivors = _python_survivors("bo.py", "test_oracle_bo.py", BO_MUTATIONS)
     assert not survivors, f"bo pins did not catch: {survivors}"
+
+
+HYPER_MUTATIONS = {
+    "adam_descent": ("th = np.clip(th + lr * mh", "th = np.clip(th - lr * mh"),
+    "no_bias_correction": ("mh = m / (1.0 - beta1 ** t)", "mh = m"),
+    "jitter_starts_high": ("sf2 * jitter0 * 10.0 ** (k - 1)", "sf2 * jitter0 * 10.0 ** k"),
+    "noise_grad_unscaled": ("g[d + 1] *= sn2 / (sn2 + jit)", "g[d + 1] *= 1.0"),
+    "best_is_min": ('if r["lml"] > res[best]["lml"]:', 'if r["lml"] < res[best]["lml"]:'),
+}
+
+
+@pytest.mark.slow
+def test_hyper_pins_catch_planted_mistakes():
+    """The same check for the hyperparameter-fitting oracle (oracle/hyper.py)
+    and its pins in tests/test_oracle_hyper.py."""
+    survivors = _python_survivors("hyper.py", "test_oracle_hyper.py", HYPER_MUTATIONS)
+    assert not survivors, f"hyper pins did not catch: {survivors}"

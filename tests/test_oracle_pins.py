@@ -175,6 +175,37 @@ def test_chol_append_n0_is_sqrt_and_not_pd_reports_new_index():
     assert st == O.OK and np.array_equal(La, np.array([[2.0, 0.0], [1.0, 1.0]]))
 
 
+@pytest.mark.parametrize("kind", [O.SE, O.MATERN52])
+@pytest.mark.parametrize("normalize", [True, False])
+def test_lml_gradient_central_differences(kind, normalize):
+    """dLML/dlog(theta) against central differences of the (separately pinned)
+    log marginal likelihood, including the noise and signal terms."""
+    rng = np.random.default_rng(71 + kind)
+    X = rng.uniform(size=(14, 3))
+    y = np.sin(4.0 * X[:, 0]) + X[:, 1] ** 2 + 0.1 * rng.standard_normal(14)
+    th = np.log([0.4, 0.7, 1.1, 1.3, 2e-2])
+
+    def lml(t):
+        return O.fit(X, y, np.exp(t[:3]), kind, np.exp(t[3]), np.exp(t[4]), normalize).lml
+
+    st, g, l0 = O.lml_grad(X, y, np.exp(th[:3]), kind, np.exp(th[3]), np.exp(th[4]), normalize)
+    assert st == O.OK and l0 == lml(th)
+    h = 1e-5
+    fd = np.array([(lml(th + h * e) - lml(th - h * e)) / (2 * h) for e in np.eye(5)])
+    np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-7)
+
+
+def test_lml_gradient_n1_closed_form():
+    """n = 1, centred only: LML = -y~^2 / (2 s) - log(s) / 2 - log(2 pi) / 2 with
+    s = sf2 + sn2 and y~ = 0, so dLML/dlog sf2 = -sf2 / (2 s), dLML/dlog sn2 =
+    -sn2 / (2 s), and the lengthscales do not enter."""
+    st, g, l0 = O.lml_grad(np.array([[0.3, 0.9]]), np.array([2.0]), [0.5, 0.5], O.SE, 1.5, 0.5,
+                           False)
+    assert st == O.OK
+    np.testing.assert_allclose(g, [0.0, 0.0, -1.5 / 4.0, -0.5 / 4.0], rtol=1e-15, atol=0)
+    assert l0 == pytest.approx(-0.5 * np.log(2.0) - 0.5 * np.log(2 * np.pi), rel=1e-15)
+
+
 def test_triangular_solves_residual():
     K = _spd(9, 11)
     _, L, _ = O.cholesky(K)
