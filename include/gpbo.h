@@ -251,6 +251,56 @@ gpbo_status gpbo_fit_batched(gpbo_ctx ctx, int32_t B, const gpbo_problem* probs,
 gpbo_status gpbo_append_batched(gpbo_ctx ctx, int32_t B, const gpbo_model* models,
                                 const double* x_new, int32_t ldx, const double* y_new);
 
+/* ---------------------------------------------------------------------- */
+/* Hyperparameter fitting (the surrogate's training, Sec. IV-D).            */
+/* ---------------------------------------------------------------------- */
+/* Gradient of the log marginal likelihood of B fitted models with respect to
+ * theta = (log l_1 .. log l_d, log signal_var, log noise_var), with the
+ * normalised y held fixed:
+ *   dLML/dtheta_j = 1/2 tr((alpha alpha^T - K^-1) dK/dtheta_j)
+ * (Rasmussen & Williams 2006, eq. 5.9), K^-1 = L^-T L^-1 formed tile by tile
+ * in float64 from the model's inverse factor.  grad: device, B x ldg float64
+ * (ldg >= every d + 2; zero beyond d + 2; a row of NaN for a model whose fit
+ * failed).  lml: device, B float64 (the models' log marginal likelihoods;
+ * may be NULL).  Asynchronous. */
+gpbo_status gpbo_lml_grad_batched(gpbo_ctx ctx, int32_t B, const gpbo_model* models, int32_t ldg,
+                                  double* grad, double* lml);
+
+/* Options of gpbo_fit_hyper_batched. */
+typedef struct {
+  int32_t starts;   /* starting points per problem (>= 1) */
+  int32_t steps;    /* Adam steps per start (>= 0) */
+  double lr;        /* Adam step size in log space (beta1 0.9, beta2 0.999, eps 1e-8) */
+  double jitter0;   /* first jitter, in units of signal_var (> 0; 1e-8 is usual) */
+  int32_t retries;  /* jitter escalations (x10 each) before a start is abandoned */
+} gpbo_hyper_opts;
+
+/* Fit the hyperparameters of B problems by maximising the log marginal
+ * likelihood from opts->starts starting points each: every start takes
+ * opts->steps Adam steps (Kingma & Ba 2015) up gpbo_lml_grad_batched's
+ * gradient, clipped to [lo, hi] after each step; all starts of all problems
+ * are fitted in one batched call per step.  A fit that is not positive
+ * definite is repeated with signal_var * jitter0 * 10^(k-1) added to the
+ * noise variance, k = 1 .. retries (the log-noise derivative stays that of
+ * the noise variance itself); a start whose retries all fail is abandoned.
+ * After the last step each start's LML is evaluated the same way and the
+ * largest wins (lowest start index among ties).
+ * probs: host, B problems; X and y (device) as for gpbo_fit, kernel,
+ *   normalize_y and refine_alpha used, lengthscale / signal_var / noise_var
+ *   ignored.
+ * theta0: host, B x starts x ldt (start s of problem b at row b*starts+s).
+ * lo, hi: host, B x ldt bounds of theta (finite, lo <= hi).  ldt >= d + 2.
+ * theta (host, B x ldt), lml (host, B), jitter (host, B, may be NULL): the
+ *   winning start's hyperparameters, LML and the jitter its last fit needed.
+ * out (host, B, may be NULL): models fitted at the winning hyperparameters
+ *   (noise_var + jitter); free them with gpbo_model_free.
+ * status (host, B): GPBO_OK, or GPBO_E_NOT_PD when every start was abandoned.
+ * SYNCHRONISES once or twice per step.  Returns the first failing status. */
+gpbo_status gpbo_fit_hyper_batched(gpbo_ctx ctx, int32_t B, const gpbo_problem* probs,
+                                   const gpbo_hyper_opts* opts, const double* theta0,
+                                   const double* lo, const double* hi, int32_t ldt, double* theta,
+                                   double* lml, double* jitter, gpbo_model* out, int32_t* status);
+
 /* Release a model (NULL is ignored).  Work still queued that uses it may
  * run on: with a context allocator the buffers go back in the order of the
  * stream they were allocated on, without a wait, when that is the stream

@@ -1733,4 +1733,255 @@ gpbo_status gpbo_mlp_prescreen_lcb(gpbo_ctx c, gpbo_mlp mlp, int64_t m, const fl
   return prescreen(c, mlp, m, Xc, true, kappa, k, topk_idx, score_out);
 }
 
+gpbo_status gpbo_lml_grad_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, int32_t ldg,
+                                  double* grad, double* lml) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (B < 0 || (B > 0 && (!models || !grad)))
+    return fail(c, GPBO_E_INVALID_ARG, "invalid batch arguments");
+  if (B == 0) return GPBO_OK;
+  DeviceGuard g(c->device);
+  if (!device_writable(grad) || (lml && !device_writable(lml)))
+    return fail(c, GPBO_E_INVALID_ARG, "grad and lml must be device memory");
+  std::vector<FitDesc> hd(B);
+  for (int b = 0; b < B; ++b) {
+    Model* M = models[b];
+    if (!M) return fail(c, GPBO_E_INVALID_ARG, "model %d is NULL", b);
+    if (M->ctx != c) return fail(c, GPBO_E_INVALID_ARG, "model %d belongs to another context", b);
+    if (ldg < M->d + 2)
+      return fail(c, GPBO_E_INVALID_ARG, "ldg %d is smaller than model %d's d + 2", ldg, b);
+    hd[b] = make_fit_desc(M, M->X64, M->il64, M->y64, M->normalize, M->refine);
+  }
+  {
+    const gpbo_status st = ensure_desc(c, hd.size() * sizeof(FitDesc));
+    if (st != GPBO_OK) return st;
+  }
+  int ldp = 0;
+  int64_t ts = 0;
+  const size_t nd = lml_grad_part_doubles(hd.data(), B, &ldp, &ts);
+  {
+    const gpbo_status st = ensure_red(c, nd * sizeof(double));
+    if (st != GPBO_OK) return st;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->desc_buf, hd.data(), hd.size() * sizeof(FitDesc),
+                            hipMemcpyHostToDevice, c->stream));
+  launch_lml_grad(hd.data(), (const FitDesc*)c->desc_buf, B, (double*)c->red, ldg, grad, lml,
+                  c->stream);
+  HIP_TRY(c, hipGetLastError());
+  for (int b = 0; b < B; ++b) note_stream(models[b], c->stream);
+  return GPBO_OK;
+}
+
+gpbo_status gpbo_fit_hyper_batched(gpbo_ctx c, int32_t B, const gpbo_problem* probs,
+                                   const gpbo_hyper_opts* o, const double* theta0, const double* lo,
+                                   const double* hi, int32_t ldt, double* theta, double* lml,
+                                   double* jitter, gpbo_model* out, int32_t* status) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (B < 0 || (B > 0 && (!probs || !o || !theta0 || !lo || !hi || !theta || !lml || !status)))
+    return fail(c, GPBO_E_INVALID_ARG, "invalid batch arguments");
+  if (o && (o->starts < 1 || o->steps < 0 || !(o->lr > 0.0) || o->retries < 0 ||
+            !(o->jitter0 > 0.0)))
+    return fail(c, GPBO_E_INVALID_ARG, "invalid optimiser options");
+  if (B == 0) return GPBO_OK;
+  DeviceGuard g(c->device);
+  const int S = o->starts, N = B * S;
+  for (int b = 0; b < B; ++b) {
+    const gpbo_problem& p = probs[b];
+    if (out) out[b] = nullptr;
+    if (p.n <= 0 || p.d <= 0 || p.d > 64 || p.n > 65536 || !p.X || !p.y ||
+        (p.kernel != GPBO_KERNEL_SE && p.kernel != GPBO_KERNEL_MATERN52))
+      return fail(c, GPBO_E_INVALID_ARG, "problem %d is invalid", b);
+    if (ldt < p.d + 2) return fail(c, GPBO_E_INVALID_ARG, "ldt %d is smaller than d + 2", ldt);
+    for (int j = 0; j < p.d + 2; ++j)
+      if (!(lo[(size_t)b * ldt + j] <= hi[(size_t)b * ldt + j]) ||
+          !std::isfinite(lo[(size_t)b * ldt + j]) || !std::isfinite(hi[(size_t)b * ldt + j]))
+        return fail(c, GPBO_E_INVALID_ARG, "bounds of problem %d are invalid", b);
+  }
+  // run r = b * S + s: start s of problem b
+  std::vector<std::vector<double>> th(N), mo(N), ve(N);
+  std::vector<char> alive(N, 1);
+  std::vector<double> fin_lml(N, -INFINITY), fin_jit(N, NAN);
+  for (int r = 0; r < N; ++r) {
+    const int b = r / S, d = probs[b].d;
+    th[r].resize(d + 2);
+    mo[r].assign(d + 2, 0.0);
+    ve[r].assign(d + 2, 0.0);
+    for (int j = 0; j < d + 2; ++j) {
+      const double v = theta0[((size_t)b * S + (r % S)) * ldt + j];
+      th[r][j] = std::min(std::max(v, lo[(size_t)b * ldt + j]), hi[(size_t)b * ldt + j]);
+    }
+  }
+  int ldg = 2;
+  for (int b = 0; b < B; ++b) ldg = std::max(ldg, probs[b].d + 2);
+  std::shared_ptr<void> gbuf = dshared(c, (size_t)N * (ldg + 1) * sizeof(double));
+  if (!gbuf) return fail(c, GPBO_E_OOM, "gradient buffer allocation failed");
+  double* g_dev = (double*)gbuf.get();
+  double* l_dev = g_dev + (size_t)N * ldg;
+  std::vector<double> g_h((size_t)N * ldg), l_h(N);
+  // Gradient and LML of the runs in `rs` at their theta, with the jitter
+  // policy: a fit that is not positive definite is repeated with
+  // sf2 * jitter0 * 10^(k-1) added to the noise, k = 1 .. retries.  Returns
+  // per run OK (grad in g_h row r, lml, jitter) or the last failure.
+  std::vector<double> jit_r(N, 0.0);
+  std::vector<int32_t> st_r(N, GPBO_OK);
+  auto evaluate = [&](const std::vector<int>& rs) -> gpbo_status {
+    std::vector<int> pend = rs;
+    std::vector<Model*> ok_m;
+    std::vector<int> ok_r;
+    for (int k = 0; k <= o->retries && !pend.empty(); ++k) {
+      const int np = (int)pend.size();
+      std::vector<gpbo_problem> pp(np);
+      std::vector<std::vector<double>> ls(np);
+      std::vector<Model*> ms(np);
+      std::vector<int32_t> st(np, GPBO_OK);
+      for (int q = 0; q < np; ++q) {
+        const int r = pend[q], b = r / S, d = probs[b].d;
+        ls[q].resize(d);
+        for (int j = 0; j < d; ++j) ls[q][j] = std::exp(th[r][j]);
+        const double sf2 = std::exp(th[r][d]), sn2 = std::exp(th[r][d + 1]);
+        jit_r[r] = k == 0 ? 0.0 : sf2 * o->jitter0 * std::pow(10.0, k - 1);
+        pp[q] = probs[b];
+        pp[q].lengthscale = ls[q].data();
+        pp[q].signal_var = sf2;
+        pp[q].noise_var = sn2 + jit_r[r];
+        ms[q] = new (std::nothrow) gpbo_model_s();
+        if (!ms[q]) st[q] = GPBO_E_OOM;
+      }
+      const gpbo_status gst = fit_group(c, np, pp.data(), ms.data(), st.data(), true);
+      std::vector<int> next;
+      for (int q = 0; q < np; ++q) {
+        const int r = pend[q];
+        gpbo_status s = gst != GPBO_OK && st[q] == GPBO_OK ? gst : (gpbo_status)st[q];
+        if (s == GPBO_OK && ms[q]) s = fit_status(c, ms[q], nullptr);
+        st_r[r] = s;
+        if (s == GPBO_OK) {
+          ok_m.push_back(ms[q]);
+          ok_r.push_back(r);
+          continue;
+        }
+        if (ms[q]) {
+          free_model_buffers(ms[q]);
+          delete ms[q];
+        }
+        if (s == GPBO_E_NOT_PD) next.push_back(r);
+      }
+      pend.swap(next);
+    }
+    gpbo_status res = GPBO_OK;
+    if (!ok_m.empty()) {
+      const int nk = (int)ok_m.size();
+      res = gpbo_lml_grad_batched(c, nk, (const gpbo_model*)ok_m.data(), ldg, g_dev, l_dev);
+      if (res == GPBO_OK) {
+        HIP_TRY(c, hipMemcpyAsync(g_h.data(), g_dev, (size_t)nk * ldg * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(l_h.data(), l_dev, (size_t)nk * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+      }
+      // rows of g_h / l_h in ok order move to the runs' slots below
+      std::vector<double> gg((size_t)nk * ldg), ll(nk);
+      std::copy(g_h.begin(), g_h.begin() + (size_t)nk * ldg, gg.begin());
+      std::copy(l_h.begin(), l_h.begin() + nk, ll.begin());
+      for (int q = 0; q < nk; ++q) {
+        const int r = ok_r[q], d = probs[r / S].d;
+        const double sn2 = std::exp(th[r][d + 1]);
+        for (int j = 0; j < ldg; ++j) g_h[(size_t)r * ldg + j] = gg[(size_t)q * ldg + j];
+        // the derivative with respect to log sn2, not the jittered variance
+        g_h[(size_t)r * ldg + d + 1] *= sn2 / (sn2 + jit_r[r]);
+        l_h[r] = ll[q];
+        free_model_buffers(ok_m[q]);
+        delete ok_m[q];
+      }
+    }
+    return res;
+  };
+  // g_h / l_h are indexed by run after evaluate (it needs N rows)
+  g_h.resize((size_t)std::max(N, 1) * ldg);
+  l_h.resize(std::max(N, 1));
+  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  for (int t = 1; t <= o->steps; ++t) {
+    std::vector<int> rs;
+    for (int r = 0; r < N; ++r)
+      if (alive[r]) rs.push_back(r);
+    if (rs.empty()) break;
+    {
+      const gpbo_status st = evaluate(rs);
+      if (st != GPBO_OK) return st;
+    }
+    for (int r : rs) {
+      if (st_r[r] != GPBO_OK) {
+        alive[r] = 0;
+        continue;
+      }
+      const int b = r / S, d = probs[b].d;
+      const double c1 = 1.0 - std::pow(b1, t), c2 = 1.0 - std::pow(b2, t);
+      for (int j = 0; j < d + 2; ++j) {
+        const double gj = g_h[(size_t)r * ldg + j];
+        mo[r][j] = b1 * mo[r][j] + (1.0 - b1) * gj;
+        ve[r][j] = b2 * ve[r][j] + (1.0 - b2) * gj * gj;
+        const double mh = mo[r][j] / c1, vh = ve[r][j] / c2;
+        const double v = th[r][j] + o->lr * mh / (std::sqrt(vh) + eps);
+        th[r][j] = std::min(std::max(v, lo[(size_t)b * ldt + j]), hi[(size_t)b * ldt + j]);
+      }
+    }
+  }
+  {
+    std::vector<int> rs;
+    for (int r = 0; r < N; ++r)
+      if (alive[r]) rs.push_back(r);
+    if (!rs.empty()) {
+      const gpbo_status st = evaluate(rs);
+      if (st != GPBO_OK) return st;
+    }
+    for (int r : rs)
+      if (st_r[r] == GPBO_OK) {
+        fin_lml[r] = l_h[r];
+        fin_jit[r] = jit_r[r];
+      }
+  }
+  gpbo_status first = GPBO_OK;
+  std::vector<int> best_r(B);
+  for (int b = 0; b < B; ++b) {
+    int best = b * S;
+    for (int s = 1; s < S; ++s)
+      if (fin_lml[b * S + s] > fin_lml[best]) best = b * S + s;
+    best_r[b] = best;
+    const int d = probs[b].d;
+    for (int j = 0; j < ldt; ++j) theta[(size_t)b * ldt + j] = j < d + 2 ? th[best][j] : 0.0;
+    lml[b] = fin_lml[best];
+    if (jitter) jitter[b] = fin_jit[best];
+    status[b] = std::isfinite(fin_lml[best]) ? GPBO_OK : GPBO_E_NOT_PD;
+    if (status[b] != GPBO_OK && first == GPBO_OK) first = (gpbo_status)status[b];
+  }
+  if (out) {  // the models at the chosen hyperparameters (with their jitter)
+    std::vector<gpbo_problem> pp;
+    std::vector<std::vector<double>> ls;
+    std::vector<int> idx;
+    for (int b = 0; b < B; ++b)
+      if (status[b] == GPBO_OK) idx.push_back(b);
+    ls.resize(idx.size());
+    for (size_t q = 0; q < idx.size(); ++q) {
+      const int b = idx[q], d = probs[b].d;
+      ls[q].resize(d);
+      for (int j = 0; j < d; ++j) ls[q][j] = std::exp(theta[(size_t)b * ldt + j]);
+      gpbo_problem p = probs[b];
+      p.lengthscale = ls[q].data();
+      p.signal_var = std::exp(theta[(size_t)b * ldt + d]);
+      p.noise_var = std::exp(theta[(size_t)b * ldt + d + 1]) + fin_jit[best_r[b]];
+      pp.push_back(p);
+    }
+    if (!pp.empty()) {
+      std::vector<gpbo_model> om(pp.size(), nullptr);
+      std::vector<int32_t> os(pp.size(), GPBO_OK);
+      const gpbo_status st = gpbo_fit_batched(c, (int32_t)pp.size(), pp.data(), om.data(), nullptr,
+                                              os.data());
+      for (size_t q = 0; q < idx.size(); ++q) {
+        out[idx[q]] = om[q];
+        if (os[q] != GPBO_OK) status[idx[q]] = os[q];
+      }
+      if (st != GPBO_OK && first == GPBO_OK) first = st;
+    }
+  }
+  return first;
+}
+
 }  // extern "C"

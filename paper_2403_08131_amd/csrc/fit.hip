@@ -1054,6 +1054,150 @@ __global__ void __launch_bounds__(64) k_status_copy(const FitDesc* __restrict__ 
   if (t < 2) inf[t] = P.info[t];
 }
 
+// ---------------------------------------------------------------------------
+// Gradient of the log marginal likelihood in the log hyperparameters
+// theta = (log l_1 .. log l_d, log sf2, log sn2) of fitted models:
+//   dLML/dtheta_j = 1/2 sum_il W_il dK_il/dtheta_j,   W = alpha alpha^T - K^-1,
+//   dK_il/dlog l_k = g(r_il) (x_ik - x_lk)^2 / l_k^2  with g = k_f (SE) or
+//                    sf2 (5/3)(1 + sqrt5 r) e^{-sqrt5 r} (Matern-5/2),
+//   dK/dlog sf2 = k_f,  dK/dlog sn2 = sn2 I.
+// Workgroup (tile, model) takes the 64 x 64 tile (I, J), J <= I, of the
+// symmetric W: K^-1 = L^-T L^-1 on that tile is sum_{k >= 64 I} Linv[k, i]
+// Linv[k, l] (the inverse factor is lower triangular), accumulated in float64
+// from 16-row slabs of Linv staged in LDS, each thread owning 4 x 4 entries.
+// The tile's d + 2 sums (off-diagonal tiles counted twice) go to
+// part[model][tile][j]; a second kernel adds the tiles in order.
+// ---------------------------------------------------------------------------
+constexpr int GK = 16;  // Linv rows per slab
+inline size_t grad_lds_bytes(int dmax) {
+  return (size_t)(2 * GK * NB + 2 * NB * (dmax + 1) + 4 * (dmax + 2) + 8) * sizeof(double);
+}
+
+__global__ void __launch_bounds__(256) k_lml_grad_tiles(const FitDesc* __restrict__ Ds, int ldp,
+                                                        int64_t tstride, double* __restrict__ part) {
+  extern __shared__ __align__(16) double gsm[];
+  const FitDesc& P = Ds[blockIdx.z];
+  const int n = P.n, d = P.d, npad = P.npad, t = threadIdx.x, lane = t % 64, wave = t / 64;
+  const int nb = npad / NB;
+  const int tile = blockIdx.x;
+  if (tile >= nb * (nb + 1) / 2 || fit_failed(P.info)) return;
+  int I, J;
+  tri_index(tile, I, J);
+  const int ds = d + 1;  // LDS row stride of the staged coordinates
+  double* A = gsm;                  // [GK][NB] Linv[k, 64 I + a]
+  double* Bm = A + GK * NB;         // [GK][NB] Linv[k, 64 J + c]
+  double* xi = Bm + GK * NB;        // [NB][ds] scaled coordinates of the tile's rows
+  double* xl = xi + NB * ds;        // [NB][ds] ... of its columns
+  double* red = xl + NB * ds;       // [4][d + 2]
+  const int i0 = I * NB, l0 = J * NB;
+  for (int e = t; e < NB * d; e += 256) {
+    const int r = e / d, k = e % d;
+    xi[r * ds + k] = i0 + r < n ? P.X[(int64_t)(i0 + r) * d + k] * P.il[k] : 0.0;
+    xl[r * ds + k] = l0 + r < n ? P.X[(int64_t)(l0 + r) * d + k] * P.il[k] : 0.0;
+  }
+  for (int e = t; e < 4 * (d + 2); e += 256) red[e] = 0.0;
+  const int ra = (t / 16) * 4, ca = (t % 16) * 4;  // this thread's 4 x 4 block of the tile
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int k0 = i0; k0 < n; k0 += GK) {
+    __syncthreads();
+    for (int e = t; e < GK * NB; e += 256) {
+      const int kk = e / NB, c = e % NB, k = k0 + kk;
+      A[e] = k < n ? P.Linv[(int64_t)k * npad + i0 + c] : 0.0;
+      Bm[e] = k < n ? P.Linv[(int64_t)k * npad + l0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < GK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = A[kk * NB + ra + u];
+        b[u] = Bm[kk * NB + ca + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    }
+  }
+  // W and the kernel factors of the thread's 16 entries
+  double base[4][4];
+  double gsf = 0.0, gsn = 0.0;
+  const double s5 = 2.23606797749978969641;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + ra + u, l = l0 + ca + v;
+      base[u][v] = 0.0;
+      if (i < n && l < n) {
+        const double w = P.alpha[i] * P.alpha[l] - acc[u][v];
+        double r2 = 0.0;
+        for (int k = 0; k < d; ++k) {
+          const double q = xi[(ra + u) * ds + k] - xl[(ca + v) * ds + k];
+          r2 = fma(q, q, r2);
+        }
+        const double kf = cov_r2(P.kernel, r2, P.sf2);
+        double g;
+        if (P.kernel == GPBO_KERNEL_SE) {
+          g = kf;
+        } else {
+          const double r = sqrt(r2);
+          g = P.sf2 * (5.0 / 3.0) * (1.0 + s5 * r) * exp(-s5 * r);
+        }
+        base[u][v] = w * g;
+        gsf = fma(w, kf, gsf);
+        if (i == l) gsn = fma(w, P.sn2, gsn);
+      }
+    }
+  const double wt = I == J ? 1.0 : 2.0;  // the mirrored tile above the diagonal
+  for (int k = 0; k < d + 2; ++k) {
+    double v = 0.0;
+    if (k < d) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double q = xi[(ra + u) * ds + k] - xl[(ca + c) * ds + k];
+          v = fma(base[u][c], q * q, v);
+        }
+    } else {
+      v = k == d ? gsf : gsn;
+    }
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) red[wave * (d + 2) + k] = v;
+  }
+  __syncthreads();
+  for (int k = t; k < d + 2; k += 256) {
+    const double v = (red[k] + red[(d + 2) + k]) + (red[2 * (d + 2) + k] + red[3 * (d + 2) + k]);
+    part[(int64_t)blockIdx.z * tstride + (int64_t)tile * ldp + k] = wt * v;
+  }
+}
+
+// grad[b][j] = 1/2 sum over the tiles (in tile order) of part[b][tile][j];
+// lml[b] from the fit's statistics.  NaN for a model whose fit failed.
+__global__ void __launch_bounds__(64) k_lml_grad_finish(const FitDesc* __restrict__ Ds, int ldp,
+                                                        int64_t tstride,
+                                                        const double* __restrict__ part, int ldg,
+                                                        double* __restrict__ grad,
+                                                        double* __restrict__ lml) {
+  const FitDesc& P = Ds[blockIdx.x];
+  const int nb = P.npad / NB, nt = nb * (nb + 1) / 2;
+  const bool failed = fit_failed(P.info);
+  for (int j = threadIdx.x; j < ldg; j += 64) {
+    double s = 0.0;
+    if (j < P.d + 2 && !failed)
+      for (int q = 0; q < nt; ++q) s += part[(int64_t)blockIdx.x * tstride + (int64_t)q * ldp + j];
+    grad[(int64_t)blockIdx.x * ldg + j] =
+        failed ? __builtin_nan("") : (j < P.d + 2 ? 0.5 * s : 0.0);
+  }
+  if (lml && threadIdx.x == 0) lml[blockIdx.x] = failed ? __builtin_nan("") : P.stats[S_LML];
+}
+
 // The two-tile kernels stage 2 x 64 x 66 doubles (66 KiB) of dynamic LDS;
 // the update kernel takes the diagonal step's 76.5 KiB.
 void allow_tile_lds() {
@@ -1220,6 +1364,44 @@ void launch_grow(const GrowDesc* dd, int B, int np_new_max, hipStream_t s) {
 
 void launch_status_copy(const FitDesc* dd, int B, unsigned char* out, int slot, hipStream_t s) {
   hipLaunchKernelGGL(k_status_copy, dim3((unsigned)B), dim3(64), 0, s, dd, out, slot);
+}
+
+}  // namespace gpbo
+
+namespace gpbo {
+
+size_t lml_grad_part_doubles(const FitDesc* h, int B, int* ldp, int64_t* tstride) {
+  int dmax = 1, nbmax = 1;
+  for (int b = 0; b < B; ++b) {
+    dmax = std::max(dmax, h[b].d);
+    nbmax = std::max(nbmax, h[b].npad / NB);
+  }
+  *ldp = dmax + 2;
+  *tstride = (int64_t)(nbmax * (nbmax + 1) / 2) * (dmax + 2);
+  return (size_t)B * (size_t)*tstride;
+}
+
+void launch_lml_grad(const FitDesc* h, const FitDesc* dd, int B, double* part, int ldg,
+                     double* grad, double* lml, hipStream_t s) {
+  int ldp = 0;
+  int64_t tstride = 0;
+  (void)lml_grad_part_doubles(h, B, &ldp, &tstride);
+  int dmax = 1, nbmax = 1;
+  for (int b = 0; b < B; ++b) {
+    dmax = std::max(dmax, h[b].d);
+    nbmax = std::max(nbmax, h[b].npad / NB);
+  }
+  const size_t sm = grad_lds_bytes(dmax);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_lml_grad_tiles,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)grad_lds_bytes(64));
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_lml_grad_tiles, dim3((unsigned)(nbmax * (nbmax + 1) / 2), 1, (unsigned)B),
+                     dim3(256), sm, s, dd, ldp, tstride, part);
+  hipLaunchKernelGGL(k_lml_grad_finish, dim3((unsigned)B), dim3(64), 0, s, dd, ldp, tstride,
+                     (const double*)part, ldg, grad, lml);
 }
 
 }  // namespace gpbo

@@ -241,6 +241,13 @@ struct GrowDesc {
   int* info2;
 };
 void launch_grow(const GrowDesc* dd, int B, int np_new_max, hipStream_t s);
+// Gradient of the log marginal likelihood in (log l_1..d, log sf2, log sn2)
+// of B fitted models: per-tile partial sums (lml_grad_part_doubles doubles of
+// scratch) reduced in order into grad (B x ldg, zero beyond d + 2, NaN rows
+// for failed fits) and lml (B, may be null).
+size_t lml_grad_part_doubles(const FitDesc* h, int B, int* ldp, int64_t* tstride);
+void launch_lml_grad(const FitDesc* h, const FitDesc* dd, int B, double* part, int ldg,
+                     double* grad, double* lml, hipStream_t s);
 // Each model's statistics and info words into out + b * slot.
 void launch_status_copy(const FitDesc* dd, int B, unsigned char* out, int slot, hipStream_t s);
 // What the grids and arguments of that launch sequence depend on besides the

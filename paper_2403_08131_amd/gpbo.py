@@ -33,6 +33,11 @@ class GpboError(RuntimeError):
         self.status = status
 
 
+class HyperOpts(C.Structure):
+    _fields_ = [("starts", C.c_int32), ("steps", C.c_int32), ("lr", C.c_double),
+                ("jitter0", C.c_double), ("retries", C.c_int32)]
+
+
 class Problem(C.Structure):
     _fields_ = [("n", C.c_int32), ("d", C.c_int32), ("X", C.c_void_p), ("y", C.c_void_p),
                 ("kernel", C.c_int32), ("lengthscale", C.POINTER(C.c_double)),
@@ -76,6 +81,12 @@ _SIGS = {
     "gpbo_next_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p),
                                     C.POINTER(C.c_int64), C.POINTER(C.c_void_p), C.c_int, C.c_void_p,
                                     C.c_int32, C.c_void_p]),
+    "gpbo_lml_grad_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_int32,
+                                        C.c_void_p, C.c_void_p]),
+    "gpbo_fit_hyper_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Problem),
+                                         C.POINTER(HyperOpts), C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.POINTER(C.c_void_p), C.POINTER(C.c_int32)]),
     "gpbo_append_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p,
                                       C.c_int32, C.c_void_p]),
     "gpbo_model_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
@@ -355,6 +366,54 @@ def next_batched(ctx: Context, models, Xcs, prec, argmax, out):
     xs = (C.c_void_p * B)(*[x.data_ptr() for x in Xcs])
     ctx.check(lib().gpbo_next_batched(ctx.h, B, hs, ms, xs, pr, _ptr(argmax), int(out.shape[1]),
                                       _ptr(out)))
+
+
+def lml_grad_batched(ctx: Context, models):
+    """gpbo_lml_grad_batched: (grad (B x ldg device float64, ldg = max d + 2),
+    lml (B device float64))."""
+    B = len(models)
+    ldg = max(mo.d for mo in models) + 2
+    grad = torch.empty((B, ldg), dtype=torch.float64, device=ctx.device)
+    lml = torch.empty(B, dtype=torch.float64, device=ctx.device)
+    hs = (C.c_void_p * B)(*[mo.h.value if isinstance(mo.h, C.c_void_p) else mo.h for mo in models])
+    ctx.check(lib().gpbo_lml_grad_batched(ctx.h, B, hs, ldg, _ptr(grad), _ptr(lml)))
+    return grad, lml
+
+
+def fit_hyper_batched(ctx: Context, problems, theta0, lo, hi, steps=100, lr=0.05, jitter0=1e-8,
+                      retries=4, want_models=True):
+    """gpbo_fit_hyper_batched.  problems: dicts with X, y (device float64) and
+    optionally kernel, normalize_y, refine_alpha; theta0: (B, S, ldt) host
+    array of starts; lo, hi: (B, ldt).  Returns (status, statuses, theta
+    (B, ldt), lml (B,), jitter (B,), models or None)."""
+    import numpy as np
+    B = len(problems)
+    theta0 = np.ascontiguousarray(theta0, dtype=np.float64)
+    S, ldt = theta0.shape[1], theta0.shape[2]
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    arr = (Problem * B)()
+    for b, pr in enumerate(problems):
+        X, y = pr["X"], pr["y"]
+        assert X.dtype == torch.float64 and y.dtype == torch.float64 and X.is_contiguous()
+        arr[b] = Problem(X.shape[0], X.shape[1], X.data_ptr(), y.data_ptr(),
+                         int(pr.get("kernel", KERNEL_SE)), None, 1.0, 0.0,
+                         1 if pr.get("normalize_y", True) else 0,
+                         1 if pr.get("refine_alpha", False) else 0)
+    o = HyperOpts(S, int(steps), float(lr), float(jitter0), int(retries))
+    th = np.zeros((B, ldt))
+    lml = np.zeros(B)
+    jit = np.zeros(B)
+    hs = (C.c_void_p * B)()
+    status = (C.c_int32 * B)()
+    st = lib().gpbo_fit_hyper_batched(ctx.h, B, arr, C.byref(o), theta0.ctypes.data, lo.ctypes.data,
+                                      hi.ctypes.data, ldt, th.ctypes.data, lml.ctypes.data,
+                                      jit.ctypes.data, hs if want_models else None, status)
+    models = None
+    if want_models:
+        models = [Model(ctx, C.c_void_p(hs[b]), pr["X"].shape[0], pr["X"].shape[1]) if hs[b]
+                  else None for b, pr in enumerate(problems)]
+    return st, list(status), th, lml, jit, models
 
 
 def status_batched(ctx: Context, models):
