@@ -42,22 +42,42 @@ __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float
 struct NormalCdf {
   float Phi, e;  // Phi(u) and exp(-u^2 / 2)
 };
-__device__ __forceinline__ NormalCdf normal_cdf(float u) {
-  const float x = fabsf(u) * 0.70710678118654752440f;
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
-  float q = fmaf(t, 1.061405429f, -1.453152027f);
-  q = fmaf(t, q, 1.421413741f);
-  q = fmaf(t, q, -0.284496736f);
-  q = fmaf(t, q, 0.254829592f);
+// Phi(-|u|) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-u^2/2) / 2 with
+// t = 1 / (1 + p |u| / sqrt 2) (the formula above at x = |u| / sqrt 2), the
+// 1/2 folded into the coefficients.
+__device__ __forceinline__ float normal_tail(float u, float* e_out = nullptr) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752440f, fabsf(u), 1.0f));
+  float q = fmaf(t, 0.5f * 1.061405429f, 0.5f * -1.453152027f);
+  q = fmaf(t, q, 0.5f * 1.421413741f);
+  q = fmaf(t, q, 0.5f * -0.284496736f);
+  q = fmaf(t, q, 0.5f * 0.254829592f);
   q *= t;
-  const float e = __builtin_amdgcn_exp2f(-x * x * 1.44269504088896340736f);
-  const float tail = 0.5f * q * e;  // Phi(-|u|)
+  const float e = __builtin_amdgcn_exp2f((u * (-0.5f * 1.44269504088896340736f)) * u);
+  if (e_out) *e_out = e;
+  return q * e;
+}
+__device__ __forceinline__ NormalCdf normal_cdf(float u) {
+  float e;
+  const float tail = normal_tail(u, &e);  // Phi(-|u|)
   return {u >= 0.0f ? 1.0f - tail : tail, e};
 }
-__device__ __forceinline__ float gelu(float u) { return u * normal_cdf(u).Phi; }
+// GELU u Phi(u) = max(u, 0) - |u| Phi(-|u|): the same value for either sign,
+// without a select on the sign.
+__device__ __forceinline__ float gelu(float u) {
+  return fmaf(-fabsf(u), normal_tail(u), fmaxf(u, 0.0f));
+}
 __device__ __forceinline__ float gelu_grad(float u) {
   const NormalCdf c = normal_cdf(u);
   return c.Phi + u * c.e * 0.39894228040143267794f;
+}
+
+// Two floats rounded to bfloat16 (round to nearest even, NaN kept) and packed,
+// the first in the low half: one v_cvt_pk_bf16_f32.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned pack_bf16x2(float lo, float hi) {
+  const f32x2_t v = {lo, hi};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2_t));
 }
 
 struct MlpDev {
@@ -147,6 +167,10 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+  // layer 1, transposed: C[h][s] = sum_k W1[h][k] x[s][k] (A = W1 rows, B =
+  // samples), so that a lane's four accumulators are four consecutive hidden
+  // units of one sample: they round to bfloat16 in pairs and go to the
+  // sample-major h1 tile as one 8-byte store
   for (int k0 = 0; k0 < DP; k0 += 32) {
     us8 av[4], bv[4];
 #pragma unroll
@@ -159,28 +183,35 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, av[a]),
-                                                            __builtin_bit_cast(bf8, bv[b]),
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, bv[b]),
+                                                            __builtin_bit_cast(bf8, av[a]),
                                                             acc[a][b], 0, 0, 0);
   }
-  // layer-1 epilogue: lane holds samples 16a + 4(lane/16) + r, unit ocol + 16b + lane%16
+  // layer-1 epilogue: lane holds hidden units h0 .. h0+3 (h0 = ocol + 16b +
+  // 4(lane/16)) of sample 16a + lane%16
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
-    const int h = ocol + b * 16 + lane % 16;
-    const float bb = p[off_b1(M) + h];
+    const int h0 = ocol + b * 16 + 4 * (lane / 16);
+    float bb[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int r = 0; r < 4; ++r) bb[r] = p[off_b1(M) + h0 + r];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int row = a * 16 + lane % 16;
+      float pre[4], g[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = a * 16 + 4 * (lane / 16) + r;
-        const float pre = acc[a][b][r] + bb;
-        const unsigned short hb = f2bf(gelu(pre));
-        hA[row * ldh + h] = hb;
-        if (TRAIN && i0 + row < n) {
-          O.pre1[((int64_t)e * n + i0 + row) * H + h] = pre;
-          O.h1[((int64_t)e * n + i0 + row) * H + h] = hb;
-        }
+        pre[r] = acc[a][b][r] + bb[r];
+        g[r] = gelu(pre[r]);
       }
+      const uint2 hb = make_uint2(pack_bf16x2(g[0], g[1]), pack_bf16x2(g[2], g[3]));
+      *(uint2*)(hA + row * ldh + h0) = hb;
+      if (TRAIN && i0 + row < n) {
+        const int64_t o = ((int64_t)e * n + i0 + row) * H + h0;
+        *(float4*)(O.pre1 + o) = make_float4(pre[0], pre[1], pre[2], pre[3]);
+        *(uint2*)(O.h1 + o) = hb;
+      }
+    }
   }
   __syncthreads();
   if (TRAIN) {  // feature-major copy, coalesced along the samples
@@ -193,7 +224,8 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
-  // layer 2: wave w computes outputs [64w, 64w + 64) for the MT samples
+  // layer 2, transposed the same way: C[j][s] = sum_k W2[j][k] h1[s][k];
+  // wave w computes outputs [64w, 64w + 64) for the MT samples
   const unsigned short* W2 = M.W2b + (int64_t)e * H * H;
   for (int k0 = 0; k0 < H; k0 += 32) {
     us8 av[4], bv[4];
@@ -207,43 +239,54 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, av[a]),
-                                                            __builtin_bit_cast(bf8, bv[b]),
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, bv[b]),
+                                                            __builtin_bit_cast(bf8, av[a]),
                                                             acc[a][b], 0, 0, 0);
   }
-  // epilogue: lane holds rows 16a + 4(lane/16) + r, columns ocol + 16b + lane%16
-  float rowsum[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) rowsum[a][r] = 0.0f;
+  // epilogue: lane holds outputs j0 .. j0+3 (j0 = ocol + 16b + 4(lane/16)) of
+  // sample 16a + lane%16; h2 = bf16(GELU(pre2)) and its dot with w3 stay in
+  // the lane until the four lane groups are summed
+  float rowsum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
-    const int j = ocol + b * 16 + lane % 16;
-    const float b2 = p[off_b2(M) + j];
-    const float w3 = bf2f(M.w3b[(int64_t)e * H + j]);
+    const int j0 = ocol + b * 16 + 4 * (lane / 16);
+    float b2[4], w3[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int r = 0; r < 4; ++r) b2[r] = p[off_b2(M) + j0 + r];
+    const uint2 w3p = *(const uint2*)(M.w3b + (int64_t)e * H + j0);
+    w3[0] = __uint_as_float(w3p.x << 16);
+    w3[1] = __uint_as_float(w3p.x & 0xffff0000u);
+    w3[2] = __uint_as_float(w3p.y << 16);
+    w3[3] = __uint_as_float(w3p.y & 0xffff0000u);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int row = a * 16 + lane % 16;
+      float pre[4], g[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = a * 16 + 4 * (lane / 16) + r;
-        const float pre = acc[a][b][r] + b2;
-        if (TRAIN && i0 + row < n) O.pre2[((int64_t)e * n + i0 + row) * H + j] = pre;
-        rowsum[a][r] = fmaf(w3, bfr(gelu(pre)), rowsum[a][r]);
+        pre[r] = acc[a][b][r] + b2[r];
+        g[r] = gelu(pre[r]);
       }
-  }
-  // sum over the 16 columns of the lane group, then over the four waves
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      float v = rowsum[a][r];
-      v += __shfl_xor(v, 1);
-      v += __shfl_xor(v, 2);
-      v += __shfl_xor(v, 4);
-      v += __shfl_xor(v, 8);
-      if (lane % 16 == 0) red[wave * MT + a * 16 + 4 * (lane / 16) + r] = v;
+      if (TRAIN && i0 + row < n)
+        *(float4*)(O.pre2 + ((int64_t)e * n + i0 + row) * H + j0) =
+            make_float4(pre[0], pre[1], pre[2], pre[3]);
+      const unsigned lo = pack_bf16x2(g[0], g[1]), hi = pack_bf16x2(g[2], g[3]);
+      float v = rowsum[a];
+      v = fmaf(w3[0], __uint_as_float(lo << 16), v);
+      v = fmaf(w3[1], __uint_as_float(lo & 0xffff0000u), v);
+      v = fmaf(w3[2], __uint_as_float(hi << 16), v);
+      v = fmaf(w3[3], __uint_as_float(hi & 0xffff0000u), v);
+      rowsum[a] = v;
     }
+  }
+  // sum over the four lane groups, then over the four waves
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    float v = rowsum[a];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    if (lane < 16) red[wave * MT + a * 16 + lane] = v;
+  }
   __syncthreads();
   if (t < MT && i0 + t < n) {
     const float o = red[t] + red[MT + t] + red[2 * MT + t] + red[3 * MT + t] + p[off_b3(M)];
