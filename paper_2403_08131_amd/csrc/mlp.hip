@@ -35,22 +35,20 @@ __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float
 
 // GELU u Phi(u) and its derivative Phi(u) + u phi(u), with the normal CDF
 // from the rational approximation of erf of Abramowitz & Stegun (1964),
-// formula 7.1.26: for x >= 0, erf x = 1 - t (a1 + t (a2 + t (a3 + t (a4 +
-// t a5)))) exp(-x^2), t = 1 / (1 + p x), absolute error <= 1.5e-7 -- far
-// below the bfloat16 rounding the activations receive next.  Branch-free;
-// exp(-u^2 / 2) is shared with the density.
+// formula 7.1.25: for x >= 0, erf x = 1 - t (a1 + t (a2 + t a3)) exp(-x^2),
+// t = 1 / (1 + p x), p = 0.47047, absolute error <= 2.5e-5 -- two orders
+// below the bfloat16 rounding (2^-9 relative) the activations receive next.
+// Branch-free; exp(-u^2 / 2) is shared with the density.
 struct NormalCdf {
   float Phi, e;  // Phi(u) and exp(-u^2 / 2)
 };
-// Phi(-|u|) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-u^2/2) / 2 with
-// t = 1 / (1 + p |u| / sqrt 2) (the formula above at x = |u| / sqrt 2), the
-// 1/2 folded into the coefficients.
+// Phi(-|u|) = t (a1 + t (a2 + t a3)) exp(-u^2/2) / 2 with t = 1 / (1 + p |u| /
+// sqrt 2) (the formula above at x = |u| / sqrt 2), the 1/2 folded into the
+// coefficients.
 __device__ __forceinline__ float normal_tail(float u, float* e_out = nullptr) {
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752440f, fabsf(u), 1.0f));
-  float q = fmaf(t, 0.5f * 1.061405429f, 0.5f * -1.453152027f);
-  q = fmaf(t, q, 0.5f * 1.421413741f);
-  q = fmaf(t, q, 0.5f * -0.284496736f);
-  q = fmaf(t, q, 0.5f * 0.254829592f);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.47047f * 0.70710678118654752440f, fabsf(u), 1.0f));
+  float q = fmaf(t, 0.5f * 0.7478556f, 0.5f * -0.0958798f);
+  q = fmaf(t, q, 0.5f * 0.3480242f);
   q *= t;
   const float e = __builtin_amdgcn_exp2f((u * (-0.5f * 1.44269504088896340736f)) * u);
   if (e_out) *e_out = e;
@@ -162,11 +160,17 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
   }
   __syncthreads();
   const int ocol = wave * 64;  // this wave's 64 columns (hidden units / outputs)
+  // the accumulators start from the biases: lane's entry r of block b is unit
+  // ocol + 16b + 4(lane/16) + r for every sample block
   f4 acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int b = 0; b < 4; ++b) {
+    const int h0 = ocol + b * 16 + 4 * (lane / 16);
+    const f4 bb = {p[off_b1(M) + h0], p[off_b1(M) + h0 + 1], p[off_b1(M) + h0 + 2],
+                   p[off_b1(M) + h0 + 3]};
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+    for (int a = 0; a < 4; ++a) acc[a][b] = bb;
+  }
   // layer 1, transposed: C[h][s] = sum_k W1[h][k] x[s][k] (A = W1 rows, B =
   // samples), so that a lane's four accumulators are four consecutive hidden
   // units of one sample: they round to bfloat16 in pairs and go to the
@@ -192,16 +196,13 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     const int h0 = ocol + b * 16 + 4 * (lane / 16);
-    float bb[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) bb[r] = p[off_b1(M) + h0 + r];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const int row = a * 16 + lane % 16;
       float pre[4], g[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        pre[r] = acc[a][b][r] + bb[r];
+        pre[r] = acc[a][b][r];
         g[r] = gelu(pre[r]);
       }
       const uint2 hb = make_uint2(pack_bf16x2(g[0], g[1]), pack_bf16x2(g[2], g[3]));
@@ -221,9 +222,13 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
     }
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int b = 0; b < 4; ++b) {
+    const int j0 = ocol + b * 16 + 4 * (lane / 16);
+    const f4 bb = {p[off_b2(M) + j0], p[off_b2(M) + j0 + 1], p[off_b2(M) + j0 + 2],
+                   p[off_b2(M) + j0 + 3]};
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+    for (int a = 0; a < 4; ++a) acc[a][b] = bb;
+  }
   // layer 2, transposed the same way: C[j][s] = sum_k W2[j][k] h1[s][k];
   // wave w computes outputs [64w, 64w + 64) for the MT samples
   const unsigned short* W2 = M.W2b + (int64_t)e * H * H;
@@ -250,9 +255,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     const int j0 = ocol + b * 16 + 4 * (lane / 16);
-    float b2[4], w3[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) b2[r] = p[off_b2(M) + j0 + r];
+    float w3[4];
     const uint2 w3p = *(const uint2*)(M.w3b + (int64_t)e * H + j0);
     w3[0] = __uint_as_float(w3p.x << 16);
     w3[1] = __uint_as_float(w3p.x & 0xffff0000u);
@@ -264,7 +267,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
       float pre[4], g[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        pre[r] = acc[a][b][r] + b2[r];
+        pre[r] = acc[a][b][r];
         g[r] = gelu(pre[r]);
       }
       if (TRAIN && i0 + row < n)
