@@ -270,6 +270,10 @@ def run_c4(args):
         r["train_ms"] = (time.perf_counter() - t0) * 1e3
         r["loss"] = float(hist[-1].mean().item())
         model.free()
+        # a persistent grid of k workgroups per compute unit would leave room
+        # for the fit's tiles; measured: k = 1 halves the forward's rate and
+        # the fit gains nothing (both need the whole GPU), so the default fills it
+        net.set_occupancy(args.fwd_occupancy)
         r["net"] = net
         reps.append(r)
     R = len(reps)
@@ -726,6 +730,8 @@ def main():
     ap.add_argument("--k1", type=int, default=65536, help="c4: candidates the network keeps")
     ap.add_argument("--k2", type=int, default=4096, help="c4: candidates the judge scores exactly")
     ap.add_argument("--lr", type=float, default=3e-3, help="c4: Adam learning rate")
+    ap.add_argument("--fwd-occupancy", type=int, default=0,
+                    help="c4: network forward workgroups per compute unit (0 = fill the GPU)")
     ap.add_argument("--case", type=int, default=3, help="bo: case of the paper's family (1..5)")
     ap.add_argument("--pool", type=int, default=65536, help="bo: candidates per search and iteration")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",

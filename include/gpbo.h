@@ -498,6 +498,14 @@ gpbo_status gpbo_mlp_train(gpbo_ctx ctx, gpbo_mlp mlp, int32_t n, const float* X
  * stream (an asynchronous fit needs no status call first).  Asynchronous. */
 gpbo_status gpbo_mlp_train_model(gpbo_ctx ctx, gpbo_mlp mlp, gpbo_model model, int32_t steps,
                                  double lr, float* loss_hist);
+/* Grid of the network's pass over a pool (gpbo_mlp_forward,
+ * gpbo_mlp_prescreen*): 0 (the default) launches one workgroup per 64-sample
+ * tile and member, filling every compute unit; k > 0 launches k workgroups
+ * per compute unit, each looping over tiles, so that part of every compute
+ * unit stays free for work queued on other streams -- the Gaussian-process
+ * fit of the same optimisation step, which the prescreen's judge needs next.
+ * Results do not depend on it.  Returns GPBO_E_INVALID_ARG for k < 0. */
+gpbo_status gpbo_mlp_set_occupancy(gpbo_ctx ctx, gpbo_mlp mlp, int32_t workgroups_per_cu);
 /* Member outputs on m candidates: out is device members x m float. */
 gpbo_status gpbo_mlp_forward(gpbo_ctx ctx, gpbo_mlp mlp, int64_t m, const float* Xc,
                              float* out);

@@ -1671,6 +1671,14 @@ gpbo_status gpbo_mlp_train_model(gpbo_ctx c, gpbo_mlp mlp, gpbo_model M, int32_t
   return GPBO_OK;
 }
 
+gpbo_status gpbo_mlp_set_occupancy(gpbo_ctx c, gpbo_mlp mlp, int32_t workgroups_per_cu) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (!mlp || workgroups_per_cu < 0)
+    return fail(c, GPBO_E_INVALID_ARG, "invalid occupancy arguments");
+  mlp_set_occupancy(mlp->st, workgroups_per_cu);
+  return GPBO_OK;
+}
+
 gpbo_status gpbo_mlp_forward(gpbo_ctx c, gpbo_mlp mlp, int64_t m, const float* Xc, float* out) {
   if (!c) return GPBO_E_INVALID_ARG;
   if (!mlp || m < 0 || (m > 0 && (!Xc || !out))) return fail(c, GPBO_E_INVALID_ARG, "invalid forward arguments");

@@ -399,6 +399,9 @@ bool mlp_grads(MlpState* st, int64_t n, const float* X, const float* y, float* g
 bool mlp_train_model(MlpState* st, const Model* M, int steps, double lr, float* loss_hist,
                      bool use_graph, hipStream_t s);
 void mlp_forward(MlpState* st, int64_t m, const float* Xc, float* out, hipStream_t s);
+// Forward grid: 0 = one workgroup per (sample tile, member); k > 0 = k
+// workgroups per compute unit, each looping over items.
+void mlp_set_occupancy(MlpState* st, int wg_per_cu);
 void mlp_ens_ei(MlpState* st, int64_t m, const float* out, double fbest, float* ei, hipStream_t s);
 void mlp_ens_lcb(MlpState* st, int64_t m, const float* out, double kappa, float* score,
                  hipStream_t s);

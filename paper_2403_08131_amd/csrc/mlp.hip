@@ -134,166 +134,173 @@ struct FwdOut {
 
 __device__ __forceinline__ int fwd_ldx(int DP) { return DP + 8; }  // bf16 row stride of x / W1 tiles
 
+// Work item q = e * ntile + tile (member-major, so consecutive items share
+// the member's W2 in L2); workgroup b takes items b, b + grid, ...  A grid of
+// one workgroup per item is the plain launch; a smaller grid keeps part of
+// every compute unit free for other streams' work.
 template <bool TRAIN>
 __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const float* __restrict__ X,
-                                                 FwdOut O) {
+                                                 FwdOut O, int ntile) {
   extern __shared__ __align__(16) unsigned char sm[];
   const int H = M.H, D = M.D, DP = M.DP;
-  const int e = blockIdx.y;
-  const int64_t i0 = (int64_t)blockIdx.x * MT;
   const int t = threadIdx.x, lane = t % 64, wave = wave_id();
-  const int ldh = H + 8;  // bf16 row stride of the h1 tile (16-byte rows, skewed banks)
-  const int ldx = fwd_ldx(DP);
-  unsigned short* hA = (unsigned short*)sm;                   // [MT][ldh]
-  unsigned short* xb = hA + MT * ldh;                         // [MT][ldx]
-  unsigned short* w1 = xb + MT * ldx;                         // [H][ldx]
-  float* red = (float*)(w1 + H * ldx);                        // [4][MT]
-  const float* p = M.master + e * M.P;
-  for (int q = t; q < MT * DP; q += 256) {
-    const int r = q / DP, k = q % DP;
-    const int64_t i = i0 + r;
-    xb[r * ldx + k] = (i < n && k < D) ? f2bf(X[i * D + k]) : (unsigned short)0;
-  }
-  for (int q = t; q < H * DP; q += 256) {
-    const int h = q / DP, k = q % DP;
-    w1[h * ldx + k] = k < D ? M.W1b[((int64_t)e * H + h) * D + k] : (unsigned short)0;
-  }
-  __syncthreads();
-  const int ocol = wave * 64;  // this wave's 64 columns (hidden units / outputs)
-  // the accumulators start from the biases: lane's entry r of block b is unit
-  // ocol + 16b + 4(lane/16) + r for every sample block
-  f4 acc[4][4];
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int h0 = ocol + b * 16 + 4 * (lane / 16);
-    const f4 bb = {p[off_b1(M) + h0], p[off_b1(M) + h0 + 1], p[off_b1(M) + h0 + 2],
-                   p[off_b1(M) + h0 + 3]};
-#pragma unroll
-    for (int a = 0; a < 4; ++a) acc[a][b] = bb;
-  }
-  // layer 1, transposed: C[h][s] = sum_k W1[h][k] x[s][k] (A = W1 rows, B =
-  // samples), so that a lane's four accumulators are four consecutive hidden
-  // units of one sample: they round to bfloat16 in pairs and go to the
-  // sample-major h1 tile as one 8-byte store
-  for (int k0 = 0; k0 < DP; k0 += 32) {
-    us8 av[4], bv[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-      av[a] = *(const us8*)(xb + (a * 16 + lane % 16) * ldx + k0 + 8 * (lane / 16));
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-      bv[b] = *(const us8*)(w1 + (ocol + b * 16 + lane % 16) * ldx + k0 + 8 * (lane / 16));
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
+  for (int64_t item = blockIdx.x; item < (int64_t)ntile * M.E; item += gridDim.x) {
+    const int e = (int)(item / ntile);
+    const int64_t i0 = (item % ntile) * MT;
+    const int ldh = H + 8;  // bf16 row stride of the h1 tile (16-byte rows, skewed banks)
+    const int ldx = fwd_ldx(DP);
+    unsigned short* hA = (unsigned short*)sm;                   // [MT][ldh]
+    unsigned short* xb = hA + MT * ldh;                         // [MT][ldx]
+    unsigned short* w1 = xb + MT * ldx;                         // [H][ldx]
+    float* red = (float*)(w1 + H * ldx);                        // [4][MT]
+    const float* p = M.master + e * M.P;
+    for (int q = t; q < MT * DP; q += 256) {
+      const int r = q / DP, k = q % DP;
+      const int64_t i = i0 + r;
+      xb[r * ldx + k] = (i < n && k < D) ? f2bf(X[i * D + k]) : (unsigned short)0;
+    }
+    for (int q = t; q < H * DP; q += 256) {
+      const int h = q / DP, k = q % DP;
+      w1[h * ldx + k] = k < D ? M.W1b[((int64_t)e * H + h) * D + k] : (unsigned short)0;
+    }
+    __syncthreads();
+    const int ocol = wave * 64;  // this wave's 64 columns (hidden units / outputs)
+    // the accumulators start from the biases: lane's entry r of block b is unit
+    // ocol + 16b + 4(lane/16) + r for every sample block
+    f4 acc[4][4];
+  #pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int h0 = ocol + b * 16 + 4 * (lane / 16);
+      const f4 bb = {p[off_b1(M) + h0], p[off_b1(M) + h0 + 1], p[off_b1(M) + h0 + 2],
+                     p[off_b1(M) + h0 + 3]};
+  #pragma unroll
+      for (int a = 0; a < 4; ++a) acc[a][b] = bb;
+    }
+    // layer 1, transposed: C[h][s] = sum_k W1[h][k] x[s][k] (A = W1 rows, B =
+    // samples), so that a lane's four accumulators are four consecutive hidden
+    // units of one sample: they round to bfloat16 in pairs and go to the
+    // sample-major h1 tile as one 8-byte store
+    for (int k0 = 0; k0 < DP; k0 += 32) {
+      us8 av[4], bv[4];
+  #pragma unroll
+      for (int a = 0; a < 4; ++a)
+        av[a] = *(const us8*)(xb + (a * 16 + lane % 16) * ldx + k0 + 8 * (lane / 16));
+  #pragma unroll
       for (int b = 0; b < 4; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, bv[b]),
-                                                            __builtin_bit_cast(bf8, av[a]),
-                                                            acc[a][b], 0, 0, 0);
-  }
-  // layer-1 epilogue: lane holds hidden units h0 .. h0+3 (h0 = ocol + 16b +
-  // 4(lane/16)) of sample 16a + lane%16
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int h0 = ocol + b * 16 + 4 * (lane / 16);
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int row = a * 16 + lane % 16;
-      float pre[4], g[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        pre[r] = acc[a][b][r];
-        g[r] = gelu(pre[r]);
-      }
-      const uint2 hb = make_uint2(pack_bf16x2(g[0], g[1]), pack_bf16x2(g[2], g[3]));
-      *(uint2*)(hA + row * ldh + h0) = hb;
-      if (TRAIN && i0 + row < n) {
-        const int64_t o = ((int64_t)e * n + i0 + row) * H + h0;
-        *(float4*)(O.pre1 + o) = make_float4(pre[0], pre[1], pre[2], pre[3]);
-        *(uint2*)(O.h1 + o) = hb;
+        bv[b] = *(const us8*)(w1 + (ocol + b * 16 + lane % 16) * ldx + k0 + 8 * (lane / 16));
+  #pragma unroll
+      for (int a = 0; a < 4; ++a)
+  #pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, bv[b]),
+                                                              __builtin_bit_cast(bf8, av[a]),
+                                                              acc[a][b], 0, 0, 0);
+    }
+    // layer-1 epilogue: lane holds hidden units h0 .. h0+3 (h0 = ocol + 16b +
+    // 4(lane/16)) of sample 16a + lane%16
+  #pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int h0 = ocol + b * 16 + 4 * (lane / 16);
+  #pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int row = a * 16 + lane % 16;
+        float pre[4], g[4];
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          pre[r] = acc[a][b][r];
+          g[r] = gelu(pre[r]);
+        }
+        const uint2 hb = make_uint2(pack_bf16x2(g[0], g[1]), pack_bf16x2(g[2], g[3]));
+        *(uint2*)(hA + row * ldh + h0) = hb;
+        if (TRAIN && i0 + row < n) {
+          const int64_t o = ((int64_t)e * n + i0 + row) * H + h0;
+          *(float4*)(O.pre1 + o) = make_float4(pre[0], pre[1], pre[2], pre[3]);
+          *(uint2*)(O.h1 + o) = hb;
+        }
       }
     }
-  }
-  __syncthreads();
-  if (TRAIN) {  // feature-major copy, coalesced along the samples
-    for (int q = t; q < H * MT; q += 256) {
-      const int h = q / MT, r = q % MT;
-      if (i0 + r < n) O.h1T[((int64_t)e * H + h) * n + i0 + r] = hA[r * ldh + h];
-    }
-  }
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int j0 = ocol + b * 16 + 4 * (lane / 16);
-    const f4 bb = {p[off_b2(M) + j0], p[off_b2(M) + j0 + 1], p[off_b2(M) + j0 + 2],
-                   p[off_b2(M) + j0 + 3]};
-#pragma unroll
-    for (int a = 0; a < 4; ++a) acc[a][b] = bb;
-  }
-  // layer 2, transposed the same way: C[j][s] = sum_k W2[j][k] h1[s][k];
-  // wave w computes outputs [64w, 64w + 64) for the MT samples
-  const unsigned short* W2 = M.W2b + (int64_t)e * H * H;
-  for (int k0 = 0; k0 < H; k0 += 32) {
-    us8 av[4], bv[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-      av[a] = *(const us8*)(hA + (a * 16 + lane % 16) * ldh + k0 + 8 * (lane / 16));
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-      bv[b] = *(const us8*)(W2 + (int64_t)(ocol + b * 16 + lane % 16) * H + k0 + 8 * (lane / 16));
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, bv[b]),
-                                                            __builtin_bit_cast(bf8, av[a]),
-                                                            acc[a][b], 0, 0, 0);
-  }
-  // epilogue: lane holds outputs j0 .. j0+3 (j0 = ocol + 16b + 4(lane/16)) of
-  // sample 16a + lane%16; h2 = bf16(GELU(pre2)) and its dot with w3 stay in
-  // the lane until the four lane groups are summed
-  float rowsum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int j0 = ocol + b * 16 + 4 * (lane / 16);
-    float w3[4];
-    const uint2 w3p = *(const uint2*)(M.w3b + (int64_t)e * H + j0);
-    w3[0] = __uint_as_float(w3p.x << 16);
-    w3[1] = __uint_as_float(w3p.x & 0xffff0000u);
-    w3[2] = __uint_as_float(w3p.y << 16);
-    w3[3] = __uint_as_float(w3p.y & 0xffff0000u);
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int row = a * 16 + lane % 16;
-      float pre[4], g[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        pre[r] = acc[a][b][r];
-        g[r] = gelu(pre[r]);
+    __syncthreads();
+    if (TRAIN) {  // feature-major copy, coalesced along the samples
+      for (int q = t; q < H * MT; q += 256) {
+        const int h = q / MT, r = q % MT;
+        if (i0 + r < n) O.h1T[((int64_t)e * H + h) * n + i0 + r] = hA[r * ldh + h];
       }
-      if (TRAIN && i0 + row < n)
-        *(float4*)(O.pre2 + ((int64_t)e * n + i0 + row) * H + j0) =
-            make_float4(pre[0], pre[1], pre[2], pre[3]);
-      const unsigned lo = pack_bf16x2(g[0], g[1]), hi = pack_bf16x2(g[2], g[3]);
+    }
+  #pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j0 = ocol + b * 16 + 4 * (lane / 16);
+      const f4 bb = {p[off_b2(M) + j0], p[off_b2(M) + j0 + 1], p[off_b2(M) + j0 + 2],
+                     p[off_b2(M) + j0 + 3]};
+  #pragma unroll
+      for (int a = 0; a < 4; ++a) acc[a][b] = bb;
+    }
+    // layer 2, transposed the same way: C[j][s] = sum_k W2[j][k] h1[s][k];
+    // wave w computes outputs [64w, 64w + 64) for the MT samples
+    const unsigned short* W2 = M.W2b + (int64_t)e * H * H;
+    for (int k0 = 0; k0 < H; k0 += 32) {
+      us8 av[4], bv[4];
+  #pragma unroll
+      for (int a = 0; a < 4; ++a)
+        av[a] = *(const us8*)(hA + (a * 16 + lane % 16) * ldh + k0 + 8 * (lane / 16));
+  #pragma unroll
+      for (int b = 0; b < 4; ++b)
+        bv[b] = *(const us8*)(W2 + (int64_t)(ocol + b * 16 + lane % 16) * H + k0 + 8 * (lane / 16));
+  #pragma unroll
+      for (int a = 0; a < 4; ++a)
+  #pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, bv[b]),
+                                                              __builtin_bit_cast(bf8, av[a]),
+                                                              acc[a][b], 0, 0, 0);
+    }
+    // epilogue: lane holds outputs j0 .. j0+3 (j0 = ocol + 16b + 4(lane/16)) of
+    // sample 16a + lane%16; h2 = bf16(GELU(pre2)) and its dot with w3 stay in
+    // the lane until the four lane groups are summed
+    float rowsum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  #pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j0 = ocol + b * 16 + 4 * (lane / 16);
+      float w3[4];
+      const uint2 w3p = *(const uint2*)(M.w3b + (int64_t)e * H + j0);
+      w3[0] = __uint_as_float(w3p.x << 16);
+      w3[1] = __uint_as_float(w3p.x & 0xffff0000u);
+      w3[2] = __uint_as_float(w3p.y << 16);
+      w3[3] = __uint_as_float(w3p.y & 0xffff0000u);
+  #pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int row = a * 16 + lane % 16;
+        float pre[4], g[4];
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          pre[r] = acc[a][b][r];
+          g[r] = gelu(pre[r]);
+        }
+        if (TRAIN && i0 + row < n)
+          *(float4*)(O.pre2 + ((int64_t)e * n + i0 + row) * H + j0) =
+              make_float4(pre[0], pre[1], pre[2], pre[3]);
+        const unsigned lo = pack_bf16x2(g[0], g[1]), hi = pack_bf16x2(g[2], g[3]);
+        float v = rowsum[a];
+        v = fmaf(w3[0], __uint_as_float(lo << 16), v);
+        v = fmaf(w3[1], __uint_as_float(lo & 0xffff0000u), v);
+        v = fmaf(w3[2], __uint_as_float(hi << 16), v);
+        v = fmaf(w3[3], __uint_as_float(hi & 0xffff0000u), v);
+        rowsum[a] = v;
+      }
+    }
+    // sum over the four lane groups, then over the four waves
+  #pragma unroll
+    for (int a = 0; a < 4; ++a) {
       float v = rowsum[a];
-      v = fmaf(w3[0], __uint_as_float(lo << 16), v);
-      v = fmaf(w3[1], __uint_as_float(lo & 0xffff0000u), v);
-      v = fmaf(w3[2], __uint_as_float(hi << 16), v);
-      v = fmaf(w3[3], __uint_as_float(hi & 0xffff0000u), v);
-      rowsum[a] = v;
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (lane < 16) red[wave * MT + a * 16 + lane] = v;
     }
-  }
-  // sum over the four lane groups, then over the four waves
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    float v = rowsum[a];
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    if (lane < 16) red[wave * MT + a * 16 + lane] = v;
-  }
-  __syncthreads();
-  if (t < MT && i0 + t < n) {
-    const float o = red[t] + red[MT + t] + red[2 * MT + t] + red[3 * MT + t] + p[off_b3(M)];
-    O.out[(int64_t)e * n + i0 + t] = o;
+    __syncthreads();
+    if (t < MT && i0 + t < n) {
+      const float o = red[t] + red[MT + t] + red[2 * MT + t] + red[3 * MT + t] + p[off_b3(M)];
+      O.out[(int64_t)e * n + i0 + t] = o;
+    }
+    __syncthreads();  // the tiles are restaged for the next item
   }
 }
 
@@ -589,7 +596,11 @@ struct MlpState {
   size_t data_bytes = 0;
   hipGraphExec_t graph = nullptr;
   std::vector<uint64_t> graph_key;
+  int ncu = 256;           // compute units of the device
+  int fwd_wg_per_cu = 0;   // forward grid: 0 = one workgroup per item, else this many per CU
 };
+
+void mlp_set_occupancy(MlpState* st, int wg_per_cu) { st->fwd_wg_per_cu = wg_per_cu; }
 
 int mlp_dp(int D) { return D <= 32 ? 32 : 64; }
 
@@ -601,6 +612,12 @@ size_t mlp_fwd_smem(int D, int H) {
 MlpState* mlp_create(Ctx* c, int E, int D, int H, const float* init, hipStream_t s) {
   MlpState* st = new MlpState();
   st->ctx = c;
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
+        ncu > 0)
+      st->ncu = ncu;
+  }
   MlpDev& M = st->dev;
   M.E = E;
   M.D = D;
@@ -718,8 +735,8 @@ void mlp_step(MlpState* st, int64_t n, const float* X, const float* y, double lr
   MlpDev& M = st->dev;
   const int E = M.E, H = M.H;
   FwdOut fo{w.out, w.pre1, w.h1, w.h1T, w.pre2};
-  hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(w.nblk, E), dim3(256), mlp_fwd_smem(M.D, H), s, M, n, X,
-                     fo);
+  hipLaunchKernelGGL(k_mlp_fwd<true>, dim3((unsigned)(w.nblk * E)), dim3(256), mlp_fwd_smem(M.D, H),
+                     s, M, n, X, fo, w.nblk);
   BwdBuf bb{w.dpre2, w.dpre2T, w.colpart};
   hipLaunchKernelGGL(k_mlp_bwd_out, dim3(w.nblk, E), dim3(256), 0, s, M, n, y, w.out, w.pre2, bb);
   // gW2 = dpre2^T h1 over the samples (split over S2 sample chunks)
@@ -881,8 +898,11 @@ bool mlp_grads(MlpState* st, int64_t n, const float* X, const float* y, float* g
 void mlp_forward(MlpState* st, int64_t m, const float* Xc, float* out, hipStream_t s) {
   MlpDev& M = st->dev;
   FwdOut fo{out, nullptr, nullptr, nullptr, nullptr};
-  hipLaunchKernelGGL(k_mlp_fwd<false>, dim3((unsigned)ceil_div(m, MT), M.E), dim3(256),
-                     mlp_fwd_smem(M.D, M.H), s, M, m, Xc, fo);
+  const int ntile = (int)ceil_div(m, MT);
+  int64_t grid = (int64_t)ntile * M.E;
+  if (st->fwd_wg_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)st->ncu * st->fwd_wg_per_cu);
+  hipLaunchKernelGGL(k_mlp_fwd<false>, dim3((unsigned)grid), dim3(256), mlp_fwd_smem(M.D, M.H), s,
+                     M, m, Xc, fo, ntile);
 }
 
 void mlp_ens_ei(MlpState* st, int64_t m, const float* out, double fbest, float* ei, hipStream_t s) {

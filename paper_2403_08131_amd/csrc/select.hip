@@ -106,14 +106,32 @@ __global__ void __launch_bounds__(SEL_BLOCK) k_eq_count(const float* __restrict_
 }
 
 // Exclusive scan of the per-block equal counts (one workgroup).
-__global__ void k_eq_scan(unsigned* __restrict__ counts, int nblocks) {
-  if (threadIdx.x == 0) {
-    unsigned run = 0;
-    for (int b = 0; b < nblocks; ++b) {
-      const unsigned c = counts[b];
-      counts[b] = run;
-      run += c;
-    }
+// (Exclusive prefix sum of the per-block counts, in place, by one workgroup:
+// each thread owns a run of consecutive blocks, the run totals are scanned
+// across the wave by shuffles and across the waves through LDS.)
+constexpr int SCAN_THREADS = 1024;
+__global__ void __launch_bounds__(SCAN_THREADS) k_eq_scan(unsigned* __restrict__ counts,
+                                                          int nblocks) {
+  __shared__ unsigned wsum[SCAN_THREADS / 64];
+  const int t = threadIdx.x, lane = t % 64, w = t / 64;
+  const int per = (nblocks + SCAN_THREADS - 1) / SCAN_THREADS;
+  const int b0 = min(nblocks, t * per), b1 = min(nblocks, b0 + per);
+  unsigned own = 0;
+  for (int b = b0; b < b1; ++b) own += counts[b];
+  unsigned x = own;  // inclusive scan within the wave
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  unsigned before = 0;
+  for (int q = 0; q < w; ++q) before += wsum[q];
+  unsigned run = before + x - own;
+  for (int b = b0; b < b1; ++b) {
+    const unsigned c = counts[b];
+    counts[b] = run;
+    run += c;
   }
 }
 
@@ -353,10 +371,10 @@ void launch_topk_set_into(int64_t m, const float* v, int64_t k, int64_t* idx, vo
   const int nblocks = (int)ceil_div(m, per_block);
   hipLaunchKernelGGL(k_eq_count, dim3(nblocks), dim3(SEL_BLOCK), 0, s, v, m, state, per_block,
                      eq_counts);
-  hipLaunchKernelGGL(k_eq_scan, dim3(1), dim3(64), 0, s, eq_counts, nblocks);
+  hipLaunchKernelGGL(k_eq_scan, dim3(1), dim3(SCAN_THREADS), 0, s, eq_counts, nblocks);
   hipLaunchKernelGGL(k_set_count, dim3(nblocks), dim3(SEL_BLOCK), 0, s, v, m, state, per_block,
                      eq_counts, sel_counts);
-  hipLaunchKernelGGL(k_eq_scan, dim3(1), dim3(64), 0, s, sel_counts, nblocks);
+  hipLaunchKernelGGL(k_eq_scan, dim3(1), dim3(SCAN_THREADS), 0, s, sel_counts, nblocks);
   hipLaunchKernelGGL(k_set_write, dim3(nblocks), dim3(SEL_BLOCK), 0, s, v, m, state, per_block,
                      eq_counts, sel_counts, idx);
 }
@@ -379,7 +397,7 @@ void launch_topk_into(int64_t m, const float* v, int64_t k, int64_t* idx, void* 
   const int nblocks = (int)ceil_div(m, per_block);
   hipLaunchKernelGGL(k_eq_count, dim3(nblocks), dim3(SEL_BLOCK), 0, s, v, m, state, per_block,
                      counts);
-  hipLaunchKernelGGL(k_eq_scan, dim3(1), dim3(64), 0, s, counts, nblocks);
+  hipLaunchKernelGGL(k_eq_scan, dim3(1), dim3(SCAN_THREADS), 0, s, counts, nblocks);
   hipLaunchKernelGGL(k_sel_write, dim3(nblocks), dim3(SEL_BLOCK), 0, s, v, m, state, per_block,
                      counts, (unsigned)k, okey, oidx);
   hipLaunchKernelGGL(k_sel_sort, dim3(1), dim3(1024), 0, s, okey, oidx, (int)k, idx);

@@ -87,6 +87,7 @@ _SIGS = {
                                          C.POINTER(HyperOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.POINTER(C.c_void_p), C.POINTER(C.c_int32)]),
+    "gpbo_mlp_set_occupancy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
     "gpbo_append_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p,
                                       C.c_int32, C.c_void_p]),
     "gpbo_model_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
@@ -635,6 +636,11 @@ class Mlp:
         self.ctx.check(lib().gpbo_mlp_prescreen(self.ctx.h, self.h, Xc.shape[0], _ptr(Xc),
                                                 float(f_best), int(k), _ptr(idx), _ptr(ei)))
         return idx, ei
+
+    def set_occupancy(self, workgroups_per_cu):
+        """gpbo_mlp_set_occupancy: 0 = fill the GPU; k > 0 = k workgroups per
+        compute unit for the pass over a pool."""
+        self.ctx.check(lib().gpbo_mlp_set_occupancy(self.ctx.h, self.h, int(workgroups_per_cu)))
 
     def prescreen_lcb(self, Xc, kappa, k, want_score=False):
         """gpbo_mlp_prescreen_lcb: top-k by -(ensemble mean - kappa * sd)."""

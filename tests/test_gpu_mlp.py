@@ -81,6 +81,20 @@ def test_mlp_forward_matches_oracle(ctx):
     print(f"  forward: vs emulated {err_em:.2e}, vs float64 {err:.2e}")
     assert err_em <= 2e-3
     assert err <= 5e-2
+    # a persistent grid of one or two workgroups per compute unit computes
+    # every tile the same way: identical outputs (5 tiles x 5 members here,
+    # and 600 tiles x 5 members, more items than workgroups)
+    Xt = torch.tensor(X, dtype=torch.float32, device=DEV)
+    Xb = torch.rand((38400, D), generator=torch.Generator(device=DEV).manual_seed(3), device=DEV)
+    base_b = net.forward(Xb)
+    for k in (1, 2):
+        net.set_occupancy(k)
+        assert torch.equal(net.forward(Xt), net.forward(Xt)) and torch.equal(
+            net.forward(Xt).double().cpu(), torch.tensor(out))
+        assert torch.equal(net.forward(Xb), base_b)
+    net.set_occupancy(0)
+    with pytest.raises(G.GpboError):
+        net.set_occupancy(-1)
     net.free()
 
 
