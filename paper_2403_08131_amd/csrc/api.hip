@@ -82,7 +82,7 @@ gpbo_status check_problem(Ctx* c, const gpbo_problem* p) {
 
 // Byte offsets of one model's buffers inside its part of a fit allocation.
 struct FitLayout {
-  size_t oX, oy, oil, oL, oLi, oD, oyt, oa, ow, o32, bytes;
+  size_t oX, oy, oil, oL, oLi, oK, oD, oyt, oa, ow, o32, bytes;
 };
 
 // X and y take npad rows so that rank-one appends fill the padding before
@@ -96,10 +96,11 @@ FitLayout fit_layout(int n, int d, bool refine) {
   f.oil = cv.take(d * sizeof(double));
   f.oL = cv.take(np * np * sizeof(double));
   f.oLi = cv.take(np * np * sizeof(double));
+  f.oK = cv.take(np * np * sizeof(double));
   f.oD = cv.take(np * NB * sizeof(double));
   f.oyt = cv.take(np * sizeof(double));
   f.oa = cv.take(np * sizeof(double));
-  f.ow = cv.take((4 + 16) * np * sizeof(double));  // 4 vectors + residual partials
+  f.ow = cv.take((4 + 1) * np * sizeof(double));  // 4 vectors + the product K alpha
   f.o32 = refine ? cv.take(np * np * sizeof(float)) : 0;
   f.bytes = cv.bytes;
   return f;
@@ -277,6 +278,7 @@ gpbo_status fit_group(Ctx* c, int B, const gpbo_problem* probs, Model* const* ms
     M->il64 = (double*)(b + f.oil);
     M->L = (double*)(b + f.oL);
     M->Linv = (double*)(b + f.oLi);
+    M->K = (double*)(b + f.oK);
     M->Dinv = (double*)(b + f.oD);
     M->yt = (double*)(b + f.oyt);
     M->alpha = (double*)(b + f.oa);
@@ -872,6 +874,7 @@ gpbo_status gpbo_append_batched(gpbo_ctx c, int32_t B, const gpbo_model* models,
       G.y = M->y64;
       G.L = M->L;
       G.Linv = M->Linv;
+      G.K = M->K;
       G.stats = M->stats;
       G.info = M->info;
       G.X2 = (double*)(p + f.oX);
@@ -879,6 +882,7 @@ gpbo_status gpbo_append_batched(gpbo_ctx c, int32_t B, const gpbo_model* models,
       G.y2 = (double*)(p + f.oy);
       G.L2 = (double*)(p + f.oL);
       G.Linv2 = (double*)(p + f.oLi);
+      G.K2 = (double*)(p + f.oK);
       G.stats2 = (double*)(gb + ostat + k * STATUS_SLOT);
       G.info2 = (int*)(gb + ostat + k * STATUS_SLOT + S_COUNT * sizeof(double));
     }
@@ -904,6 +908,7 @@ gpbo_status gpbo_append_batched(gpbo_ctx c, int32_t B, const gpbo_model* models,
       M->il64 = gd[k].il2;
       M->L = gd[k].L2;
       M->Linv = gd[k].Linv2;
+      M->K = gd[k].K2;
       M->Dinv = (double*)(p + f.oD);
       M->yt = (double*)(p + f.oyt);
       M->alpha = (double*)(p + f.oa);

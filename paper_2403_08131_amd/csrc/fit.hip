@@ -32,11 +32,20 @@ namespace {
 constexpr int LDT = NB + 2;        // LDS row stride of a 64 x 64 float64 tile (16-byte rows)
 constexpr int GRAM_DMAX = 64;      // largest supported input dimension
 constexpr int GS = GRAM_DMAX + 1;  // LDS row stride of staged coordinates (odd: no bank conflicts)
-constexpr int RES_CHUNKS = 16;     // column chunks of the residual products
 
 __device__ __forceinline__ bool fit_failed(const int* info) {
   const volatile int* v = info;
   return v[0] != INT_MAX || v[1] != 0;
+}
+
+// A block-uniform reading of the failure flags (another workgroup of the
+// same launch may set them while this one runs).
+__device__ __forceinline__ bool block_failed(const int* info, int* flag) {
+  if (threadIdx.x == 0) *flag = fit_failed(info) ? 1 : 0;
+  __syncthreads();
+  const bool f = *flag != 0;
+  __syncthreads();
+  return f;
 }
 
 // Workgroup reductions (256 threads): butterfly within each wave, then the
@@ -170,15 +179,21 @@ constexpr int KR = 16;
 
 // Lower triangle of K = sf2 k(X,X) + sn2 I (identity beyond n); the tile
 // mirrored above the diagonal is zeroed so the factor's upper part is clean.
+// The same entries also go to the model's symmetric copy of K (both
+// triangles, rows and columns < n), which the residual of the alpha solve
+// reads instead of evaluating the covariance again.
 // Workgroup 4b + h covers rows 16h..16h+15 of tile b (I, J).  The
 // coordinates are read from the caller's X; the diagonal tiles also copy
 // their rows into the model and flag non-finite values.
 __global__ void __launch_bounds__(256) k_gram(const FitDesc* __restrict__ D) {
-  __shared__ double xi[KR * GS], xj[NB * GS];
+  __shared__ double xi[KR * GS], xj[NB * GS], kt[KR * (NB + 1)];
+  __shared__ int flag;
   const FitDesc& P = D[blockIdx.z];
   const int nb = P.npad / NB;
   const int tile = blockIdx.x / (NB / KR), h = blockIdx.x % (NB / KR);
-  if (tile >= nb * (nb + 1) / 2 || fit_failed(P.info)) return;
+  // (the diagonal tiles of this launch may flag non-finite X meanwhile: the
+  // whole workgroup takes one reading)
+  if (tile >= nb * (nb + 1) / 2 || block_failed(P.info, &flag)) return;
   const int n = P.n, npad = P.npad;
   int I, J;
   tri_index(tile, I, J);
@@ -220,6 +235,16 @@ __global__ void __launch_bounds__(256) k_gram(const FitDesc* __restrict__ D) {
     if (j > i) v = 0.0;
     P.L[(int64_t)i * npad + j] = v;
     P.Linv[(int64_t)i * npad + j] = 0.0;  // the inverse factor starts from zero
+    if (i < n && j <= i) P.K[(int64_t)i * npad + j] = v;
+    kt[r * (NB + 1) + c] = v;
+  }
+  __syncthreads();
+  // the strictly lower entries mirrored above the diagonal (rows of 16
+  // consecutive columns per store group)
+  for (int e = threadIdx.x; e < NB * KR; e += 256) {
+    const int c = e / KR, r = e % KR;
+    const int i = r0 + r, j = J * NB + c;
+    if (i < n && j < i) P.K[(int64_t)j * npad + i] = kt[r * (NB + 1) + c];
   }
 }
 
@@ -837,48 +862,24 @@ __global__ void __launch_bounds__(64 * TRMV_T_WAVES) k_trmv_t(const FitDesc* __r
   }
 }
 
-// Partial products of K alpha, K recomputed in float64 exactly as the Gram
-// kernel builds it.  Workgroup (x, y) owns rows 16x..16x+15 and the column
-// chunk y; 64-column tiles of the chunk are staged in LDS, thread t takes
-// row t % 16 and every 16th column of a tile from t / 16 on.
+// K alpha from the stored K (float64, rows < n, one wave per row, lanes over
+// the columns), into work vector V_PART (one chunk).
 __global__ void __launch_bounds__(256) k_residual(const FitDesc* __restrict__ Ds) {
-  constexpr int NG = 256 / KR;  // column groups
-  __shared__ double xi[KR * GS], xj[NB * GS], aj[NB], red[NG][KR];
   const FitDesc& P = Ds[blockIdx.z];
-  const int n = P.n;
-  const int i0 = blockIdx.x * KR;
-  if (i0 >= n || (int)blockIdx.y >= P.nchunks || fit_failed(P.info)) return;
-  const int t = threadIdx.x, row = t % KR, grp = t / KR;
-  const int jbeg = blockIdx.y * P.chunk, jend = min(n, jbeg + P.chunk);
-  const int dp4 = (P.d + 3) & ~3;
-  stage_rows<KR>(P, P.X, i0, n, xi);
-  const int i = i0 + row;
-  double s = 0.0;
-  for (int j0 = jbeg; j0 < jend; j0 += NB) {
-    __syncthreads();
-    stage_rows(P, P.X, j0, jend, xj);
-    if (t < NB) aj[t] = j0 + t < jend ? P.alpha[j0 + t] : 0.0;
-    __syncthreads();
-    if (i < n) {
-#pragma unroll
-      for (int q = 0; q < NB / NG; ++q) {
-        const int c = grp + NG * q;
-        if (j0 + c < jend) {
-          double kij = cov_r2(P.kernel, sqdist4(xi + row * GS, xj + c * GS, dp4), P.sf2);
-          if (i == j0 + c) kij += P.sn2;
-          s = fma(kij, aj[c], s);
-        }
-      }
-    }
+  const int lane = threadIdx.x % 64;
+  const int row = blockIdx.x * 4 + threadIdx.x / 64;
+  if (row >= P.n || fit_failed(P.info)) return;
+  const double* k = P.K + (int64_t)row * P.npad;
+  double s0 = 0.0, s1 = 0.0;
+  int j = lane;
+  for (; j + 64 < P.n; j += 128) {
+    s0 = fma(k[j], P.alpha[j], s0);
+    s1 = fma(k[j + 64], P.alpha[j + 64], s1);
   }
-  red[grp][row] = s;
-  __syncthreads();
-  if (grp == 0 && i < P.npad) {
-    double v = 0.0;
-#pragma unroll
-    for (int g = 0; g < NG; ++g) v += red[g][row];
-    P.work[(int64_t)(V_PART + blockIdx.y) * P.npad + i] = v;
-  }
+  if (j < P.n) s0 = fma(k[j], P.alpha[j], s0);
+  double v = s0 + s1;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (lane == 0) P.work[(int64_t)V_PART * P.npad + row] = v;
 }
 
 // r = ytilde - sum_y part[y], its norm into stats[slot].  One workgroup of
@@ -934,16 +935,6 @@ __global__ void __launch_bounds__(64 * RESF_W) k_res_finish(const FitDesc* __res
 // The descriptors of the first three kernels describe the models before the
 // append (n = old number of observations).
 // ---------------------------------------------------------------------------
-
-// A block-uniform reading of the failure flags (another workgroup of the
-// same launch may set them while this one runs).
-__device__ __forceinline__ bool block_failed(const int* info, int* flag) {
-  if (threadIdx.x == 0) *flag = fit_failed(info) ? 1 : 0;
-  __syncthreads();
-  const bool f = *flag != 0;
-  __syncthreads();
-  return f;
-}
 
 // The new column of K, k_j = k(x_j, x_new) for j < n, into work vector V_W
 // (coordinates scaled and distances summed as the Gram kernel does); the
@@ -1015,11 +1006,15 @@ __global__ void __launch_bounds__(256) k_append_row(const FitDesc* __restrict__ 
   const double delta = sqrt(d2), rdelta = 1.0 / delta;
   const int j = blockIdx.x * 256 + t;
   if (j < n) {
+    const double kj = P.work[(int64_t)V_W * npad + j];
     P.L[(int64_t)n * npad + j] = l[j];
     P.Linv[(int64_t)n * npad + j] = -v[j] * rdelta;
+    P.K[(int64_t)n * npad + j] = kj;
+    P.K[(int64_t)j * npad + n] = kj;
   } else if (j == n) {
     P.L[(int64_t)n * npad + n] = delta;
     P.Linv[(int64_t)n * npad + n] = rdelta;
+    P.K[(int64_t)n * npad + n] = P.sf2 + P.sn2;
   }
 }
 
@@ -1034,6 +1029,7 @@ __global__ void __launch_bounds__(256) k_grow(const GrowDesc* __restrict__ Ds) {
     const double id = i == j ? 1.0 : 0.0;
     G.L2[e] = in ? G.L[i * G.np_old + j] : id;
     G.Linv2[e] = in ? G.Linv[i * G.np_old + j] : id;
+    G.K2[e] = in ? G.K[i * G.np_old + j] : 0.0;
   }
   for (int64_t e = t0; e < (int64_t)G.n * G.d; e += st) G.X2[e] = G.X[e];
   for (int64_t e = t0; e < G.n; e += st) G.y2[e] = G.y[e];
@@ -1221,9 +1217,8 @@ FitDesc make_fit_desc(Model* M, const double* X, const double* il, const double*
   f.kernel = M->kernel;
   f.normalize = normalize_y;
   f.refine = refine;
-  const int nch = (int)std::min<int64_t>(RES_CHUNKS, ceil_div(M->n, 64));
-  f.chunk = (int)round_up(ceil_div(M->n, nch), NB);
-  f.nchunks = (int)ceil_div(M->n, f.chunk);
+  f.chunk = M->n;  // K alpha is one product over the stored K
+  f.nchunks = 1;
   f.sf2 = M->sf2;
   f.sn2 = M->sn2;
   f.Xsrc = X;
@@ -1237,6 +1232,7 @@ FitDesc make_fit_desc(Model* M, const double* X, const double* il, const double*
   f.append = 0;
   f.L = M->L;
   f.Linv = M->Linv;
+  f.K = M->K;
   f.Dinv = M->Dinv;
   f.yt = M->yt;
   f.alpha = M->alpha;
@@ -1297,12 +1293,10 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
 // return at once), so a search that grows inside its padding replays the
 // same captured sequence.
 void launch_solve(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
-  int chmax = 1;
   int64_t npmax = 0;
   bool any_refine = false;
   for (int b = 0; b < B; ++b) {
     npmax = std::max<int64_t>(npmax, h[b].npad);
-    chmax = std::max(chmax, h[b].nchunks);
     any_refine |= h[b].refine != 0;
   }
   const unsigned Bz = (unsigned)B;
@@ -1312,7 +1306,7 @@ void launch_solve(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   // alpha = Linv^T (Linv ytilde), then one residual-and-correction step
   hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, -1, (int)V_W, 1);
   hipLaunchKernelGGL(k_trmv_t, dim3(g_cols, 1, Bz), dim3(64 * TRMV_T_WAVES), 0, s, dd, (int)V_W, -2, 0);
-  const dim3 g_res((unsigned)ceil_div(npmax, KR), (unsigned)chmax, Bz);
+  const dim3 g_res((unsigned)ceil_div(npmax, 4), 1, Bz);
   hipLaunchKernelGGL(k_residual, g_res, dim3(256), 0, s, dd);
   hipLaunchKernelGGL(k_res_finish, dim3(1, 1, Bz), dim3(64 * RESF_W), 0, s, dd, (int)S_RES0, 0);
   hipLaunchKernelGGL(k_trmv, dim3(g_rows, 1, Bz), dim3(256), 0, s, dd, (int)V_R, (int)V_W, 0);

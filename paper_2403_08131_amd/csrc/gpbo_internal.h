@@ -71,10 +71,11 @@ struct Model {
   double* il64 = nullptr;       // d, 1 / lengthscale
   double* L = nullptr;          // npad x npad, lower Cholesky factor (identity padded)
   double* Linv = nullptr;       // npad x npad, lower inverse factor
+  double* K = nullptr;          // npad x npad, K = sf2 k(X,X) + sn2 I, both triangles (n used)
   double* Dinv = nullptr;       // (npad/NB) x NB x NB inverses of the diagonal blocks
   double* yt = nullptr;         // npad, normalised observations (zero padded)
   double* alpha = nullptr;      // npad
-  double* work = nullptr;       // npad x 4 scratch vectors
+  double* work = nullptr;       // npad x 5: four scratch vectors and K alpha
   float* L32 = nullptr;         // npad x npad float32 copy of Linv (refine_alpha = 1 only)
   double* stats = nullptr;      // S_COUNT scalars
   int* info = nullptr;          // first failing pivot (INT32_MAX when none) + nonfinite flag
@@ -211,10 +212,11 @@ struct FitDesc {
   int append;
   double* L;         // npad x npad
   double* Linv;      // npad x npad
+  double* K;         // npad x npad, K symmetric (rows and columns < n)
   double* Dinv;      // npad / NB inverse diagonal tiles
   double* yt;        // npad
   double* alpha;     // npad
-  double* work;      // (4 + 16) npad
+  double* work;      // 5 npad
   float* L32;        // npad x npad (refine only)
   double* stats;
   int* info;
@@ -235,9 +237,9 @@ std::vector<uint64_t> append_launch_shape(const FitDesc* hnew, int B);
 // into the wider row stride with the identity beyond the old padding.
 struct GrowDesc {
   int n, d, np_old, np_new;
-  const double *X, *il, *y, *L, *Linv, *stats;
+  const double *X, *il, *y, *L, *Linv, *K, *stats;
   const int* info;
-  double *X2, *il2, *y2, *L2, *Linv2, *stats2;
+  double *X2, *il2, *y2, *L2, *Linv2, *K2, *stats2;
   int* info2;
 };
 void launch_grow(const GrowDesc* dd, int B, int np_new_max, hipStream_t s);
