@@ -134,19 +134,30 @@ struct FwdOut {
 
 __device__ __forceinline__ int fwd_ldx(int DP) { return DP + 8; }  // bf16 row stride of x / W1 tiles
 
-// Work item q = e * ntile + tile (member-major, so consecutive items share
-// the member's W2 in L2); workgroup b takes items b, b + grid, ...  A grid of
-// one workgroup per item is the plain launch; a smaller grid keeps part of
-// every compute unit free for other streams' work.
+// Work items: the E members of every 64-sample tile.  Workgroup b runs on
+// XCD b % 8 (round-robin dispatch); item q takes XCD x = q % 8, member
+// (q / 8) % E and tile 8 (q / 8E) + x, so the E members of a tile run back to
+// back on one XCD and read its samples from that XCD's L2 once (all members'
+// W2, 640 KB, stay resident there too).  Workgroup b takes items b, b +
+// grid, ... (grid a multiple of 8); a grid of one workgroup per item is the
+// plain launch, a smaller one keeps part of every compute unit free for
+// other streams' work.  Items past the last tile are skipped.
+__host__ __device__ inline int64_t fwd_items(int ntile, int E) {
+  return ((int64_t)(ntile + 7) / 8) * 8 * E;
+}
 template <bool TRAIN>
 __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const float* __restrict__ X,
                                                  FwdOut O, int ntile) {
   extern __shared__ __align__(16) unsigned char sm[];
   const int H = M.H, D = M.D, DP = M.DP;
   const int t = threadIdx.x, lane = t % 64, wave = wave_id();
-  for (int64_t item = blockIdx.x; item < (int64_t)ntile * M.E; item += gridDim.x) {
-    const int e = (int)(item / ntile);
-    const int64_t i0 = (item % ntile) * MT;
+  const int64_t items = fwd_items(ntile, M.E);
+  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+    const int64_t local = item / 8;
+    const int e = (int)(local % M.E);
+    const int64_t tile = (local / M.E) * 8 + item % 8;
+    if (tile >= ntile) continue;
+    const int64_t i0 = tile * MT;
     const int ldh = H + 8;  // bf16 row stride of the h1 tile (16-byte rows, skewed banks)
     const int ldx = fwd_ldx(DP);
     unsigned short* hA = (unsigned short*)sm;                   // [MT][ldh]
@@ -735,8 +746,8 @@ void mlp_step(MlpState* st, int64_t n, const float* X, const float* y, double lr
   MlpDev& M = st->dev;
   const int E = M.E, H = M.H;
   FwdOut fo{w.out, w.pre1, w.h1, w.h1T, w.pre2};
-  hipLaunchKernelGGL(k_mlp_fwd<true>, dim3((unsigned)(w.nblk * E)), dim3(256), mlp_fwd_smem(M.D, H),
-                     s, M, n, X, fo, w.nblk);
+  hipLaunchKernelGGL(k_mlp_fwd<true>, dim3((unsigned)fwd_items((int)w.nblk, E)), dim3(256),
+                     mlp_fwd_smem(M.D, H), s, M, n, X, fo, (int)w.nblk);
   BwdBuf bb{w.dpre2, w.dpre2T, w.colpart};
   hipLaunchKernelGGL(k_mlp_bwd_out, dim3(w.nblk, E), dim3(256), 0, s, M, n, y, w.out, w.pre2, bb);
   // gW2 = dpre2^T h1 over the samples (split over S2 sample chunks)
@@ -899,8 +910,9 @@ void mlp_forward(MlpState* st, int64_t m, const float* Xc, float* out, hipStream
   MlpDev& M = st->dev;
   FwdOut fo{out, nullptr, nullptr, nullptr, nullptr};
   const int ntile = (int)ceil_div(m, MT);
-  int64_t grid = (int64_t)ntile * M.E;
-  if (st->fwd_wg_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)st->ncu * st->fwd_wg_per_cu);
+  int64_t grid = fwd_items(ntile, M.E);
+  if (st->fwd_wg_per_cu > 0)
+    grid = std::min<int64_t>(grid, round_up((int64_t)st->ncu * st->fwd_wg_per_cu, 8));
   hipLaunchKernelGGL(k_mlp_fwd<false>, dim3((unsigned)grid), dim3(256), mlp_fwd_smem(M.D, M.H), s,
                      M, m, Xc, fo, ntile);
 }
