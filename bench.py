@@ -52,13 +52,29 @@ TRAFFIC["bytes_per_launch"] = round(1024 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetc
                                             + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]))
 
 
-def kernel_source_hash():
-    """Hash of the sources k_score_fused is built from."""
+def kernel_source_hash(files=("score.hip", "score_common.h", "gpbo_internal.h")):
+    """Hash of the sources a kernel is built from (default: k_score_fused's)."""
     h = hashlib.sha256()
-    for f in ("score.hip", "score_common.h", "gpbo_internal.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2403_08131_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+# The same counters for the network forward (k_mlp_fwd<false>) at c4: one
+# launch over 1,048,576 candidates x 5 members.  Algorithmic bytes per launch:
+# the float32 pool once (1,048,576 x 20 x 4) plus the member outputs
+# (5 x 1,048,576 x 4) = 104.9 MB.
+FWD_SOURCES = ("mlp.hip", "score_common.h")
+FWD_TRAFFIC = {
+    "kernel_sha": "c58a79da6df9e71e",
+    "fetch_kib": 43916.5,
+    "write_kib": 20480.0,
+    "fetch_scale": 262144 / 131083.5,
+    "write_scale": 1.0,
+}
+FWD_TRAFFIC["bytes_per_launch"] = round(1024 * (FWD_TRAFFIC["fetch_kib"] * FWD_TRAFFIC["fetch_scale"]
+                                                + FWD_TRAFFIC["write_kib"] * FWD_TRAFFIC["write_scale"]))
 
 
 # Above this many observations the library scores float32 pools on the
@@ -379,7 +395,11 @@ def run_c4(args):
         "training_pays_off_after_steps": train_ms / max(full_ms - pre_ms, 1e-9),
         "final_train_loss": [round(r["loss"], 4) for r in reps],
         "roofline": {"bound": "mfma", "achieved": ach_fwd, "peak": PEAKS["bf16"],
-                     "unit": "TFLOP/s", "frac": ach_fwd / PEAKS["bf16"], "traffic": None,
+                     "unit": "TFLOP/s", "frac": ach_fwd / PEAKS["bf16"],
+                     "traffic": (FWD_TRAFFIC["bytes_per_launch"]
+                                 if kernel_source_hash(FWD_SOURCES) == FWD_TRAFFIC["kernel_sha"]
+                                 else None),
+                     "algorithmic_bytes_per_launch": p0.m * p0.d * 4 + E * p0.m * 4,
                      "kernel": "k_mlp_fwd", "flops_per_launch": fl_fwd, "avg_launch_ms": fwd_avg,
                      "note": "prescreen arm's dominant kernel; its GELU epilogues on the vector "
                              "ALU, not the matrix cores, bound it"},
