@@ -732,6 +732,106 @@ def run_bo(args):
     print(json.dumps(res), flush=True)
 
 
+def run_hyper(args):
+    """Hyperparameter fitting of one c3 batch (64 sub-searches, d in 2..12, n
+    in 16..400, literal draws): every problem from 4 starts (log-uniform
+    lengthscales in [0.05, 1], signal variance in [0.5, 2], noise variance in
+    [1e-4, 1e-1]), 100 Adam steps up the LML gradient in log space, all 256
+    runs in one batched fit and one gradient launch pair per step.  The
+    metric is LML-gradient evaluations per second (one evaluation = one fit
+    and one gradient of one run); the gradient kernels are timed on their own
+    as well, and the oracle's gradient on the host for one problem."""
+    import torch
+    from paper_2403_08131_amd import gpbo as G
+    from paper_2403_08131_amd import inputs as I
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_stream(torch.cuda.Stream(device=dev))
+    ctx = G.Context(0)
+    probs = I.make_c3(lam=0.1, m=16)
+    B, S, steps = len(probs), 4, args.hyper_steps
+    ldt = max(p.d for p in probs) + 2
+    rng = np.random.default_rng(77)
+    th0 = np.zeros((B, S, ldt))
+    lo = np.zeros((B, ldt))
+    hi = np.zeros((B, ldt))
+    for b, p in enumerate(probs):
+        d = p.d
+        th0[b, :, :d] = rng.uniform(np.log(0.05), 0.0, size=(S, d))
+        th0[b, :, d] = np.log(rng.uniform(0.5, 2.0, size=S))
+        th0[b, :, d + 1] = np.log(rng.uniform(1e-4, 1e-1, size=S))
+        lo[b, :d + 2] = np.log([1e-3] * d + [1e-2, 1e-6])
+        hi[b, :d + 2] = np.log([1e2] * d + [1e2, 1.0])
+    dp = [dict(X=torch.tensor(p.X, device=dev), y=torch.tensor(p.y, device=dev)) for p in probs]
+    # warm-up (graphs, allocator pools), then the timed fit
+    G.fit_hyper_batched(ctx, dp, th0, lo, hi, steps=2, lr=0.05, want_models=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, status, th, lml, jit, _ = G.fit_hyper_batched(ctx, dp, th0, lo, hi, steps=steps, lr=0.05,
+                                                      want_models=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    evals = B * S * (steps + 1)
+    # LML at the starting points (one start per problem) for the gain
+    _, _, _, lml0, _, _ = G.fit_hyper_batched(ctx, dp, th0[:, :1, :], lo, hi, steps=0,
+                                              want_models=False)
+    # the gradient kernels alone on the 64 fitted models at the optimum
+    pr = [dict(X=dp[b]["X"], y=dp[b]["y"], lengthscale=list(np.exp(th[b, :probs[b].d])),
+               signal_var=float(np.exp(th[b, probs[b].d])),
+               noise_var=float(np.exp(th[b, probs[b].d + 1]) + jit[b])) for b in range(B)]
+    _, models, _, _ = G.fit_batched(ctx, pr)
+    for _ in range(3):
+        G.lml_grad_batched(ctx, models)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        G.lml_grad_batched(ctx, models)
+    e1.record()
+    torch.cuda.synchronize()
+    g_ms = e0.elapsed_time(e1) / 20
+    for m_ in models:
+        m_.free()
+    # algorithmic flops of one batched gradient: K^-1 from the inverse factor
+    # (sum over tiles of 64^3 multiply-adds x (nb - I) slabs) ~ n^3 / 3 per model
+    # as counted by the kernel, plus n^2 (d + 2) for the sums
+    npads = [((p.n + 63) // 64) * 64 for p in probs]
+    fl = sum(2 * np_ ** 3 / 3 + 2 * p.n * p.n * (p.d + 2) for np_, p in zip(npads, probs))
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        p = max(probs, key=lambda q: q.n)
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < 5.0:
+            O.lml_grad(p.X, p.y, p.lengthscale, O.SE, 1.0, 1e-2)
+            k += 1
+        dt = (time.perf_counter() - t0) / k
+        cpu = {"value": 1.0 / dt, "unit": "LML-gradient evaluations/s", "cores": 1,
+               "kind": "oracle", "cpu": cpu_model(),
+               "sample": f"the oracle's fit + LML gradient of the largest problem (n={p.n}, "
+                         f"d={p.d}), serial, {k} evaluations"}
+    res = {
+        "metric": "LML-gradient evaluations/s (batched fit + gradient, multi-start Adam)",
+        "value": evals / wall, "unit": "evaluations/s", "n_gpus": 1, "steps": steps,
+        "warmup": 2, "ms_per_step": wall / (steps + 1) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp64", "data": "synthetic",
+        "config": {"workload": f"hyper: one c3 batch (64 sub-searches, d 2..12, n 16..400), "
+                               f"4 starts each, {steps} Adam steps (lr 0.05) in log space",
+                   "problems": B, "starts": S},
+        "lml_gain": {"mean_start_lml": float(np.mean(lml0)), "mean_final_lml": float(np.mean(lml)),
+                     "problems_improved": int(np.sum(lml > lml0)), "of": B,
+                     "jittered": int(np.sum(jit > 0))},
+        "gradient_kernels": {"ms_per_batched_call": g_ms, "flops": fl,
+                             "achieved_tflops": fl / (g_ms * 1e-3) / 1e12,
+                             "peak_fp64_vector_tflops": PEAKS["fp64"],
+                             "note": "float64 FMA on the vector ALU; latency-bound at these n"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -752,6 +852,7 @@ def main():
     ap.add_argument("--lr", type=float, default=3e-3, help="c4: Adam learning rate")
     ap.add_argument("--fwd-occupancy", type=int, default=0,
                     help="c4: network forward workgroups per compute unit (0 = fill the GPU)")
+    ap.add_argument("--hyper-steps", type=int, default=100, help="hyper: Adam steps per start")
     ap.add_argument("--case", type=int, default=3, help="bo: case of the paper's family (1..5)")
     ap.add_argument("--pool", type=int, default=65536, help="bo: candidates per search and iteration")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -778,6 +879,8 @@ def main():
         return run_c3(args)
     if args.workload == "bo":
         return run_bo(args)
+    if args.workload == "hyper":
+        return run_hyper(args)
 
     import torch
     from paper_2403_08131_amd import gpbo as G
