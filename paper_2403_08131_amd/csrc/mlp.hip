@@ -33,36 +33,38 @@ constexpr int MT = 64;  // samples per forward / backward workgroup
 __device__ __forceinline__ float bfr(float x) { return __uint_as_float((unsigned)f2bf(x) << 16); }
 __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
 
-// GELU u Phi(u) and its derivative Phi(u) + u phi(u), with the normal CDF
-// from the rational approximation of erf of Abramowitz & Stegun (1964),
-// formula 7.1.25: for x >= 0, erf x = 1 - t (a1 + t (a2 + t a3)) exp(-x^2),
-// t = 1 / (1 + p x), p = 0.47047, absolute error <= 2.5e-5 -- two orders
-// below the bfloat16 rounding (2^-9 relative) the activations receive next.
-// Branch-free; exp(-u^2 / 2) is shared with the density.
+// GELU u Phi(u) and its derivative Phi(u) + u phi(u).  The normal tail
+// Phi(-a), a = |u|, is exp2(p(min(a, 6))) with p the degree-5 polynomial,
+// p(0) = -1 (Phi(0) = 1/2 exactly), fitted to log2 Phi(-a) on [0, 6] for the
+// smallest absolute error of Phi(-a) by gelu_tail_fit.py: absolute error
+// <= 3.0e-7 (relative <= 1.8e-6 for a <= 1, where most activations lie and
+// where a relative error turns directly into bfloat16 rounding flips);
+// beyond a = 6 the tail stays at its value there (~1e-9).  One v_exp_f32
+// and no reciprocal per activation.
+__device__ __forceinline__ float normal_tail(float u) {
+  const float m = fminf(fabsf(u), 6.0f);
+  float p = fmaf(m, -0.0005204600165598094f, 0.0073975189588963985f);
+  p = fmaf(m, p, -0.05256125330924988f);
+  p = fmaf(m, p, -0.4592546820640564f);
+  p = fmaf(m, p, -1.1510913372039795f);
+  p = fmaf(m, p, -1.0f);
+  return __builtin_amdgcn_exp2f(p);
+}
 struct NormalCdf {
   float Phi, e;  // Phi(u) and exp(-u^2 / 2)
 };
-// Phi(-|u|) = t (a1 + t (a2 + t a3)) exp(-u^2/2) / 2 with t = 1 / (1 + p |u| /
-// sqrt 2) (the formula above at x = |u| / sqrt 2), the 1/2 folded into the
-// coefficients.
-__device__ __forceinline__ float normal_tail(float u, float* e_out = nullptr) {
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.47047f * 0.70710678118654752440f, fabsf(u), 1.0f));
-  float q = fmaf(t, 0.5f * 0.7478556f, 0.5f * -0.0958798f);
-  q = fmaf(t, q, 0.5f * 0.3480242f);
-  q *= t;
-  const float e = __builtin_amdgcn_exp2f((u * (-0.5f * 1.44269504088896340736f)) * u);
-  if (e_out) *e_out = e;
-  return q * e;
-}
 __device__ __forceinline__ NormalCdf normal_cdf(float u) {
-  float e;
-  const float tail = normal_tail(u, &e);  // Phi(-|u|)
+  const float tail = normal_tail(u);  // Phi(-|u|)
+  const float e = __builtin_amdgcn_exp2f((u * (-0.5f * 1.44269504088896340736f)) * u);
   return {u >= 0.0f ? 1.0f - tail : tail, e};
 }
 // GELU u Phi(u) = max(u, 0) - |u| Phi(-|u|): the same value for either sign,
 // without a select on the sign.
 __device__ __forceinline__ float gelu(float u) {
-  return fmaf(-fabsf(u), normal_tail(u), fmaxf(u, 0.0f));
+  // one canonicalisation (an accumulator value is not known to be canonical)
+  // serves both the clamp inside the tail and the max
+  const float c = __builtin_canonicalizef(u);
+  return fmaf(-fabsf(c), normal_tail(c), fmaxf(c, 0.0f));
 }
 __device__ __forceinline__ float gelu_grad(float u) {
   const NormalCdf c = normal_cdf(u);
@@ -555,19 +557,23 @@ __global__ void k_mlp_zero_step(MlpDev M) {
 __global__ void k_mlp_mark(MlpDev M) { M.step[1] = M.step[0]; }
 
 // Ensemble mean / population standard deviation over the members and EI.
-__global__ void k_ens_ei(int E, int64_t m, const float* __restrict__ out, float fbest,
+// The member mean and spread, z and EI in float64 (a few dozen operations per
+// candidate): when the members nearly agree the spread is a small difference
+// of the outputs, and float32 would carry a relative error of ~eps |mean| /
+// sd into z; only the result is rounded to float32.
+__global__ void k_ens_ei(int E, int64_t m, const float* __restrict__ out, double fbest,
                          float* __restrict__ ei) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
        i += (int64_t)gridDim.x * blockDim.x) {
-    float s = 0.0f;
+    double s = 0.0;
     for (int e = 0; e < E; ++e) s += out[(int64_t)e * m + i];
-    const float mean = s / E;
-    float q = 0.0f;
+    const double mean = s / E;
+    double q = 0.0;
     for (int e = 0; e < E; ++e) {
-      const float d = out[(int64_t)e * m + i] - mean;
+      const double d = out[(int64_t)e * m + i] - mean;
       q += d * d;
     }
-    ei[i] = ei_of<float>(mean, sqrtf(q / E), fbest);
+    ei[i] = (float)ei_of<double>(mean, sqrt(q / E), fbest);
   }
 }
 
@@ -919,8 +925,8 @@ void mlp_forward(MlpState* st, int64_t m, const float* Xc, float* out, hipStream
 
 void mlp_ens_ei(MlpState* st, int64_t m, const float* out, double fbest, float* ei, hipStream_t s) {
   const int g = (int)std::min<int64_t>(8192, ceil_div(m, 256));
-  hipLaunchKernelGGL(k_ens_ei, dim3(std::max(g, 1)), dim3(256), 0, s, st->dev.E, m, out,
-                     (float)fbest, ei);
+  hipLaunchKernelGGL(k_ens_ei, dim3(std::max(g, 1)), dim3(256), 0, s, st->dev.E, m, out, fbest,
+                     ei);
 }
 
 void mlp_ens_lcb(MlpState* st, int64_t m, const float* out, double kappa, float* score,

@@ -179,8 +179,9 @@ def test_mlp_training_reduces_loss_and_graph_replays(ctx):
 def test_prescreen_ei_matches_oracle_and_sort(ctx):
     """gpbo_mlp_prescreen: the ensemble EI (member mean, population standard
     deviation, EI against f_best) of every candidate equals the oracle's
-    ens_ei on the device's member outputs to float32 evaluation error, and
-    the top-k indices equal a sort of the device's own float32 EI."""
+    ens_ei on the device's member outputs to the float32 rounding of the
+    result (the kernel evaluates in float64), and the top-k indices equal a
+    sort of the device's own float32 EI."""
     flat = _init(13)
     net = G.Mlp(ctx, torch.tensor(flat, dtype=torch.float32, device=DEV).contiguous(), E, D, H)
     X, _, _ = _data(30000, seed=14)
@@ -192,15 +193,15 @@ def test_prescreen_ei_matches_oracle_and_sort(ctx):
         idx, ei = net.prescreen(Xd, fbest, k, want_ei=True)
         ei = ei.double().cpu().numpy()
         mu_e, sd_e, ref = O.ens_ei(outs, fbest)
-        err = np.max(np.abs(ei - ref)) / np.max(ref)
-        # deep in the tail (z << 0) the two terms of EI cancel: float32
-        # evaluation loses about z^2 units of 2^-24 there
+        # float64 evaluation on both sides: the float32 result differs by its
+        # rounding, 2^-24 relative in float32's normal range and half the
+        # subnormal spacing (2^-150) below it
+        err = np.abs(ei - ref) - 2.0 ** -23 * np.abs(ref)
         j = int(np.argmax(ref))
         z = (fbest - mu_e[j]) / sd_e[j]
-        bound = 1e-5 + 16 * (z * z + 1) * 2.0 ** -24
-        print(f"  prescreen EI f_best={fbest:.3f}: max |dEI| / EI_max = {err:.2e} (z* {z:.1f}, "
-              f"bound {bound:.1e})")
-        assert err <= bound, fbest
+        print(f"  prescreen EI f_best={fbest:.3f}: max |dEI| beyond float32 rounding = "
+              f"{np.max(err):.2e} (EI_max {np.max(ref):.2e}, z* {z:.1f})")
+        assert np.all(err <= 2.0 ** -149), fbest
         want = np.lexsort((np.arange(ei.size), -ei))[:k]
         assert np.array_equal(idx.cpu().numpy(), want), fbest
     net.free()
