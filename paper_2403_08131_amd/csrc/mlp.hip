@@ -87,7 +87,7 @@ struct MlpDev {
   float* master;           // E x P
   float* mom1;             // E x P
   float* mom2;             // E x P
-  unsigned short* W1b;     // E x H x D
+  unsigned short* W1b;     // E x H x DP (rows zero-padded from D to DP)
   unsigned short* W2b;     // E x H x H  [out][in]
   unsigned short* W2Tb;    // E x H x H  [in][out]
   unsigned short* w3b;     // E x H
@@ -112,8 +112,10 @@ __global__ void k_mlp_cast(MlpDev M) {
     M.W2b[(int64_t)e * H * H + i] = b;
     M.W2Tb[(int64_t)e * H * H + (int64_t)in * H + o] = b;
   }
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H * D; i += gridDim.x * blockDim.x)
-    M.W1b[(int64_t)e * H * D + i] = f2bf(p[i]);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H * M.DP; i += gridDim.x * blockDim.x) {
+    const int h = i / M.DP, k = i % M.DP;
+    M.W1b[(int64_t)e * H * M.DP + i] = k < D ? f2bf(p[h * D + k]) : (unsigned short)0;
+  }
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H; i += gridDim.x * blockDim.x)
     M.w3b[(int64_t)e * H + i] = f2bf(p[off_w3(M) + i]);
 }
@@ -148,11 +150,17 @@ __host__ __device__ inline int64_t fwd_items(int ntile, int E) {
   return ((int64_t)(ntile + 7) / 8) * 8 * E;
 }
 template <bool TRAIN>
-__global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const float* __restrict__ X,
+__global__ void __launch_bounds__(256, 2) k_mlp_fwd(MlpDev M, int64_t n, const float* __restrict__ X,
                                                  FwdOut O, int ntile) {
   extern __shared__ __align__(16) unsigned char sm[];
   const int H = M.H, D = M.D, DP = M.DP;
   const int t = threadIdx.x, lane = t % 64, wave = wave_id();
+  const int ldh = H + 8;  // bf16 row stride of the h1 tile (16-byte rows, skewed banks)
+  const int ldx = fwd_ldx(DP);
+  unsigned short* hA = (unsigned short*)sm;  // [MT][ldh]
+  unsigned short* xb = hA + MT * ldh;        // [MT][ldx], samples in bfloat16, zero from column D
+  float* red = (float*)(xb + MT * ldx);      // [4][MT]
+  for (int q = t; q < MT * (DP - D); q += 256) xb[(q / (DP - D)) * ldx + D + q % (DP - D)] = 0;
   const int64_t items = fwd_items(ntile, M.E);
   for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
     const int64_t local = item / 8;
@@ -160,33 +168,38 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
     const int64_t tile = (local / M.E) * 8 + item % 8;
     if (tile >= ntile) continue;
     const int64_t i0 = tile * MT;
-    const int ldh = H + 8;  // bf16 row stride of the h1 tile (16-byte rows, skewed banks)
-    const int ldx = fwd_ldx(DP);
-    unsigned short* hA = (unsigned short*)sm;                   // [MT][ldh]
-    unsigned short* xb = hA + MT * ldh;                         // [MT][ldx]
-    unsigned short* w1 = xb + MT * ldx;                         // [H][ldx]
-    float* red = (float*)(w1 + H * ldx);                        // [4][MT]
     const float* p = M.master + e * M.P;
-    for (int q = t; q < MT * DP; q += 256) {
-      const int r = q / DP, k = q % DP;
-      const int64_t i = i0 + r;
-      xb[r * ldx + k] = (i < n && k < D) ? f2bf(X[i * D + k]) : (unsigned short)0;
-    }
-    for (int q = t; q < H * DP; q += 256) {
-      const int h = q / DP, k = q % DP;
-      w1[h * ldx + k] = k < D ? M.W1b[((int64_t)e * H + h) * D + k] : (unsigned short)0;
+    // the item's samples, rounded to bfloat16 (four columns per store when
+    // D is a multiple of 4; rows past n are zeros)
+    if (D % 4 == 0) {
+      const int D4 = D / 4;
+      for (int q = t; q < MT * D4; q += 256) {
+        const int r = q / D4, c = 4 * (q % D4);
+        const int64_t i = i0 + r;
+        const float4 v = i < n ? *(const float4*)(X + i * D + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+        *(uint2*)(xb + r * ldx + c) = make_uint2(pack_bf16x2(v.x, v.y), pack_bf16x2(v.z, v.w));
+      }
+    } else {
+      for (int q = t; q < MT * D; q += 256) {
+        const int r = q / D, k = q % D;
+        const int64_t i = i0 + r;
+        xb[r * ldx + k] = i < n ? f2bf(X[i * D + k]) : (unsigned short)0;
+      }
     }
     __syncthreads();
+    // W1 (bfloat16, zero-padded rows of DP) is read as the matrix-core operand
+    // straight from global memory: it is 16 KB per member and stays in L2
+    const unsigned short* W1 = M.W1b + (int64_t)e * H * DP;
     const int ocol = wave * 64;  // this wave's 64 columns (hidden units / outputs)
     // the accumulators start from the biases: lane's entry r of block b is unit
     // ocol + 16b + 4(lane/16) + r for every sample block
     f4 acc[4][4];
-  #pragma unroll
+    #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int h0 = ocol + b * 16 + 4 * (lane / 16);
       const f4 bb = {p[off_b1(M) + h0], p[off_b1(M) + h0 + 1], p[off_b1(M) + h0 + 2],
                      p[off_b1(M) + h0 + 3]};
-  #pragma unroll
+      #pragma unroll
       for (int a = 0; a < 4; ++a) acc[a][b] = bb;
     }
     // layer 1, transposed: C[h][s] = sum_k W1[h][k] x[s][k] (A = W1 rows, B =
@@ -195,15 +208,15 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
     // sample-major h1 tile as one 8-byte store
     for (int k0 = 0; k0 < DP; k0 += 32) {
       us8 av[4], bv[4];
-  #pragma unroll
+      #pragma unroll
       for (int a = 0; a < 4; ++a)
         av[a] = *(const us8*)(xb + (a * 16 + lane % 16) * ldx + k0 + 8 * (lane / 16));
-  #pragma unroll
+      #pragma unroll
       for (int b = 0; b < 4; ++b)
-        bv[b] = *(const us8*)(w1 + (ocol + b * 16 + lane % 16) * ldx + k0 + 8 * (lane / 16));
-  #pragma unroll
+        bv[b] = *(const us8*)(W1 + (ocol + b * 16 + lane % 16) * DP + k0 + 8 * (lane / 16));
+      #pragma unroll
       for (int a = 0; a < 4; ++a)
-  #pragma unroll
+        #pragma unroll
         for (int b = 0; b < 4; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, bv[b]),
                                                               __builtin_bit_cast(bf8, av[a]),
@@ -211,14 +224,14 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
     }
     // layer-1 epilogue: lane holds hidden units h0 .. h0+3 (h0 = ocol + 16b +
     // 4(lane/16)) of sample 16a + lane%16
-  #pragma unroll
+    #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int h0 = ocol + b * 16 + 4 * (lane / 16);
-  #pragma unroll
+      #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int row = a * 16 + lane % 16;
         float pre[4], g[4];
-  #pragma unroll
+        #pragma unroll
         for (int r = 0; r < 4; ++r) {
           pre[r] = acc[a][b][r];
           g[r] = gelu(pre[r]);
@@ -239,12 +252,12 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
         if (i0 + r < n) O.h1T[((int64_t)e * H + h) * n + i0 + r] = hA[r * ldh + h];
       }
     }
-  #pragma unroll
+    #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int j0 = ocol + b * 16 + 4 * (lane / 16);
       const f4 bb = {p[off_b2(M) + j0], p[off_b2(M) + j0 + 1], p[off_b2(M) + j0 + 2],
                      p[off_b2(M) + j0 + 3]};
-  #pragma unroll
+      #pragma unroll
       for (int a = 0; a < 4; ++a) acc[a][b] = bb;
     }
     // layer 2, transposed the same way: C[j][s] = sum_k W2[j][k] h1[s][k];
@@ -252,15 +265,15 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
     const unsigned short* W2 = M.W2b + (int64_t)e * H * H;
     for (int k0 = 0; k0 < H; k0 += 32) {
       us8 av[4], bv[4];
-  #pragma unroll
+      #pragma unroll
       for (int a = 0; a < 4; ++a)
         av[a] = *(const us8*)(hA + (a * 16 + lane % 16) * ldh + k0 + 8 * (lane / 16));
-  #pragma unroll
+      #pragma unroll
       for (int b = 0; b < 4; ++b)
         bv[b] = *(const us8*)(W2 + (int64_t)(ocol + b * 16 + lane % 16) * H + k0 + 8 * (lane / 16));
-  #pragma unroll
+      #pragma unroll
       for (int a = 0; a < 4; ++a)
-  #pragma unroll
+        #pragma unroll
         for (int b = 0; b < 4; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, bv[b]),
                                                               __builtin_bit_cast(bf8, av[a]),
@@ -270,7 +283,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
     // sample 16a + lane%16; h2 = bf16(GELU(pre2)) and its dot with w3 stay in
     // the lane until the four lane groups are summed
     float rowsum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  #pragma unroll
+    #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int j0 = ocol + b * 16 + 4 * (lane / 16);
       float w3[4];
@@ -279,11 +292,11 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
       w3[1] = __uint_as_float(w3p.x & 0xffff0000u);
       w3[2] = __uint_as_float(w3p.y << 16);
       w3[3] = __uint_as_float(w3p.y & 0xffff0000u);
-  #pragma unroll
+      #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int row = a * 16 + lane % 16;
         float pre[4], g[4];
-  #pragma unroll
+        #pragma unroll
         for (int r = 0; r < 4; ++r) {
           pre[r] = acc[a][b][r];
           g[r] = gelu(pre[r]);
@@ -301,7 +314,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(MlpDev M, int64_t n, const floa
       }
     }
     // sum over the four lane groups, then over the four waves
-  #pragma unroll
+    #pragma unroll
     for (int a = 0; a < 4; ++a) {
       float v = rowsum[a];
       v += __shfl_xor(v, 16);
@@ -409,32 +422,32 @@ __global__ void __launch_bounds__(256) k_gemm_nt(Gemm g) {
   const unsigned short* Bm = g.B + (int64_t)e * g.sB;
   const int kb = split * g.kchunk, ke = min(g.K, kb + g.kchunk);
   f4 acc[2][2];
-#pragma unroll
+  #pragma unroll
   for (int a = 0; a < 2; ++a)
-#pragma unroll
+    #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f4{0, 0, 0, 0};
   for (int k0 = kb; k0 < ke; k0 += 32) {
     us8 av[2], bv[2];
-#pragma unroll
+    #pragma unroll
     for (int a = 0; a < 2; ++a)
       av[a] = *(const us8*)(A + (int64_t)(r0 + a * 16 + lane % 16) * g.K + k0 + 8 * (lane / 16));
-#pragma unroll
+    #pragma unroll
     for (int b = 0; b < 2; ++b)
       bv[b] = *(const us8*)(Bm + (int64_t)(c0 + b * 16 + lane % 16) * g.K + k0 + 8 * (lane / 16));
-#pragma unroll
+    #pragma unroll
     for (int a = 0; a < 2; ++a)
-#pragma unroll
+      #pragma unroll
       for (int b = 0; b < 2; ++b)
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, av[a]),
                                                             __builtin_bit_cast(bf8, bv[b]),
                                                             acc[a][b], 0, 0, 0);
   }
   if (EPI == EPI_STORE) {
-#pragma unroll
+    #pragma unroll
     for (int a = 0; a < 2; ++a)
-#pragma unroll
+      #pragma unroll
       for (int b = 0; b < 2; ++b)
-#pragma unroll
+        #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = r0 + a * 16 + 4 * (lane / 16) + r;
           const int col = c0 + b * 16 + lane % 16;
@@ -448,15 +461,15 @@ __global__ void __launch_bounds__(256) k_gemm_nt(Gemm g) {
   // samples, so it is stored feature-major: each lane's four consecutive
   // samples are one 8-byte store); the unrounded value feeds the bias
   // gradient as column sums over this wave's 32 samples.
-#pragma unroll
+  #pragma unroll
   for (int b = 0; b < 2; ++b) {
     const int col = c0 + b * 16 + lane % 16;
     float csum = 0.0f;
-#pragma unroll
+    #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const int row0 = r0 + a * 16 + 4 * (lane / 16);
       unsigned short q[4];
-#pragma unroll
+      #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t o = ((int64_t)e * g.M + row0 + r) * g.N + col;
         const float v = acc[a][b][r] * gelu_grad(g.pre1[o]);
@@ -623,7 +636,7 @@ int mlp_dp(int D) { return D <= 32 ? 32 : 64; }
 
 size_t mlp_fwd_smem(int D, int H) {
   const int ldx = mlp_dp(D) + 8;
-  return (size_t)MT * (H + 8) * 2 + (size_t)MT * ldx * 2 + (size_t)H * ldx * 2 + 4 * MT * 4;
+  return (size_t)MT * (H + 8) * 2 + (size_t)MT * ldx * 2 + 4 * MT * 4;
 }
 
 MlpState* mlp_create(Ctx* c, int E, int D, int H, const float* init, hipStream_t s) {
@@ -645,7 +658,7 @@ MlpState* mlp_create(Ctx* c, int E, int D, int H, const float* init, hipStream_t
   M.master = (float*)dmalloc(c, pb);
   M.mom1 = (float*)dmalloc(c, pb);
   M.mom2 = (float*)dmalloc(c, pb);
-  M.W1b = (unsigned short*)dmalloc(c, (size_t)E * H * D * 2);
+  M.W1b = (unsigned short*)dmalloc(c, (size_t)E * H * mlp_dp(D) * 2);
   M.W2b = (unsigned short*)dmalloc(c, (size_t)E * H * H * 2);
   M.W2Tb = (unsigned short*)dmalloc(c, (size_t)E * H * H * 2);
   M.w3b = (unsigned short*)dmalloc(c, (size_t)E * H * 2);
