@@ -304,12 +304,15 @@ def run_c4(args):
 
     def pre_step(r):
         p = r["p"]
-        # the network's few launches go first: the fit's launch sequence keeps
-        # the host busy for ~2.5 ms at n = 4096, and the pass over the pool
-        # must not wait behind it
+        # queue order: the network's pass over the pool (one launch), then the
+        # fit (its launch sequence keeps the host busy for ~2.5 ms at n =
+        # 4096), then the selection of the top K1 (a dozen small launches that
+        # only the judge, after the fit, waits for)
         with torch.cuda.stream(s_net):
-            idx, _ = r["net"].prescreen_lcb(r["Xc"], 0.0, K1)
+            outs = r["net"].forward(r["Xc"])
         model = G.fit_async(ctx, r["X"], r["y"], p.lengthscale, p.kernel, p.signal_var, p.noise_var)
+        with torch.cuda.stream(s_net):
+            idx, _ = G.ens_select(ctx_net, outs, G.SELECT_LCB, 0.0, K1)
         done = torch.cuda.Event()
         done.record(s_net)
         torch.cuda.current_stream().wait_event(done)

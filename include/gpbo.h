@@ -509,12 +509,27 @@ gpbo_status gpbo_mlp_set_occupancy(gpbo_ctx ctx, gpbo_mlp mlp, int32_t workgroup
 /* Member outputs on m candidates: out is device members x m float. */
 gpbo_status gpbo_mlp_forward(gpbo_ctx ctx, gpbo_mlp mlp, int64_t m, const float* Xc,
                              float* out);
+/* The selection half of a prescreen, on member outputs already computed
+ * (gpbo_mlp_forward), so that a step can queue the network's pass, then the
+ * Gaussian-process fit, then the selection: outs is device E x m float
+ * (member-major); rule GPBO_SELECT_EI scores the ensemble EI against f_best
+ * = arg, GPBO_SELECT_LCB the negated lower confidence bound with kappa =
+ * arg >= 0; then the k best indices as gpbo_mlp_prescreen returns them.
+ * score_out (device m float) may be NULL.  Uses the context's scratch
+ * (allocated or grown on first need).  Asynchronous. */
+#define GPBO_SELECT_EI 0
+#define GPBO_SELECT_LCB 1
+gpbo_status gpbo_ens_select(gpbo_ctx ctx, int32_t E, int64_t m, const float* outs, int32_t rule,
+                            double arg, int64_t k, int64_t* topk_idx, float* score_out);
 /* Prescreen: ensemble mean and population standard deviation over members,
- * EI against f_best (in the network's output units), then the indices of the
- * k largest EI (device int64): for k <= 8192 sorted by descending EI,
- * ascending index among ties; for larger k (up to m) the same set in
- * ascending index order (see gpbo_topk_set).  ei_out (device m float) may
- * be NULL.  Asynchronous. */
+ * EI against f_best (in the network's output units, evaluated in float64 and
+ * rounded to float), then the indices of the k largest EI (device int64): for
+ * k <= 8192 sorted by descending EI, ascending index among ties; for larger k
+ * (up to m) the same set in ascending index order (see gpbo_topk_set).
+ * ei_out (device m float) may be NULL.  Asynchronous.  Called on the
+ * network's own context, the pass keeps its workspace (member outputs,
+ * scores, selection scratch) between calls and allocates only when a larger
+ * pool comes; such calls must stay in that context's stream order. */
 gpbo_status gpbo_mlp_prescreen(gpbo_ctx ctx, gpbo_mlp mlp, int64_t m, const float* Xc,
                                double f_best, int64_t k, int64_t* topk_idx, float* ei_out);
 /* Prescreen by the ensemble's lower confidence bound: score = -(mean - kappa

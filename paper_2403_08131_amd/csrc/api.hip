@@ -1569,6 +1569,11 @@ struct gpbo_mlp_s {
   Ctx* ctx;
   MlpState* st;
   int E, D, H;
+  // Workspace of the pass over a pool (member outputs, scores, top-k
+  // scratch), kept between calls on the network's own context so that a
+  // step allocates nothing; grown when a larger pool comes.
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
 };
 
 gpbo_status gpbo_mlp_create(gpbo_ctx c, int32_t members, int32_t d_in, int32_t hidden,
@@ -1593,6 +1598,7 @@ gpbo_status gpbo_mlp_free(gpbo_mlp mlp) {
   if (!mlp) return GPBO_OK;
   DeviceGuard g(mlp->ctx->device);
   mlp->ctx->live_mlps.erase(mlp);
+  if (mlp->ws) dfree(mlp->ctx, mlp->ws);
   mlp_destroy(mlp->st);
   delete mlp;
   return GPBO_OK;
@@ -1708,16 +1714,24 @@ static gpbo_status prescreen(Ctx* c, gpbo_mlp mlp, int64_t m, const float* Xc, b
   // up to the sort's limit the k indices come sorted by score; beyond it, as
   // the same set in ascending index order
   const bool sorted = k <= topk_max_k();
-  float* outs = (float*)dmalloc(c, (size_t)mlp->E * m * sizeof(float));
-  float* sc = score_out ? score_out : (float*)dmalloc(c, (size_t)m * sizeof(float));
-  void* scratch =
-      k > 0 ? dmalloc(c, sorted ? topk_scratch_bytes(m, k) : topk_set_scratch_bytes(m)) : nullptr;
-  if (!outs || !sc || (k > 0 && !scratch)) {
-    dfree(c, outs);
-    if (!score_out) dfree(c, sc);
-    dfree(c, scratch);
-    return fail(c, GPBO_E_OOM, "prescreen scratch allocation failed");
+  Carve cv;
+  const size_t o_outs = cv.take((size_t)mlp->E * m * sizeof(float));
+  const size_t o_sc = score_out ? 0 : cv.take((size_t)m * sizeof(float));
+  const size_t o_scr =
+      k > 0 ? cv.take(sorted ? topk_scratch_bytes(m, k) : topk_set_scratch_bytes(m)) : 0;
+  // on the network's own context the workspace persists (stream order makes
+  // the next call's reuse safe); another context allocates for the call
+  const bool own = c == mlp->ctx;
+  if (own && mlp->ws_bytes < cv.bytes) {
+    if (mlp->ws) dfree(c, mlp->ws);
+    mlp->ws = dmalloc(c, cv.bytes);
+    mlp->ws_bytes = mlp->ws ? cv.bytes : 0;
   }
+  char* wsb = own ? (char*)mlp->ws : (char*)dmalloc(c, cv.bytes);
+  if (!wsb) return fail(c, GPBO_E_OOM, "prescreen workspace allocation of %zu bytes failed", cv.bytes);
+  float* outs = (float*)(wsb + o_outs);
+  float* sc = score_out ? score_out : (float*)(wsb + o_sc);
+  void* scratch = k > 0 ? (void*)(wsb + o_scr) : nullptr;
   timed_mlp_forward(c, mlp->st, m, Xc, outs);
   if (lcb)
     mlp_ens_lcb(mlp->st, m, outs, arg, sc, s);
@@ -1728,9 +1742,39 @@ static gpbo_status prescreen(Ctx* c, gpbo_mlp mlp, int64_t m, const float* Xc, b
     else launch_topk_set_into(m, sc, k, topk_idx, scratch, s);
   }
   HIP_TRY(c, hipGetLastError());
-  dfree(c, outs);
-  if (!score_out) dfree(c, sc);
-  dfree(c, scratch);
+  if (!own) dfree(c, wsb);
+  return GPBO_OK;
+}
+
+gpbo_status gpbo_ens_select(gpbo_ctx c, int32_t E, int64_t m, const float* outs, int32_t rule,
+                            double arg, int64_t k, int64_t* topk_idx, float* score_out) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (E < 1 || m < 0 || k < 0 || k > m || (m > 0 && !outs) || (k > 0 && !topk_idx) ||
+      (rule != GPBO_SELECT_EI && rule != GPBO_SELECT_LCB))
+    return fail(c, GPBO_E_INVALID_ARG, "invalid selection arguments");
+  if (rule == GPBO_SELECT_LCB && !(arg >= 0.0))
+    return fail(c, GPBO_E_INVALID_ARG, "kappa must be >= 0");
+  if (m > 0xffffffffLL) return fail(c, GPBO_E_UNSUPPORTED, "m >= 2^32 is not supported");
+  if (m == 0) return GPBO_OK;
+  DeviceGuard g(c->device);
+  hipStream_t s = c->stream;
+  const bool sorted = k <= topk_max_k();
+  Carve cv;
+  const size_t o_sc = score_out ? 0 : cv.take((size_t)m * sizeof(float));
+  const size_t o_scr =
+      k > 0 ? cv.take(sorted ? topk_scratch_bytes(m, k) : topk_set_scratch_bytes(m)) : 0;
+  {
+    const gpbo_status st = ensure_red(c, std::max<size_t>(cv.bytes, 256));
+    if (st != GPBO_OK) return st;
+  }
+  char* wsb = (char*)c->red;
+  float* sc = score_out ? score_out : (float*)(wsb + o_sc);
+  ens_score(E, m, outs, rule == GPBO_SELECT_LCB, arg, sc, s);
+  if (k > 0) {
+    if (sorted) launch_topk_into(m, sc, k, topk_idx, wsb + o_scr, s);
+    else launch_topk_set_into(m, sc, k, topk_idx, wsb + o_scr, s);
+  }
+  HIP_TRY(c, hipGetLastError());
   return GPBO_OK;
 }
 

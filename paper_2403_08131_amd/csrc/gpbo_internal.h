@@ -407,5 +407,9 @@ void mlp_set_occupancy(MlpState* st, int wg_per_cu);
 void mlp_ens_ei(MlpState* st, int64_t m, const float* out, double fbest, float* ei, hipStream_t s);
 void mlp_ens_lcb(MlpState* st, int64_t m, const float* out, double kappa, float* score,
                  hipStream_t s);
+// Either rule on E member outputs (E x m): ensemble EI against arg = f_best,
+// or the negated lower confidence bound with arg = kappa.
+void ens_score(int E, int64_t m, const float* out, bool lcb, double arg, float* score,
+               hipStream_t s);
 
 }  // namespace gpbo

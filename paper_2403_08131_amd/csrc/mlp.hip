@@ -936,17 +936,23 @@ void mlp_forward(MlpState* st, int64_t m, const float* Xc, float* out, hipStream
                      M, m, Xc, fo, ntile);
 }
 
-void mlp_ens_ei(MlpState* st, int64_t m, const float* out, double fbest, float* ei, hipStream_t s) {
+void ens_score(int E, int64_t m, const float* out, bool lcb, double arg, float* score,
+               hipStream_t s) {
   const int g = (int)std::min<int64_t>(8192, ceil_div(m, 256));
-  hipLaunchKernelGGL(k_ens_ei, dim3(std::max(g, 1)), dim3(256), 0, s, st->dev.E, m, out, fbest,
-                     ei);
+  if (lcb)
+    hipLaunchKernelGGL(k_ens_lcb, dim3(std::max(g, 1)), dim3(256), 0, s, E, m, out, (float)arg,
+                       score);
+  else
+    hipLaunchKernelGGL(k_ens_ei, dim3(std::max(g, 1)), dim3(256), 0, s, E, m, out, arg, score);
+}
+
+void mlp_ens_ei(MlpState* st, int64_t m, const float* out, double fbest, float* ei, hipStream_t s) {
+  ens_score(st->dev.E, m, out, false, fbest, ei, s);
 }
 
 void mlp_ens_lcb(MlpState* st, int64_t m, const float* out, double kappa, float* score,
                  hipStream_t s) {
-  const int g = (int)std::min<int64_t>(8192, ceil_div(m, 256));
-  hipLaunchKernelGGL(k_ens_lcb, dim3(std::max(g, 1)), dim3(256), 0, s, st->dev.E, m, out,
-                     (float)kappa, score);
+  ens_score(st->dev.E, m, out, true, kappa, score, s);
 }
 
 }  // namespace gpbo

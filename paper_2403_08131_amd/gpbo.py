@@ -87,6 +87,8 @@ _SIGS = {
                                          C.POINTER(HyperOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.POINTER(C.c_void_p), C.POINTER(C.c_int32)]),
+    "gpbo_ens_select": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int32,
+                                  C.c_double, C.c_int64, C.c_void_p, C.c_void_p]),
     "gpbo_mlp_set_occupancy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
     "gpbo_append_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p,
                                       C.c_int32, C.c_void_p]),
@@ -415,6 +417,22 @@ def fit_hyper_batched(ctx: Context, problems, theta0, lo, hi, steps=100, lr=0.05
         models = [Model(ctx, C.c_void_p(hs[b]), pr["X"].shape[0], pr["X"].shape[1]) if hs[b]
                   else None for b, pr in enumerate(problems)]
     return st, list(status), th, lml, jit, models
+
+
+SELECT_EI, SELECT_LCB = 0, 1
+
+
+def ens_select(ctx: Context, outs, rule, arg, k, want_score=False):
+    """gpbo_ens_select on member outputs (device float32, E x m): the k best
+    indices by ensemble EI (rule SELECT_EI, arg = f_best) or negated LCB
+    (SELECT_LCB, arg = kappa); returns (idx, score or None)."""
+    assert outs.dtype == torch.float32 and outs.is_contiguous() and outs.dim() == 2
+    E, m = outs.shape
+    idx = torch.empty(k, dtype=torch.int64, device=ctx.device)
+    sc = torch.empty(m, dtype=torch.float32, device=ctx.device) if want_score else None
+    ctx.check(lib().gpbo_ens_select(ctx.h, E, m, _ptr(outs), int(rule), float(arg), int(k),
+                                    _ptr(idx), _ptr(sc)))
+    return idx, sc
 
 
 def status_batched(ctx: Context, models):

@@ -207,6 +207,27 @@ def test_prescreen_ei_matches_oracle_and_sort(ctx):
     net.free()
 
 
+def test_ens_select_equals_prescreen(ctx):
+    """gpbo_ens_select on the member outputs of gpbo_mlp_forward gives the
+    prescreen's indices and scores, both rules, sorted and set selections."""
+    flat = _init(17)
+    net = G.Mlp(ctx, torch.tensor(flat, dtype=torch.float32, device=DEV).contiguous(), E, D, H)
+    X, _, _ = _data(20000, seed=18)
+    Xd = torch.tensor(X, dtype=torch.float32, device=DEV)
+    outs = net.forward(Xd)
+    fbest = float(outs.double().mean(0).quantile(0.05))
+    for k in (1, 777, 12000):
+        i1, s1 = net.prescreen_lcb(Xd, 0.5, k, want_score=True)
+        i2, s2 = G.ens_select(ctx, outs, G.SELECT_LCB, 0.5, k, want_score=True)
+        assert torch.equal(i1, i2) and torch.equal(s1, s2), k
+        i1, e1 = net.prescreen(Xd, fbest, k, want_ei=True)
+        i2, e2 = G.ens_select(ctx, outs, G.SELECT_EI, fbest, k, want_score=True)
+        assert torch.equal(i1, i2) and torch.equal(e1, e2), k
+    with pytest.raises(G.GpboError):
+        G.ens_select(ctx, outs, 7, 0.0, 5)
+    net.free()
+
+
 def test_prescreen_lcb_matches_oracle_and_sort(ctx):
     """The LCB score equals the oracle's on the device's member outputs to
     float32 rounding, and the top-k indices equal a sort of the device's own
