@@ -67,11 +67,17 @@ def kernel_source_hash(files=("score.hip", "score_common.h", "gpbo_internal.h"))
 # (5 x 1,048,576 x 4) = 104.9 MB.
 FWD_SOURCES = ("mlp.hip", "score_common.h")
 FWD_TRAFFIC = {
-    "kernel_sha": "c58a79da6df9e71e",
-    "fetch_kib": 43916.5,
+    "kernel_sha": "43de25d50997aee1",
+    "fetch_kib": 44036.0,
     "write_kib": 20480.0,
     "fetch_scale": 262144 / 131083.5,
     "write_scale": 1.0,
+    # the same pass over the pool, full occupancy, counters per dispatch:
+    # vector-ALU busy share (VALUBusy) and matrix-core busy share (MfmaUtil)
+    "valu_busy_pct": 71.0,
+    "mfma_util_pct": 18.0,
+    "valu_insts_per_wave": 2143,
+    "mfma_insts_per_wave": 144,
 }
 FWD_TRAFFIC["bytes_per_launch"] = round(1024 * (FWD_TRAFFIC["fetch_kib"] * FWD_TRAFFIC["fetch_scale"]
                                                 + FWD_TRAFFIC["write_kib"] * FWD_TRAFFIC["write_scale"]))
@@ -405,6 +411,11 @@ def run_c4(args):
                                  if kernel_source_hash(FWD_SOURCES) == FWD_TRAFFIC["kernel_sha"]
                                  else None),
                      "algorithmic_bytes_per_launch": p0.m * p0.d * 4 + E * p0.m * 4,
+                     "counters": ({k: FWD_TRAFFIC[k] for k in ("valu_busy_pct", "mfma_util_pct",
+                                                            "valu_insts_per_wave",
+                                                            "mfma_insts_per_wave")}
+                                  if kernel_source_hash(FWD_SOURCES) == FWD_TRAFFIC["kernel_sha"]
+                                  else None),
                      "kernel": "k_mlp_fwd", "flops_per_launch": fl_fwd, "avg_launch_ms": fwd_avg,
                      "note": "prescreen arm's dominant kernel; its GELU epilogues on the vector "
                              "ALU, not the matrix cores, bound it; it runs as a persistent grid "
