@@ -452,12 +452,12 @@ def run_c4(args):
 def run_c3(args):
     """Batched independent sub-searches: three launches of 64 problems each
     (coupling lambda = 0, 0.1, 0.5, one per launch), d in {2..12}, n in
-    [16, 400], 8192 candidates per problem.  One step fits all problems of a
-    launch (one float64 launch sequence, queued without synchronising) and
-    scores all their pools with one persistent BF16 matrix-core launch
-    (replayed from its HIP graph: the batch shape repeats from step to step),
-    for the three launches, then reads the 3 x 64 argmaxes back and checks
-    the fits' statuses.  `value` = candidates scored per second of whole
+    [16, 400], 8192 candidates per problem.  One step fits all 192 problems
+    (one batched float64 launch sequence, queued without synchronising;
+    ``--c3-fit per-launch``: one per launch), scores the pools of each
+    launch with one persistent BF16 matrix-core launch (replayed from its
+    HIP graph: the batch shape repeats from step to step), then reads the
+    3 x 64 argmaxes back and checks the fits' statuses.  `value` = candidates scored per second of whole
     steps.  The scoring kernel's own time is taken in a second pass with
     kernel timing on (eager launches bracketed by HIP events)."""
     import ctypes as C
@@ -482,33 +482,50 @@ def run_c3(args):
         eis = [torch.empty(p.m, dtype=torch.float32, device=dev) for p in probs]
         am = torch.empty(len(probs), dtype=torch.int64, device=dev)
         em = torch.empty(len(probs), dtype=torch.float64, device=dev)
-        batches.append(dict(lam=lam, probs=probs, specs=specs, Xcs=Xcs, eis=eis, am=am, em=em))
+        batches.append(dict(lam=lam, probs=probs, specs=specs, Xcs=Xcs, eis=eis, am=am, em=em,
+                            batch=G.ProblemBatch(specs),
+                            ms=(C.c_int64 * len(probs))(*[x.shape[0] for x in Xcs]),
+                            xs=(C.c_void_p * len(probs))(*[x.data_ptr() for x in Xcs]),
+                            ep=(C.c_void_p * len(probs))(*[e.data_ptr() for e in eis])))
     B = len(batches[0]["probs"])
+    # the fit of all three launches' sub-searches as one batched call (one
+    # float64 launch sequence over 3 x 64 problems fills the GPU better than
+    # three of 64), or one call per launch
+    merged = args.c3_fit == "merged"
+    everything = G.ProblemBatch([s for bt in batches for s in bt["specs"]])
 
     def launch(bt, models, mus=None, sgs=None):
         hs = (C.c_void_p * B)(*[mo.h.value for mo in models])
-        ms = (C.c_int64 * B)(*[x.shape[0] for x in bt["Xcs"]])
-        xs = (C.c_void_p * B)(*[x.data_ptr() for x in bt["Xcs"]])
-        ep = (C.c_void_p * B)(*[e.data_ptr() for e in bt["eis"]])
         mp = (C.c_void_p * B)(*[t.data_ptr() for t in mus]) if mus else None
         sp = (C.c_void_p * B)(*[t.data_ptr() for t in sgs]) if sgs else None
-        ctx.check(G.lib().gpbo_score_batched(ctx.h, B, hs, ms, xs, pr, mp, sp, ep,
+        ctx.check(G.lib().gpbo_score_batched(ctx.h, B, hs, bt["ms"], bt["xs"], pr, mp, sp, bt["ep"],
                                              C.c_void_p(bt["am"].data_ptr()),
                                              C.c_void_p(bt["em"].data_ptr())))
 
+    def fit(group):
+        st, models, status, _ = G.fit_batched(ctx, group, sync=False)
+        if st != G.OK:
+            raise SystemExit(f"batched fit failed: {status}")
+        return models
+
     def step(keep=False):
-        # the three batched fits and scorings are queued back to back; one
-        # synchronisation reads the argmaxes, then the fits' statuses (one
-        # copy per batch)
+        # the fits and the three scoring launches are queued back to back;
+        # one synchronisation reads the argmaxes, then the fits' statuses
+        # (one copy per batched fit)
         kept = []
-        for bt in batches:
-            st, models, status, _ = G.fit_batched(ctx, bt["specs"], sync=False)
-            if st != G.OK:
-                raise SystemExit(f"batched fit failed: {status}")
-            launch(bt, models)
-            kept.append(models)
+        if merged:
+            models = fit(everything)
+            for i, bt in enumerate(batches):
+                kept.append(models[i * B:(i + 1) * B])
+                launch(bt, kept[-1])
+            groups = [models]
+        else:
+            for bt in batches:
+                kept.append(fit(bt["batch"]))
+                launch(bt, kept[-1])
+            groups = kept
         picks = [bt["am"].cpu() for bt in batches]  # the next configuration of every sub-search
-        for models in kept:
+        for models in groups:
             st, status, _ = G.status_batched(ctx, models)
             if st != G.OK:
                 raise SystemExit(f"batched fit failed: {status}")
@@ -532,11 +549,11 @@ def run_c3(args):
     ms_step = a.elapsed_time(b) / args.steps
     m_step = sum(p.m for bt in batches for p in bt["probs"])
 
-    # fit alone (three batched fits), for the breakdown
+    # the fits alone, synchronised, for the breakdown
     t0 = time.perf_counter()
     for _ in range(3):
-        for bt in batches:
-            _, models, _, _ = G.fit_batched(ctx, bt["specs"])
+        for group in ([everything] if merged else [bt["batch"] for bt in batches]):
+            _, models, _, _ = G.fit_batched(ctx, group)
             for mo in models:
                 mo.free()
     torch.cuda.synchronize()
@@ -615,9 +632,11 @@ def run_c3(args):
                                f"d in 2..12, n in 16..400, 8192 candidates each, SE-ARD "
                                f"log-uniform [0.05,1], {prec} contractions, fp64 fit",
                    "B": B, "launches_per_step": 3, "m_per_problem": 8192,
+                   "fit": ("one batched call over the 3 x 64 sub-searches" if merged
+                           else "one batched call per launch"),
                    "n_per_problem": [p.n for p in batches[0]["probs"]][:8] + ["..."],
                    "precision": prec},
-        "breakdown_ms": {"fit_3_batches": fit_ms, "timed_kernel_per_step": 3 * k_avg},
+        "breakdown_ms": {"fits_per_step": fit_ms, "timed_kernel_per_step": 3 * k_avg},
         "error_vs_fp64": errs,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAKS[prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAKS[prec], "traffic": None, "kernel": "k_score_batched",
@@ -870,6 +889,9 @@ def main():
     ap.add_argument("--lr", type=float, default=3e-3, help="c4: Adam learning rate")
     ap.add_argument("--fwd-occupancy", type=int, default=1,
                     help="c4: network forward workgroups per compute unit (0 = fill the GPU)")
+    ap.add_argument("--c3-fit", default="merged", choices=("merged", "per-launch"),
+                    help="c3: fit the three launches' sub-searches in one batched call or one "
+                         "call per launch")
     ap.add_argument("--hyper-steps", type=int, default=100, help="hyper: Adam steps per start")
     ap.add_argument("--case", type=int, default=3, help="bo: case of the paper's family (1..5)")
     ap.add_argument("--pool", type=int, default=65536, help="bo: candidates per search and iteration")

@@ -314,20 +314,35 @@ def fit_async(ctx: Context, X, y, lengthscale, kernel=KERNEL_SE, signal_var=1.0,
     return Model(ctx, h, X.shape[0], X.shape[1])
 
 
+class ProblemBatch:
+    """Problems marshalled once into the C array gpbo_fit_batched reads, for
+    repeated batched fits of the same observations and hyperparameters (a
+    benchmark, or a search refitted in place): holds the array and keeps the
+    tensors and lengthscale arrays it points to alive."""
+
+    def __init__(self, problems):
+        self.B = len(problems)
+        self.arr = (Problem * self.B)()
+        self._keep = []
+        self.shapes = []
+        for b, pr in enumerate(problems):
+            p, ls = _problem(pr["X"], pr["y"], pr["lengthscale"], pr.get("kernel", KERNEL_SE),
+                             pr.get("signal_var", 1.0), pr.get("noise_var", 1e-4),
+                             pr.get("normalize_y", True), pr.get("refine_alpha", False))
+            self.arr[b] = p
+            self._keep.append((pr["X"], pr["y"], ls))
+            self.shapes.append(tuple(pr["X"].shape))
+
+
 def fit_batched(ctx: Context, problems, sync=True):
-    """gpbo_fit_batched on a list of dicts with the :func:`fit` arguments.
-    With sync=False, gpbo_fit_batched_async: the statuses returned are those
-    of the checks made before queueing (``Model.status()`` gives the
-    factorisation's) and the LML list is empty."""
-    B = len(problems)
-    arr = (Problem * B)()
-    keep = []
-    for b, pr in enumerate(problems):
-        p, ls = _problem(pr["X"], pr["y"], pr["lengthscale"], pr.get("kernel", KERNEL_SE),
-                         pr.get("signal_var", 1.0), pr.get("noise_var", 1e-4),
-                         pr.get("normalize_y", True), pr.get("refine_alpha", False))
-        arr[b] = p
-        keep.append(ls)
+    """gpbo_fit_batched on a list of dicts with the :func:`fit` arguments (or
+    a :class:`ProblemBatch`).  With sync=False, gpbo_fit_batched_async: the
+    statuses returned are those of the checks made before queueing
+    (``Model.status()`` gives the factorisation's) and the LML list is empty."""
+    if not isinstance(problems, ProblemBatch):
+        problems = ProblemBatch(problems)
+    B = problems.B
+    arr = problems.arr
     hs = (C.c_void_p * B)()
     lml = (C.c_double * B)()
     status = (C.c_int32 * B)()
@@ -336,8 +351,8 @@ def fit_batched(ctx: Context, problems, sync=True):
     else:
         st = lib().gpbo_fit_batched_async(ctx.h, B, arr, hs, status)
         lml = []
-    models = [Model(ctx, C.c_void_p(hs[b]), pr["X"].shape[0], pr["X"].shape[1]) if status[b] == OK
-              else None for b, pr in enumerate(problems)]
+    models = [Model(ctx, C.c_void_p(hs[b]), sh[0], sh[1]) if status[b] == OK else None
+              for b, sh in enumerate(problems.shapes)]
     return st, models, list(status), list(lml)
 
 

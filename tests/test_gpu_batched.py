@@ -338,6 +338,35 @@ def test_fit_batched_async_matches_sync(ctx):
         mo.free()
 
 
+def test_problem_batch_refits_equal_list_fits(ctx):
+    """A ProblemBatch marshalled once and fitted twice (the second time as
+    part of a larger batch built from the same problems) gives the LMLs and
+    bit-identical scores of the list form."""
+    probs = _problems(B=4, m=500, seed=12)
+    specs = [dict(X=_t(p.X), y=_t(p.y), lengthscale=p.lengthscale, kernel=p.kernel,
+                  signal_var=p.signal_var, noise_var=p.noise_var) for p in probs]
+    st, m_ref, _, lml_ref = G.fit_batched(ctx, specs)
+    assert st == G.OK
+    pb = G.ProblemBatch(specs)
+    both = G.ProblemBatch(specs + specs)
+    Xcs = [_t(p.Xc, torch.float32) for p in probs]
+    for batch in (pb, pb, both):
+        st, ms, status, _ = G.fit_batched(ctx, batch, sync=False)
+        assert st == G.OK and len(ms) == batch.B
+        st, status, lml = G.status_batched(ctx, ms)
+        assert st == G.OK and lml[:4] == lml_ref and lml[batch.B - 4:] == lml_ref
+        for k, (mo, x) in enumerate(zip(ms[batch.B - 4:], Xcs)):
+            assert (mo.n, mo.d) == tuple(specs[k]["X"].shape)
+            o = G.score(ctx, mo, x, "fp32")
+            ref = G.score(ctx, m_ref[k], x, "fp32")
+            torch.cuda.synchronize()
+            assert torch.equal(o["ei"], ref["ei"])
+        for mo in ms:
+            mo.free()
+    for mo in m_ref:
+        mo.free()
+
+
 def test_batched_full_c3_shape_smoke(ctx):
     """The literal batch shape: 64 sub-searches, d in 2..12, n in 16..400,
     8192 candidates each; every argmax is a valid index with finite EI."""
