@@ -109,6 +109,8 @@ struct Model {
   // Score operands, built on first use per precision.
   int nx = 0;                   // row stride of Xs32 / Xs64 (n padded with far-away points)
   float* Xs32 = nullptr;        // d x nx, coordinates scaled for the float32 kernels
+  float* Xp32 = nullptr;        // dist_kp(d) x nx, observation operand of the matrix-core
+                                // squared distances (bfloat16 scoring)
   float* sc32 = nullptr;        // d, coordinate scales for candidates (float32 kernels)
   double* sc64 = nullptr;       // d, coordinate scales (float64 kernels)
   double* Xs64 = nullptr;       // d x nx, scaled coordinates (float64 kernels)
@@ -276,6 +278,7 @@ struct ScoreArgs {
   const void* pk;                  // packed sf2 * Linv
   const void* alpha;               // sf2 * alpha (precision-typed)
   const void* Xs;                  // scaled observations, dimension-major (d x nx)
+  const float* Xp;                 // observation operand of the matrix-core distances
   const void* sc;                  // candidate coordinate scales
   const double* stats;             // device statistics (ymean, ystd, fbest)
   double sf2;

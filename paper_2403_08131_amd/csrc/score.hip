@@ -56,6 +56,7 @@ struct PrepDesc {
   const double* sc;    // 2d: 1 / l, then the float32 kernels' scales
   double* Xs64;        // d x nx
   float* Xs32;         // d x nx
+  float* Xp32;         // dist_kp(d) x nx
   const int64_t* off;  // ntiles + 1 row-tile block offsets (NULL: no packed operand)
   void* pk;            // packed blocks (+ PF zero slack blocks)
   int64_t blocks;      // stored blocks including the slack
@@ -106,15 +107,53 @@ __global__ void __launch_bounds__(256) k_prep_pack(const PrepDesc* __restrict__ 
   }
 }
 
+// Centre of the coordinates of the matrix-core distances: the middle of the
+// unit box the search parameters are normalised to.  The expansion's
+// rounding error grows with |u|^2, which centring reduces about fourfold for
+// points spread over the box; distances themselves are unchanged.
+constexpr double kDistCentre = 0.5;
+
 // Transposed scaled coordinates of the observations, both precisions:
 // Xs64[k][j] = X[j][k] / l_k, Xs32[k][j] = X[j][k] sc[d + k]; padding points
-// past n.
+// past n.  Then the observation operand of the matrix-core distances:
+// p_j = (2 u_j, -|u_j|^2, -1, 0 ...) with u_j = (X[j] - kDistCentre) sc32
+// rounded to float32 (the squared norm summed in float64 and rounded once), stored
+// dimension-major with the points of each 64-point block permuted so that
+// one 16-byte load gives a lane its point in all four 16-point tiles:
+// Xp32[k][64 b + 4 r + t] = p_{64 b + 16 t + r}[k].  A padding point has
+// -|u|^2 = -1e30 (covariance exactly 0) and zeros elsewhere.
 __global__ void __launch_bounds__(256) k_prep_obs(const PrepDesc* __restrict__ D) {
   const PrepDesc& P = D[blockIdx.y];
   if (!P.obs) return;
-  const int n = P.n, d = P.d, nx = P.nx;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)nx * d;
+  const int n = P.n, d = P.d, nx = P.nx, kp = dist_kp(d);
+  const int64_t ns = (int64_t)nx * d;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ns + (int64_t)nx * kp;
        e += (int64_t)gridDim.x * blockDim.x) {
+    if (e >= ns) {
+      const int64_t f = e - ns;
+      const int k = (int)(f / nx), col = (int)(f % nx);
+      const int w = col % 64;
+      const int j = col - w + 16 * (w % 4) + w / 4;  // the point stored at this column
+      float v = 0.0f;
+      if (j < n) {
+        auto u = [&](int q) {
+          return (float)((P.X[(int64_t)j * d + q] - kDistCentre) * P.sc[d + q]);
+        };
+        if (k < d) {
+          v = 2.0f * u(k);
+        } else if (k == d) {
+          double s2 = 0.0;
+          for (int q = 0; q < d; ++q) s2 += (double)u(q) * (double)u(q);
+          v = (float)-s2;
+        } else if (k == d + 1) {
+          v = -1.0f;
+        }
+      } else if (k == d) {
+        v = -1e30f;
+      }
+      P.Xp32[f] = v;
+      continue;
+    }
     const int64_t k = e / nx, j = e % nx;
     if (j < n) {
       const double x = P.X[j * d + k];
@@ -145,9 +184,11 @@ __device__ __forceinline__ void stage_candidates(const ScoreArgs& A, int64_t til
   const int64_t c0 = tile * TM, m = A.m;
   const In* __restrict__ Xc = (const In*)A.Xc;
   const C* __restrict__ sc = (const C*)A.sc;
+  // the matrix-core distances take coordinates centred on the unit box
+  const C z = dist_mfma(P, d) ? C(kDistCentre) : C(0);
   for (int e = tid; e < TM * d; e += NW * 64) {
     const int c = e / d, k = e % d;
-    xcT[k * TM + c] = c0 + c < m ? (C)Xc[(c0 + c) * d + k] * sc[k] : C(0);
+    xcT[k * TM + c] = c0 + c < m ? ((C)Xc[(c0 + c) * d + k] - z) * sc[k] : C(0);
   }
 }
 
@@ -259,6 +300,93 @@ __device__ __forceinline__ void phase_cross(const ScoreArgs& A, typename PT<P>::
     body(0, CG, w, NW);
   else
     body((w / wp) * CG, (NW / wp) * CG, w % wp, wp);
+}
+
+// Phase 1 of the bfloat16 path (d + 2 <= 4 DIST_SMAX): the squared distances
+// on the float32 matrix cores.  With the observation operand
+// p_j = (2 u_j, -|u_j|^2, -1, 0 ...) and the candidate operand
+// q_c = (u_c, 1, |u_c|^2, 0 ...), p_j . q_c = -|u_j - u_c|^2: one
+// 16 x 16 x 4 product per (16 points, 16 candidates, 4 terms).  The
+// expansion loses to cancellation about eps_32 (|u_j|^2 + |u_c|^2) of
+// absolute accuracy in the squared distance (relative to the covariance: the
+// same times ln 2), below the bfloat16 rounding of the tile for scaled
+// coordinates up to |u|^2 ~ 1e4.  Wave w takes candidate group w mod
+// (TM / 16) and every (NW / (TM / 16))-th 64-point block from w / (TM / 16);
+// lane l holds four consecutive points 4 (l / 16) .. of each 16-point tile
+// for candidate l mod 16, so the covariances of a tile leave as one 8-byte
+// LDS store and the mean partial as one accumulator per lane.  Rows
+// 0 .. NW / (TM / 16) - 1 of mu_part are written.
+template <int KERN, int TM, int NW>
+__device__ __forceinline__ void phase_cross_mfma(const ScoreArgs& A, unsigned short* kt,
+                                                 const float* xcT, float* mu_part, int w) {
+  constexpr int NCG = TM / 16;   // candidate groups of 16
+  constexpr int WPG = NW / NCG;  // waves per candidate group
+  static_assert(NCG <= NW && NW % NCG == 0, "candidate groups must divide the waves");
+  const int d = A.d, npj = A.npj, ldk = A.ldk, nx = A.nx;
+  const int S = dist_kp(d) / 4;  // matrix-core steps
+  const int lane = threadIdx.x % 64;
+  const int r = lane % 16, kq = lane / 16;
+  const int cg = w % NCG, pr = w / NCG;
+  const int c = cg * 16 + r;
+  // candidate operand of step s: q_c[4 s + l / 16], from the LDS tile
+  float nrm = 0.0f;
+  for (int k = 0; k < d; ++k) {
+    const float u = xcT[k * TM + c];
+    nrm = fmaf(u, u, nrm);
+  }
+  float qb[DIST_SMAX];
+#pragma unroll
+  for (int s = 0; s < DIST_SMAX; ++s) {
+    const int k = 4 * s + kq;
+    float v = 0.0f;
+    if (k < d) v = xcT[k * TM + c];
+    else if (k == d) v = 1.0f;
+    else if (k == d + 1) v = nrm;
+    qb[s] = v;
+  }
+  const float* __restrict__ Xp = A.Xp + kq * (int64_t)nx + 4 * r;
+  const float* __restrict__ alpha = (const float*)A.alpha + 4 * kq;
+  unsigned short* krow = kt + c * ldk + 4 * kq;
+  float macc = 0.0f;
+  for (int jb = pr * 64; jb < npj; jb += WPG * 64) {
+    f4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    // the observation operand in two halves of DIST_SMAX / 2 steps (the
+    // second only for d + 2 > 2 DIST_SMAX), to bound the live registers
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      constexpr int SH = DIST_SMAX / 2;
+      if (h * SH >= S) break;
+      f4 a[SH];
+#pragma unroll
+      for (int s = 0; s < SH; ++s)
+        if (h * SH + s < S) a[s] = *(const f4*)(Xp + 4 * (h * SH + s) * (int64_t)nx + jb);
+#pragma unroll
+      for (int s = 0; s < SH; ++s)
+        if (h * SH + s < S)
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s][t], qb[h * SH + s], acc[t], 0, 0, 0);
+    }
+    f4 al[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) al[t] = *(const f4*)(alpha + jb + 16 * t);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float kv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        kv[i] = cov_from_r2<KERN>(fmaxf(-acc[t][i], 0.0f));
+        macc = fmaf(kv[i], al[t][i], macc);
+      }
+      *(uint2*)(krow + jb + 16 * t) = make_uint2(bf16_pair(kv[0], kv[1]), bf16_pair(kv[2], kv[3]));
+    }
+  }
+  // lanes l, l + 16, l + 32, l + 48 hold the same candidate
+  macc += __shfl_xor(macc, 16);
+  macc += __shfl_xor(macc, 32);
+  if (lane < 16) mu_part[pr * TM + cg * 16 + lane] = macc;
 }
 
 // Phase 2: v = (sf2 Linv) khat on the matrix cores; ssq_part[w][c] receives
@@ -397,15 +525,15 @@ __device__ __forceinline__ void phase_variance(const ScoreArgs& A, const typenam
 
 // Phase 3 (one wave): outputs and the tile's argmax from the partials of
 // NW waves.
-template <int P, int TM, int NW, bool SPLIT = false>
+template <int P, int TM, int NW>
 __device__ __forceinline__ void phase_finish(const ScoreArgs& A, int64_t tile,
                                              const typename PT<P>::Acc* mu_part,
-                                             const typename PT<P>::Acc* ssq_part) {
+                                             const typename PT<P>::Acc* ssq_part, int wp) {
   using Acc = typename PT<P>::Acc;
   using In = typename PT<P>::In;
   const int lane = threadIdx.x % 64;
   const int64_t c0 = tile * TM, m = A.m;
-  const int wp = SPLIT ? cross_wp<NW>(A.npj) : NW;  // rows of mu_part written by phase 1
+  // wp: rows of mu_part written by phase 1
   double bv = -INFINITY;
   int64_t bi = -1;
   for (int c = lane; c < TM; c += 64) {
@@ -443,11 +571,23 @@ __device__ __forceinline__ void score_tile(const ScoreArgs& A, int64_t tile,
   const int wave = wave_id();
   stage_candidates<P, TM, FW>(A, tile, xcT, threadIdx.x);
   __syncthreads();
-  phase_cross<P, KERN, TM, FW, 0, CG, SPLIT>(A, kt, xcT, mu_part, wave);
+  int mu_rows;
+  if constexpr (P == GPBO_BF16) {
+    if (dist_mfma(P, d)) {
+      phase_cross_mfma<KERN, TM, FW>(A, kt, xcT, mu_part, wave);
+      mu_rows = FW / (TM / 16);
+    } else {
+      phase_cross<P, KERN, TM, FW, 0, CG, SPLIT>(A, kt, xcT, mu_part, wave);
+      mu_rows = SPLIT ? cross_wp<FW>(A.npj) : FW;
+    }
+  } else {
+    phase_cross<P, KERN, TM, FW, 0, CG, SPLIT>(A, kt, xcT, mu_part, wave);
+    mu_rows = SPLIT ? cross_wp<FW>(A.npj) : FW;
+  }
   __syncthreads();
   phase_variance<P, TM, FW, RT>(A, kt, ssq_part, wave);
   __syncthreads();
-  if (wave == 0) phase_finish<P, TM, FW, SPLIT>(A, tile, mu_part, ssq_part);
+  if (wave == 0) phase_finish<P, TM, FW>(A, tile, mu_part, ssq_part, mu_rows);
 }
 
 // Below 64 candidates per workgroup the LDS tile leaves room for a second
@@ -582,8 +722,12 @@ __global__ void __launch_bounds__(256) k_plan_batched(const ScoreArgs* __restric
   }
 }
 
+// Two workgroups per CU: the bfloat16 variant is held to the 128 registers
+// of four waves per SIMD (its matrix-core distances would otherwise take
+// more); the others stay there without a cap.
 template <int P, int TM>
-__global__ void __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(1, 4)))
+__global__ void __launch_bounds__(FT)
+    __attribute__((amdgpu_waves_per_eu(P == GPBO_BF16 ? 4 : 1, 4)))
 k_score_batched(const ScoreArgs* __restrict__ descs, int B, int cls, const void* plan,
                 unsigned* __restrict__ counter) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -622,6 +766,7 @@ k_score_batched(const ScoreArgs* __restrict__ descs, int B, int cls, const void*
     A.mu = global_ptr(A.mu);
     A.sigma = global_ptr(A.sigma);
     A.Xs = global_ptr(A.Xs);
+    A.Xp = global_ptr(A.Xp);
     A.sc = global_ptr(A.sc);
     A.alpha = global_ptr(A.alpha);
     A.pk = global_ptr(A.pk);
@@ -813,7 +958,7 @@ void ensure_score_operands(Ctx* c, Model* const* models, int B, int prec, hipStr
   struct Part {
     bool obs, score;
     std::vector<int64_t> off;
-    size_t osc, ooff, oX64, oX32, opk, oal;
+    size_t osc, ooff, oX64, oX32, oXp, opk, oal;
   };
   std::vector<Part> parts(nb);
   for (int k = 0; k < nb; ++k) {
@@ -836,6 +981,7 @@ void ensure_score_operands(Ctx* c, Model* const* models, int B, int prec, hipStr
     if (q.obs) {
       q.oX64 = cv.take((size_t)nx * M->d * sizeof(double));
       q.oX32 = cv.take((size_t)nx * M->d * sizeof(float));
+      q.oXp = cv.take((size_t)nx * dist_kp(M->d) * sizeof(float));
     }
     if (q.score) {
       q.opk = cv.take((size_t)(q.off.back() + PF) * TI * kb * es);
@@ -879,12 +1025,14 @@ void ensure_score_operands(Ctx* c, Model* const* models, int B, int prec, hipStr
       M->sc32 = (float*)(M->sc64 + 2 * d);
       M->Xs64 = (double*)(g + q.oX64);
       M->Xs32 = (float*)(g + q.oX32);
+      M->Xp32 = (float*)(g + q.oXp);
       M->blk_obs = std::shared_ptr<void>(grp, g + q.oX64);
       pd.obs = 1;
       pd.sc = M->sc64;
       pd.Xs64 = M->Xs64;
       pd.Xs32 = M->Xs32;
-      max_elems = std::max<int64_t>(max_elems, (int64_t)pd.nx * d);
+      pd.Xp32 = M->Xp32;
+      max_elems = std::max<int64_t>(max_elems, (int64_t)pd.nx * (d + dist_kp(d)));
       any_obs = true;
     }
     if (q.score) {
@@ -945,6 +1093,7 @@ ScoreArgs make_score_args(Model* M, int prec, int tm) {
   a.pk = M->pk[prec];
   a.alpha = M->alphaT[prec];
   a.Xs = prec == GPBO_FP64 ? (const void*)M->Xs64 : (const void*)M->Xs32;
+  a.Xp = M->Xp32;
   a.sc = prec == GPBO_FP64 ? (const void*)M->sc64 : (const void*)M->sc32;
   a.stats = M->stats;
   a.sf2 = M->sf2;

@@ -78,6 +78,15 @@ __device__ __forceinline__ unsigned short f2bf_hw(float f) {
   return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
 
+// Two float32 values as a pair of bfloat16 (round to nearest even, the
+// first in the low half): one v_cvt_pk_bf16_f32.
+__device__ __forceinline__ unsigned bf16_pair(float lo, float hi) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+  const f2 v = {lo, hi};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, b2));
+}
+
 template <typename K, typename C>
 __device__ __forceinline__ K to_k(C v);
 template <>
@@ -90,6 +99,16 @@ __device__ __forceinline__ unsigned short to_k<unsigned short, float>(float v) {
 __device__ __forceinline__ void store_elem(double* p, double v) { *p = v; }
 __device__ __forceinline__ void store_elem(float* p, double v) { *p = (float)v; }
 __device__ __forceinline__ void store_elem(unsigned short* p, double v) { *p = f2bf((float)v); }
+
+// Matrix-core squared distances of the bfloat16 path: the contraction depth
+// (d coordinates and two extra terms, rounded up to the 4 of one float32
+// matrix-core step) and the largest number of steps taken that way (larger d
+// form the distances on the vector ALU).
+__host__ __device__ constexpr int dist_kp(int d) { return (d + 2 + 3) / 4 * 4; }
+constexpr int DIST_SMAX = 8;
+__host__ __device__ constexpr bool dist_mfma(int prec, int d) {
+  return prec == GPBO_BF16 && dist_kp(d) <= 4 * DIST_SMAX;
+}
 
 // Covariance (without the signal variance) from the squared scaled distance.
 // For the float kernels the squared-exponential coordinates carry the factor
