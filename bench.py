@@ -319,6 +319,8 @@ def run_c4(args):
         with torch.cuda.stream(s_net):
             outs = r["net"].forward(r["Xc"])
         model = G.fit_async(ctx, r["X"], r["y"], p.lengthscale, p.kernel, p.signal_var, p.noise_var)
+        # the judge's float32 operands right behind the fit, beside the selection
+        G.score_prepare_batched(ctx, [model], "fp32")
         with torch.cuda.stream(s_net):
             idx, _ = G.ens_select(ctx_net, outs, G.SELECT_LCB, 0.0, K1)
         done = torch.cuda.Event()
@@ -515,6 +517,8 @@ def run_c3(args):
         kept = []
         if merged:
             models = fit(everything)
+            # the scoring operands of all 192 fresh models in one launch pair
+            G.score_prepare_batched(ctx, models, prec)
             for i, bt in enumerate(batches):
                 kept.append(models[i * B:(i + 1) * B])
                 launch(bt, kept[-1])

@@ -359,6 +359,18 @@ gpbo_status gpbo_score_batched(gpbo_ctx ctx, int32_t B, const gpbo_model* models
                                void* const* mu, void* const* sigma, void* const* ei,
                                int64_t* argmax, double* ei_max);
 
+/* Build, now, the scoring operands of B models for a precision (the scaled
+ * observations, the packed inverse factor and scaled alpha), for all of
+ * them in one launch pair on the context's stream (the float64 operands a
+ * GPBO_FP32 batch may escalate to are still built by the scoring call).  gpbo_score and gpbo_score_batched
+ * build what a model lacks on their own; calling this first over all the
+ * models a step will score (several batched launches over fresh fits, Sec.
+ * IV-D) replaces one preparation per scoring call by one for the step.
+ * Operands already built are kept.  Asynchronous; GPBO_E_OOM when the
+ * device allocation fails. */
+gpbo_status gpbo_score_prepare_batched(gpbo_ctx ctx, int32_t B, const gpbo_model* models,
+                                       gpbo_precision prec);
+
 /* Posterior mean and two cheap upper bounds, without the triangular
  * product: the cost is the cross-covariance alone (about 2nd flops and n
  * exponentials per candidate against the n^2 of the variance), so a large

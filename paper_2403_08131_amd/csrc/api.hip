@@ -1128,6 +1128,26 @@ gpbo_status gpbo_score(gpbo_ctx c, gpbo_model M, int64_t m, const void* Xc, gpbo
   return finish_host();
 }
 
+gpbo_status gpbo_score_prepare_batched(gpbo_ctx c, int32_t B, const gpbo_model* models,
+                                       gpbo_precision prec) {
+  if (!c) return GPBO_E_INVALID_ARG;
+  if (B < 0 || (B > 0 && !models)) return fail(c, GPBO_E_INVALID_ARG, "invalid batch arguments");
+  if (prec != GPBO_FP64 && prec != GPBO_FP32 && prec != GPBO_BF16)
+    return fail(c, GPBO_E_INVALID_ARG, "unknown precision %d", (int)prec);
+  if (B == 0) return GPBO_OK;
+  DeviceGuard g(c->device);
+  hipStream_t s = c->stream;
+  for (int b = 0; b < B; ++b)
+    if (!models[b]) return fail(c, GPBO_E_INVALID_ARG, "model %d is NULL", b);
+  for (int b = 0; b < B; ++b) note_stream(models[b], s);
+  std::vector<Model*> mp(models, models + B);
+  ensure_score_operands(c, mp.data(), B, prec, s);
+  for (int b = 0; b < B; ++b)
+    if (!models[b]->blk_obs || !models[b]->blk_score[prec])
+      return fail(c, GPBO_E_OOM, "device allocation of the score operands failed (problem %d)", b);
+  return GPBO_OK;
+}
+
 gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, const int64_t* m,
                                const void* const* Xc, gpbo_precision prec, void* const* mu,
                                void* const* sigma, void* const* ei, int64_t* argmax,

@@ -34,15 +34,17 @@ __device__ __forceinline__ float bfr(float x) { return __uint_as_float((unsigned
 __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
 
 // GELU u Phi(u) and its derivative Phi(u) + u phi(u).  The normal tail
-// Phi(-a), a = |u|, is exp2(p(min(a, 6))) with p the degree-5 polynomial,
-// p(0) = -1 (Phi(0) = 1/2 exactly), fitted to log2 Phi(-a) on [0, 6] for the
-// smallest absolute error of Phi(-a) by gelu_tail_fit.py: absolute error
-// <= 3.0e-7 (relative <= 1.8e-6 for a <= 1, where most activations lie and
-// where a relative error turns directly into bfloat16 rounding flips);
-// beyond a = 6 the tail stays at its value there (~1e-9).  One v_exp_f32
+// Phi(-a), a = |u|, is exp2(p(a)) with p the degree-5 polynomial, p(0) = -1
+// (Phi(0) = 1/2 exactly), fitted to log2 Phi(-a) on [0, 6] for the smallest
+// absolute error of Phi(-a) by gelu_tail_fit.py: absolute error <= 3.0e-7
+// (relative <= 1.8e-6 for a <= 1, where most activations lie and where a
+// relative error turns directly into bfloat16 rounding flips).  Beyond
+// a = 6 p keeps decreasing (p(6) = -30.25; the float32 Horner value is
+// monotone there and reaches -inf, never NaN, for finite a), so the tail
+// needs no clamp: below 8e-10 there, where Phi(-a) < 1e-9.  One v_exp_f32
 // and no reciprocal per activation.
 __device__ __forceinline__ float normal_tail(float u) {
-  const float m = fminf(fabsf(u), 6.0f);
+  const float m = fabsf(u);
   float p = fmaf(m, -0.0005204600165598094f, 0.0073975189588963985f);
   p = fmaf(m, p, -0.05256125330924988f);
   p = fmaf(m, p, -0.4592546820640564f);
@@ -61,8 +63,8 @@ __device__ __forceinline__ NormalCdf normal_cdf(float u) {
 // GELU u Phi(u) = max(u, 0) - |u| Phi(-|u|): the same value for either sign,
 // without a select on the sign.
 __device__ __forceinline__ float gelu(float u) {
-  // one canonicalisation (an accumulator value is not known to be canonical)
-  // serves both the clamp inside the tail and the max
+  // the max needs a canonical operand (an accumulator value is not known to
+  // be one)
   const float c = __builtin_canonicalizef(u);
   return fmaf(-fabsf(c), normal_tail(c), fmaxf(c, 0.0f));
 }

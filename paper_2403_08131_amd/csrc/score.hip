@@ -348,26 +348,49 @@ __device__ __forceinline__ void phase_cross_mfma(const ScoreArgs& A, unsigned sh
   const float* __restrict__ alpha = (const float*)A.alpha + 4 * kq;
   unsigned short* krow = kt + c * ldk + 4 * kq;
   float macc = 0.0f;
+  // The observation operand in two halves of SH steps (the second only for
+  // d + 2 > 4 SH), to bound the live registers; the first half of the next
+  // block is requested before this block's covariances are formed.
+  constexpr int SH = DIST_SMAX / 2;
+  auto load_half = [&](f4 (&a)[SH], int h, int jb) {
+#pragma unroll
+    for (int s = 0; s < SH; ++s)
+      if (h * SH + s < S) a[s] = *(const f4*)(Xp + 4 * (h * SH + s) * (int64_t)nx + jb);
+  };
+  auto mma_half = [&](f4 (&acc)[4], const f4 (&a)[SH], int h) {
+#pragma unroll
+    for (int s = 0; s < SH; ++s)
+      if (h * SH + s < S)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s][t], qb[h * SH + s], acc[t], 0, 0, 0);
+  };
+  // (not at 16 candidates per workgroup: there the register budget of the
+  // variance phase leaves no room for it)
+  constexpr bool PREFETCH = TM >= 32;
+  f4 a0[SH];
+  if constexpr (PREFETCH)
+    if (pr * 64 < npj) load_half(a0, 0, pr * 64);
   for (int jb = pr * 64; jb < npj; jb += WPG * 64) {
     f4 acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    // the observation operand in two halves of DIST_SMAX / 2 steps (the
-    // second only for d + 2 > 2 DIST_SMAX), to bound the live registers
+    if constexpr (PREFETCH) {
+      mma_half(acc, a0, 0);
+      if (S > SH) {
+        f4 a1[SH];
+        load_half(a1, 1, jb);
+        mma_half(acc, a1, 1);
+      }
+      if (jb + WPG * 64 < npj) load_half(a0, 0, jb + WPG * 64);
+    } else {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      constexpr int SH = DIST_SMAX / 2;
-      if (h * SH >= S) break;
-      f4 a[SH];
-#pragma unroll
-      for (int s = 0; s < SH; ++s)
-        if (h * SH + s < S) a[s] = *(const f4*)(Xp + 4 * (h * SH + s) * (int64_t)nx + jb);
-#pragma unroll
-      for (int s = 0; s < SH; ++s)
-        if (h * SH + s < S)
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s][t], qb[h * SH + s], acc[t], 0, 0, 0);
+      for (int h = 0; h < 2; ++h) {
+        if (h * SH >= S) break;
+        f4 a[SH];
+        load_half(a, h, jb);
+        mma_half(acc, a, h);
+      }
     }
     f4 al[4];
 #pragma unroll
@@ -658,8 +681,10 @@ __host__ __device__ inline PlanView plan_view(void* base, int B) {
 // conditioning statistic), then per class an ordered prefix sum of the work
 // items over chunks of 256 problems (descriptor order, i.e. largest first,
 // is kept within each class).
+// It also clears the two item counters the scoring launches pop from.
 __global__ void __launch_bounds__(256) k_plan_batched(const ScoreArgs* __restrict__ dd, int B,
-                                                      int tm0, int tm1, int escalate, void* plan) {
+                                                      int tm0, int tm1, int escalate, void* plan,
+                                                      unsigned* __restrict__ counters) {
   __shared__ int64_t sc[2][256];
   __shared__ int sn[2][256];
   __shared__ int64_t run_items[2];
@@ -669,6 +694,7 @@ __global__ void __launch_bounds__(256) k_plan_batched(const ScoreArgs* __restric
   if (t < 2) {
     run_items[t] = 0;
     run_count[t] = 0;
+    counters[t] = 0u;
   }
   __syncthreads();
   for (int k0 = 0; k0 < B; k0 += 256) {
@@ -783,11 +809,6 @@ k_score_batched(const ScoreArgs* __restrict__ descs, int B, int cls, const void*
     if (threadIdx.x == 0) item_s = (int64_t)nxt;
     __syncthreads();
   }
-}
-
-__global__ void k_reset_counters(unsigned* c) {
-  c[0] = 0u;
-  c[1] = 0u;
 }
 
 // Block-wide (value, index) maximum over np partials.
@@ -1172,9 +1193,8 @@ size_t batch_plan_bytes(int B) {
 void launch_score_batched(const BatchLaunch& L, hipStream_t s,
                           const std::function<void(int)>* mark) {
   const bool esc = L.dd64 != nullptr;
-  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(1), 0, s, L.counters);
   hipLaunchKernelGGL(k_plan_batched, dim3(1), dim3(256), 0, s, L.dd, L.B, L.tm, L.tm64,
-                     esc ? 1 : 0, L.plan);
+                     esc ? 1 : 0, L.plan, L.counters);
   if (mark) (*mark)(0);
   switch (L.prec) {
     case GPBO_FP64:

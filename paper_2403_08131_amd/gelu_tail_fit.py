@@ -1,8 +1,9 @@
 """Coefficients of the normal tail used by the network kernels (csrc/mlp.hip).
 
-Phi(-a) for a = |u| >= 0 is evaluated as exp2(p(min(a, 6))) with p a degree-5
+Phi(-a) for a = |u| >= 0 is evaluated as exp2(p(a)) with p a degree-5
 polynomial with p(0) = -1 (so Phi(0) = 1/2 exactly), fitted to log2 Phi(-a)
-on [0, 6] so as to minimise the absolute error of Phi(-a): least squares on
+on [0, 6] (beyond, p keeps decreasing from p(6) = -30.25, so the kernels use
+it unclamped) so as to minimise the absolute error of Phi(-a): least squares on
 Chebyshev points weighted by Phi(-a) (the linearised error), reweighted by
 Lawson's iteration towards the minimax fit.  The absolute criterion keeps
 the relative error smallest where most activations are, near u = 0, where

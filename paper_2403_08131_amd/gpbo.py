@@ -101,6 +101,8 @@ _SIGS = {
                                      C.POINTER(C.c_int64), C.POINTER(C.c_void_p), C.c_int,
                                      C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]),
+    "gpbo_score_prepare_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p),
+                                             C.c_int]),
     "gpbo_topk": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     "gpbo_topk_noalloc": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     "gpbo_topk_set": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
@@ -521,6 +523,16 @@ def score_batched(ctx: Context, models, Xcs, prec="bf16", want=("ei",), host_arg
                                        _ptr_array(outs.get("sigma")), _ptr_array(outs.get("ei")),
                                        amp, emp))
     return outs, am, emax
+
+
+def score_prepare_batched(ctx: Context, models, prec="bf16"):
+    """gpbo_score_prepare_batched: build the scoring operands of all the
+    models for a precision now (one launch pair), so that later scoring
+    calls on them skip that step."""
+    pr = PREC[prec] if isinstance(prec, str) else int(prec)
+    B = len(models)
+    hs = (C.c_void_p * B)(*[mo.h.value if isinstance(mo.h, C.c_void_p) else mo.h for mo in models])
+    ctx.check(lib().gpbo_score_prepare_batched(ctx.h, B, hs, pr))
 
 
 def topk(ctx: Context, v, k):

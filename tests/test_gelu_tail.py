@@ -2,8 +2,10 @@
 csrc/mlp.hip, evaluated in float32 in the kernel's order (Horner, then
 exp2), reproduce Phi(-a) on [0, 6] within the stated bounds against scipy's
 log_ndtr (absolute error <= 5e-7, relative error <= 5e-6 for a <= 1,
-Phi(0) = 1/2 exactly) and stay at their value at 6 beyond; and they are the
-ones gelu_tail_fit.py computes."""
+Phi(0) = 1/2 exactly); beyond 6, where the kernel takes the polynomial
+unclamped, its float32 value keeps decreasing (tail below its value at 6,
+within 5e-7 of Phi(-a), 0 for huge or infinite a, never NaN); and they are
+the ones gelu_tail_fit.py computes."""
 import os
 import re
 
@@ -18,19 +20,24 @@ def _coefficients():
     body = src[src.index("float normal_tail(float u)"):]
     body = body[:body.index("return __builtin_amdgcn_exp2f(p);")]
     lits = [float(v) for v in re.findall(r"(-?\d+\.\d+(?:e-?\d+)?)f", body)]
-    # min(|u|, 6.0f), then the two highest coefficients in the first fma,
-    # then the rest down to the constant
-    assert lits[0] == 6.0
-    return [np.float32(v) for v in lits[1:]]  # highest degree first
+    # |u| unclamped, then the two highest coefficients in the first fma, then
+    # the rest down to the constant
+    assert "fminf" not in body and len(lits) == 6
+    return [np.float32(v) for v in lits]  # highest degree first
+
+
+def _poly32(a):
+    c = _coefficients()
+    m = np.abs(np.asarray(a, dtype=np.float32))
+    with np.errstate(over="ignore", invalid="ignore"):
+        p = (np.float32(c[0]) * m + np.float32(c[1])).astype(np.float32)
+        for v in c[2:]:
+            p = (p * m + v).astype(np.float32)
+    return p
 
 
 def _tail32(a):
-    c = _coefficients()
-    m = np.minimum(np.abs(a), np.float32(6.0)).astype(np.float32)
-    p = np.float32(c[0]) * m + np.float32(c[1])
-    for v in c[2:]:
-        p = (p * m + v).astype(np.float32)
-    return np.exp2(p.astype(np.float64))
+    return np.exp2(_poly32(a).astype(np.float64))
 
 
 def test_tail_within_bound():
@@ -40,9 +47,20 @@ def test_tail_within_bound():
     assert np.max(np.abs(t - exact)) <= 5e-7
     assert np.max(np.abs(t / exact - 1.0)[a <= 1.0]) <= 5e-6
     assert _tail32(np.float32(0.0)) == 0.5
-    big = np.array([6.0, 7.5, 40.0], dtype=np.float32)
-    assert np.allclose(_tail32(big), _tail32(np.float32(6.0)), rtol=0, atol=0)
     assert _tail32(np.float32(6.0)) < 1e-8
+
+
+def test_tail_beyond_the_fit_interval():
+    a = np.linspace(6.0, 1e4, 2000001).astype(np.float32)
+    p = _poly32(a)
+    assert np.all(np.diff(p) <= 0)
+    t = _tail32(a)
+    assert np.all(t <= _tail32(np.float32(6.0)))
+    exact = np.exp(log_ndtr(-a.astype(np.float64)))
+    assert np.max(np.abs(t - exact)) <= 5e-7
+    huge = np.array([1e7, 1e20, 3.4e38, np.inf], dtype=np.float32)
+    p = _poly32(huge)
+    assert not np.any(np.isnan(p)) and np.all(_tail32(huge) == 0.0)
 
 
 def test_coefficients_match_the_fit():

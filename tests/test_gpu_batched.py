@@ -367,6 +367,33 @@ def test_problem_batch_refits_equal_list_fits(ctx):
         mo.free()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_score_prepare_then_batched_equals_unprepared(ctx, prec):
+    """gpbo_score_prepare_batched over the models of two batched calls, then
+    the calls: bit-identical outputs to scoring fresh fits of the same
+    problems without the preparation; preparing twice changes nothing."""
+    probs = _problems(B=6, m=700, seed=21)
+    Xcs = [_t(p.Xc, torch.float32) for p in probs]
+    st, ref_models, _, _ = _fit_batch(ctx, probs)
+    assert st == G.OK
+    ref = [G.score_batched(ctx, ref_models[h:h + 3], Xcs[h:h + 3], prec,
+                           want=("mu", "sigma", "ei")) for h in (0, 3)]
+    st, models, _, _ = _fit_batch(ctx, probs)
+    assert st == G.OK
+    G.score_prepare_batched(ctx, models, prec)
+    G.score_prepare_batched(ctx, models, prec)
+    got = [G.score_batched(ctx, models[h:h + 3], Xcs[h:h + 3], prec,
+                           want=("mu", "sigma", "ei")) for h in (0, 3)]
+    torch.cuda.synchronize()
+    for (ro, ra, re), (go, ga, ge) in zip(ref, got):
+        for k in ("mu", "sigma", "ei"):
+            for a, b in zip(ro[k], go[k]):
+                assert torch.equal(a, b), k
+        assert torch.equal(ra, ga) and torch.equal(re, ge)
+    for mo in ref_models + models:
+        mo.free()
+
+
 def test_batched_full_c3_shape_smoke(ctx):
     """The literal batch shape: 64 sub-searches, d in 2..12, n in 16..400,
     8192 candidates each; every argmax is a valid index with finite EI."""
