@@ -104,8 +104,11 @@ __device__ __forceinline__ int64_t off_w3(const MlpDev& M) { return off_b2(M) + 
 __device__ __forceinline__ int64_t off_b3(const MlpDev& M) { return off_w3(M) + M.H; }
 
 // bfloat16 copies of the master weights (and the transposed W2).
-__global__ void k_mlp_cast(MlpDev M) {
+// bump = 1 (after an Adam step): also advances the step counter, once,
+// after every workgroup of the Adam launch has read it.
+__global__ void k_mlp_cast(MlpDev M, int bump) {
   const int e = blockIdx.y;
+  if (bump && e == 0 && blockIdx.x == 0 && threadIdx.x == 0) M.step[0] += 1;
   const float* p = M.master + e * M.P;
   const int H = M.H, D = M.D;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H * H; i += gridDim.x * blockDim.x) {
@@ -356,15 +359,25 @@ __global__ void __launch_bounds__(256) k_mlp_bwd_out(MlpDev M, int64_t n, const 
     dout_s[t] = i < n ? 2.0f * (out[(int64_t)e * n + i] - y[i]) / (float)n : 0.0f;
   }
   __syncthreads();
+  // gb3 and the squared error: the samples' terms formed in parallel (one
+  // per thread of the first wave), summed in sample order by one thread
+  static_assert(MT <= 64, "one sample per lane of the first wave");
+  __shared__ float sq_s[MT];
+  if (t < MT) {
+    const int64_t i = i0 + t;
+    float sq = 0.0f;
+    if (i < n) {
+      const float d = out[(int64_t)e * n + i] - y[i];
+      sq = d * d;
+    }
+    sq_s[t] = sq;
+  }
+  __syncthreads();
   if (t == 0) {
     float g3 = 0.0f, ls = 0.0f;
     for (int r = 0; r < MT; ++r) {
       g3 += dout_s[r];
-      const int64_t i = i0 + r;
-      if (i < n) {
-        const float d = out[(int64_t)e * n + i] - y[i];
-        ls += d * d;
-      }
+      ls += sq_s[r];
     }
     part[2 * H] = g3;
     part[2 * H + 1] = ls;
@@ -372,18 +385,30 @@ __global__ void __launch_bounds__(256) k_mlp_bwd_out(MlpDev M, int64_t n, const 
   for (int j = t; j < H; j += 256) {
     const float w3 = bf2f(M.w3b[(int64_t)e * H + j]);
     float gb2 = 0.0f, gw3 = 0.0f;
-    for (int r = 0; r < MT; ++r) {
-      const int64_t i = i0 + r;
-      unsigned short db = 0;
-      if (i < n) {
-        const float pre = pre2[((int64_t)e * n + i) * H + j];
-        const float d = dout_s[r] * w3 * gelu_grad(pre);
-        gb2 += d;
-        gw3 = fmaf(dout_s[r], bfr(gelu(pre)), gw3);
-        db = f2bf(d);
-        B.dpre2[((int64_t)e * n + i) * H + j] = db;
+    // eight samples' pre-activations requested before any is used
+    constexpr int U = 8;
+    for (int r0 = 0; r0 < MT; r0 += U) {
+      float pv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + r0 + u;
+        pv[u] = i < n ? pre2[((int64_t)e * n + i) * H + j] : 0.0f;
       }
-      tT[j][r] = db;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = r0 + u;
+        const int64_t i = i0 + r;
+        unsigned short db = 0;
+        if (i < n) {
+          const float pre = pv[u];
+          const float d = dout_s[r] * w3 * gelu_grad(pre);
+          gb2 += d;
+          gw3 = fmaf(dout_s[r], bfr(gelu(pre)), gw3);
+          db = f2bf(d);
+          B.dpre2[((int64_t)e * n + i) * H + j] = db;
+        }
+        tT[j][r] = db;
+      }
     }
     part[j] = gb2;
     part[H + j] = gw3;
@@ -516,55 +541,118 @@ struct AdamIn {
   int64_t n;
   int apply;              // 0: assemble gradients only
 };
-__global__ void __launch_bounds__(256) k_mlp_adam(MlpDev M, AdamIn in) {
-  const int e = blockIdx.y;
-  const int H = M.H, D = M.D;
+
+// One Adam update of parameter q of member e with gradient g.
+__device__ __forceinline__ void adam_update(const MlpDev& M, const AdamIn& in, int e, int64_t q,
+                                            float g, double c1, double c2) {
   const int64_t P = M.P;
-  const int t = *M.step + 1;
-  const double c1 = 1.0 - pow(0.9, t), c2 = 1.0 - pow(0.999, t);
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < P;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    float g = 0.0f;
-    if (q < off_b1(M)) {  // W1[h][d]
-      const int h = (int)(q / D), d = (int)(q % D);
-      for (int s = 0; s < in.S1; ++s) g += in.l1part[(((int64_t)s * M.E + e) * H + h) * in.DX + d];
-    } else if (q < off_W2(M)) {  // b1
-      const int h = (int)(q - off_b1(M));
-      for (int b = 0; b < in.nb1; ++b) g += in.b1part[((int64_t)e * in.nb1 + b) * H + h];
-    } else if (q < off_b2(M)) {  // W2
-      const int64_t w = q - off_W2(M);
-      for (int s = 0; s < in.S2; ++s) g += in.gW2part[((int64_t)s * M.E + e) * H * H + w];
-    } else {
-      int col;  // b2 -> [0, H), w3 -> [H, 2H), b3 -> 2H
-      if (q < off_w3(M)) col = (int)(q - off_b2(M));
-      else if (q < off_b3(M)) col = H + (int)(q - off_w3(M));
-      else col = 2 * H;
-      for (int b = 0; b < in.nblk; ++b) g += in.colpart[((int64_t)e * in.nblk + b) * (2 * H + 2) + col];
-    }
-    if (in.grad_out) in.grad_out[e * P + q] = g;
-    if (in.apply) {
-      float* w = M.master + e * P + q;
-      float* m1 = M.mom1 + e * P + q;
-      float* m2 = M.mom2 + e * P + q;
-      const float mn = 0.9f * *m1 + 0.1f * g;
-      const float vn = 0.999f * *m2 + 0.001f * g * g;
-      *m1 = mn;
-      *m2 = vn;
-      const double mh = mn / c1, vh = vn / c2;
-      *w = (float)(*w - in.lr * mh / (sqrt(vh) + 1e-8));
-    }
-  }
-  // loss history rows count from the first step of the current training call
-  if (in.loss_hist && blockIdx.x == 0 && threadIdx.x == 0) {
-    float ls = 0.0f;
-    for (int b = 0; b < in.nblk; ++b) ls += in.colpart[((int64_t)e * in.nblk + b) * (2 * H + 2) + 2 * H + 1];
-    in.loss_hist[(int64_t)(t - 1 - M.step[1]) * M.E + e] = ls / (float)in.n;
-  }
+  if (in.grad_out) in.grad_out[e * P + q] = g;
+  if (!in.apply) return;
+  float* w = M.master + e * P + q;
+  float* m1 = M.mom1 + e * P + q;
+  float* m2 = M.mom2 + e * P + q;
+  const float mn = 0.9f * *m1 + 0.1f * g;
+  const float vn = 0.999f * *m2 + 0.001f * g * g;
+  *m1 = mn;
+  *m2 = vn;
+  const double mh = mn / c1, vh = vn / c2;
+  *w = (float)(*w - in.lr * mh / (sqrt(vh) + 1e-8));
 }
 
-// step[0]: Adam steps taken so far; step[1]: step[0] at the start of the
-// current training call.
-__global__ void k_mlp_step(MlpDev M) { M.step[0] += 1; }
+// Sum of nb partials src[b * stride], b = 0 .. nb - 1, added in that order
+// (the order of a sequential loop) by lane 0 of the calling wave: the lanes
+// first load them in parallel, 64 at a time, into the wave's LDS slice.
+__device__ __forceinline__ float ordered_sum(const float* __restrict__ src, int64_t stride, int nb,
+                                             float* slice) {
+  const int lane = threadIdx.x % 64;
+  float g = 0.0f;
+  for (int b0 = 0; b0 < nb; b0 += 64) {
+    const int cnt = min(64, nb - b0);
+    if (lane < cnt) slice[lane] = src[(int64_t)(b0 + lane) * stride];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    if (lane == 0)
+      for (int b = 0; b < cnt; ++b) g += slice[b];
+    __builtin_amdgcn_wave_barrier();
+  }
+  return g;
+}
+
+// Workgroups 0 .. ADAM_BULK_WG(M) - 1 of member e (blockIdx.y): one weight
+// of W1 or W2 per thread, its gradient the sum of the S1 or S2 chunk
+// partials.  The others: one bias or output weight per wave (b1 over the
+// n / 32 block sums, b2, w3, b3 over the nblk block sums: a column of
+// partials, loaded lane-parallel and added in block order), and one wave
+// for the loss history.
+constexpr int ADAM_COLS_PER_WG = 4;  // waves per workgroup, one column each
+__host__ __device__ __forceinline__ int adam_bulk_wg(int H, int D) {
+  return (H * D + H * H + 255) / 256;
+}
+__host__ __device__ __forceinline__ int adam_grid_x(int H, int D) {
+  return adam_bulk_wg(H, D) + (3 * H + 2 + ADAM_COLS_PER_WG - 1) / ADAM_COLS_PER_WG;
+}
+__global__ void __launch_bounds__(256) k_mlp_adam(MlpDev M, AdamIn in) {
+  __shared__ double corr[2];
+  __shared__ float slices[ADAM_COLS_PER_WG][64];
+  const int e = blockIdx.y;
+  const int H = M.H, D = M.D;
+  const int t = *M.step + 1;
+  // the bias corrections 1 - beta^t, evaluated once per workgroup
+  if (threadIdx.x == 0) {
+    corr[0] = 1.0 - pow(0.9, t);
+    corr[1] = 1.0 - pow(0.999, t);
+  }
+  __syncthreads();
+  const double c1 = corr[0], c2 = corr[1];
+  const int nbulk = adam_bulk_wg(H, D);
+  if ((int)blockIdx.x < nbulk) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)H * D + (int64_t)H * H) return;
+    float g = 0.0f;
+    int64_t q;
+    if (i < (int64_t)H * D) {  // W1[h][d]
+      q = i;
+      const int h = (int)(i / D), d = (int)(i % D);
+      const float* src = in.l1part + ((int64_t)e * H + h) * in.DX + d;
+      const int64_t stride = (int64_t)M.E * H * in.DX;
+#pragma unroll 8
+      for (int s = 0; s < in.S1; ++s) g += src[s * stride];
+    } else {  // W2
+      const int64_t w = i - (int64_t)H * D;
+      q = off_W2(M) + w;
+      const float* src = in.gW2part + (int64_t)e * H * H + w;
+      const int64_t stride = (int64_t)M.E * H * H;
+#pragma unroll 8
+      for (int s = 0; s < in.S2; ++s) g += src[s * stride];
+    }
+    adam_update(M, in, e, q, g, c1, c2);
+    return;
+  }
+  const int lane = threadIdx.x % 64;
+  const int c = ((int)blockIdx.x - nbulk) * ADAM_COLS_PER_WG + (int)threadIdx.x / 64;
+  if (c > 3 * H + 1) return;
+  float* slice = slices[threadIdx.x / 64];
+  const int64_t cstride = 2 * H + 2;
+  const float* cbase = in.colpart + (int64_t)e * in.nblk * cstride;
+  if (c == 3 * H + 1) {  // the loss history row of this step
+    if (!in.loss_hist) return;
+    const float ls = ordered_sum(cbase + 2 * H + 1, cstride, in.nblk, slice);
+    if (lane == 0) in.loss_hist[(int64_t)(t - 1 - M.step[1]) * M.E + e] = ls / (float)in.n;
+    return;
+  }
+  float g;
+  int64_t q;
+  if (c < H) {  // b1
+    q = off_b1(M) + c;
+    g = ordered_sum(in.b1part + (int64_t)e * in.nb1 * H + c, H, in.nb1, slice);
+  } else {  // b2 -> columns [0, H), w3 -> [H, 2H), b3 -> 2H of the block sums
+    const int col = c - H;
+    q = off_b2(M) + col;  // b2, w3, b3 are consecutive
+    g = ordered_sum(cbase + col, cstride, in.nblk, slice);
+  }
+  if (lane == 0) adam_update(M, in, e, q, g, c1, c2);
+}
+
 __global__ void k_mlp_zero_step(MlpDev M) {
   M.step[0] = 0;
   M.step[1] = 0;
@@ -673,7 +761,7 @@ MlpState* mlp_create(Ctx* c, int E, int D, int H, const float* init, hipStream_t
   (void)hipMemsetAsync(M.mom1, 0, pb, s);
   (void)hipMemsetAsync(M.mom2, 0, pb, s);
   hipLaunchKernelGGL(k_mlp_zero_step, dim3(1), dim3(1), 0, s, M);
-  hipLaunchKernelGGL(k_mlp_cast, dim3(64, E), dim3(256), 0, s, M);
+  hipLaunchKernelGGL(k_mlp_cast, dim3(64, E), dim3(256), 0, s, M, 0);
   (void)hipFuncSetAttribute((const void*)k_mlp_fwd<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)mlp_fwd_smem(D, H));
   (void)hipFuncSetAttribute((const void*)k_mlp_fwd<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -814,11 +902,8 @@ void mlp_step(MlpState* st, int64_t n, const float* X, const float* y, double lr
   hipLaunchKernelGGL(k_gemm_nt<EPI_STORE>, dim3((H / 64) * (w.DX / 64), w.S1, E), dim3(256), 0, s, g3);
   AdamIn ai{w.gW2part, w.S2, w.l1part, w.S1, w.DX, w.b1part, (int)(n / 32), w.colpart, w.nblk,
             lr, grad_out, loss_hist, n, apply};
-  hipLaunchKernelGGL(k_mlp_adam, dim3(64, E), dim3(256), 0, s, M, ai);
-  if (apply) {
-    hipLaunchKernelGGL(k_mlp_step, dim3(1), dim3(1), 0, s, M);
-    hipLaunchKernelGGL(k_mlp_cast, dim3(64, E), dim3(256), 0, s, M);
-  }
+  hipLaunchKernelGGL(k_mlp_adam, dim3(adam_grid_x(H, st->dev.D), E), dim3(256), 0, s, M, ai);
+  if (apply) hipLaunchKernelGGL(k_mlp_cast, dim3(64, E), dim3(256), 0, s, M, 1);
 }
 
 // bf16(x) feature-major for the layer-1 weight gradient: the training data
