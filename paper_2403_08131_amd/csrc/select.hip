@@ -37,6 +37,11 @@ __device__ __forceinline__ unsigned fkey(float f) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+// Workgroups of a histogram pass: each adds its nonzero bins to the global
+// histogram with one atomic each, so on concentrated keys every workgroup
+// hits the same bin; about one per CU keeps that serialisation short.
+constexpr int kHistBlocks = 256;
+
 // state[0] = prefix, state[1] = prefix mask, state[2] = k still needed
 __global__ void __launch_bounds__(SEL_BLOCK) k_radix_hist(const float* __restrict__ v, int64_t m,
                                                           const unsigned* __restrict__ state,
@@ -45,10 +50,25 @@ __global__ void __launch_bounds__(SEL_BLOCK) k_radix_hist(const float* __restric
   for (int i = threadIdx.x; i < 256; i += SEL_BLOCK) h[i] = 0;
   __syncthreads();
   const unsigned prefix = state[0], mask = state[1];
+  const int lane = threadIdx.x % 64;
   for (int64_t i = blockIdx.x * (int64_t)SEL_BLOCK + threadIdx.x; i < m;
        i += (int64_t)gridDim.x * SEL_BLOCK) {
     const unsigned key = fkey(v[i]);
-    if ((key & mask) == prefix) atomicAdd(&h[(key >> shift) & 255u], 1u);
+    const bool mine = (key & mask) == prefix;
+    const unsigned dg = (key >> shift) & 255u;
+    // keys concentrated on one digit (the later passes, or a narrow range of
+    // values): when every counted lane of the wave has the first one's
+    // digit, one LDS atomic adds them all
+    const unsigned long long act = __ballot(mine);
+    if (act == 0ull) continue;
+    const int leader = __ffsll((long long)act) - 1;
+    const unsigned dl = __shfl(dg, leader);
+    const unsigned long long same = __ballot(mine && dg == dl);
+    if (same == act) {
+      if (lane == leader) atomicAdd(&h[dl], (unsigned)__popcll(same));
+    } else if (mine) {
+      atomicAdd(&h[dg], 1u);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 256; i += SEL_BLOCK)
@@ -362,7 +382,7 @@ void launch_topk_set_into(int64_t m, const float* v, int64_t k, int64_t* idx, vo
   unsigned* eq_counts = (unsigned*)((unsigned char*)ws + 4096);
   unsigned* sel_counts = (unsigned*)((unsigned char*)eq_counts + round_up(nb * 4, 256));
   hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, state, hist, (unsigned)k);
-  const int g = (int)std::min<int64_t>(2048, ceil_div(m, SEL_BLOCK));
+  const int g = (int)std::min<int64_t>(kHistBlocks, ceil_div(m, SEL_BLOCK));
   for (int shift = 24; shift >= 0; shift -= 8) {
     hipLaunchKernelGGL(k_radix_hist, dim3(g), dim3(SEL_BLOCK), 0, s, v, m, state, shift, hist);
     hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(256), 0, s, hist, state, shift);
@@ -388,7 +408,7 @@ void launch_topk_into(int64_t m, const float* v, int64_t k, int64_t* idx, void* 
   unsigned* okey = (unsigned*)((unsigned char*)counts + round_up(nb * 4, 256));
   int64_t* oidx = (int64_t*)((unsigned char*)okey + round_up(k * 4, 256));
   hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, state, hist, (unsigned)k);
-  const int g = (int)std::min<int64_t>(2048, ceil_div(m, SEL_BLOCK));
+  const int g = (int)std::min<int64_t>(kHistBlocks, ceil_div(m, SEL_BLOCK));
   for (int shift = 24; shift >= 0; shift -= 8) {
     hipLaunchKernelGGL(k_radix_hist, dim3(g), dim3(SEL_BLOCK), 0, s, v, m, state, shift, hist);
     hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(256), 0, s, hist, state, shift);
