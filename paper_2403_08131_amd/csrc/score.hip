@@ -348,49 +348,28 @@ __device__ __forceinline__ void phase_cross_mfma(const ScoreArgs& A, unsigned sh
   const float* __restrict__ alpha = (const float*)A.alpha + 4 * kq;
   unsigned short* krow = kt + c * ldk + 4 * kq;
   float macc = 0.0f;
-  // The observation operand in two halves of SH steps (the second only for
-  // d + 2 > 4 SH), to bound the live registers; the first half of the next
-  // block is requested before this block's covariances are formed.
+  // the observation operand in two halves of SH steps (the second only for
+  // d + 2 > 4 SH), to bound the live registers (requesting the next block's
+  // first half ahead of this block's covariances was measured: 12 % more
+  // vector instructions, no gain)
   constexpr int SH = DIST_SMAX / 2;
-  auto load_half = [&](f4 (&a)[SH], int h, int jb) {
-#pragma unroll
-    for (int s = 0; s < SH; ++s)
-      if (h * SH + s < S) a[s] = *(const f4*)(Xp + 4 * (h * SH + s) * (int64_t)nx + jb);
-  };
-  auto mma_half = [&](f4 (&acc)[4], const f4 (&a)[SH], int h) {
-#pragma unroll
-    for (int s = 0; s < SH; ++s)
-      if (h * SH + s < S)
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s][t], qb[h * SH + s], acc[t], 0, 0, 0);
-  };
-  // (not at 16 candidates per workgroup: there the register budget of the
-  // variance phase leaves no room for it)
-  constexpr bool PREFETCH = TM >= 32;
-  f4 a0[SH];
-  if constexpr (PREFETCH)
-    if (pr * 64 < npj) load_half(a0, 0, pr * 64);
   for (int jb = pr * 64; jb < npj; jb += WPG * 64) {
     f4 acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    if constexpr (PREFETCH) {
-      mma_half(acc, a0, 0);
-      if (S > SH) {
-        f4 a1[SH];
-        load_half(a1, 1, jb);
-        mma_half(acc, a1, 1);
-      }
-      if (jb + WPG * 64 < npj) load_half(a0, 0, jb + WPG * 64);
-    } else {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (h * SH >= S) break;
-        f4 a[SH];
-        load_half(a, h, jb);
-        mma_half(acc, a, h);
-      }
+    for (int h = 0; h < 2; ++h) {
+      if (h * SH >= S) break;
+      f4 a[SH];
+#pragma unroll
+      for (int s = 0; s < SH; ++s)
+        if (h * SH + s < S) a[s] = *(const f4*)(Xp + 4 * (h * SH + s) * (int64_t)nx + jb);
+#pragma unroll
+      for (int s = 0; s < SH; ++s)
+        if (h * SH + s < S)
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s][t], qb[h * SH + s], acc[t], 0, 0, 0);
     }
     f4 al[4];
 #pragma unroll
