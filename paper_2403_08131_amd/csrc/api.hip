@@ -1230,7 +1230,6 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
   unsigned char* base = (unsigned char*)c->batch_buf;
   ScoreArgs* dd = (ScoreArgs*)base;
   ScoreArgs* dd64 = (ScoreArgs*)(base + desc_bytes);
-  unsigned* counters = (unsigned*)(base + 2 * desc_bytes);
   void* plan = base + 2 * desc_bytes + 256;
   unsigned char* outs = base + 2 * desc_bytes + 256 + plan_bytes;
   double* pv = (double*)(outs + out_bytes);
@@ -1285,8 +1284,9 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
   L.tm64 = esc ? tm64 : 16;
   L.grid = c->num_cu * per_cu;
   L.grid64 = c->num_cu * std::max(per_cu64, 1);
+  L.per_cu = per_cu;
+  L.per_cu64 = std::max(per_cu64, 1);
   L.plan = plan;
-  L.counters = counters;
   L.argmax = am_dev;
   L.ei_max = em_dev;
   {

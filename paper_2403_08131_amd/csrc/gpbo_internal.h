@@ -337,8 +337,8 @@ struct BatchLaunch {
   int tm = 32, tm64 = 16;           // candidates per work item of each class
   size_t smem = 0, smem64 = 0;      // dynamic LDS of each class's kernel
   int grid = 0, grid64 = 0;         // persistent workgroups of each class
+  int per_cu = 2, per_cu64 = 1;     // their workgroups per CU (bounds the LDS of each)
   void* plan = nullptr;             // device plan area, batch_plan_bytes(B)
-  unsigned* counters = nullptr;     // two device work counters (reset by the sequence)
   int64_t* argmax = nullptr;        // device, B (may be NULL)
   double* ei_max = nullptr;         // device, B (may be NULL)
 };

@@ -26,8 +26,8 @@
 //            writes the outputs and the tile's (EI, index) maximum.
 // The single-problem launch has one workgroup per tile.  The batched launch
 // (independent sub-searches, run in parallel per Sec. IV-D) is persistent:
-// each workgroup pops (problem, tile) items from a counter until none is
-// left, largest problems first.
+// the (problem, tile) items, largest problems first, are dealt cyclically
+// over its workgroups.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -611,8 +611,7 @@ k_score_fused(ScoreArgs A) {
 // Persistent batched scoring over the work items of one class of a plan:
 // items 0 .. total-1 enumerate (problem, tile) pairs, the k-th problem of the
 // class (descriptor idx[k]) owning items [begin[k], begin[k+1]).  Every
-// workgroup pops items until the counter passes the total, so all of them
-// reach the exit; the next item is popped while the current one is scored.
+// workgroup leaves its loop once its next item index passes the total.
 // Problem starts of up to BT_MAX problems are looked up in LDS.  Candidate
 // groups of 16 keep every wave of the cross-covariance phase busy on the
 // small problems of a batch.
@@ -660,10 +659,8 @@ __host__ __device__ inline PlanView plan_view(void* base, int B) {
 // conditioning statistic), then per class an ordered prefix sum of the work
 // items over chunks of 256 problems (descriptor order, i.e. largest first,
 // is kept within each class).
-// It also clears the two item counters the scoring launches pop from.
 __global__ void __launch_bounds__(256) k_plan_batched(const ScoreArgs* __restrict__ dd, int B,
-                                                      int tm0, int tm1, int escalate, void* plan,
-                                                      unsigned* __restrict__ counters) {
+                                                      int tm0, int tm1, int escalate, void* plan) {
   __shared__ int64_t sc[2][256];
   __shared__ int sn[2][256];
   __shared__ int64_t run_items[2];
@@ -673,7 +670,6 @@ __global__ void __launch_bounds__(256) k_plan_batched(const ScoreArgs* __restric
   if (t < 2) {
     run_items[t] = 0;
     run_count[t] = 0;
-    counters[t] = 0u;
   }
   __syncthreads();
   for (int k0 = 0; k0 < B; k0 += 256) {
@@ -730,13 +726,35 @@ __global__ void __launch_bounds__(256) k_plan_batched(const ScoreArgs* __restric
 // Two workgroups per CU: the bfloat16 variant is held to the 128 registers
 // of four waves per SIMD (its matrix-core distances would otherwise take
 // more); the others stay there without a cap.
+// A descriptor read from LDS, every 32-bit word made wave-uniform (scalar
+// registers), as a scalar load from global memory would leave it.
+__device__ __forceinline__ ScoreArgs uniform_args(const ScoreArgs* p) {
+  static_assert(sizeof(ScoreArgs) % 4 == 0, "descriptor of whole words");
+  ScoreArgs a;
+  const int* src = (const int*)p;
+  int* dst = (int*)&a;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(ScoreArgs) / 4); ++i)
+    dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  return a;
+}
+
+// Items are dealt cyclically: workgroup g takes items g, g + G, g + 2G, ...
+// (G workgroups).  The items enumerate (problem, tile) with the problems in
+// decreasing n, so every round deals tiles of similar cost and the totals
+// stay balanced; no shared counter is popped (8192 items over 512
+// workgroups on one global atomic queued behind each other).
+// desc_off > 0: byte offset in the dynamic LDS (past the tile areas) where
+// the workgroup keeps a copy of the class's descriptors, in class order,
+// loaded once at its start; per item the descriptor then comes from LDS
+// instead of a dependent pair of global loads (problem index, then
+// descriptor).
 template <int P, int TM>
 __global__ void __launch_bounds__(FT)
     __attribute__((amdgpu_waves_per_eu(P == GPBO_BF16 ? 4 : 1, 4)))
 k_score_batched(const ScoreArgs* __restrict__ descs, int B, int cls, const void* plan,
-                unsigned* __restrict__ counter) {
+                int desc_off) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int64_t item_s;
   __shared__ int64_t begin_s[BT_MAX];
   const PlanView v = plan_view(const_cast<void*>(plan), B);
   const int cnt = __builtin_amdgcn_readfirstlane(v.hdr->count[cls]);
@@ -746,25 +764,37 @@ k_score_batched(const ScoreArgs* __restrict__ descs, int B, int cls, const void*
   const bool lds_table = cnt <= BT_MAX;
   if (lds_table)
     for (int b = threadIdx.x; b < cnt; b += FT) begin_s[b] = begin[b];
-  if (threadIdx.x == 0) item_s = total > 0 ? (int64_t)atomicAdd(counter, 1u) : 0;
-  __syncthreads();
-  for (;;) {
-    // item and problem are the same for the whole workgroup: kept in scalar
-    // registers, so the descriptor's fields are scalar loads
-    const int64_t item = (int64_t)__builtin_amdgcn_readfirstlane((int)item_s);
-    if (item >= total) break;
-    unsigned nxt = 0;
-    if (threadIdx.x == 0) nxt = atomicAdd(counter, 1u);
-    int lo = 0, hi = cnt - 1;  // largest k with begin[k] <= item
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) / 2;
-      const int64_t tb = lds_table ? begin_s[mid] : begin[mid];
-      if (tb <= item) lo = mid; else hi = mid - 1;
-      lo = __builtin_amdgcn_readfirstlane(lo);
-      hi = __builtin_amdgcn_readfirstlane(hi);
+  ScoreArgs* desc_s = desc_off > 0 ? (ScoreArgs*)(smem + desc_off) : nullptr;
+  if (desc_s) {
+    constexpr int W = (int)(sizeof(ScoreArgs) / 4);
+    for (int e = threadIdx.x; e < cnt * W; e += FT) {
+      const int k = e / W, w = e % W;
+      ((int*)(desc_s + k))[w] = ((const int*)(descs + idx[k]))[w];
     }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x % 64;
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    int lo;  // largest k with begin[k] <= item (the starts increase)
+    if (lds_table && cnt <= 64) {
+      // one comparison per lane: the lanes whose start is reached form a prefix
+      const bool reached = lane < cnt && begin_s[lane] <= item;
+      lo = __popcll(__ballot(reached)) - 1;
+    } else {
+      int l = 0, hi = cnt - 1;
+      while (l < hi) {
+        const int mid = (l + hi + 1) / 2;
+        const int64_t tb = lds_table ? begin_s[mid] : begin[mid];
+        if (tb <= item) l = mid; else hi = mid - 1;
+        l = __builtin_amdgcn_readfirstlane(l);
+        hi = __builtin_amdgcn_readfirstlane(hi);
+      }
+      lo = l;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
     const int64_t tile = item - (lds_table ? begin_s[lo] : begin[lo]);
-    ScoreArgs A = descs[__builtin_amdgcn_readfirstlane(idx[lo])];
+    ScoreArgs A = desc_s ? uniform_args(desc_s + lo)
+                         : descs[__builtin_amdgcn_readfirstlane(idx[lo])];
     // the descriptor's pointers are device-global memory: loads through them
     // become global (not flat) loads, with their own wait counter
     A.Xc = global_ptr(A.Xc);
@@ -784,8 +814,9 @@ k_score_batched(const ScoreArgs* __restrict__ descs, int B, int cls, const void*
       score_tile<P, GPBO_KERNEL_SE, TM, 1, 16, true>(A, tile, smem);
     else
       score_tile<P, GPBO_KERNEL_MATERN52, TM, 1, 16, true>(A, tile, smem);
-    __syncthreads();  // item_s and the LDS tile are reused by the next item
-    if (threadIdx.x == 0) item_s = (int64_t)nxt;
+    // The tile areas sit at offsets that depend on the problem (its row
+    // stride and d): the next item's candidate tile may overlap the partial
+    // sums the finish of this one still reads.
     __syncthreads();
   }
 }
@@ -877,21 +908,28 @@ void launch_fused_tm(const ScoreArgs& a, int tm, size_t smem, hipStream_t s) {
   }
 }
 
+// The descriptor copy in LDS is taken when it keeps per_cu workgroups per
+// CU (with the kernel's static LDS, ~2.1 KB).
+constexpr size_t kBatchedStaticLds = 2560;
 template <int P, int TM>
-void launch_batched_t(const ScoreArgs* dd, int B, int cls, void* plan, unsigned* counter,
-                      size_t smem, int grid, hipStream_t s) {
-  allow_smem(k_score_batched<P, TM>, smem);
-  hipLaunchKernelGGL((k_score_batched<P, TM>), dim3(grid), dim3(FT), smem, s, dd, B, cls,
-                     (const void*)plan, counter);
+void launch_batched_t(const ScoreArgs* dd, int B, int cls, void* plan, size_t smem, int grid,
+                      int per_cu, hipStream_t s) {
+  const size_t off = round_up((int64_t)smem, 16);
+  const size_t with = off + (size_t)B * sizeof(ScoreArgs);
+  const bool cache = off > 0 && (size_t)per_cu * (with + kBatchedStaticLds) <= 160 * 1024;
+  const size_t dyn = cache ? with : smem;
+  allow_smem(k_score_batched<P, TM>, dyn);
+  hipLaunchKernelGGL((k_score_batched<P, TM>), dim3(grid), dim3(FT), dyn, s, dd, B, cls,
+                     (const void*)plan, cache ? (int)off : 0);
 }
 
 template <int P>
-void launch_batched_tm(const ScoreArgs* dd, int B, int cls, void* plan, unsigned* counter, int tm,
-                       size_t smem, int grid, hipStream_t s) {
+void launch_batched_tm(const ScoreArgs* dd, int B, int cls, void* plan, int tm, size_t smem,
+                       int grid, int per_cu, hipStream_t s) {
   switch (tm) {
-    case 16: launch_batched_t<P, 16>(dd, B, cls, plan, counter, smem, grid, s); break;
-    case 32: launch_batched_t<P, 32>(dd, B, cls, plan, counter, smem, grid, s); break;
-    default: launch_batched_t<P, 64>(dd, B, cls, plan, counter, smem, grid, s); break;
+    case 16: launch_batched_t<P, 16>(dd, B, cls, plan, smem, grid, per_cu, s); break;
+    case 32: launch_batched_t<P, 32>(dd, B, cls, plan, smem, grid, per_cu, s); break;
+    default: launch_batched_t<P, 64>(dd, B, cls, plan, smem, grid, per_cu, s); break;
   }
 }
 
@@ -1173,22 +1211,22 @@ void launch_score_batched(const BatchLaunch& L, hipStream_t s,
                           const std::function<void(int)>* mark) {
   const bool esc = L.dd64 != nullptr;
   hipLaunchKernelGGL(k_plan_batched, dim3(1), dim3(256), 0, s, L.dd, L.B, L.tm, L.tm64,
-                     esc ? 1 : 0, L.plan, L.counters);
+                     esc ? 1 : 0, L.plan);
   if (mark) (*mark)(0);
   switch (L.prec) {
     case GPBO_FP64:
-      launch_batched_tm<GPBO_FP64>(L.dd, L.B, 0, L.plan, L.counters, L.tm, L.smem, L.grid, s);
+      launch_batched_tm<GPBO_FP64>(L.dd, L.B, 0, L.plan, L.tm, L.smem, L.grid, L.per_cu, s);
       break;
     case GPBO_FP32:
-      launch_batched_tm<GPBO_FP32>(L.dd, L.B, 0, L.plan, L.counters, L.tm, L.smem, L.grid, s);
+      launch_batched_tm<GPBO_FP32>(L.dd, L.B, 0, L.plan, L.tm, L.smem, L.grid, L.per_cu, s);
       break;
     default:
-      launch_batched_tm<GPBO_BF16>(L.dd, L.B, 0, L.plan, L.counters, L.tm, L.smem, L.grid, s);
+      launch_batched_tm<GPBO_BF16>(L.dd, L.B, 0, L.plan, L.tm, L.smem, L.grid, L.per_cu, s);
       break;
   }
   if (esc)
-    launch_batched_tm<P_F64IO32>(L.dd64, L.B, 1, L.plan, L.counters + 1, L.tm64, L.smem64,
-                                 L.grid64, s);
+    launch_batched_tm<P_F64IO32>(L.dd64, L.B, 1, L.plan, L.tm64, L.smem64, L.grid64,
+                                 L.per_cu64, s);
   if (mark) (*mark)(1);
   if (L.argmax || L.ei_max)
     hipLaunchKernelGGL(k_argmax_batched, dim3(L.B), dim3(256), 0, s, L.dd, L.B,
