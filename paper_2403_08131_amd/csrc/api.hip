@@ -1258,7 +1258,8 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
       a.part_v = pv + poff[k];
       a.part_i = pi + poff[k];
       a.slot = b;
-      smem = std::max(smem, score_smem(prec, a.n, a.d, tm));
+      // the batched kernel lays its tile areas out for the largest n and d
+      smem = std::max(smem, score_smem(prec, nmax, dmax, tm));
       h.push_back(a);
       if (esc) {
         ScoreArgs a64 = make_score_args(models[b], GPBO_FP64, tm64);
@@ -1270,7 +1271,7 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
         a64.part_v = a.part_v;
         a64.part_i = a.part_i;
         a64.slot = b;
-        smem64 = std::max(smem64, score_smem(GPBO_FP64, a64.n, a64.d, tm64));
+        smem64 = std::max(smem64, score_smem(GPBO_FP64, nmax, dmax, tm64));
         h64.push_back(a64);
       }
     }
@@ -1286,6 +1287,8 @@ gpbo_status gpbo_score_batched(gpbo_ctx c, int32_t B, const gpbo_model* models, 
   L.grid64 = c->num_cu * std::max(per_cu64, 1);
   L.per_cu = per_cu;
   L.per_cu64 = std::max(per_cu64, 1);
+  L.nmax = nmax;
+  L.dmax = dmax;
   L.plan = plan;
   L.argmax = am_dev;
   L.ei_max = em_dev;

@@ -338,6 +338,7 @@ struct BatchLaunch {
   size_t smem = 0, smem64 = 0;      // dynamic LDS of each class's kernel
   int grid = 0, grid64 = 0;         // persistent workgroups of each class
   int per_cu = 2, per_cu64 = 1;     // their workgroups per CU (bounds the LDS of each)
+  int nmax = 0, dmax = 0;           // largest n and d of the batch (the kernels' LDS layout)
   void* plan = nullptr;             // device plan area, batch_plan_bytes(B)
   int64_t* argmax = nullptr;        // device, B (may be NULL)
   double* ei_max = nullptr;         // device, B (may be NULL)

@@ -42,6 +42,10 @@ namespace gpbo {
 
 using namespace sc;
 
+size_t score_esize(int prec);
+int packed_npj(int n, int prec);
+int kt_stride(int prec, int npj);
+
 namespace {
 
 // Per-problem arguments of the score-operand preparation kernels (problem
@@ -559,17 +563,22 @@ __device__ __forceinline__ void phase_finish(const ScoreArgs& A, int64_t tile,
 
 // Score candidate tile `tile` of problem A (TM candidates from tile * TM)
 // with all FW waves of the workgroup in every phase.
+// xc_off >= 0 (the batched kernel): the candidate tile and the partial sums
+// sit at fixed byte offsets sized for the batch's largest row stride and d,
+// so no area of one item depends on the problem of another.
 template <int P, int KERN, int TM, int RT, int CG = 0, bool SPLIT = false>
 __device__ __forceinline__ void score_tile(const ScoreArgs& A, int64_t tile,
-                                           unsigned char* smem) {
+                                           unsigned char* smem, int xc_off = -1,
+                                           int part_off = -1) {
   using C = typename PT<P>::C;
   using K = typename PT<P>::K;
   using Acc = typename PT<P>::Acc;
   const int d = A.d, ldk = A.ldk;
   K* kt = (K*)smem;                                            // [TM][ldk]
-  C* xcT = (C*)(smem + (size_t)TM * ldk * sizeof(K));          // [d][TM]
-  Acc* mu_part = (Acc*)(xcT + round_up((int64_t)d * TM, 4));   // [FW][TM]
-  Acc* ssq_part = mu_part + FW * TM;                           // [FW][TM]
+  C* xcT = (C*)(smem + (xc_off >= 0 ? (size_t)xc_off : (size_t)TM * ldk * sizeof(K)));  // [d][TM]
+  Acc* mu_part = part_off >= 0 ? (Acc*)(smem + part_off)
+                               : (Acc*)(xcT + round_up((int64_t)d * TM, 4));  // [FW][TM]
+  Acc* ssq_part = mu_part + FW * TM;                                          // [FW][TM]
   const int wave = wave_id();
   stage_candidates<P, TM, FW>(A, tile, xcT, threadIdx.x);
   __syncthreads();
@@ -743,7 +752,8 @@ __device__ __forceinline__ ScoreArgs uniform_args(const ScoreArgs* p) {
 // (G workgroups).  The items enumerate (problem, tile) with the problems in
 // decreasing n, so every round deals tiles of similar cost and the totals
 // stay balanced; no shared counter is popped (8192 items over 512
-// workgroups on one global atomic queued behind each other).
+// workgroups on one global atomic queued behind each other), and the next
+// item's candidates are staged while wave 0 still finishes the current one.
 // desc_off > 0: byte offset in the dynamic LDS (past the tile areas) where
 // the workgroup keeps a copy of the class's descriptors, in class order,
 // loaded once at its start; per item the descriptor then comes from LDS
@@ -753,7 +763,7 @@ template <int P, int TM>
 __global__ void __launch_bounds__(FT)
     __attribute__((amdgpu_waves_per_eu(P == GPBO_BF16 ? 4 : 1, 4)))
 k_score_batched(const ScoreArgs* __restrict__ descs, int B, int cls, const void* plan,
-                int desc_off) {
+                int xc_off, int part_off, int desc_off) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int64_t begin_s[BT_MAX];
   const PlanView v = plan_view(const_cast<void*>(plan), B);
@@ -811,13 +821,14 @@ k_score_batched(const ScoreArgs* __restrict__ descs, int B, int cls, const void*
     A.part_v = global_ptr(A.part_v);
     A.part_i = global_ptr(A.part_i);
     if (A.kernel == GPBO_KERNEL_SE)
-      score_tile<P, GPBO_KERNEL_SE, TM, 1, 16, true>(A, tile, smem);
+      score_tile<P, GPBO_KERNEL_SE, TM, 1, 16, true>(A, tile, smem, xc_off, part_off);
     else
-      score_tile<P, GPBO_KERNEL_MATERN52, TM, 1, 16, true>(A, tile, smem);
-    // The tile areas sit at offsets that depend on the problem (its row
-    // stride and d): the next item's candidate tile may overlap the partial
-    // sums the finish of this one still reads.
-    __syncthreads();
+      score_tile<P, GPBO_KERNEL_MATERN52, TM, 1, 16, true>(A, tile, smem, xc_off, part_off);
+    // No barrier here: the waves that are done stage the next item's
+    // candidates while wave 0 still finishes this one.  The finish reads only
+    // the partial sums, at fixed offsets apart from the candidate tile; the
+    // next item's first phase writes them (and the covariance tile) only
+    // after the staging barrier, which wave 0 reaches when it is done.
   }
 }
 
@@ -911,25 +922,30 @@ void launch_fused_tm(const ScoreArgs& a, int tm, size_t smem, hipStream_t s) {
 // The descriptor copy in LDS is taken when it keeps per_cu workgroups per
 // CU (with the kernel's static LDS, ~2.1 KB).
 constexpr size_t kBatchedStaticLds = 2560;
+// The tile areas of the batch: the covariance tile for the largest row
+// stride, then the candidate tile for the largest d, then the partial sums
+// (score_smem of the largest n and d, the size the caller passes).
 template <int P, int TM>
-void launch_batched_t(const ScoreArgs* dd, int B, int cls, void* plan, size_t smem, int grid,
-                      int per_cu, hipStream_t s) {
+void launch_batched_t(const ScoreArgs* dd, int B, int cls, void* plan, int nmax, int dmax,
+                      size_t smem, int grid, int per_cu, hipStream_t s) {
+  const size_t xc_off = (size_t)TM * kt_stride(P, packed_npj(nmax, P)) * score_esize(P);
+  const size_t part_off = xc_off + (size_t)round_up((int64_t)dmax * TM, 4) * (arith64(P) ? 8 : 4);
   const size_t off = round_up((int64_t)smem, 16);
   const size_t with = off + (size_t)B * sizeof(ScoreArgs);
   const bool cache = off > 0 && (size_t)per_cu * (with + kBatchedStaticLds) <= 160 * 1024;
   const size_t dyn = cache ? with : smem;
   allow_smem(k_score_batched<P, TM>, dyn);
   hipLaunchKernelGGL((k_score_batched<P, TM>), dim3(grid), dim3(FT), dyn, s, dd, B, cls,
-                     (const void*)plan, cache ? (int)off : 0);
+                     (const void*)plan, (int)xc_off, (int)part_off, cache ? (int)off : 0);
 }
 
 template <int P>
-void launch_batched_tm(const ScoreArgs* dd, int B, int cls, void* plan, int tm, size_t smem,
-                       int grid, int per_cu, hipStream_t s) {
+void launch_batched_tm(const ScoreArgs* dd, int B, int cls, void* plan, int nmax, int dmax, int tm,
+                       size_t smem, int grid, int per_cu, hipStream_t s) {
   switch (tm) {
-    case 16: launch_batched_t<P, 16>(dd, B, cls, plan, smem, grid, per_cu, s); break;
-    case 32: launch_batched_t<P, 32>(dd, B, cls, plan, smem, grid, per_cu, s); break;
-    default: launch_batched_t<P, 64>(dd, B, cls, plan, smem, grid, per_cu, s); break;
+    case 16: launch_batched_t<P, 16>(dd, B, cls, plan, nmax, dmax, smem, grid, per_cu, s); break;
+    case 32: launch_batched_t<P, 32>(dd, B, cls, plan, nmax, dmax, smem, grid, per_cu, s); break;
+    default: launch_batched_t<P, 64>(dd, B, cls, plan, nmax, dmax, smem, grid, per_cu, s); break;
   }
 }
 
@@ -1215,18 +1231,21 @@ void launch_score_batched(const BatchLaunch& L, hipStream_t s,
   if (mark) (*mark)(0);
   switch (L.prec) {
     case GPBO_FP64:
-      launch_batched_tm<GPBO_FP64>(L.dd, L.B, 0, L.plan, L.tm, L.smem, L.grid, L.per_cu, s);
+      launch_batched_tm<GPBO_FP64>(L.dd, L.B, 0, L.plan, L.nmax, L.dmax, L.tm, L.smem, L.grid,
+                                   L.per_cu, s);
       break;
     case GPBO_FP32:
-      launch_batched_tm<GPBO_FP32>(L.dd, L.B, 0, L.plan, L.tm, L.smem, L.grid, L.per_cu, s);
+      launch_batched_tm<GPBO_FP32>(L.dd, L.B, 0, L.plan, L.nmax, L.dmax, L.tm, L.smem, L.grid,
+                                   L.per_cu, s);
       break;
     default:
-      launch_batched_tm<GPBO_BF16>(L.dd, L.B, 0, L.plan, L.tm, L.smem, L.grid, L.per_cu, s);
+      launch_batched_tm<GPBO_BF16>(L.dd, L.B, 0, L.plan, L.nmax, L.dmax, L.tm, L.smem, L.grid,
+                                   L.per_cu, s);
       break;
   }
   if (esc)
-    launch_batched_tm<P_F64IO32>(L.dd64, L.B, 1, L.plan, L.tm64, L.smem64, L.grid64,
-                                 L.per_cu64, s);
+    launch_batched_tm<P_F64IO32>(L.dd64, L.B, 1, L.plan, L.nmax, L.dmax, L.tm64, L.smem64,
+                                 L.grid64, L.per_cu64, s);
   if (mark) (*mark)(1);
   if (L.argmax || L.ei_max)
     hipLaunchKernelGGL(k_argmax_batched, dim3(L.B), dim3(256), 0, s, L.dd, L.B,
