@@ -41,9 +41,9 @@ PEAKS = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}  # dense matrix-core TFLOP
 # runs of this benchmark, scaled by the same counters on a plain copy of known
 # size.  Valid only while the kernel source is unchanged (hash below).
 TRAFFIC = {
-    "kernel_sha": "70a733d845078fc0",
+    "kernel_sha": "a93b750b83d89aa0",
     "workload": "c2",
-    "fetch_kib": 5028.0,       # FETCH_SIZE per dispatch of k_score_fused
+    "fetch_kib": 5027.5,       # FETCH_SIZE per dispatch of k_score_fused
     "write_kib": 896.0,        # WRITE_SIZE per dispatch
     "fetch_scale": 262144 / 131086.5,  # 256 MiB copy: FETCH_SIZE reads half the bytes moved
     "write_scale": 1.0,
@@ -645,8 +645,10 @@ def run_c3(args):
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAKS[prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAKS[prec], "traffic": None, "kernel": "k_score_batched",
                      "flops_per_launch": fl_launch, "avg_launch_ms": k_avg,
-                     "note": "the vector ALU (distances, exp2 per candidate-point pair), not the "
-                             "matrix cores, bounds this kernel at these small n and d"},
+                     "note": "bf16: squared distances on the fp32 matrix cores, the variance on "
+                             "the bf16 ones; latency per work item (lookup, staging, four "
+                             "phases) bounds it at these small n and d (vector ALU ~39 %, "
+                             "matrix cores ~16 % busy)"},
     }
     ctx.close()
     print(json.dumps(res), flush=True)
