@@ -197,21 +197,22 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fwd(MlpDev M, int64_t n, const f
     const unsigned short* W1 = M.W1b + (int64_t)e * H * DP;
     const int ocol = wave * 64;  // this wave's 64 columns (hidden units / outputs)
     // the accumulators start from the biases: lane's entry r of block b is unit
-    // ocol + 16b + 4(lane/16) + r for every sample block
-    f4 acc[4][4];
+    // ocol + 16b + 4(lane/16) + r for every sample block; the first
+    // contraction step takes them as its addend, so they are not copied into
+    // the accumulators first
+    f4 bias[4];
     #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int h0 = ocol + b * 16 + 4 * (lane / 16);
-      const f4 bb = {p[off_b1(M) + h0], p[off_b1(M) + h0 + 1], p[off_b1(M) + h0 + 2],
-                     p[off_b1(M) + h0 + 3]};
-      #pragma unroll
-      for (int a = 0; a < 4; ++a) acc[a][b] = bb;
+      bias[b] = f4{p[off_b1(M) + h0], p[off_b1(M) + h0 + 1], p[off_b1(M) + h0 + 2],
+                   p[off_b1(M) + h0 + 3]};
     }
+    f4 acc[4][4];
     // layer 1, transposed: C[h][s] = sum_k W1[h][k] x[s][k] (A = W1 rows, B =
     // samples), so that a lane's four accumulators are four consecutive hidden
     // units of one sample: they round to bfloat16 in pairs and go to the
     // sample-major h1 tile as one 8-byte store
-    for (int k0 = 0; k0 < DP; k0 += 32) {
+    auto step1 = [&](int k0, bool first) {
       us8 av[4], bv[4];
       #pragma unroll
       for (int a = 0; a < 4; ++a)
@@ -225,8 +226,10 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fwd(MlpDev M, int64_t n, const f
         for (int b = 0; b < 4; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, bv[b]),
                                                               __builtin_bit_cast(bf8, av[a]),
-                                                              acc[a][b], 0, 0, 0);
-    }
+                                                              first ? bias[b] : acc[a][b], 0, 0, 0);
+    };
+    step1(0, true);
+    for (int k0 = 32; k0 < DP; k0 += 32) step1(k0, false);
     // layer-1 epilogue: lane holds hidden units h0 .. h0+3 (h0 = ocol + 16b +
     // 4(lane/16)) of sample 16a + lane%16
     #pragma unroll
@@ -260,15 +263,13 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fwd(MlpDev M, int64_t n, const f
     #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int j0 = ocol + b * 16 + 4 * (lane / 16);
-      const f4 bb = {p[off_b2(M) + j0], p[off_b2(M) + j0 + 1], p[off_b2(M) + j0 + 2],
-                     p[off_b2(M) + j0 + 3]};
-      #pragma unroll
-      for (int a = 0; a < 4; ++a) acc[a][b] = bb;
+      bias[b] = f4{p[off_b2(M) + j0], p[off_b2(M) + j0 + 1], p[off_b2(M) + j0 + 2],
+                   p[off_b2(M) + j0 + 3]};
     }
     // layer 2, transposed the same way: C[j][s] = sum_k W2[j][k] h1[s][k];
     // wave w computes outputs [64w, 64w + 64) for the MT samples
     const unsigned short* W2 = M.W2b + (int64_t)e * H * H;
-    for (int k0 = 0; k0 < H; k0 += 32) {
+    auto step2 = [&](int k0, bool first) {
       us8 av[4], bv[4];
       #pragma unroll
       for (int a = 0; a < 4; ++a)
@@ -282,8 +283,10 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fwd(MlpDev M, int64_t n, const f
         for (int b = 0; b < 4; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, bv[b]),
                                                               __builtin_bit_cast(bf8, av[a]),
-                                                              acc[a][b], 0, 0, 0);
-    }
+                                                              first ? bias[b] : acc[a][b], 0, 0, 0);
+    };
+    step2(0, true);
+    for (int k0 = 32; k0 < H; k0 += 32) step2(k0, false);
     // epilogue: lane holds outputs j0 .. j0+3 (j0 = ocol + 16b + 4(lane/16)) of
     // sample 16a + lane%16; h2 = bf16(GELU(pre2)) and its dot with w3 stay in
     // the lane until the four lane groups are summed
@@ -291,12 +294,8 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fwd(MlpDev M, int64_t n, const f
     #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int j0 = ocol + b * 16 + 4 * (lane / 16);
-      float w3[4];
+      // w3 of the lane's four outputs as two bfloat16 pairs
       const uint2 w3p = *(const uint2*)(M.w3b + (int64_t)e * H + j0);
-      w3[0] = __uint_as_float(w3p.x << 16);
-      w3[1] = __uint_as_float(w3p.x & 0xffff0000u);
-      w3[2] = __uint_as_float(w3p.y << 16);
-      w3[3] = __uint_as_float(w3p.y & 0xffff0000u);
       #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int row = a * 16 + lane % 16;
@@ -310,11 +309,13 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fwd(MlpDev M, int64_t n, const f
           *(float4*)(O.pre2 + ((int64_t)e * n + i0 + row) * H + j0) =
               make_float4(pre[0], pre[1], pre[2], pre[3]);
         const unsigned lo = pack_bf16x2(g[0], g[1]), hi = pack_bf16x2(g[2], g[3]);
+        // h2 . w3 on the bfloat16 pairs (the products are exact in float32):
+        // one v_dot2c_f32_bf16 per pair
         float v = rowsum[a];
-        v = fmaf(w3[0], __uint_as_float(lo << 16), v);
-        v = fmaf(w3[1], __uint_as_float(lo & 0xffff0000u), v);
-        v = fmaf(w3[2], __uint_as_float(hi << 16), v);
-        v = fmaf(w3[3], __uint_as_float(hi & 0xffff0000u), v);
+        v = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, lo),
+                                            __builtin_bit_cast(bf16x2_t, w3p.x), v, false);
+        v = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, hi),
+                                            __builtin_bit_cast(bf16x2_t, w3p.y), v, false);
         rowsum[a] = v;
       }
     }
