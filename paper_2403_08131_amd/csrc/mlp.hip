@@ -68,6 +68,20 @@ __device__ __forceinline__ float gelu(float u) {
   const float c = __builtin_canonicalizef(u);
   return fmaf(-fabsf(c), normal_tail(c), fmaxf(c, 0.0f));
 }
+// 2 GELU(u) = (u + |u|) - |u| 2Phi(-|u|), with 2Phi(-a) = exp2(p(a) + 1)
+// (the same polynomial, its constant term -1 + 1 = 0): one instruction fewer
+// than GELU and no canonicalisation (u + |u| needs none).  The prescreen
+// pass uses it with the next layer's weights halved (exact in bfloat16), so
+// every product of the next layer is the one of GELU times the full weight.
+__device__ __forceinline__ float gelu2(float u) {
+  const float m = fabsf(u);
+  float p = fmaf(m, -0.0005204600165598094f, 0.0073975189588963985f);
+  p = fmaf(m, p, -0.05256125330924988f);
+  p = fmaf(m, p, -0.4592546820640564f);
+  p = fmaf(m, p, -1.1510913372039795f);
+  p = m * p;
+  return fmaf(-m, __builtin_amdgcn_exp2f(p), u + m);
+}
 __device__ __forceinline__ float gelu_grad(float u) {
   const NormalCdf c = normal_cdf(u);
   return c.Phi + u * c.e * 0.39894228040143267794f;
@@ -93,6 +107,8 @@ struct MlpDev {
   unsigned short* W2b;     // E x H x H  [out][in]
   unsigned short* W2Tb;    // E x H x H  [in][out]
   unsigned short* w3b;     // E x H
+  unsigned short* W2hb;    // E x H x H  [out][in], 0.5 W2 (the prescreen pass)
+  unsigned short* w3hb;    // E x H, 0.5 w3 (the prescreen pass)
   int* step;               // [0] Adam steps taken, [1] steps taken before this training call
 };
 
@@ -116,13 +132,16 @@ __global__ void k_mlp_cast(MlpDev M, int bump) {
     const unsigned short b = f2bf(p[off_W2(M) + i]);
     M.W2b[(int64_t)e * H * H + i] = b;
     M.W2Tb[(int64_t)e * H * H + (int64_t)in * H + o] = b;
+    M.W2hb[(int64_t)e * H * H + i] = f2bf(0.5f * p[off_W2(M) + i]);
   }
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H * M.DP; i += gridDim.x * blockDim.x) {
     const int h = i / M.DP, k = i % M.DP;
     M.W1b[(int64_t)e * H * M.DP + i] = k < D ? f2bf(p[h * D + k]) : (unsigned short)0;
   }
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H; i += gridDim.x * blockDim.x)
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H; i += gridDim.x * blockDim.x) {
     M.w3b[(int64_t)e * H + i] = f2bf(p[off_w3(M) + i]);
+    M.w3hb[(int64_t)e * H + i] = f2bf(0.5f * p[off_w3(M) + i]);
+  }
 }
 
 // Forward of MT samples through one member (blockIdx.y), 256 threads, both
@@ -238,11 +257,13 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fwd(MlpDev M, int64_t n, const f
       #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int row = a * 16 + lane % 16;
+        // training: GELU (its h1 feeds the backward); prescreen: 2 GELU, the
+        // next layer's weights halved
         float pre[4], g[4];
         #pragma unroll
         for (int r = 0; r < 4; ++r) {
           pre[r] = acc[a][b][r];
-          g[r] = gelu(pre[r]);
+          g[r] = TRAIN ? gelu(pre[r]) : gelu2(pre[r]);
         }
         const uint2 hb = make_uint2(pack_bf16x2(g[0], g[1]), pack_bf16x2(g[2], g[3]));
         *(uint2*)(hA + row * ldh + h0) = hb;
@@ -268,7 +289,7 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fwd(MlpDev M, int64_t n, const f
     }
     // layer 2, transposed the same way: C[j][s] = sum_k W2[j][k] h1[s][k];
     // wave w computes outputs [64w, 64w + 64) for the MT samples
-    const unsigned short* W2 = M.W2b + (int64_t)e * H * H;
+    const unsigned short* W2 = (TRAIN ? M.W2b : M.W2hb) + (int64_t)e * H * H;
     auto step2 = [&](int k0, bool first) {
       us8 av[4], bv[4];
       #pragma unroll
@@ -294,8 +315,9 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fwd(MlpDev M, int64_t n, const f
     #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int j0 = ocol + b * 16 + 4 * (lane / 16);
-      // w3 of the lane's four outputs as two bfloat16 pairs
-      const uint2 w3p = *(const uint2*)(M.w3b + (int64_t)e * H + j0);
+      // w3 of the lane's four outputs as two bfloat16 pairs (halved for the
+      // prescreen's 2 GELU)
+      const uint2 w3p = *(const uint2*)((TRAIN ? M.w3b : M.w3hb) + (int64_t)e * H + j0);
       #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int row = a * 16 + lane % 16;
@@ -303,7 +325,7 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fwd(MlpDev M, int64_t n, const f
         #pragma unroll
         for (int r = 0; r < 4; ++r) {
           pre[r] = acc[a][b][r];
-          g[r] = gelu(pre[r]);
+          g[r] = TRAIN ? gelu(pre[r]) : gelu2(pre[r]);
         }
         if (TRAIN && i0 + row < n)
           *(float4*)(O.pre2 + ((int64_t)e * n + i0 + row) * H + j0) =
@@ -753,8 +775,11 @@ MlpState* mlp_create(Ctx* c, int E, int D, int H, const float* init, hipStream_t
   M.W2b = (unsigned short*)dmalloc(c, (size_t)E * H * H * 2);
   M.W2Tb = (unsigned short*)dmalloc(c, (size_t)E * H * H * 2);
   M.w3b = (unsigned short*)dmalloc(c, (size_t)E * H * 2);
+  M.W2hb = (unsigned short*)dmalloc(c, (size_t)E * H * H * 2);
+  M.w3hb = (unsigned short*)dmalloc(c, (size_t)E * H * 2);
   M.step = (int*)dmalloc(c, 64);
-  if (!M.master || !M.mom1 || !M.mom2 || !M.W1b || !M.W2b || !M.W2Tb || !M.w3b || !M.step) {
+  if (!M.master || !M.mom1 || !M.mom2 || !M.W1b || !M.W2b || !M.W2Tb || !M.w3b || !M.W2hb ||
+      !M.w3hb || !M.step) {
     delete st;
     return nullptr;
   }
@@ -775,7 +800,8 @@ void mlp_destroy(MlpState* st) {
   (void)hipStreamSynchronize(c->stream);
   if (st->graph) (void)hipGraphExecDestroy(st->graph);
   void* ps[] = {st->dev.master, st->dev.mom1, st->dev.mom2, st->dev.W1b, st->dev.W2b,
-                st->dev.W2Tb, st->dev.w3b, st->dev.step, st->ws, st->data};
+                st->dev.W2Tb, st->dev.w3b, st->dev.W2hb, st->dev.w3hb, st->dev.step, st->ws,
+                st->data};
   for (void* p : ps) dfree(c, p);
   delete st;
 }

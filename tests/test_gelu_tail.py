@@ -4,8 +4,9 @@ exp2), reproduce Phi(-a) on [0, 6] within the stated bounds against scipy's
 log_ndtr (absolute error <= 5e-7, relative error <= 5e-6 for a <= 1,
 Phi(0) = 1/2 exactly); beyond 6, where the kernel takes the polynomial
 unclamped, its float32 value keeps decreasing (tail below its value at 6,
-within 5e-7 of Phi(-a), 0 for huge or infinite a, never NaN); and they are
-the ones gelu_tail_fit.py computes."""
+within 5e-7 of Phi(-a), 0 for huge or infinite a, never NaN); they are the
+ones gelu_tail_fit.py computes; and the prescreen's doubled GELU uses the
+same polynomial with its constant raised by 1 (2 Phi(-a) = exp2(p(a) + 1))."""
 import os
 import re
 
@@ -71,3 +72,13 @@ def test_coefficients_match_the_fit():
     spec.loader.exec_module(mod)
     c = mod.fit()
     np.testing.assert_array_equal(np.float32(c[::-1]), np.array(_coefficients(), dtype=np.float32))
+
+
+def test_doubled_gelu_uses_the_same_polynomial():
+    src = open(os.path.join(ROOT, "paper_2403_08131_amd", "csrc", "mlp.hip")).read()
+    body = src[src.index("float gelu2(float u)"):]
+    body = body[:body.index("return fmaf(")]
+    lits = [np.float32(float(v)) for v in re.findall(r"(-?\d+\.\d+(?:e-?\d+)?)f", body)]
+    c = _coefficients()
+    assert lits == c[:-1] and c[-1] == np.float32(-1.0)
+    assert "p = m * p;" in body  # the constant term p(0) + 1 = 0
