@@ -669,6 +669,47 @@ __device__ __forceinline__ void rowmul_tile(const FitDesc& P, int I, int J, int 
   store_block(C, npad, block_mac(At, Bt, 16 * w, 16 * h), 16 * w, 16 * h);
 }
 
+// Whole-tile variants (one workgroup per tile, each wave four 16 x 16
+// blocks): D_k is read once per tile instead of once per quarter.  A batch
+// of many problems has tiles enough to fill the GPU without the quarters,
+// and then the four reads of D_k (32 KB each) per tile dominate the launch.
+__device__ __forceinline__ void panel_tile_all(const FitDesc& P, int k, int I, double* sm) {
+  const int npad = P.npad, t = threadIdx.x, w = t / 64;
+  double* At = sm;
+  double* Bt = sm + NB * LDT;
+  double* Pk = P.L + (int64_t)I * NB * npad + k * NB;
+  for (int e = t; e < NB * NB; e += 256) {  // A_Ik transposed into At
+    const int r = e / NB, c = e % NB;
+    At[c * LDT + r] = Pk[(int64_t)r * npad + c];
+  }
+  load_tile(P.Dinv + (int64_t)k * NB * NB, NB, Bt, true);
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 4; ++h)
+    store_block(Pk, npad, block_mac(At, Bt, 16 * h, 16 * w), 16 * h, 16 * w);
+}
+
+__device__ __forceinline__ void rowmul_tile_all(const FitDesc& P, int I, int J, double* sm) {
+  const int npad = P.npad, t = threadIdx.x, w = t / 64;
+  double* C = P.Linv + (int64_t)I * NB * npad + J * NB;
+  const double* Dk = P.Dinv + (int64_t)I * NB * NB;
+  if (J == I) {
+    for (int e = t; e < NB * NB; e += 256) C[(int64_t)(e / NB) * npad + e % NB] = Dk[e];
+    return;
+  }
+  double* At = sm;
+  double* Bt = sm + NB * LDT;
+  for (int e = t; e < NB * NB; e += 256) {  // B_IJ into Bt
+    const int r = e / NB, c = e % NB;
+    Bt[r * LDT + c] = C[(int64_t)r * npad + c];
+  }
+  load_tile(Dk, NB, At, true);
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 4; ++h)
+    store_block(C, npad, block_mac(At, Bt, 16 * w, 16 * h), 16 * w, 16 * h);
+}
+
 // Inverse factor, step I: B_KJ -= L_KI X_IJ for K > I, J <= I.
 __device__ __forceinline__ void trtri_update_tile(const FitDesc& P, int I, int K, int J, double* sm) {
   const int npad = P.npad;
@@ -688,19 +729,26 @@ __device__ __forceinline__ void trtri_update_tile(const FitDesc& P, int I, int K
 // Launch of step k (k <= nbmax): panel tiles of the factorisation (the first
 // npanel workgroups, npanel = nbmax - k - 1 for the largest problem) and the
 // row-multiply tiles of inverse step k - 1.
+// quarters = 4: four workgroups per tile (h = 0..3); 1: one per tile.
 __global__ void __launch_bounds__(256) k_chol_panel(const FitDesc* __restrict__ Ds, int k,
-                                                    int npanel) {
+                                                    int npanel, int quarters) {
   extern __shared__ double sm[];
   const FitDesc& P = Ds[blockIdx.z];
   if (fit_failed(P.info)) return;
   const int nb = P.npad / NB;
-  const int bx = blockIdx.x / 4, h = blockIdx.x % 4;  // tile, quarter
+  const int bx = blockIdx.x / quarters, h = blockIdx.x % quarters;  // tile, quarter
   if (bx < npanel) {
     const int I = k + 1 + bx;
-    if (I < nb) panel_tile(P, k, I, h, sm);
+    if (I < nb) {
+      if (quarters == 1) panel_tile_all(P, k, I, sm);
+      else panel_tile(P, k, I, h, sm);
+    }
   } else {
     const int I = k - 1, J = bx - npanel;
-    if (I >= 0 && I < nb && J <= I) rowmul_tile(P, I, J, h, sm);
+    if (I >= 0 && I < nb && J <= I) {
+      if (quarters == 1) rowmul_tile_all(P, I, J, sm);
+      else rowmul_tile(P, I, J, h, sm);
+    }
   }
 }
 
@@ -1272,12 +1320,18 @@ void launch_fit(const FitDesc* h, const FitDesc* dd, int B, hipStream_t s) {
   // step k-1; trailing update k with the update of inverse step k-1 and the
   // diagonal tile k + 1; step nbmax finishes the inverse
   const size_t smu = sizeof(DiagLds);
+  // the panel launch in quarters of a tile while its tiles alone would not
+  // fill the GPU (one problem, or few); whole tiles otherwise
+  auto quarters = [&](int tiles) { return (int64_t)Bz * tiles >= 512 ? 1 : 4; };
   for (int k = 0; k <= nbmax; ++k) {
     if (k == 0) hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, Bz), dim3(256), 0, s, dd, k);
     const int npanel = std::max(nbmax - k - 1, 0);
     const int nrow = k;  // inverse step k - 1 has k tiles in its row
-    if (npanel + nrow > 0)
-      hipLaunchKernelGGL(k_chol_panel, dim3(4 * (npanel + nrow), 1, Bz), dim3(256), sm2, s, dd, k, npanel);
+    if (npanel + nrow > 0) {
+      const int qt = quarters(npanel + nrow);
+      hipLaunchKernelGGL(k_chol_panel, dim3(qt * (npanel + nrow), 1, Bz), dim3(256), sm2, s, dd, k,
+                         npanel, qt);
+    }
     const int nupd = npanel * (npanel + 1) / 2;
     const int ntri = k >= 1 ? (nbmax - k) * k : 0;  // inverse step k - 1: (nbmax-k) rows x k tiles
     if (nupd + ntri > 0)
