@@ -475,14 +475,18 @@ def run_c3(args):
     torch.cuda.set_stream(torch.cuda.Stream(device=dev))
     ctx = G.Context(0)
     batches = []
-    for lam in (0.0, 0.1, 0.5):
+    # the argmax of every sub-search of the three launches in one device
+    # array, read back with one copy per step
+    am_all = torch.empty((3, 64), dtype=torch.int64, device=dev)
+    for li, lam in enumerate((0.0, 0.1, 0.5)):
         probs = I.make_c3(lam=lam, replicate=0)
+        assert len(probs) == am_all.shape[1]
         specs = [dict(X=torch.tensor(p.X, device=dev), y=torch.tensor(p.y, device=dev),
                       lengthscale=p.lengthscale, kernel=p.kernel, signal_var=p.signal_var,
                       noise_var=p.noise_var) for p in probs]
         Xcs = [torch.tensor(p.Xc, dtype=torch.float32, device=dev) for p in probs]
         eis = [torch.empty(p.m, dtype=torch.float32, device=dev) for p in probs]
-        am = torch.empty(len(probs), dtype=torch.int64, device=dev)
+        am = am_all[li]
         em = torch.empty(len(probs), dtype=torch.float64, device=dev)
         batches.append(dict(lam=lam, probs=probs, specs=specs, Xcs=Xcs, eis=eis, am=am, em=em,
                             batch=G.ProblemBatch(specs),
@@ -528,7 +532,7 @@ def run_c3(args):
                 kept.append(fit(bt["batch"]))
                 launch(bt, kept[-1])
             groups = kept
-        picks = [bt["am"].cpu() for bt in batches]  # the next configuration of every sub-search
+        picks = am_all.cpu()  # the next configuration of every sub-search
         for models in groups:
             st, status, _ = G.status_batched(ctx, models)
             if st != G.OK:

@@ -945,12 +945,29 @@ __global__ void __launch_bounds__(64 * RESF_W) k_res_finish(const FitDesc* __res
   __shared__ double red[RESF_W];
   const FitDesc& P = Ds[blockIdx.z];
   if (fit_failed(P.info)) return;
+  // (each thread requests the values of U consecutive strides before it uses
+  // any: the loops are a chain of memory latencies otherwise, on the fit's
+  // critical path and slow to issue beside other streams' work)
+  constexpr int NT = 64 * RESF_W, U = 4;
   if (lml) {
     double q = 0.0, ld = 0.0, tr = 0.0;
-    for (int i = threadIdx.x; i < P.n; i += 64 * RESF_W) {
-      q += P.yt[i] * P.alpha[i];
-      ld += log(P.L[(int64_t)i * P.npad + i]);
-      tr += P.work[(int64_t)V_Q * P.npad + i];
+    for (int i0 = threadIdx.x; i0 < P.n; i0 += U * NT) {
+      double yv[U], av[U], lv[U], tv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * NT;
+        const bool in = i < P.n;
+        yv[u] = in ? P.yt[i] : 0.0;
+        av[u] = in ? P.alpha[i] : 0.0;
+        lv[u] = in ? P.L[(int64_t)i * P.npad + i] : 1.0;
+        tv[u] = in ? P.work[(int64_t)V_Q * P.npad + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        q += yv[u] * av[u];
+        ld += log(lv[u]);
+        tr += tv[u];
+      }
     }
     q = block_sum_w<RESF_W>(q, red);
     ld = block_sum_w<RESF_W>(ld, red);
@@ -963,15 +980,26 @@ __global__ void __launch_bounds__(64 * RESF_W) k_res_finish(const FitDesc* __res
   }
   double* r = P.work + (int64_t)V_R * P.npad;
   double q = 0.0;
-  for (int i = threadIdx.x; i < P.npad; i += 64 * RESF_W) {
-    double v = 0.0;
-    if (i < P.n) {
-      double kv = 0.0;
-      for (int c = 0; c < P.nchunks; ++c) kv += P.work[(int64_t)(V_PART + c) * P.npad + i];
-      v = P.yt[i] - kv;
+  for (int i0 = threadIdx.x; i0 < P.npad; i0 += U * NT) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * NT;
+      v[u] = 0.0;
+      if (i < P.n) {
+        double kv = 0.0;
+        for (int c = 0; c < P.nchunks; ++c) kv += P.work[(int64_t)(V_PART + c) * P.npad + i];
+        v[u] = P.yt[i] - kv;
+      }
     }
-    r[i] = v;
-    q += v * v;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * NT;
+      if (i < P.npad) {
+        r[i] = v[u];
+        q += v[u] * v[u];
+      }
+    }
   }
   q = block_sum_w<RESF_W>(q, red);
   if (threadIdx.x == 0) P.stats[slot] = sqrt(q);
