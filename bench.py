@@ -79,6 +79,9 @@ FWD_TRAFFIC = {
     "valu_insts_per_wave": 1650,
     "mfma_insts_per_wave": 144,
 }
+# the vector-ALU issue rate of the chip in lane instructions per second
+# (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz)
+VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9 / 1e12
 FWD_TRAFFIC["bytes_per_launch"] = round(1024 * (FWD_TRAFFIC["fetch_kib"] * FWD_TRAFFIC["fetch_scale"]
                                                 + FWD_TRAFFIC["write_kib"] * FWD_TRAFFIC["write_scale"]))
 
@@ -368,6 +371,7 @@ def run_c4(args):
     p0 = reps[0]["p"]
     fwd_avg = fwd_ms / max(fwd_launches, 1)
     fl_fwd = MLP_FWD_FLOPS(p0.d, H) * E * p0.m
+    fwd_waves = -(-p0.m // 64) * E * 4  # 64-sample tiles x members x 4 waves
     ach_fwd = fl_fwd / (fwd_avg * 1e-3) / 1e12
     gemm_avg = gemm_ms / max(gemm_launches, 1)
     fl_gemm = flops_per_candidate(p0.n, p0.d, "large") * p0.m * full_steps / max(gemm_launches, 1)
@@ -423,6 +427,20 @@ def run_c4(args):
                              "ALU, not the matrix cores, bound it; it runs as a persistent grid "
                              "of %d workgroup(s) per CU to leave room for the concurrent fit"
                              % args.fwd_occupancy},
+        # the same launch against the vector-ALU issue rate that bounds it:
+        # lane instructions (the counted VALU instructions per wave x 64 lanes
+        # x the launch's waves) per second, against 256 CUs x 4 SIMDs x 16
+        # lanes x 2.4 GHz = 39.3 T lane instructions/s (packed FP32 is not
+        # generated: the library is built without it)
+        "roofline_valu": ({"bound": "alu", "kernel": "k_mlp_fwd",
+                           "achieved": FWD_TRAFFIC["valu_insts_per_wave"] * 64 * fwd_waves
+                           / (fwd_avg * 1e-3) / 1e12,
+                           "peak": VALU_LANE_PEAK, "unit": "T lane instructions/s",
+                           "frac": FWD_TRAFFIC["valu_insts_per_wave"] * 64 * fwd_waves
+                           / (fwd_avg * 1e-3) / 1e12 / VALU_LANE_PEAK,
+                           "avg_launch_ms": fwd_avg}
+                          if kernel_source_hash(FWD_SOURCES) == FWD_TRAFFIC["kernel_sha"]
+                          else None),
         "roofline_full_gp": {"bound": "mfma", "achieved": ach_gemm, "peak": PEAKS["fp32"],
                              "unit": "TFLOP/s", "frac": ach_gemm / PEAKS["fp32"], "traffic": None,
                              "kernel": "k_trigemm", "flops_per_launch": fl_gemm,
