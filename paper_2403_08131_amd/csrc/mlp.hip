@@ -120,11 +120,8 @@ __device__ __forceinline__ int64_t off_w3(const MlpDev& M) { return off_b2(M) + 
 __device__ __forceinline__ int64_t off_b3(const MlpDev& M) { return off_w3(M) + M.H; }
 
 // bfloat16 copies of the master weights (and the transposed W2).
-// bump = 1 (after an Adam step): also advances the step counter, once,
-// after every workgroup of the Adam launch has read it.
-__global__ void k_mlp_cast(MlpDev M, int bump) {
+__global__ void k_mlp_cast(MlpDev M) {
   const int e = blockIdx.y;
-  if (bump && e == 0 && blockIdx.x == 0 && threadIdx.x == 0) M.step[0] += 1;
   const float* p = M.master + e * M.P;
   const int H = M.H, D = M.D;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H * H; i += gridDim.x * blockDim.x) {
@@ -173,9 +170,13 @@ __device__ __forceinline__ int fwd_ldx(int DP) { return DP + 8; }  // bf16 row s
 __host__ __device__ inline int64_t fwd_items(int ntile, int E) {
   return ((int64_t)(ntile + 7) / 8) * 8 * E;
 }
+// bump (training steps that apply Adam): the first thread advances the step
+// counter, which this step's Adam launch then reads (nothing in between
+// does).
 template <bool TRAIN>
 __global__ void __launch_bounds__(256, 2) k_mlp_fwd(MlpDev M, int64_t n, const float* __restrict__ X,
-                                                 FwdOut O, int ntile) {
+                                                 FwdOut O, int ntile, int bump) {
+  if (TRAIN && bump && blockIdx.x == 0 && threadIdx.x == 0) M.step[0] += 1;
   extern __shared__ __align__(16) unsigned char sm[];
   const int H = M.H, D = M.D, DP = M.DP;
   const int t = threadIdx.x, lane = t % 64, wave = wave_id();
@@ -548,7 +549,8 @@ __global__ void __launch_bounds__(256) k_mlp_xt(const float* __restrict__ X, int
 }
 
 // Adam on every parameter, gradients assembled from the partial sums in a
-// fixed order; then the bfloat16 copies are refreshed by k_mlp_cast.
+// fixed order; the threads that update a weight also refresh its bfloat16
+// copies.
 struct AdamIn {
   const float* gW2part;   // S2 x E x H x H
   int S2;
@@ -566,6 +568,10 @@ struct AdamIn {
 };
 
 // One Adam update of parameter q of member e with gradient g.
+// One Adam update of parameter q of member e with gradient g; with apply,
+// also the bfloat16 copies the kernels read (W1, W2 both ways, w3 and the
+// halved W2 and w3 of the prescreen pass), which k_mlp_cast builds at
+// creation.
 __device__ __forceinline__ void adam_update(const MlpDev& M, const AdamIn& in, int e, int64_t q,
                                             float g, double c1, double c2) {
   const int64_t P = M.P;
@@ -579,7 +585,23 @@ __device__ __forceinline__ void adam_update(const MlpDev& M, const AdamIn& in, i
   *m1 = mn;
   *m2 = vn;
   const double mh = mn / c1, vh = vn / c2;
-  *w = (float)(*w - in.lr * mh / (sqrt(vh) + 1e-8));
+  const float wn = (float)(*w - in.lr * mh / (sqrt(vh) + 1e-8));
+  *w = wn;
+  const int H = M.H, D = M.D;
+  if (q < off_b1(M)) {  // W1[h][d]
+    M.W1b[((int64_t)e * H + q / D) * M.DP + q % D] = f2bf(wn);
+  } else if (q >= off_W2(M) && q < off_b2(M)) {  // W2[o][in]
+    const int64_t i = q - off_W2(M);
+    const int o = (int)(i / H), c = (int)(i % H);
+    const unsigned short b = f2bf(wn);
+    M.W2b[(int64_t)e * H * H + i] = b;
+    M.W2Tb[(int64_t)e * H * H + (int64_t)c * H + o] = b;
+    M.W2hb[(int64_t)e * H * H + i] = f2bf(0.5f * wn);
+  } else if (q >= off_w3(M) && q < off_b3(M)) {  // w3
+    const int64_t j = q - off_w3(M);
+    M.w3b[(int64_t)e * H + j] = f2bf(wn);
+    M.w3hb[(int64_t)e * H + j] = f2bf(0.5f * wn);
+  }
 }
 
 // Sum of nb partials src[b * stride], b = 0 .. nb - 1, added in that order
@@ -619,7 +641,8 @@ __global__ void __launch_bounds__(256) k_mlp_adam(MlpDev M, AdamIn in) {
   __shared__ float slices[ADAM_COLS_PER_WG][64];
   const int e = blockIdx.y;
   const int H = M.H, D = M.D;
-  const int t = *M.step + 1;
+  // the step's training forward has advanced the counter already
+  const int t = *M.step;
   // the bias corrections 1 - beta^t, evaluated once per workgroup
   if (threadIdx.x == 0) {
     corr[0] = 1.0 - pow(0.9, t);
@@ -787,7 +810,7 @@ MlpState* mlp_create(Ctx* c, int E, int D, int H, const float* init, hipStream_t
   (void)hipMemsetAsync(M.mom1, 0, pb, s);
   (void)hipMemsetAsync(M.mom2, 0, pb, s);
   hipLaunchKernelGGL(k_mlp_zero_step, dim3(1), dim3(1), 0, s, M);
-  hipLaunchKernelGGL(k_mlp_cast, dim3(64, E), dim3(256), 0, s, M, 0);
+  hipLaunchKernelGGL(k_mlp_cast, dim3(64, E), dim3(256), 0, s, M);
   (void)hipFuncSetAttribute((const void*)k_mlp_fwd<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)mlp_fwd_smem(D, H));
   (void)hipFuncSetAttribute((const void*)k_mlp_fwd<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -883,7 +906,7 @@ void mlp_step(MlpState* st, int64_t n, const float* X, const float* y, double lr
   const int E = M.E, H = M.H;
   FwdOut fo{w.out, w.pre1, w.h1, w.h1T, w.pre2};
   hipLaunchKernelGGL(k_mlp_fwd<true>, dim3((unsigned)fwd_items((int)w.nblk, E)), dim3(256),
-                     mlp_fwd_smem(M.D, H), s, M, n, X, fo, (int)w.nblk);
+                     mlp_fwd_smem(M.D, H), s, M, n, X, fo, (int)w.nblk, apply);
   BwdBuf bb{w.dpre2, w.dpre2T, w.colpart};
   hipLaunchKernelGGL(k_mlp_bwd_out, dim3(w.nblk, E), dim3(256), 0, s, M, n, y, w.out, w.pre2, bb);
   // gW2 = dpre2^T h1 over the samples (split over S2 sample chunks)
@@ -930,7 +953,6 @@ void mlp_step(MlpState* st, int64_t n, const float* X, const float* y, double lr
   AdamIn ai{w.gW2part, w.S2, w.l1part, w.S1, w.DX, w.b1part, (int)(n / 32), w.colpart, w.nblk,
             lr, grad_out, loss_hist, n, apply};
   hipLaunchKernelGGL(k_mlp_adam, dim3(adam_grid_x(H, st->dev.D), E), dim3(256), 0, s, M, ai);
-  if (apply) hipLaunchKernelGGL(k_mlp_cast, dim3(64, E), dim3(256), 0, s, M, 1);
 }
 
 // bf16(x) feature-major for the layer-1 weight gradient: the training data
@@ -1047,7 +1069,7 @@ void mlp_forward(MlpState* st, int64_t m, const float* Xc, float* out, hipStream
   if (st->fwd_wg_per_cu > 0)
     grid = std::min<int64_t>(grid, round_up((int64_t)st->ncu * st->fwd_wg_per_cu, 8));
   hipLaunchKernelGGL(k_mlp_fwd<false>, dim3((unsigned)grid), dim3(256), mlp_fwd_smem(M.D, M.H), s,
-                     M, m, Xc, fo, ntile);
+                     M, m, Xc, fo, ntile, 0);
 }
 
 void ens_score(int E, int64_t m, const float* out, bool lcb, double arg, float* score,
