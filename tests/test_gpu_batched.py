@@ -394,6 +394,35 @@ def test_score_prepare_then_batched_equals_unprepared(ctx, prec):
         mo.free()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_score_batched_many_problems_and_large_n(ctx, prec):
+    """More than 64 problems (the problem of an item found by binary search,
+    not the one-wave ballot) and one problem large enough that two
+    workgroups per CU no longer leave room for the descriptor copy in LDS
+    (descriptors read from global memory): every problem's EI equals its
+    single-problem scoring within the reordering bound, and its argmax is
+    the single path's."""
+    probs = I.make_c3(lam=0.1, replicate=5, scaled=True, B=70, m=300, n_range=(16, 120))
+    probs += I.make_c3(lam=0.1, replicate=6, scaled=True, B=1, m=300, n_range=(900, 900))
+    st, models, _, _ = _fit_batch(ctx, probs)
+    assert st == G.OK
+    Xcs = [_t(p.Xc, torch.float32) for p in probs]
+    outs, am, _ = G.score_batched(ctx, models, Xcs, prec, want=("mu", "sigma", "ei"))
+    torch.cuda.synchronize()
+    am = am.cpu().numpy()
+    for b, (mo, x) in enumerate(zip(models, Xcs)):
+        single = G.score(ctx, mo, x, prec)
+        e1 = single["ei"].double().cpu().numpy()
+        eb = outs["ei"][b].double().cpu().numpy()
+        scale = float(single["mu"].abs().max()) + float(single["sigma"].abs().max())
+        assert np.max(np.abs(eb - e1)) <= 1e-5 * scale, (b, probs[b].n)
+        srt = np.sort(e1)[::-1]
+        if srt[0] - srt[1] > 1e-4 * max(srt[0], 1e-30):
+            assert am[b] == int(single["argmax"].item()), b
+    for mo in models:
+        mo.free()
+
+
 def test_batched_full_c3_shape_smoke(ctx):
     """The literal batch shape: 64 sub-searches, d in 2..12, n in 16..400,
     8192 candidates each; every argmax is a valid index with finite EI."""
