@@ -153,8 +153,9 @@ struct FwdOut {
   float* out;               // E x n
   float* pre1;              // E x n x H (TRAIN)
   unsigned short* h1;       // E x n x H (TRAIN)
-  unsigned short* h1T;      // E x H x n (TRAIN)
+  unsigned short* h1T;      // E x H x ldt (TRAIN)
   float* pre2;              // E x n x H (TRAIN)
+  int64_t ldt;              // row stride of the feature-major copies (elements)
 };
 
 __device__ __forceinline__ int fwd_ldx(int DP) { return DP + 8; }  // bf16 row stride of x / W1 tiles
@@ -279,7 +280,7 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fwd(MlpDev M, int64_t n, const f
     if (TRAIN) {  // feature-major copy, coalesced along the samples
       for (int q = t; q < H * MT; q += 256) {
         const int h = q / MT, r = q % MT;
-        if (i0 + r < n) O.h1T[((int64_t)e * H + h) * n + i0 + r] = hA[r * ldh + h];
+        if (i0 + r < n) O.h1T[((int64_t)e * H + h) * O.ldt + i0 + r] = hA[r * ldh + h];
       }
     }
     #pragma unroll
@@ -364,8 +365,9 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fwd(MlpDev M, int64_t n, const f
 // for gb2 (unrounded dpre2), gw3 (dout h2) and gb3, and the squared error.
 struct BwdBuf {
   unsigned short* dpre2;   // E x n x H
-  unsigned short* dpre2T;  // E x H x n
+  unsigned short* dpre2T;  // E x H x ldt
   float* colpart;          // E x nblk x (2H + 2): gb2, gw3, gb3, loss
+  int64_t ldt;
 };
 __global__ void __launch_bounds__(256) k_mlp_bwd_out(MlpDev M, int64_t n, const float* __restrict__ y,
                                                      const float* __restrict__ out,
@@ -441,34 +443,37 @@ __global__ void __launch_bounds__(256) k_mlp_bwd_out(MlpDev M, int64_t n, const 
   // feature-major copy, coalesced along the samples
   for (int q = t; q < H * MT; q += 256) {
     const int j = q / MT, r = q % MT;
-    if (i0 + r < n) B.dpre2T[((int64_t)e * H + j) * n + i0 + r] = tT[j][r];
+    if (i0 + r < n) B.dpre2T[((int64_t)e * H + j) * B.ldt + i0 + r] = tT[j][r];
   }
 }
 
 // C[M][N] = A[M][K] B[N][K]^T on the bfloat16 matrix cores, batched over the
-// members (blockIdx.z) and split over K (blockIdx.y); 64 x 64 tile per
-// workgroup, 32 x 32 per wave, operands read straight from L2 (16 bytes per
-// lane).  Epilogue: STORE writes C to out[split][member][M][N]; DPRE1 writes
+// members (blockIdx.z) and split over K (blockIdx.y); WM x WN waves per
+// workgroup, a 32 x 32 tile per wave (waves of one workgroup share operand
+// rows in L1), operands read straight from L2 (16 bytes per lane).  Epilogue: STORE writes C to out[split][member][M][N]; DPRE1 writes
 // C * GELU'(pre1) to out[member][M][N] (one split).
 enum { EPI_STORE = 0, EPI_DPRE1 = 1 };
+
 struct Gemm {
   const unsigned short* A;
   const unsigned short* B;
   int64_t sA, sB;   // member strides (elements)
+  int64_t lda, ldb; // row strides (elements, multiples of 8)
   int M, N, K;
   int kchunk;       // K per split
   float* out;
   const float* pre1;
-  unsigned short* dpre1T;  // DPRE1: bf16(dpre1), feature-major [member][N][M]
+  unsigned short* dpre1T;  // DPRE1: bf16(dpre1), feature-major [member][N][ldo]
+  int64_t ldo;
   float* b1part;           // DPRE1: per 32-row block column sums of dpre1 [member][M/32][N]
 };
-template <int EPI>
-__global__ void __launch_bounds__(256) k_gemm_nt(Gemm g) {
+template <int EPI, int WM, int WN, int KU>
+__global__ void __launch_bounds__(64 * WM * WN) k_gemm_nt(Gemm g) {
   const int e = blockIdx.z, split = blockIdx.y;
-  const int tilesN = g.N / 64;
+  const int tilesN = g.N / (32 * WN);
   const int tm = blockIdx.x / tilesN, tn = blockIdx.x % tilesN;
-  const int lane = threadIdx.x % 64, wave = wave_id();
-  const int r0 = tm * 64 + (wave / 2) * 32, c0 = tn * 64 + (wave % 2) * 32;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int r0 = (tm * WM + wave / WN) * 32, c0 = (tn * WN + wave % WN) * 32;
   const unsigned short* A = g.A + (int64_t)e * g.sA;
   const unsigned short* Bm = g.B + (int64_t)e * g.sB;
   const int kb = split * g.kchunk, ke = min(g.K, kb + g.kchunk);
@@ -477,21 +482,48 @@ __global__ void __launch_bounds__(256) k_gemm_nt(Gemm g) {
   for (int a = 0; a < 2; ++a)
     #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f4{0, 0, 0, 0};
-  for (int k0 = kb; k0 < ke; k0 += 32) {
-    us8 av[2], bv[2];
-    #pragma unroll
-    for (int a = 0; a < 2; ++a)
-      av[a] = *(const us8*)(A + (int64_t)(r0 + a * 16 + lane % 16) * g.K + k0 + 8 * (lane / 16));
+  // DPRE1: the pre-activations the epilogue scales by are requested before
+  // the product, so their latency hides behind it
+  float pre[2][2][4];
+  if (EPI == EPI_DPRE1) {
     #pragma unroll
     for (int b = 0; b < 2; ++b)
-      bv[b] = *(const us8*)(Bm + (int64_t)(c0 + b * 16 + lane % 16) * g.K + k0 + 8 * (lane / 16));
-    #pragma unroll
-    for (int a = 0; a < 2; ++a)
       #pragma unroll
-      for (int b = 0; b < 2; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, av[a]),
-                                                            __builtin_bit_cast(bf8, bv[b]),
-                                                            acc[a][b], 0, 0, 0);
+      for (int a = 0; a < 2; ++a)
+        #pragma unroll
+        for (int r = 0; r < 4; ++r)
+          pre[b][a][r] = g.pre1[((int64_t)e * g.M + r0 + a * 16 + 4 * (lane / 16) + r) * g.N +
+                                c0 + b * 16 + lane % 16];
+  }
+  // the operands of KU consecutive K steps are requested together (one
+  // memory latency per KU steps instead of per step); the accumulation
+  // order along K is the same for every KU.  The K range is a multiple of 32.
+  for (int k0 = kb; k0 < ke; k0 += 32 * KU) {
+    us8 av[KU][2], bv[KU][2];
+    #pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      if (k0 + 32 * u < ke) {
+        const int k = k0 + 32 * u + 8 * (lane / 16);
+        #pragma unroll
+        for (int a = 0; a < 2; ++a)
+          av[u][a] = *(const us8*)(A + (int64_t)(r0 + a * 16 + lane % 16) * g.lda + k);
+        #pragma unroll
+        for (int b = 0; b < 2; ++b)
+          bv[u][b] = *(const us8*)(Bm + (int64_t)(c0 + b * 16 + lane % 16) * g.ldb + k);
+      }
+    }
+    #pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      if (k0 + 32 * u < ke) {
+        #pragma unroll
+        for (int a = 0; a < 2; ++a)
+          #pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, av[u][a]),
+                                                                __builtin_bit_cast(bf8, bv[u][b]),
+                                                                acc[a][b], 0, 0, 0);
+      }
+    }
   }
   if (EPI == EPI_STORE) {
     #pragma unroll
@@ -522,14 +554,13 @@ __global__ void __launch_bounds__(256) k_gemm_nt(Gemm g) {
       unsigned short q[4];
       #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t o = ((int64_t)e * g.M + row0 + r) * g.N + col;
-        const float v = acc[a][b][r] * gelu_grad(g.pre1[o]);
+        const float v = acc[a][b][r] * gelu_grad(pre[b][a][r]);
         csum += v;
         q[r] = f2bf(v);
       }
       const uint2 pk = make_uint2((unsigned)q[0] | ((unsigned)q[1] << 16),
                                   (unsigned)q[2] | ((unsigned)q[3] << 16));
-      *(uint2*)(g.dpre1T + ((int64_t)e * g.N + col) * g.M + row0) = pk;
+      *(uint2*)(g.dpre1T + ((int64_t)e * g.N + col) * g.ldo + row0) = pk;
     }
     csum += __shfl_xor(csum, 16);
     csum += __shfl_xor(csum, 32);
@@ -538,13 +569,14 @@ __global__ void __launch_bounds__(256) k_gemm_nt(Gemm g) {
 }
 
 // Layer-1 inputs for the weight-gradient product: bf16(x) feature-major,
-// xT[k][i] for k < D, zero rows up to DX (the product's 64-column tile).
+// xT[k][i] (row stride ldt) for k < D, zero rows up to DX (32 or 64: whole
+// 32-column tiles).
 __global__ void __launch_bounds__(256) k_mlp_xt(const float* __restrict__ X, int64_t n, int D,
-                                                int DX, unsigned short* __restrict__ xT) {
+                                                int DX, int64_t ldt, unsigned short* __restrict__ xT) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)DX * n;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t k = e / n, i = e % n;
-    xT[e] = k < D ? f2bf(X[i * D + k]) : (unsigned short)0;
+    xT[k * ldt + i] = k < D ? f2bf(X[i * D + k]) : (unsigned short)0;
   }
 }
 
@@ -837,6 +869,7 @@ struct Ws {
   float *out, *pre1, *pre2, *b1part, *colpart, *gW2part, *l1part;
   unsigned short *h1, *h1T, *dpre2, *dpre2T, *dpre1T, *xT;
   int nblk, S2, S1, DX;
+  int64_t ldt;  // row stride of the feature-major (sample-contiguous) buffers
 };
 static Ws carve(MlpState* st, int64_t n, size_t* total) {
   const MlpDev& M = st->dev;
@@ -845,7 +878,8 @@ static Ws carve(MlpState* st, int64_t n, size_t* total) {
   w.nblk = (int)ceil_div(n, MT);
   w.S2 = (int)std::min<int64_t>(8, ceil_div(n, 512));
   w.S1 = (int)std::min<int64_t>(8, ceil_div(n, 512));
-  w.DX = 64;  // the weight-gradient product's column tile (D <= 64)
+  w.DX = D <= 32 ? 32 : 64;  // the weight-gradient product's columns (D <= 64), whole tiles
+  w.ldt = n;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -855,10 +889,9 @@ static Ws carve(MlpState* st, int64_t n, size_t* total) {
   const size_t o_out = take(E * n * 4), o_pre1 = take(E * n * H * 4), o_pre2 = take(E * n * H * 4),
                o_b1 = take(E * (n / 32) * H * 4), o_col = take(E * w.nblk * (2 * H + 2) * 4),
                o_gw2 = take((size_t)w.S2 * E * H * H * 4), o_l1 = take((size_t)w.S1 * E * H * w.DX * 4),
-               o_h1 = take(E * n * H * 2), o_h1T = take(E * n * H * 2), o_dp2 = take(E * n * H * 2),
-               o_dp2T = take(E * n * H * 2), o_dp1T = take(E * n * H * 2),
-               o_xT = take((size_t)w.DX * n * 2);
-  (void)D;
+               o_h1 = take(E * n * H * 2), o_h1T = take(E * H * w.ldt * 2), o_dp2 = take(E * n * H * 2),
+               o_dp2T = take(E * H * w.ldt * 2), o_dp1T = take(E * H * w.ldt * 2),
+               o_xT = take((size_t)w.DX * w.ldt * 2);
   *total = off;
   unsigned char* b = (unsigned char*)st->ws;
   if (b) {
@@ -904,29 +937,33 @@ void mlp_step(MlpState* st, int64_t n, const float* X, const float* y, double lr
   Ws w = carve(st, n, &bytes);
   MlpDev& M = st->dev;
   const int E = M.E, H = M.H;
-  FwdOut fo{w.out, w.pre1, w.h1, w.h1T, w.pre2};
+  FwdOut fo{w.out, w.pre1, w.h1, w.h1T, w.pre2, w.ldt};
   hipLaunchKernelGGL(k_mlp_fwd<true>, dim3((unsigned)fwd_items((int)w.nblk, E)), dim3(256),
                      mlp_fwd_smem(M.D, H), s, M, n, X, fo, (int)w.nblk, apply);
-  BwdBuf bb{w.dpre2, w.dpre2T, w.colpart};
+  BwdBuf bb{w.dpre2, w.dpre2T, w.colpart, w.ldt};
   hipLaunchKernelGGL(k_mlp_bwd_out, dim3(w.nblk, E), dim3(256), 0, s, M, n, y, w.out, w.pre2, bb);
-  // gW2 = dpre2^T h1 over the samples (split over S2 sample chunks)
+  // gW2 = dpre2^T h1 over the samples (split over S2 sample chunks; one
+  // wave per workgroup measured faster than 2 x 2 for these grids)
   Gemm g1{};
   g1.A = w.dpre2T;
   g1.B = w.h1T;
-  g1.sA = (int64_t)H * n;
-  g1.sB = (int64_t)H * n;
+  g1.sA = (int64_t)H * w.ldt;
+  g1.sB = (int64_t)H * w.ldt;
+  g1.lda = g1.ldb = w.ldt;
   g1.M = H;
   g1.N = H;
   g1.K = (int)n;
   g1.kchunk = (int)round_up(ceil_div(n, w.S2), 32);
   g1.out = w.gW2part;
-  hipLaunchKernelGGL(k_gemm_nt<EPI_STORE>, dim3((H / 64) * (H / 64), w.S2, E), dim3(256), 0, s, g1);
+  hipLaunchKernelGGL((k_gemm_nt<EPI_STORE, 1, 1, 8>), dim3((H / 32) * (H / 32), w.S2, E), dim3(64), 0, s,
+                     g1);
   // dh1 = dpre2 W2 -> dpre1 = dh1 GELU'(pre1)
   Gemm g2{};
   g2.A = w.dpre2;
   g2.B = M.W2Tb;
   g2.sA = (int64_t)n * H;
   g2.sB = (int64_t)H * H;
+  g2.lda = g2.ldb = H;
   g2.M = (int)n;
   g2.N = H;
   g2.K = H;
@@ -934,22 +971,25 @@ void mlp_step(MlpState* st, int64_t n, const float* X, const float* y, double lr
   g2.out = nullptr;
   g2.pre1 = w.pre1;
   g2.dpre1T = w.dpre1T;
+  g2.ldo = w.ldt;
   g2.b1part = w.b1part;
-  hipLaunchKernelGGL(k_gemm_nt<EPI_DPRE1>, dim3((unsigned)(n / 64) * (H / 64), 1, E), dim3(256), 0,
-                     s, g2);
+  hipLaunchKernelGGL((k_gemm_nt<EPI_DPRE1, 2, 2, 8>), dim3((unsigned)(n / 64) * (H / 64), 1, E),
+                     dim3(256), 0, s, g2);
   // gW1 = dpre1^T x over the samples (bf16 operands, split over S1 chunks);
   // x^T is shared by the members
   Gemm g3{};
   g3.A = w.dpre1T;
   g3.B = w.xT;
-  g3.sA = (int64_t)H * n;
+  g3.sA = (int64_t)H * w.ldt;
   g3.sB = 0;
+  g3.lda = g3.ldb = w.ldt;
   g3.M = H;
   g3.N = w.DX;
   g3.K = (int)n;
   g3.kchunk = (int)round_up(ceil_div(n, w.S1), 32);
   g3.out = w.l1part;
-  hipLaunchKernelGGL(k_gemm_nt<EPI_STORE>, dim3((H / 64) * (w.DX / 64), w.S1, E), dim3(256), 0, s, g3);
+  hipLaunchKernelGGL((k_gemm_nt<EPI_STORE, 1, 1, 8>), dim3((H / 32) * (w.DX / 32), w.S1, E), dim3(64), 0, s,
+                     g3);
   AdamIn ai{w.gW2part, w.S2, w.l1part, w.S1, w.DX, w.b1part, (int)(n / 32), w.colpart, w.nblk,
             lr, grad_out, loss_hist, n, apply};
   hipLaunchKernelGGL(k_mlp_adam, dim3(adam_grid_x(H, st->dev.D), E), dim3(256), 0, s, M, ai);
@@ -962,7 +1002,7 @@ static void mlp_prepare_x(MlpState* st, int64_t n, const float* X, hipStream_t s
   size_t bytes;
   Ws w = carve(st, n, &bytes);
   const unsigned g = (unsigned)std::min<int64_t>(1024, ceil_div((int64_t)w.DX * n, 256));
-  hipLaunchKernelGGL(k_mlp_xt, dim3(g), dim3(256), 0, s, X, n, st->dev.D, w.DX, w.xT);
+  hipLaunchKernelGGL(k_mlp_xt, dim3(g), dim3(256), 0, s, X, n, st->dev.D, w.DX, w.ldt, w.xT);
 }
 
 // Training: the step sequence is captured once per (n, inputs, lr, history)
