@@ -477,7 +477,8 @@ def run_c3(args):
     ``--c3-fit per-launch``: one per launch), scores the pools of each
     launch with one persistent BF16 matrix-core launch (replayed from its
     HIP graph: the batch shape repeats from step to step), then reads the
-    3 x 64 argmaxes back and checks the fits' statuses.  `value` = candidates scored per second of whole
+    3 x 64 argmaxes back and checks the fits' statuses (host work that runs
+    beside the next step's fit; the last step's before the clock stops).  `value` = candidates scored per second of whole
     steps.  The scoring kernel's own time is taken in a second pass with
     kernel timing on (eager launches bracketed by HIP events)."""
     import ctypes as C
@@ -532,10 +533,22 @@ def run_c3(args):
             raise SystemExit(f"batched fit failed: {status}")
         return models
 
-    def step(keep=False):
+    def finish(groups, kept):
+        # the fits' statuses (read from the pinned copies made behind each
+        # fit) and the models freed (their buffers return in stream order)
+        for models in groups:
+            st, status, _ = G.status_batched(ctx, models)
+            if st != G.OK:
+                raise SystemExit(f"batched fit failed: {status}")
+        for models in kept:
+            for mo in models:
+                mo.free()
+
+    def step(keep=False, pending=None):
         # the fits and the three scoring launches are queued back to back;
-        # one synchronisation reads the argmaxes, then the fits' statuses
-        # (one copy per batched fit)
+        # the previous step's status check and frees (host work only) run
+        # while this step's fit is on the GPU; one synchronisation reads the
+        # argmaxes
         kept = []
         if merged:
             models = fit(everything)
@@ -550,26 +563,31 @@ def run_c3(args):
                 kept.append(fit(bt["batch"]))
                 launch(bt, kept[-1])
             groups = kept
+        if pending is not None:
+            finish(*pending)
         picks = am_all.cpu()  # the next configuration of every sub-search
-        for models in groups:
-            st, status, _ = G.status_batched(ctx, models)
+        if keep:
+            st, status, _ = G.status_batched(ctx, [mo for models in groups for mo in models])
             if st != G.OK:
                 raise SystemExit(f"batched fit failed: {status}")
-        if not keep:
-            for models in kept:
-                for mo in models:
-                    mo.free()
-            kept = []
-        return picks, kept
+            return picks, kept
+        return picks, (groups, kept)
 
-    for _ in range(args.warmup):
-        step()
+    def run_steps(k):
+        # every step's whole work (fit, scores, argmaxes, status check,
+        # frees) is done by the time the last step returns
+        pending = None
+        for _ in range(k):
+            _, pending = step(pending=pending)
+        if pending is not None:
+            finish(*pending)
+
+    run_steps(args.warmup)
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
     a.record()
-    for _ in range(args.steps):
-        step()
+    run_steps(args.steps)
     b.record()
     torch.cuda.synchronize()
     ms_step = a.elapsed_time(b) / args.steps
