@@ -303,9 +303,11 @@ gpbo_status gpbo_fit_hyper_batched(gpbo_ctx ctx, int32_t B, const gpbo_problem* 
 
 /* Release a model (NULL is ignored).  Work still queued that uses it may
  * run on: with a context allocator the buffers go back in the order of the
- * stream they were allocated on, without a wait, when that is the stream
- * the model's work is queued on; otherwise (another stream since, or
- * hipFree) the call first waits for the context's stream. */
+ * stream they were allocated on, without a wait, when every use of the
+ * model was queued on that stream.  A model used on another stream first
+ * waits for the whole device (that stream may still be reading it); a
+ * context moved to another stream since the allocation, or hipFree
+ * without an allocator, waits for the context's stream. */
 gpbo_status gpbo_model_free(gpbo_model model);
 /* Host copy of the GPBO_NSTATS scalars (synchronises). */
 gpbo_status gpbo_model_stats(gpbo_model model, double* stats);
@@ -484,6 +486,8 @@ gpbo_status gpbo_plan_searches(int32_t P, int32_t R, const double* S, const int3
  * init: device, members x P float32 initial master weights. */
 gpbo_status gpbo_mlp_create(gpbo_ctx ctx, int32_t members, int32_t d_in, int32_t hidden,
                             const float* init, gpbo_mlp* out);
+/* Release a network (NULL is ignored).  Waits for the whole device first:
+ * its buffers may be in use on any stream the context has queued on. */
 gpbo_status gpbo_mlp_free(gpbo_mlp mlp);
 /* Number of parameters of one member. */
 int64_t gpbo_mlp_nparams(int32_t d_in, int32_t hidden);

@@ -713,11 +713,16 @@ gpbo_status gpbo_model_free(gpbo_model M) {
   if (!M) return GPBO_OK;
   DeviceGuard g(M->ctx->device);
   // With the context's allocator the buffers return in the order of the
-  // stream they were allocated on, behind the work queued there; a wait is
-  // needed only when some of them came from another stream than the one the
-  // model's work is queued on now (or without an allocator: hipFree).
+  // stream they were allocated on, behind the work queued there.  A model
+  // whose buffers were touched on another stream may still be read there
+  // (the context may have moved back to the allocating stream since), so
+  // it waits for the whole device; otherwise a wait on the context's
+  // stream covers the case of a context moved to another stream, and
+  // hipFree without an allocator.
   const Ctx* c = M->ctx;
-  if (!c->has_alloc || M->alloc_mixed || M->alloc_stream != c->stream)
+  if (M->alloc_mixed)
+    (void)hipDeviceSynchronize();
+  else if (!c->has_alloc || M->alloc_stream != c->stream)
     (void)hipStreamSynchronize(c->stream);
   M->ctx->live_models.erase(M);
   free_model_buffers(M);
@@ -798,7 +803,9 @@ static void note_stream(Model* M, hipStream_t s) {
 // Buffers of M that may still be read by queued work are released only
 // after a wait when the stream order does not cover it (see gpbo_model_free).
 static gpbo_status wait_before_release(Ctx* c, const Model* M) {
-  if (!c->has_alloc || M->alloc_mixed || M->alloc_stream != c->stream)
+  if (M->alloc_mixed)
+    HIP_TRY(c, hipDeviceSynchronize());
+  else if (!c->has_alloc || M->alloc_stream != c->stream)
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   return GPBO_OK;
 }
@@ -1620,6 +1627,9 @@ gpbo_status gpbo_mlp_create(gpbo_ctx c, int32_t members, int32_t d_in, int32_t h
 gpbo_status gpbo_mlp_free(gpbo_mlp mlp) {
   if (!mlp) return GPBO_OK;
   DeviceGuard g(mlp->ctx->device);
+  // the network's buffers may be in use on any stream the context has
+  // queued on since they were allocated: wait for the device first
+  (void)hipDeviceSynchronize();
   mlp->ctx->live_mlps.erase(mlp);
   if (mlp->ws) dfree(mlp->ctx, mlp->ws);
   mlp_destroy(mlp->st);

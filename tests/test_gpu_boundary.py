@@ -172,3 +172,85 @@ def test_debug_rejects_non_finite_pool():
     for mo in models + [m]:
         mo.free()
     dctx.close()
+
+
+def _overwrite_freed_memory():
+    # allocations on the current stream of the sizes the freed buffers came
+    # in (the caching allocator hands freed blocks out again at once),
+    # filled with NaN
+    junk = []
+    for mb in (16, 8, 4, 2, 1, 0.5, 0.25, 0.125):
+        for _ in range(4):
+            junk.append(torch.full((int(mb * 262144),), float("nan"), dtype=torch.float32, device=DEV))
+    return junk
+
+
+def _two_streams():
+    s1 = torch.cuda.Stream(device=DEV)
+    s2 = torch.cuda.Stream(device=DEV)
+    return s1, s2
+
+
+def test_model_freed_after_scoring_on_another_stream():
+    """A model fitted and scored on stream S1, scored again on S2 (a
+    2^20-candidate pool: milliseconds of work), the context moved back to S1
+    and the model freed at once: the free waits for the device, so S2's
+    scoring reads intact buffers although the freed memory is handed out
+    again on S1 and overwritten straight away.  The S2 outputs equal the S1
+    ones bit for bit."""
+    s1, s2 = _two_streams()
+    prev = torch.cuda.current_stream(DEV)
+    torch.cuda.set_stream(s1)
+    c = G.Context(0)
+    try:
+        p = I.make_config("c2", replicate=0)
+        rng = np.random.default_rng(31)
+        Xc = torch.tensor(rng.uniform(size=(1 << 20, p.d)), dtype=torch.float32, device=DEV)
+        m = G.fit(c, _t(p.X), _t(p.y), p.lengthscale, p.kernel, p.signal_var, p.noise_var)
+        ref = G.score(c, m, Xc, "fp32")
+        torch.cuda.synchronize()
+        print("score on S2, free on S1", flush=True)
+        with torch.cuda.stream(s2):
+            c.sync_stream()
+            out = G.score(c, m, Xc, "fp32")
+        c.sync_stream()  # back on S1
+        m.free()
+        junk = _overwrite_freed_memory()
+        torch.cuda.synchronize()
+        for k in ("mu", "sigma", "ei"):
+            assert torch.equal(out[k], ref[k]), k
+        assert out["argmax"].item() == ref["argmax"].item()
+        del junk
+    finally:
+        c.close()
+        torch.cuda.set_stream(prev)
+
+
+def test_network_freed_after_forward_on_another_stream():
+    """The same for a network: created and run on S1, run again on S2 over
+    2^20 candidates, freed on S1 at once; the S2 outputs equal the S1 ones."""
+    s1, s2 = _two_streams()
+    prev = torch.cuda.current_stream(DEV)
+    torch.cuda.set_stream(s1)
+    c = G.Context(0)
+    try:
+        E, D, H = 5, 20, 256
+        init = I.mlp_init(np.random.default_rng(33), members=E, d_in=D, hidden=H)
+        net = G.Mlp(c, G.Mlp.pack(**init, device=DEV), E, D, H)
+        rng = np.random.default_rng(34)
+        Xc = torch.tensor(rng.uniform(size=(1 << 20, D)), dtype=torch.float32, device=DEV)
+        ref = net.forward(Xc)
+        torch.cuda.synchronize()
+        print("forward on S2, free on S1", flush=True)
+        with torch.cuda.stream(s2):
+            c.sync_stream()
+            out = net.forward(Xc)
+        c.sync_stream()
+        net.free()
+        junk = _overwrite_freed_memory()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+        del junk
+    finally:
+        c.close()
+        torch.cuda.set_stream(prev)
