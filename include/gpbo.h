@@ -145,7 +145,8 @@ gpbo_status gpbo_ctx_create(int32_t device, void* stream, const gpbo_allocator* 
 /* Waits for the context's stream, then frees every model and MLP still
  * alive on the context (their handles become invalid) and the context. */
 gpbo_status gpbo_ctx_destroy(gpbo_ctx ctx);
-/* Replace the stream work is queued on. */
+/* Replace the stream work is queued on.  Waits first for the work queued
+ * on the previous stream (when the two differ). */
 gpbo_status gpbo_ctx_set_stream(gpbo_ctx ctx, void* stream);
 /* Kernel timing.  While enabled, every launch of a candidate-scoring kernel
  * (the dominant kernel of gpbo_score: the fused kernel, or the triangular

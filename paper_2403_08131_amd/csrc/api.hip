@@ -522,6 +522,14 @@ gpbo_status gpbo_ctx_destroy(gpbo_ctx c) {
 
 gpbo_status gpbo_ctx_set_stream(gpbo_ctx c, void* stream) {
   if (!c) return GPBO_E_INVALID_ARG;
+  // the work queued so far finishes first: the context's own buffers
+  // (descriptor uploads, reduction scratch) and its objects' buffers are
+  // then used on one stream at a time, and a release after the switch needs
+  // no wait on the old stream
+  if ((hipStream_t)stream != c->stream) {
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
   c->stream = (hipStream_t)stream;
   return GPBO_OK;
 }

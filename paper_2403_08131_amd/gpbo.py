@@ -199,7 +199,8 @@ class Context:
             raise GpboError(st, lib().gpbo_last_error(self.h).decode())
 
     def sync_stream(self):
-        """Move the context to torch's current stream."""
+        """Move the context to torch's current stream (the library first waits
+        for the work queued on the previous one)."""
         self._tstream = torch.cuda.current_stream(self.device)
         self.check(lib().gpbo_ctx_set_stream(self.h, _stream_handle(self.device)))
 

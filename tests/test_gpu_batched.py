@@ -7,6 +7,8 @@ equal to the single-problem EI to float32 rounding of reordered sums (1e-5
 relative to the pool maximum); argmax identical unless the oracle's top two
 are within 1e-4; graph replays bit-identical to an eager launch.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -394,6 +396,16 @@ def test_score_prepare_then_batched_equals_unprepared(ctx, prec):
         mo.free()
 
 
+def _mean_terms(p):
+    """ystd max_c sum_j |k(x_c, x_j) alpha_j| over the pool (SE kernel, from
+    the oracle's fit): the size of the float32 mean sum's terms."""
+    assert p.kernel == G.KERNEL_SE
+    f = O.fit(p.X, p.y, p.lengthscale, O.SE, p.signal_var, p.noise_var)
+    r2 = (((p.Xc[:, None, :] - p.X[None, :, :]) / p.lengthscale) ** 2).sum(-1)
+    k = p.signal_var * np.exp(-0.5 * r2)
+    return f.ystd * float(np.max(np.abs(k) @ np.abs(f.alpha)))
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_score_batched_many_problems_and_large_n(ctx, prec):
     """More than 64 problems (the problem of an item found by binary search,
@@ -401,9 +413,20 @@ def test_score_batched_many_problems_and_large_n(ctx, prec):
     workgroups per CU no longer leave room for the descriptor copy in LDS
     (descriptors read from global memory): every problem's EI equals its
     single-problem scoring within the reordering bound, and its argmax is
-    the single path's."""
+    the single path's.
+
+    The single path picks its tile size per problem, the batched launch one
+    for the batch by timing, so the two may group the float32 mean sum
+    differently: the bound is 1e-5 (|mu| + sigma) plus 4 u S (u = 2^-24,
+    S = ystd max_c sum_j |k_cj alpha_j|; the worst case of two groupings of
+    n terms is 2 gamma_n S, n times more, and the largest deviation seen at
+    n = 900 and cond(K) 9e5 was 0.07 u S).  The n = 900 problem takes noise
+    1e-2 (cond(K) ~ 9e3 instead of ~ 9e5 with the generator's 1e-4), so that
+    its S, and with it the bound, stays small."""
     probs = I.make_c3(lam=0.1, replicate=5, scaled=True, B=70, m=300, n_range=(16, 120))
-    probs += I.make_c3(lam=0.1, replicate=6, scaled=True, B=1, m=300, n_range=(900, 900))
+    big = I.make_c3(lam=0.1, replicate=6, scaled=True, B=1, m=300, n_range=(900, 900))[0]
+    probs.append(dataclasses.replace(big, noise_var=1e-2))
+    S = [_mean_terms(p) for p in probs]
     st, models, _, _ = _fit_batch(ctx, probs)
     assert st == G.OK
     Xcs = [_t(p.Xc, torch.float32) for p in probs]
@@ -415,9 +438,10 @@ def test_score_batched_many_problems_and_large_n(ctx, prec):
         e1 = single["ei"].double().cpu().numpy()
         eb = outs["ei"][b].double().cpu().numpy()
         scale = float(single["mu"].abs().max()) + float(single["sigma"].abs().max())
-        assert np.max(np.abs(eb - e1)) <= 1e-5 * scale, (b, probs[b].n)
+        tol = 1e-5 * scale + 4 * 2.0 ** -24 * S[b]
+        assert np.max(np.abs(eb - e1)) <= tol, (b, probs[b].n)
         srt = np.sort(e1)[::-1]
-        if srt[0] - srt[1] > 1e-4 * max(srt[0], 1e-30):
+        if srt[0] - srt[1] > 2 * tol:
             assert am[b] == int(single["argmax"].item()), b
     for mo in models:
         mo.free()
