@@ -117,10 +117,12 @@ def test_score_batched_matches_single_and_oracle(ctx, prec):
         single = G.score(ctx, mo, Xcs[b], prec)
         e1 = single["ei"].double().cpu().numpy()
         eb = eis[b].double().cpu().numpy()
-        # the single-problem path may split its partial sums differently:
-        # EI moves by at most |dmu| + |dsigma|
+        # the single-problem path may split its partial sums differently
+        # (EI moves by at most |dmu| + |dsigma|); the float32 mean's share of
+        # that grows with its terms (the bound of the large-n test below)
         scale = float(single["mu"].abs().max()) + float(single["sigma"].abs().max())
-        assert np.max(np.abs(eb - e1)) <= 1e-5 * scale, (b, p.n, p.d)
+        tol = 1e-5 * scale + 4 * 2.0 ** -24 * _mean_terms(p)
+        assert np.max(np.abs(eb - e1)) <= tol, (b, p.n, p.d)
         f = O.fit(p.X, p.y, p.lengthscale, O.SE, p.signal_var, p.noise_var)
         full = O.score(f, p.Xc)
         ref = full["ei"]
