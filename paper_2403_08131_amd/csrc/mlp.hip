@@ -148,11 +148,11 @@ __global__ void k_mlp_cast(MlpDev M) {
 //   LDS tile;
 //   layer 2: pre2 = h1 W2^T + b2, each wave 64 samples x 64 outputs;
 //   epilogue h2 = bf16(GELU(pre2)), out = w3 . h2 + b3.
-// With TRAIN the kernel also writes pre1, h1 (both layouts) and pre2.
+// With TRAIN the kernel also writes pre1, h1 (feature-major, the operand of
+// the layer-2 weight gradient) and pre2.
 struct FwdOut {
   float* out;               // E x n
   float* pre1;              // E x n x H (TRAIN)
-  unsigned short* h1;       // E x n x H (TRAIN)
   unsigned short* h1T;      // E x H x ldt (TRAIN)
   float* pre2;              // E x n x H (TRAIN)
   int64_t ldt;              // row stride of the feature-major copies (elements)
@@ -272,7 +272,6 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fwd(MlpDev M, int64_t n, const f
         if (TRAIN && i0 + row < n) {
           const int64_t o = ((int64_t)e * n + i0 + row) * H + h0;
           *(float4*)(O.pre1 + o) = make_float4(pre[0], pre[1], pre[2], pre[3]);
-          *(uint2*)(O.h1 + o) = hb;
         }
       }
     }
@@ -877,7 +876,7 @@ int64_t mlp_nparams(MlpState* st) { return st->dev.P; }
 // Workspace layout for n training samples.
 struct Ws {
   float *out, *pre1, *pre2, *b1part, *colpart, *gW2part, *l1part;
-  unsigned short *h1, *h1T, *dpre2, *dpre2T, *dpre1T, *xT;
+  unsigned short *h1T, *dpre2, *dpre2T, *dpre1T, *xT;
   int nblk, S2, S1, DX;
   int64_t ldt;  // row stride of the feature-major (sample-contiguous) buffers
 };
@@ -899,7 +898,7 @@ static Ws carve(MlpState* st, int64_t n, size_t* total) {
   const size_t o_out = take(E * n * 4), o_pre1 = take(E * n * H * 4), o_pre2 = take(E * n * H * 4),
                o_b1 = take(E * (n / 32) * H * 4), o_col = take(E * w.nblk * (2 * H + 2) * 4),
                o_gw2 = take((size_t)w.S2 * E * H * H * 4), o_l1 = take((size_t)w.S1 * E * H * w.DX * 4),
-               o_h1 = take(E * n * H * 2), o_h1T = take(E * H * w.ldt * 2), o_dp2 = take(E * n * H * 2),
+               o_h1T = take(E * H * w.ldt * 2), o_dp2 = take(E * n * H * 2),
                o_dp2T = take(E * H * w.ldt * 2), o_dp1T = take(E * H * w.ldt * 2),
                o_xT = take((size_t)w.DX * w.ldt * 2);
   *total = off;
@@ -912,7 +911,6 @@ static Ws carve(MlpState* st, int64_t n, size_t* total) {
     w.colpart = (float*)(b + o_col);
     w.gW2part = (float*)(b + o_gw2);
     w.l1part = (float*)(b + o_l1);
-    w.h1 = (unsigned short*)(b + o_h1);
     w.h1T = (unsigned short*)(b + o_h1T);
     w.dpre2 = (unsigned short*)(b + o_dp2);
     w.dpre2T = (unsigned short*)(b + o_dp2T);
@@ -947,7 +945,7 @@ void mlp_step(MlpState* st, int64_t n, const float* X, const float* y, double lr
   Ws w = carve(st, n, &bytes);
   MlpDev& M = st->dev;
   const int E = M.E, H = M.H;
-  FwdOut fo{w.out, w.pre1, w.h1, w.h1T, w.pre2, w.ldt};
+  FwdOut fo{w.out, w.pre1, w.h1T, w.pre2, w.ldt};
   hipLaunchKernelGGL(k_mlp_fwd<true>, dim3((unsigned)fwd_items((int)w.nblk, E)), dim3(256),
                      mlp_fwd_smem(M.D, H), s, M, n, X, fo, (int)w.nblk, apply);
   BwdBuf bb{w.dpre2, w.dpre2T, w.colpart, w.ldt};
@@ -1113,7 +1111,7 @@ bool mlp_grads(MlpState* st, int64_t n, const float* X, const float* y, float* g
 // Member outputs on m candidates, in chunks (out: E x m).
 void mlp_forward(MlpState* st, int64_t m, const float* Xc, float* out, hipStream_t s) {
   MlpDev& M = st->dev;
-  FwdOut fo{out, nullptr, nullptr, nullptr, nullptr};
+  FwdOut fo{out, nullptr, nullptr, nullptr};
   const int ntile = (int)ceil_div(m, MT);
   int64_t grid = fwd_items(ntile, M.E);
   if (st->fwd_wg_per_cu > 0)
