@@ -965,7 +965,8 @@ void mlp_step(MlpState* st, int64_t n, const float* X, const float* y, double lr
   g1.out = w.gW2part;
   hipLaunchKernelGGL((k_gemm_nt<EPI_STORE, 1, 1, 8>), dim3((H / 32) * (H / 32), w.S2, E), dim3(64), 0, s,
                      g1);
-  // dh1 = dpre2 W2 -> dpre1 = dh1 GELU'(pre1)
+  // dh1 = dpre2 W2 -> dpre1 = dh1 GELU'(pre1) (one wave per workgroup too;
+  // the bias partials are per 32-row block, i.e. per wave, either way)
   Gemm g2{};
   g2.A = w.dpre2;
   g2.B = M.W2Tb;
@@ -981,8 +982,8 @@ void mlp_step(MlpState* st, int64_t n, const float* X, const float* y, double lr
   g2.dpre1T = w.dpre1T;
   g2.ldo = w.ldt;
   g2.b1part = w.b1part;
-  hipLaunchKernelGGL((k_gemm_nt<EPI_DPRE1, 2, 2, 8>), dim3((unsigned)(n / 64) * (H / 64), 1, E),
-                     dim3(256), 0, s, g2);
+  hipLaunchKernelGGL((k_gemm_nt<EPI_DPRE1, 1, 1, 8>), dim3((unsigned)(n / 32) * (H / 32), 1, E),
+                     dim3(64), 0, s, g2);
   // gW1 = dpre1^T x over the samples (bf16 operands, split over S1 chunks);
   // x^T is shared by the members
   Gemm g3{};
